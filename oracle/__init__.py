@@ -1,0 +1,229 @@
+"""ctypes wrapper of the plain FP64 CPU oracle (ffpic_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+CPU-baseline leg of bench.py.  The product path never imports this package.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "libffpic_oracle.so")
+SRC = os.path.join(HERE, "ffpic_oracle.c")
+
+# field component numbering of the oracle (ffpic_oracle.h)
+ER, ETH, EPH, BR, BTH, BPH, JR, JTH, JPH, PSI, F, B0R, B0TH, B0PH = range(14)
+PHASE_MASK, PHASE_KILL, PHASE_SORT, PHASE_PUSH, PHASE_FIELDS = 1, 2, 4, 8, 16
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain C, FP contraction off)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared",
+                               "-ffp-contract=off", "-fno-fast-math", "-o", tmp,
+                               SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class _Params(C.Structure):
+    _fields_ = [("nr", C.c_int), ("nth", C.c_int),
+                ("rmin", C.c_double), ("rmax", C.c_double), ("r_lc", C.c_double),
+                ("r_abs", C.c_double), ("mu", C.c_double), ("cfl", C.c_double),
+                ("omega_b", C.c_double), ("rr_coef", C.c_double),
+                ("psi_thr", C.c_double * 4),
+                ("ff_enable", C.c_int), ("init", C.c_int),
+                ("sort_interval", C.c_int), ("nspec", C.c_int),
+                ("qm", C.c_double * 4), ("weight", C.c_double * 4)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        P = C.c_void_p
+        dp = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+        L.ora_create.restype = P
+        L.ora_create.argtypes = [C.POINTER(_Params)]
+        L.ora_destroy.argtypes = [P]
+        L.ora_info.argtypes = [P, dp]
+        L.ora_get_field.argtypes = [P, C.c_int, dp]
+        L.ora_set_field.argtypes = [P, C.c_int, dp]
+        L.ora_load_particles.restype = C.c_int64
+        L.ora_load_particles.argtypes = [P, C.c_int, C.c_int64, dp, dp, dp, dp, dp]
+        L.ora_num_particles.restype = C.c_int64
+        L.ora_num_particles.argtypes = [P, C.c_int]
+        L.ora_get_particles.restype = C.c_int64
+        L.ora_get_particles.argtypes = [P, C.c_int, dp, dp, dp, dp, dp,
+                                        np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")]
+        L.ora_step.argtypes = [P, C.c_int]
+        L.ora_run_phases.argtypes = [P, C.c_int]
+        L.ora_step_count.restype = C.c_int64
+        L.ora_step_count.argtypes = [P]
+        L.ora_removed.argtypes = [P, C.c_int, np.ctypeslib.ndpointer(np.int64)]
+        L.ora_moments.argtypes = [P, C.c_int, dp]
+        L.ora_gauss.argtypes = [P, dp]
+        L.ora_divb.argtypes = [P, dp]
+        L.ora_node_charge.argtypes = [P, dp]
+        L.ora_poynting.argtypes = [P, dp]
+        L.ora_sort_offsets.argtypes = [P, C.c_int,
+                                       np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")]
+        L.ora_boris_rr.argtypes = [dp, dp, dp, C.c_double, C.c_double, C.c_double]
+        L.ora_ff_node.argtypes = [dp, dp, dp]
+        L.ora_timestep.restype = C.c_double
+        L.ora_timestep.argtypes = [C.POINTER(_Params)]
+        L.ora_gather.argtypes = [P, C.c_double, C.c_double, dp, dp]
+        L.ora_blend.restype = C.c_double
+        L.ora_blend.argtypes = [C.c_double, dp]
+        _lib = L
+    return _lib
+
+
+def params(desc: dict) -> _Params:
+    p = _Params()
+    for k in ("nr", "nth", "ff_enable", "init", "sort_interval", "nspec"):
+        setattr(p, k, int(desc[k]))
+    for k in ("rmin", "rmax", "r_lc", "r_abs", "mu", "cfl", "omega_b", "rr_coef"):
+        setattr(p, k, float(desc[k]))
+    for k in range(4):
+        p.psi_thr[k] = float(desc["psi_thr"][k])
+    for k, (q, w) in enumerate(zip(desc["qm"], desc["weight"])):
+        p.qm[k] = float(q)
+        p.weight[k] = float(w)
+    return p
+
+
+class Oracle:
+    """One simulated magnetosphere held by the CPU oracle."""
+
+    def __init__(self, desc: dict):
+        self.desc = dict(desc)
+        self.nr, self.nth = int(desc["nr"]), int(desc["nth"])
+        self._p = params(desc)
+        self._h = lib().ora_create(C.byref(self._p))
+        if not self._h:
+            raise ValueError("oracle rejected the parameters")
+        info = np.zeros(4)
+        lib().ora_info(self._h, info)
+        self.dt, self.dlog, self.dth, self.omega = (float(x) for x in info)
+
+    def close(self):
+        if self._h:
+            lib().ora_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def shape(self):
+        return (self.nr + 1, self.nth + 1)
+
+    def field(self, comp: int) -> np.ndarray:
+        out = np.zeros(self.shape)
+        lib().ora_get_field(self._h, comp, out)
+        return out
+
+    def set_field(self, comp: int, arr: np.ndarray):
+        lib().ora_set_field(self._h, comp, np.ascontiguousarray(arr, dtype=np.float64))
+
+    def load(self, sp: int, d: dict) -> int:
+        a = [np.ascontiguousarray(d[k], dtype=np.float64) for k in ("r", "th", "ur", "uth", "uph")]
+        return int(lib().ora_load_particles(self._h, sp, len(a[0]), *a))
+
+    def n(self, sp: int) -> int:
+        return int(lib().ora_num_particles(self._h, sp))
+
+    def particles(self, sp: int) -> dict:
+        n = self.n(sp)
+        out = {k: np.zeros(n) for k in ("r", "th", "ur", "uth", "uph")}
+        cell = np.zeros(n, dtype=np.int32)
+        lib().ora_get_particles(self._h, sp, out["r"], out["th"], out["ur"],
+                                out["uth"], out["uph"], cell)
+        out["cell"] = cell
+        return out
+
+    def step(self, n: int = 1):
+        lib().ora_step(self._h, int(n))
+
+    def phases(self, mask: int):
+        lib().ora_run_phases(self._h, int(mask))
+
+    def step_count(self) -> int:
+        return int(lib().ora_step_count(self._h))
+
+    def removed(self, sp: int) -> np.ndarray:
+        out = np.zeros(4, dtype=np.int64)
+        lib().ora_removed(self._h, sp, out)
+        return out
+
+    def moments(self, sp: int) -> np.ndarray:
+        out = np.zeros(5)
+        lib().ora_moments(self._h, sp, out)
+        return out
+
+    def gauss(self) -> np.ndarray:
+        out = np.zeros(self.shape)
+        lib().ora_gauss(self._h, out)
+        return out
+
+    def divb(self) -> np.ndarray:
+        out = np.zeros(self.shape)
+        lib().ora_divb(self._h, out)
+        return out
+
+    def node_charge(self) -> np.ndarray:
+        out = np.zeros(self.shape)
+        lib().ora_node_charge(self._h, out)
+        return out
+
+    def poynting(self) -> np.ndarray:
+        out = np.zeros(self.nr + 1)
+        lib().ora_poynting(self._h, out)
+        return out
+
+    def gather(self, r: float, th: float):
+        E = np.zeros(3)
+        B = np.zeros(3)
+        lib().ora_gather(self._h, float(r), float(th), E, B)
+        return E, B
+
+    def sort_offsets(self, sp: int) -> np.ndarray:
+        out = np.zeros(self.nr * self.nth + 1, dtype=np.int32)
+        lib().ora_sort_offsets(self._h, sp, out)
+        return out
+
+
+def timestep(desc: dict) -> float:
+    p = params(desc)
+    return float(lib().ora_timestep(C.byref(p)))
+
+
+def boris_rr(u, E, B, dt, wq, rr=0.0):
+    uu = np.array(u, dtype=np.float64)
+    lib().ora_boris_rr(uu, np.asarray(E, dtype=np.float64), np.asarray(B, dtype=np.float64),
+                       float(dt), float(wq), float(rr))
+    return uu
+
+
+def ff_node(E, B):
+    out = np.zeros(3)
+    lib().ora_ff_node(np.asarray(E, dtype=np.float64), np.asarray(B, dtype=np.float64), out)
+    return out
+
+
+def blend(psi, thr):
+    return float(lib().ora_blend(float(psi), np.asarray(thr, dtype=np.float64)))

@@ -1,0 +1,77 @@
+/*
+ * Plain FP64 CPU oracle of one hybrid force-free / PIC time step on an
+ * axisymmetric (r, theta) Yee grid (Soudais, Cerutti & Contopoulos 2024,
+ * Sect. 3).  TEST INFRASTRUCTURE ONLY: it exists to check the GPU library;
+ * only the tests, the smoke check and the CPU-baseline leg of the benchmark
+ * may load it.  It shares no code with the GPU path.
+ *
+ * Storage: every field component lives in an (nr+1) x (nth+1) node-shaped
+ * array, theta fastest, index i*(nth+1)+j.  Component positions (Yee):
+ *   E_r (i+1/2, j)   E_th (i, j+1/2)   E_ph (i, j)
+ *   B_r (i, j+1/2)   B_th (i+1/2, j)   B_ph (i+1/2, j+1/2)
+ *   J like E; Psi and f at nodes.  Entry [i][j] holds the value at the
+ *   position whose lower corner is node (i, j); unused entries stay zero.
+ * Particles: per species, FP64 (r, theta, u_r, u_theta, u_phi); a dead slot
+ * has r = -1 until the next sort compacts it away.
+ */
+#ifndef FFPIC_ORACLE_H
+#define FFPIC_ORACLE_H
+#include <stdint.h>
+
+#define ORA_MAXSPEC 4
+
+typedef struct {
+    int nr, nth;
+    double rmin, rmax, r_lc, r_abs, mu, cfl, omega_b, rr_coef;
+    double psi_thr[4];
+    int ff_enable, init, sort_interval, nspec;
+    double qm[ORA_MAXSPEC], weight[ORA_MAXSPEC];
+} ora_params;
+
+enum { ORA_ER, ORA_ETH, ORA_EPH, ORA_BR, ORA_BTH, ORA_BPH,
+       ORA_JR, ORA_JTH, ORA_JPH, ORA_PSI, ORA_F,
+       ORA_B0R, ORA_B0TH, ORA_B0PH, ORA_NCOMP };
+
+enum { ORA_PHASE_MASK = 1, ORA_PHASE_KILL = 2, ORA_PHASE_SORT = 4,
+       ORA_PHASE_PUSH = 8, ORA_PHASE_FIELDS = 16 };
+
+typedef struct ora_sim ora_sim;
+
+ora_sim *ora_create(const ora_params *p);
+double ora_timestep(const ora_params *p);
+void ora_destroy(ora_sim *s);
+/* out: dt, dlog, dth, omega */
+void ora_info(const ora_sim *s, double out[4]);
+void ora_get_field(const ora_sim *s, int comp, double *dst);
+void ora_set_field(ora_sim *s, int comp, const double *src);
+/* appends, then removes out-of-domain and masked particles and sorts;
+   returns the number of particles of that species after loading */
+int64_t ora_load_particles(ora_sim *s, int sp, int64_t n, const double *r,
+                           const double *th, const double *ur,
+                           const double *uth, const double *uph);
+int64_t ora_num_particles(const ora_sim *s, int sp);
+/* copies all slots; cell = i*nth + j, or -1 for a dead slot */
+int64_t ora_get_particles(const ora_sim *s, int sp, double *r, double *th,
+                          double *ur, double *uth, double *uph, int32_t *cell);
+void ora_step(ora_sim *s, int nsteps);
+void ora_run_phases(ora_sim *s, int phases);
+int64_t ora_step_count(const ora_sim *s);
+/* removed[cause] for cause = 0 load, 1 force-free kill, 2 star, 3 absorber */
+void ora_removed(const ora_sim *s, int sp, int64_t out[4]);
+
+/* diagnostics */
+void ora_moments(const ora_sim *s, int sp, double out[5]);
+void ora_gauss(const ora_sim *s, double *g);      /* node map */
+void ora_divb(const ora_sim *s, double *d);       /* primal-cell map */
+void ora_node_charge(const ora_sim *s, double *q);/* sum Q S S per node */
+void ora_poynting(const ora_sim *s, double *L);   /* nr+1 radii */
+void ora_sort_offsets(const ora_sim *s, int sp, int32_t *off);
+
+/* pieces exported for the closed-form pins */
+void ora_boris_rr(double u[3], const double E[3], const double B[3],
+                  double dt, double omega_b_qm, double rr);
+void ora_ff_node(const double E[3], const double B[3], double out[3]);
+double ora_blend(double psi, const double thr[4]);
+void ora_gather(const ora_sim *s, double r, double th, double E[3], double B[3]);
+
+#endif
