@@ -1,0 +1,243 @@
+/*
+ * ffpic.h -- C ABI of the MI355X hybrid force-free / particle-in-cell step
+ * for axisymmetric pulsar magnetospheres (Soudais, Cerutti & Contopoulos
+ * 2024, "Scaling up global kinetic models of pulsar magnetospheres using a
+ * hybrid force-free-PIC numerical approach", Sect. 3).
+ *
+ * One call of ffpic_step advances one magnetosphere by n time steps on the
+ * GPU.  Each time step is (Sect. 3):
+ *   - the flux function Psi of eq. (psi) and the blending function f(Psi)
+ *     of eq. (transition), rebuilt from the current B_r every step;
+ *   - removal of particles from cells inside the pure force-free domain;
+ *   - every sort_interval steps, a stable sort of each species by cell;
+ *   - the particle push of eq. (motion) with the radiation-reaction force
+ *     g and the effective field of eq. (bperp), a modified Boris scheme;
+ *   - a charge-conserving current deposit;
+ *   - the Yee/FDTD field update of eqs. (faraday) and (ampere) with the
+ *     blended current of eq. (blending), whose force-free part is the
+ *     drift current of eq. (JFFE), followed by the force-free E correction
+ *     (E.B projection and the cap |E| <= |B|) on the force-free domain;
+ *   - the corotation condition on the star and the absorbing layer of
+ *     Sect. 4.
+ *
+ * Units: c = 1, lengths in stellar radii, Omega = 1 / r_lc.
+ *
+ * Grid: nr x nth cells, r log-spaced on [rmin, rmax], theta uniform on
+ * [0, pi] (Sect. 4).  Every field component is exchanged as an
+ * (nr+1) x (nth+1) node-shaped array of doubles, theta fastest
+ * (index i*(nth+1) + j).  Entry [i][j] of a component holds its value at
+ * the staggered position whose lower corner is node (i, j):
+ *   E_r (i+1/2, j)   E_th (i, j+1/2)   E_ph (i, j)
+ *   B_r (i, j+1/2)   B_th (i+1/2, j)   B_ph (i+1/2, j+1/2)
+ * Entries with no position (e.g. E_r[nr][*]) are zero.
+ *
+ * Errors: every int-returning call returns FFPIC_OK (0) or a negative
+ * status; ffpic_last_error() then describes the failure.  Errors raised by
+ * kernels (non-finite momenta, a particle moving a whole cell in a step) are
+ * recorded in a device error word and reported by the next synchronising
+ * call (ffpic_sync, ffpic_get_*, ffpic_diagnostics).  No C++ exception
+ * crosses this boundary.  A context is not thread-safe; use one context per
+ * stream.
+ */
+#ifndef FFPIC_H
+#define FFPIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FFPIC_MAX_SPECIES 4
+
+enum ffpic_status {
+    FFPIC_OK = 0,
+    FFPIC_EINVAL = -1,    /* invalid argument or descriptor */
+    FFPIC_ENOMEM = -2,    /* device or host allocation failed */
+    FFPIC_EHIP = -3,      /* a HIP runtime call failed */
+    FFPIC_ECAPACITY = -4, /* more particles than the species capacity */
+    FFPIC_ENUMERIC = -5,  /* a kernel met a non-finite value or a CFL breach */
+    FFPIC_ESTATE = -6     /* call not valid in the current state */
+};
+
+enum ffpic_precision {
+    FFPIC_FP64 = 0,       /* fields, particles and currents in FP64 */
+    FFPIC_FP32_MIXED = 1  /* int32 cell + FP32 in-cell offsets, FP32 momenta,
+                             fields and currents; FP64 Psi and residuals */
+};
+
+enum ffpic_init {
+    FFPIC_INIT_ZERO = 0,        /* all fields zero (load them yourself) */
+    FFPIC_INIT_DIPOLE = 1,      /* Psi = mu sin^2(theta)/r, eq. (flux_dipole) */
+    FFPIC_INIT_MONOPOLE = 2,    /* Psi = mu (1 - cos theta), Sect. 4 */
+    FFPIC_INIT_MICHEL = 3,      /* monopole plus Michel B_phi, Sect. 4 */
+    FFPIC_INIT_OPEN_DIPOLE = 4  /* dipole inside the light cylinder with the
+                                   lines crossing it opened to a split monopole */
+};
+/* Every non-zero init sets poloidal B from nodal Psi differences (exactly
+   divergence-free) and the corotation field E = -(Omega x r) x B in edge form
+   (E = -Omega grad Psi); E_th and E_ph on the star stay at these values
+   (corotation boundary, Sect. 4); E_th = E_ph = 0 on r = rmax. */
+
+enum ffpic_component {
+    FFPIC_ER = 0, FFPIC_ETH, FFPIC_EPH,
+    FFPIC_BR, FFPIC_BTH, FFPIC_BPH,
+    /* deposit accumulators of the last push (zeroed by the field update):
+       JR = radial charge flux through dual faces over the step, JTH = polar
+       charge flux, JPH = sum of Q v_phi S_xi S_eta per node (Q = charge) */
+    FFPIC_JR, FFPIC_JTH, FFPIC_JPH,
+    FFPIC_PSI,            /* flux function at nodes (FP64 in both modes) */
+    FFPIC_F,              /* blending function at nodes */
+    FFPIC_GAUSS,          /* node map of div E - 4 pi rho (read only) */
+    FFPIC_DIVB,           /* primal-cell map of div B (read only) */
+    FFPIC_NCOMP
+};
+
+/* Descriptor of one magnetosphere.  Reading of the paper's parameters:
+   star and light cylinder (Sect. 2, 4), grid and CFL (Sect. 4, Table 1),
+   species charge-to-mass and weight (Sect. 3, Table 1), force-free / PIC
+   flux thresholds (eq. transition, Table 1), radiation-reaction strength
+   (Sect. 3, Sect. 5.1 f_rad), absorbing layer (Sect. 4). */
+typedef struct ffpic_desc {
+    int32_t nr, nth;          /* cells in r and theta, each in [2, 65535] */
+    double rmin, rmax;        /* radial extent, 0 < rmin < rmax */
+    double r_lc;              /* light-cylinder radius; Omega = 1 / r_lc */
+    double r_abs;             /* absorbing layer starts here; rmin < r_abs <= rmax */
+    double mu;                /* dipole moment, or Psi_star for the monopoles */
+    double cfl;               /* in (0, 1]: dt = cfl / sqrt(1/dr0^2 + 1/(r0 dth)^2) */
+    double omega_b;           /* Lorentz coupling: du/dt = omega_b qm (E + beta x B) */
+    double rr_coef;           /* radiation-reaction coefficient K_e (0 = off) */
+    double psi_thr[4];        /* Psi_0 <= Psi_1 <= Psi_2 <= Psi_3 (+-inf allowed):
+                                 f = 1 for Psi < Psi_0 and Psi >= Psi_3, linear on
+                                 (Psi_0, Psi_1) and (Psi_2, Psi_3), 0 between */
+    int32_t ff_enable;        /* 0: pure PIC (f = 0 everywhere) */
+    int32_t precision;        /* enum ffpic_precision */
+    int32_t init;             /* enum ffpic_init */
+    int32_t sort_interval;    /* >= 1 */
+    int32_t nspec;            /* 0 .. FFPIC_MAX_SPECIES */
+    int32_t pad_;
+    int64_t capacity[FFPIC_MAX_SPECIES]; /* particle slots per species */
+    double qm[FFPIC_MAX_SPECIES];     /* charge-to-mass in units of e/m_e
+                                         (-1 electrons, +1 positrons, 1/1836 protons) */
+    double weight[FFPIC_MAX_SPECIES]; /* macro-particle charge magnitude */
+} ffpic_desc;
+
+typedef struct ffpic_diag {
+    int64_t step;                         /* steps taken */
+    int64_t alive[FFPIC_MAX_SPECIES];
+    int64_t removed[FFPIC_MAX_SPECIES][4]; /* causes: 0 load, 1 force-free
+                                              domain, 2 star, 3 absorber */
+    double sum_gamma[FFPIC_MAX_SPECIES];
+    double sum_u[FFPIC_MAX_SPECIES][3];   /* sums of u_r, u_theta, u_phi */
+    double energy_e, energy_b;            /* sum of E^2 / 8pi, B^2 / 8pi times
+                                             cell volume (2 pi dropped) */
+    double gauss_max;                     /* max |div E - 4 pi rho| over interior nodes */
+    double divb_max;                      /* max |div B| over primal cells */
+    uint32_t error_word;                  /* device error bits (FFPIC_ERR_*) */
+    uint32_t pad_;
+} ffpic_diag;
+
+#define FFPIC_ERR_NONFINITE 1u  /* non-finite momentum after a push */
+#define FFPIC_ERR_CFL 2u        /* a particle crossed more than one cell */
+
+#define FFPIC_DIAG_MOMENTS 1u
+#define FFPIC_DIAG_ENERGY 2u
+#define FFPIC_DIAG_RESIDUALS 4u
+#define FFPIC_DIAG_POYNTING 8u
+#define FFPIC_DIAG_ALL 15u
+
+typedef struct ffpic_ctx ffpic_ctx;
+typedef struct ffpic_batch ffpic_batch;
+
+/* Validates d, builds the FP64 geometry tables, allocates all device memory
+   (owned by the context), sets the initial fields and the mask.  `stream` is
+   a hipStream_t borrowed for the life of the context (NULL = default
+   stream).  On success *out receives the context.  EINVAL for a bad
+   descriptor, ENOMEM, EHIP. */
+int ffpic_create(const ffpic_desc *d, void *stream, ffpic_ctx **out);
+
+/* Releases everything the context owns.  NULL is ignored. */
+void ffpic_destroy(ffpic_ctx *ctx);
+
+/* Message of the last failed call on this context (owned by the context,
+   valid until its next call); a static string for ctx == NULL. */
+const char *ffpic_last_error(const ffpic_ctx *ctx);
+
+/* out[0..3] = dt, dlog, dtheta, Omega. */
+int ffpic_info(const ffpic_ctx *ctx, double out[4]);
+
+/* Replaces one field component (FFPIC_ER .. FFPIC_BPH) from an
+   (nr+1)*(nth+1) FP64 array in host memory (src_on_device = 0) or device
+   memory (1); the caller keeps ownership.  Loading a B component also makes
+   it the reference state of the absorbing layer and rebuilds Psi and f. */
+int ffpic_load_fields(ffpic_ctx *ctx, int comp, const double *src, int src_on_device);
+
+/* Appends n particles of `species` given as FP64 arrays (r, theta, u_r,
+   u_theta, u_phi) with u = gamma v / c, in host or device memory.
+   Particles outside [rmin, r_abs) or theta outside [0, pi], with a
+   non-finite value, or in a cell of the pure force-free domain are dropped
+   (counted as removed at load); the species is then sorted by cell.
+   ECAPACITY if the slots would overflow (nothing is loaded), EINVAL. */
+int ffpic_load_particles(ffpic_ctx *ctx, int species, int64_t n, const double *r,
+                         const double *th, const double *ur, const double *uth,
+                         const double *uph, int src_on_device);
+
+/* Advances nsteps time steps, asynchronously on the context's stream. */
+int ffpic_step(ffpic_ctx *ctx, int32_t nsteps);
+
+/* Test hook: runs single phases of a step without advancing the step
+   counter (bit mask of FFPIC_PHASE_*), in the order mask, kill, sort, push,
+   fields. */
+#define FFPIC_PHASE_MASK 1u
+#define FFPIC_PHASE_KILL 2u
+#define FFPIC_PHASE_SORT 4u
+#define FFPIC_PHASE_PUSH 8u
+#define FFPIC_PHASE_FIELDS 16u
+int ffpic_run_phases(ffpic_ctx *ctx, uint32_t phases);
+
+/* Waits for the stream and returns the first recorded device error
+   (ENUMERIC) or FFPIC_OK. */
+int ffpic_sync(ffpic_ctx *ctx);
+
+/* Copies one component (FFPIC_ER .. FFPIC_DIVB) as FP64 into an
+   (nr+1)*(nth+1) caller buffer in host (0) or device (1) memory.
+   Synchronises. */
+int ffpic_get_field(ffpic_ctx *ctx, int comp, double *dst, int dst_on_device);
+
+/* Number of particle slots of a species (live ones, plus dead slots not yet
+   removed by a sort).  Synchronises. */
+int ffpic_num_particles(ffpic_ctx *ctx, int species, int64_t *n);
+
+/* Copies the particle slots of a species to host buffers of at least
+   ffpic_num_particles entries (any pointer may be NULL).  cell = i*nth + j,
+   or -1 for a dead slot.  Synchronises. */
+int ffpic_get_particles(ffpic_ctx *ctx, int species, double *r, double *th,
+                        double *ur, double *uth, double *uph, int32_t *cell);
+
+/* Test hook: cell offsets of the last sort of a species (nr*nth + 1 int32
+   to host memory): offsets[k] = number of live particles with cell < k. */
+int ffpic_get_sort(ffpic_ctx *ctx, int species, int32_t *cell_offsets);
+
+/* Diagnostics selected by `what` (FFPIC_DIAG_*); L_of_r (nullable, nr+1
+   doubles, host) receives the Poynting flux through each sphere r_i
+   (Sect. 4, eq. michel_spindown form).  Synchronises. */
+int ffpic_diagnostics(ffpic_ctx *ctx, uint32_t what, ffpic_diag *out, double *L_of_r);
+
+/* Checkpoint: with buf == NULL writes the required size to *len; otherwise
+   serialises fields, Psi, f, particles, counters and the step number into
+   buf (at least *len bytes, host memory).  Restore requires a context
+   created from the same descriptor.  Synchronises. */
+int ffpic_save(ffpic_ctx *ctx, void *buf, size_t *len);
+int ffpic_restore(ffpic_ctx *ctx, const void *buf, size_t len);
+
+/* Device time of each phase of the last ffpic_step call, in ms, summed over
+   its steps: out[0] mask, [1] sort, [2] push+deposit, [3] fields.
+   Requires ffpic_set_timing(ctx, 1) before the step. */
+int ffpic_set_timing(ffpic_ctx *ctx, int enable);
+int ffpic_phase_times(ffpic_ctx *ctx, float out[4]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,129 @@
+// Internal declarations of the MI355X hybrid force-free / PIC library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ffpic.h"
+
+namespace ffpic {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// Geometry of the spherical Yee grid as 1-D tables (all computed on the host
+// in FP64, stored in the working precision R).  Index conventions:
+//   radial node i in [0, nr], half node i+1/2 stored at i in [0, nr);
+//   polar node j in [0, nth], half node j+1/2 stored at j in [0, nth).
+// Dual cell of node (i, j): r in [r_lo(i), r_hi(i)], theta in
+// [theta_lo(j), theta_hi(j)] with r_lo(0) = r_0, r_hi(nr) = r_nr and the
+// theta range clipped to [0, pi] on the axis.
+template <typename R>
+struct Geo {
+    int nr, nth, ld;        // ld = nth + 1 (row stride of every field array)
+    R dt, dth;
+    const R *rn;    // r_i                        [nr+1]
+    const R *rh;    // r_{i+1/2}                  [nr]
+    const R *rn2;   // r_i^2                      [nr+1]
+    const R *rh2;   // r_{i+1/2}^2                [nr]
+    const R *drn;   // r_{i+1} - r_i              [nr]
+    const R *drh;   // r_{i+1/2} - r_{i-1/2}      [nr+1] (entry 0 unused)
+    const R *dr2n;  // (r_{i+1}^2 - r_i^2) / 2    [nr]
+    const R *dr2h;  // (r_hi^2 - r_lo^2) / 2      [nr+1]
+    const R *dr3h;  // (r_hi^3 - r_lo^3) / 3      [nr+1]
+    const R *dr3n;  // (r_{i+1}^3 - r_i^3) / 3    [nr]
+    const R *lamn;  // absorber factor at r_i     [nr+1]
+    const R *lamh;  // absorber factor at r_{i+1/2} [nr]
+    const R *sn;    // sin(theta_j)               [nth+1]
+    const R *cn;    // cos(theta_j)               [nth+1]
+    const R *sh;    // sin(theta_{j+1/2})         [nth]
+    const R *dcn;   // cos(theta_j) - cos(theta_{j+1})   [nth]
+    const R *dcd;   // cos(theta_lo) - cos(theta_hi)     [nth+1]
+    const R *dthd;  // theta_hi - theta_lo               [nth+1]
+};
+
+enum { T_RN, T_RH, T_RN2, T_RH2, T_DRN, T_DRH, T_DR2N, T_DR2H, T_DR3H, T_DR3N,
+       T_LAMN, T_LAMH, T_SN, T_CN, T_SH, T_DCN, T_DCD, T_DTHD, T_THN, T_NTAB };
+
+struct Species {
+    int64_t cap = 0;
+    int64_t nub = 0;          // host upper bound of the slots in use
+    void *cur[6] = {};        // FP64: r, th, ur, uth, uph | FP32: cell, a, b, ur, uth, uph
+    void *alt[6] = {};
+    int narr = 0;
+    double qm = 0, weight = 0;
+};
+
+}  // namespace ffpic
+
+struct ffpic_ctx {
+    ffpic_desc d{};
+    hipStream_t stream = nullptr;
+    int nr = 0, nth = 0, ld = 0;
+    size_t nn = 0;
+    double dlog = 0, dth = 0, dt = 0, omega = 0;
+    bool fp64 = true;
+    std::vector<double> tab[ffpic::T_NTAB];   // host FP64 tables
+    void *dtab[ffpic::T_NTAB] = {};           // device tables in working precision
+    double *dtab64[ffpic::T_NTAB] = {};       // device FP64 tables
+    size_t rsz = 8;                           // sizeof(R)
+    void *E[3] = {}, *B[3] = {}, *B0[3] = {}, *J[3] = {};
+    void *scr[6] = {};                        // node scratch (J_FFE, E corrections)
+    double *psi = nullptr;
+    void *f = nullptr;
+    uint8_t *kill = nullptr;
+    ffpic::Species sp[FFPIC_MAX_SPECIES];
+    uint32_t *keys[2] = {}, *vals[2] = {};
+    void *sort_tmp = nullptr;
+    size_t sort_tmp_bytes = 0;
+    int64_t sort_cap = 0;
+    int32_t *nslots = nullptr;                // device [FFPIC_MAX_SPECIES]
+    int32_t *nalive = nullptr;                // device [FFPIC_MAX_SPECIES]
+    unsigned long long *removed = nullptr;    // device [FFPIC_MAX_SPECIES][4]
+    uint32_t *err = nullptr;                  // device error word
+    double *red = nullptr;                    // reduction scratch (device)
+    size_t red_len = 0;
+    int64_t step = 0;
+    bool sorted_once[FFPIC_MAX_SPECIES] = {};
+    int timing = 0;
+    hipEvent_t ev[8] = {};
+    float phase_ms[4] = {};
+    std::string last_error;
+};
+
+namespace ffpic {
+
+template <typename R>
+Geo<R> geo(const ffpic_ctx *c);
+
+// kernels (launchers); all enqueue on c->stream
+void psi_mask(ffpic_ctx *c);
+void sort_species(ffpic_ctx *c, int s);           // kill + stable sort by cell
+void kill_species(ffpic_ctx *c, int s);           // kill without sorting
+void push_species(ffpic_ctx *c, int s);
+void field_step(ffpic_ctx *c);
+void convert_loaded(ffpic_ctx *c, int s, int64_t off, int64_t n, const double *r,
+                    const double *th, const double *ur, const double *uth, const double *uph);
+void export_particles(ffpic_ctx *c, int s, int64_t n, double *r, double *th, double *ur,
+                      double *uth, double *uph, int32_t *cell);   // device outputs
+void to_f64(ffpic_ctx *c, const void *src, double *dst, size_t n);
+void from_f64(ffpic_ctx *c, const double *src, void *dst, size_t n);
+void sort_offsets(ffpic_ctx *c, int s, int32_t *dev_off);
+void moments(ffpic_ctx *c, int s, double *dev_out5);
+void gauss_map(ffpic_ctx *c, double *dev_map);
+void divb_map(ffpic_ctx *c, double *dev_map);
+void poynting(ffpic_ctx *c, double *dev_L);
+void energies(ffpic_ctx *c, double *dev_out2);
+double max_abs(ffpic_ctx *c, const double *dev, size_t n);
+size_t sort_temp_bytes(int64_t cap, int bits);
+void zero_counters(ffpic_ctx *c, int32_t *p, int n);
+
+}  // namespace ffpic
+
+#define FFPIC_LAUNCH_CHECK()                                                     \
+    do {                                                                         \
+        hipError_t e_ = hipGetLastError();                                       \
+        if (e_ != hipSuccess) throw std::runtime_error(hipGetErrorString(e_));   \
+    } while (0)

@@ -1,0 +1,733 @@
+// Host runtime behind the C ABI of include/ffpic.h: descriptor validation,
+// FP64 geometry tables, initial fields, device allocations, the step
+// sequence, particle load/export, diagnostics and checkpoints.  No C++
+// exception crosses the ABI: every entry point catches and maps to a status.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "ffpic_internal.h"
+
+namespace ffpic {
+void field_step64(ffpic_ctx *c);
+void field_step32(ffpic_ctx *c);
+void psi_mask64(ffpic_ctx *c);
+void psi_mask32(ffpic_ctx *c);
+void push64(ffpic_ctx *c, int s);
+void push32(ffpic_ctx *c, int s);
+
+template <typename R>
+static Geo<R> make_geo(const ffpic_ctx *c, R *const *t) {
+    Geo<R> g;
+    g.nr = c->nr; g.nth = c->nth; g.ld = c->ld;
+    g.dt = (R)c->dt; g.dth = (R)c->dth;
+    g.rn = t[T_RN]; g.rh = t[T_RH]; g.rn2 = t[T_RN2]; g.rh2 = t[T_RH2];
+    g.drn = t[T_DRN]; g.drh = t[T_DRH]; g.dr2n = t[T_DR2N]; g.dr2h = t[T_DR2H];
+    g.dr3h = t[T_DR3H]; g.dr3n = t[T_DR3N]; g.lamn = t[T_LAMN]; g.lamh = t[T_LAMH];
+    g.sn = t[T_SN]; g.cn = t[T_CN]; g.sh = t[T_SH]; g.dcn = t[T_DCN]; g.dcd = t[T_DCD];
+    g.dthd = t[T_DTHD];
+    return g;
+}
+template <>
+Geo<double> geo<double>(const ffpic_ctx *c) { return make_geo<double>(c, c->dtab64); }
+template <>
+Geo<float> geo<float>(const ffpic_ctx *c) { return make_geo<float>(c, (float *const *)c->dtab); }
+
+void psi_mask(ffpic_ctx *c) { c->fp64 ? psi_mask64(c) : psi_mask32(c); }
+void field_step(ffpic_ctx *c) { c->fp64 ? field_step64(c) : field_step32(c); }
+void push_species(ffpic_ctx *c, int s) { c->fp64 ? push64(c, s) : push32(c, s); }
+}  // namespace ffpic
+
+using namespace ffpic;
+
+namespace {
+
+struct Fail {
+    int code;
+    std::string msg;
+};
+
+#define HCHK(x)                                                                       \
+    do {                                                                              \
+        hipError_t e_ = (x);                                                          \
+        if (e_ != hipSuccess)                                                         \
+            throw Fail{FFPIC_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)};   \
+    } while (0)
+
+template <typename F>
+int guarded(ffpic_ctx *c, F &&f) {
+    try {
+        f();
+        return FFPIC_OK;
+    } catch (const Fail &e) {
+        if (c) c->last_error = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        if (c) c->last_error = "host allocation failed";
+        return FFPIC_ENOMEM;
+    } catch (const std::exception &e) {
+        if (c) c->last_error = e.what();
+        return FFPIC_EHIP;
+    }
+}
+
+void *dmalloc(size_t bytes) {
+    void *p = nullptr;
+    if (bytes == 0) bytes = 8;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        throw Fail{FFPIC_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+    }
+    return p;
+}
+
+std::string validate(const ffpic_desc *d) {
+    if (!d) return "descriptor is NULL";
+    if (d->nr < 2 || d->nth < 2 || d->nr > 65535 || d->nth > 65535)
+        return "nr and nth must lie in [2, 65535]";
+    if (!(d->rmin > 0) || !(d->rmax > d->rmin) || !std::isfinite(d->rmax))
+        return "need 0 < rmin < rmax";
+    if (!(d->r_abs > d->rmin) || !(d->r_abs <= d->rmax)) return "need rmin < r_abs <= rmax";
+    if (!(d->cfl > 0) || !(d->cfl <= 1)) return "cfl must lie in (0, 1]";
+    if (!(d->r_lc > 0) || !std::isfinite(d->r_lc)) return "r_lc must be positive";
+    if (!std::isfinite(d->mu) || !std::isfinite(d->omega_b) || !std::isfinite(d->rr_coef))
+        return "mu, omega_b and rr_coef must be finite";
+    for (int k = 0; k < 4; k++)
+        if (std::isnan(d->psi_thr[k])) return "psi thresholds must not be NaN";
+    for (int k = 0; k < 3; k++)
+        if (!(d->psi_thr[k] <= d->psi_thr[k + 1])) return "psi thresholds must be non-decreasing";
+    if (d->precision != FFPIC_FP64 && d->precision != FFPIC_FP32_MIXED) return "bad precision";
+    if (d->init < FFPIC_INIT_ZERO || d->init > FFPIC_INIT_OPEN_DIPOLE) return "bad init";
+    if (d->sort_interval < 1) return "sort_interval must be >= 1";
+    if (d->nspec < 0 || d->nspec > FFPIC_MAX_SPECIES) return "nspec out of range";
+    for (int s = 0; s < d->nspec; s++) {
+        if (d->capacity[s] < 0 || d->capacity[s] > 0x7fffffff) return "capacity out of range";
+        if (!std::isfinite(d->qm[s]) || d->qm[s] == 0.0) return "qm must be finite and non-zero";
+        if (!std::isfinite(d->weight[s]) || d->weight[s] < 0) return "weight must be >= 0";
+    }
+    return "";
+}
+
+// geometry tables (FP64, on the host)
+void build_tables(ffpic_ctx *c) {
+    const int nr = c->nr, nth = c->nth;
+    const double rmin = c->d.rmin;
+    auto &T = c->tab;
+    for (auto &t : T) t.clear();
+    T[T_RN].resize(nr + 1); T[T_RH].resize(nr); T[T_RN2].resize(nr + 1); T[T_RH2].resize(nr);
+    T[T_DRN].resize(nr); T[T_DRH].resize(nr + 1); T[T_DR2N].resize(nr); T[T_DR2H].resize(nr + 1);
+    T[T_DR3H].resize(nr + 1); T[T_DR3N].resize(nr); T[T_LAMN].resize(nr + 1); T[T_LAMH].resize(nr);
+    T[T_SN].resize(nth + 1); T[T_CN].resize(nth + 1); T[T_SH].resize(nth); T[T_DCN].resize(nth);
+    T[T_DCD].resize(nth + 1); T[T_DTHD].resize(nth + 1); T[T_THN].resize(nth + 1);
+    auto &rn = T[T_RN], &rh = T[T_RH];
+    for (int i = 0; i <= nr; i++) rn[i] = rmin * std::exp(i * c->dlog);
+    for (int i = 0; i < nr; i++) rh[i] = rmin * std::exp((i + 0.5) * c->dlog);
+    for (int i = 0; i <= nr; i++) T[T_RN2][i] = rn[i] * rn[i];
+    for (int i = 0; i < nr; i++) T[T_RH2][i] = rh[i] * rh[i];
+    for (int i = 0; i < nr; i++) T[T_DRN][i] = rn[i + 1] - rn[i];
+    for (int i = 0; i <= nr; i++) T[T_DRH][i] = (i >= 1 && i < nr) ? rh[i] - rh[i - 1] : 0.0;
+    for (int i = 0; i < nr; i++) T[T_DR2N][i] = (rn[i + 1] * rn[i + 1] - rn[i] * rn[i]) * 0.5;
+    for (int i = 0; i <= nr; i++) {
+        double lo = i == 0 ? rn[0] : rh[i - 1];
+        double hi = i == nr ? rn[nr] : rh[i];
+        T[T_DR2H][i] = (hi * hi - lo * lo) * 0.5;
+        T[T_DR3H][i] = (hi * hi * hi - lo * lo * lo) / 3.0;
+    }
+    for (int i = 0; i < nr; i++)
+        T[T_DR3N][i] = (rn[i + 1] * rn[i + 1] * rn[i + 1] - rn[i] * rn[i] * rn[i]) / 3.0;
+    // absorbing layer (Sect. 4): lambda = exp(-sigma0 dt x^3) beyond r_abs,
+    // x = (r - r_abs) / (rmax - r_abs), sigma0 = 40 / (rmax - r_abs)
+    auto absorb = [&](double r) {
+        if (!(r > c->d.r_abs)) return 1.0;
+        double L = c->d.rmax - c->d.r_abs;
+        double x = (r - c->d.r_abs) / L;
+        return std::exp(-(40.0 / L) * c->dt * x * x * x);
+    };
+    for (int i = 0; i <= nr; i++) T[T_LAMN][i] = absorb(rn[i]);
+    for (int i = 0; i < nr; i++) T[T_LAMH][i] = absorb(rh[i]);
+    std::vector<double> ch(nth);
+    for (int j = 0; j <= nth; j++) {
+        T[T_THN][j] = j * c->dth;
+        T[T_SN][j] = std::sin(T[T_THN][j]);
+        T[T_CN][j] = std::cos(T[T_THN][j]);
+    }
+    T[T_SN][0] = 0.0; T[T_CN][0] = 1.0; T[T_SN][nth] = 0.0; T[T_CN][nth] = -1.0;
+    for (int j = 0; j < nth; j++) {
+        T[T_SH][j] = std::sin((j + 0.5) * c->dth);
+        ch[j] = std::cos((j + 0.5) * c->dth);
+    }
+    for (int j = 0; j < nth; j++) T[T_DCN][j] = T[T_CN][j] - T[T_CN][j + 1];
+    for (int j = 0; j <= nth; j++) {
+        double lo = j == 0 ? 1.0 : ch[j - 1];
+        double hi = j == nth ? -1.0 : ch[j];
+        T[T_DCD][j] = lo - hi;
+        T[T_DTHD][j] = (j == 0 || j == nth) ? 0.5 * c->dth : c->dth;
+    }
+}
+
+double psi_init(const ffpic_ctx *c, int i, int j) {
+    double r = c->tab[T_RN][i], st = c->tab[T_SN][j], ct = c->tab[T_CN][j], mu = c->d.mu;
+    switch (c->d.init) {
+    case FFPIC_INIT_DIPOLE:
+        return mu * st * st / r;
+    case FFPIC_INIT_MONOPOLE:
+    case FFPIC_INIT_MICHEL:
+        return mu * (1.0 - ct);
+    case FFPIC_INIT_OPEN_DIPOLE: {
+        double cs = r < c->d.r_lc ? std::sqrt(1.0 - r / c->d.r_lc) : 0.0;
+        if (std::fabs(ct) < cs) return mu * st * st / r;
+        return mu / c->d.r_lc * (1.0 - std::fabs(ct)) / (1.0 - cs);
+    }
+    default:
+        return 0.0;
+    }
+}
+
+// initial fields from nodal Psi differences (exactly divergence-free B) and
+// the corotation field E = -Omega grad Psi in edge form
+void init_fields_host(const ffpic_ctx *c, std::vector<double> F[6]) {
+    const int nr = c->nr, nth = c->nth, ld = c->ld;
+    for (int k = 0; k < 6; k++) F[k].assign(c->nn, 0.0);
+    if (c->d.init == FFPIC_INIT_ZERO) return;
+    std::vector<double> ps(c->nn);
+    auto PS = [&](int i, int j) -> double & { return ps[(size_t)i * ld + j]; };
+    auto at = [&](int k, int i, int j) -> double & { return F[k][(size_t)i * ld + j]; };
+    for (int i = 0; i <= nr; i++)
+        for (int j = 0; j <= nth; j++) PS(i, j) = psi_init(c, i, j);
+    const auto &T = c->tab;
+    double om = c->omega;
+    for (int i = 0; i <= nr; i++)
+        for (int j = 0; j < nth; j++) {
+            at(3, i, j) = (PS(i, j + 1) - PS(i, j)) / (T[T_RN2][i] * T[T_DCN][j]);
+            at(1, i, j) = i == nr ? 0.0 : -om * (PS(i, j + 1) - PS(i, j)) / (T[T_RN][i] * c->dth);
+        }
+    for (int i = 0; i < nr; i++)
+        for (int j = 0; j <= nth; j++) {
+            if (j > 0 && j < nth)
+                at(4, i, j) = -(PS(i + 1, j) - PS(i, j)) / (T[T_SN][j] * T[T_DR2N][i]);
+            at(0, i, j) = -om * (PS(i + 1, j) - PS(i, j)) / T[T_DRN][i];
+        }
+    if (c->d.init == FFPIC_INIT_MICHEL)
+        for (int i = 0; i < nr; i++)
+            for (int j = 0; j < nth; j++)
+                at(5, i, j) = -om * (PS(i, j + 1) - PS(i, j)) / (T[T_RH][i] * c->dth);
+}
+
+void upload_field(ffpic_ctx *c, void *dst, const std::vector<double> &h) {
+    if (c->fp64) {
+        HCHK(hipMemcpyAsync(dst, h.data(), c->nn * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    } else {
+        std::vector<float> f(h.begin(), h.end());
+        HCHK(hipMemcpyAsync(dst, f.data(), c->nn * sizeof(float), hipMemcpyHostToDevice, c->stream));
+        HCHK(hipStreamSynchronize(c->stream));
+    }
+}
+
+void free_all(ffpic_ctx *c) {
+    auto F = [](void *p) { if (p) (void)hipFree(p); };
+    for (int t = 0; t < T_NTAB; t++) {
+        if (c->dtab[t] != (void *)c->dtab64[t]) F(c->dtab[t]);
+        F(c->dtab64[t]);
+    }
+    for (int k = 0; k < 3; k++) { F(c->E[k]); F(c->B[k]); F(c->B0[k]); F(c->J[k]); }
+    for (int k = 0; k < 6; k++) F(c->scr[k]);
+    F(c->psi); F(c->f); F(c->kill);
+    for (int s = 0; s < FFPIC_MAX_SPECIES; s++)
+        for (int a = 0; a < 6; a++) { F(c->sp[s].cur[a]); F(c->sp[s].alt[a]); }
+    for (int k = 0; k < 2; k++) { F(c->keys[k]); F(c->vals[k]); }
+    F(c->sort_tmp); F(c->nslots); F(c->nalive); F(c->removed); F(c->err); F(c->red);
+    for (auto &e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+}
+
+void check_ctx(ffpic_ctx *c) {
+    if (!c) throw Fail{FFPIC_EINVAL, "context is NULL"};
+}
+
+int read_err(ffpic_ctx *c) {
+    uint32_t e = 0;
+    HCHK(hipMemcpyAsync(&e, c->err, sizeof(e), hipMemcpyDeviceToHost, c->stream));
+    HCHK(hipStreamSynchronize(c->stream));
+    if (e) {
+        std::string m = "device error word 0x" + std::to_string(e) + ":";
+        if (e & FFPIC_ERR_NONFINITE) m += " non-finite momentum;";
+        if (e & FFPIC_ERR_CFL) m += " particle crossed more than one cell in a step;";
+        throw Fail{FFPIC_ENUMERIC, m};
+    }
+    return 0;
+}
+
+void one_step(ffpic_ctx *c, uint32_t ph, bool count_step, int tslot) {
+    auto mark = [&](int k) {
+        if (c->timing && tslot >= 0) HCHK(hipEventRecord(c->ev[k], c->stream));
+    };
+    mark(0);
+    if (ph & FFPIC_PHASE_MASK) psi_mask(c);
+    mark(1);
+    for (int s = 0; s < c->d.nspec; s++) {
+        if (ph & FFPIC_PHASE_SORT) sort_species(c, s);
+        else if (ph & FFPIC_PHASE_KILL) kill_species(c, s);
+    }
+    mark(2);
+    if (ph & FFPIC_PHASE_PUSH)
+        for (int s = 0; s < c->d.nspec; s++) push_species(c, s);
+    mark(3);
+    if (ph & FFPIC_PHASE_FIELDS) field_step(c);
+    mark(4);
+    if (c->timing && tslot >= 0) {
+        HCHK(hipEventSynchronize(c->ev[4]));
+        for (int k = 0; k < 4; k++) {
+            float ms = 0;
+            HCHK(hipEventElapsedTime(&ms, c->ev[k], c->ev[k + 1]));
+            c->phase_ms[k] += ms;
+        }
+    }
+    if (count_step) c->step++;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ffpic_create(const ffpic_desc *d, void *stream, ffpic_ctx **out) {
+    if (!out) return FFPIC_EINVAL;
+    *out = nullptr;
+    std::string why = validate(d);
+    if (!why.empty()) return FFPIC_EINVAL;
+    ffpic_ctx *c = new (std::nothrow) ffpic_ctx();
+    if (!c) return FFPIC_ENOMEM;
+    int rc = guarded(c, [&] {
+        c->d = *d;
+        c->stream = (hipStream_t)stream;
+        c->nr = d->nr; c->nth = d->nth; c->ld = d->nth + 1;
+        c->nn = (size_t)(d->nr + 1) * (size_t)(d->nth + 1);
+        c->fp64 = d->precision == FFPIC_FP64;
+        c->rsz = c->fp64 ? sizeof(double) : sizeof(float);
+        c->dlog = std::log(d->rmax / d->rmin) / d->nr;
+        c->dth = kPi / d->nth;
+        c->omega = 1.0 / d->r_lc;
+        {   // CFL number times the 2-D Courant limit of the innermost cell
+            double r0 = d->rmin, r1 = d->rmin * std::exp(c->dlog);
+            double drr = r1 - r0, drt = r0 * c->dth;
+            c->dt = d->cfl / std::sqrt(1.0 / (drr * drr) + 1.0 / (drt * drt));
+        }
+        build_tables(c);
+        for (int t = 0; t < T_NTAB; t++) {
+            const auto &h = c->tab[t];
+            c->dtab64[t] = (double *)dmalloc(h.size() * sizeof(double));
+            HCHK(hipMemcpy(c->dtab64[t], h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+            if (c->fp64) {
+                c->dtab[t] = c->dtab64[t];
+            } else {
+                std::vector<float> f(h.begin(), h.end());
+                c->dtab[t] = dmalloc(f.size() * sizeof(float));
+                HCHK(hipMemcpy(c->dtab[t], f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+            }
+        }
+        size_t fb = c->nn * c->rsz;
+        for (int k = 0; k < 3; k++) {
+            c->E[k] = dmalloc(fb); c->B[k] = dmalloc(fb); c->B0[k] = dmalloc(fb); c->J[k] = dmalloc(fb);
+            HCHK(hipMemset(c->J[k], 0, fb));
+        }
+        if (d->ff_enable)
+            for (int k = 0; k < 6; k++) { c->scr[k] = dmalloc(fb); HCHK(hipMemset(c->scr[k], 0, fb)); }
+        c->psi = (double *)dmalloc(c->nn * sizeof(double));
+        c->f = dmalloc(fb);
+        c->kill = (uint8_t *)dmalloc((size_t)c->nr * c->nth);
+        int64_t maxcap = 0;
+        for (int s = 0; s < d->nspec; s++) {
+            Species &S = c->sp[s];
+            S.cap = d->capacity[s];
+            S.qm = d->qm[s];
+            S.weight = d->weight[s];
+            S.narr = c->fp64 ? 5 : 6;
+            size_t eb = c->fp64 ? 8 : 4;
+            for (int a = 0; a < S.narr; a++) {
+                S.cur[a] = dmalloc((size_t)S.cap * eb);
+                S.alt[a] = dmalloc((size_t)S.cap * eb);
+            }
+            maxcap = std::max(maxcap, S.cap);
+        }
+        c->sort_cap = maxcap;
+        for (int k = 0; k < 2; k++) {
+            c->keys[k] = (uint32_t *)dmalloc((size_t)maxcap * 4);
+            c->vals[k] = (uint32_t *)dmalloc((size_t)maxcap * 4);
+        }
+        int bits = 1;
+        while ((1ull << bits) <= (uint64_t)c->nr * c->nth) bits++;
+        c->sort_tmp_bytes = sort_temp_bytes(maxcap, bits);
+        c->sort_tmp = dmalloc(c->sort_tmp_bytes);
+        c->nslots = (int32_t *)dmalloc(FFPIC_MAX_SPECIES * sizeof(int32_t));
+        c->nalive = (int32_t *)dmalloc(FFPIC_MAX_SPECIES * sizeof(int32_t));
+        c->removed = (unsigned long long *)dmalloc(FFPIC_MAX_SPECIES * 4 * sizeof(unsigned long long));
+        c->err = (uint32_t *)dmalloc(sizeof(uint32_t));
+        c->red_len = 4096;
+        c->red = (double *)dmalloc(c->red_len * sizeof(double));
+        HCHK(hipMemset(c->nslots, 0, FFPIC_MAX_SPECIES * sizeof(int32_t)));
+        HCHK(hipMemset(c->nalive, 0, FFPIC_MAX_SPECIES * sizeof(int32_t)));
+        HCHK(hipMemset(c->removed, 0, FFPIC_MAX_SPECIES * 4 * sizeof(unsigned long long)));
+        HCHK(hipMemset(c->err, 0, sizeof(uint32_t)));
+        for (auto &e : c->ev) HCHK(hipEventCreate(&e));
+        std::vector<double> F[6];
+        init_fields_host(c, F);
+        for (int k = 0; k < 3; k++) {
+            upload_field(c, c->E[k], F[k]);
+            upload_field(c, c->B[k], F[3 + k]);
+            upload_field(c, c->B0[k], F[3 + k]);
+        }
+        psi_mask(c);
+        HCHK(hipStreamSynchronize(c->stream));
+    });
+    if (rc != FFPIC_OK) {
+        free_all(c);
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return FFPIC_OK;
+}
+
+void ffpic_destroy(ffpic_ctx *c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    free_all(c);
+    delete c;
+}
+
+const char *ffpic_last_error(const ffpic_ctx *c) {
+    if (!c) return "no context";
+    return c->last_error.c_str();
+}
+
+int ffpic_info(const ffpic_ctx *c, double out[4]) {
+    if (!c || !out) return FFPIC_EINVAL;
+    out[0] = c->dt; out[1] = c->dlog; out[2] = c->dth; out[3] = c->omega;
+    return FFPIC_OK;
+}
+
+int ffpic_load_fields(ffpic_ctx *c, int comp, const double *src, int on_dev) {
+    return guarded(c, [&] {
+        check_ctx(c);
+        if (comp < FFPIC_ER || comp > FFPIC_BPH || !src) throw Fail{FFPIC_EINVAL, "bad component or NULL source"};
+        void *dst = comp < 3 ? c->E[comp] : c->B[comp - 3];
+        const double *dsrc = src;
+        double *tmp = nullptr;
+        if (!on_dev) {
+            tmp = (double *)dmalloc(c->nn * sizeof(double));
+            HCHK(hipMemcpyAsync(tmp, src, c->nn * sizeof(double), hipMemcpyHostToDevice, c->stream));
+            dsrc = tmp;
+        }
+        from_f64(c, dsrc, dst, c->nn);
+        if (comp >= FFPIC_BR) from_f64(c, dsrc, c->B0[comp - 3], c->nn);
+        if (comp == FFPIC_BR) psi_mask(c);
+        HCHK(hipStreamSynchronize(c->stream));
+        if (tmp) HCHK(hipFree(tmp));
+    });
+}
+
+int ffpic_load_particles(ffpic_ctx *c, int s, int64_t n, const double *r, const double *th,
+                         const double *ur, const double *uth, const double *uph, int on_dev) {
+    return guarded(c, [&] {
+        check_ctx(c);
+        if (s < 0 || s >= c->d.nspec) throw Fail{FFPIC_EINVAL, "species out of range"};
+        if (n < 0) throw Fail{FFPIC_EINVAL, "negative count"};
+        if (n == 0) return;
+        if (!r || !th || !ur || !uth || !uph) throw Fail{FFPIC_EINVAL, "NULL particle array"};
+        Species &S = c->sp[s];
+        if (S.nub + n > S.cap) throw Fail{FFPIC_ECAPACITY, "species capacity exceeded"};
+        const double *src[5] = {r, th, ur, uth, uph};
+        double *stage = nullptr;
+        if (!on_dev) {
+            stage = (double *)dmalloc((size_t)n * 5 * sizeof(double));
+            for (int a = 0; a < 5; a++)
+                HCHK(hipMemcpyAsync(stage + (size_t)a * n, src[a], (size_t)n * sizeof(double),
+                                    hipMemcpyHostToDevice, c->stream));
+            for (int a = 0; a < 5; a++) src[a] = stage + (size_t)a * n;
+        }
+        convert_loaded(c, s, S.nub, n, src[0], src[1], src[2], src[3], src[4]);
+        S.nub += n;
+        int32_t ns = (int32_t)S.nub;
+        HCHK(hipMemcpyAsync(c->nslots + s, &ns, sizeof(ns), hipMemcpyHostToDevice, c->stream));
+        sort_species(c, s);
+        int32_t alive = 0;
+        HCHK(hipMemcpyAsync(&alive, c->nslots + s, sizeof(alive), hipMemcpyDeviceToHost, c->stream));
+        HCHK(hipStreamSynchronize(c->stream));
+        S.nub = alive;
+        if (stage) HCHK(hipFree(stage));
+    });
+}
+
+int ffpic_step(ffpic_ctx *c, int32_t nsteps) {
+    return guarded(c, [&] {
+        check_ctx(c);
+        if (nsteps < 0) throw Fail{FFPIC_EINVAL, "negative step count"};
+        if (c->timing) for (auto &m : c->phase_ms) m = 0.f;
+        for (int k = 0; k < nsteps; k++) {
+            uint32_t ph = FFPIC_PHASE_MASK | FFPIC_PHASE_KILL | FFPIC_PHASE_PUSH | FFPIC_PHASE_FIELDS;
+            if (c->step % c->d.sort_interval == 0) ph |= FFPIC_PHASE_SORT;
+            // the push removes particles of force-free cells itself
+            if (!(ph & FFPIC_PHASE_SORT)) ph &= ~FFPIC_PHASE_KILL;
+            one_step(c, ph, true, c->timing ? 0 : -1);
+        }
+    });
+}
+
+int ffpic_run_phases(ffpic_ctx *c, uint32_t ph) {
+    return guarded(c, [&] {
+        check_ctx(c);
+        one_step(c, ph, false, -1);
+    });
+}
+
+int ffpic_sync(ffpic_ctx *c) {
+    return guarded(c, [&] {
+        check_ctx(c);
+        HCHK(hipStreamSynchronize(c->stream));
+        read_err(c);
+    });
+}
+
+int ffpic_get_field(ffpic_ctx *c, int comp, double *dst, int on_dev) {
+    return guarded(c, [&] {
+        check_ctx(c);
+        if (comp < 0 || comp >= FFPIC_NCOMP || !dst) throw Fail{FFPIC_EINVAL, "bad component or NULL destination"};
+        double *d = dst;
+        double *tmp = nullptr;
+        if (!on_dev) { tmp = (double *)dmalloc(c->nn * sizeof(double)); d = tmp; }
+        switch (comp) {
+        case FFPIC_ER: case FFPIC_ETH: case FFPIC_EPH: to_f64(c, c->E[comp], d, c->nn); break;
+        case FFPIC_BR: case FFPIC_BTH: case FFPIC_BPH: to_f64(c, c->B[comp - 3], d, c->nn); break;
+        case FFPIC_JR: case FFPIC_JTH: case FFPIC_JPH: to_f64(c, c->J[comp - 6], d, c->nn); break;
+        case FFPIC_PSI: HCHK(hipMemcpyAsync(d, c->psi, c->nn * sizeof(double), hipMemcpyDeviceToDevice, c->stream)); break;
+        case FFPIC_F: to_f64(c, c->f, d, c->nn); break;
+        case FFPIC_GAUSS: gauss_map(c, d); break;
+        case FFPIC_DIVB: divb_map(c, d); break;
+        }
+        if (tmp) {
+            HCHK(hipMemcpyAsync(dst, tmp, c->nn * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        }
+        HCHK(hipStreamSynchronize(c->stream));
+        if (tmp) HCHK(hipFree(tmp));
+        read_err(c);
+    });
+}
+
+int ffpic_num_particles(ffpic_ctx *c, int s, int64_t *n) {
+    return guarded(c, [&] {
+        check_ctx(c);
+        if (s < 0 || s >= c->d.nspec || !n) throw Fail{FFPIC_EINVAL, "bad species or NULL"};
+        int32_t ns = 0;
+        HCHK(hipMemcpyAsync(&ns, c->nslots + s, sizeof(ns), hipMemcpyDeviceToHost, c->stream));
+        HCHK(hipStreamSynchronize(c->stream));
+        *n = ns;
+    });
+}
+
+int ffpic_get_particles(ffpic_ctx *c, int s, double *r, double *th, double *ur, double *uth,
+                        double *uph, int32_t *cell) {
+    return guarded(c, [&] {
+        check_ctx(c);
+        if (s < 0 || s >= c->d.nspec) throw Fail{FFPIC_EINVAL, "bad species"};
+        int32_t ns = 0;
+        HCHK(hipMemcpyAsync(&ns, c->nslots + s, sizeof(ns), hipMemcpyDeviceToHost, c->stream));
+        HCHK(hipStreamSynchronize(c->stream));
+        if (ns == 0) return;
+        double *buf = (double *)dmalloc((size_t)ns * (5 * sizeof(double) + sizeof(int32_t)));
+        double *o[5];
+        for (int a = 0; a < 5; a++) o[a] = buf + (size_t)a * ns;
+        int32_t *oc = (int32_t *)(buf + (size_t)5 * ns);
+        export_particles(c, s, ns, o[0], o[1], o[2], o[3], o[4], oc);
+        double *h[5] = {r, th, ur, uth, uph};
+        for (int a = 0; a < 5; a++)
+            if (h[a]) HCHK(hipMemcpyAsync(h[a], o[a], (size_t)ns * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        if (cell) HCHK(hipMemcpyAsync(cell, oc, (size_t)ns * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+        HCHK(hipStreamSynchronize(c->stream));
+        HCHK(hipFree(buf));
+    });
+}
+
+int ffpic_get_sort(ffpic_ctx *c, int s, int32_t *off) {
+    return guarded(c, [&] {
+        check_ctx(c);
+        if (s < 0 || s >= c->d.nspec || !off) throw Fail{FFPIC_EINVAL, "bad species or NULL"};
+        size_t nk = (size_t)c->nr * c->nth + 1;
+        int32_t *d = (int32_t *)dmalloc(nk * sizeof(int32_t));
+        sort_offsets(c, s, d);
+        HCHK(hipMemcpyAsync(off, d, nk * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+        HCHK(hipStreamSynchronize(c->stream));
+        HCHK(hipFree(d));
+    });
+}
+
+int ffpic_diagnostics(ffpic_ctx *c, uint32_t what, ffpic_diag *out, double *L) {
+    return guarded(c, [&] {
+        check_ctx(c);
+        if (!out) throw Fail{FFPIC_EINVAL, "NULL output"};
+        std::memset(out, 0, sizeof(*out));
+        out->step = c->step;
+        HCHK(hipStreamSynchronize(c->stream));
+        unsigned long long rem[FFPIC_MAX_SPECIES * 4];
+        int32_t ns[FFPIC_MAX_SPECIES];
+        HCHK(hipMemcpy(rem, c->removed, sizeof(rem), hipMemcpyDeviceToHost));
+        HCHK(hipMemcpy(ns, c->nslots, sizeof(ns), hipMemcpyDeviceToHost));
+        HCHK(hipMemcpy(&out->error_word, c->err, sizeof(uint32_t), hipMemcpyDeviceToHost));
+        for (int s = 0; s < c->d.nspec; s++)
+            for (int k = 0; k < 4; k++) out->removed[s][k] = (int64_t)rem[4 * s + k];
+        double *dv = (double *)dmalloc(16 * sizeof(double));
+        if (what & FFPIC_DIAG_MOMENTS) {
+            for (int s = 0; s < c->d.nspec; s++) {
+                moments(c, s, dv);
+                double h[5];
+                HCHK(hipMemcpyAsync(h, dv, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+                HCHK(hipStreamSynchronize(c->stream));
+                out->alive[s] = (int64_t)h[0];
+                out->sum_gamma[s] = h[1];
+                for (int k = 0; k < 3; k++) out->sum_u[s][k] = h[2 + k];
+            }
+        }
+        if (what & FFPIC_DIAG_ENERGY) {
+            energies(c, dv);
+            double h[2];
+            HCHK(hipMemcpyAsync(h, dv, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+            HCHK(hipStreamSynchronize(c->stream));
+            out->energy_e = h[0];
+            out->energy_b = h[1];
+        }
+        if (what & FFPIC_DIAG_RESIDUALS) {
+            double *m = (double *)dmalloc(c->nn * sizeof(double));
+            gauss_map(c, m);
+            out->gauss_max = max_abs(c, m, c->nn);
+            divb_map(c, m);
+            out->divb_max = max_abs(c, m, c->nn);
+            HCHK(hipFree(m));
+        }
+        if ((what & FFPIC_DIAG_POYNTING) && L) {
+            double *dl = (double *)dmalloc((c->nr + 1) * sizeof(double));
+            poynting(c, dl);
+            HCHK(hipMemcpyAsync(L, dl, (c->nr + 1) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            HCHK(hipStreamSynchronize(c->stream));
+            HCHK(hipFree(dl));
+        }
+        HCHK(hipFree(dv));
+    });
+}
+
+// ---------------------------------------------------------------------------
+// checkpoints: header, then raw device images of the state
+
+namespace {
+struct SaveHeader {
+    char magic[8];
+    uint32_t version, precision;
+    int32_t nr, nth, nspec, pad;
+    int64_t step;
+    int64_t nslots[FFPIC_MAX_SPECIES];
+    unsigned long long removed[FFPIC_MAX_SPECIES * 4];
+    uint32_t err, pad2;
+};
+
+size_t save_size(ffpic_ctx *c, const int32_t *ns) {
+    size_t fb = c->nn * c->rsz;
+    size_t bytes = sizeof(SaveHeader) + 9 * fb + c->nn * sizeof(double) + fb;
+    for (int s = 0; s < c->d.nspec; s++)
+        bytes += (size_t)ns[s] * (c->fp64 ? 5 * 8 : 6 * 4);
+    return bytes;
+}
+}  // namespace
+
+int ffpic_save(ffpic_ctx *c, void *buf, size_t *len) {
+    return guarded(c, [&] {
+        check_ctx(c);
+        if (!len) throw Fail{FFPIC_EINVAL, "NULL length"};
+        HCHK(hipStreamSynchronize(c->stream));
+        int32_t ns[FFPIC_MAX_SPECIES] = {};
+        HCHK(hipMemcpy(ns, c->nslots, sizeof(ns), hipMemcpyDeviceToHost));
+        size_t need = save_size(c, ns);
+        if (!buf) { *len = need; return; }
+        if (*len < need) throw Fail{FFPIC_EINVAL, "checkpoint buffer too small"};
+        SaveHeader h{};
+        std::memcpy(h.magic, "FFPICSV1", 8);
+        h.version = 1;
+        h.precision = (uint32_t)c->d.precision;
+        h.nr = c->nr; h.nth = c->nth; h.nspec = c->d.nspec;
+        h.step = c->step;
+        for (int s = 0; s < FFPIC_MAX_SPECIES; s++) h.nslots[s] = ns[s];
+        HCHK(hipMemcpy(h.removed, c->removed, sizeof(h.removed), hipMemcpyDeviceToHost));
+        HCHK(hipMemcpy(&h.err, c->err, sizeof(uint32_t), hipMemcpyDeviceToHost));
+        char *p = (char *)buf;
+        std::memcpy(p, &h, sizeof(h));
+        p += sizeof(h);
+        size_t fb = c->nn * c->rsz;
+        void *arrs[9] = {c->E[0], c->E[1], c->E[2], c->B[0], c->B[1], c->B[2], c->B0[0], c->B0[1], c->B0[2]};
+        for (void *a : arrs) { HCHK(hipMemcpy(p, a, fb, hipMemcpyDeviceToHost)); p += fb; }
+        HCHK(hipMemcpy(p, c->psi, c->nn * sizeof(double), hipMemcpyDeviceToHost)); p += c->nn * sizeof(double);
+        HCHK(hipMemcpy(p, c->f, fb, hipMemcpyDeviceToHost)); p += fb;
+        size_t eb = c->fp64 ? 8 : 4;
+        for (int s = 0; s < c->d.nspec; s++)
+            for (int a = 0; a < c->sp[s].narr; a++) {
+                HCHK(hipMemcpy(p, c->sp[s].cur[a], (size_t)ns[s] * eb, hipMemcpyDeviceToHost));
+                p += (size_t)ns[s] * eb;
+            }
+        *len = need;
+    });
+}
+
+int ffpic_restore(ffpic_ctx *c, const void *buf, size_t len) {
+    return guarded(c, [&] {
+        check_ctx(c);
+        if (!buf || len < sizeof(SaveHeader)) throw Fail{FFPIC_EINVAL, "checkpoint too short"};
+        SaveHeader h;
+        std::memcpy(&h, buf, sizeof(h));
+        if (std::memcmp(h.magic, "FFPICSV1", 8) != 0 || h.version != 1)
+            throw Fail{FFPIC_EINVAL, "not a checkpoint of this library"};
+        if (h.precision != (uint32_t)c->d.precision || h.nr != c->nr || h.nth != c->nth ||
+            h.nspec != c->d.nspec)
+            throw Fail{FFPIC_EINVAL, "checkpoint does not match this context"};
+        int32_t ns[FFPIC_MAX_SPECIES] = {};
+        for (int s = 0; s < FFPIC_MAX_SPECIES; s++) ns[s] = (int32_t)h.nslots[s];
+        for (int s = 0; s < c->d.nspec; s++)
+            if (ns[s] > c->sp[s].cap) throw Fail{FFPIC_ECAPACITY, "checkpoint exceeds capacity"};
+        if (len < save_size(c, ns)) throw Fail{FFPIC_EINVAL, "checkpoint truncated"};
+        HCHK(hipStreamSynchronize(c->stream));
+        const char *p = (const char *)buf + sizeof(h);
+        size_t fb = c->nn * c->rsz;
+        void *arrs[9] = {c->E[0], c->E[1], c->E[2], c->B[0], c->B[1], c->B[2], c->B0[0], c->B0[1], c->B0[2]};
+        for (void *a : arrs) { HCHK(hipMemcpy(a, p, fb, hipMemcpyHostToDevice)); p += fb; }
+        HCHK(hipMemcpy(c->psi, p, c->nn * sizeof(double), hipMemcpyHostToDevice)); p += c->nn * sizeof(double);
+        HCHK(hipMemcpy(c->f, p, fb, hipMemcpyHostToDevice)); p += fb;
+        size_t eb = c->fp64 ? 8 : 4;
+        for (int s = 0; s < c->d.nspec; s++) {
+            for (int a = 0; a < c->sp[s].narr; a++) {
+                HCHK(hipMemcpy(c->sp[s].cur[a], p, (size_t)ns[s] * eb, hipMemcpyHostToDevice));
+                p += (size_t)ns[s] * eb;
+            }
+            c->sp[s].nub = ns[s];
+        }
+        HCHK(hipMemcpy(c->nslots, ns, sizeof(ns), hipMemcpyHostToDevice));
+        HCHK(hipMemcpy(c->removed, h.removed, sizeof(h.removed), hipMemcpyHostToDevice));
+        HCHK(hipMemcpy(c->err, &h.err, sizeof(uint32_t), hipMemcpyHostToDevice));
+        for (int k = 0; k < 3; k++) HCHK(hipMemset(c->J[k], 0, fb));
+        // the kill flags follow from Psi
+        psi_mask(c);
+        HCHK(hipStreamSynchronize(c->stream));
+        c->step = h.step;
+    });
+}
+
+int ffpic_set_timing(ffpic_ctx *c, int enable) {
+    if (!c) return FFPIC_EINVAL;
+    c->timing = enable ? 1 : 0;
+    return FFPIC_OK;
+}
+
+int ffpic_phase_times(ffpic_ctx *c, float out[4]) {
+    if (!c || !out) return FFPIC_EINVAL;
+    for (int k = 0; k < 4; k++) out[k] = c->phase_ms[k];
+    return FFPIC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,244 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 CPU
+oracle on the same seeded inputs.
+
+Tolerances: bit-exact for the particle -> cell index, the sort permutation,
+the flux function and the initial fields; 1e-12 relative (L2 over nodes, per
+component) for the FP64 path; 2e-5 relative for the FP32-mixed path after
+100 steps.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2406_14512_amd import ffpic
+from paper_2406_14512_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = [(ffpic.ER, oracle.ER, "Er"), (ffpic.ETH, oracle.ETH, "Eth"), (ffpic.EPH, oracle.EPH, "Eph"),
+          (ffpic.BR, oracle.BR, "Br"), (ffpic.BTH, oracle.BTH, "Bth"), (ffpic.BPH, oracle.BPH, "Bph")]
+FP64_TOL = 1e-12
+FP32_TOL = 2e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    oracle.build(force=False)
+    ffpic.lib()
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a - b)
+
+
+def pair(w, precision=W.FP64, cap=None):
+    d = w.desc()
+    d["precision"] = precision
+    cap = cap if cap is not None else max(w.n_per_species, 1)
+    sim = ffpic.Sim(d, capacity=[cap] * d["nspec"])
+    ora = oracle.Oracle(d)
+    return sim, ora
+
+
+def load_both(sim, ora, w, limit=None):
+    for s in range(w.nspec):
+        p = w.particles(s, limit)
+        sim.load_particles(s, p)
+        ora.load(s, p)
+
+
+def field_errors(sim, ora, comps=FIELDS):
+    return {name: rel(sim.field(g), ora.field(o)) for g, o, name in comps}
+
+
+def moment_errors(sim, ora, nspec):
+    dg = sim.diagnostics(ffpic.DIAG_MOMENTS)
+    out = {}
+    for s in range(nspec):
+        mo = ora.moments(s)
+        out[f"n{s}"] = abs(dg["alive"][s] - mo[0])
+        out[f"gamma{s}"] = abs(dg["sum_gamma"][s] - mo[1]) / abs(mo[1])
+        for k, nm in enumerate(("ur", "uth", "uph")):
+            scale = max(abs(mo[2 + k]), 1e-3 * mo[1])
+            out[f"{nm}{s}"] = abs(dg["sum_u"][s][k] - mo[2 + k]) / scale
+    return out
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("init", [W.INIT_DIPOLE, W.INIT_MONOPOLE, W.INIT_MICHEL,
+                                  W.INIT_OPEN_DIPOLE])
+def test_initial_fields_and_psi_bit_exact_fp64(init):
+    w = W.tiny_open_dipole(10)
+    w.nr, w.nth, w.init = 96, 80, init
+    sim, ora = pair(w)
+    for g, o, name in FIELDS:
+        assert np.array_equal(sim.field(g), ora.field(o)), name
+    assert np.array_equal(sim.field(ffpic.PSI), ora.field(oracle.PSI))
+    assert np.array_equal(sim.field(ffpic.F), ora.field(oracle.F))
+
+
+def test_psi_bit_exact_fp32_from_rounded_br():
+    w = W.tiny_open_dipole(10)
+    w.nr, w.nth = 96, 80
+    sim, ora = pair(w, W.FP32_MIXED)
+    br32 = sim.field(ffpic.BR)
+    assert np.array_equal(br32, ora.field(oracle.BR).astype(np.float32).astype(np.float64))
+    ora.set_field(oracle.BR, br32)                  # oracle Psi of the same FP32 B_r
+    assert np.array_equal(sim.field(ffpic.PSI), ora.field(oracle.PSI))
+    assert np.array_equal(sim.field(ffpic.F), ora.field(oracle.F))
+
+
+@pytest.mark.parametrize("precision", [W.FP64, W.FP32_MIXED])
+def test_load_cells_and_sort_permutation_bit_exact(precision):
+    w = W.tiny_open_dipole(30_000)
+    sim, ora = pair(w, precision)
+    load_both(sim, ora, w)
+    for s in range(2):
+        g, o = sim.particles(s), ora.particles(s)
+        assert len(g["cell"]) == len(o["cell"]) > 1000
+        assert np.array_equal(g["cell"], o["cell"])
+        if precision == W.FP64:
+            for k in ("r", "th", "ur", "uth", "uph"):
+                assert np.array_equal(g[k], o[k]), k
+        else:
+            assert np.allclose(g["r"], o["r"], rtol=1e-7, atol=0)
+            assert np.allclose(g["uph"], o["uph"].astype(np.float32), rtol=0, atol=0)
+        assert np.array_equal(sim.sort_offsets(s), ora.sort_offsets(s))
+        assert np.array_equal(sim.diagnostics(ffpic.DIAG_MOMENTS)["removed"][s],
+                              ora.removed(s))
+
+
+def test_push_and_deposit_one_step_fp64():
+    w = W.tiny_dipole(50_000)
+    sim, ora = pair(w)
+    load_both(sim, ora, w)
+    sim.run_phases(ffpic.PHASE_PUSH)
+    ora.phases(oracle.PHASE_PUSH)
+    for s in range(2):
+        g, o = sim.particles(s), ora.particles(s)
+        assert np.array_equal(g["cell"], o["cell"])
+        live = o["cell"] >= 0
+        for k in ("r", "th", "ur", "uth", "uph"):
+            assert np.allclose(g[k][live], o[k][live], rtol=1e-13, atol=1e-13), k
+    for gc, oc in ((ffpic.JR, oracle.JR), (ffpic.JTH, oracle.JTH), (ffpic.JPH, oracle.JPH)):
+        assert rel(sim.field(gc), ora.field(oc)) < FP64_TOL
+
+
+def test_field_step_fp64():
+    w = W.tiny_open_dipole(50_000)
+    sim, ora = pair(w)
+    load_both(sim, ora, w)
+    for ph_g, ph_o in ((ffpic.PHASE_PUSH, oracle.PHASE_PUSH), (ffpic.PHASE_FIELDS, oracle.PHASE_FIELDS)):
+        sim.run_phases(ph_g)
+        ora.phases(ph_o)
+    errs = field_errors(sim, ora)
+    assert max(errs.values()) < FP64_TOL, errs
+
+
+@pytest.mark.parametrize("factory", [W.tiny_dipole, W.tiny_open_dipole])
+def test_full_steps_fp64(factory):
+    w = factory(100_000, steps=20)
+    sim, ora = pair(w)
+    load_both(sim, ora, w)
+    sim.step(20)
+    ora.step(20)
+    sim.sync()
+    errs = field_errors(sim, ora)
+    assert max(errs.values()) < FP64_TOL, errs
+    m = moment_errors(sim, ora, 2)
+    for k, v in m.items():
+        assert v < (0.5 if k.startswith("n") else FP64_TOL), (k, v)
+    for s in range(2):
+        g, o = sim.particles(s), ora.particles(s)
+        assert len(g["cell"]) == len(o["cell"])
+        assert np.count_nonzero(g["cell"] != o["cell"]) == 0
+
+
+def test_michel_monopole_pure_ff_fp64_gpu():
+    w = W.michel_monopole(64, pure_ff=True, init=W.INIT_MONOPOLE)
+    sim, ora = pair(w, cap=1)
+    sim.step(200)
+    ora.step(200)
+    errs = field_errors(sim, ora)
+    assert max(errs.values()) < FP64_TOL, errs
+    L = sim.diagnostics(ffpic.DIAG_ENERGY, poynting=True)["L"]
+    assert np.allclose(L, ora.poynting(), rtol=1e-10, atol=1e-14)
+
+
+def small_sheet(n_total=200_000, nr=256):
+    w = W.sheet_1024(n_total=n_total, steps=100)
+    w.nr = w.nth = nr
+    return w
+
+
+def test_fp32_mixed_vs_fp64_oracle_100_steps():
+    w = small_sheet()
+    sim, ora = pair(w, W.FP32_MIXED)
+    load_both(sim, ora, w)
+    sim.step(100)
+    ora.step(100)
+    sim.sync()
+    errs = field_errors(sim, ora)
+    print("FP32-mixed field errors after 100 steps:", errs)
+    assert max(errs.values()) < FP32_TOL, errs
+    m = moment_errors(sim, ora, 2)
+    print("FP32-mixed moment errors after 100 steps:", m)
+    for k, v in m.items():
+        if k.startswith("n"):
+            assert v <= 2e-5 * w.n_per_species + 2, (k, v)
+        else:
+            assert v < FP32_TOL, (k, v)
+
+
+def test_residual_maps_match_oracle_fp64():
+    w = W.tiny_dipole(50_000)
+    sim, ora = pair(w)
+    load_both(sim, ora, w)
+    sim.step(5)
+    ora.step(5)
+    g, o = sim.field(ffpic.GAUSS), ora.gauss()
+    assert rel(g, o) < 1e-10
+    g, o = sim.field(ffpic.DIVB), ora.divb()
+    assert np.allclose(g, o, rtol=1e-9, atol=1e-9 * np.abs(o).max())
+    dg = sim.diagnostics(ffpic.DIAG_RESIDUALS)
+    assert abs(dg["gauss_max"] - np.abs(ora.gauss()).max()) <= 1e-9 * np.abs(ora.gauss()).max()
+
+
+@pytest.mark.parametrize("precision", [W.FP64, W.FP32_MIXED])
+def test_save_restore_resumes(precision):
+    w = W.tiny_open_dipole(20_000)
+    sim, _ = pair(w, precision)
+    for s in range(2):
+        sim.load_particles(s, w.particles(s))
+    sim.step(3)
+    blob = sim.save()
+    sim.step(4)
+    a = {n: sim.field(g) for g, _, n in FIELDS}
+    pa = sim.particles(0)
+    sim.restore(blob)
+    assert sim.diagnostics(0)["step"] == 3
+    sim.step(4)
+    b = {n: sim.field(g) for g, _, n in FIELDS}
+    pb = sim.particles(0)
+    tol = 1e-13 if precision == W.FP64 else 1e-6
+    for n in a:
+        assert rel(b[n], a[n]) < tol, n
+    assert np.array_equal(pa["cell"], pb["cell"])
+
+
+def test_error_paths():
+    w = W.tiny_dipole(100)
+    sim, _ = pair(w, cap=150)
+    p = w.particles(0)
+    p["r"][:5] = np.nan
+    p["th"][5:8] = -1.0
+    sim.load_particles(0, p)
+    assert sim.n(0) == 92
+    assert sim.diagnostics(0)["removed"][0][0] == 8
+    with pytest.raises(ffpic.FfpicError) as e:
+        sim.load_particles(0, w.particles(0))          # 92 + 100 > 150 slots
+    assert e.value.code == ffpic.ECAPACITY
+    assert sim.n(0) == 92
