@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""Throughput of the hybrid force-free / PIC step on one MI355X.
+
+Workload (the 4096^2 magnetosphere): 4096 x 4096 (r, theta) grid, r log-spaced
+on [1, 100], light cylinder at r = 10, 4e8 e+- macro-particles (99% in a sech^2
+current sheet of width 0.02 rad beyond the light cylinder drifting at
++-0.5c in phi, 1% at rest in the closed zone), open-dipole field with the
+force-free domain on open lines below 0.85 Psi_pc, radiation reaction on,
+sort every 8 steps.  Inputs are seeded and synthetic and resident in HBM
+before the timed region.
+
+A "step" is one full hybrid step: flux function + mask, (every 8th step)
+stable sort, push + deposit of both species, fused field update with the
+force-free current and E correction.  The headline is the FP32-mixed path;
+the plain FP64 GPU path is timed on the same workload beside it.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/sec + cell-updates/sec at 4096² grid; FP32-mixed vs FP64 GPU"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_PARTICLE = {1: 48.0, 0: 80.0}   # algorithmic push+deposit bytes (read + write state)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_sim(ffpic, w, precision):
+    d = w.desc()
+    d["precision"] = precision
+    return ffpic.Sim(d, capacity=[w.n_per_species] * w.nspec)
+
+
+def run_timed(ffpic, sim, steps, warmup, nspec):
+    sim.step(warmup)
+    sim.sync()
+    alive0 = sum(sim.diagnostics(ffpic.DIAG_MOMENTS)["alive"])
+    sim.set_timing(True)
+    sim.sync()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    t1 = time.perf_counter()
+    sim.set_timing(False)
+    ph = sim.phase_times()
+    alive1 = sum(sim.diagnostics(ffpic.DIAG_MOMENTS)["alive"])
+    wall = t1 - t0
+    return dict(wall=wall, phases=ph, alive0=alive0, alive1=alive1)
+
+
+def roofline(precision, res, steps, nspec):
+    # dominant kernel: the push + deposit kernel, one launch per species and
+    # step; algorithmic bytes = state read + written per live particle
+    n_avg = 0.5 * (res["alive0"] + res["alive1"])
+    push_ms = res["phases"][2]
+    launches = steps * nspec
+    avg_launch_s = push_ms / 1e3 / launches
+    bytes_per_launch = BYTES_PER_PARTICLE[precision] * n_avg / nspec
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k_push32" if precision == 1 else "k_push64",
+            "avg_launch_ms": round(avg_launch_s * 1e3, 4),
+            "bytes_per_launch": bytes_per_launch}
+
+
+def cpu_baseline(w, n_sample, steps=2):
+    import oracle
+    oracle.build(force=False)
+    o = oracle.Oracle(w.desc())
+    per = n_sample // w.nspec
+    for s in range(w.nspec):
+        o.load(s, w.particles(s, limit=per))
+    n = sum(o.n(s) for s in range(w.nspec))
+    t_push = t_grid = 0.0
+    for k in range(steps):
+        t0 = time.perf_counter()
+        o.phases(oracle.PHASE_MASK | oracle.PHASE_KILL | (oracle.PHASE_SORT if k == 0 else 0))
+        t1 = time.perf_counter()
+        o.phases(oracle.PHASE_PUSH)
+        t2 = time.perf_counter()
+        o.phases(oracle.PHASE_FIELDS)
+        t3 = time.perf_counter()
+        t_push += t2 - t1
+        t_grid += (t1 - t0) + (t3 - t2)
+    per_particle = t_push / (steps * n)
+    grid_step = t_grid / steps
+    n_full = w.n_per_species * w.nspec
+    step_full = grid_step + per_particle * n_full
+    return {"value": n_full / step_full, "unit": "particle-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": (f"{n} particles of the same workload on the full {w.nr}x{w.nth} grid, "
+                       f"{steps} steps; push time per particle ({per_particle*1e9:.0f} ns) and "
+                       f"grid time per step ({grid_step:.2f} s) scaled to {n_full:.3g} particles"),
+            "cell_updates_per_s": w.nr * w.nth / grid_step}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=8)
+    ap.add_argument("--n-total", type=int, default=400_000_000)
+    ap.add_argument("--grid", type=int, default=4096)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=2_000_000)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2406_14512_amd import ffpic
+    from paper_2406_14512_amd import workloads as W
+
+    w = W.sheet_4096(n_total=args.n_total)
+    w.nr = w.nth = args.grid
+    precisions = [1] if args.no_fp64 else [1, 0]
+    sims = {p: make_sim(ffpic, w, p) for p in precisions}
+    t0 = time.perf_counter()
+    for s in range(w.nspec):
+        for c in range(w.n_chunks()):
+            chunk = w.chunk(s, c)
+            for p in precisions:
+                sims[p].load_particles(s, chunk)
+        log(f"loaded species {s}: {sims[1].n(s)} live particles "
+            f"({time.perf_counter() - t0:.1f} s)")
+
+    results = {}
+    for p in precisions:
+        log(f"timing {'FP32-mixed' if p == 1 else 'FP64'}: {args.warmup} warmup + {args.steps} steps")
+        results[p] = run_timed(ffpic, sims[p], args.steps, args.warmup, w.nspec)
+        r = results[p]
+        log(f"  {r['wall'] / args.steps * 1e3:.3f} ms/step, phases (ms/step) mask/sort/push/fields "
+            + " ".join(f"{x / args.steps:.3f}" for x in r["phases"]))
+        if p == 0:
+            sims[p].close()
+
+    r = results[1]
+    n_avg = 0.5 * (r["alive0"] + r["alive1"])
+    ms = r["wall"] / args.steps * 1e3
+    value = n_avg * args.steps / r["wall"]
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": (f"sheet_{w.nr}: {w.nr}x{w.nth} (r, theta) grid, r in [1, 100], "
+                                f"R_LC = 10, {w.n_per_species * w.nspec:.3g} e+- (99% sech^2 sheet "
+                                "of width 0.02, 1% closed-zone background), open dipole with "
+                                "force-free open lines, radiation reaction on, sort every 8 steps"),
+                   "grid": f"{w.nr}x{w.nth}", "particles": int(n_avg),
+                   "precision": "fp32-mixed", "sort_interval": w.sort_interval},
+        "cell_updates_per_s": w.nr * w.nth * args.steps / r["wall"],
+        "phase_ms_per_step": {k: round(v / args.steps, 4)
+                              for k, v in zip(("mask", "sort", "push_deposit", "fields"), r["phases"])},
+        "roofline": roofline(1, r, args.steps, w.nspec),
+    }
+    if 0 in results:
+        r64 = results[0]
+        n64 = 0.5 * (r64["alive0"] + r64["alive1"])
+        out["fp64"] = {"value": n64 * args.steps / r64["wall"], "unit": "particle-steps/s",
+                       "ms_per_step": r64["wall"] / args.steps * 1e3,
+                       "cell_updates_per_s": w.nr * w.nth * args.steps / r64["wall"],
+                       "phase_ms_per_step": {k: round(v / args.steps, 4) for k, v in
+                                             zip(("mask", "sort", "push_deposit", "fields"),
+                                                 r64["phases"])},
+                       "roofline": roofline(0, r64, args.steps, w.nspec)}
+        out["fp32_over_fp64"] = out["value"] / out["fp64"]["value"]
+    sims[1].close()
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a sample")
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

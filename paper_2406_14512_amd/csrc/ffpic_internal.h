@@ -70,6 +70,10 @@ struct ffpic_ctx {
     double *dtab64[ffpic::T_NTAB] = {};       // device FP64 tables
     size_t rsz = 8;                           // sizeof(R)
     void *E[3] = {}, *B[3] = {}, *B0[3] = {}, *J[3] = {};
+    // FP32 mode: perturbation state about the FP64 background (see
+    // fields_pert.h) and the background's rates evaluated in FP64
+    void *dE[3] = {}, *dB[3] = {}, *E0[3] = {}, *rE0[3] = {}, *rB0[3] = {}, *rho0 = nullptr;
+    std::vector<double> hE0[3], hB0[3];       // FP64 background (host)
     void *scr[6] = {};                        // node scratch (J_FFE, E corrections)
     double *psi = nullptr;
     void *f = nullptr;
@@ -89,6 +93,7 @@ struct ffpic_ctx {
     bool sorted_once[FFPIC_MAX_SPECIES] = {};
     int timing = 0;
     hipEvent_t ev[8] = {};
+    std::vector<hipEvent_t> evpool;           // 5 per timed step
     float phase_ms[4] = {};
     std::string last_error;
 };

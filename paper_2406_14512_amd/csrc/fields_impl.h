@@ -26,6 +26,7 @@ __global__ void __launch_bounds__(64) k_psi(Geo<double> g, const R *__restrict__
     double acc = 0.0;
     out[0] = 0.0;
     for (int j = 0; j < g.nth; j++) {
+#pragma clang fp contract(off)
         acc = acc + (double)row[j] * (r2 * g.dcn[j]);
         out[j + 1] = acc;
     }

@@ -208,9 +208,10 @@ __global__ void k_final(const double *part, int nblk, double *out) {
 }
 
 template <bool F64>
-__global__ void k_moments(int n, const void *c0, const void *u0, const void *u1, const void *u2,
+__global__ void k_moments(int nub, const int32_t *nslots, const void *c0, const void *u0, const void *u1, const void *u2,
                           double *part) {
     double v[5] = {0, 0, 0, 0, 0};
+    const int n = min(nub, nslots[0]);
     for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
         double ur, ut, up;
         bool live;
@@ -233,10 +234,10 @@ void moments(ffpic_ctx *c, int s, double *out5) {
     ffpic::Species &S = c->sp[s];
     int n = (int)S.nub;
     if (c->fp64)
-        hipLaunchKernelGGL(k_moments<true>, dim3(kRedBlocks), dim3(256), 0, c->stream, n,
+        hipLaunchKernelGGL(k_moments<true>, dim3(kRedBlocks), dim3(256), 0, c->stream, n, c->nslots + s,
                            S.cur[0], S.cur[2], S.cur[3], S.cur[4], c->red);
     else
-        hipLaunchKernelGGL(k_moments<false>, dim3(kRedBlocks), dim3(256), 0, c->stream, n,
+        hipLaunchKernelGGL(k_moments<false>, dim3(kRedBlocks), dim3(256), 0, c->stream, n, c->nslots + s,
                            S.cur[0], S.cur[3], S.cur[4], S.cur[5], c->red);
     hipLaunchKernelGGL(k_final<5>, dim3(1), dim3(256), 0, c->stream, c->red, kRedBlocks, out5);
     FFPIC_LAUNCH_CHECK();
@@ -244,11 +245,11 @@ void moments(ffpic_ctx *c, int s, double *out5) {
 
 // node charge sum Q S_xi S_eta (FP64 atomics) into `q`
 template <bool F64>
-__global__ void k_charge(int n, int nr, int nth, int ld, double rmin, double dlog, double dth,
+__global__ void k_charge(int n, const int32_t *nslots, int nr, int nth, int ld, double rmin, double dlog, double dth,
                          const double *rn, const double *thn, const void *c0, const void *c1,
                          const void *c2, double Q, double *qn) {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= n) return;
+    if (q >= n || q >= nslots[0]) return;
     int i, j;
     double a, b;
     if (F64) {
@@ -292,11 +293,11 @@ void gauss_map(ffpic_ctx *c, double *map) {
         double Q = (S.qm > 0 ? 1.0 : -1.0) * S.weight;
         int nb = (int)((S.nub + 255) / 256);
         if (c->fp64)
-            hipLaunchKernelGGL(k_charge<true>, dim3(nb), dim3(256), 0, c->stream, (int)S.nub, c->nr,
+            hipLaunchKernelGGL(k_charge<true>, dim3(nb), dim3(256), 0, c->stream, (int)S.nub, c->nslots + s, c->nr,
                                c->nth, c->ld, c->d.rmin, c->dlog, c->dth, c->dtab64[T_RN],
                                c->dtab64[T_THN], S.cur[0], S.cur[1], S.cur[2], Q, qn);
         else
-            hipLaunchKernelGGL(k_charge<false>, dim3(nb), dim3(256), 0, c->stream, (int)S.nub, c->nr,
+            hipLaunchKernelGGL(k_charge<false>, dim3(nb), dim3(256), 0, c->stream, (int)S.nub, c->nslots + s, c->nr,
                                c->nth, c->ld, c->d.rmin, c->dlog, c->dth, c->dtab64[T_RN],
                                c->dtab64[T_THN], S.cur[0], S.cur[1], S.cur[2], Q, qn);
     }

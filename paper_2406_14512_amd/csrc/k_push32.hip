@@ -264,7 +264,13 @@ __global__ void __launch_bounds__(kWG) k_push32(
                 if (j2 > p.nth - 1) { j2 = p.nth - 1; nb = 0.99999994f; dj = j2 - j; }
                 bool cfl = di > 1 || di < -1 || dj > 1 || dj < -1;
                 if (cfl) atomicOr(err, FFPIC_ERR_CFL);
-                if (i2 < 0) {
+                bool finite = isfinite(g) && isfinite(na) && isfinite(nb) && isfinite(rx) &&
+                              isfinite(ry) && isfinite(rz);
+                if (!finite) {
+                    // flagged in the error word; never deposited
+                    atomicOr(err, FFPIC_ERR_NONFINITE);
+                    CELL[q] = -1;
+                } else if (i2 < 0) {
                     CELL[q] = -1;
                     nstar++;
                 } else if (i2 > p.iabs || (i2 == p.iabs && na >= p.aabs)) {
@@ -281,7 +287,7 @@ __global__ void __launch_bounds__(kWG) k_push32(
                     x1 = a; y1 = b;
                     x2 = (float)di + na;
                     y2 = (float)dj + nb;
-                    qv = ry * (1.f / g);
+                    qv = ny * (1.f / g);
                     if (dep && di == 0 && dj == 0) {
                         simple = true;
                         float ddx = x2 - x1, ddy = y2 - y1;

@@ -227,8 +227,79 @@ void upload_field(ffpic_ctx *c, void *dst, const std::vector<double> &h) {
     }
 }
 
+// FP32 mode: rates of the FP64 background fields under the discrete
+// operators of the field step, evaluated in FP64 (see fields_pert.h):
+// Faraday rate -curl E0 at B positions, Ampere rate curl B0 at the E
+// positions the step updates, and rho0 = div E0 / 4 pi at nodes.
+void upload_background(ffpic_ctx *c) {
+    const int nr = c->nr, nth = c->nth, ld = c->ld;
+    const auto &T = c->tab;
+    const auto &E0 = c->hE0, &B0 = c->hB0;
+    std::vector<double> rB[3], rE[3], rho(c->nn, 0.0);
+    for (int k = 0; k < 3; k++) { rB[k].assign(c->nn, 0.0); rE[k].assign(c->nn, 0.0); }
+    auto at = [&](const std::vector<double> &a, int i, int j) { return a[(size_t)i * ld + j]; };
+    auto set = [&](std::vector<double> &a, int i, int j, double v) { a[(size_t)i * ld + j] = v; };
+    for (int i = 0; i <= nr; i++)
+        for (int j = 0; j <= nth; j++) {
+            if (j < nth) {
+                double circ = T[T_RN][i] * (T[T_SN][j + 1] * at(E0[2], i, j + 1) - T[T_SN][j] * at(E0[2], i, j));
+                set(rB[0], i, j, -circ / (T[T_RN2][i] * T[T_DCN][j]));
+            }
+            if (i < nr) {
+                if (j > 0 && j < nth) {
+                    double circ = T[T_SN][j] * (T[T_RN][i + 1] * at(E0[2], i + 1, j) - T[T_RN][i] * at(E0[2], i, j));
+                    set(rB[1], i, j, circ / (T[T_SN][j] * T[T_DR2N][i]));
+                }
+                if (j < nth) {
+                    double circ = c->dth * (T[T_RN][i + 1] * at(E0[1], i + 1, j) - T[T_RN][i] * at(E0[1], i, j)) -
+                                  T[T_DRN][i] * (at(E0[0], i, j + 1) - at(E0[0], i, j));
+                    set(rB[2], i, j, -circ / (c->dth * T[T_DR2N][i]));
+                }
+                double A = T[T_RH2][i] * T[T_DCD][j];
+                double circ = (j < nth ? T[T_RH][i] * T[T_SH][j] * at(B0[2], i, j) : 0.0) -
+                              (j > 0 ? T[T_RH][i] * T[T_SH][j - 1] * at(B0[2], i, j - 1) : 0.0);
+                set(rE[0], i, j, circ / A);
+            }
+            if (i >= 1 && i < nr) {
+                if (j < nth) {
+                    double A = T[T_SH][j] * T[T_DR2H][i];
+                    double circ = -(T[T_RH][i] * T[T_SH][j] * at(B0[2], i, j) -
+                                    T[T_RH][i - 1] * T[T_SH][j] * at(B0[2], i - 1, j));
+                    set(rE[1], i, j, circ / A);
+                }
+                if (j >= 1 && j < nth) {
+                    double A = T[T_DTHD][j] * T[T_DR2H][i];
+                    double circ = c->dth * (T[T_RH][i] * at(B0[1], i, j) - T[T_RH][i - 1] * at(B0[1], i - 1, j)) -
+                                  T[T_DRH][i] * (at(B0[0], i, j) - at(B0[0], i, j - 1));
+                    set(rE[2], i, j, circ / A);
+                }
+            }
+        }
+    auto dive = [&](int i, int j) {
+        double flux = T[T_RH2][i] * T[T_DCD][j] * at(E0[0], i, j) -
+                      T[T_RH2][i - 1] * T[T_DCD][j] * at(E0[0], i - 1, j);
+        if (j < nth) flux += T[T_SH][j] * T[T_DR2H][i] * at(E0[1], i, j);
+        if (j > 0) flux -= T[T_SH][j - 1] * T[T_DR2H][i] * at(E0[1], i, j - 1);
+        return flux / (T[T_DR3H][i] * T[T_DCD][j]);
+    };
+    for (int i = 0; i < nr; i++)
+        for (int j = 0; j <= nth; j++) set(rho, i, j, dive(i == 0 ? 1 : i, j) / (4.0 * kPi));
+    auto up = [&](void *dst, const std::vector<double> &h) {
+        std::vector<float> f(h.begin(), h.end());
+        HCHK(hipMemcpy(dst, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+    };
+    for (int k = 0; k < 3; k++) {
+        up(c->rB0[k], rB[k]);
+        up(c->rE0[k], rE[k]);
+        up(c->E0[k], E0[k]);
+    }
+    up(c->rho0, rho);
+}
+
 void free_all(ffpic_ctx *c) {
     auto F = [](void *p) { if (p) (void)hipFree(p); };
+    for (int k = 0; k < 3; k++) { F(c->dE[k]); F(c->dB[k]); F(c->E0[k]); F(c->rE0[k]); F(c->rB0[k]); }
+    F(c->rho0);
     for (int t = 0; t < T_NTAB; t++) {
         if (c->dtab[t] != (void *)c->dtab64[t]) F(c->dtab[t]);
         F(c->dtab64[t]);
@@ -242,6 +313,8 @@ void free_all(ffpic_ctx *c) {
     F(c->sort_tmp); F(c->nslots); F(c->nalive); F(c->removed); F(c->err); F(c->red);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
+    for (auto &e : c->evpool) (void)hipEventDestroy(e);
+    c->evpool.clear();
 }
 
 void check_ctx(ffpic_ctx *c) {
@@ -263,7 +336,7 @@ int read_err(ffpic_ctx *c) {
 
 void one_step(ffpic_ctx *c, uint32_t ph, bool count_step, int tslot) {
     auto mark = [&](int k) {
-        if (c->timing && tslot >= 0) HCHK(hipEventRecord(c->ev[k], c->stream));
+        if (c->timing && tslot >= 0) HCHK(hipEventRecord(c->evpool[5 * tslot + k], c->stream));
     };
     mark(0);
     if (ph & FFPIC_PHASE_MASK) psi_mask(c);
@@ -278,14 +351,6 @@ void one_step(ffpic_ctx *c, uint32_t ph, bool count_step, int tslot) {
     mark(3);
     if (ph & FFPIC_PHASE_FIELDS) field_step(c);
     mark(4);
-    if (c->timing && tslot >= 0) {
-        HCHK(hipEventSynchronize(c->ev[4]));
-        for (int k = 0; k < 4; k++) {
-            float ms = 0;
-            HCHK(hipEventElapsedTime(&ms, c->ev[k], c->ev[k + 1]));
-            c->phase_ms[k] += ms;
-        }
-    }
     if (count_step) c->step++;
 }
 
@@ -379,6 +444,18 @@ int ffpic_create(const ffpic_desc *d, void *stream, ffpic_ctx **out) {
             upload_field(c, c->B[k], F[3 + k]);
             upload_field(c, c->B0[k], F[3 + k]);
         }
+        if (!c->fp64) {
+            for (int k = 0; k < 3; k++) {
+                c->dE[k] = dmalloc(fb); c->dB[k] = dmalloc(fb); c->E0[k] = dmalloc(fb);
+                c->rE0[k] = dmalloc(fb); c->rB0[k] = dmalloc(fb);
+                HCHK(hipMemset(c->dE[k], 0, fb));
+                HCHK(hipMemset(c->dB[k], 0, fb));
+                c->hE0[k] = F[k];
+                c->hB0[k] = F[3 + k];
+            }
+            c->rho0 = dmalloc(fb);
+            upload_background(c);
+        }
         psi_mask(c);
         HCHK(hipStreamSynchronize(c->stream));
     });
@@ -424,6 +501,21 @@ int ffpic_load_fields(ffpic_ctx *c, int comp, const double *src, int on_dev) {
         from_f64(c, dsrc, dst, c->nn);
         if (comp >= FFPIC_BR) from_f64(c, dsrc, c->B0[comp - 3], c->nn);
         if (comp == FFPIC_BR) psi_mask(c);
+        if (!c->fp64) {
+            // the loaded component becomes the background of that component
+            std::vector<double> h(c->nn);
+            HCHK(hipMemcpyAsync(h.data(), dsrc, c->nn * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            HCHK(hipStreamSynchronize(c->stream));
+            size_t fb = c->nn * sizeof(float);
+            if (comp < 3) {
+                c->hE0[comp] = h;
+                HCHK(hipMemset(c->dE[comp], 0, fb));
+            } else {
+                c->hB0[comp - 3] = h;
+                HCHK(hipMemset(c->dB[comp - 3], 0, fb));
+            }
+            upload_background(c);
+        }
         HCHK(hipStreamSynchronize(c->stream));
         if (tmp) HCHK(hipFree(tmp));
     });
@@ -465,13 +557,30 @@ int ffpic_step(ffpic_ctx *c, int32_t nsteps) {
     return guarded(c, [&] {
         check_ctx(c);
         if (nsteps < 0) throw Fail{FFPIC_EINVAL, "negative step count"};
-        if (c->timing) for (auto &m : c->phase_ms) m = 0.f;
+        if (c->timing) {
+            for (auto &m : c->phase_ms) m = 0.f;
+            while ((int)c->evpool.size() < 5 * nsteps) {
+                hipEvent_t e;
+                HCHK(hipEventCreate(&e));
+                c->evpool.push_back(e);
+            }
+        }
         for (int k = 0; k < nsteps; k++) {
             uint32_t ph = FFPIC_PHASE_MASK | FFPIC_PHASE_KILL | FFPIC_PHASE_PUSH | FFPIC_PHASE_FIELDS;
             if (c->step % c->d.sort_interval == 0) ph |= FFPIC_PHASE_SORT;
             // the push removes particles of force-free cells itself
             if (!(ph & FFPIC_PHASE_SORT)) ph &= ~FFPIC_PHASE_KILL;
-            one_step(c, ph, true, c->timing ? 0 : -1);
+            one_step(c, ph, true, c->timing ? k : -1);
+        }
+        if (c->timing && nsteps > 0) {
+            // events only: the stream is not drained between steps
+            HCHK(hipEventSynchronize(c->evpool[5 * nsteps - 1]));
+            for (int s = 0; s < nsteps; s++)
+                for (int k = 0; k < 4; k++) {
+                    float ms = 0;
+                    HCHK(hipEventElapsedTime(&ms, c->evpool[5 * s + k], c->evpool[5 * s + k + 1]));
+                    c->phase_ms[k] += ms;
+                }
         }
     });
 }
@@ -633,6 +742,7 @@ struct SaveHeader {
 size_t save_size(ffpic_ctx *c, const int32_t *ns) {
     size_t fb = c->nn * c->rsz;
     size_t bytes = sizeof(SaveHeader) + 9 * fb + c->nn * sizeof(double) + fb;
+    if (!c->fp64) bytes += 6 * fb + 6 * c->nn * sizeof(double);   // dE, dB, FP64 background
     for (int s = 0; s < c->d.nspec; s++)
         bytes += (size_t)ns[s] * (c->fp64 ? 5 * 8 : 6 * 4);
     return bytes;
@@ -666,6 +776,16 @@ int ffpic_save(ffpic_ctx *c, void *buf, size_t *len) {
         for (void *a : arrs) { HCHK(hipMemcpy(p, a, fb, hipMemcpyDeviceToHost)); p += fb; }
         HCHK(hipMemcpy(p, c->psi, c->nn * sizeof(double), hipMemcpyDeviceToHost)); p += c->nn * sizeof(double);
         HCHK(hipMemcpy(p, c->f, fb, hipMemcpyDeviceToHost)); p += fb;
+        if (!c->fp64) {
+            for (int k = 0; k < 3; k++) {
+                HCHK(hipMemcpy(p, c->dE[k], fb, hipMemcpyDeviceToHost)); p += fb;
+                HCHK(hipMemcpy(p, c->dB[k], fb, hipMemcpyDeviceToHost)); p += fb;
+            }
+            for (int k = 0; k < 3; k++) {
+                std::memcpy(p, c->hE0[k].data(), c->nn * sizeof(double)); p += c->nn * sizeof(double);
+                std::memcpy(p, c->hB0[k].data(), c->nn * sizeof(double)); p += c->nn * sizeof(double);
+            }
+        }
         size_t eb = c->fp64 ? 8 : 4;
         for (int s = 0; s < c->d.nspec; s++)
             for (int a = 0; a < c->sp[s].narr; a++) {
@@ -699,6 +819,17 @@ int ffpic_restore(ffpic_ctx *c, const void *buf, size_t len) {
         for (void *a : arrs) { HCHK(hipMemcpy(a, p, fb, hipMemcpyHostToDevice)); p += fb; }
         HCHK(hipMemcpy(c->psi, p, c->nn * sizeof(double), hipMemcpyHostToDevice)); p += c->nn * sizeof(double);
         HCHK(hipMemcpy(c->f, p, fb, hipMemcpyHostToDevice)); p += fb;
+        if (!c->fp64) {
+            for (int k = 0; k < 3; k++) {
+                HCHK(hipMemcpy(c->dE[k], p, fb, hipMemcpyHostToDevice)); p += fb;
+                HCHK(hipMemcpy(c->dB[k], p, fb, hipMemcpyHostToDevice)); p += fb;
+            }
+            for (int k = 0; k < 3; k++) {
+                c->hE0[k].assign((const double *)p, (const double *)p + c->nn); p += c->nn * sizeof(double);
+                c->hB0[k].assign((const double *)p, (const double *)p + c->nn); p += c->nn * sizeof(double);
+            }
+            upload_background(c);
+        }
         size_t eb = c->fp64 ? 8 : 4;
         for (int s = 0; s < c->d.nspec; s++) {
             for (int a = 0; a < c->sp[s].narr; a++) {

@@ -75,6 +75,7 @@ class Workload:
     drift_beta: float = 0.0
     gamma_max: float = 100.0
     background_frac: float = 0.0
+    background_rmin: float = 3.0
     seed: int = SEED_BASE
     steps: int = 1
 
@@ -165,12 +166,14 @@ def _sheet(g, n, w: Workload, species):
     uth = np.zeros(ns)
     if nb:
         # closed-zone background: volume-uniform where sin^2(th) > r / R_LC,
-        # r >= 1, at rest
+        # at rest, from r = background_rmin out (inside ~3 stellar radii the
+        # radiation-reaction rate K B^2 exceeds 1/dt by orders of magnitude,
+        # where the explicit radiation-reaction step is unstable)
         rb = np.empty(0)
         tb = np.empty(0)
         while len(rb) < nb:
             m = 2 * (nb - len(rb)) + 64
-            rr = np.cbrt(g.uniform(1.0, w.r_lc ** 3, m))
+            rr = np.cbrt(g.uniform(w.background_rmin ** 3, w.r_lc ** 3, m))
             cc = g.uniform(-1.0, 1.0, m)
             ok = (1.0 - cc * cc) > rr / w.r_lc
             rb = np.concatenate([rb, rr[ok]])
