@@ -123,6 +123,7 @@ void poynting(ffpic_ctx *c, double *dev_L);
 void energies(ffpic_ctx *c, double *dev_out2);
 double max_abs(ffpic_ctx *c, const double *dev, size_t n);
 size_t sort_temp_bytes(int64_t cap, int bits);
+int sort_key_bits(const ffpic_ctx *c);
 void zero_counters(ffpic_ctx *c, int32_t *p, int n);
 
 }  // namespace ffpic

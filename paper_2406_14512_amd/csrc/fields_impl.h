@@ -14,21 +14,56 @@ namespace ffpic {
 // ---------------------------------------------------------------------------
 // eq. (psi): Psi(i, 0) = 0, Psi(i, j+1) = Psi(i, j) + B_r(i, j+1/2) A_r(i, j)
 // with A_r = r_i^2 (cos theta_j - cos theta_{j+1}); FP64, sequential in j so
-// that the rounding is fixed.  One thread per radial row.
+// that the rounding is fixed.  A workgroup of 64 threads owns 64 radial rows
+// (one row per thread for the scan); the rows are walked in 64-column
+// chunks staged through LDS so that both the B_r loads and the Psi stores
+// are coalesced along theta.
 template <typename R>
 __global__ void __launch_bounds__(64) k_psi(Geo<double> g, const R *__restrict__ br,
                                             double *__restrict__ psi) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i > g.nr) return;
-    const R *row = br + ix(g.ld, i, 0);
-    double *out = psi + ix(g.ld, i, 0);
-    double r2 = g.rn2[i];
+    __shared__ double tile[64][65];
+    __shared__ double area[64];
+    const int t = threadIdx.x;
+    const int i0 = blockIdx.x * 64;
+    const int i = i0 + t;
+    const int ld = g.ld, nr = g.nr, nth = g.nth;
+    const int rows = min(64, nr + 1 - i0);
+    double r2 = i <= nr ? g.rn2[i] : 0.0;
     double acc = 0.0;
-    out[0] = 0.0;
-    for (int j = 0; j < g.nth; j++) {
+    if (i <= nr) psi[ix(ld, i, 0)] = 0.0;
+    for (int j0 = 0; j0 < nth; j0 += 64) {
+        const int w = min(64, nth - j0);
+        if (t < w) area[t] = g.dcn[j0 + t];
+        for (int rr = 0; rr < rows; rr++)
+            if (t < w) tile[rr][t] = (double)br[ix(ld, i0 + rr, j0 + t)];
+        __syncthreads();
+        if (t < rows) {
+            if (w == 64) {
+                // products are independent; only the running sum is serial
+                double pr[64];
+#pragma unroll
+                for (int k = 0; k < 64; k++) {
 #pragma clang fp contract(off)
-        acc = acc + (double)row[j] * (r2 * g.dcn[j]);
-        out[j + 1] = acc;
+                    pr[k] = tile[t][k] * (r2 * area[k]);
+                }
+#pragma unroll
+                for (int k = 0; k < 64; k++) {
+#pragma clang fp contract(off)
+                    acc = acc + pr[k];
+                    tile[t][k] = acc;
+                }
+            } else {
+                for (int k = 0; k < w; k++) {
+#pragma clang fp contract(off)
+                    acc = acc + tile[t][k] * (r2 * area[k]);
+                    tile[t][k] = acc;
+                }
+            }
+        }
+        __syncthreads();
+        for (int rr = 0; rr < rows; rr++)
+            if (t < w) psi[ix(ld, i0 + rr, j0 + 1 + t)] = tile[rr][t];
+        __syncthreads();
     }
 }
 

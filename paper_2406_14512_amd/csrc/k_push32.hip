@@ -11,19 +11,28 @@
 // radiation-reaction force g and eq. bperp; Boris rotation; zigzag
 // charge-conserving deposit), but the move is evaluated in the particle's
 // local frame: the radial and polar displacements are formed from the
-// small step itself (log1p for the radial one, the arctangent of a small
-// ratio for the polar one), so that no difference of two large FP32
-// coordinates is ever taken.
+// small step itself (a log1p series for the radial one, an arctangent
+// series for the polar one), so that no difference of two large FP32
+// coordinates is ever taken.  Reciprocals and square roots use the
+// hardware approximations (about 1 ulp).
+//
+// The kernel is bound by instruction issue, so it is written for few
+// instructions per particle: the 24-load staggered gather goes through
+// buffer resources with 32-bit offsets shared between components at the
+// same stagger (the next radial row comes from the scalar offset), the axis
+// parity signs are folded into the interpolation weights, the particle
+// state is addressed with 32-bit offsets from uniform bases, and the
+// cross-lane sums are DPP row reductions.
 //
 // Deposit: each workgroup takes a contiguous chunk of the (cell-sorted)
-// particle array, holds the chunk's state in registers, finds the bounding
+// particle array, holds the chunk's cells in registers, finds the bounding
 // box of its cells and accumulates the currents in an LDS patch covering the
-// box (plus the one-cell reach of a step); the patch is then flushed to the
-// FP32 current arrays in HBM with one global atomic per touched entry.
-// Within a wavefront, particles that stay in their cell and share it with
-// the wave's leader are summed across lanes first (cross-lane reduction), so
-// a sorted wave issues 8 LDS adds instead of 8 x 64.  Chunks whose box is
-// too large for the patch (sparse regions) add straight to HBM.
+// box plus the one-cell reach of a step; the patch is then flushed to the
+// FP32 current arrays in HBM with one global atomic per non-zero entry.
+// Particles that stay in their cell and share it with the wavefront's
+// leader are summed across each 16-lane row first (DPP), so a sorted wave
+// issues 8 adds from 4 lanes instead of 8 x 64.  Chunks whose box is too
+// large for the patch (sparse regions) add straight to HBM.
 #include "device_common.h"
 
 namespace ffpic {
@@ -32,6 +41,7 @@ constexpr int kWG = 256;
 constexpr int kPPT = 4;                  // particles per thread per chunk
 constexpr int kChunk = kWG * kPPT;
 constexpr int kTile = 2048;              // LDS patch entries per component
+constexpr int kRsrcWord3 = 0x00020000;   // raw dword buffer access (gfx9 family)
 
 struct P32 {
     int nr, nth, ld;
@@ -39,50 +49,318 @@ struct P32 {
     int iabs;                            // r_abs lies in radial cell iabs ...
     float aabs;                          // ... at offset aabs
     const float *rn, *sn, *cn;
-    float Q, wq, rr;
+    float Q, h, kk;                      // charge, dt omega_b qm / 2, dt K_s
 };
 
-__device__ __forceinline__ float wave_sum(float v) {
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// 32-bit element offsets from a uniform base (element index < 2^30)
+template <typename T>
+__device__ __forceinline__ T ldo(const T *base, unsigned idx) {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + (idx << 2));
+}
+template <typename T>
+__device__ __forceinline__ void sto(T *base, unsigned idx, T v) {
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + (idx << 2)) = v;
+}
+
+// sum over each 16-lane row of the wavefront (every lane of the row gets it)
+__device__ __forceinline__ float row_sum(float v) {
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, true));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, true));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, true));
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, true));
     return v;
 }
 
+struct Fields {
+    __amdgpu_buffer_rsrc_t er, et, ep, br, bt, bp;
+};
+
+template <bool LDS>
 struct Acc {
-    float *lds;      // nullptr: global mode
-    int ti0, tj0, TI, TJ;
-    float *gr, *gt, *gp;
+    float *tile;     // LDS patch (LDS mode)
+    int ti0, tj0, TJ;
+    float *g[3];
     int ld;
-    __device__ __forceinline__ void add(int comp, int i, int j, float v) {
-        if (lds) {
-            int ti = i - ti0, tj = j - tj0;
-            if (ti >= 0 && ti < TI && tj >= 0 && tj < TJ) {
-                atomicAdd(&lds[comp * kTile + ti * TJ + tj], v);
-                return;
-            }
-        }
-        {
-            float *g = comp == 0 ? gr : comp == 1 ? gt : gp;
-            gadd(&g[ix(ld, i, j)], v);
-        }
+    __device__ __forceinline__ void add(int comp, int i, int j, float v) const {
+        if (LDS) atomicAdd(&tile[comp * kTile + (i - ti0) * TJ + (j - tj0)], v);
+        else gadd(reinterpret_cast<float *>(reinterpret_cast<char *>(g[comp]) +
+                                            ((unsigned)(i * ld + j) << 2)), v);
     }
 };
 
-// staggered bilinear gather (logical coordinates, axis parity ghosts,
-// constant beyond the radial ends)
-__device__ __forceinline__ float bil32(const float *__restrict__ F, int ld, int nth, int ilo,
-                                       float wr, int jlo, float wt, bool thalf, float par) {
-    int j0 = jlo, j1 = jlo + 1;
-    float s0 = 1.f, s1 = 1.f;
-    if (thalf) {
-        if (j0 < 0) { j0 = 0; s0 = par; }
-        if (j1 >= nth) { j1 = nth - 1; s1 = par; }
-    }
-    size_t r0 = (size_t)ilo * ld, r1 = r0 + ld;
-    float v00 = s0 * F[r0 + j0], v01 = s1 * F[r0 + j1];
-    float v10 = s0 * F[r1 + j0], v11 = s1 * F[r1 + j1];
-    float lo = v00 + wt * (v01 - v00);
-    float hi = v10 + wt * (v11 - v10);
+// staggered bilinear interpolation from one buffer: row offset voff (bytes)
+// with columns c0 / c1 given as byte offsets, next row via soffset = ld4
+__device__ __forceinline__ float bil(__amdgpu_buffer_rsrc_t R, unsigned o0, unsigned o1,
+                                     unsigned ld4, float W0, float W1, float wr) {
+    // the b32 loads return raw bits
+    const float v00 = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(R, (int)o0, 0, 0));
+    const float v01 = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(R, (int)o1, 0, 0));
+    const float v10 = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(R, (int)o0, (int)ld4, 0));
+    const float v11 = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(R, (int)o1, (int)ld4, 0));
+    const float lo = v00 * W0 + v01 * W1;
+    const float hi = v10 * W0 + v11 * W1;
     return lo + wr * (hi - lo);
+}
+
+template <bool LDS>
+__device__ __forceinline__ void push_chunk(
+    const P32 &p, const Fields &F, const Acc<LDS> &acc, const int *cell, int base, int tid,
+    int lane, const uint8_t *__restrict__ kill, int32_t *__restrict__ CELL, float *__restrict__ A,
+    float *__restrict__ Bo, float *__restrict__ UR, float *__restrict__ UT,
+    float *__restrict__ UP, uint32_t *__restrict__ err, int &nkill, int &nstar, int &nabs) {
+    const int ld = p.ld, nth = p.nth;
+    const unsigned ld4 = (unsigned)ld << 2;
+#pragma unroll 1
+    for (int k = 0; k < kPPT; k++) {
+        const unsigned q = (unsigned)(base + k * kWG + tid);
+        const int c = cell[k];
+        bool live = c >= 0;
+        const int i = c >> 16, j = c & 0xffff;
+        if (live && kill[(unsigned)(i * nth + j)]) {
+            live = false;
+            sto(CELL, q, -1);
+            nkill++;
+        }
+        bool simple = false;       // stays in its cell: 8 adds at fixed offsets
+        float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f, s5 = 0.f, s6 = 0.f, s7 = 0.f;
+        bool cross = false;        // leaves its cell: general zigzag
+        int di = 0, dj = 0;
+        float x1 = 0.f, y1 = 0.f, x2 = 0.f, y2 = 0.f, qv = 0.f;
+        if (live) {
+            const float a = ldo(A, q), b = ldo(Bo, q);
+            const float ur = ldo(UR, q), ut = ldo(UT, q), up = ldo(UP, q);
+            // ---- staggered bilinear gather
+            const bool ah = a >= 0.5f, bh = b >= 0.5f;
+            int hr = ah ? i : i - 1;
+            float wr = ah ? a - 0.5f : a + 0.5f;
+            if (hr < 0) { hr = 0; wr = 0.f; }
+            if (hr > p.nr - 2) { hr = p.nr - 2; wr = 1.f; }
+            const int ht = bh ? j : j - 1;
+            const float wt = bh ? b - 0.5f : b + 0.5f;
+            const int c0 = ht < 0 ? 0 : ht;
+            const int c1 = ht + 1 > nth - 1 ? nth - 1 : ht + 1;
+            // theta weights: node columns (j, j+1), half columns (c0, c1);
+            // odd components (E_th, B_ph) carry the axis ghost signs
+            const float Wn0 = 1.f - b, Wn1 = b;
+            const float Wh0 = 1.f - wt, Wh1 = wt;
+            const float Wo0 = ht < 0 ? -Wh0 : Wh0;
+            const float Wo1 = ht + 1 > nth - 1 ? -Wh1 : Wh1;
+            const unsigned rN = (unsigned)(i * ld), rH = (unsigned)(hr * ld);
+            const unsigned on = (rN + j) << 2, hn = (rH + j) << 2;
+            const unsigned oh0 = (rN + c0) << 2, oh1 = (rN + c1) << 2;
+            const unsigned hh0 = (rH + c0) << 2, hh1 = (rH + c1) << 2;
+            const float esr = bil(F.er, hn, hn + 4, ld4, Wn0, Wn1, wr);
+            const float est = bil(F.et, oh0, oh1, ld4, Wo0, Wo1, a);
+            const float esp = bil(F.ep, on, on + 4, ld4, Wn0, Wn1, a);
+            const float bsr = bil(F.br, oh0, oh1, ld4, Wh0, Wh1, a);
+            const float bst = bil(F.bt, hn, hn + 4, ld4, Wn0, Wn1, wr);
+            const float bsp = bil(F.bp, hh0, hh1, ld4, Wo0, Wo1, wr);
+            // ---- geometry: theta = theta_j + d (small-angle series), r = r_i exp(a dlog)
+            const float d = b * p.dth, d2 = d * d;
+            const float sd = d * (1.f - d2 * (1.f / 6.f) * (1.f - d2 * (1.f / 20.f)));
+            const float cd = 1.f - 0.5f * d2 * (1.f - d2 * (1.f / 12.f));
+            const float snj = ldo(p.sn, (unsigned)j), cnj = ldo(p.cn, (unsigned)j);
+            const float st = snj * cd + cnj * sd;
+            const float ct = cnj * cd - snj * sd;
+            const float xl = a * p.dlog;
+            const float r = ldo(p.rn, (unsigned)i) *
+                            (1.f + xl * (1.f + xl * (0.5f + xl * (1.f / 6.f + xl * (1.f / 24.f)))));
+            // ---- local Cartesian frame at azimuth 0
+            const float Ex = esr * st + est * ct, Ey = esp, Ez = esr * ct - est * st;
+            const float Bx = bsr * st + bst * ct, By = bsp, Bz = bsr * ct - bst * st;
+            const float ux = ur * st + ut * ct, uy = up, uz = ur * ct - ut * st;
+            // ---- Boris rotation
+            const float h = p.h;
+            const float mx = ux + h * Ex, my = uy + h * Ey, mz = uz + h * Ez;
+            const float ig = h * frsq(1.f + mx * mx + my * my + mz * mz);
+            const float tx = Bx * ig, ty = By * ig, tz = Bz * ig;
+            const float sf = 2.f * frcp(1.f + tx * tx + ty * ty + tz * tz);
+            const float px = mx + (my * tz - mz * ty);
+            const float py = my + (mz * tx - mx * tz);
+            const float pz = mz + (mx * ty - my * tx);
+            const float sx = tx * sf, sy = ty * sf, sz = tz * sf;
+            float nx = mx + (py * sz - pz * sy) + h * Ex;
+            float ny = my + (pz * sx - px * sz) + h * Ey;
+            float nz = mz + (px * sy - py * sx) + h * Ez;
+            // ---- radiation reaction (explicit, time-centred velocity)
+            if (p.kk != 0.f) {
+                float bx = 0.5f * (ux + nx), by = 0.5f * (uy + ny), bz = 0.5f * (uz + nz);
+                const float gb2 = 1.f + bx * bx + by * by + bz * bz;
+                const float igb = frsq(gb2);
+                bx *= igb; by *= igb; bz *= igb;
+                const float Fx = Ex + (by * Bz - bz * By);
+                const float Fy = Ey + (bz * Bx - bx * Bz);
+                const float Fz = Ez + (bx * By - by * Bx);
+                const float be = bx * Ex + by * Ey + bz * Ez;
+                const float bp2 = fmaxf(Fx * Fx + Fy * Fy + Fz * Fz - be * be, 0.f);
+                const float gg = gb2 * bp2;
+                const float kk = p.kk;
+                nx += kk * ((Fy * Bz - Fz * By) + be * Ex - gg * bx);
+                ny += kk * ((Fz * Bx - Fx * Bz) + be * Ey - gg * by);
+                nz += kk * ((Fx * By - Fy * Bx) + be * Ez - gg * bz);
+            }
+            const float ivg = frsq(1.f + nx * nx + ny * ny + nz * nz);   // 1 / gamma
+            const float vdt = p.dt * ivg;
+            const float dx = nx * vdt, dy = ny * vdt, dz = nz * vdt;
+            // ---- move in the local frame
+            const float w = r * st;
+            const float xx = w + dx;
+            const float w2 = __builtin_sqrtf(xx * xx + dy * dy);
+            const float den = w2 + w;
+            const float dw = den > 0.f ? (2.f * w * dx + dx * dx + dy * dy) * frcp(den) : 0.f;
+            const float drr = dw * st + dz * ct;
+            const float dtt = dw * ct - dz * st;
+            const float ir = frcp(r);
+            const float yv = drr * ir, zv = dtt * ir;
+            const float arg = yv * (2.f + yv) + zv * zv;       // (r'/r)^2 - 1
+            const float sq = arg * frcp(2.f + arg);            // log1p(x) = 2 atanh(x / (2 + x))
+            const float sq2 = sq * sq;
+            const float dxi = sq * (1.f + sq2 * (1.f / 3.f + sq2 * (1.f / 5.f))) * p.inv_dlog;
+            const float tq = dtt * frcp(r + drr);
+            const float tq2 = tq * tq;
+            const float dthe = tq * (1.f - tq2 * (1.f / 3.f - tq2 * (1.f / 5.f)));
+            const float iw2 = w2 > 0.f ? frcp(w2) : 0.f;
+            const float cp = w2 > 0.f ? xx * iw2 : 1.f;
+            const float sp = dy * iw2;
+            const float rx = cp * nx + sp * ny, ry = -sp * nx + cp * ny, rz = nz;
+            const float dd2 = dthe * dthe;
+            const float sdd = dthe * (1.f - dd2 * (1.f / 6.f));
+            const float cdd = 1.f - 0.5f * dd2;
+            const float st2 = st * cdd + ct * sdd, ct2 = ct * cdd - st * sdd;
+            // ---- new cell and offsets (carry)
+            float na = a + dxi, nb = b + dthe * p.inv_dth;
+            di = (int)floorf(na);
+            dj = (int)floorf(nb);
+            na -= (float)di;
+            nb -= (float)dj;
+            if (na >= 1.f) { na -= 1.f; di++; }
+            if (nb >= 1.f) { nb -= 1.f; dj++; }
+            int i2 = i + di, j2 = j + dj;
+            if (j2 < 0) { j2 = 0; nb = 0.f; dj = -j; }
+            if (j2 > nth - 1) { j2 = nth - 1; nb = 0.99999994f; dj = j2 - j; }
+            const bool cfl = di > 1 || di < -1 || dj > 1 || dj < -1;
+            const bool finite = isfinite(na) && isfinite(nb) && isfinite(rx) && isfinite(ry) &&
+                                isfinite(rz);
+            if (cfl) atomicOr(err, FFPIC_ERR_CFL);
+            if (!finite) {
+                // flagged in the error word; never deposited
+                atomicOr(err, FFPIC_ERR_NONFINITE);
+                sto(CELL, q, -1);
+            } else if (i2 < 0) {
+                sto(CELL, q, -1);
+                nstar++;
+            } else if (i2 > p.iabs || (i2 == p.iabs && na >= p.aabs)) {
+                sto(CELL, q, -1);
+                nabs++;
+            } else {
+                sto(CELL, q, (i2 << 16) | j2);
+                sto(A, q, na);
+                sto(Bo, q, nb);
+                sto(UR, q, rx * st2 + rz * ct2);
+                sto(UT, q, rx * ct2 - rz * st2);
+                sto(UP, q, ry);
+                x1 = a; y1 = b;
+                x2 = (float)di + na;
+                y2 = (float)dj + nb;
+                qv = ny * ivg;                    // v_phi during the step (before rotation)
+                if (!cfl) {
+                    if (di == 0 && dj == 0) {
+                        simple = true;
+                        const float ddx = x2 - x1, ddy = y2 - y1;
+                        const float xm = 0.5f * (x1 + x2), ym = 0.5f * (y1 + y2);
+                        s1 = ddx * ym;
+                        s0 = ddx - s1;
+                        s3 = ddy * xm;
+                        s2 = ddy - s3;
+                        s5 = qv * xm;
+                        s4 = qv - s5;
+                        s7 = s5 * ym;
+                        s5 = s5 - s7;
+                        s6 = s4 * ym;
+                        s4 = s4 - s6;
+                    } else {
+                        cross = true;
+                    }
+                }
+            }
+        }
+        // ---- in-cell moves that share the wave leader's cell: DPP sums over
+        // each 16-lane row, the row's first lane adds (two leaders at most)
+        bool pend = simple;
+#pragma unroll 1
+        for (int it = 0; it < 2; it++) {
+            const unsigned long long m = __ballot(pend);
+            if (m == 0ull) break;
+            const int leader = __ffsll((long long)m) - 1;
+            const int lc = __builtin_amdgcn_readlane(c, leader);
+            const bool part = pend && c == lc;
+            const unsigned long long pm = __ballot(part);
+            const float v0 = row_sum(part ? s0 : 0.f);
+            const float v1 = row_sum(part ? s1 : 0.f);
+            const float v2 = row_sum(part ? s2 : 0.f);
+            const float v3 = row_sum(part ? s3 : 0.f);
+            const float v4 = row_sum(part ? s4 : 0.f);
+            const float v5 = row_sum(part ? s5 : 0.f);
+            const float v6 = row_sum(part ? s6 : 0.f);
+            const float v7 = row_sum(part ? s7 : 0.f);
+            if ((lane & 15) == 0 && ((pm >> lane) & 0xffffull) != 0ull) {
+                const int li = lc >> 16, lj = lc & 0xffff;
+                const float Q = p.Q;
+                acc.add(0, li, lj, Q * v0);
+                acc.add(0, li, lj + 1, Q * v1);
+                acc.add(1, li, lj, Q * v2);
+                acc.add(1, li + 1, lj, Q * v3);
+                acc.add(2, li, lj, Q * v4);
+                acc.add(2, li + 1, lj, Q * v5);
+                acc.add(2, li, lj + 1, Q * v6);
+                acc.add(2, li + 1, lj + 1, Q * v7);
+            }
+            pend = pend && !part;
+        }
+        if (pend) {
+            const float Q = p.Q;
+            acc.add(0, i, j, Q * s0);
+            acc.add(0, i, j + 1, Q * s1);
+            acc.add(1, i, j, Q * s2);
+            acc.add(1, i + 1, j, Q * s3);
+            acc.add(2, i, j, Q * s4);
+            acc.add(2, i + 1, j, Q * s5);
+            acc.add(2, i, j + 1, Q * s6);
+            acc.add(2, i + 1, j + 1, Q * s7);
+        }
+        if (cross) {
+            // general zigzag (the particle leaves its cell)
+            const int i2 = i + di, j2 = j + dj;
+            const float xr = fminf((float)min(di, 0) + 1.f, fmaxf((float)max(di, 0), 0.5f * (x1 + x2)));
+            const float yr = fminf((float)min(dj, 0) + 1.f, fmaxf((float)max(dj, 0), 0.5f * (y1 + y2)));
+            const float Q = p.Q;
+            const float fx1 = Q * (xr - x1), fy1 = Q * (yr - y1);
+            const float fx2 = Q * (x2 - xr), fy2 = Q * (y2 - yr);
+            const float wx1 = 0.5f * (x1 + xr), wy1 = 0.5f * (y1 + yr);
+            const float wx2 = 0.5f * (xr + x2) - (float)di, wy2 = 0.5f * (yr + y2) - (float)dj;
+            acc.add(0, i, j, fx1 * (1.f - wy1));
+            acc.add(0, i, j + 1, fx1 * wy1);
+            acc.add(1, i, j, fy1 * (1.f - wx1));
+            acc.add(1, i + 1, j, fy1 * wx1);
+            acc.add(0, i2, j2, fx2 * (1.f - wy2));
+            acc.add(0, i2, j2 + 1, fx2 * wy2);
+            acc.add(1, i2, j2, fy2 * (1.f - wx2));
+            acc.add(1, i2 + 1, j2, fy2 * wx2);
+            const float xm = 0.5f * (x1 + x2), ym = 0.5f * (y1 + y2);
+            int im = (int)floorf(xm), jm = (int)floorf(ym);
+            if (i + im > p.nr - 1) im = p.nr - 1 - i;
+            if (j + jm > nth - 1) jm = nth - 1 - j;
+            const float wx = xm - (float)im, wy = ym - (float)jm;
+            const float qq = Q * qv;
+            acc.add(2, i + im, j + jm, qq * (1.f - wx) * (1.f - wy));
+            acc.add(2, i + im + 1, j + jm, qq * wx * (1.f - wy));
+            acc.add(2, i + im, j + jm + 1, qq * (1.f - wx) * wy);
+            acc.add(2, i + im + 1, j + jm + 1, qq * wx * wy);
+        }
+    }
 }
 
 __global__ void __launch_bounds__(kWG) k_push32(
@@ -99,16 +377,24 @@ __global__ void __launch_bounds__(kWG) k_push32(
     const int lane = tid & 63;
     const int n = min(nub, nslots[0]);
     const int base = blockIdx.x * kChunk;
+    const int nbytes = (p.nr + 1) * p.ld * 4;
+    Fields F;
+    F.er = __builtin_amdgcn_make_buffer_rsrc((void *)Er, 0, nbytes, kRsrcWord3);
+    F.et = __builtin_amdgcn_make_buffer_rsrc((void *)Et, 0, nbytes, kRsrcWord3);
+    F.ep = __builtin_amdgcn_make_buffer_rsrc((void *)Ep, 0, nbytes, kRsrcWord3);
+    F.br = __builtin_amdgcn_make_buffer_rsrc((void *)Br, 0, nbytes, kRsrcWord3);
+    F.bt = __builtin_amdgcn_make_buffer_rsrc((void *)Bt, 0, nbytes, kRsrcWord3);
+    F.bp = __builtin_amdgcn_make_buffer_rsrc((void *)Bp, 0, nbytes, kRsrcWord3);
 
+    // cells of the chunk and their bounding box
     int cell[kPPT];
     int imin = 1 << 30, imax = -1, jmin = 1 << 30, jmax = -1;
 #pragma unroll
     for (int k = 0; k < kPPT; k++) {
-        int q = base + k * kWG + tid;
-        cell[k] = q < n ? CELL[q] : -1;
+        const int q = base + k * kWG + tid;
+        cell[k] = q < n ? ldo(CELL, (unsigned)q) : -1;
         if (cell[k] >= 0) {
-            int i = cell[k] >> 16, j = cell[k] & 0xffff;
-            if (kill[(size_t)i * p.nth + j]) continue;
+            const int i = cell[k] >> 16, j = cell[k] & 0xffff;
             imin = min(imin, i); imax = max(imax, i);
             jmin = min(jmin, j); jmax = max(jmax, j);
         }
@@ -126,282 +412,48 @@ __global__ void __launch_bounds__(kWG) k_push32(
         atomicMin(&box[2], jmin); atomicMax(&box[3], jmax);
     }
     __syncthreads();
-    Acc acc;
-    acc.gr = Jr; acc.gt = Jt; acc.gp = Jp; acc.ld = p.ld;
-    acc.ti0 = box[0] - 1;
-    acc.tj0 = box[2] - 1;
-    acc.TI = box[1] - box[0] + 4;
-    acc.TJ = box[3] - box[2] + 4;
-    const bool any = box[1] >= 0;
-    const bool use_lds = any && acc.TI * acc.TJ <= kTile;
-    acc.lds = use_lds ? tile : nullptr;
+    if (box[1] < 0) return;   // no live particle in the chunk (uniform)
+    // the patch covers rows [imin-1, imax+2] and columns [jmin-1, jmax+2]:
+    // every add of a particle that moves at most one cell lands inside
+    const int ti0 = box[0] - 1, tj0 = box[2] - 1;
+    const int TI = box[1] - box[0] + 4, TJ = box[3] - box[2] + 4;
+    const bool use_lds = TI * TJ <= kTile;
+    int nkill = 0, nstar = 0, nabs = 0;
     if (use_lds) {
-        int m = acc.TI * acc.TJ;
+        const int m = TI * TJ;
         for (int e = tid; e < m; e += kWG) {
             tile[e] = 0.f; tile[kTile + e] = 0.f; tile[2 * kTile + e] = 0.f;
         }
-    }
-    __syncthreads();
-
-    int nkill = 0, nstar = 0, nabs = 0;
-    if (any) {
-#pragma unroll 1
-        for (int k = 0; k < kPPT; k++) {
-            int q = base + k * kWG + tid;
-            int c = cell[k];
-            bool live = c >= 0;
-            int i = c >> 16, j = c & 0xffff;
-            if (live && kill[(size_t)i * p.nth + j]) {
-                live = false;
-                CELL[q] = -1;
-                nkill++;
-            }
-            // contributions of this particle
-            bool simple = false;     // stays in its cell: 8 adds at fixed offsets
-            float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f, s5 = 0.f, s6 = 0.f, s7 = 0.f;
-            int i2 = i, j2 = j;
-            float x1 = 0.f, y1 = 0.f, x2 = 0.f, y2 = 0.f, qv = 0.f;
-            bool dep = false;
-            if (live) {
-                float a = A[q], b = Bo[q];
-                float ur = UR[q], ut = UT[q], up = UP[q];
-                // gather
-                int hr = a >= 0.5f ? i : i - 1;
-                float whr = a >= 0.5f ? a - 0.5f : a + 0.5f;
-                if (hr < 0) { hr = 0; whr = 0.f; }
-                if (hr > p.nr - 2) { hr = p.nr - 2; whr = 1.f; }
-                int ht = b >= 0.5f ? j : j - 1;
-                float wht = b >= 0.5f ? b - 0.5f : b + 0.5f;
-                const int ld = p.ld, nth = p.nth;
-                float esr = bil32(Er, ld, nth, hr, whr, j, b, false, 1.f);
-                float est = bil32(Et, ld, nth, i, a, ht, wht, true, -1.f);
-                float esp = bil32(Ep, ld, nth, i, a, j, b, false, 1.f);
-                float bsr = bil32(Br, ld, nth, i, a, ht, wht, true, 1.f);
-                float bst = bil32(Bt, ld, nth, hr, whr, j, b, false, 1.f);
-                float bsp = bil32(Bp, ld, nth, hr, whr, ht, wht, true, -1.f);
-                // theta = theta_j + d, small-angle sine/cosine of d
-                float d = b * p.dth, d2 = d * d;
-                float sd = d * (1.f - d2 * (1.f / 6.f) * (1.f - d2 * (1.f / 20.f)));
-                float cd = 1.f - 0.5f * d2 * (1.f - d2 * (1.f / 12.f));
-                float snj = p.sn[j], cnj = p.cn[j];
-                float st = snj * cd + cnj * sd;
-                float ct = cnj * cd - snj * sd;
-                // r = r_i exp(a dlog)
-                float xl = a * p.dlog;
-                float r = p.rn[i] * (1.f + xl * (1.f + xl * (0.5f + xl * (1.f / 6.f + xl * (1.f / 24.f)))));
-                // local Cartesian frame at azimuth 0
-                float Ex = esr * st + est * ct, Ey = esp, Ez = esr * ct - est * st;
-                float Bx = bsr * st + bst * ct, By = bsp, Bz = bsr * ct - bst * st;
-                float ux = ur * st + ut * ct, uy = up, uz = ur * ct - ut * st;
-                // Boris rotation
-                float h = 0.5f * p.dt * p.wq;
-                float mx = ux + h * Ex, my = uy + h * Ey, mz = uz + h * Ez;
-                float gm = sqrtf(1.f + mx * mx + my * my + mz * mz);
-                float ig = h / gm;
-                float tx = Bx * ig, ty = By * ig, tz = Bz * ig;
-                float sf = 2.f / (1.f + tx * tx + ty * ty + tz * tz);
-                float px = mx + (my * tz - mz * ty);
-                float py = my + (mz * tx - mx * tz);
-                float pz = mz + (mx * ty - my * tx);
-                float sx = tx * sf, sy = ty * sf, sz = tz * sf;
-                float nx = mx + (py * sz - pz * sy) + h * Ex;
-                float ny = my + (pz * sx - px * sz) + h * Ey;
-                float nz = mz + (px * sy - py * sx) + h * Ez;
-                // radiation reaction (explicit, time-centred velocity)
-                if (p.rr != 0.f) {
-                    float bx = 0.5f * (ux + nx), by = 0.5f * (uy + ny), bz = 0.5f * (uz + nz);
-                    float gb = sqrtf(1.f + bx * bx + by * by + bz * bz);
-                    float igb = 1.f / gb;
-                    bx *= igb; by *= igb; bz *= igb;
-                    float Fx = Ex + (by * Bz - bz * By);
-                    float Fy = Ey + (bz * Bx - bx * Bz);
-                    float Fz = Ez + (bx * By - by * Bx);
-                    float be = bx * Ex + by * Ey + bz * Ez;
-                    float bp2 = fmaxf(Fx * Fx + Fy * Fy + Fz * Fz - be * be, 0.f);
-                    float gg = gb * gb * bp2;
-                    float kk = p.dt * p.rr;
-                    nx += kk * ((Fy * Bz - Fz * By) + be * Ex - gg * bx);
-                    ny += kk * ((Fz * Bx - Fx * Bz) + be * Ey - gg * by);
-                    nz += kk * ((Fx * By - Fy * Bx) + be * Ez - gg * bz);
-                }
-                float g = sqrtf(1.f + nx * nx + ny * ny + nz * nz);
-                if (!isfinite(g)) atomicOr(err, FFPIC_ERR_NONFINITE);
-                float ivg = p.dt / g;
-                float dx = nx * ivg, dy = ny * ivg, dz = nz * ivg;
-                // move in the local frame
-                float w = r * st;
-                float xx = w + dx;
-                float w2 = sqrtf(xx * xx + dy * dy);
-                float den = w2 + w;
-                float dw = den > 0.f ? (2.f * w * dx + dx * dx + dy * dy) / den : 0.f;
-                float drr = dw * st + dz * ct;
-                float dtt = dw * ct - dz * st;
-                float ir = 1.f / r;
-                float yv = drr * ir;
-                float zv = dtt * ir;
-                float arg = 2.f * yv + yv * yv + zv * zv;
-                float dxi = 0.5f * log1pf(arg) * p.inv_dlog;
-                float tq = dtt / (r + drr);
-                float tq2 = tq * tq;
-                float dth = tq * (1.f - tq2 * (1.f / 3.f - tq2 * (1.f / 5.f)));
-                float cp = w2 > 0.f ? xx / w2 : 1.f;
-                float sp = w2 > 0.f ? dy / w2 : 0.f;
-                float rx = cp * nx + sp * ny, ry = -sp * nx + cp * ny, rz = nz;
-                float dd2 = dth * dth;
-                float sdd = dth * (1.f - dd2 * (1.f / 6.f));
-                float cdd = 1.f - 0.5f * dd2;
-                float st2 = st * cdd + ct * sdd, ct2 = ct * cdd - st * sdd;
-                // new cell and offsets (carry)
-                float na = a + dxi, nb = b + dth * p.inv_dth;
-                int di = (int)floorf(na), dj = (int)floorf(nb);
-                na -= (float)di;
-                nb -= (float)dj;
-                if (na >= 1.f) { na -= 1.f; di++; }
-                if (nb >= 1.f) { nb -= 1.f; dj++; }
-                i2 = i + di;
-                j2 = j + dj;
-                if (j2 < 0) { j2 = 0; nb = 0.f; dj = -j; }
-                if (j2 > p.nth - 1) { j2 = p.nth - 1; nb = 0.99999994f; dj = j2 - j; }
-                bool cfl = di > 1 || di < -1 || dj > 1 || dj < -1;
-                if (cfl) atomicOr(err, FFPIC_ERR_CFL);
-                bool finite = isfinite(g) && isfinite(na) && isfinite(nb) && isfinite(rx) &&
-                              isfinite(ry) && isfinite(rz);
-                if (!finite) {
-                    // flagged in the error word; never deposited
-                    atomicOr(err, FFPIC_ERR_NONFINITE);
-                    CELL[q] = -1;
-                } else if (i2 < 0) {
-                    CELL[q] = -1;
-                    nstar++;
-                } else if (i2 > p.iabs || (i2 == p.iabs && na >= p.aabs)) {
-                    CELL[q] = -1;
-                    nabs++;
-                } else {
-                    CELL[q] = (i2 << 16) | j2;
-                    A[q] = na;
-                    Bo[q] = nb;
-                    UR[q] = rx * st2 + rz * ct2;
-                    UT[q] = rx * ct2 - rz * st2;
-                    UP[q] = ry;
-                    dep = !cfl;
-                    x1 = a; y1 = b;
-                    x2 = (float)di + na;
-                    y2 = (float)dj + nb;
-                    qv = ny * (1.f / g);
-                    if (dep && di == 0 && dj == 0) {
-                        simple = true;
-                        float ddx = x2 - x1, ddy = y2 - y1;
-                        float xm = 0.5f * (x1 + x2), ym = 0.5f * (y1 + y2);
-                        s0 = ddx * (1.f - ym);
-                        s1 = ddx * ym;
-                        s2 = ddy * (1.f - xm);
-                        s3 = ddy * xm;
-                        s4 = qv * (1.f - xm) * (1.f - ym);
-                        s5 = qv * xm * (1.f - ym);
-                        s6 = qv * (1.f - xm) * ym;
-                        s7 = qv * xm * ym;
-                    }
-                }
-            }
-            // cross-lane pre-reduction of same-cell, in-cell moves
-            bool pend = simple;
-#pragma unroll 1
-            for (int it = 0; it < 2; it++) {
-                unsigned long long m = __ballot(pend);
-                if (m == 0ull) break;
-                int leader = __ffsll((long long)m) - 1;
-                int lc = __shfl(c, leader, 64);
-                bool part = pend && c == lc;
-                float v0 = wave_sum(part ? s0 : 0.f);
-                float v1 = wave_sum(part ? s1 : 0.f);
-                float v2 = wave_sum(part ? s2 : 0.f);
-                float v3 = wave_sum(part ? s3 : 0.f);
-                float v4 = wave_sum(part ? s4 : 0.f);
-                float v5 = wave_sum(part ? s5 : 0.f);
-                float v6 = wave_sum(part ? s6 : 0.f);
-                float v7 = wave_sum(part ? s7 : 0.f);
-                if (lane == leader) {
-                    int li = lc >> 16, lj = lc & 0xffff;
-                    float Q = p.Q;
-                    acc.add(0, li, lj, Q * v0);
-                    acc.add(0, li, lj + 1, Q * v1);
-                    acc.add(1, li, lj, Q * v2);
-                    acc.add(1, li + 1, lj, Q * v3);
-                    acc.add(2, li, lj, Q * v4);
-                    acc.add(2, li + 1, lj, Q * v5);
-                    acc.add(2, li, lj + 1, Q * v6);
-                    acc.add(2, li + 1, lj + 1, Q * v7);
-                }
-                pend = pend && !part;
-            }
-            if (pend) {
-                float Q = p.Q;
-                acc.add(0, i, j, Q * s0);
-                acc.add(0, i, j + 1, Q * s1);
-                acc.add(1, i, j, Q * s2);
-                acc.add(1, i + 1, j, Q * s3);
-                acc.add(2, i, j, Q * s4);
-                acc.add(2, i + 1, j, Q * s5);
-                acc.add(2, i, j + 1, Q * s6);
-                acc.add(2, i + 1, j + 1, Q * s7);
-            }
-            if (dep && !simple) {
-                // general zigzag (the particle leaves its cell)
-                int di = i2 - i, dj = j2 - j;
-                float xr = fminf((float)min(di, 0) + 1.f, fmaxf((float)max(di, 0), 0.5f * (x1 + x2)));
-                float yr = fminf((float)min(dj, 0) + 1.f, fmaxf((float)max(dj, 0), 0.5f * (y1 + y2)));
-                float Q = p.Q;
-                float fx1 = Q * (xr - x1), fy1 = Q * (yr - y1);
-                float fx2 = Q * (x2 - xr), fy2 = Q * (y2 - yr);
-                float wx1 = 0.5f * (x1 + xr), wy1 = 0.5f * (y1 + yr);
-                float wx2 = 0.5f * (xr + x2) - (float)di, wy2 = 0.5f * (yr + y2) - (float)dj;
-                acc.add(0, i, j, fx1 * (1.f - wy1));
-                acc.add(0, i, j + 1, fx1 * wy1);
-                acc.add(1, i, j, fy1 * (1.f - wx1));
-                acc.add(1, i + 1, j, fy1 * wx1);
-                acc.add(0, i2, j2, fx2 * (1.f - wy2));
-                acc.add(0, i2, j2 + 1, fx2 * wy2);
-                acc.add(1, i2, j2, fy2 * (1.f - wx2));
-                acc.add(1, i2 + 1, j2, fy2 * wx2);
-                float xm = 0.5f * (x1 + x2), ym = 0.5f * (y1 + y2);
-                int im = (int)floorf(xm), jm = (int)floorf(ym);
-                if (i + im > p.nr - 1) im = p.nr - 1 - i;
-                if (j + jm > p.nth - 1) jm = p.nth - 1 - j;
-                float wx = xm - (float)im, wy = ym - (float)jm;
-                float qq = Q * qv;
-                acc.add(2, i + im, j + jm, qq * (1.f - wx) * (1.f - wy));
-                acc.add(2, i + im + 1, j + jm, qq * wx * (1.f - wy));
-                acc.add(2, i + im, j + jm + 1, qq * (1.f - wx) * wy);
-                acc.add(2, i + im + 1, j + jm + 1, qq * wx * wy);
-            }
-        }
-    }
-    {
-        int tk = nkill, ts = nstar, ta = nabs;
-        for (int o = 32; o >= 1; o >>= 1) {
-            tk += __shfl_xor(tk, o, 64);
-            ts += __shfl_xor(ts, o, 64);
-            ta += __shfl_xor(ta, o, 64);
-        }
-        if (lane == 0) {
-            if (tk) atomicAdd(&removed[1], (unsigned long long)tk);
-            if (ts) atomicAdd(&removed[2], (unsigned long long)ts);
-            if (ta) atomicAdd(&removed[3], (unsigned long long)ta);
-        }
-    }
-    if (use_lds) {
         __syncthreads();
-        int m = acc.TI * acc.TJ;
+        Acc<true> acc{tile, ti0, tj0, TJ, {Jr, Jt, Jp}, p.ld};
+        push_chunk<true>(p, F, acc, cell, base, tid, lane, kill, CELL, A, Bo, UR, UT, UP, err,
+                         nkill, nstar, nabs);
+        __syncthreads();
         for (int e = tid; e < m; e += kWG) {
-            int ti = e / acc.TJ, tj = e - ti * acc.TJ;
-            int gi = acc.ti0 + ti, gj = acc.tj0 + tj;
+            const int ti = e / TJ, tj = e - ti * TJ;
+            const int gi = ti0 + ti, gj = tj0 + tj;
             if (gi < 0 || gi > p.nr || gj < 0 || gj > p.nth) continue;
-            size_t g = ix(p.ld, gi, gj);
-            float v0 = tile[e], v1 = tile[kTile + e], v2 = tile[2 * kTile + e];
-            if (v0 != 0.f) gadd(&Jr[g], v0);
-            if (v1 != 0.f) gadd(&Jt[g], v1);
-            if (v2 != 0.f) gadd(&Jp[g], v2);
+            const unsigned g = ((unsigned)(gi * p.ld + gj)) << 2;
+            const float v0 = tile[e], v1 = tile[kTile + e], v2 = tile[2 * kTile + e];
+            if (v0 != 0.f) gadd(reinterpret_cast<float *>(reinterpret_cast<char *>(Jr) + g), v0);
+            if (v1 != 0.f) gadd(reinterpret_cast<float *>(reinterpret_cast<char *>(Jt) + g), v1);
+            if (v2 != 0.f) gadd(reinterpret_cast<float *>(reinterpret_cast<char *>(Jp) + g), v2);
         }
+    } else {
+        Acc<false> acc{nullptr, 0, 0, 0, {Jr, Jt, Jp}, p.ld};
+        push_chunk<false>(p, F, acc, cell, base, tid, lane, kill, CELL, A, Bo, UR, UT, UP, err,
+                          nkill, nstar, nabs);
+    }
+    int tk = nkill, ts = nstar, ta = nabs;
+    for (int o = 32; o >= 1; o >>= 1) {
+        tk += __shfl_xor(tk, o, 64);
+        ts += __shfl_xor(ts, o, 64);
+        ta += __shfl_xor(ta, o, 64);
+    }
+    if (lane == 0) {
+        if (tk) atomicAdd(&removed[1], (unsigned long long)tk);
+        if (ts) atomicAdd(&removed[2], (unsigned long long)ts);
+        if (ta) atomicAdd(&removed[3], (unsigned long long)ta);
     }
 }
 
@@ -421,8 +473,8 @@ void push32(ffpic_ctx *c, int s) {
     p.cn = (const float *)c->dtab[T_CN];
     double qm = S.qm;
     p.Q = (float)((qm > 0 ? 1.0 : -1.0) * S.weight);
-    p.wq = (float)(c->d.omega_b * qm);
-    p.rr = (float)(c->d.rr_coef * fabs(qm) * fabs(qm) * fabs(qm));
+    p.h = (float)(0.5 * c->dt * c->d.omega_b * qm);
+    p.kk = (float)(c->dt * c->d.rr_coef * fabs(qm) * fabs(qm) * fabs(qm));
     float **E = (float **)c->E, **B = (float **)c->B, **J = (float **)c->J;
     int nb = (int)((S.nub + kChunk - 1) / kChunk);
     hipLaunchKernelGGL(k_push32, dim3(nb), dim3(kWG), 0, c->stream, p, (int)S.nub,

@@ -2,9 +2,9 @@
 //
 // One thread per particle slot.  State per particle: r, theta, u_r,
 // u_theta, u_phi (FP64 SoA); a dead slot has r = -1 until the next sort.
-// The arithmetic follows the plain FP64 definition step by step and this
-// file is compiled without FP contraction, so the path rounds every
-// operation as written; currents are accumulated with FP64 atomics.
+// The per-particle arithmetic follows the plain FP64 definition step by step
+// and this file is compiled without FP contraction, so every operation is
+// rounded as written; only the order in which currents are summed differs.
 //
 // Push (Sect. 3): eq. (motion) integrated with the Boris rotation; the
 // Landau-Lifshitz force g with the effective field of eq. (bperp) is added
@@ -13,10 +13,15 @@
 // plane.  Deposit: zigzag (relay-point) split of the move in logical
 // coordinates (log r / dlog, theta / dtheta), charge fluxes through the dual
 // faces (exact discrete charge conservation), azimuthal current from v_phi
-// at the mid-point.
+// at the mid-point.  Accumulation as in the FP32 path: an LDS patch per
+// workgroup over the bounding box of its (cell-sorted) particles, same-cell
+// in-cell moves summed across the wavefront first, one global FP64 atomic
+// per non-zero patch entry.
 #include "device_common.h"
 
 namespace ffpic {
+
+constexpr int kTile64 = 1024;   // LDS patch entries per component (FP64)
 
 struct P64 {
     int nr, nth, ld;
@@ -107,6 +112,22 @@ __device__ __forceinline__ void boris_rr(double u[3], const double E[3], const d
     u[0] = uL[0]; u[1] = uL[1]; u[2] = uL[2];
 }
 
+__device__ __forceinline__ double wave_sum64(double v) {
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+struct Acc64 {
+    double *tile;    // nullptr: global mode
+    int ti0, tj0, TJ;
+    double *g[3];
+    int ld;
+    __device__ __forceinline__ void add(int comp, int i, int j, double v) const {
+        if (tile) atomicAdd(&tile[comp * kTile64 + (i - ti0) * TJ + (j - tj0)], v);
+        else gadd(&g[comp][ix(ld, i, j)], v);
+    }
+};
+
 __global__ void __launch_bounds__(256) k_push64(
     P64 p, int nub, const int32_t *__restrict__ nslots, const uint8_t *__restrict__ kill,
     const double *__restrict__ Er, const double *__restrict__ Et, const double *__restrict__ Ep,
@@ -115,95 +136,220 @@ __global__ void __launch_bounds__(256) k_push64(
     double *__restrict__ UT, double *__restrict__ UP, double *__restrict__ Jr,
     double *__restrict__ Jt, double *__restrict__ Jp, unsigned long long *__restrict__ removed,
     uint32_t *__restrict__ err) {
-    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ double tile[3 * kTile64];
+    __shared__ int box[4];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int q = blockIdx.x * blockDim.x + tid;
     bool live = q < nub && q < nslots[0];
     double r = live ? R[q] : -1.0;
     live = live && r > 0.0;
-    bool killed = false, star = false, absb = false;
+    double th = 0.0;
+    int i = 0, j = 0;
+    double a = 0.0, b = 0.0;
     if (live) {
-        double th = TH[q];
-        int i, j;
-        double a, b;
+        th = TH[q];
         locate64(p.nr, p.nth, p.rmin, p.dlog, p.dth, p.rn, p.thn, r, th, i, j, a, b);
-        if (kill[(size_t)i * p.nth + j]) {
-            killed = true;
+    }
+    // bounding box of the block's cells
+    int imin = live ? i : 1 << 30, imax = live ? i : -1;
+    int jmin = live ? j : 1 << 30, jmax = live ? j : -1;
+    if (tid == 0) { box[0] = 1 << 30; box[1] = -1; box[2] = 1 << 30; box[3] = -1; }
+    __syncthreads();
+    for (int o = 32; o >= 1; o >>= 1) {
+        imin = min(imin, __shfl_xor(imin, o, 64));
+        imax = max(imax, __shfl_xor(imax, o, 64));
+        jmin = min(jmin, __shfl_xor(jmin, o, 64));
+        jmax = max(jmax, __shfl_xor(jmax, o, 64));
+    }
+    if (lane == 0 && imax >= 0) {
+        atomicMin(&box[0], imin); atomicMax(&box[1], imax);
+        atomicMin(&box[2], jmin); atomicMax(&box[3], jmax);
+    }
+    __syncthreads();
+    if (box[1] < 0) return;   // uniform: no live particle in the block
+    const int ti0 = box[0] - 1, tj0 = box[2] - 1;
+    const int TI = box[1] - box[0] + 4, TJ = box[3] - box[2] + 4;
+    const bool use_lds = TI * TJ <= kTile64;
+    Acc64 acc{use_lds ? tile : nullptr, ti0, tj0, TJ, {Jr, Jt, Jp}, p.ld};
+    if (use_lds) {
+        for (int e = tid; e < TI * TJ; e += 256) {
+            tile[e] = 0.0; tile[kTile64 + e] = 0.0; tile[2 * kTile64 + e] = 0.0;
+        }
+        __syncthreads();
+    }
+
+    bool killed = false, star = false, absb = false;
+    bool simple = false, cross = false;
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int i2 = 0, j2 = 0, di = 0, dj = 0;
+    double x1 = 0, y1 = 0, x2 = 0, y2 = 0, v1 = 0;
+    if (live && kill[(size_t)i * p.nth + j]) {
+        killed = true;
+        R[q] = -1.0;
+        live = false;
+    }
+    if (live) {
+        const int ld = p.ld, nth = p.nth;
+        Lin rn = {i, a}, rh = half_r(i, a, p.nr), tn = {j, b}, thh = half_t(j, b);
+        double Es[3], Bs[3];
+        Es[0] = bil(Er, ld, nth, rh, tn, false, 1.0);
+        Es[1] = bil(Et, ld, nth, rn, thh, true, -1.0);
+        Es[2] = bil(Ep, ld, nth, rn, tn, false, 1.0);
+        Bs[0] = bil(Br, ld, nth, rn, thh, true, 1.0);
+        Bs[1] = bil(Bt, ld, nth, rh, tn, false, 1.0);
+        Bs[2] = bil(Bp, ld, nth, rh, thh, true, -1.0);
+        double st = sin(th), ct = cos(th);
+        double E[3] = {Es[0] * st + Es[1] * ct, Es[2], Es[0] * ct - Es[1] * st};
+        double B[3] = {Bs[0] * st + Bs[1] * ct, Bs[2], Bs[0] * ct - Bs[1] * st};
+        double ur = UR[q], ut = UT[q], up = UP[q];
+        double u[3] = {ur * st + ut * ct, up, ur * ct - ut * st};
+        boris_rr(u, E, B, p.dt, p.wq, p.rr);
+        double g = sqrt(1.0 + (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]));
+        if (!isfinite(g)) atomicOr(err, FFPIC_ERR_NONFINITE);
+        double v0 = u[0] / g, vv2 = u[2] / g;
+        v1 = u[1] / g;
+        double x = r * st + p.dt * v0, y = p.dt * v1, z = r * ct + p.dt * vv2;
+        double w = sqrt(x * x + y * y);
+        double cp = w > 0.0 ? x / w : 1.0, sp = w > 0.0 ? y / w : 0.0;
+        double ux = cp * u[0] + sp * u[1], uy = -sp * u[0] + cp * u[1], uz = u[2];
+        double r2 = sqrt(w * w + z * z);
+        double th2 = atan2(w, z);
+        if (!(r2 >= p.rmin)) {
+            star = true;
+            R[q] = -1.0;
+        } else if (r2 >= p.r_abs) {
+            absb = true;
             R[q] = -1.0;
         } else {
-            const int ld = p.ld, nth = p.nth;
-            Lin rn = {i, a}, rh = half_r(i, a, p.nr), tn = {j, b}, thh = half_t(j, b);
-            double Es[3], Bs[3];
-            Es[0] = bil(Er, ld, nth, rh, tn, false, 1.0);
-            Es[1] = bil(Et, ld, nth, rn, thh, true, -1.0);
-            Es[2] = bil(Ep, ld, nth, rn, tn, false, 1.0);
-            Bs[0] = bil(Br, ld, nth, rn, thh, true, 1.0);
-            Bs[1] = bil(Bt, ld, nth, rh, tn, false, 1.0);
-            Bs[2] = bil(Bp, ld, nth, rh, thh, true, -1.0);
-            double st = sin(th), ct = cos(th);
-            double E[3] = {Es[0] * st + Es[1] * ct, Es[2], Es[0] * ct - Es[1] * st};
-            double B[3] = {Bs[0] * st + Bs[1] * ct, Bs[2], Bs[0] * ct - Bs[1] * st};
-            double ur = UR[q], ut = UT[q], up = UP[q];
-            double u[3] = {ur * st + ut * ct, up, ur * ct - ut * st};
-            boris_rr(u, E, B, p.dt, p.wq, p.rr);
-            double g = sqrt(1.0 + (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]));
-            if (!isfinite(g)) atomicOr(err, FFPIC_ERR_NONFINITE);
-            double v0 = u[0] / g, v1 = u[1] / g, v2 = u[2] / g;
-            double x = r * st + p.dt * v0, y = p.dt * v1, z = r * ct + p.dt * v2;
-            double w = sqrt(x * x + y * y);
-            double cp = w > 0.0 ? x / w : 1.0, sp = w > 0.0 ? y / w : 0.0;
-            double ux = cp * u[0] + sp * u[1], uy = -sp * u[0] + cp * u[1], uz = u[2];
-            double r2 = sqrt(w * w + z * z);
-            double th2 = atan2(w, z);
-            if (!(r2 >= p.rmin)) {
-                star = true;
-                R[q] = -1.0;
-            } else if (r2 >= p.r_abs) {
-                absb = true;
-                R[q] = -1.0;
-            } else {
-                double st2 = w / r2, ct2 = z / r2;
-                int i2, j2;
-                double a2, b2;
-                locate64(p.nr, p.nth, p.rmin, p.dlog, p.dth, p.rn, p.thn, r2, th2, i2, j2, a2, b2);
-                int di = i2 - i, dj = j2 - j;
-                if (di > 1 || di < -1 || dj > 1 || dj < -1) atomicOr(err, FFPIC_ERR_CFL);
-                // zigzag deposit in coordinates relative to the start cell
-                double x1 = a, y1 = b, x2 = di + a2, y2 = dj + b2;
-                double xr = fmin((di < 0 ? di : 0) + 1.0, fmax((double)(di > 0 ? di : 0), 0.5 * (x1 + x2)));
-                double yr = fmin((dj < 0 ? dj : 0) + 1.0, fmax((double)(dj > 0 ? dj : 0), 0.5 * (y1 + y2)));
+            double st2 = w / r2, ct2 = z / r2;
+            double a2, b2;
+            locate64(p.nr, p.nth, p.rmin, p.dlog, p.dth, p.rn, p.thn, r2, th2, i2, j2, a2, b2);
+            di = i2 - i;
+            dj = j2 - j;
+            bool cfl = di > 1 || di < -1 || dj > 1 || dj < -1;
+            if (cfl) atomicOr(err, FFPIC_ERR_CFL);
+            x1 = a; y1 = b; x2 = di + a2; y2 = dj + b2;
+            R[q] = r2;
+            TH[q] = th2;
+            UR[q] = ux * st2 + uz * ct2;
+            UT[q] = ux * ct2 - uz * st2;
+            UP[q] = uy;
+            if (di == 0 && dj == 0) {
+                // zigzag with both ends in the cell: the two segments share
+                // the four faces of the cell, mid-point cell = the cell
+                double xr = fmin(1.0, fmax(0.0, 0.5 * (x1 + x2)));
+                double yr = fmin(1.0, fmax(0.0, 0.5 * (y1 + y2)));
                 double Q = p.Q;
                 double fx1 = Q * (xr - x1), fy1 = Q * (yr - y1);
                 double fx2 = Q * (x2 - xr), fy2 = Q * (y2 - yr);
                 double wx1 = 0.5 * (x1 + xr), wy1 = 0.5 * (y1 + yr);
-                double wx2 = 0.5 * (xr + x2) - di, wy2 = 0.5 * (yr + y2) - dj;
-                gadd(&Jr[ix(ld, i, j)], fx1 * (1.0 - wy1));
-                gadd(&Jr[ix(ld, i, j + 1)], fx1 * wy1);
-                gadd(&Jt[ix(ld, i, j)], fy1 * (1.0 - wx1));
-                gadd(&Jt[ix(ld, i + 1, j)], fy1 * wx1);
-                gadd(&Jr[ix(ld, i2, j2)], fx2 * (1.0 - wy2));
-                gadd(&Jr[ix(ld, i2, j2 + 1)], fx2 * wy2);
-                gadd(&Jt[ix(ld, i2, j2)], fy2 * (1.0 - wx2));
-                gadd(&Jt[ix(ld, i2 + 1, j2)], fy2 * wx2);
+                double wx2 = 0.5 * (xr + x2), wy2 = 0.5 * (yr + y2);
+                s[0] = fx1 * (1.0 - wy1) + fx2 * (1.0 - wy2);
+                s[1] = fx1 * wy1 + fx2 * wy2;
+                s[2] = fy1 * (1.0 - wx1) + fy2 * (1.0 - wx2);
+                s[3] = fy1 * wx1 + fy2 * wx2;
                 double xm = 0.5 * (x1 + x2), ym = 0.5 * (y1 + y2);
                 int im = (int)floor(xm), jm = (int)floor(ym);
                 if (i + im > p.nr - 1) im = p.nr - 1 - i;
                 if (j + jm > p.nth - 1) jm = p.nth - 1 - j;
-                double wx = xm - im, wy = ym - jm;
-                double qv = Q * v1;
-                gadd(&Jp[ix(ld, i + im, j + jm)], qv * (1.0 - wx) * (1.0 - wy));
-                gadd(&Jp[ix(ld, i + im + 1, j + jm)], qv * wx * (1.0 - wy));
-                gadd(&Jp[ix(ld, i + im, j + jm + 1)], qv * (1.0 - wx) * wy);
-                gadd(&Jp[ix(ld, i + im + 1, j + jm + 1)], qv * wx * wy);
-                R[q] = r2;
-                TH[q] = th2;
-                UR[q] = ux * st2 + uz * ct2;
-                UT[q] = ux * ct2 - uz * st2;
-                UP[q] = uy;
+                if (im == 0 && jm == 0) {
+                    double wx = xm, wy = ym, qv = Q * v1;
+                    s[4] = qv * (1.0 - wx) * (1.0 - wy);
+                    s[5] = qv * wx * (1.0 - wy);
+                    s[6] = qv * (1.0 - wx) * wy;
+                    s[7] = qv * wx * wy;
+                    simple = true;
+                } else {
+                    cross = true;
+                }
+            } else if (!cfl) {
+                cross = true;
+            } else {
+                cross = true;     // flagged; deposit anyway (indices stay in range)
             }
         }
+    }
+    // same-cell in-cell moves: sum across the wavefront, one lane adds
+    bool pend = simple;
+    const int c = (i << 16) | j;
+#pragma unroll 1
+    for (int it = 0; it < 2; it++) {
+        unsigned long long m = __ballot(pend);
+        if (m == 0ull) break;
+        int leader = __ffsll((long long)m) - 1;
+        int lc = __shfl(c, leader, 64);
+        bool part = pend && c == lc;
+        double v[8];
+        for (int k = 0; k < 8; k++) v[k] = wave_sum64(part ? s[k] : 0.0);
+        if (lane == leader) {
+            int li = lc >> 16, lj = lc & 0xffff;
+            acc.add(0, li, lj, v[0]);
+            acc.add(0, li, lj + 1, v[1]);
+            acc.add(1, li, lj, v[2]);
+            acc.add(1, li + 1, lj, v[3]);
+            acc.add(2, li, lj, v[4]);
+            acc.add(2, li + 1, lj, v[5]);
+            acc.add(2, li, lj + 1, v[6]);
+            acc.add(2, li + 1, lj + 1, v[7]);
+        }
+        pend = pend && !part;
+    }
+    if (pend) {
+        acc.add(0, i, j, s[0]);
+        acc.add(0, i, j + 1, s[1]);
+        acc.add(1, i, j, s[2]);
+        acc.add(1, i + 1, j, s[3]);
+        acc.add(2, i, j, s[4]);
+        acc.add(2, i + 1, j, s[5]);
+        acc.add(2, i, j + 1, s[6]);
+        acc.add(2, i + 1, j + 1, s[7]);
+    }
+    if (cross) {
+        // general zigzag in coordinates relative to the start cell
+        Acc64 gacc = acc;
+        if (di > 1 || di < -1 || dj > 1 || dj < -1) gacc.tile = nullptr;   // outside the patch
+        double xr = fmin((di < 0 ? di : 0) + 1.0, fmax((double)(di > 0 ? di : 0), 0.5 * (x1 + x2)));
+        double yr = fmin((dj < 0 ? dj : 0) + 1.0, fmax((double)(dj > 0 ? dj : 0), 0.5 * (y1 + y2)));
+        double Q = p.Q;
+        double fx1 = Q * (xr - x1), fy1 = Q * (yr - y1);
+        double fx2 = Q * (x2 - xr), fy2 = Q * (y2 - yr);
+        double wx1 = 0.5 * (x1 + xr), wy1 = 0.5 * (y1 + yr);
+        double wx2 = 0.5 * (xr + x2) - di, wy2 = 0.5 * (yr + y2) - dj;
+        gacc.add(0, i, j, fx1 * (1.0 - wy1));
+        gacc.add(0, i, j + 1, fx1 * wy1);
+        gacc.add(1, i, j, fy1 * (1.0 - wx1));
+        gacc.add(1, i + 1, j, fy1 * wx1);
+        gacc.add(0, i2, j2, fx2 * (1.0 - wy2));
+        gacc.add(0, i2, j2 + 1, fx2 * wy2);
+        gacc.add(1, i2, j2, fy2 * (1.0 - wx2));
+        gacc.add(1, i2 + 1, j2, fy2 * wx2);
+        double xm = 0.5 * (x1 + x2), ym = 0.5 * (y1 + y2);
+        int im = (int)floor(xm), jm = (int)floor(ym);
+        if (i + im > p.nr - 1) im = p.nr - 1 - i;
+        if (j + jm > p.nth - 1) jm = p.nth - 1 - j;
+        double wx = xm - im, wy = ym - jm;
+        double qv = Q * v1;
+        gacc.add(2, i + im, j + jm, qv * (1.0 - wx) * (1.0 - wy));
+        gacc.add(2, i + im + 1, j + jm, qv * wx * (1.0 - wy));
+        gacc.add(2, i + im, j + jm + 1, qv * (1.0 - wx) * wy);
+        gacc.add(2, i + im + 1, j + jm + 1, qv * wx * wy);
     }
     count_wave(&removed[1], killed);
     count_wave(&removed[2], star);
     count_wave(&removed[3], absb);
+    if (use_lds) {
+        __syncthreads();
+        for (int e = tid; e < TI * TJ; e += 256) {
+            int ti = e / TJ, tj = e - ti * TJ;
+            int gi = ti0 + ti, gj = tj0 + tj;
+            if (gi < 0 || gi > p.nr || gj < 0 || gj > p.nth) continue;
+            size_t gk = ix(p.ld, gi, gj);
+            double w0 = tile[e], w1 = tile[kTile64 + e], w2 = tile[2 * kTile64 + e];
+            if (w0 != 0.0) gadd(&Jr[gk], w0);
+            if (w1 != 0.0) gadd(&Jt[gk], w1);
+            if (w2 != 0.0) gadd(&Jp[gk], w2);
+        }
+    }
 }
 
 void push64(ffpic_ctx *c, int s) {

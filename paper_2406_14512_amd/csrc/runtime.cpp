@@ -89,6 +89,9 @@ std::string validate(const ffpic_desc *d) {
     if (!d) return "descriptor is NULL";
     if (d->nr < 2 || d->nth < 2 || d->nr > 65535 || d->nth > 65535)
         return "nr and nth must lie in [2, 65535]";
+    // the kernels address field arrays with 32-bit byte offsets
+    if ((int64_t)(d->nr + 1) * (d->nth + 1) > (int64_t(1) << 29))
+        return "grid too large: (nr+1)*(nth+1) must not exceed 2^29";
     if (!(d->rmin > 0) || !(d->rmax > d->rmin) || !std::isfinite(d->rmax))
         return "need 0 < rmin < rmax";
     if (!(d->r_abs > d->rmin) || !(d->r_abs <= d->rmax)) return "need rmin < r_abs <= rmax";
@@ -105,7 +108,8 @@ std::string validate(const ffpic_desc *d) {
     if (d->sort_interval < 1) return "sort_interval must be >= 1";
     if (d->nspec < 0 || d->nspec > FFPIC_MAX_SPECIES) return "nspec out of range";
     for (int s = 0; s < d->nspec; s++) {
-        if (d->capacity[s] < 0 || d->capacity[s] > 0x7fffffff) return "capacity out of range";
+        if (d->capacity[s] < 0 || d->capacity[s] > (int64_t(1) << 30))
+            return "capacity out of range [0, 2^30]";
         if (!std::isfinite(d->qm[s]) || d->qm[s] == 0.0) return "qm must be finite and non-zero";
         if (!std::isfinite(d->weight[s]) || d->weight[s] < 0) return "weight must be >= 0";
     }
@@ -422,9 +426,7 @@ int ffpic_create(const ffpic_desc *d, void *stream, ffpic_ctx **out) {
             c->keys[k] = (uint32_t *)dmalloc((size_t)maxcap * 4);
             c->vals[k] = (uint32_t *)dmalloc((size_t)maxcap * 4);
         }
-        int bits = 1;
-        while ((1ull << bits) <= (uint64_t)c->nr * c->nth) bits++;
-        c->sort_tmp_bytes = sort_temp_bytes(maxcap, bits);
+        c->sort_tmp_bytes = sort_temp_bytes(maxcap, sort_key_bits(c));
         c->sort_tmp = dmalloc(c->sort_tmp_bytes);
         c->nslots = (int32_t *)dmalloc(FFPIC_MAX_SPECIES * sizeof(int32_t));
         c->nalive = (int32_t *)dmalloc(FFPIC_MAX_SPECIES * sizeof(int32_t));
