@@ -19,8 +19,8 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -33,8 +33,66 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_PARTICLE = {1: 48.0, 0: 80.0}   # algorithmic push+deposit bytes (read + write state)
 
 
+# HBM counters of the dominant kernel (rocprofv3 FETCH_SIZE / WRITE_SIZE runs of
+# this script, scaled by the same counters for a plain copy); valid only for the
+# kernel source they were taken from
+COUNTER_FILE = {1: "profiles/k_push32_sheet4096_hbm_counters.txt",
+                0: "profiles/k_push64_sheet4096_hbm_counters.txt"}
+KERNEL_SOURCES = {1: ["paper_2406_14512_amd/csrc/k_push32.hip"],
+                  0: ["paper_2406_14512_amd/csrc/k_push64.hip"]}
+COMMON_SOURCES = ["paper_2406_14512_amd/csrc/device_common.h",
+                  "paper_2406_14512_amd/csrc/ffpic_internal.h"]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash(precision):
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[precision] + COMMON_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(precision):
+    """HBM bytes per launch from the committed counter summary, or None when
+    the summary is absent or the kernel source has changed since."""
+    path = os.path.join(ROOT, COUNTER_FILE[precision])
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith(" "):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != kernel_source_hash(precision):
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_bandwidth(nbytes=1 << 30, reps=5):
+    """Plain device-to-device copy of nbytes, timed with events: GB/s of
+    read + written bytes (the measured ceiling beside the 8 TB/s spec)."""
+    import torch
+    a = torch.ones(nbytes // 4, device="cuda", dtype=torch.float32)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    s = e0.elapsed_time(e1) / 1e3 / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / s / 1e9
 
 
 def make_sim(ffpic, w, precision):
@@ -60,7 +118,7 @@ def run_timed(ffpic, sim, steps, warmup, nspec):
     return dict(wall=wall, phases=ph, alive0=alive0, alive1=alive1)
 
 
-def roofline(precision, res, steps, nspec):
+def roofline(precision, res, steps, nspec, copy_gbs):
     # dominant kernel: the push + deposit kernel, one launch per species and
     # step; algorithmic bytes = state read + written per live particle
     n_avg = 0.5 * (res["alive0"] + res["alive1"])
@@ -70,10 +128,12 @@ def roofline(precision, res, steps, nspec):
     bytes_per_launch = BYTES_PER_PARTICLE[precision] * n_avg / nspec
     achieved = bytes_per_launch / avg_launch_s / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(precision),
             "kernel": "k_push32" if precision == 1 else "k_push64",
             "avg_launch_ms": round(avg_launch_s * 1e3, 4),
-            "bytes_per_launch": bytes_per_launch}
+            "bytes_per_launch": bytes_per_launch,
+            "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
 
 
 def cpu_baseline(w, n_sample, steps=2):
@@ -117,17 +177,30 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2_000_000)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run three plain 1 GiB device copies (for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no "
               "multi-GPU path", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        import torch
+        a = torch.ones(1 << 28, device="cuda", dtype=torch.float32)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": 1 << 30, "copies": 3}), flush=True)
+        return
 
     from paper_2406_14512_amd import ffpic
     from paper_2406_14512_amd import workloads as W
 
     w = W.sheet_4096(n_total=args.n_total)
     w.nr = w.nth = args.grid
+    copy_gbs = copy_bandwidth()
+    log(f"plain device copy: {copy_gbs:.0f} GB/s")
     precisions = [1] if args.no_fp64 else [1, 0]
     sims = {p: make_sim(ffpic, w, p) for p in precisions}
     t0 = time.perf_counter()
@@ -175,7 +248,7 @@ def main():
         "cell_updates_per_s": w.nr * w.nth * args.steps / r["wall"],
         "phase_ms_per_step": {k: round(v / args.steps, 4)
                               for k, v in zip(("mask", "sort", "push_deposit", "fields"), r["phases"])},
-        "roofline": roofline(1, r, args.steps, w.nspec),
+        "roofline": roofline(1, r, args.steps, w.nspec, copy_gbs),
     }
     if 0 in results:
         r64 = results[0]
@@ -186,7 +259,7 @@ def main():
                        "phase_ms_per_step": {k: round(v / args.steps, 4) for k, v in
                                              zip(("mask", "sort", "push_deposit", "fields"),
                                                  r64["phases"])},
-                       "roofline": roofline(0, r64, args.steps, w.nspec)}
+                       "roofline": roofline(0, r64, args.steps, w.nspec, copy_gbs)}
         out["fp32_over_fp64"] = out["value"] / out["fp64"]["value"]
     sims[1].close()
     if not args.no_cpu_baseline:
