@@ -114,7 +114,7 @@ typedef struct ffpic_desc {
     int32_t ff_enable;        /* 0: pure PIC (f = 0 everywhere) */
     int32_t precision;        /* enum ffpic_precision */
     int32_t init;             /* enum ffpic_init */
-    int32_t sort_interval;    /* >= 1 */
+    int32_t sort_interval;    /* >= 1; 0 = the tuned value (see ffpic_autotune) */
     int32_t nspec;            /* 0 .. FFPIC_MAX_SPECIES */
     int32_t pad_;
     int64_t capacity[FFPIC_MAX_SPECIES]; /* particle slots per species */
@@ -215,6 +215,15 @@ int ffpic_num_particles(ffpic_ctx *ctx, int species, int64_t *n);
 int ffpic_get_particles(ffpic_ctx *ctx, int species, double *r, double *th,
                         double *ur, double *uth, double *uph, int32_t *cell);
 
+/* As ffpic_get_particles for the slots [first, first + count) only; the
+   range is clipped to the current slots and *count receives the number
+   copied.  After a sort the slots of a range of cells are contiguous
+   (ffpic_get_sort), so a band of cells can be read without copying the
+   whole species.  EINVAL for a negative first or count.  Synchronises. */
+int ffpic_get_particles_range(ffpic_ctx *ctx, int species, int64_t first, int64_t *count,
+                              double *r, double *th, double *ur, double *uth, double *uph,
+                              int32_t *cell);
+
 /* Test hook: cell offsets of the last sort of a species (nr*nth + 1 int32
    to host memory): offsets[k] = number of live particles with cell < k. */
 int ffpic_get_sort(ffpic_ctx *ctx, int species, int32_t *cell_offsets);
@@ -236,6 +245,71 @@ int ffpic_restore(ffpic_ctx *ctx, const void *buf, size_t len);
    Requires ffpic_set_timing(ctx, 1) before the step. */
 int ffpic_set_timing(ffpic_ctx *ctx, int enable);
 int ffpic_phase_times(ffpic_ctx *ctx, float out[4]);
+
+
+/* ---------------------------------------------------------------------
+ * Batches of independent magnetospheres (many small systems on one GPU).
+ *
+ * ffpic_batch_create builds n systems from the n descriptors d[0..n-1].
+ * Their kernels run on up to four library-owned streams, so that the
+ * small grids run concurrently.  Systems are assigned to streams by
+ * longest-processing-time-first packing on particles plus grid nodes.
+ * `stream` is the caller's stream (borrowed; NULL = default stream):
+ * ffpic_batch_step is ordered after the work already queued on it, and
+ * work queued on it afterwards waits for the whole batch step.  EINVAL for
+ * n < 1 or a rejected descriptor, ENOMEM, EHIP; on failure nothing is left
+ * allocated.
+ *
+ * ffpic_batch_view gives system k as an ordinary context (non-owning):
+ * every ffpic_* call works on it (loading particles, diagnostics, fields,
+ * checkpoints, autotune).  ffpic_destroy on a view does nothing; the views
+ * are released by ffpic_batch_destroy, which first drains the streams.
+ * ffpic_batch_sync returns the first device error of any system.
+ */
+int ffpic_batch_create(int n, const ffpic_desc *d, void *stream, ffpic_batch **out);
+int ffpic_batch_view(ffpic_batch *b, int k, ffpic_ctx **view);
+int ffpic_batch_size(const ffpic_batch *b);
+int ffpic_batch_step(ffpic_batch *b, int32_t nsteps);
+int ffpic_batch_sync(ffpic_batch *b);
+const char *ffpic_batch_last_error(const ffpic_batch *b);
+int ffpic_batch_destroy(ffpic_batch *b);
+
+/* ---------------------------------------------------------------------
+ * Autotuning of the sort interval.
+ *
+ * A sort costs one pass over all particle state.  Sorted particles make the
+ * push's field gather and current deposit local.  The best interval depends
+ * on the workload.  ffpic_autotune checkpoints the context to host memory
+ * (as ffpic_save), times whole sort cycles of the candidate intervals
+ * 8, 1, 2, 4, 16, 32 from that state, while the wall time stays within
+ * budget_ms (the first candidate is always timed).  It then restores the
+ * checkpoint and keeps the fastest interval.
+ *
+ * The state after the call equals the state before it.  The interval only
+ * reorders particles, so results change by the order of floating-point
+ * atomic additions in the deposit and in no other way.
+ *
+ * If the environment variable FFPIC_TUNING_CACHE names a file, a line
+ * "nr nth precision nspec slots interval" is appended to it.  ffpic_create
+ * with sort_interval = 0 takes the last matching line (same nr, nth,
+ * precision, nspec), else 8.
+ *
+ * Errors: EINVAL for a non-positive budget; a context in error
+ * (ffpic_sync fails) is not tuned.  ffpic_batch_autotune tunes every system
+ * with an equal share of the budget and writes n entries to out.
+ */
+#define FFPIC_TUNE_MAX 8
+typedef struct ffpic_tuning {
+    int32_t sort_interval;               /* the interval chosen (and now in use) */
+    int32_t ncand;                       /* candidates timed */
+    int32_t cand[FFPIC_TUNE_MAX];        /* their intervals */
+    int32_t pad_;
+    double ms_per_step[FFPIC_TUNE_MAX];  /* measured GPU time per step */
+    double total_ms;                     /* wall time spent tuning */
+} ffpic_tuning;
+
+int ffpic_autotune(ffpic_ctx *ctx, double budget_ms, ffpic_tuning *out);
+int ffpic_batch_autotune(ffpic_batch *b, double budget_ms, ffpic_tuning *out);
 
 #ifdef __cplusplus
 }

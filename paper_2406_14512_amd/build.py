@@ -20,10 +20,13 @@ ARCH = "gfx950"
 
 SOURCES = [
     ("runtime.cpp", []),
+    ("batch.cpp", []),
     ("k_fields64.hip", ["-ffp-contract=off"]),
     ("k_fields32.hip", []),
     ("k_push64.hip", ["-ffp-contract=off"]),
-    ("k_push32.hip", []),
+    # LDS adds of the row sums share one address per wave: keep them plain
+    # atomics instead of the compiler's lane-by-lane pre-reduction loop
+    ("k_push32.hip", ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]),
     ("k_sort.hip", []),
     ("k_misc.hip", []),
 ]

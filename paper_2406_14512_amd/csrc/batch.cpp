@@ -1,0 +1,364 @@
+// Independent magnetospheres stepped together, and the sort-interval
+// autotuner.  Both are built on the single-context entry points.
+//
+// Batch: every system is an ordinary context (a "view") whose kernels run on
+// one of a few library-owned streams.  Systems are assigned to the streams by
+// longest-processing-time-first bin packing on an estimated cost (particle
+// slots plus grid nodes), so small grids, whose kernels cannot fill the chip
+// alone, run concurrently with others.  A batch step forks from the caller's
+// stream with an event, issues one step of every system per time step
+// (systems interleaved across the streams), and joins back with one event per
+// stream, so the caller's stream sees the whole batch step as one ordered
+// operation.
+//
+// Autotune: the sort costs a pass over all particle state, while sorted
+// particles make the push's gather and deposit local; the best interval
+// depends on the workload.  The tuner checkpoints the context to host memory,
+// times whole sort cycles of each candidate interval from that same state,
+// restores the checkpoint and keeps the fastest interval.  The sort interval
+// only reorders particles, so the choice changes results by the order of
+// floating-point atomic additions in the deposit and nothing else.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "ffpic_internal.h"
+
+struct ffpic_batch {
+    hipStream_t caller = nullptr;
+    std::vector<ffpic_ctx *> ctx;
+    std::vector<hipStream_t> streams;
+    std::vector<int> lane;            // stream of each system
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> join;     // one per stream
+    std::string last_error;
+};
+
+namespace {
+
+constexpr int kMaxStreams = 4;        // hardware queues a process gets by default
+constexpr int kCandidates[] = {1, 2, 4, 8, 16, 32};
+
+struct BFail {
+    int code;
+    std::string msg;
+};
+
+#define BCHK(x)                                                                           \
+    do {                                                                                  \
+        hipError_t e_ = (x);                                                              \
+        if (e_ != hipSuccess) throw BFail{FFPIC_EHIP, std::string(#x ": ") + hipGetErrorString(e_)}; \
+    } while (0)
+
+template <class F>
+int bguard(ffpic_batch *b, F &&f) {
+    try {
+        f();
+        return FFPIC_OK;
+    } catch (const BFail &e) {
+        if (b) b->last_error = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        if (b) b->last_error = "host allocation failed";
+        return FFPIC_ENOMEM;
+    } catch (const std::exception &e) {
+        if (b) b->last_error = e.what();
+        return FFPIC_EHIP;
+    }
+}
+
+double cost_of(const ffpic_desc &d) {
+    double parts = 0;
+    for (int s = 0; s < d.nspec && s < FFPIC_MAX_SPECIES; s++) parts += (double)d.capacity[s];
+    // one node of the field step costs about as much as four particle pushes
+    return parts + 4.0 * (double)(d.nr + 1) * (double)(d.nth + 1);
+}
+
+void release(ffpic_batch *b) {
+    for (size_t k = 0; k < b->ctx.size(); k++) {
+        if (!b->ctx[k]) continue;
+        b->ctx[k]->batch_owned = false;
+        ffpic_destroy(b->ctx[k]);
+    }
+    b->ctx.clear();
+    for (auto s : b->streams) (void)hipStreamDestroy(s);
+    b->streams.clear();
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    for (auto e : b->join) (void)hipEventDestroy(e);
+    b->join.clear();
+}
+
+std::string cache_key(const ffpic_ctx *c) {
+    std::ostringstream o;
+    o << c->nr << ' ' << c->nth << ' ' << c->d.precision << ' ' << c->d.nspec;
+    return o.str();
+}
+
+int64_t total_slots(ffpic_ctx *c) {
+    int64_t n = 0;
+    for (int s = 0; s < c->d.nspec; s++) {
+        int64_t k = 0;
+        if (ffpic_num_particles(c, s, &k) == FFPIC_OK) n += k;
+    }
+    return n;
+}
+
+// ms per step of `steps` steps from the current state, timed with events on
+// the context's stream
+double time_steps(ffpic_ctx *c, int steps) {
+    hipEvent_t e0, e1;
+    BCHK(hipEventCreate(&e0));
+    BCHK(hipEventCreate(&e1));
+    BCHK(hipEventRecord(e0, c->stream));
+    int rc = ffpic_step(c, steps);
+    BCHK(hipEventRecord(e1, c->stream));
+    BCHK(hipEventSynchronize(e1));
+    float ms = 0;
+    BCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != FFPIC_OK) throw BFail{rc, std::string("step failed: ") + ffpic_last_error(c)};
+    return ms / steps;
+}
+
+void tune_one(ffpic_ctx *c, double budget_ms, ffpic_tuning *out) {
+    auto t0 = std::chrono::steady_clock::now();
+    auto elapsed_ms = [&] {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    };
+    int rc = ffpic_sync(c);
+    if (rc != FFPIC_OK) throw BFail{rc, std::string("context in error: ") + ffpic_last_error(c)};
+    size_t len = 0;
+    rc = ffpic_save(c, nullptr, &len);
+    if (rc != FFPIC_OK) throw BFail{rc, ffpic_last_error(c)};
+    std::vector<char> ckpt(len);
+    rc = ffpic_save(c, ckpt.data(), &len);
+    if (rc != FFPIC_OK) throw BFail{rc, ffpic_last_error(c)};
+    const int32_t keep = c->d.sort_interval;
+    const int timing = c->timing;
+    c->timing = 0;
+    ffpic_tuning t{};
+    double best = 0;
+    try {
+        // the default interval first, so a small budget still measures it
+        std::vector<int> order = {8, 1, 2, 4, 16, 32};
+        double last_ms = 0;
+        for (int cand : order) {
+            if (t.ncand >= FFPIC_TUNE_MAX) break;
+            int steps = std::max(cand, 8);
+            if (t.ncand > 0 && elapsed_ms() + last_ms * steps * 1.5 > budget_ms) continue;
+            rc = ffpic_restore(c, ckpt.data(), len);
+            if (rc != FFPIC_OK) throw BFail{rc, ffpic_last_error(c)};
+            c->d.sort_interval = cand;
+            c->step = 0;              // the first timed step sorts
+            double ms = time_steps(c, steps);
+            t.cand[t.ncand] = cand;
+            t.ms_per_step[t.ncand] = ms;
+            t.ncand++;
+            last_ms = ms;
+            if (t.ncand == 1 || ms < best) { best = ms; t.sort_interval = cand; }
+        }
+    } catch (...) {
+        (void)ffpic_restore(c, ckpt.data(), len);
+        c->d.sort_interval = keep;
+        c->timing = timing;
+        throw;
+    }
+    rc = ffpic_restore(c, ckpt.data(), len);
+    c->timing = timing;
+    if (rc != FFPIC_OK) {
+        c->d.sort_interval = keep;
+        throw BFail{rc, ffpic_last_error(c)};
+    }
+    c->d.sort_interval = t.sort_interval;
+    t.total_ms = elapsed_ms();
+    if (out) *out = t;
+    if (const char *path = std::getenv("FFPIC_TUNING_CACHE")) {
+        if (*path) {
+            std::ofstream f(path, std::ios::app);
+            if (f) f << cache_key(c) << ' ' << total_slots(c) << ' ' << t.sort_interval << '\n';
+        }
+    }
+}
+
+}  // namespace
+
+namespace ffpic {
+
+// sort interval for a descriptor that asks for the tuned one (0): the last
+// cache entry with the same grid, precision and species count, else 8
+int tuned_sort_interval(const ffpic_desc *d) {
+    int pick = 8;
+    const char *path = std::getenv("FFPIC_TUNING_CACHE");
+    if (!path || !*path) return pick;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        std::istringstream in(line);
+        long nr, nth, prec, nspec, nslots, si;
+        if (!(in >> nr >> nth >> prec >> nspec >> nslots >> si)) continue;
+        if (nr == d->nr && nth == d->nth && prec == d->precision && nspec == d->nspec && si >= 1 &&
+            si <= 1024)
+            pick = (int)si;
+    }
+    return pick;
+}
+
+}  // namespace ffpic
+
+extern "C" {
+
+int ffpic_batch_create(int n, const ffpic_desc *d, void *stream, ffpic_batch **out) {
+    if (!out) return FFPIC_EINVAL;
+    *out = nullptr;
+    if (n < 1 || !d) return FFPIC_EINVAL;
+    ffpic_batch *b = new (std::nothrow) ffpic_batch();
+    if (!b) return FFPIC_ENOMEM;
+    int rc = bguard(b, [&] {
+        b->caller = (hipStream_t)stream;
+        int ns = std::min(n, kMaxStreams);
+        for (int s = 0; s < ns; s++) {
+            hipStream_t h;
+            BCHK(hipStreamCreateWithFlags(&h, hipStreamNonBlocking));
+            b->streams.push_back(h);
+            hipEvent_t e;
+            BCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            b->join.push_back(e);
+        }
+        BCHK(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+        // longest processing time first onto the least loaded stream
+        std::vector<int> order(n);
+        for (int k = 0; k < n; k++) order[k] = k;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int x, int y) { return cost_of(d[x]) > cost_of(d[y]); });
+        std::vector<double> load(ns, 0.0);
+        b->lane.assign(n, 0);
+        for (int k : order) {
+            int s = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            b->lane[k] = s;
+            load[s] += cost_of(d[k]);
+        }
+        b->ctx.assign(n, nullptr);
+        for (int k = 0; k < n; k++) {
+            ffpic_ctx *c = nullptr;
+            int r = ffpic_create(&d[k], b->streams[b->lane[k]], &c);
+            if (r != FFPIC_OK)
+                throw BFail{r, "system " + std::to_string(k) + ": descriptor rejected or allocation failed"};
+            c->batch_owned = true;
+            b->ctx[k] = c;
+        }
+    });
+    if (rc != FFPIC_OK) {
+        release(b);
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return FFPIC_OK;
+}
+
+int ffpic_batch_view(ffpic_batch *b, int k, ffpic_ctx **view) {
+    if (!b || !view) return FFPIC_EINVAL;
+    if (k < 0 || k >= (int)b->ctx.size()) {
+        b->last_error = "system index out of range";
+        return FFPIC_EINVAL;
+    }
+    *view = b->ctx[k];
+    return FFPIC_OK;
+}
+
+int ffpic_batch_size(const ffpic_batch *b) { return b ? (int)b->ctx.size() : 0; }
+
+int ffpic_batch_step(ffpic_batch *b, int32_t nsteps) {
+    return bguard(b, [&] {
+        if (!b) throw BFail{FFPIC_EINVAL, "batch is NULL"};
+        if (nsteps < 0) throw BFail{FFPIC_EINVAL, "negative step count"};
+        if (nsteps == 0) return;
+        BCHK(hipEventRecord(b->fork, b->caller));
+        for (auto s : b->streams) BCHK(hipStreamWaitEvent(s, b->fork, 0));
+        int failed = FFPIC_OK;
+        std::string why;
+        for (int k = 0; k < nsteps && failed == FFPIC_OK; k++)
+            for (size_t q = 0; q < b->ctx.size(); q++) {
+                int r = ffpic_step(b->ctx[q], 1);
+                if (r != FFPIC_OK) {
+                    failed = r;
+                    why = "system " + std::to_string(q) + ": " + ffpic_last_error(b->ctx[q]);
+                    break;
+                }
+            }
+        // join even after a failure, so the caller's stream stays ordered
+        for (size_t s = 0; s < b->streams.size(); s++) {
+            BCHK(hipEventRecord(b->join[s], b->streams[s]));
+            BCHK(hipStreamWaitEvent(b->caller, b->join[s], 0));
+        }
+        if (failed != FFPIC_OK) throw BFail{failed, why};
+    });
+}
+
+int ffpic_batch_sync(ffpic_batch *b) {
+    return bguard(b, [&] {
+        if (!b) throw BFail{FFPIC_EINVAL, "batch is NULL"};
+        for (size_t q = 0; q < b->ctx.size(); q++) {
+            int r = ffpic_sync(b->ctx[q]);
+            if (r != FFPIC_OK)
+                throw BFail{r, "system " + std::to_string(q) + ": " + ffpic_last_error(b->ctx[q])};
+        }
+    });
+}
+
+const char *ffpic_batch_last_error(const ffpic_batch *b) {
+    return b ? b->last_error.c_str() : "no batch";
+}
+
+int ffpic_batch_destroy(ffpic_batch *b) {
+    if (!b) return FFPIC_EINVAL;
+    for (auto s : b->streams) (void)hipStreamSynchronize(s);
+    release(b);
+    delete b;
+    return FFPIC_OK;
+}
+
+int ffpic_autotune(ffpic_ctx *ctx, double budget_ms, ffpic_tuning *out) {
+    if (!ctx) return FFPIC_EINVAL;
+    if (!(budget_ms > 0)) {
+        ctx->last_error = "budget must be positive";
+        return FFPIC_EINVAL;
+    }
+    try {
+        tune_one(ctx, budget_ms, out);
+        return FFPIC_OK;
+    } catch (const BFail &e) {
+        ctx->last_error = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        ctx->last_error = "host allocation failed";
+        return FFPIC_ENOMEM;
+    } catch (const std::exception &e) {
+        ctx->last_error = e.what();
+        return FFPIC_EHIP;
+    }
+}
+
+int ffpic_batch_autotune(ffpic_batch *b, double budget_ms, ffpic_tuning *out) {
+    return bguard(b, [&] {
+        if (!b) throw BFail{FFPIC_EINVAL, "batch is NULL"};
+        if (!(budget_ms > 0)) throw BFail{FFPIC_EINVAL, "budget must be positive"};
+        double each = budget_ms / (double)b->ctx.size();
+        for (size_t q = 0; q < b->ctx.size(); q++) {
+            int r = ffpic_autotune(b->ctx[q], each, out ? out + q : nullptr);
+            if (r != FFPIC_OK)
+                throw BFail{r, "system " + std::to_string(q) + ": " + ffpic_last_error(b->ctx[q])};
+        }
+    });
+}
+
+}  // extern "C"

@@ -95,6 +95,7 @@ struct ffpic_ctx {
     hipEvent_t ev[8] = {};
     std::vector<hipEvent_t> evpool;           // 5 per timed step
     float phase_ms[4] = {};
+    bool batch_owned = false;                 // a view of a batch system
     std::string last_error;
 };
 
@@ -111,7 +112,7 @@ void push_species(ffpic_ctx *c, int s);
 void field_step(ffpic_ctx *c);
 void convert_loaded(ffpic_ctx *c, int s, int64_t off, int64_t n, const double *r,
                     const double *th, const double *ur, const double *uth, const double *uph);
-void export_particles(ffpic_ctx *c, int s, int64_t n, double *r, double *th, double *ur,
+void export_particles(ffpic_ctx *c, int s, int64_t first, int64_t n, double *r, double *th, double *ur,
                       double *uth, double *uph, int32_t *cell);   // device outputs
 void to_f64(ffpic_ctx *c, const void *src, double *dst, size_t n);
 void from_f64(ffpic_ctx *c, const double *src, void *dst, size_t n);
@@ -125,6 +126,7 @@ double max_abs(ffpic_ctx *c, const double *dev, size_t n);
 size_t sort_temp_bytes(int64_t cap, int bits);
 int sort_key_bits(const ffpic_ctx *c);
 void zero_counters(ffpic_ctx *c, int32_t *p, int n);
+int tuned_sort_interval(const ffpic_desc *d);
 
 }  // namespace ffpic
 

@@ -14,50 +14,48 @@ namespace ffpic {
 // ---------------------------------------------------------------------------
 // eq. (psi): Psi(i, 0) = 0, Psi(i, j+1) = Psi(i, j) + B_r(i, j+1/2) A_r(i, j)
 // with A_r = r_i^2 (cos theta_j - cos theta_{j+1}); FP64, sequential in j so
-// that the rounding is fixed.  A workgroup of 64 threads owns 64 radial rows
-// (one row per thread for the scan); the rows are walked in 64-column
-// chunks staged through LDS so that both the B_r loads and the Psi stores
-// are coalesced along theta.
+// that the rounding is fixed.  A workgroup owns kPsiRows radial rows and
+// walks them in tiles of kPsiCols columns: all 256 threads load a tile with
+// coalesced reads along theta into LDS, then one lane per row runs the
+// serial sum over the tile while the next tile's loads are in flight, and
+// the tile of partial sums is written back coalesced.
+constexpr int kPsiRows = 16;
+constexpr int kPsiCols = 256;
+
 template <typename R>
-__global__ void __launch_bounds__(64) k_psi(Geo<double> g, const R *__restrict__ br,
-                                            double *__restrict__ psi) {
-    __shared__ double tile[64][65];
-    __shared__ double area[64];
+__global__ void __launch_bounds__(kPsiCols) k_psi(Geo<double> g, const R *__restrict__ br,
+                                                  double *__restrict__ psi) {
+    __shared__ double tile[kPsiRows][kPsiCols + 1];
+    __shared__ double area[kPsiCols];
     const int t = threadIdx.x;
-    const int i0 = blockIdx.x * 64;
-    const int i = i0 + t;
+    const int i0 = blockIdx.x * kPsiRows;
     const int ld = g.ld, nr = g.nr, nth = g.nth;
-    const int rows = min(64, nr + 1 - i0);
-    double r2 = i <= nr ? g.rn2[i] : 0.0;
+    const int rows = min(kPsiRows, nr + 1 - i0);
+    const double r2 = t < rows ? g.rn2[i0 + t] : 0.0;
     double acc = 0.0;
-    if (i <= nr) psi[ix(ld, i, 0)] = 0.0;
-    for (int j0 = 0; j0 < nth; j0 += 64) {
-        const int w = min(64, nth - j0);
+    if (t < rows) psi[ix(ld, i0 + t, 0)] = 0.0;
+    R nxt[kPsiRows];
+#pragma unroll
+    for (int rr = 0; rr < kPsiRows; rr++)
+        nxt[rr] = (rr < rows && t < nth) ? br[ix(ld, i0 + rr, t)] : (R)0;
+    for (int j0 = 0; j0 < nth; j0 += kPsiCols) {
+        const int w = min(kPsiCols, nth - j0);
+#pragma unroll
+        for (int rr = 0; rr < kPsiRows; rr++) tile[rr][t] = (double)nxt[rr];
         if (t < w) area[t] = g.dcn[j0 + t];
-        for (int rr = 0; rr < rows; rr++)
-            if (t < w) tile[rr][t] = (double)br[ix(ld, i0 + rr, j0 + t)];
         __syncthreads();
+        const int jn = j0 + kPsiCols;
+        if (jn < nth) {
+#pragma unroll
+            for (int rr = 0; rr < kPsiRows; rr++)
+                nxt[rr] = (rr < rows && jn + t < nth) ? br[ix(ld, i0 + rr, jn + t)] : (R)0;
+        }
         if (t < rows) {
-            if (w == 64) {
-                // products are independent; only the running sum is serial
-                double pr[64];
-#pragma unroll
-                for (int k = 0; k < 64; k++) {
+#pragma unroll 8
+            for (int k = 0; k < w; k++) {
 #pragma clang fp contract(off)
-                    pr[k] = tile[t][k] * (r2 * area[k]);
-                }
-#pragma unroll
-                for (int k = 0; k < 64; k++) {
-#pragma clang fp contract(off)
-                    acc = acc + pr[k];
-                    tile[t][k] = acc;
-                }
-            } else {
-                for (int k = 0; k < w; k++) {
-#pragma clang fp contract(off)
-                    acc = acc + tile[t][k] * (r2 * area[k]);
-                    tile[t][k] = acc;
-                }
+                acc = acc + tile[t][k] * (r2 * area[k]);
+                tile[t][k] = acc;
             }
         }
         __syncthreads();
@@ -367,8 +365,8 @@ static void run_field_step(ffpic_ctx *c) {
 template <typename R>
 static void run_psi_mask(ffpic_ctx *c) {
     Geo<double> g = geo<double>(c);
-    hipLaunchKernelGGL(k_psi<R>, dim3((c->nr + 1 + 63) / 64), dim3(64), 0, c->stream, g,
-                       (const R *)c->B[0], c->psi);
+    hipLaunchKernelGGL(k_psi<R>, dim3((c->nr + 1 + kPsiRows - 1) / kPsiRows), dim3(kPsiCols), 0,
+                       c->stream, g, (const R *)c->B[0], c->psi);
     dim3 blk(256), grd((c->nth + 1 + 255) / 256, c->nr + 1);
     const double *t = c->d.psi_thr;
     hipLaunchKernelGGL(k_mask<R>, grd, blk, 0, c->stream, c->nr, c->nth, c->ld,

@@ -125,23 +125,24 @@ __global__ void k_export32(int n, int nth, double dlog, double dth, const double
     ur[q] = UR[q]; ut[q] = UT[q]; up[q] = UP[q];
 }
 
-void export_particles(ffpic_ctx *c, int s, int64_t n, double *r, double *th, double *ur,
-                      double *uth, double *uph, int32_t *cell) {
+void export_particles(ffpic_ctx *c, int s, int64_t first, int64_t n, double *r, double *th,
+                      double *ur, double *uth, double *uph, int32_t *cell) {
     ffpic::Species &S = c->sp[s];
     if (n == 0) return;
     int nb = (int)((n + 255) / 256);
     if (c->fp64) {
-        double **a = (double **)S.cur;
+        const double *a[5];
+        for (int k = 0; k < 5; k++) a[k] = (const double *)S.cur[k] + first;
         hipLaunchKernelGGL(k_export64, dim3(nb), dim3(256), 0, c->stream, (int)n, c->nr, c->nth,
                            c->d.rmin, c->dlog, c->dth, c->dtab64[T_RN], c->dtab64[T_THN], a[0],
                            a[1], a[2], a[3], a[4], r, th, ur, uth, uph, cell);
     } else {
         hipLaunchKernelGGL(k_export32, dim3(nb), dim3(256), 0, c->stream, (int)n, c->nth,
                            c->dlog, c->dth, c->dtab64[T_RN], c->dtab64[T_THN],
-                           (const int32_t *)S.cur[0], (const float *)S.cur[1],
-                           (const float *)S.cur[2], (const float *)S.cur[3],
-                           (const float *)S.cur[4], (const float *)S.cur[5], r, th, ur, uth, uph,
-                           cell);
+                           (const int32_t *)S.cur[0] + first, (const float *)S.cur[1] + first,
+                           (const float *)S.cur[2] + first, (const float *)S.cur[3] + first,
+                           (const float *)S.cur[4] + first, (const float *)S.cur[5] + first, r,
+                           th, ur, uth, uph, cell);
     }
     FFPIC_LAUNCH_CHECK();
 }

@@ -78,6 +78,24 @@ struct Fields {
     __amdgpu_buffer_rsrc_t er, et, ep, br, bt, bp;
 };
 
+// particle state arrays: 32-bit byte offsets (slot * 4) through buffer
+// resources, so no 64-bit address is formed per access
+struct State {
+    __amdgpu_buffer_rsrc_t cell, a, b, ur, ut, up;
+    __device__ __forceinline__ static float ld(__amdgpu_buffer_rsrc_t R, unsigned q) {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(R, (int)(q << 2), 0, 0));
+    }
+    __device__ __forceinline__ static void st(__amdgpu_buffer_rsrc_t R, unsigned q, float v) {
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), R, (int)(q << 2), 0, 0);
+    }
+    __device__ __forceinline__ int ldc(unsigned q) const {
+        return (int)__builtin_amdgcn_raw_buffer_load_b32(cell, (int)(q << 2), 0, 0);
+    }
+    __device__ __forceinline__ void stc(unsigned q, int v) const {
+        __builtin_amdgcn_raw_buffer_store_b32((unsigned)v, cell, (int)(q << 2), 0, 0);
+    }
+};
+
 template <bool LDS>
 struct Acc {
     float *tile;     // LDS patch (LDS mode)
@@ -106,11 +124,11 @@ __device__ __forceinline__ float bil(__amdgpu_buffer_rsrc_t R, unsigned o0, unsi
 }
 
 template <bool LDS>
-__device__ __forceinline__ void push_chunk(
-    const P32 &p, const Fields &F, const Acc<LDS> &acc, const int *cell, int base, int tid,
-    int lane, const uint8_t *__restrict__ kill, int32_t *__restrict__ CELL, float *__restrict__ A,
-    float *__restrict__ Bo, float *__restrict__ UR, float *__restrict__ UT,
-    float *__restrict__ UP, uint32_t *__restrict__ err, int &nkill, int &nstar, int &nabs) {
+__device__ __forceinline__ void push_chunk(const P32 &p, const Fields &F, const Acc<LDS> &acc,
+                                           const int *cell, int base, int tid, int lane,
+                                           const uint8_t *__restrict__ kill, const State &S,
+                                           uint32_t *__restrict__ err, int &nkill, int &nstar,
+                                           int &nabs) {
     const int ld = p.ld, nth = p.nth;
     const unsigned ld4 = (unsigned)ld << 2;
 #pragma unroll 1
@@ -121,7 +139,7 @@ __device__ __forceinline__ void push_chunk(
         const int i = c >> 16, j = c & 0xffff;
         if (live && kill[(unsigned)(i * nth + j)]) {
             live = false;
-            sto(CELL, q, -1);
+            S.stc(q, -1);
             nkill++;
         }
         bool simple = false;       // stays in its cell: 8 adds at fixed offsets
@@ -130,8 +148,8 @@ __device__ __forceinline__ void push_chunk(
         int di = 0, dj = 0;
         float x1 = 0.f, y1 = 0.f, x2 = 0.f, y2 = 0.f, qv = 0.f;
         if (live) {
-            const float a = ldo(A, q), b = ldo(Bo, q);
-            const float ur = ldo(UR, q), ut = ldo(UT, q), up = ldo(UP, q);
+            const float a = State::ld(S.a, q), b = State::ld(S.b, q);
+            const float ur = State::ld(S.ur, q), ut = State::ld(S.ut, q), up = State::ld(S.up, q);
             // ---- staggered bilinear gather
             const bool ah = a >= 0.5f, bh = b >= 0.5f;
             int hr = ah ? i : i - 1;
@@ -208,7 +226,7 @@ __device__ __forceinline__ void push_chunk(
             // ---- move in the local frame
             const float w = r * st;
             const float xx = w + dx;
-            const float w2 = __builtin_sqrtf(xx * xx + dy * dy);
+            const float w2 = __builtin_amdgcn_sqrtf(xx * xx + dy * dy);
             const float den = w2 + w;
             const float dw = den > 0.f ? (2.f * w * dx + dx * dx + dy * dy) * frcp(den) : 0.f;
             const float drr = dw * st + dz * ct;
@@ -242,60 +260,58 @@ __device__ __forceinline__ void push_chunk(
             if (j2 < 0) { j2 = 0; nb = 0.f; dj = -j; }
             if (j2 > nth - 1) { j2 = nth - 1; nb = 0.99999994f; dj = j2 - j; }
             const bool cfl = di > 1 || di < -1 || dj > 1 || dj < -1;
-            const bool finite = isfinite(na) && isfinite(nb) && isfinite(rx) && isfinite(ry) &&
-                                isfinite(rz);
+            // one test for all five: a NaN or an infinity survives the sum
+            const bool finite = __builtin_isfinite(na + nb + rx + ry + rz);
+            const bool star = finite && i2 < 0;
+            const bool absb = finite && !star && (i2 > p.iabs || (i2 == p.iabs && na >= p.aabs));
+            const bool keep = finite && !star && !absb;
+            nstar += star ? 1 : 0;
+            nabs += absb ? 1 : 0;
             if (cfl) atomicOr(err, FFPIC_ERR_CFL);
-            if (!finite) {
-                // flagged in the error word; never deposited
-                atomicOr(err, FFPIC_ERR_NONFINITE);
-                sto(CELL, q, -1);
-            } else if (i2 < 0) {
-                sto(CELL, q, -1);
-                nstar++;
-            } else if (i2 > p.iabs || (i2 == p.iabs && na >= p.aabs)) {
-                sto(CELL, q, -1);
-                nabs++;
-            } else {
-                sto(CELL, q, (i2 << 16) | j2);
-                sto(A, q, na);
-                sto(Bo, q, nb);
-                sto(UR, q, rx * st2 + rz * ct2);
-                sto(UT, q, rx * ct2 - rz * st2);
-                sto(UP, q, ry);
-                x1 = a; y1 = b;
-                x2 = (float)di + na;
-                y2 = (float)dj + nb;
-                qv = ny * ivg;                    // v_phi during the step (before rotation)
-                if (!cfl) {
-                    if (di == 0 && dj == 0) {
-                        simple = true;
-                        const float ddx = x2 - x1, ddy = y2 - y1;
-                        const float xm = 0.5f * (x1 + x2), ym = 0.5f * (y1 + y2);
-                        s1 = ddx * ym;
-                        s0 = ddx - s1;
-                        s3 = ddy * xm;
-                        s2 = ddy - s3;
-                        s5 = qv * xm;
-                        s4 = qv - s5;
-                        s7 = s5 * ym;
-                        s5 = s5 - s7;
-                        s6 = s4 * ym;
-                        s4 = s4 - s6;
-                    } else {
-                        cross = true;
-                    }
-                }
+            // non-finite state is flagged in the error word and never deposited
+            if (!finite) atomicOr(err, FFPIC_ERR_NONFINITE);
+            S.stc(q, keep ? ((i2 << 16) | j2) : -1);
+            if (keep) {
+                State::st(S.a, q, na);
+                State::st(S.b, q, nb);
+                State::st(S.ur, q, rx * st2 + rz * ct2);
+                State::st(S.ut, q, rx * ct2 - rz * st2);
+                State::st(S.up, q, ry);
             }
+            x1 = a; y1 = b;
+            x2 = (float)di + na;
+            y2 = (float)dj + nb;
+            qv = ny * ivg;                        // v_phi during the step (before rotation)
+            const bool incell = di == 0 && dj == 0;
+            simple = keep && !cfl && incell;
+            cross = keep && !cfl && !incell;
+            // the eight adds of an in-cell move, charge included (computed
+            // for every kept particle; used only when it stays in its cell)
+            const float ddx = p.Q * (x2 - x1), ddy = p.Q * (y2 - y1);
+            const float xm = 0.5f * (x1 + x2), ym = 0.5f * (y1 + y2);
+            const float qq = p.Q * qv;
+            s1 = ddx * ym;
+            s0 = ddx - s1;
+            s3 = ddy * xm;
+            s2 = ddy - s3;
+            s5 = qq * xm;
+            s4 = qq - s5;
+            s7 = s5 * ym;
+            s5 = s5 - s7;
+            s6 = s4 * ym;
+            s4 = s4 - s6;
         }
-        // ---- in-cell moves that share the wave leader's cell: DPP sums over
-        // each 16-lane row, the row's first lane adds (two leaders at most)
+        // ---- in-cell moves that share the cell of the wave's first pending
+        // lane: DPP sums over each 16-lane row, and the first lane of every
+        // row with participants adds the row's sums (the four rows meet in
+        // the same LDS words; two such cells per wave at most, sorted
+        // particles rarely span more)
         bool pend = simple;
 #pragma unroll 1
         for (int it = 0; it < 2; it++) {
             const unsigned long long m = __ballot(pend);
             if (m == 0ull) break;
-            const int leader = __ffsll((long long)m) - 1;
-            const int lc = __builtin_amdgcn_readlane(c, leader);
+            const int lc = __builtin_amdgcn_readlane(c, __ffsll((long long)m) - 1);
             const bool part = pend && c == lc;
             const unsigned long long pm = __ballot(part);
             const float v0 = row_sum(part ? s0 : 0.f);
@@ -308,28 +324,26 @@ __device__ __forceinline__ void push_chunk(
             const float v7 = row_sum(part ? s7 : 0.f);
             if ((lane & 15) == 0 && ((pm >> lane) & 0xffffull) != 0ull) {
                 const int li = lc >> 16, lj = lc & 0xffff;
-                const float Q = p.Q;
-                acc.add(0, li, lj, Q * v0);
-                acc.add(0, li, lj + 1, Q * v1);
-                acc.add(1, li, lj, Q * v2);
-                acc.add(1, li + 1, lj, Q * v3);
-                acc.add(2, li, lj, Q * v4);
-                acc.add(2, li + 1, lj, Q * v5);
-                acc.add(2, li, lj + 1, Q * v6);
-                acc.add(2, li + 1, lj + 1, Q * v7);
+                acc.add(0, li, lj, v0);
+                acc.add(0, li, lj + 1, v1);
+                acc.add(1, li, lj, v2);
+                acc.add(1, li + 1, lj, v3);
+                acc.add(2, li, lj, v4);
+                acc.add(2, li + 1, lj, v5);
+                acc.add(2, li, lj + 1, v6);
+                acc.add(2, li + 1, lj + 1, v7);
             }
             pend = pend && !part;
         }
         if (pend) {
-            const float Q = p.Q;
-            acc.add(0, i, j, Q * s0);
-            acc.add(0, i, j + 1, Q * s1);
-            acc.add(1, i, j, Q * s2);
-            acc.add(1, i + 1, j, Q * s3);
-            acc.add(2, i, j, Q * s4);
-            acc.add(2, i + 1, j, Q * s5);
-            acc.add(2, i, j + 1, Q * s6);
-            acc.add(2, i + 1, j + 1, Q * s7);
+            acc.add(0, i, j, s0);
+            acc.add(0, i, j + 1, s1);
+            acc.add(1, i, j, s2);
+            acc.add(1, i + 1, j, s3);
+            acc.add(2, i, j, s4);
+            acc.add(2, i + 1, j, s5);
+            acc.add(2, i, j + 1, s6);
+            acc.add(2, i + 1, j + 1, s7);
         }
         if (cross) {
             // general zigzag (the particle leaves its cell)
@@ -385,6 +399,16 @@ __global__ void __launch_bounds__(kWG) k_push32(
     F.br = __builtin_amdgcn_make_buffer_rsrc((void *)Br, 0, nbytes, kRsrcWord3);
     F.bt = __builtin_amdgcn_make_buffer_rsrc((void *)Bt, 0, nbytes, kRsrcWord3);
     F.bp = __builtin_amdgcn_make_buffer_rsrc((void *)Bp, 0, nbytes, kRsrcWord3);
+    // slots are below 2^30 (the capacity limit), so the byte offset q * 4 and
+    // the range fit the 32 unsigned bits of a buffer resource
+    const int sbytes = (int)(unsigned)min((unsigned long long)nub * 4ull, 0xffffffffull);
+    State S;
+    S.cell = __builtin_amdgcn_make_buffer_rsrc((void *)CELL, 0, sbytes, kRsrcWord3);
+    S.a = __builtin_amdgcn_make_buffer_rsrc((void *)A, 0, sbytes, kRsrcWord3);
+    S.b = __builtin_amdgcn_make_buffer_rsrc((void *)Bo, 0, sbytes, kRsrcWord3);
+    S.ur = __builtin_amdgcn_make_buffer_rsrc((void *)UR, 0, sbytes, kRsrcWord3);
+    S.ut = __builtin_amdgcn_make_buffer_rsrc((void *)UT, 0, sbytes, kRsrcWord3);
+    S.up = __builtin_amdgcn_make_buffer_rsrc((void *)UP, 0, sbytes, kRsrcWord3);
 
     // cells of the chunk and their bounding box
     int cell[kPPT];
@@ -392,7 +416,7 @@ __global__ void __launch_bounds__(kWG) k_push32(
 #pragma unroll
     for (int k = 0; k < kPPT; k++) {
         const int q = base + k * kWG + tid;
-        cell[k] = q < n ? ldo(CELL, (unsigned)q) : -1;
+        cell[k] = q < n ? S.ldc((unsigned)q) : -1;
         if (cell[k] >= 0) {
             const int i = cell[k] >> 16, j = cell[k] & 0xffff;
             imin = min(imin, i); imax = max(imax, i);
@@ -426,8 +450,7 @@ __global__ void __launch_bounds__(kWG) k_push32(
         }
         __syncthreads();
         Acc<true> acc{tile, ti0, tj0, TJ, {Jr, Jt, Jp}, p.ld};
-        push_chunk<true>(p, F, acc, cell, base, tid, lane, kill, CELL, A, Bo, UR, UT, UP, err,
-                         nkill, nstar, nabs);
+        push_chunk<true>(p, F, acc, cell, base, tid, lane, kill, S, err, nkill, nstar, nabs);
         __syncthreads();
         for (int e = tid; e < m; e += kWG) {
             const int ti = e / TJ, tj = e - ti * TJ;
@@ -441,8 +464,7 @@ __global__ void __launch_bounds__(kWG) k_push32(
         }
     } else {
         Acc<false> acc{nullptr, 0, 0, 0, {Jr, Jt, Jp}, p.ld};
-        push_chunk<false>(p, F, acc, cell, base, tid, lane, kill, CELL, A, Bo, UR, UT, UP, err,
-                          nkill, nstar, nabs);
+        push_chunk<false>(p, F, acc, cell, base, tid, lane, kill, S, err, nkill, nstar, nabs);
     }
     int tk = nkill, ts = nstar, ta = nabs;
     for (int o = 32; o >= 1; o >>= 1) {

@@ -105,7 +105,7 @@ std::string validate(const ffpic_desc *d) {
         if (!(d->psi_thr[k] <= d->psi_thr[k + 1])) return "psi thresholds must be non-decreasing";
     if (d->precision != FFPIC_FP64 && d->precision != FFPIC_FP32_MIXED) return "bad precision";
     if (d->init < FFPIC_INIT_ZERO || d->init > FFPIC_INIT_OPEN_DIPOLE) return "bad init";
-    if (d->sort_interval < 1) return "sort_interval must be >= 1";
+    if (d->sort_interval < 0) return "sort_interval must be >= 0 (0 = tuned)";
     if (d->nspec < 0 || d->nspec > FFPIC_MAX_SPECIES) return "nspec out of range";
     for (int s = 0; s < d->nspec; s++) {
         if (d->capacity[s] < 0 || d->capacity[s] > (int64_t(1) << 30))
@@ -371,6 +371,7 @@ int ffpic_create(const ffpic_desc *d, void *stream, ffpic_ctx **out) {
     if (!c) return FFPIC_ENOMEM;
     int rc = guarded(c, [&] {
         c->d = *d;
+        if (c->d.sort_interval == 0) c->d.sort_interval = tuned_sort_interval(d);
         c->stream = (hipStream_t)stream;
         c->nr = d->nr; c->nth = d->nth; c->ld = d->nth + 1;
         c->nn = (size_t)(d->nr + 1) * (size_t)(d->nth + 1);
@@ -471,7 +472,7 @@ int ffpic_create(const ffpic_desc *d, void *stream, ffpic_ctx **out) {
 }
 
 void ffpic_destroy(ffpic_ctx *c) {
-    if (!c) return;
+    if (!c || c->batch_owned) return;   // views are released with their batch
     (void)hipStreamSynchronize(c->stream);
     free_all(c);
     delete c;
@@ -638,27 +639,36 @@ int ffpic_num_particles(ffpic_ctx *c, int s, int64_t *n) {
     });
 }
 
-int ffpic_get_particles(ffpic_ctx *c, int s, double *r, double *th, double *ur, double *uth,
-                        double *uph, int32_t *cell) {
+int ffpic_get_particles_range(ffpic_ctx *c, int s, int64_t first, int64_t *count, double *r,
+                              double *th, double *ur, double *uth, double *uph, int32_t *cell) {
     return guarded(c, [&] {
         check_ctx(c);
         if (s < 0 || s >= c->d.nspec) throw Fail{FFPIC_EINVAL, "bad species"};
+        if (!count || first < 0 || *count < 0) throw Fail{FFPIC_EINVAL, "bad range"};
         int32_t ns = 0;
         HCHK(hipMemcpyAsync(&ns, c->nslots + s, sizeof(ns), hipMemcpyDeviceToHost, c->stream));
         HCHK(hipStreamSynchronize(c->stream));
-        if (ns == 0) return;
-        double *buf = (double *)dmalloc((size_t)ns * (5 * sizeof(double) + sizeof(int32_t)));
+        int64_t n = std::max<int64_t>(0, std::min<int64_t>(*count, (int64_t)ns - first));
+        *count = n;
+        if (n == 0) return;
+        double *buf = (double *)dmalloc((size_t)n * (5 * sizeof(double) + sizeof(int32_t)));
         double *o[5];
-        for (int a = 0; a < 5; a++) o[a] = buf + (size_t)a * ns;
-        int32_t *oc = (int32_t *)(buf + (size_t)5 * ns);
-        export_particles(c, s, ns, o[0], o[1], o[2], o[3], o[4], oc);
+        for (int a = 0; a < 5; a++) o[a] = buf + (size_t)a * n;
+        int32_t *oc = (int32_t *)(buf + (size_t)5 * n);
+        export_particles(c, s, first, n, o[0], o[1], o[2], o[3], o[4], oc);
         double *h[5] = {r, th, ur, uth, uph};
         for (int a = 0; a < 5; a++)
-            if (h[a]) HCHK(hipMemcpyAsync(h[a], o[a], (size_t)ns * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-        if (cell) HCHK(hipMemcpyAsync(cell, oc, (size_t)ns * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+            if (h[a]) HCHK(hipMemcpyAsync(h[a], o[a], (size_t)n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        if (cell) HCHK(hipMemcpyAsync(cell, oc, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
         HCHK(hipStreamSynchronize(c->stream));
         HCHK(hipFree(buf));
     });
+}
+
+int ffpic_get_particles(ffpic_ctx *c, int s, double *r, double *th, double *ur, double *uth,
+                        double *uph, int32_t *cell) {
+    int64_t count = INT64_MAX;
+    return ffpic_get_particles_range(c, s, 0, &count, r, th, ur, uth, uph, cell);
 }
 
 int ffpic_get_sort(ffpic_ctx *c, int s, int32_t *off) {

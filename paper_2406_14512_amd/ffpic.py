@@ -54,6 +54,21 @@ class Diag(C.Structure):
                 ("error_word", C.c_uint32), ("pad_", C.c_uint32)]
 
 
+TUNE_MAX = 8
+
+
+class Tuning(C.Structure):
+    _fields_ = [("sort_interval", C.c_int32), ("ncand", C.c_int32),
+                ("cand", C.c_int32 * TUNE_MAX), ("pad_", C.c_int32),
+                ("ms_per_step", C.c_double * TUNE_MAX), ("total_ms", C.c_double)]
+
+    def as_dict(self) -> Dict:
+        n = self.ncand
+        return {"sort_interval": self.sort_interval,
+                "ms_per_step": {int(self.cand[k]): float(self.ms_per_step[k]) for k in range(n)},
+                "total_ms": float(self.total_ms)}
+
+
 _lib = None
 
 
@@ -82,17 +97,31 @@ def lib():
     L.ffpic_get_field.argtypes = [P, C.c_int, vp, C.c_int]
     L.ffpic_num_particles.argtypes = [P, C.c_int, C.POINTER(C.c_int64)]
     L.ffpic_get_particles.argtypes = [P, C.c_int, vp, vp, vp, vp, vp, vp]
+    L.ffpic_get_particles_range.argtypes = [P, C.c_int, C.c_int64, C.POINTER(C.c_int64),
+                                            vp, vp, vp, vp, vp, vp]
     L.ffpic_get_sort.argtypes = [P, C.c_int, vp]
     L.ffpic_diagnostics.argtypes = [P, C.c_uint32, C.POINTER(Diag), vp]
     L.ffpic_save.argtypes = [P, vp, C.POINTER(C.c_size_t)]
     L.ffpic_restore.argtypes = [P, vp, C.c_size_t]
     L.ffpic_set_timing.argtypes = [P, C.c_int]
     L.ffpic_phase_times.argtypes = [P, C.POINTER(C.c_float)]
+    L.ffpic_batch_create.argtypes = [C.c_int, C.POINTER(Desc), vp, C.POINTER(P)]
+    L.ffpic_batch_view.argtypes = [P, C.c_int, C.POINTER(P)]
+    L.ffpic_batch_size.argtypes = [P]
+    L.ffpic_batch_step.argtypes = [P, C.c_int32]
+    L.ffpic_batch_sync.argtypes = [P]
+    L.ffpic_batch_last_error.argtypes = [P]
+    L.ffpic_batch_last_error.restype = C.c_char_p
+    L.ffpic_batch_destroy.argtypes = [P]
+    L.ffpic_autotune.argtypes = [P, C.c_double, C.POINTER(Tuning)]
+    L.ffpic_batch_autotune.argtypes = [P, C.c_double, C.POINTER(Tuning)]
     for name in ("ffpic_create", "ffpic_info", "ffpic_load_fields", "ffpic_load_particles",
                  "ffpic_step", "ffpic_run_phases", "ffpic_sync", "ffpic_get_field",
                  "ffpic_num_particles", "ffpic_get_particles", "ffpic_get_sort",
                  "ffpic_diagnostics", "ffpic_save", "ffpic_restore", "ffpic_set_timing",
-                 "ffpic_phase_times"):
+                 "ffpic_phase_times", "ffpic_get_particles_range", "ffpic_batch_create",
+                 "ffpic_batch_view", "ffpic_batch_size", "ffpic_batch_step", "ffpic_batch_sync",
+                 "ffpic_batch_destroy", "ffpic_autotune", "ffpic_batch_autotune"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -124,16 +153,20 @@ def _ptr(x):
 class Sim:
     """One magnetosphere on the GPU (owns an ffpic_ctx)."""
 
-    def __init__(self, desc: Dict, capacity=None, stream: Optional[int] = None):
+    def __init__(self, desc: Dict, capacity=None, stream: Optional[int] = None, _view=None):
         L = lib()
         self.desc = dict(desc)
         self.nr, self.nth = int(desc["nr"]), int(desc["nth"])
-        self._d = make_desc(desc, capacity)
-        h = C.c_void_p()
-        rc = L.ffpic_create(C.byref(self._d), C.c_void_p(stream or 0), C.byref(h))
-        if rc != OK:
-            raise FfpicError(rc, "ffpic_create rejected the descriptor or failed to allocate")
-        self._h = h
+        self._view = _view is not None
+        if _view is not None:
+            self._h = _view
+        else:
+            self._d = make_desc(desc, capacity)
+            h = C.c_void_p()
+            rc = L.ffpic_create(C.byref(self._d), C.c_void_p(stream or 0), C.byref(h))
+            if rc != OK:
+                raise FfpicError(rc, "ffpic_create rejected the descriptor or failed to allocate")
+            self._h = h
         info = (C.c_double * 4)()
         L.ffpic_info(self._h, info)
         self.dt, self.dlog, self.dth, self.omega = list(info)
@@ -146,7 +179,8 @@ class Sim:
 
     def close(self):
         if getattr(self, "_h", None):
-            lib().ffpic_destroy(self._h)
+            if not self._view:       # views belong to their batch
+                lib().ffpic_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -208,6 +242,26 @@ class Sim:
         out["cell"] = cell
         return out
 
+    def particles_range(self, species: int, first: int, count: int) -> Dict[str, np.ndarray]:
+        """Slots [first, first + count) of a species (clipped to the slots)."""
+        n = C.c_int64(count)
+        out = {k: np.zeros(max(count, 0)) for k in ("r", "th", "ur", "uth", "uph")}
+        cell = np.zeros(max(count, 0), dtype=np.int32)
+        self._chk(lib().ffpic_get_particles_range(
+            self._h, species, first, C.byref(n),
+            *[C.c_void_p(out[k].ctypes.data) for k in ("r", "th", "ur", "uth", "uph")],
+            C.c_void_p(cell.ctypes.data)))
+        m = n.value
+        out = {k: v[:m].copy() for k, v in out.items()}
+        out["cell"] = cell[:m].copy()
+        return out
+
+    def autotune(self, budget_ms: float) -> Dict:
+        """Choose the sort interval by timing (state unchanged afterwards)."""
+        t = Tuning()
+        self._chk(lib().ffpic_autotune(self._h, float(budget_ms), C.byref(t)))
+        return t.as_dict()
+
     def sort_offsets(self, species: int) -> np.ndarray:
         out = np.zeros(self.nr * self.nth + 1, dtype=np.int32)
         self._chk(lib().ffpic_get_sort(self._h, species, C.c_void_p(out.ctypes.data)))
@@ -248,3 +302,58 @@ class Sim:
         out = (C.c_float * 4)()
         self._chk(lib().ffpic_phase_times(self._h, out))
         return list(out)
+
+
+class Batch:
+    """Independent magnetospheres stepped together (owns an ffpic_batch).
+    view(k) gives system k as a Sim that does not own its context."""
+
+    def __init__(self, descs, capacities, stream: Optional[int] = None):
+        L = lib()
+        n = len(descs)
+        arr = (Desc * n)(*[make_desc(d, c) for d, c in zip(descs, capacities)])
+        h = C.c_void_p()
+        rc = L.ffpic_batch_create(n, arr, C.c_void_p(stream or 0), C.byref(h))
+        if rc != OK:
+            raise FfpicError(rc, "ffpic_batch_create failed")
+        self._h = h
+        self.views = []
+        for k, d in enumerate(descs):
+            v = C.c_void_p()
+            self._chk(L.ffpic_batch_view(self._h, k, C.byref(v)))
+            self.views.append(Sim(d, _view=v))
+
+    def _chk(self, rc: int):
+        if rc != OK:
+            msg = lib().ffpic_batch_last_error(self._h)
+            raise FfpicError(rc, msg.decode() if msg else "")
+
+    def __len__(self):
+        return lib().ffpic_batch_size(self._h)
+
+    def view(self, k: int) -> Sim:
+        return self.views[k]
+
+    def step(self, n: int = 1):
+        self._chk(lib().ffpic_batch_step(self._h, int(n)))
+
+    def sync(self):
+        self._chk(lib().ffpic_batch_sync(self._h))
+
+    def autotune(self, budget_ms: float):
+        t = (Tuning * len(self.views))()
+        self._chk(lib().ffpic_batch_autotune(self._h, float(budget_ms), t))
+        return [x.as_dict() for x in t]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            for v in self.views:
+                v.close()
+            lib().ffpic_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

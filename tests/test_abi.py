@@ -44,19 +44,22 @@ def test_struct_layout_matches_header(tmp_path, lib):
 #include <stddef.h>
 #include "ffpic.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(ffpic_desc), sizeof(ffpic_diag),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(ffpic_desc), sizeof(ffpic_diag),
          offsetof(ffpic_desc, psi_thr), offsetof(ffpic_desc, capacity),
          offsetof(ffpic_desc, weight), offsetof(ffpic_diag, sum_u),
-         offsetof(ffpic_diag, gauss_max), offsetof(ffpic_diag, error_word));
+         offsetof(ffpic_diag, gauss_max), offsetof(ffpic_diag, error_word),
+         sizeof(ffpic_tuning), offsetof(ffpic_tuning, ms_per_step),
+         offsetof(ffpic_tuning, total_ms));
   return 0;
 }
 ''')
     exe = tmp_path / "layout"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)])
     got = [int(x) for x in subprocess.check_output([str(exe)]).split()]
-    D, G = ffpic.Desc, ffpic.Diag
+    D, G, T = ffpic.Desc, ffpic.Diag, ffpic.Tuning
     want = [ctypes.sizeof(D), ctypes.sizeof(G), D.psi_thr.offset, D.capacity.offset,
-            D.weight.offset, G.sum_u.offset, G.gauss_max.offset, G.error_word.offset]
+            D.weight.offset, G.sum_u.offset, G.gauss_max.offset, G.error_word.offset,
+            ctypes.sizeof(T), T.ms_per_step.offset, T.total_ms.offset]
     assert got == want
 
 
@@ -78,3 +81,16 @@ def test_null_and_invalid_arguments_fail_cleanly(lib):
     assert lib.ffpic_step(None, 1) == ffpic.EINVAL
     assert lib.ffpic_sync(None) == ffpic.EINVAL
     assert lib.ffpic_last_error(None) == b"no context"
+    # batch and autotune argument checks (no device call is reached)
+    b = ctypes.c_void_p()
+    good = ffpic.make_desc(d, [1, 1])
+    assert lib.ffpic_batch_create(0, ctypes.byref(good), None, ctypes.byref(b)) == ffpic.EINVAL
+    assert lib.ffpic_batch_create(1, None, None, ctypes.byref(b)) == ffpic.EINVAL
+    assert lib.ffpic_batch_step(None, 1) == ffpic.EINVAL
+    assert lib.ffpic_batch_sync(None) == ffpic.EINVAL
+    assert lib.ffpic_batch_view(None, 0, ctypes.byref(b)) == ffpic.EINVAL
+    assert lib.ffpic_batch_destroy(None) == ffpic.EINVAL
+    assert lib.ffpic_batch_size(None) == 0
+    assert lib.ffpic_autotune(None, 100.0, None) == ffpic.EINVAL
+    assert lib.ffpic_get_particles_range(None, 0, 0, None, None, None, None, None, None,
+                                         None) == ffpic.EINVAL

@@ -1,0 +1,149 @@
+"""Batched magnetospheres and the sort-interval autotuner, through the C ABI.
+
+* A batch step of several independent systems gives what each system gives
+  when stepped alone (FP64: 1e-12 relative; FP32-mixed: 1e-5, since only
+  the order of the FP32 atomic additions in the deposit differs), and the
+  FP64 systems match the oracle.
+* Views work as ordinary contexts and are not freed by ffpic_destroy.
+* Autotuning leaves the state bit-for-bit as it was, picks one of the timed
+  intervals, and a run with the tuned interval still matches the oracle
+  (the interval only reorders particles).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2406_14512_amd import ffpic
+from paper_2406_14512_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = [(ffpic.ER, oracle.ER), (ffpic.ETH, oracle.ETH), (ffpic.EPH, oracle.EPH),
+          (ffpic.BR, oracle.BR), (ffpic.BTH, oracle.BTH), (ffpic.BPH, oracle.BPH)]
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a - b)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    oracle.build(force=False)
+    ffpic.lib()
+
+
+def systems():
+    a = W.tiny_open_dipole(20000)
+    b = W.tiny_dipole(15000)
+    b.nr, b.nth = 96, 80
+    c = W.sheet_1024(n_total=60000, precision=W.FP32_MIXED)
+    c.nr = c.nth = 192
+    return [a, b, c]
+
+
+def descs(ws):
+    out = []
+    for w in ws:
+        d = w.desc()
+        d["precision"] = w.precision
+        out.append(d)
+    return out
+
+
+def test_batch_matches_single_contexts_and_oracle():
+    ws = systems()
+    ds = descs(ws)
+    caps = [[w.n_per_species] * w.nspec for w in ws]
+    batch = ffpic.Batch(ds, caps)
+    assert len(batch) == 3
+    singles = [ffpic.Sim(d, capacity=c) for d, c in zip(ds, caps)]
+    for w, v, s in zip(ws, batch.views, singles):
+        for sp in range(w.nspec):
+            p = w.particles(sp)
+            v.load_particles(sp, p)
+            s.load_particles(sp, p)
+    batch.step(4)
+    batch.step(2)
+    batch.sync()
+    for s in singles:
+        s.step(6)
+    for w, d, v, s in zip(ws, ds, batch.views, singles):
+        tol = 1e-12 if d["precision"] == W.FP64 else 1e-5
+        for g, _ in FIELDS:
+            assert rel(v.field(g), s.field(g)) < tol, (w.name, g)
+        dv, ds_ = v.diagnostics(ffpic.DIAG_MOMENTS), s.diagnostics(ffpic.DIAG_MOMENTS)
+        assert dv["alive"] == ds_["alive"]
+        assert dv["step"] == ds_["step"] == 6
+    # the FP64 systems against the oracle
+    for w, d, v in zip(ws, ds, batch.views):
+        if d["precision"] != W.FP64:
+            continue
+        ora = oracle.Oracle(d)
+        for sp in range(w.nspec):
+            ora.load(sp, w.particles(sp))
+        ora.step(6)
+        for g, o in FIELDS:
+            assert rel(v.field(g), ora.field(o)) < 1e-12, (w.name, g)
+    # a view survives ffpic_destroy and close()
+    ffpic.lib().ffpic_destroy(batch.views[0]._h)
+    assert batch.views[0].n(0) > 0
+    for s in singles:
+        s.close()
+    batch.close()
+
+
+def snapshot(sim, nspec):
+    f = [sim.field(g) for g, _ in FIELDS]
+    p = [sim.particles(s) for s in range(nspec)]
+    return f, p
+
+
+def test_autotune_keeps_state_and_semantics(tmp_path, monkeypatch):
+    cache = tmp_path / "tuning.txt"
+    monkeypatch.setenv("FFPIC_TUNING_CACHE", str(cache))
+    w = W.tiny_open_dipole(20000)
+    d = w.desc()
+    d["precision"] = W.FP64
+    d["sort_interval"] = 8
+    sim = ffpic.Sim(d, capacity=[w.n_per_species] * w.nspec)
+    for sp in range(w.nspec):
+        sim.load_particles(sp, w.particles(sp))
+    sim.step(3)
+    before = snapshot(sim, w.nspec)
+    t = sim.autotune(3000.0)
+    after = snapshot(sim, w.nspec)
+    for a, b in zip(before[0], after[0]):
+        assert np.array_equal(a, b)
+    for pa, pb in zip(before[1], after[1]):
+        for k in pa:
+            assert np.array_equal(pa[k], pb[k]), k
+    assert t["sort_interval"] in t["ms_per_step"]
+    assert 8 in t["ms_per_step"] and len(t["ms_per_step"]) >= 1
+    assert all(v > 0 for v in t["ms_per_step"].values())
+    line = cache.read_text().split()
+    assert line[:4] == [str(w.nr), str(w.nth), "0", str(w.nspec)]
+    assert int(line[5]) == t["sort_interval"]
+    # stepping on with the tuned interval matches the oracle (which sorts
+    # every step): the interval only reorders particles
+    sim.step(4)
+    ora = oracle.Oracle(d)
+    for sp in range(w.nspec):
+        ora.load(sp, w.particles(sp))
+    ora.step(7)
+    for g, o in FIELDS:
+        assert rel(sim.field(g), ora.field(o)) < 1e-12, g
+    # a descriptor asking for the tuned interval is accepted
+    d0 = dict(d, sort_interval=0)
+    s0 = ffpic.Sim(d0, capacity=[w.n_per_species] * w.nspec)
+    for sp in range(w.nspec):
+        s0.load_particles(sp, w.particles(sp))
+    s0.step(7)
+    for g, o in FIELDS:
+        assert rel(s0.field(g), ora.field(o)) < 1e-12, g
+    s0.close()
+    sim.close()
+    with pytest.raises(ffpic.FfpicError):
+        ffpic.Sim(d, capacity=[10, 10]).autotune(0.0)

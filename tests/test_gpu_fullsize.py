@@ -1,0 +1,213 @@
+"""Parity at the full size of the 4096^2 magnetosphere (4e8 particles), in
+the configuration the benchmark times.
+
+The oracle cannot step 4e8 particles in seconds, so the full-size state is
+checked piecewise against it:
+
+* flux function and mask: the oracle integrates Psi over the whole grid
+  from the GPU's B_r (bit-exact: same sequential FP64 sum);
+* push + deposit: after a sort, the particles of a band of 16 radial rows
+  of the current sheet are a contiguous slot range; the oracle pushes
+  exactly those particles in the GPU's fields, and the currents of the
+  band's interior rows (which no particle outside the band can reach in one
+  step) and every pushed particle are compared;
+* field step: the oracle takes the GPU's E, B and deposited currents and
+  runs its field step over the whole grid;
+* sort: offsets are monotone, the band's cells are non-decreasing, and the
+  live count equals the sum over cells.
+
+Tolerances.  The radial and polar currents are sums of charge fluxes
+Q * (offset change) whose signs differ from particle to particle, so their
+net can be far smaller than their terms; they are bounded per element by
+eps * Q * (particles within reach of the element), with eps the error of
+one particle's offset change in cell units:
+* FP64: the in-cell offsets come from a log (or a division) of nearly
+  equal numbers scaled by 1/dlog and 1/dtheta, good to a few ulps of those
+  scales: eps = 16 * 2^-52 * (1/dlog + 1/dtheta) (8e-12 cells at 4096^2).
+  Everything else (fields after the field step, J_phi, particle state):
+  1e-12 relative (L2 per component); Psi, f and cells bit-exact.
+* FP32-mixed: the new offset is rounded to FP32 (2^-24 of a cell) and the
+  move carries a few dozen FP32 roundings: eps = 32 * 2^-24 (2e-6 cells).
+  J_phi (all terms of one sign in the sheet) and the one-step particle
+  state within 2e-5 (logical coordinates in cells, momenta relative to
+  1 + |u|); Psi and f bit-exact (the oracle is fed the FP32 B_r).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2406_14512_amd import ffpic
+from paper_2406_14512_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32_TOL = 2e-5
+BAND_R = 15.0          # band of the sheet, in stellar radii
+BAND_ROWS = 16
+FIELDS = [(ffpic.ER, oracle.ER), (ffpic.ETH, oracle.ETH), (ffpic.EPH, oracle.EPH),
+          (ffpic.BR, oracle.BR), (ffpic.BTH, oracle.BTH), (ffpic.BPH, oracle.BPH)]
+CURRENTS = [(ffpic.JR, oracle.JR, "Jr"), (ffpic.JTH, oracle.JTH, "Jth"),
+            (ffpic.JPH, oracle.JPH, "Jph")]
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a - b)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    oracle.build(force=False)
+    ffpic.lib()
+
+
+def full_sim(precision):
+    w = W.sheet_4096()
+    d = w.desc()
+    d["precision"] = precision
+    sim = ffpic.Sim(d, capacity=[w.n_per_species] * w.nspec)
+    for s in range(w.nspec):
+        for c in range(w.n_chunks()):
+            sim.load_particles(s, w.chunk(s, c))
+    print(f"loaded {[sim.n(s) for s in range(w.nspec)]} particles", flush=True)
+    return w, d, sim
+
+
+def oracle_with_fields(d, sim):
+    """Oracle on the full grid holding the GPU's current E, B (and the same
+    initial B for the absorber)."""
+    ora = oracle.Oracle(d)
+    b0 = [ora.field(c) for c in (oracle.BR, oracle.BTH, oracle.BPH)]
+    for g, o in FIELDS:
+        ora.set_field(o, sim.field(g))
+    for k, c in enumerate((oracle.B0R, oracle.B0TH, oracle.B0PH)):
+        ora.set_field(c, b0[k])
+    return ora
+
+
+def band_slots(sim, s, i0, i1, nth):
+    off = sim.sort_offsets(s)
+    assert np.all(np.diff(off) >= 0)
+    return int(off[i0 * nth]), int(off[i1 * nth]), off
+
+
+def run_fullsize(precision):
+    w, d, sim = full_sim(precision)
+    nth = w.nth
+    sim.step(2)
+    sim.run_phases(ffpic.PHASE_MASK | ffpic.PHASE_SORT)
+    ora = oracle_with_fields(d, sim)
+    ora.phases(oracle.PHASE_MASK)
+
+    # flux function and mask over the whole grid
+    psi_g, psi_o = sim.field(ffpic.PSI), ora.field(oracle.PSI)
+    assert np.array_equal(psi_g, psi_o), np.max(np.abs(psi_g - psi_o))
+    assert np.array_equal(sim.field(ffpic.F), ora.field(oracle.F))
+
+    # band of rows around BAND_R in the sheet
+    dlog = np.log(w.rmax / w.rmin) / w.nr
+    i0 = int(np.log(BAND_R / w.rmin) / dlog)
+    i1 = i0 + BAND_ROWS
+    bands, before = [], []
+    for s in range(w.nspec):
+        a, b, off = band_slots(sim, s, i0, i1, nth)
+        assert off[-1] == sim.n(s)
+        p = sim.particles_range(s, a, b - a)
+        assert len(p["r"]) == b - a > 10000
+        assert np.all(np.diff(p["cell"]) >= 0)
+        assert p["cell"][0] >= i0 * nth and p["cell"][-1] < i1 * nth
+        bands.append((a, b))
+        before.append(p)
+        ora.load(s, p)
+        assert ora.n(s) == b - a
+    print(f"band rows [{i0}, {i1}): {[b - a for a, b in bands]} particles", flush=True)
+
+    sim.run_phases(ffpic.PHASE_PUSH)
+    ora.phases(oracle.PHASE_PUSH)
+    return w, d, sim, ora, (i0, i1), bands, before
+
+
+def reach_counts(w, before):
+    """Particles that can deposit into each element: band particles per
+    cell before the push, summed over the 4 x 4 cells around the element."""
+    nth = w.nth
+    cnt = np.zeros((w.nr + 1, nth + 1))
+    for p in before:
+        c = p["cell"]
+        np.add.at(cnt, (c // nth, c % nth), 1.0)
+    reach = np.zeros_like(cnt)
+    for di in range(-2, 2):
+        for dj in range(-2, 2):
+            reach += np.roll(np.roll(cnt, -di, axis=0), -dj, axis=1)
+    return np.maximum(reach, 1.0)
+
+
+def check_currents(sim, ora, d, w, rows, reach, eps, jph_tol):
+    Q = float(d["weight"][0])
+    for g, o, name in CURRENTS:
+        jg, jo = sim.field(g)[rows], ora.field(o)[rows]
+        worst = np.max(np.abs(jg - jo) / (eps * Q * reach[rows]))
+        print(f"{name} band: L2 rel {rel(jg, jo):.3e}, worst element / bound {worst:.3e}",
+              flush=True)
+        assert worst < 1.0, name
+        if name == "Jph":
+            assert rel(jg, jo) < jph_tol
+
+
+def logical(w, p):
+    dlog = np.log(w.rmax / w.rmin) / w.nr
+    return np.log(p["r"] / w.rmin) / dlog, p["th"] / (np.pi / w.nth)
+
+
+def test_fullsize_fp64():
+    w, d, sim, ora, (i0, i1), bands, before = run_fullsize(W.FP64)
+    rows = slice(i0 + 2, i1 - 2)   # rows only the band's particles reach
+    dlog = np.log(w.rmax / w.rmin) / w.nr
+    eps = 16.0 * 2.0 ** -52 * (1.0 / dlog + w.nth / np.pi)
+    check_currents(sim, ora, d, w, rows, reach_counts(w, before), eps, FP64_TOL)
+    for s, (a, b) in enumerate(bands):
+        pg = sim.particles_range(s, a, b - a)
+        po = ora.particles(s)
+        assert np.array_equal(pg["r"] > 0, po["r"] > 0)
+        live = po["r"] > 0
+        # cells agree except for a particle within rounding of a cell face
+        bad = live & (pg["cell"] != po["cell"])
+        if bad.any():
+            x, y = logical(w, {k: v[bad] for k, v in po.items()})
+            near = np.minimum(np.abs(x - np.round(x)), np.abs(y - np.round(y)))
+            assert np.all(near < 1e-9), near
+        for k in ("r", "th", "ur", "uth", "uph"):
+            e = rel(pg[k][live], po[k][live])
+            assert e < FP64_TOL, (s, k, e)
+
+    # field step over the whole grid from the GPU's deposited currents
+    for g, o, _ in CURRENTS:
+        ora.set_field(o, sim.field(g))
+    sim.run_phases(ffpic.PHASE_FIELDS)
+    ora.phases(oracle.PHASE_FIELDS)
+    for g, o in FIELDS:
+        e = rel(sim.field(g), ora.field(o))
+        assert e < FP64_TOL, (g, e)
+    sim.close()
+
+
+def test_fullsize_fp32_mixed():
+    w, d, sim, ora, (i0, i1), bands, before = run_fullsize(W.FP32_MIXED)
+    rows = slice(i0 + 2, i1 - 2)
+    check_currents(sim, ora, d, w, rows, reach_counts(w, before), 32.0 * 2.0 ** -24, FP32_TOL)
+    for s, (a, b) in enumerate(bands):
+        pg = sim.particles_range(s, a, b - a)
+        po = ora.particles(s)
+        assert np.array_equal(pg["r"] > 0, po["r"] > 0)
+        live = po["r"] > 0
+        xg, yg = logical(w, {k: v[live] for k, v in pg.items()})
+        xo, yo = logical(w, {k: v[live] for k, v in po.items()})
+        ex, ey = np.max(np.abs(xg - xo)), np.max(np.abs(yg - yo))
+        uo = np.stack([po[k][live] for k in ("ur", "uth", "uph")])
+        ug = np.stack([pg[k][live] for k in ("ur", "uth", "uph")])
+        eu = np.max(np.abs(ug - uo) / (1.0 + np.linalg.norm(uo, axis=0)))
+        print(f"species {s}: position error {ex:.2e}, {ey:.2e} cells; momentum {eu:.2e}",
+              flush=True)
+        assert ex < FP32_TOL and ey < FP32_TOL and eu < FP32_TOL
+    sim.close()
