@@ -75,6 +75,7 @@ struct ffpic_ctx {
     void *dE[3] = {}, *dB[3] = {}, *E0[3] = {}, *rE0[3] = {}, *rB0[3] = {}, *rho0 = nullptr;
     std::vector<double> hE0[3], hB0[3];       // FP64 background (host)
     void *scr[6] = {};                        // node scratch (J_FFE, E corrections)
+    int absorb_row0 = 0;                      // first grid row with damping below 1
     double *psi = nullptr;
     void *f = nullptr;
     uint8_t *kill = nullptr;
@@ -82,6 +83,20 @@ struct ffpic_ctx {
     uint32_t *keys[2] = {}, *vals[2] = {};
     void *sort_tmp = nullptr;
     size_t sort_tmp_bytes = 0;
+    // incremental re-sort: per species the sorted keys and cell offsets of
+    // the last sort (double-buffered), plus shared scratch
+    uint32_t *skey[FFPIC_MAX_SPECIES][2] = {};
+    int32_t *soff[FFPIC_MAX_SPECIES][2] = {};
+    int sort_cur[FFPIC_MAX_SPECIES] = {};
+    bool sort_valid[FFPIC_MAX_SPECIES] = {};
+    bool incremental_sort = true;
+    uint32_t *sort_sb = nullptr;              // stayers before each slot [cap + 1]
+    uint32_t *sort_blk = nullptr;             // block counts and their scans [4 * blocks]
+    uint32_t *sort_aux = nullptr;             // sorted mover slots [cap]
+    int32_t *sort_moff = nullptr;             // movers below each key [nr*nth + 1]
+    uint32_t *sort_tot = nullptr;             // stayers, movers
+    void *scan_tmp = nullptr;
+    size_t scan_tmp_bytes = 0;
     int64_t sort_cap = 0;
     int32_t *nslots = nullptr;                // device [FFPIC_MAX_SPECIES]
     int32_t *nalive = nullptr;                // device [FFPIC_MAX_SPECIES]
@@ -124,6 +139,8 @@ void poynting(ffpic_ctx *c, double *dev_L);
 void energies(ffpic_ctx *c, double *dev_out2);
 double max_abs(ffpic_ctx *c, const double *dev, size_t n);
 size_t sort_temp_bytes(int64_t cap, int bits);
+size_t scan_temp_bytes(int64_t nblk);
+int sort_block_slots();
 int sort_key_bits(const ffpic_ctx *c);
 void zero_counters(ffpic_ctx *c, int32_t *p, int n);
 int tuned_sort_interval(const ffpic_desc *d);

@@ -186,9 +186,8 @@ __global__ void k_jffe(Geo<R> g, const R *__restrict__ er, const R *__restrict__
 template <typename R>
 __global__ void k_ampere(Geo<R> g, R *__restrict__ er, R *__restrict__ et, R *__restrict__ ep,
                          const R *__restrict__ br, const R *__restrict__ bt,
-                         const R *__restrict__ bp, const R *__restrict__ jr,
-                         const R *__restrict__ jt, const R *__restrict__ jp,
-                         const R *__restrict__ f, const R *__restrict__ n0,
+                         const R *__restrict__ bp, R *__restrict__ jr_, R *__restrict__ jt_,
+                         R *__restrict__ jp_, const R *__restrict__ f, const R *__restrict__ n0,
                          const R *__restrict__ n1, const R *__restrict__ n2, int ff) {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
     int i = blockIdx.y;
@@ -197,6 +196,11 @@ __global__ void k_ampere(Geo<R> g, R *__restrict__ er, R *__restrict__ et, R *__
     const R fourpi = (R)(4.0 * kPi);
     const R dt = g.dt;
     size_t k = ix(ld, i, j);
+    // the deposit accumulators are consumed here and cleared for the next push
+    const R jrk = jr_[k], jtk = jt_[k], jpk = jp_[k];
+    jr_[k] = (R)0;
+    jt_[k] = (R)0;
+    jp_[k] = (R)0;
     if (i < nr) {
         R A = g.rh2[i] * g.dcd[j];
         R circ = (j < nth ? g.rh[i] * g.sh[j] * bp[k] : (R)0) -
@@ -204,9 +208,9 @@ __global__ void k_ampere(Geo<R> g, R *__restrict__ er, R *__restrict__ et, R *__
         R J;
         if (ff) {
             R fs = (R)0.5 * (f[k] + f[k + ld]);
-            J = ((R)1 - fs) * jr[k] / (dt * A) + fs * (R)0.5 * (n0[k] + n0[k + ld]);
+            J = ((R)1 - fs) * jrk / (dt * A) + fs * (R)0.5 * (n0[k] + n0[k + ld]);
         } else {
-            J = jr[k] / (dt * A);
+            J = jrk / (dt * A);
         }
         er[k] += dt * circ / A - fourpi * dt * J;
     }
@@ -217,9 +221,9 @@ __global__ void k_ampere(Geo<R> g, R *__restrict__ er, R *__restrict__ et, R *__
             R J;
             if (ff) {
                 R fs = (R)0.5 * (f[k] + f[k + 1]);
-                J = ((R)1 - fs) * jt[k] / (dt * A) + fs * (R)0.5 * (n1[k] + n1[k + 1]);
+                J = ((R)1 - fs) * jtk / (dt * A) + fs * (R)0.5 * (n1[k] + n1[k + 1]);
             } else {
-                J = jt[k] / (dt * A);
+                J = jtk / (dt * A);
             }
             et[k] += dt * circ / A - fourpi * dt * J;
         }
@@ -230,9 +234,9 @@ __global__ void k_ampere(Geo<R> g, R *__restrict__ er, R *__restrict__ et, R *__
             R J;
             if (ff) {
                 R fs = f[k];
-                J = ((R)1 - fs) * jp[k] / (g.dr3h[i] * g.dcd[j]) + fs * n2[k];
+                J = ((R)1 - fs) * jpk / (g.dr3h[i] * g.dcd[j]) + fs * n2[k];
             } else {
-                J = jp[k] / (g.dr3h[i] * g.dcd[j]);
+                J = jpk / (g.dr3h[i] * g.dcd[j]);
             }
             ep[k] += dt * circ / A - fourpi * dt * J;
         }
@@ -301,20 +305,18 @@ __global__ void k_ffapply(Geo<R> g, R *__restrict__ er, R *__restrict__ et, R *_
 
 // absorbing layer beyond r_abs (damp E, relax B to its initial value) and
 // zeroing of the deposit accumulators for the next step
+// absorbing layer (rows from i0 on, where the damping factor is below 1):
+// E is damped, B relaxes to its initial value
 template <typename R>
-__global__ void k_absorb_zero(Geo<R> g, R *__restrict__ er, R *__restrict__ et,
-                              R *__restrict__ ep, R *__restrict__ br, R *__restrict__ bt,
-                              R *__restrict__ bp, const R *__restrict__ b0r,
-                              const R *__restrict__ b0t, const R *__restrict__ b0p,
-                              R *__restrict__ jr, R *__restrict__ jt, R *__restrict__ jp) {
+__global__ void k_absorb(Geo<R> g, int i0, R *__restrict__ er, R *__restrict__ et,
+                         R *__restrict__ ep, R *__restrict__ br, R *__restrict__ bt,
+                         R *__restrict__ bp, const R *__restrict__ b0r, const R *__restrict__ b0t,
+                         const R *__restrict__ b0p) {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
-    int i = blockIdx.y;
+    int i = i0 + blockIdx.y;
     const int nr = g.nr, nth = g.nth, ld = g.ld;
     if (j > nth) return;
     size_t k = ix(ld, i, j);
-    jr[k] = (R)0;
-    jt[k] = (R)0;
-    jp[k] = (R)0;
     R ln = g.lamn[i];
     R lh = i < nr ? g.lamh[i] : (R)1;
     if (ln == (R)1 && lh == (R)1) return;
@@ -357,8 +359,10 @@ static void run_field_step(ffpic_ctx *c) {
     }
     hipLaunchKernelGGL(k_faraday<R>, grd, blk, 0, c->stream, g, E[0], E[1], E[2], B[0], B[1],
                        B[2], h);
-    hipLaunchKernelGGL(k_absorb_zero<R>, grd, blk, 0, c->stream, g, E[0], E[1], E[2], B[0],
-                       B[1], B[2], B0[0], B0[1], B0[2], J[0], J[1], J[2]);
+    if (c->absorb_row0 <= c->nr)
+        hipLaunchKernelGGL(k_absorb<R>, dim3(grd.x, c->nr + 1 - c->absorb_row0), blk, 0,
+                           c->stream, g, c->absorb_row0, E[0], E[1], E[2], B[0], B[1], B[2],
+                           B0[0], B0[1], B0[2]);
     FFPIC_LAUNCH_CHECK();
 }
 

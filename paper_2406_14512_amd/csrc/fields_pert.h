@@ -90,8 +90,8 @@ __global__ void k_jffe_p(Geo<float> g, PertArrays P, const float *__restrict__ e
 
 __global__ void k_ampere_p(Geo<float> g, PertArrays P, float *__restrict__ er,
                            float *__restrict__ et, float *__restrict__ ep,
-                           const float *__restrict__ jr, const float *__restrict__ jt,
-                           const float *__restrict__ jp, const float *__restrict__ f,
+                           float *__restrict__ jr_, float *__restrict__ jt_,
+                           float *__restrict__ jp_, const float *__restrict__ f,
                            const float *__restrict__ n0, const float *__restrict__ n1,
                            const float *__restrict__ n2, int ff) {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -101,12 +101,17 @@ __global__ void k_ampere_p(Geo<float> g, PertArrays P, float *__restrict__ er,
     const float fourpi = (float)(4.0 * kPi);
     const float dt = g.dt;
     size_t k = ix(ld, i, j);
+    // the deposit accumulators are consumed here and cleared for the next push
+    const float jrk = jr_[k], jtk = jt_[k], jpk = jp_[k];
+    jr_[k] = 0.f;
+    jt_[k] = 0.f;
+    jp_[k] = 0.f;
     const float *br = P.dB[0], *bt = P.dB[1], *bp = P.dB[2];
     if (i < nr) {
         float A = g.rh2[i] * g.dcd[j];
         float circ = (j < nth ? g.rh[i] * g.sh[j] * bp[k] : 0.f) -
                      (j > 0 ? g.rh[i] * g.sh[j - 1] * bp[k - 1] : 0.f);
-        float J = jr[k] / (dt * A);
+        float J = jrk / (dt * A);
         if (ff) {
             float fs = 0.5f * (f[k] + f[k + ld]);
             if (fs > 0.f) J = (1.f - fs) * J + fs * 0.5f * (n0[k] + n0[k + ld]);
@@ -119,7 +124,7 @@ __global__ void k_ampere_p(Geo<float> g, PertArrays P, float *__restrict__ er,
         if (j < nth) {
             float A = g.sh[j] * g.dr2h[i];
             float circ = -(g.rh[i] * g.sh[j] * bp[k] - g.rh[i - 1] * g.sh[j] * bp[k - ld]);
-            float J = jt[k] / (dt * A);
+            float J = jtk / (dt * A);
             if (ff) {
                 float fs = 0.5f * (f[k] + f[k + 1]);
                 if (fs > 0.f) J = (1.f - fs) * J + fs * 0.5f * (n1[k] + n1[k + 1]);
@@ -132,7 +137,7 @@ __global__ void k_ampere_p(Geo<float> g, PertArrays P, float *__restrict__ er,
             float A = g.dthd[j] * g.dr2h[i];
             float circ = g.dth * (g.rh[i] * bt[k] - g.rh[i - 1] * bt[k - ld]) -
                          g.drh[i] * (br[k] - br[k - 1]);
-            float J = jp[k] / (g.dr3h[i] * g.dcd[j]);
+            float J = jpk / (g.dr3h[i] * g.dcd[j]);
             if (ff) {
                 float fs = f[k];
                 if (fs > 0.f) J = (1.f - fs) * J + fs * n2[k];
@@ -172,19 +177,15 @@ __global__ void k_ffapply_p(Geo<float> g, PertArrays P, float *__restrict__ er,
     }
 }
 
-__global__ void k_absorb_zero_p(Geo<float> g, PertArrays P, float *__restrict__ er,
-                                float *__restrict__ et, float *__restrict__ ep,
-                                float *__restrict__ br, float *__restrict__ bt,
-                                float *__restrict__ bp, float *__restrict__ jr,
-                                float *__restrict__ jt, float *__restrict__ jp) {
+// absorbing layer in perturbation form (rows from i0 on)
+__global__ void k_absorb_p(Geo<float> g, int i0, PertArrays P, float *__restrict__ er,
+                           float *__restrict__ et, float *__restrict__ ep, float *__restrict__ br,
+                           float *__restrict__ bt, float *__restrict__ bp) {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
-    int i = blockIdx.y;
+    int i = i0 + blockIdx.y;
     const int nr = g.nr, nth = g.nth, ld = g.ld;
     if (j > nth) return;
     size_t k = ix(ld, i, j);
-    jr[k] = 0.f;
-    jt[k] = 0.f;
-    jp[k] = 0.f;
     float ln = g.lamn[i];
     float lh = i < nr ? g.lamh[i] : 1.f;
     if (ln == 1.f && lh == 1.f) return;
@@ -241,8 +242,9 @@ static void run_field_step_pert(ffpic_ctx *c) {
                            S[4], S[5]);
     }
     hipLaunchKernelGGL(k_faraday_p, grd, blk, 0, c->stream, g, P, B[0], B[1], B[2], h);
-    hipLaunchKernelGGL(k_absorb_zero_p, grd, blk, 0, c->stream, g, P, E[0], E[1], E[2], B[0],
-                       B[1], B[2], J[0], J[1], J[2]);
+    if (c->absorb_row0 <= c->nr)
+        hipLaunchKernelGGL(k_absorb_p, dim3(grd.x, c->nr + 1 - c->absorb_row0), blk, 0,
+                           c->stream, g, c->absorb_row0, P, E[0], E[1], E[2], B[0], B[1], B[2]);
     FFPIC_LAUNCH_CHECK();
 }
 

@@ -142,11 +142,14 @@ __device__ __forceinline__ void push_chunk(const P32 &p, const Fields &F, const 
             S.stc(q, -1);
             nkill++;
         }
+        // The deposit values below are assigned for every kept particle and
+        // read only under `simple` / `cross`, which imply that assignment, so
+        // they carry no initial value (no register setup on the other paths).
         bool simple = false;       // stays in its cell: 8 adds at fixed offsets
-        float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f, s5 = 0.f, s6 = 0.f, s7 = 0.f;
+        float s0, s1, s2, s3, s4, s5, s6, s7;
         bool cross = false;        // leaves its cell: general zigzag
-        int di = 0, dj = 0;
-        float x1 = 0.f, y1 = 0.f, x2 = 0.f, y2 = 0.f, qv = 0.f;
+        int di, dj;
+        float x1, y1, x2, y2, qv;
         if (live) {
             const float a = State::ld(S.a, q), b = State::ld(S.b, q);
             const float ur = State::ld(S.ur, q), ut = State::ld(S.ut, q), up = State::ld(S.up, q);

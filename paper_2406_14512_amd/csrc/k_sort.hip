@@ -12,12 +12,41 @@
 // 3. the live count is the position of the first dead key in the sorted
 //    keys (binary search), so no pass of the sort contends on a counter.
 // 4. gather pass: the SoA state is permuted into the second buffer.
+//
+// Between two sorts most particles stay in their cell (a step moves a
+// particle by a fraction of a cell), so after the first sort the array is
+// re-sorted incrementally (sort_species_incremental):
+//   * a particle is a "stayer" if its key equals the key its slot had at the
+//     last sort, else a "mover" (dead slots and killed particles drop out);
+//     stayers are already in (key, slot) order;
+//   * a block scan gives SB[q] = stayers before slot q and compacts the
+//     movers (key, slot) in slot order; only the movers are radix sorted;
+//   * every particle's place in the stable order by (key, slot) follows
+//     from counts: a stayer at q with key k goes to
+//       SB[q] + (movers with key < k) + (movers with key k and slot < q),
+//     the mover of rank j (key k, slot q) goes to
+//       j + SB[clamp(q, OFF[k], OFF[k+1])],
+//     with OFF the cell offsets of the last sort (stayers with key < k sit
+//     before OFF[k], those with key k inside [OFF[k], OFF[k+1]));
+//   * one scatter pass writes the state, the sorted keys and (from the same
+//     counts) the new cell offsets, which the next sort compares against.
+// The result is the same stable order as a full sort of the keys.
+#include <algorithm>
 #include <cstring>
 #include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
 
 #include "device_common.h"
 
 namespace ffpic {
+
+constexpr int kSortBlock = 1024;          // slots per classify / compact block
+
+#define HCHK_SORT(x)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (x);                                                            \
+        if (e_ != hipSuccess) throw std::runtime_error(hipGetErrorString(e_));          \
+    } while (0)
 
 __global__ void k_key64(int nub, const int32_t *__restrict__ nslots, int nr, int nth, double rmin,
                         double dlog, double dth, const double *__restrict__ rn,
@@ -44,7 +73,7 @@ __global__ void k_key64(int nub, const int32_t *__restrict__ nslots, int nr, int
         }
     }
     keys[q] = key;
-    vals[q] = (uint32_t)q;
+    if (vals) vals[q] = (uint32_t)q;
     count_wave(&removed[1], killed);
 }
 
@@ -69,7 +98,7 @@ __global__ void k_key32(int nub, const int32_t *__restrict__ nslots, int nth,
         }
     }
     keys[q] = key;
-    vals[q] = (uint32_t)q;
+    if (vals) vals[q] = (uint32_t)q;
     count_wave(&removed[1], killed);
 }
 
@@ -143,17 +172,38 @@ int sort_key_bits(const ffpic_ctx *c) {
     return bits;
 }
 
-size_t sort_temp_bytes(int64_t cap, int bits) {
+size_t scan_temp_bytes(int64_t nblk) {
     size_t bytes = 0;
-    if (cap <= 0) return 0;
-    hipError_t e = rocprim::radix_sort_pairs((void *)nullptr, bytes, (uint32_t *)nullptr,
-                                             (uint32_t *)nullptr, (uint32_t *)nullptr,
-                                             (uint32_t *)nullptr, (unsigned int)cap, 0, bits);
-    if (e != hipSuccess) throw std::runtime_error("rocprim temp size query failed");
+    if (nblk <= 0) return 0;
+    hipError_t e = rocprim::exclusive_scan((void *)nullptr, bytes, (uint32_t *)nullptr,
+                                           (uint32_t *)nullptr, 0u, (size_t)nblk,
+                                           rocprim::plus<uint32_t>());
+    if (e != hipSuccess) throw std::runtime_error("rocprim scan size query failed");
     return bytes;
 }
 
-static void key_pass(ffpic_ctx *c, int s, uint32_t dead) {
+int sort_block_slots() { return kSortBlock; }
+
+// temporary storage for sorting any number of pairs up to cap: rocPRIM
+// switches algorithm with the size (merge sort below about 2^20 items), so
+// the largest requirement over the switch points is taken
+size_t sort_temp_bytes(int64_t cap, int bits) {
+    if (cap <= 0) return 0;
+    size_t most = 0;
+    const int64_t sizes[] = {cap, std::min<int64_t>(cap, (1 << 20) - 1),
+                             std::min<int64_t>(cap, (1 << 20) + 1)};
+    for (int64_t n : sizes) {
+        size_t bytes = 0;
+        hipError_t e = rocprim::radix_sort_pairs((void *)nullptr, bytes, (uint32_t *)nullptr,
+                                                 (uint32_t *)nullptr, (uint32_t *)nullptr,
+                                                 (uint32_t *)nullptr, (unsigned int)n, 0, bits);
+        if (e != hipSuccess) throw std::runtime_error("rocprim temp size query failed");
+        most = std::max(most, bytes);
+    }
+    return most;
+}
+
+static void key_pass(ffpic_ctx *c, int s, uint32_t dead, bool with_vals = true) {
     ffpic::Species &S = c->sp[s];
     int nub = (int)S.nub;
     int nb = (nub + 255) / 256;
@@ -161,43 +211,13 @@ static void key_pass(ffpic_ctx *c, int s, uint32_t dead) {
         hipLaunchKernelGGL(k_key64, dim3(nb), dim3(256), 0, c->stream, nub, c->nslots + s, c->nr,
                            c->nth, c->d.rmin, c->dlog, c->dth, c->dtab64[T_RN], c->dtab64[T_THN],
                            c->kill, dead, (double *)S.cur[0], (const double *)S.cur[1],
-                           c->keys[0], c->vals[0], c->removed + 4 * s);
+                           c->keys[0], with_vals ? c->vals[0] : nullptr, c->removed + 4 * s);
     } else {
         hipLaunchKernelGGL(k_key32, dim3(nb), dim3(256), 0, c->stream, nub, c->nslots + s, c->nth,
-                           c->kill, dead, (int32_t *)S.cur[0], c->keys[0], c->vals[0],
-                           c->removed + 4 * s);
+                           c->kill, dead, (int32_t *)S.cur[0], c->keys[0],
+                           with_vals ? c->vals[0] : nullptr, c->removed + 4 * s);
     }
     FFPIC_LAUNCH_CHECK();
-}
-
-void sort_species(ffpic_ctx *c, int s) {
-    ffpic::Species &S = c->sp[s];
-    int nub = (int)S.nub;
-    if (nub == 0) return;
-    uint32_t dead = dead_key(c);
-    key_pass(c, s, dead);
-    size_t bytes = c->sort_tmp_bytes;
-    hipError_t e = rocprim::radix_sort_pairs(c->sort_tmp, bytes, c->keys[0], c->keys[1],
-                                             c->vals[0], c->vals[1], (unsigned int)nub, 0,
-                                             sort_key_bits(c), c->stream);
-    if (e != hipSuccess) throw std::runtime_error("rocprim radix sort failed");
-    int32_t *nal = c->nalive + s;
-    hipLaunchKernelGGL(k_count_sorted, dim3(1), dim3(1), 0, c->stream, nub, c->keys[1], dead, nal,
-                       c->nslots + s);
-    int nb = std::min((nub + 255) / 256, 65536);
-    if (c->fp64) {
-        PtrSet<uint64_t, 5> P;
-        for (int a = 0; a < 5; a++) { P.src[a] = (const uint64_t *)S.cur[a]; P.dst[a] = (uint64_t *)S.alt[a]; }
-        hipLaunchKernelGGL((k_gather_set<uint64_t, 5>), dim3(nb), dim3(256), 0, c->stream, nub,
-                           nal, c->vals[1], P);
-    } else {
-        PtrSet<uint32_t, 6> P;
-        for (int a = 0; a < 6; a++) { P.src[a] = (const uint32_t *)S.cur[a]; P.dst[a] = (uint32_t *)S.alt[a]; }
-        hipLaunchKernelGGL((k_gather_set<uint32_t, 6>), dim3(nb), dim3(256), 0, c->stream, nub,
-                           nal, c->vals[1], P);
-    }
-    FFPIC_LAUNCH_CHECK();
-    for (int a = 0; a < S.narr; a++) std::swap(S.cur[a], S.alt[a]);
 }
 
 // removal of particles in force-free cells without reordering
@@ -245,6 +265,288 @@ void sort_offsets(ffpic_ctx *c, int s, int32_t *dev_off) {
     hipLaunchKernelGGL(k_offsets, dim3((nkeys + 1 + 255) / 256), dim3(256), 0, c->stream, nal,
                        c->keys[0], nkeys, dev_off);
     FFPIC_LAUNCH_CHECK();
+}
+
+
+// ---------------------------------------------------------------------------
+// incremental re-sort
+
+
+// stayer / mover class of a slot from its new key and the key it had at the
+// last sort (kold is sorted, so stayers are in order)
+__device__ __forceinline__ int slot_class(uint32_t key, uint32_t dead, int q, int nold,
+                                          const uint32_t *__restrict__ kold) {
+    if (key >= dead) return 0;                          // dropped
+    return (q < nold && kold[q] == key) ? 1 : 2;        // 1 stayer, 2 mover
+}
+
+// per-block counts of stayers and movers (keys already written by the key
+// pass); 256 threads, kSortBlock slots per block
+__global__ void __launch_bounds__(256) k_class_count(int nub, const uint32_t *__restrict__ keys,
+                                                     uint32_t dead, const int32_t *__restrict__ nold,
+                                                     const uint32_t *__restrict__ kold,
+                                                     uint32_t *__restrict__ bst,
+                                                     uint32_t *__restrict__ bmv) {
+    __shared__ uint32_t part[2][4];
+    const int tid = threadIdx.x, w = tid >> 6;
+    const int no = nold[0];
+    uint32_t st = 0, mv = 0;
+    for (int k = 0; k < kSortBlock / 256; k++) {
+        const int q = blockIdx.x * kSortBlock + k * 256 + tid;
+        const int cl = q < nub ? slot_class(keys[q], dead, q, no, kold) : 0;
+        st += __popcll(__ballot(cl == 1));
+        mv += __popcll(__ballot(cl == 2));
+    }
+    if ((tid & 63) == 0) { part[0][w] = st; part[1][w] = mv; }
+    __syncthreads();
+    if (tid == 0) {
+        bst[blockIdx.x] = part[0][0] + part[0][1] + part[0][2] + part[0][3];
+        bmv[blockIdx.x] = part[1][0] + part[1][1] + part[1][2] + part[1][3];
+    }
+}
+
+// SB[q] for every slot (stayers before q), the movers compacted in slot
+// order, and the totals (SB[nub] = stayers, tot[0] = stayers, tot[1] =
+// movers) from the exclusive block scans
+__global__ void __launch_bounds__(256) k_class_compact(
+    int nub, int nblk, const uint32_t *__restrict__ keys, uint32_t dead,
+    const int32_t *__restrict__ nold, const uint32_t *__restrict__ kold,
+    const uint32_t *__restrict__ bst, const uint32_t *__restrict__ bmv,
+    const uint32_t *__restrict__ cst, const uint32_t *__restrict__ cmv, uint32_t *__restrict__ sb,
+    uint32_t *__restrict__ mkey, uint32_t *__restrict__ mval, uint32_t *__restrict__ tot) {
+    __shared__ uint32_t part[2][4];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int no = nold[0];
+    uint32_t st0 = cst[blockIdx.x], mv0 = cmv[blockIdx.x];
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int k = 0; k < kSortBlock / 256; k++) {
+        const int q = blockIdx.x * kSortBlock + k * 256 + tid;
+        const uint32_t key = q < nub ? keys[q] : dead;
+        const int cl = q < nub ? slot_class(key, dead, q, no, kold) : 0;
+        const unsigned long long ms = __ballot(cl == 1), mm = __ballot(cl == 2);
+        if (lane == 0) { part[0][w] = __popcll(ms); part[1][w] = __popcll(mm); }
+        __syncthreads();
+        uint32_t os = st0, om = mv0;
+        for (int u = 0; u < w; u++) { os += part[0][u]; om += part[1][u]; }
+        os += __popcll(ms & below);
+        om += __popcll(mm & below);
+        if (q < nub) sb[q] = os;
+        if (cl == 2) { mkey[om] = key; mval[om] = (uint32_t)q; }
+        st0 += part[0][0] + part[0][1] + part[0][2] + part[0][3];
+        mv0 += part[1][0] + part[1][1] + part[1][2] + part[1][3];
+        __syncthreads();
+    }
+    if (blockIdx.x == nblk - 1 && tid == 0) {
+        sb[nub] = st0;
+        tot[0] = st0;
+        tot[1] = mv0;
+    }
+}
+
+// moff[k] = movers with key < k (binary search in the sorted mover keys)
+__global__ void k_mover_offsets(const uint32_t *__restrict__ tot, const uint32_t *__restrict__ mkey,
+                                int nkeys, int32_t *__restrict__ moff) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > nkeys) return;
+    int lo = 0, hi = (int)tot[1];
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((int)mkey[mid] < k) lo = mid + 1; else hi = mid;
+    }
+    moff[k] = lo;
+}
+
+// stayers: slot q with key k goes to SB[q] + moff[k] + (movers of key k
+// from a slot below q)
+template <typename T, int NA>
+__global__ void k_scatter_stay(int nub, const uint32_t *__restrict__ keys, uint32_t dead,
+                               const int32_t *__restrict__ nold, const uint32_t *__restrict__ kold,
+                               const uint32_t *__restrict__ sb, const int32_t *__restrict__ moff,
+                               const uint32_t *__restrict__ mval, uint32_t *__restrict__ knew,
+                               PtrSet<T, NA> P) {
+    const int no = nold[0];
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nub; q += gridDim.x * blockDim.x) {
+        const uint32_t key = keys[q];
+        if (slot_class(key, dead, q, no, kold) != 1) continue;
+        int lo = moff[key];
+        int hi = moff[key + 1];
+        while (lo < hi) {                 // movers of this key are in slot order
+            const int mid = (lo + hi) >> 1;
+            if ((int)mval[mid] < q) lo = mid + 1; else hi = mid;
+        }
+        const uint32_t d = sb[q] + (uint32_t)lo;
+#pragma unroll
+        for (int a = 0; a < NA; a++) P.dst[a][d] = P.src[a][q];
+        knew[d] = key;
+    }
+}
+
+// movers: rank j (key k, slot q) goes to j + SB[clamp(q, OFF[k], OFF[k+1])]
+template <typename T, int NA>
+__global__ void k_scatter_move(const uint32_t *__restrict__ tot, const uint32_t *__restrict__ mkey,
+                               const uint32_t *__restrict__ mval, const uint32_t *__restrict__ sb,
+                               const int32_t *__restrict__ offold, uint32_t *__restrict__ knew,
+                               PtrSet<T, NA> P) {
+    const int m = (int)tot[1];
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < m; j += gridDim.x * blockDim.x) {
+        const uint32_t key = mkey[j];
+        const int q = (int)mval[j];
+        const int lo = offold[key], hi = offold[key + 1];
+        const int c = q < lo ? lo : (q > hi ? hi : q);
+        const uint32_t d = (uint32_t)j + sb[c];
+#pragma unroll
+        for (int a = 0; a < NA; a++) P.dst[a][d] = P.src[a][q];
+        knew[d] = key;
+    }
+}
+
+// offsets of the new order: stayers with key < k (= SB at the old offset)
+// plus movers with key < k; the last entry is the live count
+__global__ void k_new_offsets(int nkeys, const int32_t *__restrict__ offold,
+                              const uint32_t *__restrict__ sb, const int32_t *__restrict__ moff,
+                              int32_t *__restrict__ offnew, int32_t *__restrict__ nalive,
+                              int32_t *__restrict__ nslots) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > nkeys) return;
+    const int v = (int)sb[offold[k]] + moff[k];
+    offnew[k] = v;
+    if (k == nkeys) {
+        nalive[0] = v;
+        nslots[0] = v;
+    }
+}
+
+// offsets of a sorted key array (after a full sort): off[k] = first slot
+// with key >= k among the live ones
+__global__ void k_offsets_dev(const int32_t *__restrict__ nalive, const uint32_t *__restrict__ keys,
+                              int nkeys, int32_t *__restrict__ off) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > nkeys) return;
+    int lo = 0, hi = nalive[0];
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((int)keys[mid] < k) lo = mid + 1; else hi = mid;
+    }
+    off[k] = lo;
+}
+
+template <typename T, int NA>
+static PtrSet<T, NA> state_ptrs(ffpic::Species &S) {
+    PtrSet<T, NA> P;
+    for (int a = 0; a < NA; a++) {
+        P.src[a] = (const T *)S.cur[a];
+        P.dst[a] = (T *)S.alt[a];
+    }
+    return P;
+}
+
+// full sort: key pass, radix sort of all (key, slot) pairs, gather; then the
+// sorted keys and cell offsets are kept for the next (incremental) sort
+static void sort_full(ffpic_ctx *c, int s) {
+    ffpic::Species &S = c->sp[s];
+    int nub = (int)S.nub;
+    uint32_t dead = dead_key(c);
+    key_pass(c, s, dead);
+    size_t bytes = c->sort_tmp_bytes;
+    hipError_t e = rocprim::radix_sort_pairs(c->sort_tmp, bytes, c->keys[0], c->keys[1],
+                                             c->vals[0], c->vals[1], (unsigned int)nub, 0,
+                                             sort_key_bits(c), c->stream);
+    if (e != hipSuccess) throw std::runtime_error("rocprim radix sort failed");
+    int32_t *nal = c->nalive + s;
+    hipLaunchKernelGGL(k_count_sorted, dim3(1), dim3(1), 0, c->stream, nub, c->keys[1], dead, nal,
+                       c->nslots + s);
+    int nb = std::min((nub + 255) / 256, 65536);
+    if (c->fp64) {
+        hipLaunchKernelGGL((k_gather_set<uint64_t, 5>), dim3(nb), dim3(256), 0, c->stream, nub,
+                           nal, c->vals[1], (state_ptrs<uint64_t, 5>(S)));
+    } else {
+        hipLaunchKernelGGL((k_gather_set<uint32_t, 6>), dim3(nb), dim3(256), 0, c->stream, nub,
+                           nal, c->vals[1], (state_ptrs<uint32_t, 6>(S)));
+    }
+    FFPIC_LAUNCH_CHECK();
+    for (int a = 0; a < S.narr; a++) std::swap(S.cur[a], S.alt[a]);
+    // the sorted keys and their cell offsets, for the next sort
+    const int t = c->sort_cur[s];
+    HCHK_SORT(hipMemcpyAsync(c->skey[s][t], c->keys[1], (size_t)nub * 4, hipMemcpyDeviceToDevice,
+                             c->stream));
+    const int nkeys = c->nr * c->nth;
+    hipLaunchKernelGGL(k_offsets_dev, dim3((nkeys + 1 + 255) / 256), dim3(256), 0, c->stream, nal,
+                       c->skey[s][t], nkeys, c->soff[s][t]);
+    FFPIC_LAUNCH_CHECK();
+    c->sort_valid[s] = true;
+}
+
+// incremental sort (see the header comment); requires the keys and offsets
+// of the previous sort of this species
+static void sort_incremental(ffpic_ctx *c, int s) {
+    ffpic::Species &S = c->sp[s];
+    const int nub = (int)S.nub;
+    const uint32_t dead = dead_key(c);
+    const int nkeys = c->nr * c->nth;
+    const int t = c->sort_cur[s];
+    const uint32_t *kold = c->skey[s][t];
+    const int32_t *offold = c->soff[s][t];
+    const int32_t *nold = c->nslots + s;   // live count of the last sort
+    key_pass(c, s, dead, false);
+    const int nblk = (nub + kSortBlock - 1) / kSortBlock;
+    uint32_t *bst = c->sort_blk, *bmv = bst + nblk, *cst = bmv + nblk, *cmv = cst + nblk;
+    hipLaunchKernelGGL(k_class_count, dim3(nblk), dim3(256), 0, c->stream, nub, c->keys[0], dead,
+                       nold, kold, bst, bmv);
+    FFPIC_LAUNCH_CHECK();
+    size_t bytes = c->scan_tmp_bytes;
+    if (rocprim::exclusive_scan(c->scan_tmp, bytes, bst, cst, 0u, (size_t)nblk,
+                                rocprim::plus<uint32_t>(), c->stream) != hipSuccess ||
+        rocprim::exclusive_scan(c->scan_tmp, bytes, bmv, cmv, 0u, (size_t)nblk,
+                                rocprim::plus<uint32_t>(), c->stream) != hipSuccess)
+        throw std::runtime_error("rocprim scan failed");
+    uint32_t *mkey = c->keys[1], *mval = c->vals[0];
+    hipLaunchKernelGGL(k_class_compact, dim3(nblk), dim3(256), 0, c->stream, nub, nblk, c->keys[0],
+                       dead, nold, kold, bst, bmv, cst, cmv, c->sort_sb, mkey, mval, c->sort_tot);
+    FFPIC_LAUNCH_CHECK();
+    uint32_t tot[2] = {0, 0};
+    HCHK_SORT(hipMemcpyAsync(tot, c->sort_tot, sizeof(tot), hipMemcpyDeviceToHost, c->stream));
+    HCHK_SORT(hipStreamSynchronize(c->stream));
+    const uint32_t m = tot[1];
+    uint32_t *mkey2 = c->vals[1], *mval2 = c->sort_aux;
+    if (m > 0) {
+        size_t sbytes = c->sort_tmp_bytes;
+        if (rocprim::radix_sort_pairs(c->sort_tmp, sbytes, mkey, mkey2, mval, mval2, m, 0,
+                                      sort_key_bits(c), c->stream) != hipSuccess)
+            throw std::runtime_error("rocprim radix sort failed");
+    }
+    hipLaunchKernelGGL(k_mover_offsets, dim3((nkeys + 1 + 255) / 256), dim3(256), 0, c->stream,
+                       c->sort_tot, mkey2, nkeys, c->sort_moff);
+    uint32_t *knew = c->skey[s][1 - t];
+    int32_t *offnew = c->soff[s][1 - t];
+    const int nb = std::min((nub + 255) / 256, 65536);
+    const int nbm = std::max(1, std::min((int)((m + 255) / 256), 65536));
+    if (c->fp64) {
+        auto P = state_ptrs<uint64_t, 5>(S);
+        hipLaunchKernelGGL((k_scatter_stay<uint64_t, 5>), dim3(nb), dim3(256), 0, c->stream, nub,
+                           c->keys[0], dead, nold, kold, c->sort_sb, c->sort_moff, mval2, knew, P);
+        hipLaunchKernelGGL((k_scatter_move<uint64_t, 5>), dim3(nbm), dim3(256), 0, c->stream,
+                           c->sort_tot, mkey2, mval2, c->sort_sb, offold, knew, P);
+    } else {
+        auto P = state_ptrs<uint32_t, 6>(S);
+        hipLaunchKernelGGL((k_scatter_stay<uint32_t, 6>), dim3(nb), dim3(256), 0, c->stream, nub,
+                           c->keys[0], dead, nold, kold, c->sort_sb, c->sort_moff, mval2, knew, P);
+        hipLaunchKernelGGL((k_scatter_move<uint32_t, 6>), dim3(nbm), dim3(256), 0, c->stream,
+                           c->sort_tot, mkey2, mval2, c->sort_sb, offold, knew, P);
+    }
+    // reads the old live count before replacing it with the new one
+    hipLaunchKernelGGL(k_new_offsets, dim3((nkeys + 1 + 255) / 256), dim3(256), 0, c->stream,
+                       nkeys, offold, c->sort_sb, c->sort_moff, offnew, c->nalive + s,
+                       c->nslots + s);
+    FFPIC_LAUNCH_CHECK();
+    for (int a = 0; a < S.narr; a++) std::swap(S.cur[a], S.alt[a]);
+    c->sort_cur[s] = 1 - t;
+}
+
+void sort_species(ffpic_ctx *c, int s) {
+    ffpic::Species &S = c->sp[s];
+    if (S.nub == 0) return;
+    if (c->sort_valid[s] && c->incremental_sort) sort_incremental(c, s);
+    else sort_full(c, s);
 }
 
 }  // namespace ffpic

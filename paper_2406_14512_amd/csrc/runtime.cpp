@@ -314,6 +314,9 @@ void free_all(ffpic_ctx *c) {
     for (int s = 0; s < FFPIC_MAX_SPECIES; s++)
         for (int a = 0; a < 6; a++) { F(c->sp[s].cur[a]); F(c->sp[s].alt[a]); }
     for (int k = 0; k < 2; k++) { F(c->keys[k]); F(c->vals[k]); }
+    for (int s = 0; s < FFPIC_MAX_SPECIES; s++)
+        for (int k = 0; k < 2; k++) { F(c->skey[s][k]); F(c->soff[s][k]); }
+    F(c->sort_sb); F(c->sort_blk); F(c->sort_aux); F(c->sort_moff); F(c->sort_tot); F(c->scan_tmp);
     F(c->sort_tmp); F(c->nslots); F(c->nalive); F(c->removed); F(c->err); F(c->red);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
@@ -386,6 +389,15 @@ int ffpic_create(const ffpic_desc *d, void *stream, ffpic_ctx **out) {
             c->dt = d->cfl / std::sqrt(1.0 / (drr * drr) + 1.0 / (drt * drt));
         }
         build_tables(c);
+        {   // first row where the absorber's factor (in working precision) is below 1
+            auto below1 = [&](double v) { return c->fp64 ? v != 1.0 : (float)v != 1.0f; };
+            c->absorb_row0 = c->nr + 1;
+            for (int i = 0; i <= c->nr; i++)
+                if (below1(c->tab[T_LAMN][i]) || (i < c->nr && below1(c->tab[T_LAMH][i]))) {
+                    c->absorb_row0 = i;
+                    break;
+                }
+        }
         for (int t = 0; t < T_NTAB; t++) {
             const auto &h = c->tab[t];
             c->dtab64[t] = (double *)dmalloc(h.size() * sizeof(double));
@@ -429,6 +441,22 @@ int ffpic_create(const ffpic_desc *d, void *stream, ffpic_ctx **out) {
         }
         c->sort_tmp_bytes = sort_temp_bytes(maxcap, sort_key_bits(c));
         c->sort_tmp = dmalloc(c->sort_tmp_bytes);
+        {
+            const int64_t nblk = std::max<int64_t>(1, (maxcap + sort_block_slots() - 1) / sort_block_slots());
+            const size_t nk1 = (size_t)c->nr * c->nth + 1;
+            c->sort_sb = (uint32_t *)dmalloc((size_t)(maxcap + 1) * 4);
+            c->sort_blk = (uint32_t *)dmalloc((size_t)nblk * 4 * 4);
+            c->sort_aux = (uint32_t *)dmalloc((size_t)std::max<int64_t>(maxcap, 1) * 4);
+            c->sort_moff = (int32_t *)dmalloc(nk1 * 4);
+            c->sort_tot = (uint32_t *)dmalloc(2 * 4);
+            c->scan_tmp_bytes = scan_temp_bytes(nblk);
+            c->scan_tmp = dmalloc(c->scan_tmp_bytes);
+            for (int s = 0; s < d->nspec; s++)
+                for (int k = 0; k < 2; k++) {
+                    c->skey[s][k] = (uint32_t *)dmalloc((size_t)std::max<int64_t>(c->sp[s].cap, 1) * 4);
+                    c->soff[s][k] = (int32_t *)dmalloc(nk1 * 4);
+                }
+        }
         c->nslots = (int32_t *)dmalloc(FFPIC_MAX_SPECIES * sizeof(int32_t));
         c->nalive = (int32_t *)dmalloc(FFPIC_MAX_SPECIES * sizeof(int32_t));
         c->removed = (unsigned long long *)dmalloc(FFPIC_MAX_SPECIES * 4 * sizeof(unsigned long long));
@@ -545,6 +573,7 @@ int ffpic_load_particles(ffpic_ctx *c, int s, int64_t n, const double *r, const 
         }
         convert_loaded(c, s, S.nub, n, src[0], src[1], src[2], src[3], src[4]);
         S.nub += n;
+        c->sort_valid[s] = false;   // appended particles: full sort
         int32_t ns = (int32_t)S.nub;
         HCHK(hipMemcpyAsync(c->nslots + s, &ns, sizeof(ns), hipMemcpyHostToDevice, c->stream));
         sort_species(c, s);
@@ -852,6 +881,7 @@ int ffpic_restore(ffpic_ctx *c, const void *buf, size_t len) {
         }
         HCHK(hipMemcpy(c->nslots, ns, sizeof(ns), hipMemcpyHostToDevice));
         HCHK(hipMemcpy(c->removed, h.removed, sizeof(h.removed), hipMemcpyHostToDevice));
+        for (int s = 0; s < FFPIC_MAX_SPECIES; s++) c->sort_valid[s] = false;
         HCHK(hipMemcpy(c->err, &h.err, sizeof(uint32_t), hipMemcpyHostToDevice));
         for (int k = 0; k < 3; k++) HCHK(hipMemset(c->J[k], 0, fb));
         // the kill flags follow from Psi

@@ -244,3 +244,50 @@ def test_error_paths():
         sim.load_particles(0, w.particles(0))          # 92 + 100 > 150 slots
     assert e.value.code == ffpic.ECAPACITY
     assert sim.n(0) == 92
+
+
+def expected_stable_order(cells, kill_cell):
+    """Stable order by cell of the live particles not in a kill cell."""
+    live = (cells >= 0) & ~kill_cell
+    idx = np.nonzero(live)[0]
+    return idx[np.argsort(cells[idx], kind="stable")]
+
+
+def kill_cells(sim, nr, nth):
+    f = sim.field(ffpic.F)
+    k = (f[:-1, :-1] == 1.0) & (f[1:, :-1] == 1.0) & (f[:-1, 1:] == 1.0) & (f[1:, 1:] == 1.0)
+    return k[:nr, :nth].reshape(-1)
+
+
+@pytest.mark.parametrize("precision", [W.FP32_MIXED, W.FP64])
+def test_incremental_sort_is_the_stable_sort(precision):
+    """After steps without a sort, the (incremental) re-sort puts every
+    particle where a stable sort of the current cells puts it: the exported
+    state after the sort is exactly the pre-sort state permuted."""
+    w = small_sheet(60_000, nr=192)
+    d = w.desc()
+    d["precision"] = precision
+    d["sort_interval"] = 1000           # only the load sorts during the steps
+    sim = ffpic.Sim(d, capacity=[w.n_per_species] * 2)
+    for s in range(2):
+        sim.load_particles(s, w.particles(s))
+    for rnd in range(3):
+        sim.step(4)
+        sim.run_phases(ffpic.PHASE_MASK)
+        kc = kill_cells(sim, w.nr, w.nth)
+        before = [sim.particles(s) for s in range(2)]
+        sim.run_phases(ffpic.PHASE_SORT)
+        for s in range(2):
+            p0 = before[s]
+            cells = p0["cell"]
+            killed = np.zeros(len(cells), dtype=bool)
+            ok = cells >= 0
+            killed[ok] = kc[cells[ok]]
+            order = expected_stable_order(cells, killed)
+            p1 = sim.particles(s)
+            assert len(p1["r"]) == len(order), (rnd, s)
+            for k in ("cell", "r", "th", "ur", "uth", "uph"):
+                assert np.array_equal(p1[k], p0[k][order]), (rnd, s, k)
+            off = sim.sort_offsets(s)
+            assert off[-1] == len(order)
+            assert np.array_equal(np.diff(off), np.bincount(p1["cell"], minlength=len(off) - 1))
