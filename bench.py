@@ -136,6 +136,40 @@ def roofline(precision, res, steps, nspec, copy_gbs):
             "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
 
 
+def batch_run(ffpic, W, steps, warmup, scale):
+    """The batched workload: 64 independent magnetospheres (grids 256^2 to
+    1024^2, 1e6-1e7 particles each, FP32-mixed) stepped together through
+    ffpic_batch_step; wall time around the batch step and a full sync."""
+    ws = W.batched_systems(64, scale=scale)
+    descs, caps = [], []
+    for w in ws:
+        d = w.desc()
+        d["precision"] = w.precision
+        descs.append(d)
+        caps.append([w.n_per_species] * w.nspec)
+    b = ffpic.Batch(descs, caps)
+    for w, v in zip(ws, b.views):
+        for s in range(w.nspec):
+            for c in range(w.n_chunks()):
+                v.load_particles(s, w.chunk(s, c))
+    b.step(warmup)
+    b.sync()
+    alive = lambda: sum(sum(v.diagnostics(ffpic.DIAG_MOMENTS)["alive"]) for v in b.views)
+    n0 = alive()
+    t0 = time.perf_counter()
+    b.step(steps)
+    b.sync()
+    t1 = time.perf_counter()
+    n1 = alive()
+    cells = sum(w.nr * w.nth for w in ws)
+    b.close()
+    wall = t1 - t0
+    return {"systems": len(ws), "particles": int(0.5 * (n0 + n1)), "cells": cells,
+            "steps": steps, "ms_per_step": wall / steps * 1e3,
+            "particle_steps_per_s": 0.5 * (n0 + n1) * steps / wall,
+            "cell_updates_per_s": cells * steps / wall}
+
+
 def cpu_baseline(w, n_sample, steps=2):
     import oracle
     oracle.build(force=False)
@@ -177,6 +211,10 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2_000_000)
+    ap.add_argument("--batch", action="store_true",
+                    help="also time the batched workload (64 systems) and report it under 'batch'")
+    ap.add_argument("--batch-scale", type=float, default=1.0,
+                    help="particle-count scale of the batched workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three plain 1 GiB device copies (for scaling HBM counters)")
     args = ap.parse_args()
@@ -262,6 +300,11 @@ def main():
                        "roofline": roofline(0, r64, args.steps, w.nspec, copy_gbs)}
         out["fp32_over_fp64"] = out["value"] / out["fp64"]["value"]
     sims[1].close()
+    if args.batch:
+        log("timing the batched workload (64 systems)")
+        out["batch"] = batch_run(ffpic, W, args.steps, args.warmup, args.batch_scale)
+        log(f"  batch: {out['batch']['ms_per_step']:.3f} ms/step, "
+            f"{out['batch']['particle_steps_per_s']:.3e} particle-steps/s")
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)

@@ -13,6 +13,24 @@
  *   position whose lower corner is node (i, j); unused entries stay zero.
  * Particles: per species, FP64 (r, theta, u_r, u_theta, u_phi); a dead slot
  * has r = -1 until the next sort compacts it away.
+ *
+ * What pins each part (tests/test_oracle_pins.py, tests/golden/):
+ *   time step and radial spacing: Table 1 values; Boris rotation: the exact
+ *   discrete rotation angle and |u| conservation; E x B drift; radiation
+ *   reaction: closed-form cooling, first-order convergence; flux function:
+ *   telescoping of B built from nodal Psi (three inits), second-order
+ *   dipole; blending function: equality cases and linear bands; force-free
+ *   node correction: E.B = 0, |E| <= |B|, idempotence; gather: exact for
+ *   linear fields, axis parity; deposit + Ampere: discrete Gauss law kept
+ *   to roundoff; Faraday: div B kept to roundoff; corotation E curl-free;
+ *   sort: stability; Michel monopole: stationary to second order, and a
+ *   vacuum monopole spinning up to Michel's luminosity.
+ * Parity unpinned (defined here and checked GPU against oracle only, no
+ * closed form behind them): the blend of J at staggered points (mean of
+ * the adjacent node f), averaging the correction back from nodes rather
+ * than E itself, the absorbing-layer profile, the opened-dipole initial
+ * field, and the placement of the radiation-reaction kick after the Boris
+ * rotation (its first-order convergence is pinned, its ordering is not).
  */
 #ifndef FFPIC_ORACLE_H
 #define FFPIC_ORACLE_H

@@ -20,6 +20,22 @@
 
 namespace ffpic {
 
+// force-free correction at a node in FP32 (Sect. 3: E.B projection, then
+// |E| <= |B|), with the hardware reciprocal and square roots (about 1 ulp)
+// in place of the divisions; B = 0 gives E = 0
+__device__ __forceinline__ void ff_node_f(const float e[3], const float b[3], float o[3]) {
+    const float b2 = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+    if (!(b2 > 0.f)) { o[0] = o[1] = o[2] = 0.f; return; }
+    const float ib2 = __builtin_amdgcn_rcpf(b2);
+    const float eb = (e[0] * b[0] + e[1] * b[1] + e[2] * b[2]) * ib2;
+    for (int c = 0; c < 3; c++) o[c] = e[c] - eb * b[c];
+    const float e2 = o[0] * o[0] + o[1] * o[1] + o[2] * o[2];
+    if (e2 >= b2 && e2 > 0.f) {
+        const float s = __builtin_amdgcn_sqrtf(b2) * __builtin_amdgcn_rsqf(e2);
+        for (int c = 0; c < 3; c++) o[c] = s * o[c];
+    }
+}
+
 struct PertArrays {
     float *dE[3], *dB[3];
     const float *E0[3], *B0[3];
@@ -83,9 +99,10 @@ __global__ void k_jffe_p(Geo<float> g, PertArrays P, const float *__restrict__ e
     float x2 = e[0] * b[1] - e[1] * b[0];
     // at a magnetic null the drift current is undefined: zero (as for B = 0)
     bool ok = b2 > 1e-30f;
-    j0[k] = ok ? rho * x0 / b2 : 0.f;
-    j1[k] = ok ? rho * x1 / b2 : 0.f;
-    j2[k] = ok ? rho * x2 / b2 : 0.f;
+    const float rb = ok ? rho * __builtin_amdgcn_rcpf(b2) : 0.f;
+    j0[k] = rb * x0;
+    j1[k] = rb * x1;
+    j2[k] = rb * x2;
 }
 
 __global__ void k_ampere_p(Geo<float> g, PertArrays P, float *__restrict__ er,
@@ -211,6 +228,31 @@ __global__ void k_absorb_p(Geo<float> g, int i0, PertArrays P, float *__restrict
     }
 }
 
+
+// node corrections delta = f (E* - E) from E^{n+1} and B^{n+1/2} (FP32)
+__global__ void k_ffdelta_f(Geo<float> g, const float *__restrict__ er, const float *__restrict__ et,
+                            const float *__restrict__ ep, const float *__restrict__ br,
+                            const float *__restrict__ bt, const float *__restrict__ bp,
+                            const float *__restrict__ f, float *__restrict__ d0,
+                            float *__restrict__ d1, float *__restrict__ d2) {
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = blockIdx.y;
+    if (j > g.nth) return;
+    size_t k = ix(g.ld, i, j);
+    float fv = f[k];
+    float o[3] = {0.f, 0.f, 0.f};
+    if (fv > 0.f) {
+        float e[3], b[3], s[3];
+        node_e(g, er, et, ep, i, j, e);
+        node_b(g, br, bt, bp, i, j, b);
+        ff_node_f(e, b, s);
+        for (int c = 0; c < 3; c++) o[c] = fv * (s[c] - e[c]);
+    }
+    d0[k] = o[0];
+    d1[k] = o[1];
+    d2[k] = o[2];
+}
+
 static void run_field_step_pert(ffpic_ctx *c) {
     Geo<float> g = geo<float>(c);
     dim3 blk(256), grd((c->nth + 1 + 255) / 256, c->nr + 1);
@@ -236,7 +278,7 @@ static void run_field_step_pert(ffpic_ctx *c) {
     hipLaunchKernelGGL(k_ampere_p, grd, blk, 0, c->stream, g, P, E[0], E[1], E[2], J[0], J[1],
                        J[2], f, S[0], S[1], S[2], ff);
     if (ff) {
-        hipLaunchKernelGGL(k_ffdelta<float>, grd, blk, 0, c->stream, g, E[0], E[1], E[2], B[0],
+        hipLaunchKernelGGL(k_ffdelta_f, grd, blk, 0, c->stream, g, E[0], E[1], E[2], B[0],
                            B[1], B[2], f, S[3], S[4], S[5]);
         hipLaunchKernelGGL(k_ffapply_p, grd, blk, 0, c->stream, g, P, E[0], E[1], E[2], S[3],
                            S[4], S[5]);

@@ -131,17 +131,26 @@ __device__ __forceinline__ void push_chunk(const P32 &p, const Fields &F, const 
                                            int &nabs) {
     const int ld = p.ld, nth = p.nth;
     const unsigned ld4 = (unsigned)ld << 2;
+    // the offsets of the next particle are loaded one iteration ahead, and
+    // the kill flag is applied at the end, so that neither load sits on the
+    // latency chain in front of the field gather
+    float an = 0.f, bn = 0.f;
+    if (cell[0] >= 0) {
+        an = State::ld(S.a, (unsigned)(base + tid));
+        bn = State::ld(S.b, (unsigned)(base + tid));
+    }
 #pragma unroll 1
     for (int k = 0; k < kPPT; k++) {
         const unsigned q = (unsigned)(base + k * kWG + tid);
         const int c = cell[k];
-        bool live = c >= 0;
+        const bool live = c >= 0;
         const int i = c >> 16, j = c & 0xffff;
-        if (live && kill[(unsigned)(i * nth + j)]) {
-            live = false;
-            S.stc(q, -1);
-            nkill++;
+        const float a = an, b = bn;
+        if (k + 1 < kPPT && cell[k + 1] >= 0) {
+            an = State::ld(S.a, q + kWG);
+            bn = State::ld(S.b, q + kWG);
         }
+        const bool killed = live && kill[(unsigned)(i * nth + j)] != 0;
         // The deposit values below are assigned for every kept particle and
         // read only under `simple` / `cross`, which imply that assignment, so
         // they carry no initial value (no register setup on the other paths).
@@ -151,7 +160,6 @@ __device__ __forceinline__ void push_chunk(const P32 &p, const Fields &F, const 
         int di, dj;
         float x1, y1, x2, y2, qv;
         if (live) {
-            const float a = State::ld(S.a, q), b = State::ld(S.b, q);
             const float ur = State::ld(S.ur, q), ut = State::ld(S.ut, q), up = State::ld(S.up, q);
             // ---- staggered bilinear gather
             const bool ah = a >= 0.5f, bh = b >= 0.5f;
@@ -265,14 +273,17 @@ __device__ __forceinline__ void push_chunk(const P32 &p, const Fields &F, const 
             const bool cfl = di > 1 || di < -1 || dj > 1 || dj < -1;
             // one test for all five: a NaN or an infinity survives the sum
             const bool finite = __builtin_isfinite(na + nb + rx + ry + rz);
-            const bool star = finite && i2 < 0;
-            const bool absb = finite && !star && (i2 > p.iabs || (i2 == p.iabs && na >= p.aabs));
-            const bool keep = finite && !star && !absb;
+            // a particle in a force-free cell is removed before it moves
+            const bool star = !killed && finite && i2 < 0;
+            const bool absb = !killed && finite && !star &&
+                              (i2 > p.iabs || (i2 == p.iabs && na >= p.aabs));
+            const bool keep = !killed && finite && !star && !absb;
+            nkill += killed ? 1 : 0;
             nstar += star ? 1 : 0;
             nabs += absb ? 1 : 0;
-            if (cfl) atomicOr(err, FFPIC_ERR_CFL);
+            if (cfl && !killed) atomicOr(err, FFPIC_ERR_CFL);
             // non-finite state is flagged in the error word and never deposited
-            if (!finite) atomicOr(err, FFPIC_ERR_NONFINITE);
+            if (!finite && !killed) atomicOr(err, FFPIC_ERR_NONFINITE);
             S.stc(q, keep ? ((i2 << 16) | j2) : -1);
             if (keep) {
                 State::st(S.a, q, na);

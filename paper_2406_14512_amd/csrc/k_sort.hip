@@ -280,29 +280,90 @@ __device__ __forceinline__ int slot_class(uint32_t key, uint32_t dead, int q, in
     return (q < nold && kold[q] == key) ? 1 : 2;        // 1 stayer, 2 mover
 }
 
-// per-block counts of stayers and movers (keys already written by the key
-// pass); 256 threads, kSortBlock slots per block
-__global__ void __launch_bounds__(256) k_class_count(int nub, const uint32_t *__restrict__ keys,
-                                                     uint32_t dead, const int32_t *__restrict__ nold,
-                                                     const uint32_t *__restrict__ kold,
-                                                     uint32_t *__restrict__ bst,
-                                                     uint32_t *__restrict__ bmv) {
+// key pass fused with the stayer / mover counts of each block of
+// kSortBlock slots (incremental sort); same keys and removals as k_key32 /
+// k_key64
+__device__ __forceinline__ void block_counts(uint32_t st, uint32_t mv, uint32_t *bst,
+                                             uint32_t *bmv) {
     __shared__ uint32_t part[2][4];
     const int tid = threadIdx.x, w = tid >> 6;
-    const int no = nold[0];
-    uint32_t st = 0, mv = 0;
-    for (int k = 0; k < kSortBlock / 256; k++) {
-        const int q = blockIdx.x * kSortBlock + k * 256 + tid;
-        const int cl = q < nub ? slot_class(keys[q], dead, q, no, kold) : 0;
-        st += __popcll(__ballot(cl == 1));
-        mv += __popcll(__ballot(cl == 2));
-    }
     if ((tid & 63) == 0) { part[0][w] = st; part[1][w] = mv; }
     __syncthreads();
     if (tid == 0) {
         bst[blockIdx.x] = part[0][0] + part[0][1] + part[0][2] + part[0][3];
         bmv[blockIdx.x] = part[1][0] + part[1][1] + part[1][2] + part[1][3];
     }
+}
+
+__global__ void __launch_bounds__(256) k_keyclass32(int nub, const int32_t *__restrict__ nslots,
+                                                    int nth, const uint8_t *__restrict__ kill,
+                                                    uint32_t dead, int32_t *__restrict__ CELL,
+                                                    uint32_t *__restrict__ keys,
+                                                    unsigned long long *__restrict__ removed,
+                                                    const uint32_t *__restrict__ kold,
+                                                    uint32_t *__restrict__ bst,
+                                                    uint32_t *__restrict__ bmv) {
+    const int ns = nslots[0];
+    uint32_t st = 0, mv = 0;
+    for (int k = 0; k < kSortBlock / 256; k++) {
+        const int q = blockIdx.x * kSortBlock + k * 256 + threadIdx.x;
+        uint32_t key = dead;
+        bool killed = false;
+        if (q < ns) {
+            const int c = CELL[q];
+            if (c >= 0) {
+                const int i = c >> 16, j = c & 0xffff;
+                if (kill[(size_t)i * nth + j]) {
+                    killed = true;
+                    CELL[q] = -1;
+                } else {
+                    key = (uint32_t)i * (uint32_t)nth + (uint32_t)j;
+                }
+            }
+        }
+        if (q < nub) keys[q] = key;
+        count_wave(&removed[1], killed);
+        const int cl = q < nub ? slot_class(key, dead, q, ns, kold) : 0;
+        st += __popcll(__ballot(cl == 1));
+        mv += __popcll(__ballot(cl == 2));
+    }
+    block_counts(st, mv, bst, bmv);
+}
+
+__global__ void __launch_bounds__(256) k_keyclass64(
+    int nub, const int32_t *__restrict__ nslots, int nr, int nth, double rmin, double dlog,
+    double dth, const double *__restrict__ rn, const double *__restrict__ thn,
+    const uint8_t *__restrict__ kill, uint32_t dead, double *__restrict__ R,
+    const double *__restrict__ TH, uint32_t *__restrict__ keys,
+    unsigned long long *__restrict__ removed, const uint32_t *__restrict__ kold,
+    uint32_t *__restrict__ bst, uint32_t *__restrict__ bmv) {
+    const int ns = nslots[0];
+    uint32_t st = 0, mv = 0;
+    for (int k = 0; k < kSortBlock / 256; k++) {
+        const int q = blockIdx.x * kSortBlock + k * 256 + threadIdx.x;
+        uint32_t key = dead;
+        bool killed = false;
+        if (q < ns) {
+            const double r = R[q];
+            if (r > 0.0) {
+                int i, j;
+                double a, b;
+                locate64(nr, nth, rmin, dlog, dth, rn, thn, r, TH[q], i, j, a, b);
+                if (kill[(size_t)i * nth + j]) {
+                    killed = true;
+                    R[q] = -1.0;
+                } else {
+                    key = (uint32_t)i * (uint32_t)nth + (uint32_t)j;
+                }
+            }
+        }
+        if (q < nub) keys[q] = key;
+        count_wave(&removed[1], killed);
+        const int cl = q < nub ? slot_class(key, dead, q, ns, kold) : 0;
+        st += __popcll(__ballot(cl == 1));
+        mv += __popcll(__ballot(cl == 2));
+    }
+    block_counts(st, mv, bst, bmv);
 }
 
 // SB[q] for every slot (stayers before q), the movers compacted in slot
@@ -358,46 +419,52 @@ __global__ void k_mover_offsets(const uint32_t *__restrict__ tot, const uint32_t
 
 // stayers: slot q with key k goes to SB[q] + moff[k] + (movers of key k
 // from a slot below q)
+// One kernel places both classes: the first nbm blocks stride over the
+// sorted movers (dispatched first, so their dependent loads overlap the
+// streaming copy), the remaining blocks take one slot per thread (stayers).
+//   stayer: slot q with key k goes to SB[q] + moff[k] + (movers of key k
+//           from a slot below q);
+//   mover:  rank j (key k, slot q) goes to j + SB[clamp(q, OFF[k], OFF[k+1])].
 template <typename T, int NA>
-__global__ void k_scatter_stay(int nub, const uint32_t *__restrict__ keys, uint32_t dead,
-                               const int32_t *__restrict__ nold, const uint32_t *__restrict__ kold,
-                               const uint32_t *__restrict__ sb, const int32_t *__restrict__ moff,
-                               const uint32_t *__restrict__ mval, uint32_t *__restrict__ knew,
-                               PtrSet<T, NA> P) {
-    const int no = nold[0];
-    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nub; q += gridDim.x * blockDim.x) {
-        const uint32_t key = keys[q];
-        if (slot_class(key, dead, q, no, kold) != 1) continue;
-        int lo = moff[key];
-        int hi = moff[key + 1];
-        while (lo < hi) {                 // movers of this key are in slot order
-            const int mid = (lo + hi) >> 1;
-            if ((int)mval[mid] < q) lo = mid + 1; else hi = mid;
+__global__ void k_scatter(int nub, int nbm, const uint32_t *__restrict__ keys, uint32_t dead,
+                          const int32_t *__restrict__ nold, const uint32_t *__restrict__ kold,
+                          const uint32_t *__restrict__ sb, const int32_t *__restrict__ moff,
+                          const uint32_t *__restrict__ tot, const uint32_t *__restrict__ mkey,
+                          const uint32_t *__restrict__ mval, const int32_t *__restrict__ offold,
+                          uint32_t *__restrict__ knew, PtrSet<T, NA> P) {
+    if ((int)blockIdx.x < nbm) {
+        const int m = (int)tot[1];
+        for (int j = (int)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += nbm * blockDim.x) {
+            const uint32_t key = mkey[j];
+            const int q = (int)mval[j];
+            const int lo = offold[key], hi = offold[key + 1];
+            const int c = q < lo ? lo : (q > hi ? hi : q);
+            const uint32_t d = (uint32_t)j + sb[c];
+#pragma unroll
+            for (int a = 0; a < NA; a++) P.dst[a][d] = P.src[a][q];
+            knew[d] = key;
         }
-        const uint32_t d = sb[q] + (uint32_t)lo;
-#pragma unroll
-        for (int a = 0; a < NA; a++) P.dst[a][d] = P.src[a][q];
-        knew[d] = key;
+        return;
     }
-}
-
-// movers: rank j (key k, slot q) goes to j + SB[clamp(q, OFF[k], OFF[k+1])]
-template <typename T, int NA>
-__global__ void k_scatter_move(const uint32_t *__restrict__ tot, const uint32_t *__restrict__ mkey,
-                               const uint32_t *__restrict__ mval, const uint32_t *__restrict__ sb,
-                               const int32_t *__restrict__ offold, uint32_t *__restrict__ knew,
-                               PtrSet<T, NA> P) {
-    const int m = (int)tot[1];
-    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < m; j += gridDim.x * blockDim.x) {
-        const uint32_t key = mkey[j];
-        const int q = (int)mval[j];
-        const int lo = offold[key], hi = offold[key + 1];
-        const int c = q < lo ? lo : (q > hi ? hi : q);
-        const uint32_t d = (uint32_t)j + sb[c];
+    const int q = ((int)blockIdx.x - nbm) * blockDim.x + threadIdx.x;
+    if (q >= nub) return;
+    // the state is read before the class is known, so its loads overlap the
+    // key and offset loads (dead slots are read and dropped)
+    T v[NA];
 #pragma unroll
-        for (int a = 0; a < NA; a++) P.dst[a][d] = P.src[a][q];
-        knew[d] = key;
+    for (int a = 0; a < NA; a++) v[a] = P.src[a][q];
+    const uint32_t key = keys[q];
+    if (slot_class(key, dead, q, nold[0], kold) != 1) return;
+    int lo = moff[key];
+    int hi = moff[key + 1];
+    while (lo < hi) {                     // movers of this key are in slot order
+        const int mid = (lo + hi) >> 1;
+        if ((int)mval[mid] < q) lo = mid + 1; else hi = mid;
     }
+    const uint32_t d = sb[q] + (uint32_t)lo;
+#pragma unroll
+    for (int a = 0; a < NA; a++) P.dst[a][d] = v[a];
+    knew[d] = key;
 }
 
 // offsets of the new order: stayers with key < k (= SB at the old offset)
@@ -487,11 +554,19 @@ static void sort_incremental(ffpic_ctx *c, int s) {
     const uint32_t *kold = c->skey[s][t];
     const int32_t *offold = c->soff[s][t];
     const int32_t *nold = c->nslots + s;   // live count of the last sort
-    key_pass(c, s, dead, false);
     const int nblk = (nub + kSortBlock - 1) / kSortBlock;
     uint32_t *bst = c->sort_blk, *bmv = bst + nblk, *cst = bmv + nblk, *cmv = cst + nblk;
-    hipLaunchKernelGGL(k_class_count, dim3(nblk), dim3(256), 0, c->stream, nub, c->keys[0], dead,
-                       nold, kold, bst, bmv);
+    if (c->fp64) {
+        hipLaunchKernelGGL(k_keyclass64, dim3(nblk), dim3(256), 0, c->stream, nub, c->nslots + s,
+                           c->nr, c->nth, c->d.rmin, c->dlog, c->dth, c->dtab64[T_RN],
+                           c->dtab64[T_THN], c->kill, dead, (double *)S.cur[0],
+                           (const double *)S.cur[1], c->keys[0], c->removed + 4 * s, kold, bst,
+                           bmv);
+    } else {
+        hipLaunchKernelGGL(k_keyclass32, dim3(nblk), dim3(256), 0, c->stream, nub, c->nslots + s,
+                           c->nth, c->kill, dead, (int32_t *)S.cur[0], c->keys[0],
+                           c->removed + 4 * s, kold, bst, bmv);
+    }
     FFPIC_LAUNCH_CHECK();
     size_t bytes = c->scan_tmp_bytes;
     if (rocprim::exclusive_scan(c->scan_tmp, bytes, bst, cst, 0u, (size_t)nblk,
@@ -518,20 +593,16 @@ static void sort_incremental(ffpic_ctx *c, int s) {
                        c->sort_tot, mkey2, nkeys, c->sort_moff);
     uint32_t *knew = c->skey[s][1 - t];
     int32_t *offnew = c->soff[s][1 - t];
-    const int nb = std::min((nub + 255) / 256, 65536);
-    const int nbm = std::max(1, std::min((int)((m + 255) / 256), 65536));
+    const int nbs = (nub + 255) / 256;
+    const int nbm = std::max(1, std::min((int)((m + 255) / 256), 4096));
     if (c->fp64) {
-        auto P = state_ptrs<uint64_t, 5>(S);
-        hipLaunchKernelGGL((k_scatter_stay<uint64_t, 5>), dim3(nb), dim3(256), 0, c->stream, nub,
-                           c->keys[0], dead, nold, kold, c->sort_sb, c->sort_moff, mval2, knew, P);
-        hipLaunchKernelGGL((k_scatter_move<uint64_t, 5>), dim3(nbm), dim3(256), 0, c->stream,
-                           c->sort_tot, mkey2, mval2, c->sort_sb, offold, knew, P);
+        hipLaunchKernelGGL((k_scatter<uint64_t, 5>), dim3(nbs + nbm), dim3(256), 0, c->stream,
+                           nub, nbm, c->keys[0], dead, nold, kold, c->sort_sb, c->sort_moff,
+                           c->sort_tot, mkey2, mval2, offold, knew, (state_ptrs<uint64_t, 5>(S)));
     } else {
-        auto P = state_ptrs<uint32_t, 6>(S);
-        hipLaunchKernelGGL((k_scatter_stay<uint32_t, 6>), dim3(nb), dim3(256), 0, c->stream, nub,
-                           c->keys[0], dead, nold, kold, c->sort_sb, c->sort_moff, mval2, knew, P);
-        hipLaunchKernelGGL((k_scatter_move<uint32_t, 6>), dim3(nbm), dim3(256), 0, c->stream,
-                           c->sort_tot, mkey2, mval2, c->sort_sb, offold, knew, P);
+        hipLaunchKernelGGL((k_scatter<uint32_t, 6>), dim3(nbs + nbm), dim3(256), 0, c->stream,
+                           nub, nbm, c->keys[0], dead, nold, kold, c->sort_sb, c->sort_moff,
+                           c->sort_tot, mkey2, mval2, offold, knew, (state_ptrs<uint32_t, 6>(S)));
     }
     // reads the old live count before replacing it with the new one
     hipLaunchKernelGGL(k_new_offsets, dim3((nkeys + 1 + 255) / 256), dim3(256), 0, c->stream,

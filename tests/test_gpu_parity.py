@@ -157,6 +157,41 @@ def test_full_steps_fp64(factory):
         assert np.count_nonzero(g["cell"] != o["cell"]) == 0
 
 
+@pytest.mark.parametrize("precision", [W.FP64, W.FP32_MIXED])
+def test_table1_transition_layers_both_ff_domains(precision):
+    """The flux bands of Table 1 on the open dipole: force-free below
+    0.85 Psi_pc, linear layer to 0.9 Psi_pc, PIC up to 2.3 Psi_pc, linear
+    layer to 2.4 Psi_pc, force-free above (the closed zone near the star).
+    Exercises fractional f in the blend, the weighted correction and both
+    force-free domains."""
+    w = W.tiny_open_dipole(40_000, steps=12)
+    psi_pc = w.mu / w.r_lc
+    w.psi_thr = (0.85 * psi_pc, 0.9 * psi_pc, 2.3 * psi_pc, 2.4 * psi_pc)
+    sim, ora = pair(w, precision)
+    f = sim.field(ffpic.F)
+    assert np.any((f > 0) & (f < 1)) and np.any(f == 1.0) and np.any(f == 0.0)
+    fo = ora.field(oracle.F)
+    if precision == W.FP64:
+        assert np.array_equal(f, fo)
+    else:
+        # Psi comes from the FP32 B_r, so f inside the linear layers moves by
+        # (relative Psi change ~1e-7) * Psi / (layer width)
+        assert np.allclose(f, fo, rtol=0, atol=1e-5)
+    load_both(sim, ora, w)
+    sim.step(12)
+    ora.step(12)
+    sim.sync()
+    errs = field_errors(sim, ora)
+    tol = FP64_TOL if precision == W.FP64 else FP32_TOL
+    assert max(errs.values()) < tol, errs
+    m = moment_errors(sim, ora, 2)
+    for k, v in m.items():
+        if k.startswith("n"):
+            assert v <= (0 if precision == W.FP64 else 2e-5 * w.n_per_species + 2), (k, v)
+        else:
+            assert v < tol, (k, v)
+
+
 def test_michel_monopole_pure_ff_fp64_gpu():
     w = W.michel_monopole(64, pure_ff=True, init=W.INIT_MONOPOLE)
     sim, ora = pair(w, cap=1)
@@ -244,6 +279,49 @@ def test_error_paths():
         sim.load_particles(0, w.particles(0))          # 92 + 100 > 150 slots
     assert e.value.code == ffpic.ECAPACITY
     assert sim.n(0) == 92
+
+
+def edge_particles(w, base):
+    """Particles on the domain's edges and on grid lines: r at r_min, on a
+    node radius and just below the absorber, theta on the axis, on a node
+    angle and at the equator; plus a few outside the domain."""
+    dlog = math.log(w.rmax / w.rmin) / w.nr
+    dth = math.pi / w.nth
+    r_edge = [w.rmin, w.rmin * math.exp(3 * dlog), w.r_abs * (1 - 1e-12), 0.5 * (w.r_lc + w.r_abs),
+              w.rmin * 0.999, w.r_abs * 1.0001]
+    th_edge = [0.0, math.pi, 7 * dth, 0.5 * math.pi, 1e-300, math.pi - 1e-15]
+    rr, tt = np.meshgrid(r_edge, th_edge, indexing="ij")
+    n = rr.size
+    out = {"r": np.concatenate([base["r"], rr.ravel()]),
+           "th": np.concatenate([base["th"], tt.ravel()])}
+    for k, v in (("ur", 0.3), ("uth", -0.2), ("uph", 0.5)):
+        out[k] = np.concatenate([base[k], np.full(n, v)])
+    return out
+
+
+@pytest.mark.parametrize("precision", [W.FP64, W.FP32_MIXED])
+def test_ragged_grid_edge_particles_and_empty_species(precision):
+    """A grid whose sizes match no tile (97 x 61), particles on the domain's
+    edges and grid lines (cells bit-exact in FP64), an empty second species,
+    a few steps against the oracle."""
+    w = W.tiny_open_dipole(3000, steps=6)
+    w.nr, w.nth = 97, 61
+    sim, ora = pair(w, precision, cap=w.n_per_species + 64)
+    p = edge_particles(w, w.particles(0))
+    sim.load_particles(0, p)
+    ora.load(0, p)
+    g, o = sim.particles(0), ora.particles(0)
+    assert len(g["cell"]) == len(o["cell"])
+    assert sim.diagnostics(ffpic.DIAG_MOMENTS)["removed"][0] == list(ora.removed(0))
+    if precision == W.FP64:
+        assert np.array_equal(g["cell"], o["cell"])
+    sim.step(6)
+    ora.step(6)
+    sim.sync()
+    assert sim.n(1) == 0
+    assert sim.diagnostics(ffpic.DIAG_MOMENTS)["alive"][1] == 0
+    errs = field_errors(sim, ora)
+    assert max(errs.values()) < (FP64_TOL if precision == W.FP64 else FP32_TOL), errs
 
 
 def expected_stable_order(cells, kill_cell):
