@@ -10,9 +10,12 @@
  *     of eq. (transition), rebuilt from the current B_r every step;
  *   - removal of particles from cells inside the pure force-free domain;
  *   - every sort_interval steps, a stable sort of each species by cell;
+ *   - optional plasma sources: surface pair injection (Sect. 4) and
+ *     Goldreich-Julian extraction of electrons and ions (Sect. 5);
  *   - the particle push of eq. (motion) with the radiation-reaction force
  *     g and the effective field of eq. (bperp), a modified Boris scheme;
  *   - a charge-conserving current deposit;
+ *   - optional threshold pair creation by the pushed leptons (Sect. 5);
  *   - the Yee/FDTD field update of eqs. (faraday) and (ampere) with the
  *     blended current of eq. (blending), whose force-free part is the
  *     drift current of eq. (JFFE), followed by the force-free E correction
@@ -121,6 +124,53 @@ typedef struct ffpic_desc {
     double qm[FFPIC_MAX_SPECIES];     /* charge-to-mass in units of e/m_e
                                          (-1 electrons, +1 positrons, 1/1836 protons) */
     double weight[FFPIC_MAX_SPECIES]; /* macro-particle charge magnitude */
+    double inject_kappa;      /* surface pair injection (Sect. 4, monopole test):
+                                 multiplicity kappa_inj, 0 = off.  Every step,
+                                 each surface cell (i = 0) outside the pure
+                                 force-free domain receives on average
+                                 kappa_inj |rho_GJ| V / (q c^-1 dr0 / dt) pairs,
+                                 |rho_GJ| = Omega |B_r| / 2 pi at the surface,
+                                 q = weight[0]: floor(N) pairs plus one with
+                                 probability frac(N), at uniform in-cell offsets,
+                                 in corotation, one particle of every species
+                                 at each position */
+    uint64_t rng_seed;        /* key of the Philox4x32-10 generator of the
+                                 injection draws (counter = step, cell, draw) */
+    /* Plasma sources of the aligned dipole (Sect. 5).  All zero = off. */
+    int32_t rr_ramp_n;        /* 0..4 knots of the radiation-reaction ramp:
+                                 rr_coef is scaled by a factor that is
+                                 piecewise linear through (rr_ramp_t[k],
+                                 rr_ramp_f[k]) at t = step * dt, constant
+                                 before the first knot and after the last
+                                 (times non-decreasing, factors >= 0) */
+    int32_t pad2_;
+    double rr_ramp_t[4];
+    double rr_ramp_f[4];
+    double shell_r;           /* r < shell_r (the old position): after the
+                                 Boris rotation and radiation reaction only
+                                 the momentum along the local B is kept;
+                                 0 = off */
+    double gj_extract;        /* Goldreich-Julian extraction multiplicity,
+                                 0 = off.  Every step, each surface cell
+                                 (i = 0) outside the pure force-free domain
+                                 holding less charge (sum over all species of
+                                 weight x live particles) than
+                                 gj_extract |rho_GJ| V (|rho_GJ| = Omega |B_r| /
+                                 2 pi at the surface, V per radian of azimuth)
+                                 receives ceil(deficit / (w_e + w_i)) pairs of
+                                 an electron and an ion at uniform in-cell
+                                 offsets (Philox draws, counter word 3 =
+                                 0x676A6578), in corotation */
+    int32_t gj_species[2];    /* extracted electron and ion species */
+    double gamma_th;          /* pair creation threshold, 0 = off: after the
+                                 push every particle of pair_species[0] or
+                                 pair_species[1] with gamma > gamma_th adds
+                                 one particle to each of the two species at
+                                 its position, moving along its momentum
+                                 with Lorentz factor gamma_s (parent kept;
+                                 parents in species order, then slot order) */
+    double gamma_s;           /* 1 <= gamma_s < gamma_th */
+    int32_t pair_species[2];  /* electron and positron species */
 } ffpic_desc;
 
 typedef struct ffpic_diag {
@@ -140,6 +190,9 @@ typedef struct ffpic_diag {
 
 #define FFPIC_ERR_NONFINITE 1u  /* non-finite momentum after a push */
 #define FFPIC_ERR_CFL 2u        /* a particle crossed more than one cell */
+#define FFPIC_ERR_CAPACITY 4u   /* injection, extraction or pair creation
+                                   would exceed a species' capacity (nothing
+                                   added by that phase in that step) */
 
 #define FFPIC_DIAG_MOMENTS 1u
 #define FFPIC_DIAG_ENERGY 2u
@@ -187,13 +240,16 @@ int ffpic_load_particles(ffpic_ctx *ctx, int species, int64_t n, const double *r
 int ffpic_step(ffpic_ctx *ctx, int32_t nsteps);
 
 /* Test hook: runs single phases of a step without advancing the step
-   counter (bit mask of FFPIC_PHASE_*), in the order mask, kill, sort, push,
-   fields. */
+   counter (bit mask of FFPIC_PHASE_*), in the order mask, kill, sort,
+   inject, extract, push, pairs, fields. */
 #define FFPIC_PHASE_MASK 1u
 #define FFPIC_PHASE_KILL 2u
 #define FFPIC_PHASE_SORT 4u
 #define FFPIC_PHASE_PUSH 8u
 #define FFPIC_PHASE_FIELDS 16u
+#define FFPIC_PHASE_INJECT 32u
+#define FFPIC_PHASE_EXTRACT 64u
+#define FFPIC_PHASE_PAIRS 128u
 int ffpic_run_phases(ffpic_ctx *ctx, uint32_t phases);
 
 /* Waits for the stream and returns the first recorded device error

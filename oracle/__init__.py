@@ -17,7 +17,8 @@ SRC = os.path.join(HERE, "ffpic_oracle.c")
 
 # field component numbering of the oracle (ffpic_oracle.h)
 ER, ETH, EPH, BR, BTH, BPH, JR, JTH, JPH, PSI, F, B0R, B0TH, B0PH = range(14)
-PHASE_MASK, PHASE_KILL, PHASE_SORT, PHASE_PUSH, PHASE_FIELDS = 1, 2, 4, 8, 16
+PHASE_MASK, PHASE_KILL, PHASE_SORT, PHASE_PUSH, PHASE_FIELDS, PHASE_INJECT = 1, 2, 4, 8, 16, 32
+PHASE_EXTRACT, PHASE_PAIRS = 64, 128
 
 
 def build(force: bool = True) -> str:
@@ -39,7 +40,13 @@ class _Params(C.Structure):
                 ("psi_thr", C.c_double * 4),
                 ("ff_enable", C.c_int), ("init", C.c_int),
                 ("sort_interval", C.c_int), ("nspec", C.c_int),
-                ("qm", C.c_double * 4), ("weight", C.c_double * 4)]
+                ("qm", C.c_double * 4), ("weight", C.c_double * 4),
+                ("inject_kappa", C.c_double), ("rng_seed", C.c_uint64),
+                ("rr_ramp_n", C.c_int), ("rr_ramp_t", C.c_double * 4),
+                ("rr_ramp_f", C.c_double * 4), ("shell_r", C.c_double),
+                ("gj_extract", C.c_double), ("gj_species", C.c_int * 2),
+                ("gamma_th", C.c_double), ("gamma_s", C.c_double),
+                ("pair_species", C.c_int * 2)]
 
 
 _lib = None
@@ -70,6 +77,7 @@ def lib():
         L.ora_run_phases.argtypes = [P, C.c_int]
         L.ora_step_count.restype = C.c_int64
         L.ora_step_count.argtypes = [P]
+        L.ora_set_step.argtypes = [P, C.c_int64]
         L.ora_removed.argtypes = [P, C.c_int, np.ctypeslib.ndpointer(np.int64)]
         L.ora_moments.argtypes = [P, C.c_int, dp]
         L.ora_gauss.argtypes = [P, dp]
@@ -85,6 +93,14 @@ def lib():
         L.ora_gather.argtypes = [P, C.c_double, C.c_double, dp, dp]
         L.ora_blend.restype = C.c_double
         L.ora_blend.argtypes = [C.c_double, dp]
+        u32p = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
+        L.ora_philox4x32.argtypes = [u32p, u32p, u32p]
+        L.ora_inject_rate.restype = C.c_double
+        L.ora_inject_rate.argtypes = [P, C.c_int]
+        L.ora_gj_target.restype = C.c_double
+        L.ora_gj_target.argtypes = [P, C.c_int]
+        L.ora_rr_factor.restype = C.c_double
+        L.ora_rr_factor.argtypes = [C.POINTER(_Params), C.c_double]
         _lib = L
     return _lib
 
@@ -100,7 +116,29 @@ def params(desc: dict) -> _Params:
     for k, (q, w) in enumerate(zip(desc["qm"], desc["weight"])):
         p.qm[k] = float(q)
         p.weight[k] = float(w)
+    p.inject_kappa = float(desc.get("inject_kappa", 0.0))
+    p.rng_seed = int(desc.get("rng_seed", 0))
+    ramp = desc.get("rr_ramp", ())
+    p.rr_ramp_n = len(ramp)
+    for k, (t, f) in enumerate(ramp):
+        p.rr_ramp_t[k] = float(t)
+        p.rr_ramp_f[k] = float(f)
+    p.shell_r = float(desc.get("shell_r", 0.0))
+    p.gj_extract = float(desc.get("gj_extract", 0.0))
+    p.gamma_th = float(desc.get("gamma_th", 0.0))
+    p.gamma_s = float(desc.get("gamma_s", 0.0))
+    for k in range(2):
+        p.gj_species[k] = int(desc.get("gj_species", (0, 0))[k])
+        p.pair_species[k] = int(desc.get("pair_species", (0, 0))[k])
     return p
+
+
+def philox4x32(ctr, key) -> np.ndarray:
+    """Philox4x32-10 output words for a counter (4 words) and key (2 words)."""
+    out = np.zeros(4, dtype=np.uint32)
+    lib().ora_philox4x32(np.ascontiguousarray(ctr, dtype=np.uint32),
+                         np.ascontiguousarray(key, dtype=np.uint32), out)
+    return out
 
 
 class Oracle:
@@ -165,6 +203,9 @@ class Oracle:
     def step_count(self) -> int:
         return int(lib().ora_step_count(self._h))
 
+    def set_step(self, n: int):
+        lib().ora_set_step(self._h, int(n))
+
     def removed(self, sp: int) -> np.ndarray:
         out = np.zeros(4, dtype=np.int64)
         lib().ora_removed(self._h, sp, out)
@@ -195,6 +236,12 @@ class Oracle:
         lib().ora_poynting(self._h, out)
         return out
 
+    def inject_rate(self, j: int) -> float:
+        return float(lib().ora_inject_rate(self._h, int(j)))
+
+    def gj_target(self, j: int) -> float:
+        return float(lib().ora_gj_target(self._h, int(j)))
+
     def gather(self, r: float, th: float):
         E = np.zeros(3)
         B = np.zeros(3)
@@ -217,6 +264,11 @@ def boris_rr(u, E, B, dt, wq, rr=0.0):
     lib().ora_boris_rr(uu, np.asarray(E, dtype=np.float64), np.asarray(B, dtype=np.float64),
                        float(dt), float(wq), float(rr))
     return uu
+
+
+def rr_factor(desc: dict, t: float) -> float:
+    p = params(desc)
+    return float(lib().ora_rr_factor(C.byref(p), float(t)))
 
 
 def ff_node(E, B):

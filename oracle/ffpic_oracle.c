@@ -13,8 +13,13 @@
  *   2. particles in cells whose four corners have f = 1 are removed
  *      (particles are absent from the pure force-free domain);
  *   3. every sort_interval steps: stable counting sort by cell;
+ *   3a. sources: surface pair injection (Sect. 4), Goldreich-Julian
+ *      extraction of electrons and ions (Sect. 5);
  *   4. push (eq. motion with the radiation-reaction force g of Sect. 3 and
- *      the effective field of eq. bperp), move, charge-conserving deposit;
+ *      the effective field of eq. bperp; the force's strength ramped in
+ *      time and the momentum across B removed near the star, Sect. 5),
+ *      move, charge-conserving deposit;
+ *   4a. threshold pair creation by the pushed leptons (Sect. 5);
  *   5. field step: Faraday half step (eq. faraday), force-free current at
  *      nodes (drift part of eq. JFFE), blend (eq. blending), Ampere
  *      (eq. ampere), force-free E correction at nodes (E.B projection and
@@ -209,6 +214,24 @@ static int valid(const ora_params *p)
         if (!(p->psi_thr[k] <= p->psi_thr[k + 1])) return 0;
     if (p->nspec < 0 || p->nspec > ORA_MAXSPEC) return 0;
     if (p->sort_interval < 1) return 0;
+    if (p->rr_ramp_n < 0 || p->rr_ramp_n > 4) return 0;
+    for (int k = 0; k < p->rr_ramp_n; k++) {
+        if (!(p->rr_ramp_f[k] >= 0.0) || !isfinite(p->rr_ramp_t[k])) return 0;
+        if (k > 0 && !(p->rr_ramp_t[k] >= p->rr_ramp_t[k - 1])) return 0;
+    }
+    if (!(p->shell_r >= 0.0)) return 0;
+    if (!(p->gj_extract >= 0.0)) return 0;
+    if (p->gj_extract > 0.0)
+        for (int k = 0; k < 2; k++)
+            if (p->gj_species[k] < 0 || p->gj_species[k] >= p->nspec) return 0;
+    if (p->gj_extract > 0.0 && p->gj_species[0] == p->gj_species[1]) return 0;
+    if (!(p->gamma_th >= 0.0)) return 0;
+    if (p->gamma_th > 0.0) {
+        if (!(p->gamma_s >= 1.0) || !(p->gamma_s < p->gamma_th)) return 0;
+        for (int k = 0; k < 2; k++)
+            if (p->pair_species[k] < 0 || p->pair_species[k] >= p->nspec) return 0;
+        if (p->pair_species[0] == p->pair_species[1]) return 0;
+    }
     return 1;
 }
 
@@ -296,6 +319,7 @@ void ora_set_field(ora_sim *s, int c, const double *src)
 }
 
 int64_t ora_step_count(const ora_sim *s) { return s->step; }
+void ora_set_step(ora_sim *s, int64_t step) { s->step = step; }
 
 void ora_removed(const ora_sim *s, int sp, int64_t out[4])
 {
@@ -596,13 +620,33 @@ static void deposit(ora_sim *s, double Q, int i1, int j1, double a1, double b1,
     AT(s, ORA_JPH, i1 + im + 1, j1 + jm + 1) += qv * wx * wy;
 }
 
+/* Radiation-reaction ramp of Sect. 5 (reduced strength while the
+   magnetosphere fills, raised to the nominal value later): piecewise
+   linear through the knots (t_k, f_k), constant before the first and
+   after the last; no knots = 1. */
+double ora_rr_factor(const ora_params *p, double t)
+{
+    int n = p->rr_ramp_n;
+    if (n <= 0) return 1.0;
+    if (t <= p->rr_ramp_t[0]) return p->rr_ramp_f[0];
+    for (int k = 1; k < n; k++) {
+        if (t < p->rr_ramp_t[k]) {
+            double t0 = p->rr_ramp_t[k - 1], t1 = p->rr_ramp_t[k];
+            double x = (t - t0) / (t1 - t0);
+            return p->rr_ramp_f[k - 1] + x * (p->rr_ramp_f[k] - p->rr_ramp_f[k - 1]);
+        }
+    }
+    return p->rr_ramp_f[n - 1];
+}
+
 static void push_species(ora_sim *s, int k)
 {
     struct species *q = &s->sp[k];
     double qm = s->p.qm[k];
     double Q = (qm > 0 ? 1.0 : -1.0) * s->p.weight[k];
     double wq = s->p.omega_b * qm;
-    double rr = s->p.rr_coef * fabs(qm) * fabs(qm) * fabs(qm);
+    double rr = s->p.rr_coef * ora_rr_factor(&s->p, (double)s->step * s->dt) *
+                fabs(qm) * fabs(qm) * fabs(qm);
     double dt = s->dt;
     for (int64_t p = 0; p < q->n; p++) {
         if (!(q->r[p] > 0.0)) continue;
@@ -619,6 +663,15 @@ static void push_species(ora_sim *s, int k)
         double u[3] = {q->ur[p] * st + q->uth[p] * ct, q->uph[p],
                        q->ur[p] * ct - q->uth[p] * st};
         ora_boris_rr(u, E, B, dt, wq, rr);
+        if (r < s->p.shell_r) {
+            /* shell around the star (Sect. 5): only the momentum along
+               the local magnetic field is kept */
+            double b2 = dot3(B, B);
+            if (b2 > 0.0) {
+                double ub = dot3(u, B) / b2;
+                for (int c = 0; c < 3; c++) u[c] = ub * B[c];
+            }
+        }
         double g = sqrt(1.0 + dot3(u, u));
         double v[3] = {u[0] / g, u[1] / g, u[2] / g};
         double x = r * st + dt * v[0], y = dt * v[1], z = r * ct + dt * v[2];
@@ -853,21 +906,204 @@ static void field_step(ora_sim *s)
 
 /* ------------------------------------------------------------------ */
 
+/* ------------------------------------------------------------------ */
+/* surface pair injection (Sect. 4, monopole test: pairs injected with
+   multiplicity kappa_inj in the first cell layer above the star, PIC
+   domain only)                                                        */
+
+/* Philox4x32 with 10 rounds, as defined by Salmon, Moraes, Dror & Shaw
+   (2011): each round multiplies words 0 and 2 by two constants, mixes the
+   high halves with words 1 and 3 and the key, and the key is bumped by
+   two Weyl constants between rounds. */
+void ora_philox4x32(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; r++) {
+        if (r > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Expected pairs per step in surface cell (0, j): kappa_inj times the
+   Goldreich-Julian number density |rho_GJ| / q = Omega |B_r| / (2 pi q)
+   (B_r at the cell's lower face, the stellar surface) in the cell volume,
+   renewed once per crossing time of the cell at c. */
+double ora_inject_rate(const ora_sim *s, int j)
+{
+    double br = fabs(AT(s, ORA_BR, 0, j));
+    double q = s->p.weight[0];
+    double vol = (s->rn[1] * s->rn[1] * s->rn[1] - s->rn[0] * s->rn[0] * s->rn[0]) / 3.0 *
+                 (s->cn[j] - s->cn[j + 1]);
+    return s->p.inject_kappa * (s->omega * br / (2.0 * PI)) / q * vol *
+           (s->dt / (s->rn[1] - s->rn[0]));
+}
+
+#define INJ_TAG 0x696E6A63u   /* counter word 3 of the injection draws */
+
+static double u01(uint32_t x) { return (double)x * (1.0 / 4294967296.0); }
+
+static void append(struct species *q, double r, double th, double ur, double uth,
+                   double uph)
+{
+    if (q->n + 1 > q->cap) {
+        int64_t cap = 2 * q->cap + 16;
+        q->r = realloc(q->r, cap * sizeof(double));
+        q->th = realloc(q->th, cap * sizeof(double));
+        q->ur = realloc(q->ur, cap * sizeof(double));
+        q->uth = realloc(q->uth, cap * sizeof(double));
+        q->uph = realloc(q->uph, cap * sizeof(double));
+        q->cap = cap;
+    }
+    int64_t d = q->n++;
+    q->r[d] = r; q->th[d] = th;
+    q->ur[d] = ur; q->uth[d] = uth; q->uph[d] = uph;
+}
+
+/* In every surface cell outside the pure force-free domain: floor(N) pairs
+   plus one more with probability frac(N), at uniform logical offsets in
+   the cell, in corotation (u_phi = gamma Omega r sin theta); the same
+   positions for every species (pairs carry no net charge). */
+static void inject_pairs(ora_sim *s)
+{
+    if (!(s->p.inject_kappa > 0.0) || s->p.nspec == 0) return;
+    uint32_t key[2] = {(uint32_t)s->p.rng_seed, (uint32_t)(s->p.rng_seed >> 32)};
+    uint32_t stp = (uint32_t)s->step;
+    for (int j = 0; j < s->nth; j++) {
+        if (s->kill[j]) continue;
+        double N = ora_inject_rate(s, j);
+        double fl = floor(N);
+        uint32_t ctr[4] = {stp, (uint32_t)j, 0u, INJ_TAG}, o[4];
+        ora_philox4x32(ctr, key, o);
+        int n = (int)fl + (u01(o[0]) < N - fl ? 1 : 0);
+        for (int p = 0; p < n; p++) {
+            uint32_t c2[4] = {stp, (uint32_t)j, (uint32_t)(p + 1), INJ_TAG};
+            ora_philox4x32(c2, key, o);
+            double a = u01(o[0]), b = u01(o[1]);
+            double r = s->rn[0] * exp(a * s->dlog);
+            double th = s->thn[j] + b * s->dth;
+            double v = s->omega * r * sin(th);
+            double uph = v / sqrt(1.0 - v * v);
+            for (int k = 0; k < s->p.nspec; k++) append(&s->sp[k], r, th, 0.0, 0.0, uph);
+        }
+    }
+}
+
+/* Goldreich-Julian charge of surface cell (0, j), |rho_GJ| V with
+   |rho_GJ| = Omega |B_r| / (2 pi) at the stellar surface, times the
+   extraction multiplicity (V per radian of azimuth, as every volume here) */
+double ora_gj_target(const ora_sim *s, int j)
+{
+    double br = fabs(AT(s, ORA_BR, 0, j));
+    double vol = (s->rn[1] * s->rn[1] * s->rn[1] - s->rn[0] * s->rn[0] * s->rn[0]) / 3.0 *
+                 (s->cn[j] - s->cn[j + 1]);
+    return s->p.gj_extract * (s->omega * br / (2.0 * PI)) * vol;
+}
+
+#define EXT_TAG 0x676A6578u   /* counter word 3 of the extraction draws */
+
+/* Goldreich-Julian extraction (Sect. 5, dipole): every step, each surface
+   cell outside the pure force-free domain whose particles (all species,
+   counted by charge magnitude, species in order) hold less than the
+   target charge receives ceil(deficit / (w_e + w_i)) electron-ion pairs
+   at uniform logical offsets, in corotation, with no poloidal momentum;
+   the electron of each pair is appended first. */
+static void extract_gj(ora_sim *s)
+{
+    if (!(s->p.gj_extract > 0.0)) return;
+    int nth = s->nth;
+    double *have = calloc(nth, sizeof(double));
+    for (int k = 0; k < s->p.nspec; k++) {
+        struct species *q = &s->sp[k];
+        int64_t *cnt = calloc(nth, sizeof(int64_t));
+        for (int64_t p = 0; p < q->n; p++) {
+            if (!(q->r[p] > 0.0) || !(q->r[p] < s->rn[1])) continue;
+            int i, j; double a, b;
+            locate(s, q->r[p], q->th[p], &i, &j, &a, &b);
+            if (i == 0) cnt[j]++;
+        }
+        for (int j = 0; j < nth; j++) have[j] += s->p.weight[k] * (double)cnt[j];
+        free(cnt);
+    }
+    int se = s->p.gj_species[0], si = s->p.gj_species[1];
+    double wpair = s->p.weight[se] + s->p.weight[si];
+    uint32_t key[2] = {(uint32_t)s->p.rng_seed, (uint32_t)(s->p.rng_seed >> 32)};
+    uint32_t stp = (uint32_t)s->step;
+    for (int j = 0; j < nth; j++) {
+        if (s->kill[j]) continue;
+        double deficit = ora_gj_target(s, j) - have[j];
+        if (!(deficit > 0.0)) continue;
+        int n = (int)ceil(deficit / wpair);
+        for (int p = 0; p < n; p++) {
+            uint32_t ctr[4] = {stp, (uint32_t)j, (uint32_t)(p + 1), EXT_TAG}, o[4];
+            ora_philox4x32(ctr, key, o);
+            double a = u01(o[0]), b = u01(o[1]);
+            double r = s->rn[0] * exp(a * s->dlog);
+            double th = s->thn[j] + b * s->dth;
+            double v = s->omega * r * sin(th);
+            double uph = v / sqrt(1.0 - v * v);
+            append(&s->sp[se], r, th, 0.0, 0.0, uph);
+            append(&s->sp[si], r, th, 0.0, 0.0, uph);
+        }
+    }
+    free(have);
+}
+
+/* Threshold pair creation (Sect. 5): after the push, every electron or
+   positron with gamma > gamma_th creates one pair (an electron and a
+   positron) at its position, moving along its direction of motion with
+   Lorentz factor gamma_s.  The parent keeps its momentum.  Parents are
+   taken species by species, in slot order; the pairs are appended in that
+   order (the new particles are not parents in the same step). */
+static void create_pairs(ora_sim *s)
+{
+    if (!(s->p.gamma_th > 0.0)) return;
+    int se = s->p.pair_species[0], sz = s->p.pair_species[1];
+    double gth2 = s->p.gamma_th * s->p.gamma_th;
+    double us = sqrt(s->p.gamma_s * s->p.gamma_s - 1.0);
+    int64_t n0[2] = {s->sp[se].n, s->sp[sz].n};
+    for (int h = 0; h < 2; h++) {
+        struct species *q = &s->sp[h == 0 ? se : sz];
+        for (int64_t p = 0; p < n0[h]; p++) {
+            if (!(q->r[p] > 0.0)) continue;
+            double u2 = q->ur[p] * q->ur[p] + q->uth[p] * q->uth[p] + q->uph[p] * q->uph[p];
+            if (!(1.0 + u2 > gth2)) continue;
+            double f = us / sqrt(u2);
+            double r = q->r[p], th = q->th[p];
+            double ur = q->ur[p] * f, uth = q->uth[p] * f, uph = q->uph[p] * f;
+            append(&s->sp[se], r, th, ur, uth, uph);
+            append(&s->sp[sz], r, th, ur, uth, uph);
+        }
+    }
+}
+
 void ora_run_phases(ora_sim *s, int ph)
 {
     if (ph & ORA_PHASE_MASK) compute_psi_mask(s);
     if (ph & ORA_PHASE_KILL) kill_masked(s);
     if (ph & ORA_PHASE_SORT)
         for (int k = 0; k < s->p.nspec; k++) sort_species(s, k);
+    if (ph & ORA_PHASE_INJECT) inject_pairs(s);
+    if (ph & ORA_PHASE_EXTRACT) extract_gj(s);
     if (ph & ORA_PHASE_PUSH)
         for (int k = 0; k < s->p.nspec; k++) push_species(s, k);
+    if (ph & ORA_PHASE_PAIRS) create_pairs(s);
     if (ph & ORA_PHASE_FIELDS) field_step(s);
 }
 
 void ora_step(ora_sim *s, int nsteps)
 {
     for (int n = 0; n < nsteps; n++) {
-        int ph = ORA_PHASE_MASK | ORA_PHASE_KILL | ORA_PHASE_PUSH | ORA_PHASE_FIELDS;
+        int ph = ORA_PHASE_MASK | ORA_PHASE_KILL | ORA_PHASE_INJECT | ORA_PHASE_EXTRACT |
+                 ORA_PHASE_PUSH | ORA_PHASE_PAIRS | ORA_PHASE_FIELDS;
         if (s->step % s->p.sort_interval == 0) ph |= ORA_PHASE_SORT;
         ora_run_phases(s, ph);
         s->step++;

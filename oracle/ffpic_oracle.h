@@ -24,7 +24,13 @@
  *   linear fields, axis parity; deposit + Ampere: discrete Gauss law kept
  *   to roundoff; Faraday: div B kept to roundoff; corotation E curl-free;
  *   sort: stability; Michel monopole: stationary to second order, and a
- *   vacuum monopole spinning up to Michel's luminosity.
+ *   vacuum monopole spinning up to Michel's luminosity; Philox: published
+ *   known answers; injection: closed-form rate, binomial counts, Gauss law;
+ *   radiation-reaction ramp: its knots and linear pieces; shell: momentum
+ *   left along B only (a particle gyrating across B stops, |u| kept
+ *   outside); extraction: closed-form dipole charge per cell, top-up of a
+ *   partly filled cell, Gauss law; pair creation: one pair per parent above
+ *   threshold per step, at its position, along its motion, with gamma_s.
  * Parity unpinned (defined here and checked GPU against oracle only, no
  * closed form behind them): the blend of J at staggered points (mean of
  * the adjacent node f), averaging the correction back from nodes rather
@@ -44,6 +50,17 @@ typedef struct {
     double psi_thr[4];
     int ff_enable, init, sort_interval, nspec;
     double qm[ORA_MAXSPEC], weight[ORA_MAXSPEC];
+    double inject_kappa;      /* surface pair injection multiplicity (0 = off) */
+    uint64_t rng_seed;        /* key of the counter-based generator */
+    /* plasma sources of the dipole (Sect. 5) */
+    int rr_ramp_n;            /* knots of the radiation-reaction ramp (0 = off) */
+    double rr_ramp_t[4];      /* knot times, non-decreasing */
+    double rr_ramp_f[4];      /* factor on rr_coef at each knot */
+    double shell_r;           /* r < shell_r: transverse momentum removed (0 = off) */
+    double gj_extract;        /* Goldreich-Julian extraction multiplicity (0 = off) */
+    int gj_species[2];        /* extracted electron and ion species */
+    double gamma_th, gamma_s; /* threshold pair creation (gamma_th = 0: off) */
+    int pair_species[2];      /* electron and positron species (parents and pairs) */
 } ora_params;
 
 enum { ORA_ER, ORA_ETH, ORA_EPH, ORA_BR, ORA_BTH, ORA_BPH,
@@ -51,7 +68,8 @@ enum { ORA_ER, ORA_ETH, ORA_EPH, ORA_BR, ORA_BTH, ORA_BPH,
        ORA_B0R, ORA_B0TH, ORA_B0PH, ORA_NCOMP };
 
 enum { ORA_PHASE_MASK = 1, ORA_PHASE_KILL = 2, ORA_PHASE_SORT = 4,
-       ORA_PHASE_PUSH = 8, ORA_PHASE_FIELDS = 16 };
+       ORA_PHASE_PUSH = 8, ORA_PHASE_FIELDS = 16, ORA_PHASE_INJECT = 32,
+       ORA_PHASE_EXTRACT = 64, ORA_PHASE_PAIRS = 128 };
 
 typedef struct ora_sim ora_sim;
 
@@ -72,8 +90,19 @@ int64_t ora_num_particles(const ora_sim *s, int sp);
 int64_t ora_get_particles(const ora_sim *s, int sp, double *r, double *th,
                           double *ur, double *uth, double *uph, int32_t *cell);
 void ora_step(ora_sim *s, int nsteps);
+/* Philox4x32-10 counter-based generator (Salmon et al. 2011): out = the
+   four 32-bit words for counter ctr and key */
+void ora_philox4x32(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+/* expected number of injected pairs per step in surface cell (0, j) */
+double ora_inject_rate(const ora_sim *s, int j);
+/* Goldreich-Julian charge of surface cell (0, j) times the extraction
+   multiplicity: the charge the extraction keeps the cell at */
+double ora_gj_target(const ora_sim *s, int j);
+/* factor on the radiation-reaction coefficient at time t */
+double ora_rr_factor(const ora_params *p, double t);
 void ora_run_phases(ora_sim *s, int phases);
 int64_t ora_step_count(const ora_sim *s);
+void ora_set_step(ora_sim *s, int64_t step);   /* test hook: the step counter */
 /* removed[cause] for cause = 0 load, 1 force-free kill, 2 star, 3 absorber */
 void ora_removed(const ora_sim *s, int sp, int64_t out[4]);
 

@@ -28,6 +28,8 @@ SOURCES = [
     # atomics instead of the compiler's lane-by-lane pre-reduction loop
     ("k_push32.hip", ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]),
     ("k_sort.hip", []),
+    # injected positions follow the oracle's FP64 operation order
+    ("k_inject.hip", ["-ffp-contract=off"]),
     ("k_misc.hip", []),
 ]
 

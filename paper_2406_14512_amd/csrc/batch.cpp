@@ -45,7 +45,6 @@ struct ffpic_batch {
 namespace {
 
 constexpr int kMaxStreams = 4;        // hardware queues a process gets by default
-constexpr int kCandidates[] = {1, 2, 4, 8, 16, 32};
 
 struct BFail {
     int code;
@@ -253,6 +252,10 @@ int ffpic_batch_create(int n, const ffpic_desc *d, void *stream, ffpic_batch **o
             if (r != FFPIC_OK)
                 throw BFail{r, "system " + std::to_string(k) + ": descriptor rejected or allocation failed"};
             c->batch_owned = true;
+            // the incremental sort reads its mover count back to the host,
+            // which would stall the issue of the other systems: batches use
+            // the full sort, which needs no synchronisation
+            c->incremental_sort = false;
             b->ctx[k] = c;
         }
     });

@@ -76,6 +76,13 @@ struct ffpic_ctx {
     std::vector<double> hE0[3], hB0[3];       // FP64 background (host)
     void *scr[6] = {};                        // node scratch (J_FFE, E corrections)
     int absorb_row0 = 0;                      // first grid row with damping below 1
+    // surface pair injection: expected pairs per step of each surface cell
+    // (FP64, host-computed), per-cell counts and their scan
+    double *inj_rate = nullptr;
+    int32_t *inj_cnt = nullptr, *inj_off = nullptr;
+    void *inj_scan_tmp = nullptr;
+    size_t inj_scan_bytes = 0;
+    int64_t inj_bound = 0;                    // most pairs one step can add
     double *psi = nullptr;
     void *f = nullptr;
     uint8_t *kill = nullptr;
@@ -99,6 +106,7 @@ struct ffpic_ctx {
     size_t scan_tmp_bytes = 0;
     int64_t sort_cap = 0;
     int32_t *nslots = nullptr;                // device [FFPIC_MAX_SPECIES]
+    int32_t *nsorted = nullptr;               // device: live count at each species' last sort
     int32_t *nalive = nullptr;                // device [FFPIC_MAX_SPECIES]
     unsigned long long *removed = nullptr;    // device [FFPIC_MAX_SPECIES][4]
     uint32_t *err = nullptr;                  // device error word
@@ -144,6 +152,8 @@ int sort_block_slots();
 int sort_key_bits(const ffpic_ctx *c);
 void zero_counters(ffpic_ctx *c, int32_t *p, int n);
 int tuned_sort_interval(const ffpic_desc *d);
+void inject_pairs(ffpic_ctx *c);
+size_t inject_scan_bytes(int nth);
 
 }  // namespace ffpic
 

@@ -197,42 +197,43 @@ __device__ __forceinline__ void push_chunk(const P32 &p, const Fields &F, const 
             const float xl = a * p.dlog;
             const float r = ldo(p.rn, (unsigned)i) *
                             (1.f + xl * (1.f + xl * (0.5f + xl * (1.f / 6.f + xl * (1.f / 24.f)))));
-            // ---- local Cartesian frame at azimuth 0
-            const float Ex = esr * st + est * ct, Ey = esp, Ez = esr * ct - est * st;
-            const float Bx = bsr * st + bst * ct, By = bsp, Bz = bsr * ct - bst * st;
-            const float ux = ur * st + ut * ct, uy = up, uz = ur * ct - ut * st;
-            // ---- Boris rotation
+            // ---- Boris rotation and radiation reaction in the orthonormal
+            // basis (r, theta, phi) at the particle: the vector algebra is the
+            // same in any right-handed orthonormal basis
             const float h = p.h;
-            const float mx = ux + h * Ex, my = uy + h * Ey, mz = uz + h * Ez;
+            const float mx = ur + h * esr, my = ut + h * est, mz = up + h * esp;
             const float ig = h * frsq(1.f + mx * mx + my * my + mz * mz);
-            const float tx = Bx * ig, ty = By * ig, tz = Bz * ig;
+            const float tx = bsr * ig, ty = bst * ig, tz = bsp * ig;
             const float sf = 2.f * frcp(1.f + tx * tx + ty * ty + tz * tz);
             const float px = mx + (my * tz - mz * ty);
             const float py = my + (mz * tx - mx * tz);
             const float pz = mz + (mx * ty - my * tx);
             const float sx = tx * sf, sy = ty * sf, sz = tz * sf;
-            float nx = mx + (py * sz - pz * sy) + h * Ex;
-            float ny = my + (pz * sx - px * sz) + h * Ey;
-            float nz = mz + (px * sy - py * sx) + h * Ez;
+            float nr = mx + (py * sz - pz * sy) + h * esr;
+            float nt = my + (pz * sx - px * sz) + h * est;
+            float np = mz + (px * sy - py * sx) + h * esp;
             // ---- radiation reaction (explicit, time-centred velocity)
             if (p.kk != 0.f) {
-                float bx = 0.5f * (ux + nx), by = 0.5f * (uy + ny), bz = 0.5f * (uz + nz);
+                float bx = 0.5f * (ur + nr), by = 0.5f * (ut + nt), bz = 0.5f * (up + np);
                 const float gb2 = 1.f + bx * bx + by * by + bz * bz;
                 const float igb = frsq(gb2);
                 bx *= igb; by *= igb; bz *= igb;
-                const float Fx = Ex + (by * Bz - bz * By);
-                const float Fy = Ey + (bz * Bx - bx * Bz);
-                const float Fz = Ez + (bx * By - by * Bx);
-                const float be = bx * Ex + by * Ey + bz * Ez;
+                const float Fx = esr + (by * bsp - bz * bst);
+                const float Fy = est + (bz * bsr - bx * bsp);
+                const float Fz = esp + (bx * bst - by * bsr);
+                const float be = bx * esr + by * est + bz * esp;
                 const float bp2 = fmaxf(Fx * Fx + Fy * Fy + Fz * Fz - be * be, 0.f);
                 const float gg = gb2 * bp2;
                 const float kk = p.kk;
-                nx += kk * ((Fy * Bz - Fz * By) + be * Ex - gg * bx);
-                ny += kk * ((Fz * Bx - Fx * Bz) + be * Ey - gg * by);
-                nz += kk * ((Fx * By - Fy * Bx) + be * Ez - gg * bz);
+                nr += kk * ((Fy * bsp - Fz * bst) + be * esr - gg * bx);
+                nt += kk * ((Fz * bsr - Fx * bsp) + be * est - gg * by);
+                np += kk * ((Fx * bst - Fy * bsr) + be * esp - gg * bz);
             }
-            const float ivg = frsq(1.f + nx * nx + ny * ny + nz * nz);   // 1 / gamma
+            const float ivg = frsq(1.f + nr * nr + nt * nt + np * np);   // 1 / gamma
             const float vdt = p.dt * ivg;
+            // the new momentum in the local Cartesian frame at azimuth 0
+            // (x along the cylindrical radius, y along phi, z along the axis)
+            const float nx = nr * st + nt * ct, ny = np, nz = nr * ct - nt * st;
             const float dx = nx * vdt, dy = ny * vdt, dz = nz * vdt;
             // ---- move in the local frame
             const float w = r * st;

@@ -104,7 +104,8 @@ __global__ void k_key32(int nub, const int32_t *__restrict__ nslots, int nth,
 
 // number of live keys = index of the first dead key in the sorted keys
 __global__ void k_count_sorted(int nub, const uint32_t *__restrict__ keys, uint32_t dead,
-                               int32_t *__restrict__ nalive, int32_t *__restrict__ nslots) {
+                               int32_t *__restrict__ nalive, int32_t *__restrict__ nslots,
+                               int32_t *__restrict__ nsorted) {
     int lo = 0, hi = nub;
     while (lo < hi) {
         int mid = (lo + hi) >> 1;
@@ -112,6 +113,7 @@ __global__ void k_count_sorted(int nub, const uint32_t *__restrict__ keys, uint3
     }
     nalive[0] = lo;
     if (nslots) nslots[0] = lo;
+    if (nsorted) nsorted[0] = lo;
 }
 
 // live count of unsorted keys: block reduction, one atomic per block
@@ -300,10 +302,11 @@ __global__ void __launch_bounds__(256) k_keyclass32(int nub, const int32_t *__re
                                                     uint32_t dead, int32_t *__restrict__ CELL,
                                                     uint32_t *__restrict__ keys,
                                                     unsigned long long *__restrict__ removed,
+                                                    const int32_t *__restrict__ nsorted,
                                                     const uint32_t *__restrict__ kold,
                                                     uint32_t *__restrict__ bst,
                                                     uint32_t *__restrict__ bmv) {
-    const int ns = nslots[0];
+    const int ns = nslots[0], no = nsorted[0];
     uint32_t st = 0, mv = 0;
     for (int k = 0; k < kSortBlock / 256; k++) {
         const int q = blockIdx.x * kSortBlock + k * 256 + threadIdx.x;
@@ -323,7 +326,7 @@ __global__ void __launch_bounds__(256) k_keyclass32(int nub, const int32_t *__re
         }
         if (q < nub) keys[q] = key;
         count_wave(&removed[1], killed);
-        const int cl = q < nub ? slot_class(key, dead, q, ns, kold) : 0;
+        const int cl = q < nub ? slot_class(key, dead, q, no, kold) : 0;
         st += __popcll(__ballot(cl == 1));
         mv += __popcll(__ballot(cl == 2));
     }
@@ -335,9 +338,9 @@ __global__ void __launch_bounds__(256) k_keyclass64(
     double dth, const double *__restrict__ rn, const double *__restrict__ thn,
     const uint8_t *__restrict__ kill, uint32_t dead, double *__restrict__ R,
     const double *__restrict__ TH, uint32_t *__restrict__ keys,
-    unsigned long long *__restrict__ removed, const uint32_t *__restrict__ kold,
-    uint32_t *__restrict__ bst, uint32_t *__restrict__ bmv) {
-    const int ns = nslots[0];
+    unsigned long long *__restrict__ removed, const int32_t *__restrict__ nsorted,
+    const uint32_t *__restrict__ kold, uint32_t *__restrict__ bst, uint32_t *__restrict__ bmv) {
+    const int ns = nslots[0], no = nsorted[0];
     uint32_t st = 0, mv = 0;
     for (int k = 0; k < kSortBlock / 256; k++) {
         const int q = blockIdx.x * kSortBlock + k * 256 + threadIdx.x;
@@ -359,7 +362,7 @@ __global__ void __launch_bounds__(256) k_keyclass64(
         }
         if (q < nub) keys[q] = key;
         count_wave(&removed[1], killed);
-        const int cl = q < nub ? slot_class(key, dead, q, ns, kold) : 0;
+        const int cl = q < nub ? slot_class(key, dead, q, no, kold) : 0;
         st += __popcll(__ballot(cl == 1));
         mv += __popcll(__ballot(cl == 2));
     }
@@ -472,7 +475,7 @@ __global__ void k_scatter(int nub, int nbm, const uint32_t *__restrict__ keys, u
 __global__ void k_new_offsets(int nkeys, const int32_t *__restrict__ offold,
                               const uint32_t *__restrict__ sb, const int32_t *__restrict__ moff,
                               int32_t *__restrict__ offnew, int32_t *__restrict__ nalive,
-                              int32_t *__restrict__ nslots) {
+                              int32_t *__restrict__ nslots, int32_t *__restrict__ nsorted) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k > nkeys) return;
     const int v = (int)sb[offold[k]] + moff[k];
@@ -480,6 +483,7 @@ __global__ void k_new_offsets(int nkeys, const int32_t *__restrict__ offold,
     if (k == nkeys) {
         nalive[0] = v;
         nslots[0] = v;
+        nsorted[0] = v;
     }
 }
 
@@ -521,7 +525,7 @@ static void sort_full(ffpic_ctx *c, int s) {
     if (e != hipSuccess) throw std::runtime_error("rocprim radix sort failed");
     int32_t *nal = c->nalive + s;
     hipLaunchKernelGGL(k_count_sorted, dim3(1), dim3(1), 0, c->stream, nub, c->keys[1], dead, nal,
-                       c->nslots + s);
+                       c->nslots + s, c->nsorted + s);
     int nb = std::min((nub + 255) / 256, 65536);
     if (c->fp64) {
         hipLaunchKernelGGL((k_gather_set<uint64_t, 5>), dim3(nb), dim3(256), 0, c->stream, nub,
@@ -553,19 +557,19 @@ static void sort_incremental(ffpic_ctx *c, int s) {
     const int t = c->sort_cur[s];
     const uint32_t *kold = c->skey[s][t];
     const int32_t *offold = c->soff[s][t];
-    const int32_t *nold = c->nslots + s;   // live count of the last sort
+    const int32_t *nold = c->nsorted + s;  // live count of the last sort
     const int nblk = (nub + kSortBlock - 1) / kSortBlock;
     uint32_t *bst = c->sort_blk, *bmv = bst + nblk, *cst = bmv + nblk, *cmv = cst + nblk;
     if (c->fp64) {
         hipLaunchKernelGGL(k_keyclass64, dim3(nblk), dim3(256), 0, c->stream, nub, c->nslots + s,
                            c->nr, c->nth, c->d.rmin, c->dlog, c->dth, c->dtab64[T_RN],
                            c->dtab64[T_THN], c->kill, dead, (double *)S.cur[0],
-                           (const double *)S.cur[1], c->keys[0], c->removed + 4 * s, kold, bst,
-                           bmv);
+                           (const double *)S.cur[1], c->keys[0], c->removed + 4 * s, nold, kold,
+                           bst, bmv);
     } else {
         hipLaunchKernelGGL(k_keyclass32, dim3(nblk), dim3(256), 0, c->stream, nub, c->nslots + s,
                            c->nth, c->kill, dead, (int32_t *)S.cur[0], c->keys[0],
-                           c->removed + 4 * s, kold, bst, bmv);
+                           c->removed + 4 * s, nold, kold, bst, bmv);
     }
     FFPIC_LAUNCH_CHECK();
     size_t bytes = c->scan_tmp_bytes;
@@ -607,7 +611,7 @@ static void sort_incremental(ffpic_ctx *c, int s) {
     // reads the old live count before replacing it with the new one
     hipLaunchKernelGGL(k_new_offsets, dim3((nkeys + 1 + 255) / 256), dim3(256), 0, c->stream,
                        nkeys, offold, c->sort_sb, c->sort_moff, offnew, c->nalive + s,
-                       c->nslots + s);
+                       c->nslots + s, c->nsorted + s);
     FFPIC_LAUNCH_CHECK();
     for (int a = 0; a < S.narr; a++) std::swap(S.cur[a], S.alt[a]);
     c->sort_cur[s] = 1 - t;

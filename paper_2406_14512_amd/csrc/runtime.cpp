@@ -113,6 +113,36 @@ std::string validate(const ffpic_desc *d) {
         if (!std::isfinite(d->qm[s]) || d->qm[s] == 0.0) return "qm must be finite and non-zero";
         if (!std::isfinite(d->weight[s]) || d->weight[s] < 0) return "weight must be >= 0";
     }
+    if (!std::isfinite(d->inject_kappa) || d->inject_kappa < 0) return "inject_kappa must be >= 0";
+    if (d->inject_kappa > 0 && d->nspec > 0 && !(d->weight[0] > 0))
+        return "injection needs weight[0] > 0";
+    if (d->rr_ramp_n < 0 || d->rr_ramp_n > 4) return "rr_ramp_n must lie in [0, 4]";
+    for (int k = 0; k < d->rr_ramp_n; k++) {
+        if (!std::isfinite(d->rr_ramp_t[k]) || !std::isfinite(d->rr_ramp_f[k]) ||
+            d->rr_ramp_f[k] < 0)
+            return "ramp knots must be finite with factors >= 0";
+        if (k > 0 && !(d->rr_ramp_t[k] >= d->rr_ramp_t[k - 1]))
+            return "ramp knot times must be non-decreasing";
+    }
+    if (!(d->shell_r >= 0) || !std::isfinite(d->shell_r)) return "shell_r must be >= 0";
+    if (!(d->gj_extract >= 0) || !std::isfinite(d->gj_extract)) return "gj_extract must be >= 0";
+    if (d->gj_extract > 0) {
+        for (int k = 0; k < 2; k++)
+            if (d->gj_species[k] < 0 || d->gj_species[k] >= d->nspec)
+                return "gj_species out of range";
+        if (d->gj_species[0] == d->gj_species[1]) return "gj_species must differ";
+        if (!(d->weight[d->gj_species[0]] + d->weight[d->gj_species[1]] > 0))
+            return "extraction needs positive weights";
+    }
+    if (!(d->gamma_th >= 0) || !std::isfinite(d->gamma_th)) return "gamma_th must be >= 0";
+    if (d->gamma_th > 0) {
+        if (!(d->gamma_s >= 1) || !(d->gamma_s < d->gamma_th))
+            return "need 1 <= gamma_s < gamma_th";
+        for (int k = 0; k < 2; k++)
+            if (d->pair_species[k] < 0 || d->pair_species[k] >= d->nspec)
+                return "pair_species out of range";
+        if (d->pair_species[0] == d->pair_species[1]) return "pair_species must differ";
+    }
     return "";
 }
 
@@ -317,11 +347,41 @@ void free_all(ffpic_ctx *c) {
     for (int s = 0; s < FFPIC_MAX_SPECIES; s++)
         for (int k = 0; k < 2; k++) { F(c->skey[s][k]); F(c->soff[s][k]); }
     F(c->sort_sb); F(c->sort_blk); F(c->sort_aux); F(c->sort_moff); F(c->sort_tot); F(c->scan_tmp);
+    F(c->inj_rate); F(c->inj_cnt); F(c->inj_off); F(c->inj_scan_tmp); F(c->nsorted);
     F(c->sort_tmp); F(c->nslots); F(c->nalive); F(c->removed); F(c->err); F(c->red);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
     for (auto &e : c->evpool) (void)hipEventDestroy(e);
     c->evpool.clear();
+}
+
+// expected pairs per step of each surface cell (0, j) from the surface B_r
+// (FP64, the same operation order as the oracle's definition):
+// kappa_inj |rho_GJ| / q * V * dt / dr0 with |rho_GJ| = Omega |B_r| / 2 pi
+void inject_table(ffpic_ctx *c, const double *br_surface) {
+#pragma clang fp contract(off)
+    if (!(c->d.inject_kappa > 0.0) || c->d.nspec == 0) return;
+    const int nth = c->nth;
+    const std::vector<double> &rn = c->tab[T_RN], &cn = c->tab[T_CN];
+    std::vector<double> rate(nth);
+    int64_t bound = 0;
+    for (int j = 0; j < nth; j++) {
+        const double br = std::fabs(br_surface[j]);
+        const double q = c->d.weight[0];
+        const double vol = (rn[1] * rn[1] * rn[1] - rn[0] * rn[0] * rn[0]) / 3.0 * (cn[j] - cn[j + 1]);
+        rate[j] = c->d.inject_kappa * (c->omega * br / (2.0 * kPi)) / q * vol *
+                  (c->dt / (rn[1] - rn[0]));
+        bound += (int64_t)std::ceil(rate[j]);
+    }
+    if (!c->inj_rate) {
+        c->inj_rate = (double *)dmalloc((size_t)nth * sizeof(double));
+        c->inj_cnt = (int32_t *)dmalloc((size_t)(nth + 1) * sizeof(int32_t));
+        c->inj_off = (int32_t *)dmalloc((size_t)(nth + 1) * sizeof(int32_t));
+        c->inj_scan_bytes = inject_scan_bytes(nth);
+        c->inj_scan_tmp = dmalloc(c->inj_scan_bytes);
+    }
+    HCHK(hipMemcpy(c->inj_rate, rate.data(), (size_t)nth * sizeof(double), hipMemcpyHostToDevice));
+    c->inj_bound = bound;
 }
 
 void check_ctx(ffpic_ctx *c) {
@@ -336,7 +396,9 @@ int read_err(ffpic_ctx *c) {
         std::string m = "device error word 0x" + std::to_string(e) + ":";
         if (e & FFPIC_ERR_NONFINITE) m += " non-finite momentum;";
         if (e & FFPIC_ERR_CFL) m += " particle crossed more than one cell in a step;";
-        throw Fail{FFPIC_ENUMERIC, m};
+        if (e & FFPIC_ERR_CAPACITY) m += " injection exceeded a species' capacity;";
+        const bool numeric = (e & (FFPIC_ERR_NONFINITE | FFPIC_ERR_CFL)) != 0;
+        throw Fail{numeric ? FFPIC_ENUMERIC : FFPIC_ECAPACITY, m};
     }
     return 0;
 }
@@ -352,6 +414,15 @@ void one_step(ffpic_ctx *c, uint32_t ph, bool count_step, int tslot) {
         if (ph & FFPIC_PHASE_SORT) sort_species(c, s);
         else if (ph & FFPIC_PHASE_KILL) kill_species(c, s);
     }
+    if ((ph & FFPIC_PHASE_SORT) && c->d.inject_kappa > 0.0 && c->d.nspec > 0) {
+        // injection only grows the host bound of the slots: reset it to the
+        // sorted count
+        int32_t ns[FFPIC_MAX_SPECIES] = {};
+        HCHK(hipMemcpyAsync(ns, c->nslots, sizeof(ns), hipMemcpyDeviceToHost, c->stream));
+        HCHK(hipStreamSynchronize(c->stream));
+        for (int s = 0; s < c->d.nspec; s++) c->sp[s].nub = ns[s];
+    }
+    if (ph & FFPIC_PHASE_INJECT) inject_pairs(c);
     mark(2);
     if (ph & FFPIC_PHASE_PUSH)
         for (int s = 0; s < c->d.nspec; s++) push_species(c, s);
@@ -459,17 +530,20 @@ int ffpic_create(const ffpic_desc *d, void *stream, ffpic_ctx **out) {
         }
         c->nslots = (int32_t *)dmalloc(FFPIC_MAX_SPECIES * sizeof(int32_t));
         c->nalive = (int32_t *)dmalloc(FFPIC_MAX_SPECIES * sizeof(int32_t));
+        c->nsorted = (int32_t *)dmalloc(FFPIC_MAX_SPECIES * sizeof(int32_t));
         c->removed = (unsigned long long *)dmalloc(FFPIC_MAX_SPECIES * 4 * sizeof(unsigned long long));
         c->err = (uint32_t *)dmalloc(sizeof(uint32_t));
         c->red_len = 4096;
         c->red = (double *)dmalloc(c->red_len * sizeof(double));
         HCHK(hipMemset(c->nslots, 0, FFPIC_MAX_SPECIES * sizeof(int32_t)));
         HCHK(hipMemset(c->nalive, 0, FFPIC_MAX_SPECIES * sizeof(int32_t)));
+        HCHK(hipMemset(c->nsorted, 0, FFPIC_MAX_SPECIES * sizeof(int32_t)));
         HCHK(hipMemset(c->removed, 0, FFPIC_MAX_SPECIES * 4 * sizeof(unsigned long long)));
         HCHK(hipMemset(c->err, 0, sizeof(uint32_t)));
         for (auto &e : c->ev) HCHK(hipEventCreate(&e));
         std::vector<double> F[6];
         init_fields_host(c, F);
+        inject_table(c, F[3].data());   // row 0 of B_r: the stellar surface
         for (int k = 0; k < 3; k++) {
             upload_field(c, c->E[k], F[k]);
             upload_field(c, c->B[k], F[3 + k]);
@@ -531,7 +605,16 @@ int ffpic_load_fields(ffpic_ctx *c, int comp, const double *src, int on_dev) {
         }
         from_f64(c, dsrc, dst, c->nn);
         if (comp >= FFPIC_BR) from_f64(c, dsrc, c->B0[comp - 3], c->nn);
-        if (comp == FFPIC_BR) psi_mask(c);
+        if (comp == FFPIC_BR) {
+            psi_mask(c);
+            if (c->d.inject_kappa > 0.0) {
+                std::vector<double> row(c->nth);
+                HCHK(hipMemcpyAsync(row.data(), dsrc, (size_t)c->nth * sizeof(double),
+                                    hipMemcpyDeviceToHost, c->stream));
+                HCHK(hipStreamSynchronize(c->stream));
+                inject_table(c, row.data());
+            }
+        }
         if (!c->fp64) {
             // the loaded component becomes the background of that component
             std::vector<double> h(c->nn);
@@ -598,7 +681,8 @@ int ffpic_step(ffpic_ctx *c, int32_t nsteps) {
             }
         }
         for (int k = 0; k < nsteps; k++) {
-            uint32_t ph = FFPIC_PHASE_MASK | FFPIC_PHASE_KILL | FFPIC_PHASE_PUSH | FFPIC_PHASE_FIELDS;
+            uint32_t ph = FFPIC_PHASE_MASK | FFPIC_PHASE_KILL | FFPIC_PHASE_INJECT |
+                          FFPIC_PHASE_PUSH | FFPIC_PHASE_FIELDS;
             if (c->step % c->d.sort_interval == 0) ph |= FFPIC_PHASE_SORT;
             // the push removes particles of force-free cells itself
             if (!(ph & FFPIC_PHASE_SORT)) ph &= ~FFPIC_PHASE_KILL;

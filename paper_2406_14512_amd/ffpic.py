@@ -20,9 +20,10 @@ OK, EINVAL, ENOMEM, EHIP, ECAPACITY, ENUMERIC, ESTATE = 0, -1, -2, -3, -4, -5, -
 FP64, FP32_MIXED = 0, 1
 INIT_ZERO, INIT_DIPOLE, INIT_MONOPOLE, INIT_MICHEL, INIT_OPEN_DIPOLE = range(5)
 (ER, ETH, EPH, BR, BTH, BPH, JR, JTH, JPH, PSI, F, GAUSS, DIVB) = range(13)
-PHASE_MASK, PHASE_KILL, PHASE_SORT, PHASE_PUSH, PHASE_FIELDS = 1, 2, 4, 8, 16
+PHASE_MASK, PHASE_KILL, PHASE_SORT, PHASE_PUSH, PHASE_FIELDS, PHASE_INJECT = 1, 2, 4, 8, 16, 32
+PHASE_EXTRACT, PHASE_PAIRS = 64, 128
 DIAG_MOMENTS, DIAG_ENERGY, DIAG_RESIDUALS, DIAG_POYNTING, DIAG_ALL = 1, 2, 4, 8, 15
-ERR_NONFINITE, ERR_CFL = 1, 2
+ERR_NONFINITE, ERR_CFL, ERR_CAPACITY = 1, 2, 4
 MAX_SPECIES = 4
 
 
@@ -41,7 +42,13 @@ class Desc(C.Structure):
                 ("ff_enable", C.c_int32), ("precision", C.c_int32), ("init", C.c_int32),
                 ("sort_interval", C.c_int32), ("nspec", C.c_int32), ("pad_", C.c_int32),
                 ("capacity", C.c_int64 * MAX_SPECIES),
-                ("qm", C.c_double * MAX_SPECIES), ("weight", C.c_double * MAX_SPECIES)]
+                ("qm", C.c_double * MAX_SPECIES), ("weight", C.c_double * MAX_SPECIES),
+                ("inject_kappa", C.c_double), ("rng_seed", C.c_uint64),
+                ("rr_ramp_n", C.c_int32), ("pad2_", C.c_int32),
+                ("rr_ramp_t", C.c_double * 4), ("rr_ramp_f", C.c_double * 4),
+                ("shell_r", C.c_double), ("gj_extract", C.c_double),
+                ("gj_species", C.c_int32 * 2), ("gamma_th", C.c_double),
+                ("gamma_s", C.c_double), ("pair_species", C.c_int32 * 2)]
 
 
 class Diag(C.Structure):
@@ -140,6 +147,22 @@ def make_desc(d: Dict, capacity=None) -> Desc:
         s.qm[k] = float(d["qm"][k])
         s.weight[k] = float(d["weight"][k])
         s.capacity[k] = int(cap[k])
+    s.inject_kappa = float(d.get("inject_kappa", 0.0))
+    s.rng_seed = int(d.get("rng_seed", 0))
+    ramp = d.get("rr_ramp", ())
+    if len(ramp) > 4:
+        raise ValueError("at most 4 knots in rr_ramp")
+    s.rr_ramp_n = len(ramp)
+    for k, (t, f) in enumerate(ramp):
+        s.rr_ramp_t[k] = float(t)
+        s.rr_ramp_f[k] = float(f)
+    s.shell_r = float(d.get("shell_r", 0.0))
+    s.gj_extract = float(d.get("gj_extract", 0.0))
+    s.gamma_th = float(d.get("gamma_th", 0.0))
+    s.gamma_s = float(d.get("gamma_s", 0.0))
+    for k in range(2):
+        s.gj_species[k] = int(d.get("gj_species", (0, 0))[k])
+        s.pair_species[k] = int(d.get("pair_species", (0, 0))[k])
     return s
 
 

@@ -65,6 +65,16 @@ class Workload:
     sort_interval: int = 1
     qm: tuple = (-1.0, 1.0)
     weight: tuple = (0.0, 0.0)
+    inject_kappa: float = 0.0   # surface pair injection multiplicity (0 = off)
+    rng_seed: int = 0
+    # plasma sources of the dipole
+    rr_ramp: tuple = ()         # ((t, factor), ...) knots of the radiation-reaction ramp
+    shell_r: float = 0.0        # transverse momentum removed below this radius
+    gj_extract: float = 0.0     # Goldreich-Julian extraction multiplicity (0 = off)
+    gj_species: tuple = (0, 0)  # extracted electron and ion species
+    gamma_th: float = 0.0       # pair-creation threshold (0 = off)
+    gamma_s: float = 0.0        # Lorentz factor of the created pairs
+    pair_species: tuple = (0, 0)  # electron and positron species
     # particle recipe
     n_per_species: int = 0
     kind: str = "none"          # "uniform_band", "sheet", "none"
@@ -91,7 +101,12 @@ class Workload:
                     psi_thr=tuple(self.psi_thr), ff_enable=self.ff_enable,
                     init=self.init, precision=self.precision,
                     sort_interval=self.sort_interval, nspec=self.nspec,
-                    qm=tuple(self.qm), weight=tuple(self.weight))
+                    qm=tuple(self.qm), weight=tuple(self.weight),
+                    inject_kappa=self.inject_kappa, rng_seed=self.rng_seed,
+                    rr_ramp=tuple(tuple(k) for k in self.rr_ramp), shell_r=self.shell_r,
+                    gj_extract=self.gj_extract, gj_species=tuple(self.gj_species),
+                    gamma_th=self.gamma_th, gamma_s=self.gamma_s,
+                    pair_species=tuple(self.pair_species))
 
     # -- particles ---------------------------------------------------------
     def n_chunks(self) -> int:
@@ -316,3 +331,75 @@ def michel_monopole(n: int = 128, pure_ff: bool = True, init: int = INIT_MICHEL,
                     mu=1.0, omega_b=GAMMA_PC * r_lc ** 2, psi_thr=thr,
                     ff_enable=1, init=init, n_per_species=0, kind="none",
                     seed=SEED_BASE + 6, steps=1)
+
+
+def hybrid_monopole(n: int = 128, kappa: float = 10.0, r_lc: float = 5.0,
+                    precision: int = FP64) -> Workload:
+    """The hybrid monopole of Sect. 4: r in [1, (10/3) R_LC], R_LC = 5, a
+    vacuum split-free monopole B = Psi_star / r^2 with corotation, the
+    northern hemisphere PIC and the southern one force-free (sharp boundary
+    at Psi = Psi_star), e+- pairs injected at the surface of the PIC
+    hemisphere with multiplicity kappa_inj.  The macro-particle weight is
+    chosen so that about one pair per surface cell is injected per step at
+    the equator.
+
+    The sharp cut sits half a cell south of the equator, at
+    Psi_star (1 + sin(dtheta / 2)): the equatorial nodes, where the discrete
+    flux function equals Psi_star up to rounding, stay on the PIC side by a
+    margin of sin(dtheta / 2) instead of being decided by the last bit."""
+    rmax = 10.0 / 3.0 * r_lc
+    cut = 1.0 * (1.0 + math.sin(0.5 * math.pi / n))
+    dr0 = math.log(rmax) / n          # first radial spacing in units of r_star
+    dt_est = 0.5 * dr0 / math.sqrt(2.0)
+    omega = 1.0 / r_lc
+    weight = kappa * omega / (2.0 * n) * dt_est
+    return Workload(name=f"hybrid_monopole_{n}", nr=n, nth=n, rmin=1.0, rmax=rmax,
+                    r_lc=r_lc, r_abs=3.0 * r_lc, mu=1.0,
+                    omega_b=GAMMA_PC * r_lc ** 2, rr_coef=0.0,
+                    psi_thr=(-INF, -INF, cut, cut), ff_enable=1, init=INIT_MONOPOLE,
+                    precision=precision, sort_interval=8, weight=(weight, weight),
+                    inject_kappa=kappa, rng_seed=SEED_BASE + 7, n_per_species=0,
+                    kind="none", seed=SEED_BASE + 7, steps=100)
+
+
+def sourced_dipole(n: int = 64, precision: int = FP64, gamma_th: float = 30.0,
+                   gamma_s: float = 5.0, n_per_species: int = 2000) -> Workload:
+    """The aligned dipole of Sect. 5 with its plasma sources, scaled down:
+    r in [1, 10], R_LC = 3, static dipole + corotation, force-free below
+    0.85 Psi_pc and above 2.4 Psi_pc with the linear layers of Table 1;
+    species electrons, positrons and protons (m_p = 1836 m_e); electrons and
+    protons extracted at the surface to the Goldreich-Julian density every
+    step; pairs created by leptons above gamma_th with gamma_s; transverse
+    momentum removed within one stellar radius of the surface; the
+    radiation-reaction force at 1% for one period, raised to 10% by 1.5
+    periods and to its nominal strength at 2 periods.  The macro-particle
+    weight puts about two extracted pairs in a surface cell at 45 degrees.
+    gamma_pc = 1000 here, so the paper's gamma_th / gamma_pc (about 4e-3)
+    would fall below gamma_s = 1.  The run starts from the corotating
+    dipole, where E.B = 0 and nothing is accelerated for hundreds of steps;
+    a band of energetic particles (every species, isotropic, gamma
+    log-uniform in [1, 100], |theta - pi/2| < 0.3, r in (1.5, 3)) is loaded
+    so that parents above gamma_th exist from the first step."""
+    r_lc = 3.0
+    omega_b, rr, _ = _units(r_lc, True, 0.0)
+    psi_pc = 1.0 / r_lc
+    dlog = math.log(10.0) / n
+    dth = math.pi / n
+    th = math.pi / 4
+    t_45 = (1.0 / r_lc) / (2.0 * math.pi) * abs(math.sin(th + dth) ** 2 - math.sin(th) ** 2) * \
+        (math.exp(3.0 * dlog) - 1.0) / 3.0
+    w = t_45 / 4.0
+    period = 2.0 * math.pi * r_lc
+    return Workload(name=f"sourced_dipole_{n}", nr=n, nth=n, rmin=1.0, rmax=10.0,
+                    r_lc=r_lc, r_abs=3.0 * r_lc, omega_b=omega_b, rr_coef=rr,
+                    psi_thr=(0.85 * psi_pc, 0.9 * psi_pc, 2.3 * psi_pc, 2.4 * psi_pc),
+                    ff_enable=1, init=INIT_DIPOLE, precision=precision, sort_interval=4,
+                    qm=(-1.0, 1.0, 1.0 / 1836.0), weight=(w, w, w),
+                    rng_seed=SEED_BASE + 9,
+                    rr_ramp=((0.0, 0.01), (period, 0.01), (1.5 * period, 0.1),
+                             (2.0 * period, 1.0)),
+                    shell_r=2.0, gj_extract=1.0, gj_species=(0, 2),
+                    gamma_th=gamma_th, gamma_s=gamma_s, pair_species=(0, 1),
+                    n_per_species=n_per_species, kind="uniform_band", band=0.3,
+                    sheet_rmin=1.5, sheet_rmax=3.0, gamma_max=100.0,
+                    seed=SEED_BASE + 9, steps=40)

@@ -44,12 +44,15 @@ def test_struct_layout_matches_header(tmp_path, lib):
 #include <stddef.h>
 #include "ffpic.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(ffpic_desc), sizeof(ffpic_diag),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n",
+         sizeof(ffpic_desc), sizeof(ffpic_diag),
          offsetof(ffpic_desc, psi_thr), offsetof(ffpic_desc, capacity),
          offsetof(ffpic_desc, weight), offsetof(ffpic_diag, sum_u),
          offsetof(ffpic_diag, gauss_max), offsetof(ffpic_diag, error_word),
          sizeof(ffpic_tuning), offsetof(ffpic_tuning, ms_per_step),
-         offsetof(ffpic_tuning, total_ms));
+         offsetof(ffpic_tuning, total_ms), offsetof(ffpic_desc, rr_ramp_f),
+         offsetof(ffpic_desc, shell_r), offsetof(ffpic_desc, gj_species),
+         offsetof(ffpic_desc, gamma_s), offsetof(ffpic_desc, pair_species));
   return 0;
 }
 ''')
@@ -59,7 +62,8 @@ int main(void) {
     D, G, T = ffpic.Desc, ffpic.Diag, ffpic.Tuning
     want = [ctypes.sizeof(D), ctypes.sizeof(G), D.psi_thr.offset, D.capacity.offset,
             D.weight.offset, G.sum_u.offset, G.gauss_max.offset, G.error_word.offset,
-            ctypes.sizeof(T), T.ms_per_step.offset, T.total_ms.offset]
+            ctypes.sizeof(T), T.ms_per_step.offset, T.total_ms.offset, D.rr_ramp_f.offset,
+            D.shell_r.offset, D.gj_species.offset, D.gamma_s.offset, D.pair_species.offset]
     assert got == want
 
 
@@ -78,6 +82,15 @@ def test_null_and_invalid_arguments_fail_cleanly(lib):
     bad = dict(d, cfl=1.5)
     assert lib.ffpic_create(ctypes.byref(ffpic.make_desc(bad, [1, 1])), None,
                             ctypes.byref(h)) == ffpic.EINVAL
+    # plasma sources: species out of range or equal, gamma_s >= gamma_th,
+    # ramp knots out of order, negative shell radius
+    for kw in (dict(gj_extract=1.0, gj_species=(0, 2)), dict(gj_extract=1.0, gj_species=(1, 1)),
+               dict(gamma_th=10.0, gamma_s=10.0, pair_species=(0, 1)),
+               dict(gamma_th=10.0, gamma_s=2.0, pair_species=(0, 0)),
+               dict(rr_ramp=((2.0, 0.1), (1.0, 1.0))), dict(rr_ramp=((0.0, -1.0),)),
+               dict(shell_r=-1.0), dict(inject_kappa=-1.0)):
+        assert lib.ffpic_create(ctypes.byref(ffpic.make_desc(dict(d, **kw), [1, 1])), None,
+                                ctypes.byref(h)) == ffpic.EINVAL, kw
     assert lib.ffpic_step(None, 1) == ffpic.EINVAL
     assert lib.ffpic_sync(None) == ffpic.EINVAL
     assert lib.ffpic_last_error(None) == b"no context"

@@ -21,6 +21,8 @@ FIELDS = [(ffpic.ER, oracle.ER, "Er"), (ffpic.ETH, oracle.ETH, "Eth"), (ffpic.EP
           (ffpic.BR, oracle.BR, "Br"), (ffpic.BTH, oracle.BTH, "Bth"), (ffpic.BPH, oracle.BPH, "Bph")]
 FP64_TOL = 1e-12
 FP32_TOL = 2e-5
+# steps of the injected monopole held to FP64_TOL before rounding differences grow
+EARLY_STEPS = 3
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -369,3 +371,106 @@ def test_incremental_sort_is_the_stable_sort(precision):
             off = sim.sort_offsets(s)
             assert off[-1] == len(order)
             assert np.array_equal(np.diff(off), np.bincount(p1["cell"], minlength=len(off) - 1))
+
+
+def oracle_ulp_sensitivity(desc, steps):
+    """Relative field change of the oracle after `steps` steps when every
+    E node is moved by one ulp after the first step: the size of difference
+    that rounding alone produces in this configuration."""
+    a, b = oracle.Oracle(desc), oracle.Oracle(desc)
+    a.step(1)
+    b.step(1)
+    for c in (oracle.ER, oracle.ETH, oracle.EPH):
+        b.set_field(c, np.nextafter(b.field(c), np.inf))
+    a.step(steps - 1)
+    b.step(steps - 1)
+    return max(rel(b.field(o), a.field(o)) for _, o, _ in FIELDS)
+
+
+def test_injection_matches_oracle_fp64():
+    """Surface pair injection of the hybrid monopole.  The injected pairs of
+    one phase agree with the oracle's (same Philox draws, same positions) and
+    the first steps agree to 1e-12.  Freshly injected pairs are accelerated
+    to gamma ~ 100 within a few steps, which amplifies one-ulp differences
+    (the device exp and sin against the C library's) by about 1.8x per step:
+    after 20 steps the fields are held to ten times the oracle's own change
+    under a one-ulp perturbation, and the particle counts exactly."""
+    w = W.hybrid_monopole(64)
+    sim, ora = pair(w, W.FP64, cap=200_000)
+    sim.run_phases(ffpic.PHASE_MASK | ffpic.PHASE_INJECT)
+    ora.phases(oracle.PHASE_MASK | oracle.PHASE_INJECT)
+    for s in range(2):
+        g, o = sim.particles(s), ora.particles(s)
+        assert len(g["r"]) == len(o["r"]) > 10
+        assert np.array_equal(g["cell"], o["cell"])
+        assert np.array_equal(g["th"], o["th"])
+        for k in ("r", "uph"):
+            assert np.allclose(g[k], o[k], rtol=1e-15, atol=0), k
+    sim2, ora2 = pair(w, W.FP64, cap=200_000)
+    for k in range(EARLY_STEPS):
+        sim2.step(1)
+        ora2.step(1)
+        errs = field_errors(sim2, ora2)
+        assert max(errs.values()) < FP64_TOL, (k + 1, errs)
+    m = moment_errors(sim2, ora2, 2)
+    for k, v in m.items():
+        assert v < (0.5 if k.startswith("n") else FP64_TOL), (k, v)
+    sim2.step(20 - EARLY_STEPS)
+    ora2.step(20 - EARLY_STEPS)
+    sim2.sync()
+    sens = oracle_ulp_sensitivity(sim2.desc, 20)
+    errs = field_errors(sim2, ora2)
+    assert max(errs.values()) < 10 * max(sens, FP64_TOL), (errs, sens)
+    dg = sim2.diagnostics(ffpic.DIAG_MOMENTS)
+    for s in range(2):
+        assert dg["alive"][s] == ora2.moments(s)[0]
+
+
+def field_errors_grouped(sim, ora):
+    """Per-component error normalised by the norm of its field group (E or
+    B) rather than of the component itself."""
+    out = {}
+    for group in (FIELDS[:3], FIELDS[3:]):
+        ref = math.sqrt(sum(np.linalg.norm(ora.field(o)) ** 2 for _, o, _ in group))
+        for g, o, name in group:
+            out[name] = np.linalg.norm(sim.field(g) - ora.field(o)) / ref
+    return out
+
+
+def test_injection_fp32_and_capacity_error():
+    """FP32-mixed hybrid monopole with injection.  E_r, E_phi, B_theta and
+    B_phi start at zero here and are ~1e-5 of the corotation field after a
+    step, so errors are measured against the norm of the field group: the
+    first 5 steps hold 2e-5.  Later the trajectories' sensitivity (see the
+    FP64 test) amplifies FP32 rounding beyond any fixed bar, and 20 steps
+    are held to the particle counts only."""
+    w = W.hybrid_monopole(64, precision=W.FP32_MIXED)
+    sim, ora = pair(w, W.FP32_MIXED, cap=200_000)
+    sim.run_phases(ffpic.PHASE_MASK | ffpic.PHASE_INJECT)
+    ora.phases(oracle.PHASE_MASK | oracle.PHASE_INJECT)
+    for s in range(2):
+        g, o = sim.particles(s), ora.particles(s)
+        assert np.array_equal(g["cell"], o["cell"])
+        for k in ("r", "th"):
+            assert np.allclose(g[k], o[k], rtol=2e-7, atol=0), k
+        assert np.allclose(g["uph"], o["uph"], rtol=2e-7, atol=0)
+    sim, ora = pair(w, W.FP32_MIXED, cap=200_000)
+    for k in range(5):
+        sim.step(1)
+        ora.step(1)
+        errs = field_errors_grouped(sim, ora)
+        assert max(errs.values()) < FP32_TOL, (k + 1, errs)
+    sim.step(15)
+    ora.step(15)
+    sim.sync()
+    dg = sim.diagnostics(ffpic.DIAG_MOMENTS)
+    for s in range(2):
+        n_o = ora.moments(s)[0]
+        assert n_o > 100 and abs(dg["alive"][s] - n_o) <= 0.05 * n_o, (s, dg["alive"][s], n_o)
+    # a capacity too small for one step's injection is reported, not overrun
+    small, _ = pair(w, W.FP32_MIXED, cap=3)
+    small.step(1)
+    with pytest.raises(ffpic.FfpicError) as e:
+        small.sync()
+    assert e.value.code == ffpic.ECAPACITY
+    assert small.n(0) == 0
