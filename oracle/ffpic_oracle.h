@@ -37,6 +37,12 @@
  * than E itself, the absorbing-layer profile, the opened-dipole initial
  * field, and the placement of the radiation-reaction kick after the Boris
  * rotation (its first-order convergence is pinned, its ordering is not).
+ * The paper leaves these choices of the plasma sources open; the pins check
+ * that the code does what the choice says, not the choice itself: the
+ * extraction's top-up rule (all species' charge counted, ceil of the
+ * deficit over a pair's charge), the parent keeping its momentum when it
+ * creates a pair, the shell projection placed after the radiation-reaction
+ * kick, and the knots of the ramp.
  */
 #ifndef FFPIC_ORACLE_H
 #define FFPIC_ORACLE_H

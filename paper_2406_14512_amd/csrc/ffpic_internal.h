@@ -83,6 +83,18 @@ struct ffpic_ctx {
     void *inj_scan_tmp = nullptr;
     size_t inj_scan_bytes = 0;
     int64_t inj_bound = 0;                    // most pairs one step can add
+    // Goldreich-Julian extraction: target charge of each surface cell (FP64,
+    // host-computed), per-species particle counts of the surface cells
+    double *gj_target = nullptr;
+    int32_t *gj_have = nullptr;               // [nspec][nth]
+    int64_t gj_bound = 0;                     // most pairs one step can add
+    // threshold pair creation: per-block parent counts of both parent
+    // species and their exclusive scan
+    int32_t *pair_cnt = nullptr, *pair_off = nullptr;
+    void *pair_scan_tmp = nullptr;
+    size_t pair_scan_bytes = 0;
+    int64_t pair_blocks = 0;                  // capacity of pair_cnt (entries - 1)
+    int32_t *nslots_host = nullptr;           // pinned copy of nslots
     double *psi = nullptr;
     void *f = nullptr;
     uint8_t *kill = nullptr;
@@ -153,7 +165,12 @@ int sort_key_bits(const ffpic_ctx *c);
 void zero_counters(ffpic_ctx *c, int32_t *p, int n);
 int tuned_sort_interval(const ffpic_desc *d);
 void inject_pairs(ffpic_ctx *c);
+void extract_gj(ffpic_ctx *c);
+void create_pairs(ffpic_ctx *c);
 size_t inject_scan_bytes(int nth);
+size_t pair_scan_bytes(int64_t nblk);
+int pair_block_slots();
+double rr_factor(const ffpic_ctx *c);   // radiation-reaction ramp at this step
 
 }  // namespace ffpic
 

@@ -1,7 +1,9 @@
-// Surface pair injection (Sect. 4, monopole test: electron-positron pairs
-// injected with multiplicity kappa_inj in the first layer of cells above the
-// star, in the PIC domain only).
+// Particle sources at the stellar surface: the pair injection of the
+// monopole test (Sect. 4) and the Goldreich-Julian extraction of electrons
+// and ions of the dipole (Sect. 5).
 //
+// Pair injection: electron-positron pairs injected with multiplicity
+// kappa_inj in the first layer of cells above the star, PIC domain only.
 // Every step, surface cell (0, j) outside the pure force-free domain gets
 // floor(N_j) pairs plus one more with probability frac(N_j), where N_j (a
 // host table, FP64) is kappa_inj times the Goldreich-Julian number density
@@ -15,13 +17,20 @@
 // the draws do not depend on the order in which threads run.  The new
 // particles are appended behind the current slots in (cell, draw) order: a
 // per-cell count, an exclusive scan, then one writer per cell.
+//
+// Extraction: the charge held by each surface cell outside the pure
+// force-free domain (every species' weight times its live particles in the
+// cell, species in order) is topped up to gj_extract |rho_GJ| V with
+// ceil(deficit / (w_e + w_i)) electron-ion pairs, placed and appended like
+// the injected pairs (counter word 3 = kExtTag).
 #include <rocprim/device/device_scan.hpp>
 
 #include "device_common.h"
 
 namespace ffpic {
 
-constexpr uint32_t kInjTag = 0x696E6A63u;            // counter word 3 of the draws
+constexpr uint32_t kInjTag = 0x696E6A63u;            // counter word 3 of the injection draws
+constexpr uint32_t kExtTag = 0x676A6578u;            // ... and of the extraction draws
 constexpr double kNear1 = 0.99999994039535522;       // largest float below 1
 
 __device__ __forceinline__ void philox4x32(uint32_t c[4], uint32_t k0, uint32_t k1) {
@@ -65,12 +74,13 @@ struct InjSpecies {
     int64_t cap;
 };
 
+// the species that receive one particle at each drawn position
 struct InjArgs {
     InjSpecies sp[FFPIC_MAX_SPECIES];
     int nspec, nth, nr;
     double rn0, dlog, dth, omega;
     const double *thn;
-    uint32_t step, k0, k1;
+    uint32_t step, k0, k1, tag;
 };
 
 // all species fit, else nothing is injected this step
@@ -88,7 +98,7 @@ __global__ void k_inject_write(const int32_t *__restrict__ cnt, const int32_t *_
     const int n = cnt[j];
     if (n == 0 || !inject_fits(A, off[A.nth])) return;
     for (int p = 0; p < n; p++) {
-        uint32_t c[4] = {A.step, (uint32_t)j, (uint32_t)(p + 1), kInjTag};
+        uint32_t c[4] = {A.step, (uint32_t)j, (uint32_t)(p + 1), A.tag};
         philox4x32(c, A.k0, A.k1);
         const double a = u01(c[0]), b = u01(c[1]);
         const double r = A.rn0 * exp(a * A.dlog);
@@ -143,36 +153,43 @@ size_t inject_scan_bytes(int nth) {
     return bytes;
 }
 
-void inject_pairs(ffpic_ctx *c) {
-    if (!(c->d.inject_kappa > 0.0) || c->d.nspec == 0) return;
-    const int nth = c->nth;
-    const uint32_t k0 = (uint32_t)c->d.rng_seed, k1 = (uint32_t)(c->d.rng_seed >> 32);
-    const uint32_t step = (uint32_t)c->step;
-    const int nb = (nth + 1 + 255) / 256;
-    hipLaunchKernelGGL(k_inject_count, dim3(nb), dim3(256), 0, c->stream, nth, c->kill,
-                       c->inj_rate, step, k0, k1, c->inj_cnt);
-    size_t bytes = c->inj_scan_bytes;
-    if (rocprim::exclusive_scan(c->inj_scan_tmp, bytes, c->inj_cnt, c->inj_off, 0,
-                                (size_t)nth + 1, rocprim::plus<int32_t>(),
-                                c->stream) != hipSuccess)
-        throw std::runtime_error("rocprim scan failed");
+namespace {
+
+InjArgs inj_args(ffpic_ctx *c, const int *targets, int ntargets, uint32_t tag) {
     InjArgs A{};
-    A.nspec = c->d.nspec;
-    A.nth = nth;
+    A.nspec = ntargets;
+    A.nth = c->nth;
     A.nr = c->nr;
     A.rn0 = c->tab[T_RN][0];
     A.dlog = c->dlog;
     A.dth = c->dth;
     A.omega = c->omega;
     A.thn = c->dtab64[T_THN];
-    A.step = step;
-    A.k0 = k0;
-    A.k1 = k1;
-    for (int s = 0; s < c->d.nspec; s++) {
-        for (int a = 0; a < c->sp[s].narr; a++) A.sp[s].arr[a] = c->sp[s].cur[a];
-        A.sp[s].nslots = c->nslots + s;
-        A.sp[s].cap = c->sp[s].cap;
+    A.step = (uint32_t)c->step;
+    A.k0 = (uint32_t)c->d.rng_seed;
+    A.k1 = (uint32_t)(c->d.rng_seed >> 32);
+    A.tag = tag;
+    for (int t = 0; t < ntargets; t++) {
+        const int s = targets[t];
+        for (int a = 0; a < c->sp[s].narr; a++) A.sp[t].arr[a] = c->sp[s].cur[a];
+        A.sp[t].nslots = c->nslots + s;
+        A.sp[t].cap = c->sp[s].cap;
     }
+    return A;
+}
+
+// scan of the per-cell counts in c->inj_cnt, then the ordered append and
+// the commit (or the capacity error)
+void append_surface(ffpic_ctx *c, const int *targets, int ntargets, uint32_t tag,
+                    int64_t bound) {
+    const InjArgs A = inj_args(c, targets, ntargets, tag);
+    const int nth = c->nth;
+    const int nb = (nth + 1 + 255) / 256;
+    size_t bytes = c->inj_scan_bytes;
+    if (rocprim::exclusive_scan(c->inj_scan_tmp, bytes, c->inj_cnt, c->inj_off, 0,
+                                (size_t)nth + 1, rocprim::plus<int32_t>(),
+                                c->stream) != hipSuccess)
+        throw std::runtime_error("rocprim scan failed");
     if (c->fp64)
         hipLaunchKernelGGL(k_inject_write<true>, dim3(nb), dim3(256), 0, c->stream, c->inj_cnt,
                            c->inj_off, A);
@@ -182,8 +199,93 @@ void inject_pairs(ffpic_ctx *c) {
     hipLaunchKernelGGL(k_inject_commit, dim3(1), dim3(1), 0, c->stream, c->inj_off, A, c->err);
     FFPIC_LAUNCH_CHECK();
     // host upper bound of the slots in use
-    for (int s = 0; s < c->d.nspec; s++)
-        c->sp[s].nub = std::min<int64_t>(c->sp[s].nub + c->inj_bound, c->sp[s].cap);
+    for (int t = 0; t < ntargets; t++) {
+        ffpic::Species &S = c->sp[targets[t]];
+        S.nub = std::min<int64_t>(S.nub + bound, S.cap);
+    }
+}
+
+// live particles of one species in each surface cell (i = 0)
+template <bool FP64>
+__global__ void k_surface_count(int nub, const int32_t *__restrict__ nslots, int nr, int nth,
+                                double rmin, double dlog, double dth,
+                                const double *__restrict__ rn, const double *__restrict__ thn,
+                                const void *__restrict__ a0, const void *__restrict__ a1,
+                                int32_t *__restrict__ have) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nub || q >= nslots[0]) return;
+    if (FP64) {
+        const double r = ((const double *)a0)[q];
+        if (!(r > 0.0) || !(r < rn[1])) return;
+        int i, j;
+        double a, b;
+        locate64(nr, nth, rmin, dlog, dth, rn, thn, r, ((const double *)a1)[q], i, j, a, b);
+        if (i == 0) atomicAdd(&have[j], 1);
+    } else {
+        const int cell = ((const int32_t *)a0)[q];
+        if (cell >= 0 && (cell >> 16) == 0) atomicAdd(&have[cell & 0xffff], 1);
+    }
+}
+
+struct ExtArgs {
+    double w[FFPIC_MAX_SPECIES];
+    double wpair;
+    int nspec, nth;
+};
+
+// pairs to extract per surface cell (cnt[nth] = 0 for the scan's total)
+__global__ void k_extract_count(ExtArgs X, const uint8_t *__restrict__ kill,
+                                const double *__restrict__ target,
+                                const int32_t *__restrict__ have, int32_t *__restrict__ cnt) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j > X.nth) return;
+    int n = 0;
+    if (j < X.nth && !kill[j]) {
+        double held = 0.0;
+        for (int s = 0; s < X.nspec; s++) held += X.w[s] * (double)have[s * X.nth + j];
+        const double deficit = target[j] - held;
+        if (deficit > 0.0) n = (int)ceil(deficit / X.wpair);
+    }
+    cnt[j] = n;
+}
+
+}  // namespace
+
+void inject_pairs(ffpic_ctx *c) {
+    if (!(c->d.inject_kappa > 0.0) || c->d.nspec == 0) return;
+    const int nth = c->nth;
+    const uint32_t k0 = (uint32_t)c->d.rng_seed, k1 = (uint32_t)(c->d.rng_seed >> 32);
+    const uint32_t step = (uint32_t)c->step;
+    const int nb = (nth + 1 + 255) / 256;
+    hipLaunchKernelGGL(k_inject_count, dim3(nb), dim3(256), 0, c->stream, nth, c->kill,
+                       c->inj_rate, step, k0, k1, c->inj_cnt);
+    int all[FFPIC_MAX_SPECIES];
+    for (int s = 0; s < c->d.nspec; s++) all[s] = s;
+    append_surface(c, all, c->d.nspec, kInjTag, c->inj_bound);
+}
+
+void extract_gj(ffpic_ctx *c) {
+    if (!(c->d.gj_extract > 0.0)) return;
+    const int nth = c->nth, ns = c->d.nspec;
+    zero_counters(c, c->gj_have, ns * nth);
+    for (int s = 0; s < ns; s++) {
+        const ffpic::Species &S = c->sp[s];
+        if (S.nub == 0) continue;
+        const int nbs = (int)((S.nub + 255) / 256);
+        hipLaunchKernelGGL(c->fp64 ? k_surface_count<true> : k_surface_count<false>, dim3(nbs),
+                           dim3(256), 0, c->stream, (int)S.nub, c->nslots + s, c->nr, nth,
+                           c->d.rmin, c->dlog, c->dth, c->dtab64[T_RN], c->dtab64[T_THN],
+                           S.cur[0], S.cur[1], c->gj_have + (size_t)s * nth);
+    }
+    ExtArgs X{};
+    for (int s = 0; s < ns; s++) X.w[s] = c->d.weight[s];
+    X.wpair = c->d.weight[c->d.gj_species[0]] + c->d.weight[c->d.gj_species[1]];
+    X.nspec = ns;
+    X.nth = nth;
+    hipLaunchKernelGGL(k_extract_count, dim3((nth + 1 + 255) / 256), dim3(256), 0, c->stream, X,
+                       c->kill, c->gj_target, c->gj_have, c->inj_cnt);
+    FFPIC_LAUNCH_CHECK();
+    append_surface(c, c->d.gj_species, 2, kExtTag, c->gj_bound);
 }
 
 }  // namespace ffpic

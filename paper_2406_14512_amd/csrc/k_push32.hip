@@ -50,6 +50,8 @@ struct P32 {
     float aabs;                          // ... at offset aabs
     const float *rn, *sn, *cn;
     float Q, h, kk;                      // charge, dt omega_b qm / 2, dt K_s
+    int ishell;                          // the shell of kept momentum along B ends in
+    float ashell;                        // radial cell ishell at offset ashell
 };
 
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -123,7 +125,7 @@ __device__ __forceinline__ float bil(__amdgpu_buffer_rsrc_t R, unsigned o0, unsi
     return lo + wr * (hi - lo);
 }
 
-template <bool LDS>
+template <bool LDS, bool SHELL>
 __device__ __forceinline__ void push_chunk(const P32 &p, const Fields &F, const Acc<LDS> &acc,
                                            const int *cell, int base, int tid, int lane,
                                            const uint8_t *__restrict__ kill, const State &S,
@@ -228,6 +230,14 @@ __device__ __forceinline__ void push_chunk(const P32 &p, const Fields &F, const 
                 nr += kk * ((Fy * bsp - Fz * bst) + be * esr - gg * bx);
                 nt += kk * ((Fz * bsr - Fx * bsp) + be * est - gg * by);
                 np += kk * ((Fx * bst - Fy * bsr) + be * esp - gg * bz);
+            }
+            if (SHELL && (i < p.ishell || (i == p.ishell && a < p.ashell))) {
+                // shell around the star (Sect. 5): drop the momentum across B
+                const float b2 = bsr * bsr + bst * bst + bsp * bsp;
+                if (b2 > 0.f) {
+                    const float ub = (nr * bsr + nt * bst + np * bsp) / b2;
+                    nr = ub * bsr; nt = ub * bst; np = ub * bsp;
+                }
             }
             const float ivg = frsq(1.f + nr * nr + nt * nt + np * np);   // 1 / gamma
             const float vdt = p.dt * ivg;
@@ -392,6 +402,7 @@ __device__ __forceinline__ void push_chunk(const P32 &p, const Fields &F, const 
     }
 }
 
+template <bool SHELL>
 __global__ void __launch_bounds__(kWG) k_push32(
     P32 p, int nub, const int32_t *__restrict__ nslots, const uint8_t *__restrict__ kill,
     const float *__restrict__ Er, const float *__restrict__ Et, const float *__restrict__ Ep,
@@ -465,7 +476,8 @@ __global__ void __launch_bounds__(kWG) k_push32(
         }
         __syncthreads();
         Acc<true> acc{tile, ti0, tj0, TJ, {Jr, Jt, Jp}, p.ld};
-        push_chunk<true>(p, F, acc, cell, base, tid, lane, kill, S, err, nkill, nstar, nabs);
+        push_chunk<true, SHELL>(p, F, acc, cell, base, tid, lane, kill, S, err, nkill, nstar,
+                                nabs);
         __syncthreads();
         for (int e = tid; e < m; e += kWG) {
             const int ti = e / TJ, tj = e - ti * TJ;
@@ -479,7 +491,8 @@ __global__ void __launch_bounds__(kWG) k_push32(
         }
     } else {
         Acc<false> acc{nullptr, 0, 0, 0, {Jr, Jt, Jp}, p.ld};
-        push_chunk<false>(p, F, acc, cell, base, tid, lane, kill, S, err, nkill, nstar, nabs);
+        push_chunk<false, SHELL>(p, F, acc, cell, base, tid, lane, kill, S, err, nkill, nstar,
+                                 nabs);
     }
     int tk = nkill, ts = nstar, ta = nabs;
     for (int o = 32; o >= 1; o >>= 1) {
@@ -511,10 +524,16 @@ void push32(ffpic_ctx *c, int s) {
     double qm = S.qm;
     p.Q = (float)((qm > 0 ? 1.0 : -1.0) * S.weight);
     p.h = (float)(0.5 * c->dt * c->d.omega_b * qm);
-    p.kk = (float)(c->dt * c->d.rr_coef * fabs(qm) * fabs(qm) * fabs(qm));
+    p.kk = (float)(c->dt * c->d.rr_coef * rr_factor(c) * fabs(qm) * fabs(qm) * fabs(qm));
+    // the shell radius in cell units, split like r_abs
+    const bool shell = c->d.shell_r > c->d.rmin;
+    const double xs = shell ? log(c->d.shell_r / c->d.rmin) / c->dlog : 0.0;
+    p.ishell = (int)floor(xs);
+    p.ashell = (float)(xs - floor(xs));
     float **E = (float **)c->E, **B = (float **)c->B, **J = (float **)c->J;
     int nb = (int)((S.nub + kChunk - 1) / kChunk);
-    hipLaunchKernelGGL(k_push32, dim3(nb), dim3(kWG), 0, c->stream, p, (int)S.nub,
+    auto kern = shell ? k_push32<true> : k_push32<false>;
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(kWG), 0, c->stream, p, (int)S.nub,
                        c->nslots + s, c->kill, E[0], E[1], E[2], B[0], B[1], B[2],
                        (int32_t *)S.cur[0], (float *)S.cur[1], (float *)S.cur[2],
                        (float *)S.cur[3], (float *)S.cur[4], (float *)S.cur[5], J[0], J[1], J[2],

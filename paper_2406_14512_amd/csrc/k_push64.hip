@@ -8,7 +8,9 @@
 //
 // Push (Sect. 3): eq. (motion) integrated with the Boris rotation; the
 // Landau-Lifshitz force g with the effective field of eq. (bperp) is added
-// explicitly with the time-centred velocity.  The particle is moved in the
+// explicitly with the time-centred velocity (its strength scaled by the
+// ramp of Sect. 5); inside the shell around the star only the momentum
+// along B is kept.  The particle is moved in the
 // local Cartesian frame at azimuth 0 and rotated back to the meridional
 // plane.  Deposit: zigzag (relay-point) split of the move in logical
 // coordinates (log r / dlog, theta / dtheta), charge fluxes through the dual
@@ -28,6 +30,7 @@ struct P64 {
     double rmin, r_abs, dlog, dth, dt;
     const double *rn, *thn;
     double Q, wq, rr;
+    double shell_r;        // r below this: only the momentum along B is kept
 };
 
 struct Lin {
@@ -204,6 +207,14 @@ __global__ void __launch_bounds__(256) k_push64(
         double ur = UR[q], ut = UT[q], up = UP[q];
         double u[3] = {ur * st + ut * ct, up, ur * ct - ut * st};
         boris_rr(u, E, B, p.dt, p.wq, p.rr);
+        if (r < p.shell_r) {
+            // shell around the star (Sect. 5): drop the momentum across B
+            const double b2 = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
+            if (b2 > 0.0) {
+                const double ub = (u[0] * B[0] + u[1] * B[1] + u[2] * B[2]) / b2;
+                u[0] = ub * B[0]; u[1] = ub * B[1]; u[2] = ub * B[2];
+            }
+        }
         double g = sqrt(1.0 + (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]));
         if (!isfinite(g)) atomicOr(err, FFPIC_ERR_NONFINITE);
         double v0 = u[0] / g, vv2 = u[2] / g;
@@ -363,7 +374,8 @@ void push64(ffpic_ctx *c, int s) {
     double qm = S.qm;
     p.Q = (qm > 0 ? 1.0 : -1.0) * S.weight;
     p.wq = c->d.omega_b * qm;
-    p.rr = c->d.rr_coef * fabs(qm) * fabs(qm) * fabs(qm);
+    p.rr = c->d.rr_coef * rr_factor(c) * fabs(qm) * fabs(qm) * fabs(qm);
+    p.shell_r = c->d.shell_r;
     double **E = (double **)c->E, **B = (double **)c->B, **J = (double **)c->J;
     double **a = (double **)S.cur;
     int nb = (int)((S.nub + 255) / 256);

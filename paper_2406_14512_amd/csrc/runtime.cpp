@@ -348,6 +348,8 @@ void free_all(ffpic_ctx *c) {
         for (int k = 0; k < 2; k++) { F(c->skey[s][k]); F(c->soff[s][k]); }
     F(c->sort_sb); F(c->sort_blk); F(c->sort_aux); F(c->sort_moff); F(c->sort_tot); F(c->scan_tmp);
     F(c->inj_rate); F(c->inj_cnt); F(c->inj_off); F(c->inj_scan_tmp); F(c->nsorted);
+    F(c->gj_target); F(c->gj_have); F(c->pair_cnt); F(c->pair_off); F(c->pair_scan_tmp);
+    if (c->nslots_host) (void)hipHostFree(c->nslots_host);
     F(c->sort_tmp); F(c->nslots); F(c->nalive); F(c->removed); F(c->err); F(c->red);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
@@ -355,33 +357,73 @@ void free_all(ffpic_ctx *c) {
     c->evpool.clear();
 }
 
-// expected pairs per step of each surface cell (0, j) from the surface B_r
-// (FP64, the same operation order as the oracle's definition):
-// kappa_inj |rho_GJ| / q * V * dt / dr0 with |rho_GJ| = Omega |B_r| / 2 pi
-void inject_table(ffpic_ctx *c, const double *br_surface) {
+// Tables of the surface sources from the surface B_r (FP64, the same
+// operation order as the oracle's definitions), V the volume of surface cell
+// (0, j) per radian of azimuth and |rho_GJ| = Omega |B_r| / 2 pi:
+//   pairs injected per step: kappa_inj |rho_GJ| / q * V * dt / dr0;
+//   charge kept by the extraction: gj_extract |rho_GJ| V.
+void surface_tables(ffpic_ctx *c, const double *br_surface) {
 #pragma clang fp contract(off)
-    if (!(c->d.inject_kappa > 0.0) || c->d.nspec == 0) return;
+    const bool inj = c->d.inject_kappa > 0.0 && c->d.nspec > 0;
+    const bool ext = c->d.gj_extract > 0.0;
+    if (!inj && !ext) return;
     const int nth = c->nth;
     const std::vector<double> &rn = c->tab[T_RN], &cn = c->tab[T_CN];
-    std::vector<double> rate(nth);
-    int64_t bound = 0;
+    std::vector<double> rate(nth), target(nth);
+    int64_t ibound = 0, ebound = 0;
+    const double wpair = ext ? c->d.weight[c->d.gj_species[0]] + c->d.weight[c->d.gj_species[1]]
+                             : 1.0;
     for (int j = 0; j < nth; j++) {
         const double br = std::fabs(br_surface[j]);
-        const double q = c->d.weight[0];
         const double vol = (rn[1] * rn[1] * rn[1] - rn[0] * rn[0] * rn[0]) / 3.0 * (cn[j] - cn[j + 1]);
-        rate[j] = c->d.inject_kappa * (c->omega * br / (2.0 * kPi)) / q * vol *
-                  (c->dt / (rn[1] - rn[0]));
-        bound += (int64_t)std::ceil(rate[j]);
+        if (inj) {
+            const double q = c->d.weight[0];
+            rate[j] = c->d.inject_kappa * (c->omega * br / (2.0 * kPi)) / q * vol *
+                      (c->dt / (rn[1] - rn[0]));
+            ibound += (int64_t)std::ceil(rate[j]);
+        }
+        if (ext) {
+            target[j] = c->d.gj_extract * (c->omega * br / (2.0 * kPi)) * vol;
+            ebound += (int64_t)std::ceil(target[j] / wpair);
+        }
     }
-    if (!c->inj_rate) {
-        c->inj_rate = (double *)dmalloc((size_t)nth * sizeof(double));
+    if (!c->inj_cnt) {
         c->inj_cnt = (int32_t *)dmalloc((size_t)(nth + 1) * sizeof(int32_t));
         c->inj_off = (int32_t *)dmalloc((size_t)(nth + 1) * sizeof(int32_t));
         c->inj_scan_bytes = inject_scan_bytes(nth);
         c->inj_scan_tmp = dmalloc(c->inj_scan_bytes);
     }
-    HCHK(hipMemcpy(c->inj_rate, rate.data(), (size_t)nth * sizeof(double), hipMemcpyHostToDevice));
-    c->inj_bound = bound;
+    if (inj) {
+        if (!c->inj_rate) c->inj_rate = (double *)dmalloc((size_t)nth * sizeof(double));
+        HCHK(hipMemcpy(c->inj_rate, rate.data(), (size_t)nth * sizeof(double), hipMemcpyHostToDevice));
+        c->inj_bound = ibound;
+    }
+    if (ext) {
+        if (!c->gj_target) {
+            c->gj_target = (double *)dmalloc((size_t)nth * sizeof(double));
+            c->gj_have = (int32_t *)dmalloc((size_t)c->d.nspec * nth * sizeof(int32_t));
+        }
+        HCHK(hipMemcpy(c->gj_target, target.data(), (size_t)nth * sizeof(double),
+                       hipMemcpyHostToDevice));
+        c->gj_bound = ebound;
+    }
+}
+
+// radiation-reaction ramp at t = step * dt: piecewise linear through the
+// knots, flat outside them (the same operation order as the oracle's)
+double rr_factor_at(const ffpic_desc &d, double t) {
+#pragma clang fp contract(off)
+    const int n = d.rr_ramp_n;
+    if (n <= 0) return 1.0;
+    if (t <= d.rr_ramp_t[0]) return d.rr_ramp_f[0];
+    for (int k = 1; k < n; k++) {
+        if (t < d.rr_ramp_t[k]) {
+            const double t0 = d.rr_ramp_t[k - 1], t1 = d.rr_ramp_t[k];
+            const double x = (t - t0) / (t1 - t0);
+            return d.rr_ramp_f[k - 1] + x * (d.rr_ramp_f[k] - d.rr_ramp_f[k - 1]);
+        }
+    }
+    return d.rr_ramp_f[n - 1];
 }
 
 void check_ctx(ffpic_ctx *c) {
@@ -414,18 +456,22 @@ void one_step(ffpic_ctx *c, uint32_t ph, bool count_step, int tslot) {
         if (ph & FFPIC_PHASE_SORT) sort_species(c, s);
         else if (ph & FFPIC_PHASE_KILL) kill_species(c, s);
     }
-    if ((ph & FFPIC_PHASE_SORT) && c->d.inject_kappa > 0.0 && c->d.nspec > 0) {
-        // injection only grows the host bound of the slots: reset it to the
-        // sorted count
+    const bool sources = (c->d.inject_kappa > 0.0 || c->d.gj_extract > 0.0 ||
+                          c->d.gamma_th > 0.0) && c->d.nspec > 0;
+    if ((ph & FFPIC_PHASE_SORT) && sources) {
+        // the sources only grow the host bound of the slots: reset it to
+        // the sorted count
         int32_t ns[FFPIC_MAX_SPECIES] = {};
         HCHK(hipMemcpyAsync(ns, c->nslots, sizeof(ns), hipMemcpyDeviceToHost, c->stream));
         HCHK(hipStreamSynchronize(c->stream));
         for (int s = 0; s < c->d.nspec; s++) c->sp[s].nub = ns[s];
     }
     if (ph & FFPIC_PHASE_INJECT) inject_pairs(c);
+    if (ph & FFPIC_PHASE_EXTRACT) extract_gj(c);
     mark(2);
     if (ph & FFPIC_PHASE_PUSH)
         for (int s = 0; s < c->d.nspec; s++) push_species(c, s);
+    if (ph & FFPIC_PHASE_PAIRS) create_pairs(c);
     mark(3);
     if (ph & FFPIC_PHASE_FIELDS) field_step(c);
     mark(4);
@@ -528,6 +574,17 @@ int ffpic_create(const ffpic_desc *d, void *stream, ffpic_ctx **out) {
                     c->soff[s][k] = (int32_t *)dmalloc(nk1 * 4);
                 }
         }
+        if (d->gamma_th > 0.0) {
+            const int64_t per = (maxcap + pair_block_slots() - 1) / pair_block_slots();
+            c->pair_blocks = 2 * per;
+            c->pair_cnt = (int32_t *)dmalloc((size_t)(c->pair_blocks + 1) * sizeof(int32_t));
+            c->pair_off = (int32_t *)dmalloc((size_t)(c->pair_blocks + 1) * sizeof(int32_t));
+            c->pair_scan_bytes = pair_scan_bytes(c->pair_blocks);
+            c->pair_scan_tmp = dmalloc(c->pair_scan_bytes);
+            void *h = nullptr;
+            HCHK(hipHostMalloc(&h, FFPIC_MAX_SPECIES * sizeof(int32_t), hipHostMallocDefault));
+            c->nslots_host = (int32_t *)h;
+        }
         c->nslots = (int32_t *)dmalloc(FFPIC_MAX_SPECIES * sizeof(int32_t));
         c->nalive = (int32_t *)dmalloc(FFPIC_MAX_SPECIES * sizeof(int32_t));
         c->nsorted = (int32_t *)dmalloc(FFPIC_MAX_SPECIES * sizeof(int32_t));
@@ -543,7 +600,7 @@ int ffpic_create(const ffpic_desc *d, void *stream, ffpic_ctx **out) {
         for (auto &e : c->ev) HCHK(hipEventCreate(&e));
         std::vector<double> F[6];
         init_fields_host(c, F);
-        inject_table(c, F[3].data());   // row 0 of B_r: the stellar surface
+        surface_tables(c, F[3].data());   // row 0 of B_r: the stellar surface
         for (int k = 0; k < 3; k++) {
             upload_field(c, c->E[k], F[k]);
             upload_field(c, c->B[k], F[3 + k]);
@@ -612,7 +669,7 @@ int ffpic_load_fields(ffpic_ctx *c, int comp, const double *src, int on_dev) {
                 HCHK(hipMemcpyAsync(row.data(), dsrc, (size_t)c->nth * sizeof(double),
                                     hipMemcpyDeviceToHost, c->stream));
                 HCHK(hipStreamSynchronize(c->stream));
-                inject_table(c, row.data());
+                surface_tables(c, row.data());
             }
         }
         if (!c->fp64) {
@@ -682,7 +739,8 @@ int ffpic_step(ffpic_ctx *c, int32_t nsteps) {
         }
         for (int k = 0; k < nsteps; k++) {
             uint32_t ph = FFPIC_PHASE_MASK | FFPIC_PHASE_KILL | FFPIC_PHASE_INJECT |
-                          FFPIC_PHASE_PUSH | FFPIC_PHASE_FIELDS;
+                          FFPIC_PHASE_EXTRACT | FFPIC_PHASE_PUSH | FFPIC_PHASE_PAIRS |
+                          FFPIC_PHASE_FIELDS;
             if (c->step % c->d.sort_interval == 0) ph |= FFPIC_PHASE_SORT;
             // the push removes particles of force-free cells itself
             if (!(ph & FFPIC_PHASE_SORT)) ph &= ~FFPIC_PHASE_KILL;
@@ -988,3 +1046,12 @@ int ffpic_phase_times(ffpic_ctx *c, float out[4]) {
 }
 
 }  // extern "C"
+
+namespace ffpic {
+
+double rr_factor(const ffpic_ctx *c) {
+#pragma clang fp contract(off)
+    return rr_factor_at(c->d, (double)c->step * c->dt);
+}
+
+}  // namespace ffpic
