@@ -49,6 +49,13 @@ class _Params(C.Structure):
                 ("pair_species", C.c_int * 2)]
 
 
+class _SpecReq(C.Structure):
+    _fields_ = [("rmin", C.c_double), ("rmax", C.c_double), ("thmin", C.c_double),
+                ("thmax", C.c_double), ("gmin", C.c_double), ("gmax", C.c_double),
+                ("numin", C.c_double), ("numax", C.c_double),
+                ("ngamma", C.c_int), ("nnu", C.c_int)]
+
+
 _lib = None
 
 
@@ -99,6 +106,9 @@ def lib():
         L.ora_inject_rate.argtypes = [P, C.c_int]
         L.ora_gj_target.restype = C.c_double
         L.ora_gj_target.argtypes = [P, C.c_int]
+        L.ora_spectra.argtypes = [P, C.c_int, C.POINTER(_SpecReq), dp, dp, dp]
+        L.ora_synchrotron_F.restype = C.c_double
+        L.ora_synchrotron_F.argtypes = [C.c_double]
         L.ora_rr_factor.restype = C.c_double
         L.ora_rr_factor.argtypes = [C.POINTER(_Params), C.c_double]
         _lib = L
@@ -239,6 +249,14 @@ class Oracle:
     def inject_rate(self, j: int) -> float:
         return float(lib().ora_inject_rate(self._h, int(j)))
 
+    def spectra(self, sp: int, req: dict) -> dict:
+        """gamma histogram dN, radiated power prad and synchrotron SED of one
+        species over a region; req keys as in spec_request()."""
+        q = spec_request(req)
+        dN, sed, prad = np.zeros(q.ngamma), np.zeros(q.nnu), np.zeros(1)
+        lib().ora_spectra(self._h, int(sp), C.byref(q), dN, sed, prad)
+        return {"dN": dN, "sed": sed, "prad": float(prad[0])}
+
     def gj_target(self, j: int) -> float:
         return float(lib().ora_gj_target(self._h, int(j)))
 
@@ -264,6 +282,18 @@ def boris_rr(u, E, B, dt, wq, rr=0.0):
     lib().ora_boris_rr(uu, np.asarray(E, dtype=np.float64), np.asarray(B, dtype=np.float64),
                        float(dt), float(wq), float(rr))
     return uu
+
+
+def spec_request(req: dict) -> _SpecReq:
+    q = _SpecReq()
+    for k in ("rmin", "rmax", "thmin", "thmax", "gmin", "gmax", "numin", "numax"):
+        setattr(q, k, float(req[k]))
+    q.ngamma, q.nnu = int(req["ngamma"]), int(req["nnu"])
+    return q
+
+
+def synchrotron_F(x: float) -> float:
+    return float(lib().ora_synchrotron_F(float(x)))
 
 
 def rr_factor(desc: dict, t: float) -> float:

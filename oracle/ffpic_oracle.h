@@ -119,6 +119,18 @@ void ora_divb(const ora_sim *s, double *d);       /* primal-cell map */
 void ora_node_charge(const ora_sim *s, double *q);/* sum Q S S per node */
 void ora_poynting(const ora_sim *s, double *L);   /* nr+1 radii */
 void ora_sort_offsets(const ora_sim *s, int sp, int32_t *off);
+/* species spectra over a region: gamma histogram, radiated power and the
+   synchrotron SED (see the definition in the source) */
+typedef struct {
+    double rmin, rmax, thmin, thmax;   /* region: rmin <= r < rmax, thmin <= theta < thmax */
+    double gmin, gmax;                 /* ngamma log-spaced gamma bins */
+    double numin, numax;               /* nnu log-spaced frequencies (code units) */
+    int ngamma, nnu;
+} ora_spec_req;
+void ora_spectra(const ora_sim *s, int sp, const ora_spec_req *req, double *dN,
+                 double *sed, double *prad);
+/* synchrotron function x int_x^inf K_{5/3} */
+double ora_synchrotron_F(double x);
 
 /* pieces exported for the closed-form pins */
 void ora_boris_rr(double u[3], const double E[3], const double B[3],

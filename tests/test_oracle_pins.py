@@ -798,3 +798,91 @@ def test_sourced_dipole_keeps_gauss_in_pic_domain():
     drho = np.abs(4 * math.pi * (q1 - q0) / vstar * deep).max()
     assert drho > 0
     assert np.abs((g1 - g0) * deep).max() < 1e-12 * drho
+
+
+# ---------------------------------------------------------------------------
+# Spectra and synchrotron emission (Sect. 5 observables)
+
+def test_synchrotron_function_known_properties():
+    """F(x) = x int_x^inf K_5/3: its integral 8 pi / (9 sqrt 3), the
+    small-argument law 4 pi / (sqrt(3) Gamma(1/3)) (x/2)^(1/3), the
+    large-argument series sqrt(pi x / 2) e^-x (1 + 55/(72x) - 10151/(10368x^2)),
+    and the textbook peak 0.918 near x = 0.29."""
+    F = oracle.synchrotron_F
+    xs = np.exp(np.linspace(math.log(1e-9), math.log(200.0), 4000))
+    fs = np.array([F(x) for x in xs])
+    assert np.trapezoid(fs * xs, np.log(xs)) == pytest.approx(8 * math.pi / (9 * math.sqrt(3)),
+                                                               rel=1e-9)
+    A = 4 * math.pi / (math.sqrt(3) * math.gamma(1 / 3)) * 2 ** (-1 / 3)
+    for x in (1e-8, 1e-6, 1e-4):
+        assert abs(F(x) / (A * x ** (1 / 3)) - 1) < 2 * x ** (2 / 3)
+    for x in (20.0, 30.0, 50.0):
+        series = math.sqrt(math.pi * x / 2) * math.exp(-x) * (1 + 55 / (72 * x) -
+                                                             10151 / (10368 * x * x))
+        assert abs(F(x) / series - 1) < 5 / x ** 3
+    k = int(np.argmax(fs))
+    assert fs[k] == pytest.approx(0.918, abs=1e-3) and xs[k] == pytest.approx(0.286, abs=0.01)
+
+
+def _spectra_setup(us, rs, ths, rr=2.0):
+    d = desc(init=W.INIT_MONOPOLE, nspec=1, qm=(-1.0,), weight=(3e-5,), rr_coef=rr,
+             omega_b=80.0)
+    o = oracle.Oracle(d)
+    for c in (oracle.ER, oracle.ETH, oracle.EPH):
+        o.set_field(c, np.zeros(o.shape))
+    us = np.asarray(us, dtype=np.float64)
+    o.load(0, dict(r=np.asarray(rs, dtype=np.float64), th=np.asarray(ths, dtype=np.float64),
+                   ur=us[:, 0], uth=us[:, 1], uph=us[:, 2]))
+    return d, o
+
+
+def test_spectra_histogram_and_region():
+    """Particles of known Lorentz factor land in the log bin that contains
+    it (edges gmin (gmax/gmin)^(m/n)); the region excludes the others."""
+    gam = np.array([1.5, 3.0, 9.9, 10.1, 55.0, 99.0, 150.0, 2.0])
+    u = np.sqrt(gam ** 2 - 1)
+    us = np.stack([np.zeros_like(u), u, np.zeros_like(u)], 1)
+    rs = np.array([3.0, 3.2, 3.4, 3.6, 3.8, 4.0, 4.2, 7.0])
+    ths = np.full(8, 1.0)
+    d, o = _spectra_setup(us, rs, ths)
+    req = dict(rmin=2.0, rmax=6.0, thmin=0.0, thmax=math.pi, gmin=1.0, gmax=100.0,
+               numin=1.0, numax=10.0, ngamma=4, nnu=2)
+    sp = o.spectra(0, req)
+    w = d["weight"][0]
+    # decades [1, 3.16), [3.16, 10), [10, 31.6), [31.6, 100); 150 out, r = 7 out
+    assert np.allclose(sp["dN"], np.array([2, 1, 1, 2]) * w, rtol=1e-15)
+
+
+def test_radiated_power_gyration_closed_form():
+    """E = 0 and u across B: Bperp = |beta x B| = beta |B|, so each particle
+    radiates K (gamma^2 - 1) |B|^2 with B the field at its position."""
+    gam = np.array([5.0, 20.0, 80.0])
+    rs = np.array([2.5, 3.5, 5.0])
+    ths = np.array([0.7, 1.4, 2.2])
+    # monopole field is radial: momentum along theta and phi is across it
+    u = np.sqrt(gam ** 2 - 1)
+    us = np.stack([np.zeros(3), u * 0.6, u * 0.8], 1)
+    d, o = _spectra_setup(us, rs, ths)
+    req = dict(rmin=1.0, rmax=10.0, thmin=0.0, thmax=math.pi, gmin=1.0, gmax=100.0,
+               numin=1.0, numax=10.0, ngamma=2, nnu=2)
+    got = o.spectra(0, req)["prad"]
+    want = 0.0
+    for k in range(3):
+        _, B = o.gather(rs[k], ths[k])
+        want += d["weight"][0] * d["rr_coef"] * (gam[k] ** 2 - 1) * float(B @ B)
+    assert got == pytest.approx(want, rel=1e-13)
+
+
+def test_sed_integrates_to_radiated_power():
+    """Summed over all frequencies (trapezoid in log nu on a grid wide enough
+    to hold the whole spectrum) the SED returns the radiated power."""
+    gam = np.array([5.0, 20.0, 80.0])
+    u = np.sqrt(gam ** 2 - 1)
+    us = np.stack([np.zeros(3), u * 0.6, u * 0.8], 1)
+    d, o = _spectra_setup(us, [2.5, 3.5, 5.0], [0.7, 1.4, 2.2])
+    req = dict(rmin=1.0, rmax=10.0, thmin=0.0, thmax=math.pi, gmin=1.0, gmax=100.0,
+               numin=1e-4, numax=1e8, ngamma=2, nnu=600)
+    sp = o.spectra(0, req)
+    nu = req["numin"] * (req["numax"] / req["numin"]) ** (np.arange(600) / 599)
+    assert np.trapezoid(sp["sed"], np.log(nu)) == pytest.approx(sp["prad"], rel=1e-5)
+    assert sp["prad"] > 0
