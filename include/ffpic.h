@@ -289,6 +289,35 @@ int ffpic_get_sort(ffpic_ctx *ctx, int species, int32_t *cell_offsets);
    (Sect. 4, eq. michel_spindown form).  Synchronises. */
 int ffpic_diagnostics(ffpic_ctx *ctx, uint32_t what, ffpic_diag *out, double *L_of_r);
 
+/* Spectra of one species over a region of the meridional plane (the
+   observables of Sect. 5: particle energy spectra and the synchrotron
+   spectral energy distribution).  A live particle counts when
+   rmin <= r < rmax and thmin <= theta < thmax.  With w the species' weight,
+   gamma = sqrt(1 + u.u) and Bperp of eq. (bperp) from E and B gathered at
+   the particle as in the push:
+     dN[m]  (ngamma doubles, host): summed w of the particles with gamma in
+            [gmin (gmax/gmin)^(m/ngamma), gmin (gmax/gmin)^((m+1)/ngamma));
+     prad   (1 double, host): summed w P, P = K gamma^2 Bperp^2 the leading
+            power of the radiation-reaction force g, K the coefficient the
+            push applies at the current step (ramp included);
+     sed[k] (nnu doubles, host): summed w nu dP/dnu at
+            nu_k = numin (numax/numin)^(k/(nnu-1)) (code frequency units),
+            nu dP/dnu = P x F(x) 9 sqrt(3) / (8 pi), x = nu / nu_c,
+            nu_c = 3/(4 pi) gamma^2 omega_b |qm| Bperp, F the synchrotron
+            function x int_x^inf K_{5/3}: the single-particle synchrotron
+            spectrum normalised to P (F from a table, about 1e-5 relative).
+   EINVAL for a bad species, a NULL output, an empty region or range, or
+   ngamma / nnu outside [1, FFPIC_SPEC_MAX].  Synchronises. */
+#define FFPIC_SPEC_MAX 256
+typedef struct ffpic_spectra_req {
+    double rmin, rmax, thmin, thmax;
+    double gmin, gmax;
+    double numin, numax;
+    int32_t ngamma, nnu;
+} ffpic_spectra_req;
+int ffpic_spectra(ffpic_ctx *ctx, int species, const ffpic_spectra_req *req, double *dN,
+                  double *sed, double *prad);
+
 /* Checkpoint: with buf == NULL writes the required size to *len; otherwise
    serialises fields, Psi, f, particles, counters and the step number into
    buf (at least *len bytes, host memory).  Restore requires a context

@@ -33,6 +33,8 @@ SOURCES = [
     # the parent test is evaluated twice and must round the same both times
     ("k_pairs.hip", ["-ffp-contract=off"]),
     ("k_misc.hip", []),
+    # spectra follow the oracle's FP64 operation order
+    ("k_diag.hip", ["-ffp-contract=off"]),
 ]
 
 COMMON = ["-x", "hip", f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",

@@ -95,6 +95,9 @@ struct ffpic_ctx {
     size_t pair_scan_bytes = 0;
     int64_t pair_blocks = 0;                  // capacity of pair_cnt (entries - 1)
     int32_t *nslots_host = nullptr;           // pinned copy of nslots
+    // spectra: table of ln F of the synchrotron function, the gamma bin
+    // edges and frequencies of the last request
+    double *spec_tab = nullptr, *spec_edge = nullptr, *spec_nu = nullptr;
     double *psi = nullptr;
     void *f = nullptr;
     uint8_t *kill = nullptr;
@@ -171,6 +174,8 @@ size_t inject_scan_bytes(int nth);
 size_t pair_scan_bytes(int64_t nblk);
 int pair_block_slots();
 double rr_factor(const ffpic_ctx *c);   // radiation-reaction ramp at this step
+// dev_out: ngamma + nnu + 1 doubles (dN, sed, prad)
+void spectra(ffpic_ctx *c, int s, const ffpic_spectra_req *req, double *dev_out);
 
 }  // namespace ffpic
 

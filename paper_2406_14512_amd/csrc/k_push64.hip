@@ -19,7 +19,7 @@
 // workgroup over the bounding box of its (cell-sorted) particles, same-cell
 // in-cell moves summed across the wavefront first, one global FP64 atomic
 // per non-zero patch entry.
-#include "device_common.h"
+#include "gather.h"
 
 namespace ffpic {
 
@@ -32,48 +32,6 @@ struct P64 {
     double Q, wq, rr;
     double shell_r;        // r below this: only the momentum along B is kept
 };
-
-struct Lin {
-    int lo;
-    double w;
-};
-
-__device__ __forceinline__ Lin half_r(int i, double a, int nr) {
-    Lin l;
-    if (a >= 0.5) { l.lo = i; l.w = a - 0.5; } else { l.lo = i - 1; l.w = a + 0.5; }
-    if (l.lo < 0) { l.lo = 0; l.w = 0.0; }
-    if (l.lo > nr - 2) { l.lo = nr - 2; l.w = 1.0; }
-    return l;
-}
-__device__ __forceinline__ Lin half_t(int j, double b) {
-    Lin l;
-    if (b >= 0.5) { l.lo = j; l.w = b - 0.5; } else { l.lo = j - 1; l.w = b + 0.5; }
-    return l;
-}
-
-__device__ __forceinline__ double hv(const double *F, int ld, int nth, int i, int k, double par) {
-    if (k < 0) return par * F[ix(ld, i, 0)];
-    if (k >= nth) return par * F[ix(ld, i, nth - 1)];
-    return F[ix(ld, i, k)];
-}
-
-__device__ __forceinline__ double bil(const double *F, int ld, int nth, Lin lr, Lin lt,
-                                      bool thalf, double par) {
-    double v00, v10, v01, v11;
-    if (thalf) {
-        v00 = hv(F, ld, nth, lr.lo, lt.lo, par);
-        v10 = hv(F, ld, nth, lr.lo + 1, lt.lo, par);
-        v01 = hv(F, ld, nth, lr.lo, lt.lo + 1, par);
-        v11 = hv(F, ld, nth, lr.lo + 1, lt.lo + 1, par);
-    } else {
-        v00 = F[ix(ld, lr.lo, lt.lo)];
-        v10 = F[ix(ld, lr.lo + 1, lt.lo)];
-        v01 = F[ix(ld, lr.lo, lt.lo + 1)];
-        v11 = F[ix(ld, lr.lo + 1, lt.lo + 1)];
-    }
-    return (1.0 - lr.w) * (1.0 - lt.w) * v00 + lr.w * (1.0 - lt.w) * v10 +
-           (1.0 - lr.w) * lt.w * v01 + lr.w * lt.w * v11;
-}
 
 __device__ __forceinline__ void boris_rr(double u[3], const double E[3], const double B[3],
                                          double dt, double wq, double rr) {
@@ -192,15 +150,8 @@ __global__ void __launch_bounds__(256) k_push64(
         live = false;
     }
     if (live) {
-        const int ld = p.ld, nth = p.nth;
-        Lin rn = {i, a}, rh = half_r(i, a, p.nr), tn = {j, b}, thh = half_t(j, b);
         double Es[3], Bs[3];
-        Es[0] = bil(Er, ld, nth, rh, tn, false, 1.0);
-        Es[1] = bil(Et, ld, nth, rn, thh, true, -1.0);
-        Es[2] = bil(Ep, ld, nth, rn, tn, false, 1.0);
-        Bs[0] = bil(Br, ld, nth, rn, thh, true, 1.0);
-        Bs[1] = bil(Bt, ld, nth, rh, tn, false, 1.0);
-        Bs[2] = bil(Bp, ld, nth, rh, thh, true, -1.0);
+        gather_eb(Er, Et, Ep, Br, Bt, Bp, p.nr, p.nth, p.ld, i, j, a, b, Es, Bs);
         double st = sin(th), ct = cos(th);
         double E[3] = {Es[0] * st + Es[1] * ct, Es[2], Es[0] * ct - Es[1] * st};
         double B[3] = {Bs[0] * st + Bs[1] * ct, Bs[2], Bs[0] * ct - Bs[1] * st};

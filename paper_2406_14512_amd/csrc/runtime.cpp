@@ -349,6 +349,7 @@ void free_all(ffpic_ctx *c) {
     F(c->sort_sb); F(c->sort_blk); F(c->sort_aux); F(c->sort_moff); F(c->sort_tot); F(c->scan_tmp);
     F(c->inj_rate); F(c->inj_cnt); F(c->inj_off); F(c->inj_scan_tmp); F(c->nsorted);
     F(c->gj_target); F(c->gj_have); F(c->pair_cnt); F(c->pair_off); F(c->pair_scan_tmp);
+    F(c->spec_tab); F(c->spec_edge); F(c->spec_nu);
     if (c->nslots_host) (void)hipHostFree(c->nslots_host);
     F(c->sort_tmp); F(c->nslots); F(c->nalive); F(c->removed); F(c->err); F(c->red);
     for (auto &e : c->ev)
@@ -852,6 +853,35 @@ int ffpic_get_sort(ffpic_ctx *c, int s, int32_t *off) {
         HCHK(hipMemcpyAsync(off, d, nk * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
         HCHK(hipStreamSynchronize(c->stream));
         HCHK(hipFree(d));
+    });
+}
+
+int ffpic_spectra(ffpic_ctx *c, int s, const ffpic_spectra_req *q, double *dN, double *sed,
+                  double *prad) {
+    return guarded(c, [&] {
+        check_ctx(c);
+        if (s < 0 || s >= c->d.nspec) throw Fail{FFPIC_EINVAL, "species out of range"};
+        if (!q || !dN || !sed || !prad) throw Fail{FFPIC_EINVAL, "NULL request or output"};
+        if (q->ngamma < 1 || q->ngamma > FFPIC_SPEC_MAX || q->nnu < 1 || q->nnu > FFPIC_SPEC_MAX)
+            throw Fail{FFPIC_EINVAL, "ngamma and nnu must lie in [1, FFPIC_SPEC_MAX]"};
+        if (!(q->rmin < q->rmax) || !(q->thmin < q->thmax))
+            throw Fail{FFPIC_EINVAL, "empty region"};
+        if (!(q->gmin > 0) || !(q->gmax > q->gmin) || !std::isfinite(q->gmax))
+            throw Fail{FFPIC_EINVAL, "need 0 < gmin < gmax"};
+        if (!(q->numin > 0) || !std::isfinite(q->numax) ||
+            !(q->nnu == 1 ? q->numax >= q->numin : q->numax > q->numin))
+            throw Fail{FFPIC_EINVAL, "need 0 < numin < numax"};
+        const size_t len = (size_t)q->ngamma + q->nnu + 1;
+        if (len > c->red_len) throw Fail{FFPIC_EINVAL, "request too large"};
+        spectra(c, s, q, c->red);
+        std::vector<double> h(len);
+        HCHK(hipMemcpyAsync(h.data(), c->red, len * sizeof(double), hipMemcpyDeviceToHost,
+                            c->stream));
+        HCHK(hipStreamSynchronize(c->stream));
+        read_err(c);
+        std::copy(h.begin(), h.begin() + q->ngamma, dN);
+        std::copy(h.begin() + q->ngamma, h.begin() + q->ngamma + q->nnu, sed);
+        *prad = h[len - 1];
     });
 }
 

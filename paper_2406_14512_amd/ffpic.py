@@ -61,6 +61,16 @@ class Diag(C.Structure):
                 ("error_word", C.c_uint32), ("pad_", C.c_uint32)]
 
 
+SPEC_MAX = 256
+
+
+class SpectraReq(C.Structure):
+    _fields_ = [("rmin", C.c_double), ("rmax", C.c_double), ("thmin", C.c_double),
+                ("thmax", C.c_double), ("gmin", C.c_double), ("gmax", C.c_double),
+                ("numin", C.c_double), ("numax", C.c_double),
+                ("ngamma", C.c_int32), ("nnu", C.c_int32)]
+
+
 TUNE_MAX = 8
 
 
@@ -108,6 +118,8 @@ def lib():
                                             vp, vp, vp, vp, vp, vp]
     L.ffpic_get_sort.argtypes = [P, C.c_int, vp]
     L.ffpic_diagnostics.argtypes = [P, C.c_uint32, C.POINTER(Diag), vp]
+    dptr = C.POINTER(C.c_double)
+    L.ffpic_spectra.argtypes = [P, C.c_int, C.POINTER(SpectraReq), dptr, dptr, dptr]
     L.ffpic_save.argtypes = [P, vp, C.POINTER(C.c_size_t)]
     L.ffpic_restore.argtypes = [P, vp, C.c_size_t]
     L.ffpic_set_timing.argtypes = [P, C.c_int]
@@ -128,7 +140,8 @@ def lib():
                  "ffpic_diagnostics", "ffpic_save", "ffpic_restore", "ffpic_set_timing",
                  "ffpic_phase_times", "ffpic_get_particles_range", "ffpic_batch_create",
                  "ffpic_batch_view", "ffpic_batch_size", "ffpic_batch_step", "ffpic_batch_sync",
-                 "ffpic_batch_destroy", "ffpic_autotune", "ffpic_batch_autotune"):
+                 "ffpic_batch_destroy", "ffpic_autotune", "ffpic_batch_autotune",
+                 "ffpic_spectra"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -306,6 +319,21 @@ class Sim:
         if L is not None:
             out["L"] = L
         return out
+
+    def spectra(self, species: int, req: Dict) -> Dict:
+        """Gamma histogram dN, radiated power prad and synchrotron SED of one
+        species over a region (keys rmin, rmax, thmin, thmax, gmin, gmax,
+        numin, numax, ngamma, nnu)."""
+        q = SpectraReq()
+        for k in ("rmin", "rmax", "thmin", "thmax", "gmin", "gmax", "numin", "numax"):
+            setattr(q, k, float(req[k]))
+        q.ngamma, q.nnu = int(req["ngamma"]), int(req["nnu"])
+        dN, sed, prad = np.zeros(q.ngamma), np.zeros(q.nnu), np.zeros(1)
+        dp = dN.ctypes.data_as(C.POINTER(C.c_double))
+        self._chk(lib().ffpic_spectra(self._h, int(species), C.byref(q), dp,
+                                      sed.ctypes.data_as(C.POINTER(C.c_double)),
+                                      prad.ctypes.data_as(C.POINTER(C.c_double))))
+        return {"dN": dN, "sed": sed, "prad": float(prad[0])}
 
     def save(self) -> bytes:
         n = C.c_size_t(0)

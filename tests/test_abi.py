@@ -44,7 +44,7 @@ def test_struct_layout_matches_header(tmp_path, lib):
 #include <stddef.h>
 #include "ffpic.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n",
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n",
          sizeof(ffpic_desc), sizeof(ffpic_diag),
          offsetof(ffpic_desc, psi_thr), offsetof(ffpic_desc, capacity),
          offsetof(ffpic_desc, weight), offsetof(ffpic_diag, sum_u),
@@ -52,7 +52,8 @@ int main(void) {
          sizeof(ffpic_tuning), offsetof(ffpic_tuning, ms_per_step),
          offsetof(ffpic_tuning, total_ms), offsetof(ffpic_desc, rr_ramp_f),
          offsetof(ffpic_desc, shell_r), offsetof(ffpic_desc, gj_species),
-         offsetof(ffpic_desc, gamma_s), offsetof(ffpic_desc, pair_species));
+         offsetof(ffpic_desc, gamma_s), offsetof(ffpic_desc, pair_species),
+         sizeof(ffpic_spectra_req), offsetof(ffpic_spectra_req, nnu));
   return 0;
 }
 ''')
@@ -63,7 +64,8 @@ int main(void) {
     want = [ctypes.sizeof(D), ctypes.sizeof(G), D.psi_thr.offset, D.capacity.offset,
             D.weight.offset, G.sum_u.offset, G.gauss_max.offset, G.error_word.offset,
             ctypes.sizeof(T), T.ms_per_step.offset, T.total_ms.offset, D.rr_ramp_f.offset,
-            D.shell_r.offset, D.gj_species.offset, D.gamma_s.offset, D.pair_species.offset]
+            D.shell_r.offset, D.gj_species.offset, D.gamma_s.offset, D.pair_species.offset,
+            ctypes.sizeof(ffpic.SpectraReq), ffpic.SpectraReq.nnu.offset]
     assert got == want
 
 
@@ -107,3 +109,6 @@ def test_null_and_invalid_arguments_fail_cleanly(lib):
     assert lib.ffpic_autotune(None, 100.0, None) == ffpic.EINVAL
     assert lib.ffpic_get_particles_range(None, 0, 0, None, None, None, None, None, None,
                                          None) == ffpic.EINVAL
+    q = ffpic.SpectraReq(1.0, 2.0, 0.0, 3.0, 1.0, 10.0, 1.0, 2.0, 4, 4)
+    buf = (ctypes.c_double * 8)()
+    assert lib.ffpic_spectra(None, 0, ctypes.byref(q), buf, buf, buf) == ffpic.EINVAL
