@@ -115,6 +115,7 @@ struct ffpic_ctx {
     uint32_t *sort_sb = nullptr;              // stayers before each slot [cap + 1]
     uint32_t *sort_blk = nullptr;             // block counts and their scans [4 * blocks]
     uint32_t *sort_aux = nullptr;             // sorted mover slots [cap]
+    uint8_t *sort_cls = nullptr;              // FP32: class of each slot [cap]
     int32_t *sort_moff = nullptr;             // movers below each key [nr*nth + 1]
     uint32_t *sort_tot = nullptr;             // stayers, movers
     void *scan_tmp = nullptr;

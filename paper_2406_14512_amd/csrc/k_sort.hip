@@ -297,36 +297,48 @@ __device__ __forceinline__ void block_counts(uint32_t st, uint32_t mv, uint32_t 
     }
 }
 
+// FP32 key pass of the incremental sort: kill, then the class of every slot
+// (0 dropped, 1 stayer, 2 mover) as one byte, with the block counts.  The
+// later passes take the key of a slot from its cell, so no key array is
+// written.  The loads of the block's four slots per thread are issued first.
 __global__ void __launch_bounds__(256) k_keyclass32(int nub, const int32_t *__restrict__ nslots,
                                                     int nth, const uint8_t *__restrict__ kill,
                                                     uint32_t dead, int32_t *__restrict__ CELL,
-                                                    uint32_t *__restrict__ keys,
+                                                    uint8_t *__restrict__ cls,
                                                     unsigned long long *__restrict__ removed,
                                                     const int32_t *__restrict__ nsorted,
                                                     const uint32_t *__restrict__ kold,
                                                     uint32_t *__restrict__ bst,
                                                     uint32_t *__restrict__ bmv) {
+    constexpr int K = kSortBlock / 256;
     const int ns = nslots[0], no = nsorted[0];
-    uint32_t st = 0, mv = 0;
-    for (int k = 0; k < kSortBlock / 256; k++) {
+    int cell[K];
+    uint32_t ko[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) {
         const int q = blockIdx.x * kSortBlock + k * 256 + threadIdx.x;
-        uint32_t key = dead;
+        cell[k] = q < ns ? CELL[q] : -1;
+        ko[k] = q < no ? kold[q] : dead;
+    }
+    uint32_t st = 0, mv = 0;
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        const int q = blockIdx.x * kSortBlock + k * 256 + threadIdx.x;
+        const int c = cell[k];
         bool killed = false;
-        if (q < ns) {
-            const int c = CELL[q];
-            if (c >= 0) {
-                const int i = c >> 16, j = c & 0xffff;
-                if (kill[(size_t)i * nth + j]) {
-                    killed = true;
-                    CELL[q] = -1;
-                } else {
-                    key = (uint32_t)i * (uint32_t)nth + (uint32_t)j;
-                }
+        int cl = 0;
+        if (c >= 0) {
+            const int i = c >> 16, j = c & 0xffff;
+            if (kill[(size_t)i * nth + j]) {
+                killed = true;
+                CELL[q] = -1;
+            } else {
+                const uint32_t key = (uint32_t)i * (uint32_t)nth + (uint32_t)j;
+                cl = key >= dead ? 0 : (key == ko[k] ? 1 : 2);
             }
         }
-        if (q < nub) keys[q] = key;
+        if (q < nub) cls[q] = (uint8_t)cl;
         count_wave(&removed[1], killed);
-        const int cl = q < nub ? slot_class(key, dead, q, no, kold) : 0;
         st += __popcll(__ballot(cl == 1));
         mv += __popcll(__ballot(cl == 2));
     }
@@ -407,6 +419,50 @@ __global__ void __launch_bounds__(256) k_class_compact(
     }
 }
 
+// FP32 variant of the compaction: classes from the byte array, the key of a
+// mover from its cell
+__global__ void __launch_bounds__(256) k_class_compact32(
+    int nub, int nblk, int nth, const uint8_t *__restrict__ cls, const int32_t *__restrict__ CELL,
+    const uint32_t *__restrict__ cst, const uint32_t *__restrict__ cmv, uint32_t *__restrict__ sb,
+    uint32_t *__restrict__ mkey, uint32_t *__restrict__ mval, uint32_t *__restrict__ tot) {
+    constexpr int K = kSortBlock / 256;
+    __shared__ uint32_t part[2][4];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    int cl[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        const int q = blockIdx.x * kSortBlock + k * 256 + tid;
+        cl[k] = q < nub ? (int)cls[q] : 0;
+    }
+    uint32_t st0 = cst[blockIdx.x], mv0 = cmv[blockIdx.x];
+    const unsigned long long below = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        const int q = blockIdx.x * kSortBlock + k * 256 + tid;
+        const unsigned long long ms = __ballot(cl[k] == 1), mm = __ballot(cl[k] == 2);
+        if (lane == 0) { part[0][w] = __popcll(ms); part[1][w] = __popcll(mm); }
+        __syncthreads();
+        uint32_t os = st0, om = mv0;
+        for (int u = 0; u < w; u++) { os += part[0][u]; om += part[1][u]; }
+        os += __popcll(ms & below);
+        om += __popcll(mm & below);
+        if (q < nub) sb[q] = os;
+        if (cl[k] == 2) {
+            const int c = CELL[q];
+            mkey[om] = (uint32_t)(c >> 16) * (uint32_t)nth + (uint32_t)(c & 0xffff);
+            mval[om] = (uint32_t)q;
+        }
+        st0 += part[0][0] + part[0][1] + part[0][2] + part[0][3];
+        mv0 += part[1][0] + part[1][1] + part[1][2] + part[1][3];
+        __syncthreads();
+    }
+    if (blockIdx.x == nblk - 1 && tid == 0) {
+        sb[nub] = st0;
+        tot[0] = st0;
+        tot[1] = mv0;
+    }
+}
+
 // moff[k] = movers with key < k (binary search in the sorted mover keys)
 __global__ void k_mover_offsets(const uint32_t *__restrict__ tot, const uint32_t *__restrict__ mkey,
                                 int nkeys, int32_t *__restrict__ moff) {
@@ -467,6 +523,47 @@ __global__ void k_scatter(int nub, int nbm, const uint32_t *__restrict__ keys, u
     const uint32_t d = sb[q] + (uint32_t)lo;
 #pragma unroll
     for (int a = 0; a < NA; a++) P.dst[a][d] = v[a];
+    knew[d] = key;
+}
+
+// FP32 variant of the scatter: a stayer's class from the byte array and its
+// key from its cell (the first state array)
+__global__ void k_scatter32(int nub, int nbm, int nth, const uint8_t *__restrict__ cls,
+                            const uint32_t *__restrict__ sb, const int32_t *__restrict__ moff,
+                            const uint32_t *__restrict__ tot, const uint32_t *__restrict__ mkey,
+                            const uint32_t *__restrict__ mval, const int32_t *__restrict__ offold,
+                            uint32_t *__restrict__ knew, PtrSet<uint32_t, 6> P) {
+    if ((int)blockIdx.x < nbm) {
+        const int m = (int)tot[1];
+        for (int j = (int)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += nbm * blockDim.x) {
+            const uint32_t key = mkey[j];
+            const int q = (int)mval[j];
+            const int lo = offold[key], hi = offold[key + 1];
+            const int c = q < lo ? lo : (q > hi ? hi : q);
+            const uint32_t d = (uint32_t)j + sb[c];
+#pragma unroll
+            for (int a = 0; a < 6; a++) P.dst[a][d] = P.src[a][q];
+            knew[d] = key;
+        }
+        return;
+    }
+    const int q = ((int)blockIdx.x - nbm) * blockDim.x + threadIdx.x;
+    if (q >= nub) return;
+    uint32_t v[6];
+#pragma unroll
+    for (int a = 0; a < 6; a++) v[a] = P.src[a][q];
+    if (cls[q] != 1) return;
+    const int cell = (int)v[0];
+    const uint32_t key = (uint32_t)(cell >> 16) * (uint32_t)nth + (uint32_t)(cell & 0xffff);
+    int lo = moff[key];
+    int hi = moff[key + 1];
+    while (lo < hi) {                     // movers of this key are in slot order
+        const int mid = (lo + hi) >> 1;
+        if ((int)mval[mid] < q) lo = mid + 1; else hi = mid;
+    }
+    const uint32_t d = sb[q] + (uint32_t)lo;
+#pragma unroll
+    for (int a = 0; a < 6; a++) P.dst[a][d] = v[a];
     knew[d] = key;
 }
 
@@ -568,7 +665,7 @@ static void sort_incremental(ffpic_ctx *c, int s) {
                            bst, bmv);
     } else {
         hipLaunchKernelGGL(k_keyclass32, dim3(nblk), dim3(256), 0, c->stream, nub, c->nslots + s,
-                           c->nth, c->kill, dead, (int32_t *)S.cur[0], c->keys[0],
+                           c->nth, c->kill, dead, (int32_t *)S.cur[0], c->sort_cls,
                            c->removed + 4 * s, nold, kold, bst, bmv);
     }
     FFPIC_LAUNCH_CHECK();
@@ -579,8 +676,14 @@ static void sort_incremental(ffpic_ctx *c, int s) {
                                 rocprim::plus<uint32_t>(), c->stream) != hipSuccess)
         throw std::runtime_error("rocprim scan failed");
     uint32_t *mkey = c->keys[1], *mval = c->vals[0];
-    hipLaunchKernelGGL(k_class_compact, dim3(nblk), dim3(256), 0, c->stream, nub, nblk, c->keys[0],
-                       dead, nold, kold, bst, bmv, cst, cmv, c->sort_sb, mkey, mval, c->sort_tot);
+    if (c->fp64)
+        hipLaunchKernelGGL(k_class_compact, dim3(nblk), dim3(256), 0, c->stream, nub, nblk,
+                           c->keys[0], dead, nold, kold, bst, bmv, cst, cmv, c->sort_sb, mkey, mval,
+                           c->sort_tot);
+    else
+        hipLaunchKernelGGL(k_class_compact32, dim3(nblk), dim3(256), 0, c->stream, nub, nblk,
+                           c->nth, c->sort_cls, (const int32_t *)S.cur[0], cst, cmv, c->sort_sb,
+                           mkey, mval, c->sort_tot);
     FFPIC_LAUNCH_CHECK();
     uint32_t tot[2] = {0, 0};
     HCHK_SORT(hipMemcpyAsync(tot, c->sort_tot, sizeof(tot), hipMemcpyDeviceToHost, c->stream));
@@ -604,9 +707,9 @@ static void sort_incremental(ffpic_ctx *c, int s) {
                            nub, nbm, c->keys[0], dead, nold, kold, c->sort_sb, c->sort_moff,
                            c->sort_tot, mkey2, mval2, offold, knew, (state_ptrs<uint64_t, 5>(S)));
     } else {
-        hipLaunchKernelGGL((k_scatter<uint32_t, 6>), dim3(nbs + nbm), dim3(256), 0, c->stream,
-                           nub, nbm, c->keys[0], dead, nold, kold, c->sort_sb, c->sort_moff,
-                           c->sort_tot, mkey2, mval2, offold, knew, (state_ptrs<uint32_t, 6>(S)));
+        hipLaunchKernelGGL(k_scatter32, dim3(nbs + nbm), dim3(256), 0, c->stream, nub, nbm,
+                           c->nth, c->sort_cls, c->sort_sb, c->sort_moff, c->sort_tot, mkey2,
+                           mval2, offold, knew, (state_ptrs<uint32_t, 6>(S)));
     }
     // reads the old live count before replacing it with the new one
     hipLaunchKernelGGL(k_new_offsets, dim3((nkeys + 1 + 255) / 256), dim3(256), 0, c->stream,
