@@ -372,7 +372,7 @@ void surface_tables(ffpic_ctx *c, const double *br_surface) {
     const int nth = c->nth;
     const std::vector<double> &rn = c->tab[T_RN], &cn = c->tab[T_CN];
     std::vector<double> rate(nth), target(nth);
-    int64_t ibound = 0, ebound = 0;
+    double ibound = 0.0, ebound = 0.0;   // most particles a step adds (sums of ceilings)
     const double wpair = ext ? c->d.weight[c->d.gj_species[0]] + c->d.weight[c->d.gj_species[1]]
                              : 1.0;
     for (int j = 0; j < nth; j++) {
@@ -382,13 +382,18 @@ void surface_tables(ffpic_ctx *c, const double *br_surface) {
             const double q = c->d.weight[0];
             rate[j] = c->d.inject_kappa * (c->omega * br / (2.0 * kPi)) / q * vol *
                       (c->dt / (rn[1] - rn[0]));
-            ibound += (int64_t)std::ceil(rate[j]);
+            ibound += std::ceil(rate[j]);
         }
         if (ext) {
             target[j] = c->d.gj_extract * (c->omega * br / (2.0 * kPi)) * vol;
-            ebound += (int64_t)std::ceil(target[j] / wpair);
+            ebound += std::ceil(target[j] / wpair);
         }
     }
+    // per-cell counts and their scan are int32: the most a step can add must
+    // stay far below 2^31
+    if (!(ibound <= 1073741824.0) || !(ebound <= 1073741824.0))
+        throw Fail{FFPIC_EINVAL, "a surface source would add more than 2^30 particles in one "
+                                 "step: raise the weights"};
     if (!c->inj_cnt) {
         c->inj_cnt = (int32_t *)dmalloc((size_t)(nth + 1) * sizeof(int32_t));
         c->inj_off = (int32_t *)dmalloc((size_t)(nth + 1) * sizeof(int32_t));
@@ -398,7 +403,7 @@ void surface_tables(ffpic_ctx *c, const double *br_surface) {
     if (inj) {
         if (!c->inj_rate) c->inj_rate = (double *)dmalloc((size_t)nth * sizeof(double));
         HCHK(hipMemcpy(c->inj_rate, rate.data(), (size_t)nth * sizeof(double), hipMemcpyHostToDevice));
-        c->inj_bound = ibound;
+        c->inj_bound = (int64_t)ibound;
     }
     if (ext) {
         if (!c->gj_target) {
@@ -407,7 +412,7 @@ void surface_tables(ffpic_ctx *c, const double *br_surface) {
         }
         HCHK(hipMemcpy(c->gj_target, target.data(), (size_t)nth * sizeof(double),
                        hipMemcpyHostToDevice));
-        c->gj_bound = ebound;
+        c->gj_bound = (int64_t)ebound;
     }
 }
 

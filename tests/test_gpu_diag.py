@@ -75,3 +75,25 @@ def test_spectra_fp32_and_region():
     # an empty region gives zeros
     g = sim.spectra(0, dict(req, rmin=9.5, rmax=9.6))
     assert g["prad"] == 0 and not g["dN"].any() and not g["sed"].any()
+
+
+def test_spectra_edge_cases():
+    """One bin and one frequency agree with the oracle; a species with no
+    particles gives zeros; malformed requests are refused."""
+    w = W.sourced_dipole(32, n_per_species=500)
+    sim, ora = both(w, W.FP64, cap=5000)
+    one = dict(REQ, ngamma=1, nnu=1, numax=REQ["numin"])
+    g, o = sim.spectra(0, one), ora.spectra(0, one)
+    assert np.rint(g["dN"][0] / w.weight[0]) == np.rint(o["dN"][0] / w.weight[0])
+    assert g["sed"][0] == pytest.approx(o["sed"][0], rel=1e-4)
+    d = dict(w.desc(), precision=W.FP64)
+    empty = ffpic.Sim(d, capacity=[10] * 3)
+    e = empty.spectra(1, REQ)
+    assert e["prad"] == 0 and not e["dN"].any() and not e["sed"].any()
+    for bad in (dict(REQ, gmax=0.5), dict(REQ, ngamma=0), dict(REQ, nnu=ffpic.SPEC_MAX + 1),
+                dict(REQ, rmin=3.0, rmax=2.0), dict(REQ, numin=-1.0)):
+        with pytest.raises(ffpic.FfpicError) as err:
+            sim.spectra(0, bad)
+        assert err.value.code == ffpic.EINVAL
+    with pytest.raises(ffpic.FfpicError):
+        sim.spectra(5, REQ)

@@ -259,3 +259,13 @@ def test_sourced_dipole_checkpoint_resumes_fp64():
         for k in KEYS:
             assert np.allclose(pa[k], pb[k], rtol=1e-13, atol=1e-13), (s, k)
     assert b.diagnostics(ffpic.DIAG_MOMENTS)["step"] == 6
+
+
+def test_source_that_would_overflow_a_step_is_rejected():
+    """Weights so small that one extraction would add more than 2^30
+    particles are refused at creation (the per-cell counts are int32)."""
+    w = W.sourced_dipole(64, n_per_species=0)
+    d = dict(w.desc(), precision=W.FP64, weight=(1e-30, 1e-30, 1e-30))
+    with pytest.raises(ffpic.FfpicError) as e:
+        ffpic.Sim(d, capacity=[1000] * 3)
+    assert e.value.code == ffpic.EINVAL
