@@ -51,22 +51,22 @@ __device__ __forceinline__ int count_wave_i(int *ctr, bool pred) {
 namespace ffpic {
 
 // Cell of an FP64 position by comparison against the node tables (so the
-// cell is a function of (r, theta) alone, whatever the rounding of log),
-// plus the in-cell offsets in log r / dlog and theta / dtheta, in [0, 1].
+// cell is a function of (r, theta) alone, whatever the rounding of the first
+// guess), plus the in-cell offsets in log r / dlog and theta / dtheta, in
+// [0, 1].  The starting guess is taken in single precision: the comparisons
+// settle the cell, and only the offset needs the FP64 logarithm.
 __device__ __forceinline__ void locate64(int nr, int nth, double rmin, double dlog, double dth,
                                          const double *rn, const double *thn, double r,
                                          double th, int &ci, int &cj, double &a, double &b) {
-    int i = (int)floor(log(r / rmin) / dlog);
-    if (i < 0) i = 0;
-    if (i > nr - 1) i = nr - 1;
+    const float gi = __logf((float)(r / rmin)) * (float)(1.0 / dlog);
+    int i = gi > 0.f ? (gi < (float)(nr - 1) ? (int)gi : nr - 1) : 0;
     while (i > 0 && r < rn[i]) i--;
     while (i < nr - 1 && r >= rn[i + 1]) i++;
     double aa = log(r / rn[i]) / dlog;
     if (aa < 0.0) aa = 0.0;
     if (aa > 1.0) aa = 1.0;
-    int j = (int)floor(th / dth);
-    if (j < 0) j = 0;
-    if (j > nth - 1) j = nth - 1;
+    const float gj = (float)th * (float)(1.0 / dth);
+    int j = gj > 0.f ? (gj < (float)(nth - 1) ? (int)gj : nth - 1) : 0;
     while (j > 0 && th < thn[j]) j--;
     while (j < nth - 1 && th >= thn[j + 1]) j++;
     double bb = (th - thn[j]) / dth;
