@@ -17,8 +17,8 @@
 // faces (exact discrete charge conservation), azimuthal current from v_phi
 // at the mid-point.  Accumulation as in the FP32 path: an LDS patch per
 // workgroup over the bounding box of its (cell-sorted) particles, same-cell
-// in-cell moves summed across the wavefront first, one global FP64 atomic
-// per non-zero patch entry.
+// in-cell moves summed across each 16-lane row first (DPP), one global FP64
+// atomic per non-zero patch entry.
 #include "gather.h"
 
 namespace ffpic {
@@ -73,8 +73,22 @@ __device__ __forceinline__ void boris_rr(double u[3], const double E[3], const d
     u[0] = uL[0]; u[1] = uL[1]; u[2] = uL[2];
 }
 
-__device__ __forceinline__ double wave_sum64(double v) {
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+// a DPP lane permutation of a double (both 32-bit halves moved the same way)
+template <int CTRL>
+__device__ __forceinline__ double dpp64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// sum over each 16-lane row of the wavefront (every lane of the row gets it):
+// quad swaps, then the half-row and row mirrors
+__device__ __forceinline__ double row_sum64(double v) {
+    v += dpp64<0xB1>(v);
+    v += dpp64<0x4E>(v);
+    v += dpp64<0x141>(v);
+    v += dpp64<0x140>(v);
     return v;
 }
 
@@ -231,19 +245,20 @@ __global__ void __launch_bounds__(256) k_push64(
             }
         }
     }
-    // same-cell in-cell moves: sum across the wavefront, one lane adds
+    // same-cell in-cell moves: sums over each 16-lane row, and the first lane
+    // of every row with participants adds its row's sums
     bool pend = simple;
     const int c = (i << 16) | j;
 #pragma unroll 1
     for (int it = 0; it < 2; it++) {
         unsigned long long m = __ballot(pend);
         if (m == 0ull) break;
-        int leader = __ffsll((long long)m) - 1;
-        int lc = __shfl(c, leader, 64);
+        int lc = __builtin_amdgcn_readlane(c, __ffsll((long long)m) - 1);
         bool part = pend && c == lc;
+        const unsigned long long pm = __ballot(part);
         double v[8];
-        for (int k = 0; k < 8; k++) v[k] = wave_sum64(part ? s[k] : 0.0);
-        if (lane == leader) {
+        for (int k = 0; k < 8; k++) v[k] = row_sum64(part ? s[k] : 0.0);
+        if ((lane & 15) == 0 && ((pm >> lane) & 0xffffull) != 0ull) {
             int li = lc >> 16, lj = lc & 0xffff;
             acc.add(0, li, lj, v[0]);
             acc.add(0, li, lj + 1, v[1]);
