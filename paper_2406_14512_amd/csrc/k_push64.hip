@@ -103,7 +103,9 @@ struct Acc64 {
     }
 };
 
-__global__ void __launch_bounds__(256) k_push64(
+// five waves per SIMD fit without spills (94 VGPRs); the default allocation
+// takes 98 and leaves four
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) k_push64(
     P64 p, int nub, const int32_t *__restrict__ nslots, const uint8_t *__restrict__ kill,
     const double *__restrict__ Er, const double *__restrict__ Et, const double *__restrict__ Ep,
     const double *__restrict__ Br, const double *__restrict__ Bt, const double *__restrict__ Bp,
