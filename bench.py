@@ -39,7 +39,8 @@ BYTES_PER_PARTICLE = {1: 48.0, 0: 80.0}   # algorithmic push+deposit bytes (read
 COUNTER_FILE = {1: "profiles/k_push32_sheet4096_hbm_counters.txt",
                 0: "profiles/k_push64_sheet4096_hbm_counters.txt"}
 KERNEL_SOURCES = {1: ["paper_2406_14512_amd/csrc/k_push32.hip"],
-                  0: ["paper_2406_14512_amd/csrc/k_push64.hip"]}
+                  0: ["paper_2406_14512_amd/csrc/k_push64.hip",
+                      "paper_2406_14512_amd/csrc/gather.h"]}
 COMMON_SOURCES = ["paper_2406_14512_amd/csrc/device_common.h",
                   "paper_2406_14512_amd/csrc/ffpic_internal.h"]
 
