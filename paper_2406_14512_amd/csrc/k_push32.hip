@@ -31,8 +31,12 @@
 // FP32 current arrays in HBM with one global atomic per non-zero entry.
 // Particles that stay in their cell and share it with the wavefront's
 // leader are summed across each 16-lane row first (DPP), so a sorted wave
-// issues 8 adds from 4 lanes instead of 8 x 64.  Chunks whose box is too
-// large for the patch (sparse regions) add straight to HBM.
+// issues one add instruction from 32 lanes (eight sums in each of four rows)
+// instead of eight from all 64.  Moves that leave their cell (a few per
+// cent of a step) are queued in LDS and deposited after the chunk, so the
+// zigzag runs in one wave per chunk rather than in nearly every wave.
+// Chunks whose box is too large for the patch (sparse regions) add
+// straight to HBM.
 #include "device_common.h"
 
 namespace ffpic {
@@ -41,6 +45,7 @@ constexpr int kWG = 256;
 constexpr int kPPT = 4;                  // particles per thread per chunk
 constexpr int kChunk = kWG * kPPT;
 constexpr int kTile = 2048;              // LDS patch entries per component
+constexpr int kQueue = 64;               // queued cell-crossing moves per workgroup
 constexpr int kRsrcWord3 = 0x00020000;   // raw dword buffer access (gfx9 family)
 
 struct P32 {
@@ -67,35 +72,50 @@ __device__ __forceinline__ void sto(T *base, unsigned idx, T v) {
     *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + (idx << 2)) = v;
 }
 
-// sum over each 16-lane row of the wavefront (every lane of the row gets it)
-__device__ __forceinline__ float row_sum(float v) {
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, true));
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, true));
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, true));
-    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, true));
-    return v;
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+// Sums eight per-lane values over each 16-lane row, halving the number of
+// values at every stage: exchange with lane^1 (keep four), lane^2 (keep
+// two), a rotation by four lanes (keep one; it flips bit 2 of the lane and
+// keeps bits 0 and 1), and a rotation by eight that adds the other half of
+// the row.  Lane l then holds the row sum of value 4*bit0(l) + 2*bit1(l) +
+// bit2(l); lanes l and l+8 hold the same sum.  keep[] are the four values a
+// lane sums in the first stage (values 4..7 on lanes with bit 0 set, 0..3
+// otherwise), pass[] the four its neighbour sums.
+__device__ __forceinline__ float row_sum8(const float keep[4], const float pass[4], bool b1,
+                                          bool b2) {
+    float y[4];
+#pragma unroll
+    for (int m = 0; m < 4; m++) y[m] = keep[m] + dpp<0xB1>(pass[m]);
+    const float z0 = (b1 ? y[2] : y[0]) + dpp<0x4E>(b1 ? y[0] : y[2]);
+    const float z1 = (b1 ? y[3] : y[1]) + dpp<0x4E>(b1 ? y[1] : y[3]);
+    const float w = (b2 ? z1 : z0) + dpp<0x124>(b2 ? z0 : z1);
+    return w + dpp<0x128>(w);
+}
+
+// component (0 = J_r, 1 = J_theta, 2 = J_phi) of the row sum a lane holds
+// after row_sum8: values 0, 1 are J_r, 2, 3 J_theta, 4..7 J_phi
+__device__ __forceinline__ int lane_comp(int lane) {
+    const int kq = ((lane & 1) ? 4 : 0) + ((lane & 2) ? 2 : 0) + ((lane & 4) ? 1 : 0);
+    return kq < 2 ? 0 : (kq < 4 ? 1 : 2);
 }
 
 struct Fields {
     __amdgpu_buffer_rsrc_t er, et, ep, br, bt, bp;
 };
 
-// particle state arrays: 32-bit byte offsets (slot * 4) through buffer
-// resources, so no 64-bit address is formed per access
+// particle state arrays: 32-bit byte offsets (slot * 4) from uniform bases,
+// so no 64-bit address is formed per access
 struct State {
-    __amdgpu_buffer_rsrc_t cell, a, b, ur, ut, up;
-    __device__ __forceinline__ static float ld(__amdgpu_buffer_rsrc_t R, unsigned q) {
-        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(R, (int)(q << 2), 0, 0));
-    }
-    __device__ __forceinline__ static void st(__amdgpu_buffer_rsrc_t R, unsigned q, float v) {
-        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), R, (int)(q << 2), 0, 0);
-    }
-    __device__ __forceinline__ int ldc(unsigned q) const {
-        return (int)__builtin_amdgcn_raw_buffer_load_b32(cell, (int)(q << 2), 0, 0);
-    }
-    __device__ __forceinline__ void stc(unsigned q, int v) const {
-        __builtin_amdgcn_raw_buffer_store_b32((unsigned)v, cell, (int)(q << 2), 0, 0);
-    }
+    int32_t *cell;
+    float *a, *b, *ur, *ut, *up;
+    __device__ __forceinline__ static float ld(const float *R, unsigned q) { return ldo(R, q); }
+    __device__ __forceinline__ static void st(float *R, unsigned q, float v) { sto(R, q, v); }
+    __device__ __forceinline__ int ldc(unsigned q) const { return ldo(cell, q); }
+    __device__ __forceinline__ void stc(unsigned q, int v) const { sto(cell, q, v); }
 };
 
 template <bool LDS>
@@ -125,21 +145,69 @@ __device__ __forceinline__ float bil(__amdgpu_buffer_rsrc_t R, unsigned o0, unsi
     return lo + wr * (hi - lo);
 }
 
+// zigzag (relay-point) deposit of a move from (x1, y1) in cell (i, j) to
+// (x2, y2) in the same frame, ending in cell (i + di, j + dj): the radial and
+// polar charge fluxes of the two straight segments, and J_phi at the midpoint
+template <bool LDS>
+__device__ __forceinline__ void zigzag(const P32 &p, const Acc<LDS> &acc, int i, int j, int di,
+                                       int dj, float x1, float y1, float x2, float y2, float qv) {
+    const int nth = p.nth;
+    const int i2 = i + di, j2 = j + dj;
+    const float xr = fminf((float)min(di, 0) + 1.f, fmaxf((float)max(di, 0), 0.5f * (x1 + x2)));
+    const float yr = fminf((float)min(dj, 0) + 1.f, fmaxf((float)max(dj, 0), 0.5f * (y1 + y2)));
+    const float Q = p.Q;
+    const float fx1 = Q * (xr - x1), fy1 = Q * (yr - y1);
+    const float fx2 = Q * (x2 - xr), fy2 = Q * (y2 - yr);
+    const float wx1 = 0.5f * (x1 + xr), wy1 = 0.5f * (y1 + yr);
+    const float wx2 = 0.5f * (xr + x2) - (float)di, wy2 = 0.5f * (yr + y2) - (float)dj;
+    acc.add(0, i, j, fx1 * (1.f - wy1));
+    acc.add(0, i, j + 1, fx1 * wy1);
+    acc.add(1, i, j, fy1 * (1.f - wx1));
+    acc.add(1, i + 1, j, fy1 * wx1);
+    acc.add(0, i2, j2, fx2 * (1.f - wy2));
+    acc.add(0, i2, j2 + 1, fx2 * wy2);
+    acc.add(1, i2, j2, fy2 * (1.f - wx2));
+    acc.add(1, i2 + 1, j2, fy2 * wx2);
+    const float xm = 0.5f * (x1 + x2), ym = 0.5f * (y1 + y2);
+    int im = (int)floorf(xm), jm = (int)floorf(ym);
+    if (i + im > p.nr - 1) im = p.nr - 1 - i;
+    if (j + jm > nth - 1) jm = nth - 1 - j;
+    const float wx = xm - (float)im, wy = ym - (float)jm;
+    const float qq = Q * qv;
+    acc.add(2, i + im, j + jm, qq * (1.f - wx) * (1.f - wy));
+    acc.add(2, i + im + 1, j + jm, qq * wx * (1.f - wy));
+    acc.add(2, i + im, j + jm + 1, qq * (1.f - wx) * wy);
+    acc.add(2, i + im + 1, j + jm + 1, qq * wx * wy);
+}
+
 template <bool LDS, bool SHELL>
 __device__ __forceinline__ void push_chunk(const P32 &p, const Fields &F, const Acc<LDS> &acc,
                                            const int *cell, int base, int tid, int lane,
                                            const uint8_t *__restrict__ kill, const State &S,
                                            uint32_t *__restrict__ err, int &nkill, int &nstar,
-                                           int &nabs) {
+                                           int &nabs, float4 *queue, int *qn, float *kg) {
     const int ld = p.ld, nth = p.nth;
     const unsigned ld4 = (unsigned)ld << 2;
-    // the offsets of the next particle are loaded one iteration ahead, and
-    // the kill flag is applied at the end, so that neither load sits on the
-    // latency chain in front of the field gather
-    float an = 0.f, bn = 0.f;
+    // the next particle's offsets and momentum are loaded one iteration
+    // ahead, and the kill flag is applied at the end, so that no state load
+    // sits on the latency chain in front of the field gather
+    // the deposit value this lane adds after the row reduction: component,
+    // radial and polar node offsets from the cell (values 0..7 as below)
+    const int rl = lane & 15;
+    const bool b0 = rl & 1, b1 = rl & 2, b2 = rl & 4;
+    const int kq = (b0 ? 4 : 0) + (b1 ? 2 : 0) + (b2 ? 1 : 0);
+    const int kcomp = lane_comp(lane);
+    const int kdi = (kq == 3 || kq == 5 || kq == 7) ? 1 : 0;
+    const int kdj = (kq == 1 || kq == 6 || kq == 7) ? 1 : 0;
+    const bool row_lead = (lane & 8) == 0;
+    float an = 0.f, bn = 0.f, urn = 0.f, utn = 0.f, upn = 0.f;
     if (cell[0] >= 0) {
-        an = State::ld(S.a, (unsigned)(base + tid));
-        bn = State::ld(S.b, (unsigned)(base + tid));
+        const unsigned q0 = (unsigned)(base + tid);
+        an = State::ld(S.a, q0);
+        bn = State::ld(S.b, q0);
+        urn = State::ld(S.ur, q0);
+        utn = State::ld(S.ut, q0);
+        upn = State::ld(S.up, q0);
     }
 #pragma unroll 1
     for (int k = 0; k < kPPT; k++) {
@@ -147,10 +215,13 @@ __device__ __forceinline__ void push_chunk(const P32 &p, const Fields &F, const 
         const int c = cell[k];
         const bool live = c >= 0;
         const int i = c >> 16, j = c & 0xffff;
-        const float a = an, b = bn;
+        const float a = an, b = bn, ur = urn, ut = utn, up = upn;
         if (k + 1 < kPPT && cell[k + 1] >= 0) {
             an = State::ld(S.a, q + kWG);
             bn = State::ld(S.b, q + kWG);
+            urn = State::ld(S.ur, q + kWG);
+            utn = State::ld(S.ut, q + kWG);
+            upn = State::ld(S.up, q + kWG);
         }
         const bool killed = live && kill[(unsigned)(i * nth + j)] != 0;
         // The deposit values below are assigned for every kept particle and
@@ -158,11 +229,11 @@ __device__ __forceinline__ void push_chunk(const P32 &p, const Fields &F, const 
         // they carry no initial value (no register setup on the other paths).
         bool simple = false;       // stays in its cell: 8 adds at fixed offsets
         float s0, s1, s2, s3, s4, s5, s6, s7;
+        float rk[4], rp[4];     // the values split for the row reduction
         bool cross = false;        // leaves its cell: general zigzag
         int di, dj;
         float x1, y1, x2, y2, qv;
         if (live) {
-            const float ur = State::ld(S.ur, q), ut = State::ld(S.ut, q), up = State::ld(S.up, q);
             // ---- staggered bilinear gather
             const bool ah = a >= 0.5f, bh = b >= 0.5f;
             int hr = ah ? i : i - 1;
@@ -325,12 +396,16 @@ __device__ __forceinline__ void push_chunk(const P32 &p, const Fields &F, const 
             s5 = s5 - s7;
             s6 = s4 * ym;
             s4 = s4 - s6;
+            rk[0] = b0 ? s4 : s0; rp[0] = b0 ? s0 : s4;
+            rk[1] = b0 ? s5 : s1; rp[1] = b0 ? s1 : s5;
+            rk[2] = b0 ? s6 : s2; rp[2] = b0 ? s2 : s6;
+            rk[3] = b0 ? s7 : s3; rp[3] = b0 ? s3 : s7;
         }
         // ---- in-cell moves that share the cell of the wave's first pending
-        // lane: DPP sums over each 16-lane row, and the first lane of every
-        // row with participants adds the row's sums (the four rows meet in
-        // the same LDS words; two such cells per wave at most, sorted
-        // particles rarely span more)
+        // lane: the eight values are summed over each 16-lane row, and lanes
+        // 0..7 of every row with participants add one sum each (the four
+        // rows meet in the same LDS words; two such cells per wave at most,
+        // sorted particles rarely span more)
         bool pend = simple;
 #pragma unroll 1
         for (int it = 0; it < 2; it++) {
@@ -339,24 +414,18 @@ __device__ __forceinline__ void push_chunk(const P32 &p, const Fields &F, const 
             const int lc = __builtin_amdgcn_readlane(c, __ffsll((long long)m) - 1);
             const bool part = pend && c == lc;
             const unsigned long long pm = __ballot(part);
-            const float v0 = row_sum(part ? s0 : 0.f);
-            const float v1 = row_sum(part ? s1 : 0.f);
-            const float v2 = row_sum(part ? s2 : 0.f);
-            const float v3 = row_sum(part ? s3 : 0.f);
-            const float v4 = row_sum(part ? s4 : 0.f);
-            const float v5 = row_sum(part ? s5 : 0.f);
-            const float v6 = row_sum(part ? s6 : 0.f);
-            const float v7 = row_sum(part ? s7 : 0.f);
-            if ((lane & 15) == 0 && ((pm >> lane) & 0xffffull) != 0ull) {
-                const int li = lc >> 16, lj = lc & 0xffff;
-                acc.add(0, li, lj, v0);
-                acc.add(0, li, lj + 1, v1);
-                acc.add(1, li, lj, v2);
-                acc.add(1, li + 1, lj, v3);
-                acc.add(2, li, lj, v4);
-                acc.add(2, li + 1, lj, v5);
-                acc.add(2, li, lj + 1, v6);
-                acc.add(2, li + 1, lj + 1, v7);
+            float pk[4], pp[4];
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                pk[e] = part ? rk[e] : 0.f;
+                pp[e] = part ? rp[e] : 0.f;
+            }
+            const float v = row_sum8(pk, pp, b1, b2);
+            if (row_lead && ((pm >> (lane & 48)) & 0xffffull) != 0ull) {
+                const int li = (lc >> 16) + kdi, lj = (lc & 0xffff) + kdj;
+                if (LDS) acc.add(kcomp, li, lj, v);
+                else gadd(reinterpret_cast<float *>(reinterpret_cast<char *>(kg) +
+                                                    ((unsigned)(li * acc.ld + lj) << 2)), v);
             }
             pend = pend && !part;
         }
@@ -370,40 +439,41 @@ __device__ __forceinline__ void push_chunk(const P32 &p, const Fields &F, const 
             acc.add(2, i, j + 1, s6);
             acc.add(2, i + 1, j + 1, s7);
         }
-        if (cross) {
-            // general zigzag (the particle leaves its cell)
-            const int i2 = i + di, j2 = j + dj;
-            const float xr = fminf((float)min(di, 0) + 1.f, fmaxf((float)max(di, 0), 0.5f * (x1 + x2)));
-            const float yr = fminf((float)min(dj, 0) + 1.f, fmaxf((float)max(dj, 0), 0.5f * (y1 + y2)));
-            const float Q = p.Q;
-            const float fx1 = Q * (xr - x1), fy1 = Q * (yr - y1);
-            const float fx2 = Q * (x2 - xr), fy2 = Q * (y2 - yr);
-            const float wx1 = 0.5f * (x1 + xr), wy1 = 0.5f * (y1 + yr);
-            const float wx2 = 0.5f * (xr + x2) - (float)di, wy2 = 0.5f * (yr + y2) - (float)dj;
-            acc.add(0, i, j, fx1 * (1.f - wy1));
-            acc.add(0, i, j + 1, fx1 * wy1);
-            acc.add(1, i, j, fy1 * (1.f - wx1));
-            acc.add(1, i + 1, j, fy1 * wx1);
-            acc.add(0, i2, j2, fx2 * (1.f - wy2));
-            acc.add(0, i2, j2 + 1, fx2 * wy2);
-            acc.add(1, i2, j2, fy2 * (1.f - wx2));
-            acc.add(1, i2 + 1, j2, fy2 * wx2);
-            const float xm = 0.5f * (x1 + x2), ym = 0.5f * (y1 + y2);
-            int im = (int)floorf(xm), jm = (int)floorf(ym);
-            if (i + im > p.nr - 1) im = p.nr - 1 - i;
-            if (j + jm > nth - 1) jm = nth - 1 - j;
-            const float wx = xm - (float)im, wy = ym - (float)jm;
-            const float qq = Q * qv;
-            acc.add(2, i + im, j + jm, qq * (1.f - wx) * (1.f - wy));
-            acc.add(2, i + im + 1, j + jm, qq * wx * (1.f - wy));
-            acc.add(2, i + im, j + jm + 1, qq * (1.f - wx) * wy);
-            acc.add(2, i + im + 1, j + jm + 1, qq * wx * wy);
+        // moves that leave their cell go to the workgroup's queue and are
+        // deposited after the chunk, where one wave takes them all instead of
+        // every wave that holds one running the zigzag with a few lanes
+        const unsigned long long cm = __ballot(cross);
+        if (cm != 0ull) {
+            int e0 = 0;
+            if (lane == 0) e0 = atomicAdd(qn, __popcll(cm));
+            e0 = __builtin_amdgcn_readfirstlane(e0);
+            if (cross) {
+                const int e = e0 + (int)__builtin_amdgcn_mbcnt_hi(
+                                       (unsigned)(cm >> 32),
+                                       __builtin_amdgcn_mbcnt_lo((unsigned)cm, 0u));
+                if (e < kQueue) {
+                    queue[2 * e] = make_float4(__int_as_float(c),
+                                               __int_as_float((di + 1) | ((dj + 1) << 2)), x1, y1);
+                    queue[2 * e + 1] = make_float4(x2, y2, qv, 0.f);
+                } else {
+                    zigzag(p, acc, i, j, di, dj, x1, y1, x2, y2, qv);
+                }
+            }
         }
+    }
+    __syncthreads();
+    const int nq = min(*qn, kQueue);
+    if (tid < nq) {
+        const float4 r0 = queue[2 * tid], r1 = queue[2 * tid + 1];
+        const int c = __float_as_int(r0.x), dd = __float_as_int(r0.y);
+        zigzag(p, acc, c >> 16, c & 0xffff, (dd & 3) - 1, ((dd >> 2) & 3) - 1, r0.z, r0.w, r1.x,
+               r1.y, r1.z);
     }
 }
 
+// six waves per SIMD: the prefetched momentum fits in 80 VGPRs without spills
 template <bool SHELL>
-__global__ void __launch_bounds__(kWG) k_push32(
+__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(6, 8))) k_push32(
     P32 p, int nub, const int32_t *__restrict__ nslots, const uint8_t *__restrict__ kill,
     const float *__restrict__ Er, const float *__restrict__ Et, const float *__restrict__ Ep,
     const float *__restrict__ Br, const float *__restrict__ Bt, const float *__restrict__ Bp,
@@ -412,7 +482,9 @@ __global__ void __launch_bounds__(kWG) k_push32(
     float *__restrict__ Jr, float *__restrict__ Jt, float *__restrict__ Jp,
     unsigned long long *__restrict__ removed, uint32_t *__restrict__ err) {
     __shared__ float tile[3 * kTile];
+    __shared__ float4 queue[2 * kQueue];
     __shared__ int box[4];
+    __shared__ int qn;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int n = min(nub, nslots[0]);
@@ -425,16 +497,9 @@ __global__ void __launch_bounds__(kWG) k_push32(
     F.br = __builtin_amdgcn_make_buffer_rsrc((void *)Br, 0, nbytes, kRsrcWord3);
     F.bt = __builtin_amdgcn_make_buffer_rsrc((void *)Bt, 0, nbytes, kRsrcWord3);
     F.bp = __builtin_amdgcn_make_buffer_rsrc((void *)Bp, 0, nbytes, kRsrcWord3);
-    // slots are below 2^30 (the capacity limit), so the byte offset q * 4 and
-    // the range fit the 32 unsigned bits of a buffer resource
-    const int sbytes = (int)(unsigned)min((unsigned long long)nub * 4ull, 0xffffffffull);
-    State S;
-    S.cell = __builtin_amdgcn_make_buffer_rsrc((void *)CELL, 0, sbytes, kRsrcWord3);
-    S.a = __builtin_amdgcn_make_buffer_rsrc((void *)A, 0, sbytes, kRsrcWord3);
-    S.b = __builtin_amdgcn_make_buffer_rsrc((void *)Bo, 0, sbytes, kRsrcWord3);
-    S.ur = __builtin_amdgcn_make_buffer_rsrc((void *)UR, 0, sbytes, kRsrcWord3);
-    S.ut = __builtin_amdgcn_make_buffer_rsrc((void *)UT, 0, sbytes, kRsrcWord3);
-    S.up = __builtin_amdgcn_make_buffer_rsrc((void *)UP, 0, sbytes, kRsrcWord3);
+    // slots are below 2^30 (the capacity limit), so the byte offset q * 4
+    // fits 32 unsigned bits
+    const State S{CELL, A, Bo, UR, UT, UP};
 
     // cells of the chunk and their bounding box
     int cell[kPPT];
@@ -449,7 +514,10 @@ __global__ void __launch_bounds__(kWG) k_push32(
             jmin = min(jmin, j); jmax = max(jmax, j);
         }
     }
-    if (tid == 0) { box[0] = 1 << 30; box[1] = -1; box[2] = 1 << 30; box[3] = -1; }
+    if (tid == 0) {
+        box[0] = 1 << 30; box[1] = -1; box[2] = 1 << 30; box[3] = -1;
+        qn = 0;
+    }
     __syncthreads();
     for (int o = 32; o >= 1; o >>= 1) {
         imin = min(imin, __shfl_xor(imin, o, 64));
@@ -477,7 +545,7 @@ __global__ void __launch_bounds__(kWG) k_push32(
         __syncthreads();
         Acc<true> acc{tile, ti0, tj0, TJ, {Jr, Jt, Jp}, p.ld};
         push_chunk<true, SHELL>(p, F, acc, cell, base, tid, lane, kill, S, err, nkill, nstar,
-                                nabs);
+                                nabs, queue, &qn, nullptr);
         __syncthreads();
         for (int e = tid; e < m; e += kWG) {
             const int ti = e / TJ, tj = e - ti * TJ;
@@ -491,8 +559,10 @@ __global__ void __launch_bounds__(kWG) k_push32(
         }
     } else {
         Acc<false> acc{nullptr, 0, 0, 0, {Jr, Jt, Jp}, p.ld};
+        const int kc = lane_comp(lane);
+        float *kg = kc == 0 ? Jr : (kc == 1 ? Jt : Jp);
         push_chunk<false, SHELL>(p, F, acc, cell, base, tid, lane, kill, S, err, nkill, nstar,
-                                 nabs);
+                                 nabs, queue, &qn, kg);
     }
     int tk = nkill, ts = nstar, ta = nabs;
     for (int o = 32; o >= 1; o >>= 1) {
