@@ -44,7 +44,8 @@ namespace ffpic {
 constexpr int kWG = 256;
 constexpr int kPPT = 4;                  // particles per thread per chunk
 constexpr int kChunk = kWG * kPPT;
-constexpr int kTile = 2048;              // LDS patch entries per component
+constexpr int kTile = 1024;              // LDS deposit patch entries per component
+constexpr int kFld = 512;                // LDS field patch nodes (six components each)
 constexpr int kQueue = 64;               // queued cell-crossing moves per workgroup
 constexpr int kRsrcWord3 = 0x00020000;   // raw dword buffer access (gfx9 family)
 
@@ -61,6 +62,9 @@ struct P32 {
 
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
+// index products: both factors are grid or patch indices below 2^24 and the
+// products stay below 2^32, so the full-rate 24-bit multiply is exact
+__device__ __forceinline__ unsigned mul24(int x, unsigned y) { return __umul24((unsigned)x, y); }
 
 // 32-bit element offsets from a uniform base (element index < 2^30)
 template <typename T>
@@ -125,9 +129,9 @@ struct Acc {
     float *g[3];
     int ld;
     __device__ __forceinline__ void add(int comp, int i, int j, float v) const {
-        if (LDS) atomicAdd(&tile[comp * kTile + (i - ti0) * TJ + (j - tj0)], v);
+        if (LDS) atomicAdd(&tile[comp * kTile + mul24(i - ti0, TJ) + (j - tj0)], v);
         else gadd(reinterpret_cast<float *>(reinterpret_cast<char *>(g[comp]) +
-                                            ((unsigned)(i * ld + j) << 2)), v);
+                                            ((mul24(i, ld) + (unsigned)j) << 2)), v);
     }
 };
 
@@ -180,9 +184,31 @@ __device__ __forceinline__ void zigzag(const P32 &p, const Acc<LDS> &acc, int i,
     acc.add(2, i + im + 1, j + jm + 1, qq * wx * wy);
 }
 
+// the same interpolation from the LDS field patch: the node at byte offset
+// o of the patch and the next column, and the same pair one patch row (rowB
+// bytes) further; the six components of a node are interleaved, so COMP
+// selects the word
+template <int COMP>
+__device__ __forceinline__ float bil_lds(const float *fld, unsigned o, unsigned rowB, float W0,
+                                         float W1, float wr) {
+    const float *r0 = reinterpret_cast<const float *>(reinterpret_cast<const char *>(fld) + o) + COMP;
+    const float *r1 =
+        reinterpret_cast<const float *>(reinterpret_cast<const char *>(fld) + o + rowB) + COMP;
+    const float lo = r0[0] * W0 + r0[6] * W1;
+    const float hi = r1[0] * W0 + r1[6] * W1;
+    return lo + wr * (hi - lo);
+}
+
+struct Patch {
+    const float *fld;    // LDS field patch (LDS mode)
+    int fi0, fj0;        // its first row and column
+    unsigned rowB;       // bytes per patch row (24 per node)
+};
+
 template <bool LDS, bool SHELL>
-__device__ __forceinline__ void push_chunk(const P32 &p, const Fields &F, const Acc<LDS> &acc,
-                                           const int *cell, int base, int tid, int lane,
+__device__ __forceinline__ void push_chunk(const P32 &p, const Fields &F, const Patch &P,
+                                           const Acc<LDS> &acc,
+                                           int n, int base, int tid, int lane,
                                            const uint8_t *__restrict__ kill, const State &S,
                                            uint32_t *__restrict__ err, int &nkill, int &nstar,
                                            int &nabs, float4 *queue, int *qn, float *kg) {
@@ -201,8 +227,10 @@ __device__ __forceinline__ void push_chunk(const P32 &p, const Fields &F, const 
     const int kdj = (kq == 1 || kq == 6 || kq == 7) ? 1 : 0;
     const bool row_lead = (lane & 8) == 0;
     float an = 0.f, bn = 0.f, urn = 0.f, utn = 0.f, upn = 0.f;
-    if (cell[0] >= 0) {
+    int cn = -1;
+    if (base + tid < n) {
         const unsigned q0 = (unsigned)(base + tid);
+        cn = S.ldc(q0);
         an = State::ld(S.a, q0);
         bn = State::ld(S.b, q0);
         urn = State::ld(S.ur, q0);
@@ -212,18 +240,20 @@ __device__ __forceinline__ void push_chunk(const P32 &p, const Fields &F, const 
 #pragma unroll 1
     for (int k = 0; k < kPPT; k++) {
         const unsigned q = (unsigned)(base + k * kWG + tid);
-        const int c = cell[k];
+        const int c = cn;
         const bool live = c >= 0;
         const int i = c >> 16, j = c & 0xffff;
         const float a = an, b = bn, ur = urn, ut = utn, up = upn;
-        if (k + 1 < kPPT && cell[k + 1] >= 0) {
+        cn = -1;
+        if (k + 1 < kPPT && (int)(q + kWG) < n) {
+            cn = S.ldc(q + kWG);
             an = State::ld(S.a, q + kWG);
             bn = State::ld(S.b, q + kWG);
             urn = State::ld(S.ur, q + kWG);
             utn = State::ld(S.ut, q + kWG);
             upn = State::ld(S.up, q + kWG);
         }
-        const bool killed = live && kill[(unsigned)(i * nth + j)] != 0;
+        const bool killed = live && kill[mul24(i, nth) + (unsigned)j] != 0;
         // The deposit values below are assigned for every kept particle and
         // read only under `simple` / `cross`, which imply that assignment, so
         // they carry no initial value (no register setup on the other paths).
@@ -242,24 +272,46 @@ __device__ __forceinline__ void push_chunk(const P32 &p, const Fields &F, const 
             if (hr > p.nr - 2) { hr = p.nr - 2; wr = 1.f; }
             const int ht = bh ? j : j - 1;
             const float wt = bh ? b - 0.5f : b + 0.5f;
-            const int c0 = ht < 0 ? 0 : ht;
-            const int c1 = ht + 1 > nth - 1 ? nth - 1 : ht + 1;
-            // theta weights: node columns (j, j+1), half columns (c0, c1);
-            // odd components (E_th, B_ph) carry the axis ghost signs
+            // theta weights: node columns (j, j+1); half columns as the pair
+            // (pb, pb+1), where a particle within half a cell of an axis
+            // reads the one edge column with both weights (the axis ghost
+            // equals it, with the sign flipped for the odd components E_th
+            // and B_ph)
             const float Wn0 = 1.f - b, Wn1 = b;
             const float Wh0 = 1.f - wt, Wh1 = wt;
-            const float Wo0 = ht < 0 ? -Wh0 : Wh0;
-            const float Wo1 = ht + 1 > nth - 1 ? -Wh1 : Wh1;
-            const unsigned rN = (unsigned)(i * ld), rH = (unsigned)(hr * ld);
-            const unsigned on = (rN + j) << 2, hn = (rH + j) << 2;
-            const unsigned oh0 = (rN + c0) << 2, oh1 = (rN + c1) << 2;
-            const unsigned hh0 = (rH + c0) << 2, hh1 = (rH + c1) << 2;
-            const float esr = bil(F.er, hn, hn + 4, ld4, Wn0, Wn1, wr);
-            const float est = bil(F.et, oh0, oh1, ld4, Wo0, Wo1, a);
-            const float esp = bil(F.ep, on, on + 4, ld4, Wn0, Wn1, a);
-            const float bsr = bil(F.br, oh0, oh1, ld4, Wh0, Wh1, a);
-            const float bst = bil(F.bt, hn, hn + 4, ld4, Wn0, Wn1, wr);
-            const float bsp = bil(F.bp, hh0, hh1, ld4, Wo0, Wo1, wr);
+            const bool lo_ax = ht < 0, hi_ax = ht > nth - 2;
+            int pb = ht;
+            float E0 = Wh0, E1 = Wh1, O0 = Wh0, O1 = Wh1;
+            if (__ballot(lo_ax || hi_ax) != 0ull) {   // a wave near an axis (uniform)
+                pb = lo_ax ? 0 : (hi_ax ? nth - 2 : ht);
+                E0 = lo_ax ? Wh0 + Wh1 : (hi_ax ? 0.f : Wh0);
+                E1 = lo_ax ? 0.f : (hi_ax ? Wh0 + Wh1 : Wh1);
+                O0 = lo_ax ? Wh1 - Wh0 : (hi_ax ? 0.f : Wh0);
+                O1 = lo_ax ? 0.f : (hi_ax ? Wh0 - Wh1 : Wh1);
+            }
+            float esr, est, esp, bsr, bst, bsp;
+            if (LDS) {
+                // byte offsets in the patch (24 bytes a node, rowB a row)
+                const unsigned rowB = P.rowB;
+                const unsigned bn = mul24(i - P.fi0, rowB), bh = mul24(hr - P.fi0, rowB);
+                const unsigned cn = mul24(j - P.fj0, 24), ch = mul24(pb - P.fj0, 24);
+                esr = bil_lds<0>(P.fld, bh + cn, rowB, Wn0, Wn1, wr);
+                est = bil_lds<1>(P.fld, bn + ch, rowB, O0, O1, a);
+                esp = bil_lds<2>(P.fld, bn + cn, rowB, Wn0, Wn1, a);
+                bsr = bil_lds<3>(P.fld, bn + ch, rowB, E0, E1, a);
+                bst = bil_lds<4>(P.fld, bh + cn, rowB, Wn0, Wn1, wr);
+                bsp = bil_lds<5>(P.fld, bh + ch, rowB, O0, O1, wr);
+            } else {
+                const unsigned rN = mul24(i, ld), rH = mul24(hr, ld);
+                const unsigned on = (rN + j) << 2, hn = (rH + j) << 2;
+                const unsigned oh = (rN + pb) << 2, hh = (rH + pb) << 2;
+                esr = bil(F.er, hn, hn + 4, ld4, Wn0, Wn1, wr);
+                est = bil(F.et, oh, oh + 4, ld4, O0, O1, a);
+                esp = bil(F.ep, on, on + 4, ld4, Wn0, Wn1, a);
+                bsr = bil(F.br, oh, oh + 4, ld4, E0, E1, a);
+                bst = bil(F.bt, hn, hn + 4, ld4, Wn0, Wn1, wr);
+                bsp = bil(F.bp, hh, hh + 4, ld4, O0, O1, wr);
+            }
             // ---- geometry: theta = theta_j + d (small-angle series), r = r_i exp(a dlog)
             const float d = b * p.dth, d2 = d * d;
             const float sd = d * (1.f - d2 * (1.f / 6.f) * (1.f - d2 * (1.f / 20.f)));
@@ -425,7 +477,7 @@ __device__ __forceinline__ void push_chunk(const P32 &p, const Fields &F, const 
                 const int li = (lc >> 16) + kdi, lj = (lc & 0xffff) + kdj;
                 if (LDS) acc.add(kcomp, li, lj, v);
                 else gadd(reinterpret_cast<float *>(reinterpret_cast<char *>(kg) +
-                                                    ((unsigned)(li * acc.ld + lj) << 2)), v);
+                                                    ((mul24(li, acc.ld) + (unsigned)lj) << 2)), v);
             }
             pend = pend && !part;
         }
@@ -482,6 +534,7 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(6, 8))
     float *__restrict__ Jr, float *__restrict__ Jt, float *__restrict__ Jp,
     unsigned long long *__restrict__ removed, uint32_t *__restrict__ err) {
     __shared__ float tile[3 * kTile];
+    __shared__ float fld[6 * kFld];
     __shared__ float4 queue[2 * kQueue];
     __shared__ int box[4];
     __shared__ int qn;
@@ -489,27 +542,18 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(6, 8))
     const int lane = tid & 63;
     const int n = min(nub, nslots[0]);
     const int base = blockIdx.x * kChunk;
-    const int nbytes = (p.nr + 1) * p.ld * 4;
-    Fields F;
-    F.er = __builtin_amdgcn_make_buffer_rsrc((void *)Er, 0, nbytes, kRsrcWord3);
-    F.et = __builtin_amdgcn_make_buffer_rsrc((void *)Et, 0, nbytes, kRsrcWord3);
-    F.ep = __builtin_amdgcn_make_buffer_rsrc((void *)Ep, 0, nbytes, kRsrcWord3);
-    F.br = __builtin_amdgcn_make_buffer_rsrc((void *)Br, 0, nbytes, kRsrcWord3);
-    F.bt = __builtin_amdgcn_make_buffer_rsrc((void *)Bt, 0, nbytes, kRsrcWord3);
-    F.bp = __builtin_amdgcn_make_buffer_rsrc((void *)Bp, 0, nbytes, kRsrcWord3);
     // slots are below 2^30 (the capacity limit), so the byte offset q * 4
     // fits 32 unsigned bits
     const State S{CELL, A, Bo, UR, UT, UP};
 
-    // cells of the chunk and their bounding box
-    int cell[kPPT];
+    // bounding box of the chunk's cells
     int imin = 1 << 30, imax = -1, jmin = 1 << 30, jmax = -1;
 #pragma unroll
     for (int k = 0; k < kPPT; k++) {
         const int q = base + k * kWG + tid;
-        cell[k] = q < n ? S.ldc((unsigned)q) : -1;
-        if (cell[k] >= 0) {
-            const int i = cell[k] >> 16, j = cell[k] & 0xffff;
+        const int ck = q < n ? S.ldc((unsigned)q) : -1;
+        if (ck >= 0) {
+            const int i = ck >> 16, j = ck & 0xffff;
             imin = min(imin, i); imax = max(imax, i);
             jmin = min(jmin, j); jmax = max(jmax, j);
         }
@@ -535,16 +579,32 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(6, 8))
     // every add of a particle that moves at most one cell lands inside
     const int ti0 = box[0] - 1, tj0 = box[2] - 1;
     const int TI = box[1] - box[0] + 4, TJ = box[3] - box[2] + 4;
-    const bool use_lds = TI * TJ <= kTile;
+    // the field patch: rows [imin-1, imax+1] and columns [jmin-1, jmax+1]
+    // within the grid hold every node the chunk's gathers read
+    const int fi0 = max(box[0] - 1, 0), fj0 = max(box[2] - 1, 0);
+    const int TIf = min(box[1] + 1, p.nr) - fi0 + 1, TJf = min(box[3] + 1, p.nth) - fj0 + 1;
+    const bool use_lds = TI * TJ <= kTile && TIf * TJf <= kFld;
     int nkill = 0, nstar = 0, nabs = 0;
     if (use_lds) {
         const int m = TI * TJ;
         for (int e = tid; e < m; e += kWG) {
             tile[e] = 0.f; tile[kTile + e] = 0.f; tile[2 * kTile + e] = 0.f;
         }
+        const int mf = TIf * TJf;
+        for (int e = tid; e < mf; e += kWG) {
+            const int ti = e / TJf, tj = e - ti * TJf;
+            const unsigned g = (unsigned)((fi0 + ti) * p.ld + fj0 + tj);
+            fld[e * 6 + 0] = ldo(Er, g);
+            fld[e * 6 + 1] = ldo(Et, g);
+            fld[e * 6 + 2] = ldo(Ep, g);
+            fld[e * 6 + 3] = ldo(Br, g);
+            fld[e * 6 + 4] = ldo(Bt, g);
+            fld[e * 6 + 5] = ldo(Bp, g);
+        }
         __syncthreads();
+        const Patch P{fld, fi0, fj0, (unsigned)TJf * 24u};
         Acc<true> acc{tile, ti0, tj0, TJ, {Jr, Jt, Jp}, p.ld};
-        push_chunk<true, SHELL>(p, F, acc, cell, base, tid, lane, kill, S, err, nkill, nstar,
+        push_chunk<true, SHELL>(p, Fields{}, P, acc, n, base, tid, lane, kill, S, err, nkill, nstar,
                                 nabs, queue, &qn, nullptr);
         __syncthreads();
         for (int e = tid; e < m; e += kWG) {
@@ -558,10 +618,21 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(6, 8))
             if (v2 != 0.f) gadd(reinterpret_cast<float *>(reinterpret_cast<char *>(Jp) + g), v2);
         }
     } else {
+        // the gather reads the fields through buffer resources in this mode
+        // (nr + 1) * ld stays near the 2^29-node grid limit, so the byte count
+        // fits 32 unsigned bits
+        const int nbytes = (int)((unsigned)(p.nr + 1) * (unsigned)p.ld * 4u);
+        Fields F;
+        F.er = __builtin_amdgcn_make_buffer_rsrc((void *)Er, 0, nbytes, kRsrcWord3);
+        F.et = __builtin_amdgcn_make_buffer_rsrc((void *)Et, 0, nbytes, kRsrcWord3);
+        F.ep = __builtin_amdgcn_make_buffer_rsrc((void *)Ep, 0, nbytes, kRsrcWord3);
+        F.br = __builtin_amdgcn_make_buffer_rsrc((void *)Br, 0, nbytes, kRsrcWord3);
+        F.bt = __builtin_amdgcn_make_buffer_rsrc((void *)Bt, 0, nbytes, kRsrcWord3);
+        F.bp = __builtin_amdgcn_make_buffer_rsrc((void *)Bp, 0, nbytes, kRsrcWord3);
         Acc<false> acc{nullptr, 0, 0, 0, {Jr, Jt, Jp}, p.ld};
         const int kc = lane_comp(lane);
         float *kg = kc == 0 ? Jr : (kc == 1 ? Jt : Jp);
-        push_chunk<false, SHELL>(p, F, acc, cell, base, tid, lane, kill, S, err, nkill, nstar,
+        push_chunk<false, SHELL>(p, F, Patch{nullptr, 0, 0, 0u}, acc, n, base, tid, lane, kill, S, err, nkill, nstar,
                                  nabs, queue, &qn, kg);
     }
     int tk = nkill, ts = nstar, ta = nabs;
