@@ -476,18 +476,37 @@ __global__ void k_mover_offsets(const uint32_t *__restrict__ tot, const uint32_t
     moff[k] = lo;
 }
 
-// stayers: slot q with key k goes to SB[q] + moff[k] + (movers of key k
-// from a slot below q)
+// mst[k] = moff[k] + (movers of key k from a slot below OFF[k]).  A stayer
+// of key k sits in the old range [OFF[k], OFF[k+1]) of its key, and no mover
+// of key k does (its key changed, or it was appended after the sort), so
+// every stayer of key k has the same movers of its key before it: mst[k].
+__global__ void k_mover_start(int nkeys, const int32_t *__restrict__ moff,
+                              const int32_t *__restrict__ offold,
+                              const uint32_t *__restrict__ mval, int32_t *__restrict__ mst) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > nkeys) return;
+    int lo = moff[k];
+    if (k < nkeys) {
+        int hi = moff[k + 1];
+        const int q0 = offold[k];
+        while (lo < hi) {                 // movers of this key are in slot order
+            const int mid = (lo + hi) >> 1;
+            if ((int)mval[mid] < q0) lo = mid + 1; else hi = mid;
+        }
+    }
+    mst[k] = lo;
+}
+
+// stayers: slot q with key k goes to SB[q] + mst[k]
 // One kernel places both classes: the first nbm blocks stride over the
 // sorted movers (dispatched first, so their dependent loads overlap the
 // streaming copy), the remaining blocks take one slot per thread (stayers).
-//   stayer: slot q with key k goes to SB[q] + moff[k] + (movers of key k
-//           from a slot below q);
+//   stayer: slot q with key k goes to SB[q] + mst[k];
 //   mover:  rank j (key k, slot q) goes to j + SB[clamp(q, OFF[k], OFF[k+1])].
 template <typename T, int NA>
 __global__ void k_scatter(int nub, int nbm, const uint32_t *__restrict__ keys, uint32_t dead,
                           const int32_t *__restrict__ nold, const uint32_t *__restrict__ kold,
-                          const uint32_t *__restrict__ sb, const int32_t *__restrict__ moff,
+                          const uint32_t *__restrict__ sb, const int32_t *__restrict__ mst,
                           const uint32_t *__restrict__ tot, const uint32_t *__restrict__ mkey,
                           const uint32_t *__restrict__ mval, const int32_t *__restrict__ offold,
                           uint32_t *__restrict__ knew, PtrSet<T, NA> P) {
@@ -514,13 +533,7 @@ __global__ void k_scatter(int nub, int nbm, const uint32_t *__restrict__ keys, u
     for (int a = 0; a < NA; a++) v[a] = P.src[a][q];
     const uint32_t key = keys[q];
     if (slot_class(key, dead, q, nold[0], kold) != 1) return;
-    int lo = moff[key];
-    int hi = moff[key + 1];
-    while (lo < hi) {                     // movers of this key are in slot order
-        const int mid = (lo + hi) >> 1;
-        if ((int)mval[mid] < q) lo = mid + 1; else hi = mid;
-    }
-    const uint32_t d = sb[q] + (uint32_t)lo;
+    const uint32_t d = sb[q] + (uint32_t)mst[key];
 #pragma unroll
     for (int a = 0; a < NA; a++) P.dst[a][d] = v[a];
     knew[d] = key;
@@ -529,7 +542,7 @@ __global__ void k_scatter(int nub, int nbm, const uint32_t *__restrict__ keys, u
 // FP32 variant of the scatter: a stayer's class from the byte array and its
 // key from its cell (the first state array)
 __global__ void k_scatter32(int nub, int nbm, int nth, const uint8_t *__restrict__ cls,
-                            const uint32_t *__restrict__ sb, const int32_t *__restrict__ moff,
+                            const uint32_t *__restrict__ sb, const int32_t *__restrict__ mst,
                             const uint32_t *__restrict__ tot, const uint32_t *__restrict__ mkey,
                             const uint32_t *__restrict__ mval, const int32_t *__restrict__ offold,
                             uint32_t *__restrict__ knew, PtrSet<uint32_t, 6> P) {
@@ -555,13 +568,7 @@ __global__ void k_scatter32(int nub, int nbm, int nth, const uint8_t *__restrict
     if (cls[q] != 1) return;
     const int cell = (int)v[0];
     const uint32_t key = (uint32_t)(cell >> 16) * (uint32_t)nth + (uint32_t)(cell & 0xffff);
-    int lo = moff[key];
-    int hi = moff[key + 1];
-    while (lo < hi) {                     // movers of this key are in slot order
-        const int mid = (lo + hi) >> 1;
-        if ((int)mval[mid] < q) lo = mid + 1; else hi = mid;
-    }
-    const uint32_t d = sb[q] + (uint32_t)lo;
+    const uint32_t d = sb[q] + (uint32_t)mst[key];
 #pragma unroll
     for (int a = 0; a < 6; a++) P.dst[a][d] = v[a];
     knew[d] = key;
@@ -698,17 +705,19 @@ static void sort_incremental(ffpic_ctx *c, int s) {
     }
     hipLaunchKernelGGL(k_mover_offsets, dim3((nkeys + 1 + 255) / 256), dim3(256), 0, c->stream,
                        c->sort_tot, mkey2, nkeys, c->sort_moff);
+    hipLaunchKernelGGL(k_mover_start, dim3((nkeys + 1 + 255) / 256), dim3(256), 0, c->stream,
+                       nkeys, c->sort_moff, offold, mval2, c->sort_mst);
     uint32_t *knew = c->skey[s][1 - t];
     int32_t *offnew = c->soff[s][1 - t];
     const int nbs = (nub + 255) / 256;
     const int nbm = std::max(1, std::min((int)((m + 255) / 256), 4096));
     if (c->fp64) {
         hipLaunchKernelGGL((k_scatter<uint64_t, 5>), dim3(nbs + nbm), dim3(256), 0, c->stream,
-                           nub, nbm, c->keys[0], dead, nold, kold, c->sort_sb, c->sort_moff,
+                           nub, nbm, c->keys[0], dead, nold, kold, c->sort_sb, c->sort_mst,
                            c->sort_tot, mkey2, mval2, offold, knew, (state_ptrs<uint64_t, 5>(S)));
     } else {
         hipLaunchKernelGGL(k_scatter32, dim3(nbs + nbm), dim3(256), 0, c->stream, nub, nbm,
-                           c->nth, c->sort_cls, c->sort_sb, c->sort_moff, c->sort_tot, mkey2,
+                           c->nth, c->sort_cls, c->sort_sb, c->sort_mst, c->sort_tot, mkey2,
                            mval2, offold, knew, (state_ptrs<uint32_t, 6>(S)));
     }
     // reads the old live count before replacing it with the new one
