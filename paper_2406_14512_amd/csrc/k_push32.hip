@@ -29,9 +29,9 @@
 // box of its cells and accumulates the currents in an LDS patch covering the
 // box plus the one-cell reach of a step; the patch is then flushed to the
 // FP32 current arrays in HBM with one global atomic per non-zero entry.
-// Particles that stay in their cell and share it with the wavefront's
-// leader are summed across each 16-lane row first (DPP), so a sorted wave
-// issues one add instruction from 32 lanes (eight sums in each of four rows)
+// Particles that stay in their cell are summed across each 16-lane row
+// first (DPP), one cell per row and pass, so a sorted wave issues one add
+// instruction from 32 lanes (eight sums in each of four rows) per pass
 // instead of eight from all 64.  Moves that leave their cell (a few per
 // cent of a step) are queued in LDS and deposited after the chunk, so the
 // zigzag runs in one wave per chunk rather than in nearly every wave.
@@ -453,17 +453,22 @@ __device__ __forceinline__ void push_chunk(const P32 &p, const Fields &F, const 
             rk[2] = b0 ? s6 : s2; rp[2] = b0 ? s2 : s6;
             rk[3] = b0 ? s7 : s3; rp[3] = b0 ? s3 : s7;
         }
-        // ---- in-cell moves that share the cell of the wave's first pending
-        // lane: the eight values are summed over each 16-lane row, and lanes
-        // 0..7 of every row with participants add one sum each (the four
-        // rows meet in the same LDS words; two such cells per wave at most,
-        // sorted particles rarely span more)
+        // ---- in-cell moves, one cell per 16-lane row and pass: the lanes of
+        // a row whose cell is that of the row's first pending lane sum their
+        // eight values over the row, and lanes 0..7 of the row add one sum
+        // each.  Every pass retires at least the first pending lane of each
+        // row, so the loop ends within 16 passes with every in-cell move
+        // deposited.  (Sorted particles drift into neighbouring cells between
+        // sorts, so a wave holds several cells; the passes with few lanes
+        // still cost less than per-lane adds.)
         bool pend = simple;
 #pragma unroll 1
-        for (int it = 0; it < 2; it++) {
+        while (true) {
             const unsigned long long m = __ballot(pend);
             if (m == 0ull) break;
-            const int lc = __builtin_amdgcn_readlane(c, __ffsll((long long)m) - 1);
+            const unsigned rowm = (unsigned)(m >> (lane & 48)) & 0xffffu;
+            const int src = rowm ? (lane & 48) + __builtin_ctz(rowm) : lane;
+            const int lc = __shfl(c, src, 64);
             const bool part = pend && c == lc;
             const unsigned long long pm = __ballot(part);
             float pk[4], pp[4];
@@ -480,16 +485,6 @@ __device__ __forceinline__ void push_chunk(const P32 &p, const Fields &F, const 
                                                     ((mul24(li, acc.ld) + (unsigned)lj) << 2)), v);
             }
             pend = pend && !part;
-        }
-        if (pend) {
-            acc.add(0, i, j, s0);
-            acc.add(0, i, j + 1, s1);
-            acc.add(1, i, j, s2);
-            acc.add(1, i + 1, j, s3);
-            acc.add(2, i, j, s4);
-            acc.add(2, i + 1, j, s5);
-            acc.add(2, i, j + 1, s6);
-            acc.add(2, i + 1, j + 1, s7);
         }
         // moves that leave their cell go to the workgroup's queue and are
         // deposited after the chunk, where one wave takes them all instead of
