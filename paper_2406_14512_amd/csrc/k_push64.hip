@@ -92,6 +92,23 @@ __device__ __forceinline__ double row_sum64(double v) {
     return v;
 }
 
+// Sums eight per-lane values over each 16-lane row, halving the number of
+// values at every stage (exchange with lane^1, lane^2, a rotation by four
+// lanes, a rotation by eight).  Lane l then holds the row sum of value
+// 4*bit0(l) + 2*bit1(l) + bit2(l); keep[] are the four values a lane sums in
+// the first stage (values 4..7 on lanes with bit 0 set, 0..3 otherwise),
+// pass[] the four its neighbour sums.
+__device__ __forceinline__ double row_sum8_64(const double keep[4], const double pass[4], bool b1,
+                                              bool b2) {
+    double y[4];
+#pragma unroll
+    for (int m = 0; m < 4; m++) y[m] = keep[m] + dpp64<0xB1>(pass[m]);
+    const double z0 = (b1 ? y[2] : y[0]) + dpp64<0x4E>(b1 ? y[0] : y[2]);
+    const double z1 = (b1 ? y[3] : y[1]) + dpp64<0x4E>(b1 ? y[1] : y[3]);
+    const double w = (b2 ? z1 : z0) + dpp64<0x124>(b2 ? z0 : z1);
+    return w + dpp64<0x128>(w);
+}
+
 struct Acc64 {
     double *tile;    // nullptr: global mode
     int ti0, tj0, TJ;
@@ -148,6 +165,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
     const int TI = box[1] - box[0] + 4, TJ = box[3] - box[2] + 4;
     const bool use_lds = TI * TJ <= kTile64;
     Acc64 acc{use_lds ? tile : nullptr, ti0, tj0, TJ, {Jr, Jt, Jp}, p.ld};
+    // the deposit value this lane adds after the row reduction: component,
+    // radial and polar node offsets from the cell (values 0..7 of s[] below)
+    const int rl = lane & 15;
+    const bool b0 = rl & 1, b1 = rl & 2, b2 = rl & 4;
+    const int kq = (b0 ? 4 : 0) + (b1 ? 2 : 0) + (b2 ? 1 : 0);
+    const int kcomp = kq < 2 ? 0 : (kq < 4 ? 1 : 2);
+    const int kdi = (kq == 3 || kq == 5 || kq == 7) ? 1 : 0;
+    const int kdj = (kq == 1 || kq == 6 || kq == 7) ? 1 : 0;
+    double *kg = kcomp == 0 ? Jr : (kcomp == 1 ? Jt : Jp);   // global mode
     if (use_lds) {
         for (int e = tid; e < TI * TJ; e += 256) {
             tile[e] = 0.0; tile[kTile64 + e] = 0.0; tile[2 * kTile64 + e] = 0.0;
@@ -247,41 +273,41 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
             }
         }
     }
-    // same-cell in-cell moves: sums over each 16-lane row, and the first lane
-    // of every row with participants adds its row's sums
+    // ---- in-cell moves, one cell per 16-lane row and pass: the lanes of a
+    // row whose cell is that of the row's first pending lane sum their eight
+    // values over the row, and lanes 0..7 of the row add one sum each.  Every
+    // pass retires at least the first pending lane of each row, so the loop
+    // ends within 16 passes with every in-cell move deposited.
     bool pend = simple;
     const int c = (i << 16) | j;
+    double rk[4], rp[4];
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+        rk[e] = b0 ? s[4 + e] : s[e];
+        rp[e] = b0 ? s[e] : s[4 + e];
+    }
 #pragma unroll 1
-    for (int it = 0; it < 2; it++) {
-        unsigned long long m = __ballot(pend);
+    while (true) {
+        const unsigned long long m = __ballot(pend);
         if (m == 0ull) break;
-        int lc = __builtin_amdgcn_readlane(c, __ffsll((long long)m) - 1);
-        bool part = pend && c == lc;
+        const unsigned rowm = (unsigned)(m >> (lane & 48)) & 0xffffu;
+        const int src = rowm ? (lane & 48) + __builtin_ctz(rowm) : lane;
+        const int lc = __shfl(c, src, 64);
+        const bool part = pend && c == lc;
         const unsigned long long pm = __ballot(part);
-        double v[8];
-        for (int k = 0; k < 8; k++) v[k] = row_sum64(part ? s[k] : 0.0);
-        if ((lane & 15) == 0 && ((pm >> lane) & 0xffffull) != 0ull) {
-            int li = lc >> 16, lj = lc & 0xffff;
-            acc.add(0, li, lj, v[0]);
-            acc.add(0, li, lj + 1, v[1]);
-            acc.add(1, li, lj, v[2]);
-            acc.add(1, li + 1, lj, v[3]);
-            acc.add(2, li, lj, v[4]);
-            acc.add(2, li + 1, lj, v[5]);
-            acc.add(2, li, lj + 1, v[6]);
-            acc.add(2, li + 1, lj + 1, v[7]);
+        double pk[4], pp[4];
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            pk[e] = part ? rk[e] : 0.0;
+            pp[e] = part ? rp[e] : 0.0;
+        }
+        const double v = row_sum8_64(pk, pp, b1, b2);
+        if ((lane & 8) == 0 && ((pm >> (lane & 48)) & 0xffffull) != 0ull) {
+            const int li = (lc >> 16) + kdi, lj = (lc & 0xffff) + kdj;
+            if (acc.tile) atomicAdd(&tile[kcomp * kTile64 + (li - ti0) * TJ + (lj - tj0)], v);
+            else gadd(&kg[ix(p.ld, li, lj)], v);
         }
         pend = pend && !part;
-    }
-    if (pend) {
-        acc.add(0, i, j, s[0]);
-        acc.add(0, i, j + 1, s[1]);
-        acc.add(1, i, j, s[2]);
-        acc.add(1, i + 1, j, s[3]);
-        acc.add(2, i, j, s[4]);
-        acc.add(2, i + 1, j, s[5]);
-        acc.add(2, i, j + 1, s[6]);
-        acc.add(2, i + 1, j + 1, s[7]);
     }
     if (cross) {
         // general zigzag in coordinates relative to the start cell
