@@ -129,6 +129,34 @@ def test_push_and_deposit_one_step_fp64():
         assert rel(sim.field(gc), ora.field(oc)) < FP64_TOL
 
 
+@pytest.mark.parametrize("band", [(3.0, 9.0), (1.05, 1.6)])
+def test_push_and_deposit_one_step_fp32(band):
+    """One FP32-mixed push against the FP64 oracle.  The (3, 9) band puts
+    about 2.4 cells in a 64-particle wave (the in-cell deposit takes several
+    passes); the band next to the star has about a fifth of the particles
+    crossing a cell in the step, more than the workgroup's queue of
+    cell-crossing moves holds, so the inline zigzag runs as well."""
+    w = W.tiny_dipole(50_000)
+    w.sheet_rmin, w.sheet_rmax = band
+    sim, ora = pair(w, W.FP32_MIXED)
+    load_both(sim, ora, w)
+    sim.run_phases(ffpic.PHASE_PUSH)
+    ora.phases(oracle.PHASE_PUSH)
+    for s in range(2):
+        g, o = sim.particles(s), ora.particles(s)
+        live = o["cell"] >= 0
+        # FP32 positions can put a particle within rounding of an edge on the
+        # other side of it
+        assert np.mean(g["cell"] != o["cell"]) < 1e-3
+        same = live & (g["cell"] == o["cell"])
+        for k in ("ur", "uth", "uph"):
+            assert np.allclose(g[k][same], o[k][same], rtol=1e-5, atol=1e-5 * np.abs(o[k]).max()), k
+    for gc, oc in ((ffpic.JR, oracle.JR), (ffpic.JTH, oracle.JTH), (ffpic.JPH, oracle.JPH)):
+        e = rel(sim.field(gc), ora.field(oc))
+        print("FP32 deposit error", band, gc, e)
+        assert e < 1e-4, (gc, e)
+
+
 def test_field_step_fp64():
     w = W.tiny_open_dipole(50_000)
     sim, ora = pair(w)
