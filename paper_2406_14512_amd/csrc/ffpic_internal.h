@@ -118,6 +118,8 @@ struct ffpic_ctx {
     uint8_t *sort_cls = nullptr;              // FP32: class of each slot [cap]
     int32_t *sort_moff = nullptr;             // movers below each key [nr*nth + 1]
     int32_t *sort_mst = nullptr;              // movers before each key's stayers [nr*nth + 1]
+    uint32_t *sort_cbuf = nullptr;            // FP32: non-stayers' state, compacted [6 * cbuf_n]
+    int64_t sort_cbuf_n = 0;
     uint32_t *sort_tot = nullptr;             // stayers, movers
     void *scan_tmp = nullptr;
     size_t scan_tmp_bytes = 0;

@@ -574,6 +574,57 @@ __global__ void k_scatter32(int nub, int nbm, int nth, const uint8_t *__restrict
     knew[d] = key;
 }
 
+// The same placement in two passes, for sorts whose non-stayers fit the
+// compact buffer.  The stayer pass reads every slot once (coalesced), places
+// the stayers, and copies the state of each mover to the buffer at q - SB[q]
+// (the non-stayers before q), so the movers' writes there are coalesced too.
+// The mover pass then reads the movers' state from that dense buffer instead
+// of from their scattered old slots.
+__global__ void k_scatter32_stay(int nub, int nth, const uint8_t *__restrict__ cls,
+                                 const uint32_t *__restrict__ sb, const int32_t *__restrict__ mst,
+                                 uint32_t *__restrict__ knew, PtrSet<uint32_t, 6> P,
+                                 uint32_t *__restrict__ cbuf, int64_t cn) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nub) return;
+    uint32_t v[6];
+#pragma unroll
+    for (int a = 0; a < 6; a++) v[a] = P.src[a][q];
+    const int cl = cls[q];
+    if (cl == 1) {
+        const int cell = (int)v[0];
+        const uint32_t key = (uint32_t)(cell >> 16) * (uint32_t)nth + (uint32_t)(cell & 0xffff);
+        const uint32_t d = sb[q] + (uint32_t)mst[key];
+#pragma unroll
+        for (int a = 0; a < 6; a++) P.dst[a][d] = v[a];
+        knew[d] = key;
+    } else if (cl == 2) {
+        const size_t t = (size_t)((uint32_t)q - sb[q]);
+#pragma unroll
+        for (int a = 0; a < 6; a++) cbuf[(size_t)a * (size_t)cn + t] = v[a];
+    }
+}
+
+__global__ void k_scatter32_move(int nbm, const uint32_t *__restrict__ tot,
+                                 const uint32_t *__restrict__ mkey,
+                                 const uint32_t *__restrict__ mval,
+                                 const int32_t *__restrict__ offold,
+                                 const uint32_t *__restrict__ sb, uint32_t *__restrict__ knew,
+                                 PtrSet<uint32_t, 6> P, const uint32_t *__restrict__ cbuf,
+                                 int64_t cn) {
+    const int m = (int)tot[1];
+    for (int j = (int)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += nbm * blockDim.x) {
+        const uint32_t key = mkey[j];
+        const int q = (int)mval[j];
+        const int lo = offold[key], hi = offold[key + 1];
+        const int c = q < lo ? lo : (q > hi ? hi : q);
+        const uint32_t d = (uint32_t)j + sb[c];
+        const size_t t = (size_t)((uint32_t)q - sb[q]);
+#pragma unroll
+        for (int a = 0; a < 6; a++) P.dst[a][d] = cbuf[(size_t)a * (size_t)cn + t];
+        knew[d] = key;
+    }
+}
+
 // offsets of the new order: stayers with key < k (= SB at the old offset)
 // plus movers with key < k; the last entry is the live count
 __global__ void k_new_offsets(int nkeys, const int32_t *__restrict__ offold,
@@ -715,6 +766,14 @@ static void sort_incremental(ffpic_ctx *c, int s) {
         hipLaunchKernelGGL((k_scatter<uint64_t, 5>), dim3(nbs + nbm), dim3(256), 0, c->stream,
                            nub, nbm, c->keys[0], dead, nold, kold, c->sort_sb, c->sort_mst,
                            c->sort_tot, mkey2, mval2, offold, knew, (state_ptrs<uint64_t, 5>(S)));
+    } else if (c->sort_cbuf && (int64_t)nub - (int64_t)tot[0] <= c->sort_cbuf_n) {
+        const auto P = state_ptrs<uint32_t, 6>(S);
+        hipLaunchKernelGGL(k_scatter32_stay, dim3(nbs), dim3(256), 0, c->stream, nub, c->nth,
+                           c->sort_cls, c->sort_sb, c->sort_mst, knew, P, c->sort_cbuf,
+                           c->sort_cbuf_n);
+        hipLaunchKernelGGL(k_scatter32_move, dim3(nbm), dim3(256), 0, c->stream, nbm, c->sort_tot,
+                           mkey2, mval2, offold, c->sort_sb, knew, P, c->sort_cbuf,
+                           c->sort_cbuf_n);
     } else {
         hipLaunchKernelGGL(k_scatter32, dim3(nbs + nbm), dim3(256), 0, c->stream, nub, nbm,
                            c->nth, c->sort_cls, c->sort_sb, c->sort_mst, c->sort_tot, mkey2,

@@ -346,7 +346,7 @@ void free_all(ffpic_ctx *c) {
     for (int k = 0; k < 2; k++) { F(c->keys[k]); F(c->vals[k]); }
     for (int s = 0; s < FFPIC_MAX_SPECIES; s++)
         for (int k = 0; k < 2; k++) { F(c->skey[s][k]); F(c->soff[s][k]); }
-    F(c->sort_sb); F(c->sort_blk); F(c->sort_aux); F(c->sort_moff); F(c->sort_mst); F(c->sort_tot); F(c->scan_tmp);
+    F(c->sort_sb); F(c->sort_blk); F(c->sort_aux); F(c->sort_moff); F(c->sort_mst); F(c->sort_cbuf); F(c->sort_tot); F(c->scan_tmp);
     F(c->sort_cls);
     F(c->inj_rate); F(c->inj_cnt); F(c->inj_off); F(c->inj_scan_tmp); F(c->nsorted);
     F(c->gj_target); F(c->gj_have); F(c->pair_cnt); F(c->pair_off); F(c->pair_scan_tmp);
@@ -574,6 +574,12 @@ int ffpic_create(const ffpic_desc *d, void *stream, ffpic_ctx **out) {
             if (!c->fp64) c->sort_cls = (uint8_t *)dmalloc((size_t)std::max<int64_t>(maxcap, 1));
             c->sort_moff = (int32_t *)dmalloc(nk1 * 4);
             c->sort_mst = (int32_t *)dmalloc(nk1 * 4);
+            if (!c->fp64) {
+                // room for the state of a quarter of the slots changing cell
+                // between two sorts; a sort with more uses the direct scatter
+                c->sort_cbuf_n = std::max<int64_t>(maxcap / 4, 1);
+                c->sort_cbuf = (uint32_t *)dmalloc((size_t)c->sort_cbuf_n * 6 * 4);
+            }
             c->sort_tot = (uint32_t *)dmalloc(2 * 4);
             c->scan_tmp_bytes = scan_temp_bytes(nblk);
             c->scan_tmp = dmalloc(c->scan_tmp_bytes);
