@@ -16,27 +16,30 @@
 // coordinates is ever taken.  Reciprocals and square roots use the
 // hardware approximations (about 1 ulp).
 //
-// The kernel is bound by instruction issue, so it is written for few
-// instructions per particle: the 24-load staggered gather goes through
-// buffer resources with 32-bit offsets shared between components at the
-// same stagger (the next radial row comes from the scalar offset), the axis
-// parity signs are folded into the interpolation weights, the particle
-// state is addressed with 32-bit offsets from uniform bases, and the
-// cross-lane sums are DPP row reductions.
+// The kernel is bound by VALU issue, so it is written for few instructions
+// per particle: the axis parity signs are folded into the interpolation
+// weights, the particle state is addressed with 32-bit offsets from uniform
+// bases, index products use 24-bit multiplies, and the cross-lane sums are
+// DPP row reductions.
 //
-// Deposit: each workgroup takes a contiguous chunk of the (cell-sorted)
-// particle array, holds the chunk's cells in registers, finds the bounding
-// box of its cells and accumulates the currents in an LDS patch covering the
-// box plus the one-cell reach of a step; the patch is then flushed to the
-// FP32 current arrays in HBM with one global atomic per non-zero entry.
+// Gather: each workgroup takes a contiguous chunk of the (cell-sorted)
+// particle array and finds the bounding box of its cells.  It copies the six
+// field components over the box, with one node of margin, into an LDS patch
+// (interleaved per node), and every particle reads its corner pairs from
+// there with one ds_read2 each.  Loads from HBM whose lanes read a few nodes
+// each would otherwise saturate the vector-memory address unit.
+//
+// Deposit: the currents accumulate in a second LDS patch covering the box
+// plus the one-cell reach of a step; the patch is then flushed to the FP32
+// current arrays in HBM with one global atomic per non-zero entry.
 // Particles that stay in their cell are summed across each 16-lane row
 // first (DPP), one cell per row and pass, so a sorted wave issues one add
 // instruction from 32 lanes (eight sums in each of four rows) per pass
 // instead of eight from all 64.  Moves that leave their cell (a few per
 // cent of a step) are queued in LDS and deposited after the chunk, so the
 // zigzag runs in one wave per chunk rather than in nearly every wave.
-// Chunks whose box is too large for the patch (sparse regions) add
-// straight to HBM.
+// Chunks whose box is too large for the patches (sparse regions) gather
+// from HBM through buffer resources and add straight to HBM.
 #include "device_common.h"
 
 namespace ffpic {

@@ -16,9 +16,9 @@
 // coordinates (log r / dlog, theta / dtheta), charge fluxes through the dual
 // faces (exact discrete charge conservation), azimuthal current from v_phi
 // at the mid-point.  Accumulation as in the FP32 path: an LDS patch per
-// workgroup over the bounding box of its (cell-sorted) particles, same-cell
-// in-cell moves summed across each 16-lane row first (DPP), one global FP64
-// atomic per non-zero patch entry.
+// workgroup over the bounding box of its (cell-sorted) particles, in-cell
+// moves summed across each 16-lane row first (DPP, one cell per row and
+// pass), one global FP64 atomic per non-zero patch entry.
 #include "gather.h"
 
 namespace ffpic {
@@ -80,16 +80,6 @@ __device__ __forceinline__ double dpp64(double v) {
     const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, true);
     const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
-
-// sum over each 16-lane row of the wavefront (every lane of the row gets it):
-// quad swaps, then the half-row and row mirrors
-__device__ __forceinline__ double row_sum64(double v) {
-    v += dpp64<0xB1>(v);
-    v += dpp64<0x4E>(v);
-    v += dpp64<0x141>(v);
-    v += dpp64<0x140>(v);
-    return v;
 }
 
 // Sums eight per-lane values over each 16-lane row, halving the number of
