@@ -157,6 +157,48 @@ def test_push_and_deposit_one_step_fp32(band):
         assert e < 2e-5, (gc, e)        # measured 1.4e-7 .. 1.2e-6
 
 
+@pytest.mark.parametrize("poles", ["north", "both"])
+@pytest.mark.parametrize("precision", [W.FP32_MIXED, W.FP64])
+def test_push_near_the_axes(poles, precision):
+    """Particles within half a cell of the axis, where the gather takes the
+    axis ghosts (even components reflected, odd ones with the sign flipped).
+    With one pole only, a chunk's cell box is narrow and the FP32 push
+    gathers from its LDS patch; with both poles every radial row holds both
+    edge columns, the box spans the grid's width and the push gathers from
+    HBM."""
+    w = W.tiny_dipole(20_000)
+    d = w.desc()
+    d["precision"] = precision
+    g = np.random.Generator(np.random.PCG64(20260))
+    n = 20_000
+    dth = math.pi / w.nth
+    th = g.uniform(0.0, 0.5 * dth, n)
+    if poles == "both":
+        th[::2] = math.pi - th[::2]
+    p = dict(r=g.uniform(2.0, 8.0, n), th=th)
+    gam = np.exp(g.uniform(0.0, math.log(10.0), n))
+    um = np.sqrt(gam * gam - 1.0)
+    mu = g.uniform(-1.0, 1.0, n)
+    ph = g.uniform(0.0, 2.0 * math.pi, n)
+    p["ur"], p["uth"], p["uph"] = um * mu, um * np.sqrt(1 - mu * mu) * np.cos(ph), um * np.sqrt(1 - mu * mu) * np.sin(ph)
+    sim = ffpic.Sim(d, capacity=[n, n])
+    ora = oracle.Oracle(d)
+    for s in range(2):
+        sim.load_particles(s, p)
+        ora.load(s, p)
+    sim.run_phases(ffpic.PHASE_PUSH)
+    ora.phases(oracle.PHASE_PUSH)
+    rtol = 1e-12 if precision == W.FP64 else 1e-5
+    for s in range(2):
+        a, o = sim.particles(s), ora.particles(s)
+        same = (o["cell"] >= 0) & (a["cell"] == o["cell"])
+        assert np.mean(same) > 0.99
+        for k in ("ur", "uth", "uph"):
+            assert np.allclose(a[k][same], o[k][same], rtol=rtol, atol=rtol * np.abs(o[k]).max()), k
+    for gc, oc in ((ffpic.JR, oracle.JR), (ffpic.JTH, oracle.JTH), (ffpic.JPH, oracle.JPH)):
+        assert rel(sim.field(gc), ora.field(oc)) < (FP64_TOL if precision == W.FP64 else 2e-5), gc
+
+
 def test_field_step_fp64():
     w = W.tiny_open_dipole(50_000)
     sim, ora = pair(w)
