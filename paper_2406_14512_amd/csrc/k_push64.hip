@@ -184,7 +184,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
     if (live) {
         double Es[3], Bs[3];
         gather_eb(Er, Et, Ep, Br, Bt, Bp, p.nr, p.nth, p.ld, i, j, a, b, Es, Bs);
-        double st = sin(th), ct = cos(th);
+        double st, ct;
+        sincos(th, &st, &ct);           // one argument reduction for both
         double E[3] = {Es[0] * st + Es[1] * ct, Es[2], Es[0] * ct - Es[1] * st};
         double B[3] = {Bs[0] * st + Bs[1] * ct, Bs[2], Bs[0] * ct - Bs[1] * st};
         double ur = UR[q], ut = UT[q], up = UP[q];
