@@ -45,7 +45,9 @@
 namespace ffpic {
 
 constexpr int kWG = 256;
-constexpr int kPPT = 4;                  // particles per thread per chunk
+// particles per thread per chunk: a chunk of 4096 sorted particles spans few
+// cells, so its patches' load and flush are spread over many particles
+constexpr int kPPT = 16;
 constexpr int kChunk = kWG * kPPT;
 constexpr int kTile = 1024;              // LDS deposit patch entries per component
 constexpr int kFld = 512;                // LDS field patch nodes (six components each)
