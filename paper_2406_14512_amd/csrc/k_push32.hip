@@ -475,7 +475,6 @@ __device__ __forceinline__ void push_chunk(const P32 &p, const Fields &F, const 
             const int src = rowm ? (lane & 48) + __builtin_ctz(rowm) : lane;
             const int lc = __shfl(c, src, 64);
             const bool part = pend && c == lc;
-            const unsigned long long pm = __ballot(part);
             float pk[4], pp[4];
 #pragma unroll
             for (int e = 0; e < 4; e++) {
@@ -483,7 +482,8 @@ __device__ __forceinline__ void push_chunk(const P32 &p, const Fields &F, const 
                 pp[e] = part ? rp[e] : 0.f;
             }
             const float v = row_sum8(pk, pp, b1, b2);
-            if (row_lead && ((pm >> (lane & 48)) & 0xffffull) != 0ull) {
+            // a row with pending lanes has participants: its leader
+            if (row_lead && rowm != 0u) {
                 const int li = (lc >> 16) + kdi, lj = (lc & 0xffff) + kdj;
                 if (LDS) acc.add(kcomp, li, lj, v);
                 else gadd(reinterpret_cast<float *>(reinterpret_cast<char *>(kg) +
