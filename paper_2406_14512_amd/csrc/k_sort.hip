@@ -426,35 +426,44 @@ __global__ void __launch_bounds__(256) k_class_compact32(
     const uint32_t *__restrict__ cst, const uint32_t *__restrict__ cmv, uint32_t *__restrict__ sb,
     uint32_t *__restrict__ mkey, uint32_t *__restrict__ mval, uint32_t *__restrict__ tot) {
     constexpr int K = kSortBlock / 256;
-    __shared__ uint32_t part[2][4];
+    // per-wave counts, double-buffered: a wave writes buffer k & 1 only after
+    // the barrier of pass k - 1, which every wave passes after its reads of
+    // pass k - 2, so one barrier per pass suffices
+    __shared__ uint32_t part[2][2][4];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    int cl[K];
+    int cl[K], cc[K];
 #pragma unroll
     for (int k = 0; k < K; k++) {
         const int q = blockIdx.x * kSortBlock + k * 256 + tid;
         cl[k] = q < nub ? (int)cls[q] : 0;
+    }
+    // the movers' cells are loaded before the passes, off their barriers
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        const int q = blockIdx.x * kSortBlock + k * 256 + tid;
+        cc[k] = cl[k] == 2 ? CELL[q] : 0;
     }
     uint32_t st0 = cst[blockIdx.x], mv0 = cmv[blockIdx.x];
     const unsigned long long below = (1ull << lane) - 1ull;
 #pragma unroll
     for (int k = 0; k < K; k++) {
         const int q = blockIdx.x * kSortBlock + k * 256 + tid;
+        uint32_t(*pt)[4] = part[k & 1];
         const unsigned long long ms = __ballot(cl[k] == 1), mm = __ballot(cl[k] == 2);
-        if (lane == 0) { part[0][w] = __popcll(ms); part[1][w] = __popcll(mm); }
+        if (lane == 0) { pt[0][w] = __popcll(ms); pt[1][w] = __popcll(mm); }
         __syncthreads();
         uint32_t os = st0, om = mv0;
-        for (int u = 0; u < w; u++) { os += part[0][u]; om += part[1][u]; }
+        for (int u = 0; u < w; u++) { os += pt[0][u]; om += pt[1][u]; }
         os += __popcll(ms & below);
         om += __popcll(mm & below);
         if (q < nub) sb[q] = os;
         if (cl[k] == 2) {
-            const int c = CELL[q];
+            const int c = cc[k];
             mkey[om] = (uint32_t)(c >> 16) * (uint32_t)nth + (uint32_t)(c & 0xffff);
             mval[om] = (uint32_t)q;
         }
-        st0 += part[0][0] + part[0][1] + part[0][2] + part[0][3];
-        mv0 += part[1][0] + part[1][1] + part[1][2] + part[1][3];
-        __syncthreads();
+        st0 += pt[0][0] + pt[0][1] + pt[0][2] + pt[0][3];
+        mv0 += pt[1][0] + pt[1][1] + pt[1][2] + pt[1][3];
     }
     if (blockIdx.x == nblk - 1 && tid == 0) {
         sb[nub] = st0;
