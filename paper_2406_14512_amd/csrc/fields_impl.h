@@ -16,52 +16,79 @@ namespace ffpic {
 // with A_r = r_i^2 (cos theta_j - cos theta_{j+1}); FP64, sequential in j so
 // that the rounding is fixed.  A workgroup owns kPsiRows radial rows and
 // walks them in tiles of kPsiCols columns: all 256 threads load a tile with
-// coalesced reads along theta into LDS, then one lane per row runs the
-// serial sum over the tile while the next tile's loads are in flight, and
-// the tile of partial sums is written back coalesced.
+// coalesced reads along theta and form its terms B_r A_r in parallel (each
+// product rounded as in the serial form) into LDS, then one lane per row
+// runs the serial sum over the tile while the next tile's loads are in
+// flight, and the tile of partial sums is written back coalesced.
 constexpr int kPsiRows = 16;
 constexpr int kPsiCols = 256;
+
+// workgroup barrier that orders LDS accesses only: unlike __syncthreads it
+// does not wait for the thread's global loads and stores, so the next
+// tile's loads and the write-back stay in flight across it
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
 
 template <typename R>
 __global__ void __launch_bounds__(kPsiCols) k_psi(Geo<double> g, const R *__restrict__ br,
                                                   double *__restrict__ psi) {
     __shared__ double tile[kPsiRows][kPsiCols + 1];
-    __shared__ double area[kPsiCols];
     const int t = threadIdx.x;
     const int i0 = blockIdx.x * kPsiRows;
     const int ld = g.ld, nr = g.nr, nth = g.nth;
     const int rows = min(kPsiRows, nr + 1 - i0);
-    const double r2 = t < rows ? g.rn2[i0 + t] : 0.0;
+    double r2[kPsiRows];
+#pragma unroll
+    for (int rr = 0; rr < kPsiRows; rr++) r2[rr] = rr < rows ? g.rn2[i0 + rr] : 0.0;
     double acc = 0.0;
     if (t < rows) psi[ix(ld, i0 + t, 0)] = 0.0;
+    // The tile's B_r and column areas are loaded one tile ahead.
     R nxt[kPsiRows];
+    double arn;
+    auto load = [&](int jt) {
+        arn = jt + t < nth ? g.dcn[jt + t] : 0.0;
 #pragma unroll
-    for (int rr = 0; rr < kPsiRows; rr++)
-        nxt[rr] = (rr < rows && t < nth) ? br[ix(ld, i0 + rr, t)] : (R)0;
+        for (int rr = 0; rr < kPsiRows; rr++)
+            nxt[rr] = (rr < rows && jt + t < nth) ? br[ix(ld, i0 + rr, jt + t)] : (R)0;
+    };
+    // the tile's terms B_r A_r, each product rounded as in the serial form
+    auto terms = [&]() {
+#pragma unroll
+        for (int rr = 0; rr < kPsiRows; rr++) {
+#pragma clang fp contract(off)
+            tile[rr][t] = (double)nxt[rr] * (r2[rr] * arn);
+        }
+    };
+    load(0);
+    terms();
     for (int j0 = 0; j0 < nth; j0 += kPsiCols) {
         const int w = min(kPsiCols, nth - j0);
-#pragma unroll
-        for (int rr = 0; rr < kPsiRows; rr++) tile[rr][t] = (double)nxt[rr];
-        if (t < w) area[t] = g.dcn[j0 + t];
-        __syncthreads();
+        lds_barrier();
         const int jn = j0 + kPsiCols;
-        if (jn < nth) {
-#pragma unroll
-            for (int rr = 0; rr < kPsiRows; rr++)
-                nxt[rr] = (rr < rows && jn + t < nth) ? br[ix(ld, i0 + rr, jn + t)] : (R)0;
-        }
+        if (jn < nth) load(jn);
         if (t < rows) {
-#pragma unroll 8
+#pragma unroll 16
             for (int k = 0; k < w; k++) {
 #pragma clang fp contract(off)
-                acc = acc + tile[t][k] * (r2 * area[k]);
+                acc = acc + tile[t][k];
                 tile[t][k] = acc;
             }
         }
-        __syncthreads();
-        for (int rr = 0; rr < rows; rr++)
-            if (t < w) psi[ix(ld, i0 + rr, j0 + 1 + t)] = tile[rr][t];
-        __syncthreads();
+        lds_barrier();
+        // every lane stores every row: a lane past the last column or row
+        // writes the last one instead (that entry's own value again), so
+        // that with no branch around the stores the compiler can count those
+        // still in flight, and the wait for the next tile's loads does not
+        // also wait for this write-back
+        const int tc = min(t, w - 1);
+#pragma unroll
+        for (int rr = 0; rr < kPsiRows; rr++) {
+            const int rc = min(rr, rows - 1);
+            psi[ix(ld, i0 + rc, j0 + 1 + tc)] = tile[rc][tc];
+        }
+        lds_barrier();
+        if (jn < nth) terms();
     }
 }
 
