@@ -12,8 +12,11 @@ import subprocess
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB = os.path.join(HERE, "libffpic_oracle.so")
 SRC = os.path.join(HERE, "ffpic_oracle.c")
+# A test may point this at another build of the oracle (the mutation test
+# loads copies with one planted mistake); such a library is used as given.
+LIB_OVERRIDE = os.environ.get("FFPIC_ORACLE_LIB", "")
+LIB = LIB_OVERRIDE or os.path.join(HERE, "libffpic_oracle.so")
 
 # field component numbering of the oracle (ffpic_oracle.h)
 ER, ETH, EPH, BR, BTH, BPH, JR, JTH, JPH, PSI, F, B0R, B0TH, B0PH = range(14)
@@ -21,14 +24,22 @@ PHASE_MASK, PHASE_KILL, PHASE_SORT, PHASE_PUSH, PHASE_FIELDS, PHASE_INJECT = 1, 
 PHASE_EXTRACT, PHASE_PAIRS = 64, 128
 
 
+def compile_to(src: str, out: str) -> None:
+    """Compile an oracle source file into a shared library with gcc (plain C,
+    FP contraction off)."""
+    tmp = out + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared",
+                           "-ffp-contract=off", "-fno-fast-math", "-o", tmp,
+                           src, "-lm"])
+    os.replace(tmp, out)
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (plain C, FP contraction off)."""
+    if LIB_OVERRIDE:
+        return LIB
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared",
-                               "-ffp-contract=off", "-fno-fast-math", "-o", tmp,
-                               SRC, "-lm"])
-        os.replace(tmp, LIB)
+        compile_to(SRC, LIB)
     return LIB
 
 

@@ -14,7 +14,16 @@
  * Particles: per species, FP64 (r, theta, u_r, u_theta, u_phi); a dead slot
  * has r = -1 until the next sort compacts it away.
  *
- * What pins each part (tests/test_oracle_pins.py, tests/golden/):
+ * What pins each part (tests/test_oracle_pins.py, tests/test_oracle_kinematics.py,
+ * tests/golden/; tests/test_oracle_mutations.py checks that planted mistakes
+ * in the push's frame changes, move and azimuthal deposit fail these pins):
+ *   push frame changes and move: free streaming follows the 3-D straight
+ *   line (also across the equator and past the poles), a uniform E along the
+ *   axis accelerates u_z linearly, gyration in a uniform B0 z built from
+ *   nodal Psi follows the discrete orbit to second order, the azimuthal
+ *   E x B drift -E0/B0; azimuthal deposit: total Q v_phi centred on the
+ *   move's midpoint, its density integrating to the ring current Q v_phi /
+ *   varpi;
  *   time step and radial spacing: Table 1 values; Boris rotation: the exact
  *   discrete rotation angle and |u| conservation; E x B drift; radiation
  *   reaction: closed-form cooling, first-order convergence; flux function:
