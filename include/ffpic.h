@@ -284,6 +284,44 @@ int ffpic_get_particles_range(ffpic_ctx *ctx, int species, int64_t first, int64_
    to host memory): offsets[k] = number of live particles with cell < k. */
 int ffpic_get_sort(ffpic_ctx *ctx, int species, int32_t *cell_offsets);
 
+/* Test hooks, host only (no device is touched, no context is made): what
+   ffpic_create builds on the host for descriptor d, so that it can be
+   checked without a GPU.
+   ffpic_host_table copies the FP64 geometry table `table` (FFPIC_TAB_*) to
+   out (nullable) and its length to *n.  The grid of Sect. 4: r_i = rmin
+   exp(i dlog), dlog = ln(rmax/rmin)/nr, theta_j = j pi/nth; half points at
+   i+1/2 and j+1/2; the dual cell of node (i, j) spans [r_lo, r_hi] x
+   [theta_lo, theta_hi] (half points, clipped to the grid ends and to
+   [0, pi] on the axis).
+   ffpic_host_initial_field copies initial field component comp
+   (FFPIC_ER .. FFPIC_BPH) as an (nr+1)*(nth+1) node-shaped FP64 array.
+   EINVAL for a rejected descriptor, a table or component out of range or a
+   NULL pointer. */
+enum ffpic_table {
+    FFPIC_TAB_RN = 0,   /* r_i [nr+1] */
+    FFPIC_TAB_RH,       /* r_{i+1/2} [nr] */
+    FFPIC_TAB_RN2,      /* r_i^2 [nr+1] */
+    FFPIC_TAB_RH2,      /* r_{i+1/2}^2 [nr] */
+    FFPIC_TAB_DRN,      /* r_{i+1} - r_i [nr] */
+    FFPIC_TAB_DRH,      /* r_{i+1/2} - r_{i-1/2} [nr+1], 0 at both ends */
+    FFPIC_TAB_DR2N,     /* (r_{i+1}^2 - r_i^2)/2 [nr] */
+    FFPIC_TAB_DR2H,     /* (r_hi^2 - r_lo^2)/2 [nr+1] */
+    FFPIC_TAB_DR3H,     /* (r_hi^3 - r_lo^3)/3 [nr+1] */
+    FFPIC_TAB_DR3N,     /* (r_{i+1}^3 - r_i^3)/3 [nr] */
+    FFPIC_TAB_LAMN,     /* absorber factor at r_i [nr+1] */
+    FFPIC_TAB_LAMH,     /* absorber factor at r_{i+1/2} [nr] */
+    FFPIC_TAB_SN,       /* sin theta_j [nth+1], 0 at both poles */
+    FFPIC_TAB_CN,       /* cos theta_j [nth+1], +1 and -1 at the poles */
+    FFPIC_TAB_SH,       /* sin theta_{j+1/2} [nth] */
+    FFPIC_TAB_DCN,      /* cos theta_j - cos theta_{j+1} [nth] */
+    FFPIC_TAB_DCD,      /* cos theta_lo - cos theta_hi [nth+1] */
+    FFPIC_TAB_DTHD,     /* theta_hi - theta_lo [nth+1] */
+    FFPIC_TAB_THN,      /* theta_j [nth+1] */
+    FFPIC_NTAB
+};
+int ffpic_host_table(const ffpic_desc *d, int table, double *out, int64_t *n);
+int ffpic_host_initial_field(const ffpic_desc *d, int comp, double *out);
+
 /* Diagnostics selected by `what` (FFPIC_DIAG_*); L_of_r (nullable, nr+1
    doubles, host) receives the Poynting flux through each sphere r_i
    (Sect. 4, eq. michel_spindown form).  Synchronises. */

@@ -28,8 +28,13 @@ def compile_to(src: str, out: str) -> None:
     """Compile an oracle source file into a shared library with gcc (plain C,
     FP contraction off)."""
     tmp = out + ".tmp"
+    # sin and cos are called as written: with them as builtins GCC merges a
+    # sin and a cos of one argument into one sincos call, whose results
+    # differ from sin's and cos's in the last bit at some angles (theta_j =
+    # 80 pi / 300 and 159 pi / 300, for example)
     subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared",
-                           "-ffp-contract=off", "-fno-fast-math", "-o", tmp,
+                           "-ffp-contract=off", "-fno-fast-math",
+                           "-fno-builtin-sin", "-fno-builtin-cos", "-o", tmp,
                            src, "-lm"])
     os.replace(tmp, out)
 
@@ -83,6 +88,7 @@ def lib():
         L.ora_destroy.argtypes = [P]
         L.ora_info.argtypes = [P, dp]
         L.ora_get_field.argtypes = [P, C.c_int, dp]
+        L.ora_geometry.argtypes = [P, C.c_int, dp]
         L.ora_set_field.argtypes = [P, C.c_int, dp]
         L.ora_load_particles.restype = C.c_int64
         L.ora_load_particles.argtypes = [P, C.c_int, C.c_int64, dp, dp, dp, dp, dp]
@@ -194,6 +200,15 @@ class Oracle:
     def field(self, comp: int) -> np.ndarray:
         out = np.zeros(self.shape)
         lib().ora_get_field(self._h, comp, out)
+        return out
+
+    def geometry(self, which: int) -> np.ndarray:
+        """0 r_i, 1 r_{i+1/2}, 2 theta_j, 3 sin theta_j, 4 cos theta_j,
+        5 sin theta_{j+1/2}, 6 cos theta_{j+1/2}"""
+        n = [self.nr + 1, self.nr, self.nth + 1, self.nth + 1, self.nth + 1,
+             self.nth, self.nth][which]
+        out = np.zeros(n)
+        lib().ora_geometry(self._h, int(which), out)
         return out
 
     def set_field(self, comp: int, arr: np.ndarray):

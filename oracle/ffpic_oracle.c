@@ -305,6 +305,17 @@ void ora_info(const ora_sim *s, double out[4])
     out[0] = s->dt; out[1] = s->dlog; out[2] = s->dth; out[3] = s->omega;
 }
 
+/* geometry tables: 0 r_i (nr+1), 1 r_{i+1/2} (nr), 2 theta_j (nth+1),
+   3 sin theta_j (nth+1), 4 cos theta_j (nth+1), 5 sin theta_{j+1/2} (nth),
+   6 cos theta_{j+1/2} (nth) */
+void ora_geometry(const ora_sim *s, int which, double *dst)
+{
+    const double *src[7] = {s->rn, s->rh, s->thn, s->sn, s->cn, s->sh, s->ch};
+    size_t len[7] = {(size_t)s->nr + 1, (size_t)s->nr, (size_t)s->nth + 1, (size_t)s->nth + 1,
+                     (size_t)s->nth + 1, (size_t)s->nth, (size_t)s->nth};
+    if (which >= 0 && which < 7) memcpy(dst, src[which], len[which] * sizeof(double));
+}
+
 void ora_get_field(const ora_sim *s, int c, double *dst)
 {
     memcpy(dst, s->F[c], s->nn * sizeof(double));

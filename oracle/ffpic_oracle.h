@@ -94,6 +94,9 @@ void ora_destroy(ora_sim *s);
 /* out: dt, dlog, dth, omega */
 void ora_info(const ora_sim *s, double out[4]);
 void ora_get_field(const ora_sim *s, int comp, double *dst);
+/* geometry tables: 0 r_i, 1 r_{i+1/2}, 2 theta_j, 3 sin theta_j,
+   4 cos theta_j, 5 sin theta_{j+1/2}, 6 cos theta_{j+1/2} */
+void ora_geometry(const ora_sim *s, int which, double *dst);
 void ora_set_field(ora_sim *s, int comp, const double *src);
 /* appends, then removes out-of-domain and masked particles and sorts;
    returns the number of particles of that species after loading */

@@ -46,6 +46,9 @@ struct Geo {
 
 enum { T_RN, T_RH, T_RN2, T_RH2, T_DRN, T_DRH, T_DR2N, T_DR2H, T_DR3H, T_DR3N,
        T_LAMN, T_LAMH, T_SN, T_CN, T_SH, T_DCN, T_DCD, T_DTHD, T_THN, T_NTAB };
+static_assert(T_RN == FFPIC_TAB_RN && T_DCN == FFPIC_TAB_DCN && T_THN == FFPIC_TAB_THN &&
+                  T_NTAB == FFPIC_NTAB,
+              "the internal table order is the one ffpic_host_table exports");
 
 struct Species {
     int64_t cap = 0;

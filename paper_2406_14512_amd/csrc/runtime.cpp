@@ -146,6 +146,27 @@ std::string validate(const ffpic_desc *d) {
     return "";
 }
 
+void build_tables(ffpic_ctx *c);
+
+// grid sizes, spacings, time step and the geometry tables of a descriptor
+// (host only; no device call)
+void setup_geometry(ffpic_ctx *c, const ffpic_desc *d) {
+    c->d = *d;
+    c->nr = d->nr; c->nth = d->nth; c->ld = d->nth + 1;
+    c->nn = (size_t)(d->nr + 1) * (size_t)(d->nth + 1);
+    c->fp64 = d->precision == FFPIC_FP64;
+    c->rsz = c->fp64 ? sizeof(double) : sizeof(float);
+    c->dlog = std::log(d->rmax / d->rmin) / d->nr;
+    c->dth = kPi / d->nth;
+    c->omega = 1.0 / d->r_lc;
+    {   // CFL number times the 2-D Courant limit of the innermost cell
+        double r0 = d->rmin, r1 = d->rmin * std::exp(c->dlog);
+        double drr = r1 - r0, drt = r0 * c->dth;
+        c->dt = d->cfl / std::sqrt(1.0 / (drr * drr) + 1.0 / (drt * drt));
+    }
+    build_tables(c);
+}
+
 // geometry tables (FP64, on the host)
 void build_tables(ffpic_ctx *c) {
     const int nr = c->nr, nth = c->nth;
@@ -497,22 +518,9 @@ int ffpic_create(const ffpic_desc *d, void *stream, ffpic_ctx **out) {
     ffpic_ctx *c = new (std::nothrow) ffpic_ctx();
     if (!c) return FFPIC_ENOMEM;
     int rc = guarded(c, [&] {
-        c->d = *d;
-        if (c->d.sort_interval == 0) c->d.sort_interval = tuned_sort_interval(d);
         c->stream = (hipStream_t)stream;
-        c->nr = d->nr; c->nth = d->nth; c->ld = d->nth + 1;
-        c->nn = (size_t)(d->nr + 1) * (size_t)(d->nth + 1);
-        c->fp64 = d->precision == FFPIC_FP64;
-        c->rsz = c->fp64 ? sizeof(double) : sizeof(float);
-        c->dlog = std::log(d->rmax / d->rmin) / d->nr;
-        c->dth = kPi / d->nth;
-        c->omega = 1.0 / d->r_lc;
-        {   // CFL number times the 2-D Courant limit of the innermost cell
-            double r0 = d->rmin, r1 = d->rmin * std::exp(c->dlog);
-            double drr = r1 - r0, drt = r0 * c->dth;
-            c->dt = d->cfl / std::sqrt(1.0 / (drr * drr) + 1.0 / (drt * drt));
-        }
-        build_tables(c);
+        setup_geometry(c, d);
+        if (c->d.sort_interval == 0) c->d.sort_interval = tuned_sort_interval(d);
         {   // first row where the absorber's factor (in working precision) is below 1
             auto below1 = [&](double v) { return c->fp64 ? v != 1.0 : (float)v != 1.0f; };
             c->absorb_row0 = c->nr + 1;
@@ -643,6 +651,28 @@ int ffpic_create(const ffpic_desc *d, void *stream, ffpic_ctx **out) {
     }
     *out = c;
     return FFPIC_OK;
+}
+
+int ffpic_host_table(const ffpic_desc *d, int table, double *out, int64_t *n) {
+    if (!validate(d).empty() || table < 0 || table >= T_NTAB || !n) return FFPIC_EINVAL;
+    return guarded(nullptr, [&] {
+        ffpic_ctx c;
+        setup_geometry(&c, d);
+        const auto &t = c.tab[table];
+        if (out) std::copy(t.begin(), t.end(), out);
+        *n = (int64_t)t.size();
+    });
+}
+
+int ffpic_host_initial_field(const ffpic_desc *d, int comp, double *out) {
+    if (!validate(d).empty() || comp < FFPIC_ER || comp > FFPIC_BPH || !out) return FFPIC_EINVAL;
+    return guarded(nullptr, [&] {
+        ffpic_ctx c;
+        setup_geometry(&c, d);
+        std::vector<double> F[6];
+        init_fields_host(&c, F);
+        std::copy(F[comp].begin(), F[comp].end(), out);
+    });
 }
 
 void ffpic_destroy(ffpic_ctx *c) {

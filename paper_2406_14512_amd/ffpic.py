@@ -132,6 +132,8 @@ def lib():
     L.ffpic_batch_last_error.argtypes = [P]
     L.ffpic_batch_last_error.restype = C.c_char_p
     L.ffpic_batch_destroy.argtypes = [P]
+    L.ffpic_host_table.argtypes = [C.POINTER(Desc), C.c_int, vp, C.POINTER(C.c_int64)]
+    L.ffpic_host_initial_field.argtypes = [C.POINTER(Desc), C.c_int, vp]
     L.ffpic_autotune.argtypes = [P, C.c_double, C.POINTER(Tuning)]
     L.ffpic_batch_autotune.argtypes = [P, C.c_double, C.POINTER(Tuning)]
     for name in ("ffpic_create", "ffpic_info", "ffpic_load_fields", "ffpic_load_particles",
@@ -141,7 +143,7 @@ def lib():
                  "ffpic_phase_times", "ffpic_get_particles_range", "ffpic_batch_create",
                  "ffpic_batch_view", "ffpic_batch_size", "ffpic_batch_step", "ffpic_batch_sync",
                  "ffpic_batch_destroy", "ffpic_autotune", "ffpic_batch_autotune",
-                 "ffpic_spectra"):
+                 "ffpic_spectra", "ffpic_host_table", "ffpic_host_initial_field"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -177,6 +179,34 @@ def make_desc(d: Dict, capacity=None) -> Desc:
         s.gj_species[k] = int(d.get("gj_species", (0, 0))[k])
         s.pair_species[k] = int(d.get("pair_species", (0, 0))[k])
     return s
+
+
+(TAB_RN, TAB_RH, TAB_RN2, TAB_RH2, TAB_DRN, TAB_DRH, TAB_DR2N, TAB_DR2H, TAB_DR3H, TAB_DR3N,
+ TAB_LAMN, TAB_LAMH, TAB_SN, TAB_CN, TAB_SH, TAB_DCN, TAB_DCD, TAB_DTHD, TAB_THN) = range(19)
+
+
+def host_table(desc: Dict, table: int) -> np.ndarray:
+    """FP64 geometry table as ffpic_create builds it on the host (no device)."""
+    L = lib()
+    d = make_desc(desc, [0] * int(desc["nspec"]))
+    n = C.c_int64(0)
+    rc = L.ffpic_host_table(C.byref(d), int(table), None, C.byref(n))
+    if rc != OK:
+        raise FfpicError(rc, "ffpic_host_table rejected its arguments")
+    out = np.zeros(n.value)
+    L.ffpic_host_table(C.byref(d), int(table), C.c_void_p(out.ctypes.data), C.byref(n))
+    return out
+
+
+def host_initial_field(desc: Dict, comp: int) -> np.ndarray:
+    """Initial field component as ffpic_create builds it on the host (no device)."""
+    L = lib()
+    d = make_desc(desc, [0] * int(desc["nspec"]))
+    out = np.zeros((int(desc["nr"]) + 1, int(desc["nth"]) + 1))
+    rc = L.ffpic_host_initial_field(C.byref(d), int(comp), C.c_void_p(out.ctypes.data))
+    if rc != OK:
+        raise FfpicError(rc, "ffpic_host_initial_field rejected its arguments")
+    return out
 
 
 def _ptr(x):

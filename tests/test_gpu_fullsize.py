@@ -38,6 +38,7 @@ import pytest
 import oracle
 from paper_2406_14512_amd import ffpic
 from paper_2406_14512_amd import workloads as W
+from parity_util import rel, rel_grouped  # noqa: F401
 
 pytestmark = pytest.mark.gpu
 
@@ -49,11 +50,6 @@ FIELDS = [(ffpic.ER, oracle.ER), (ffpic.ETH, oracle.ETH), (ffpic.EPH, oracle.EPH
           (ffpic.BR, oracle.BR), (ffpic.BTH, oracle.BTH), (ffpic.BPH, oracle.BPH)]
 CURRENTS = [(ffpic.JR, oracle.JR, "Jr"), (ffpic.JTH, oracle.JTH, "Jth"),
             (ffpic.JPH, oracle.JPH, "Jph")]
-
-
-def rel(a, b):
-    nb = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a - b)
 
 
 @pytest.fixture(scope="module", autouse=True)

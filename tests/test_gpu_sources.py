@@ -15,6 +15,7 @@ import pytest
 import oracle
 from paper_2406_14512_amd import ffpic
 from paper_2406_14512_amd import workloads as W
+from parity_util import rel, rel_grouped  # noqa: F401
 
 pytestmark = pytest.mark.gpu
 
@@ -31,11 +32,6 @@ def _built():
     ffpic.lib()
 
 
-def rel(a, b):
-    nb = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a - b)
-
-
 def both(d, precision, cap):
     d = dict(d, precision=precision)
     return ffpic.Sim(d, capacity=[cap] * d["nspec"]), oracle.Oracle(d)
@@ -46,13 +42,10 @@ def field_errors(sim, ora):
 
 
 def field_errors_grouped(sim, ora):
-    out = {}
-    for group in (FIELDS[:3], FIELDS[3:]):
-        ref = math.sqrt(sum(np.linalg.norm(ora.field(o)) ** 2 for _, o, _ in group))
-        for g, o, name in group:
-            out[name] = np.linalg.norm(sim.field(g) - ora.field(o)) / ref
-    return out
-
+    """Per-component errors normalised by the field group (E or B)
+    rather than by the component itself."""
+    return {**rel_grouped([(n, sim.field(g), ora.field(o)) for g, o, n in FIELDS[:3]]),
+            **rel_grouped([(n, sim.field(g), ora.field(o)) for g, o, n in FIELDS[3:]])}
 
 def same_particles(sim, ora, nspec, rtol):
     for s in range(nspec):
