@@ -76,6 +76,10 @@ struct ffpic_ctx {
     // FP32 mode: perturbation state about the FP64 background (see
     // fields_pert.h) and the background's rates evaluated in FP64
     void *dE[3] = {}, *dB[3] = {}, *E0[3] = {}, *rE0[3] = {}, *rB0[3] = {}, *rho0 = nullptr;
+    // FP32 mode: FP64 device copies of the background E_r, E_th, B_r, B_th
+    // (the FP64 Gauss and div B residuals are formed from them plus dE, dB)
+    double *E0d[2] = {}, *B0d[2] = {};
+    int device = 0;                           // HIP device the context was created on
     std::vector<double> hE0[3], hB0[3];       // FP64 background (host)
     void *scr[6] = {};                        // node scratch (J_FFE, E corrections)
     int absorb_row0 = 0;                      // first grid row with damping below 1
@@ -162,12 +166,31 @@ void export_particles(ffpic_ctx *c, int s, int64_t first, int64_t n, double *r, 
 void to_f64(ffpic_ctx *c, const void *src, double *dst, size_t n);
 void from_f64(ffpic_ctx *c, const double *src, void *dst, size_t n);
 void sort_offsets(ffpic_ctx *c, int s, int32_t *dev_off);
-void moments(ffpic_ctx *c, int s, double *dev_out5);
-void gauss_map(ffpic_ctx *c, double *dev_map);
-void divb_map(ffpic_ctx *c, double *dev_map);
+// FP64 diagnostics.  `part` holds diag_partials() * 5 doubles of per-block
+// partial results (device scratch), `out*` device result slots.
+int diag_partials();
+void moments(ffpic_ctx *c, int s, double *part, double *dev_out5);
+// Gauss residual: node charges into qn (nn doubles, cleared here), then the
+// map (nullable) and/or the per-block maxima of |G| (part, nullable)
+void gauss(ffpic_ctx *c, double *qn, double *dev_map, double *part);
+void divb(ffpic_ctx *c, double *dev_map, double *part);
 void poynting(ffpic_ctx *c, double *dev_L);
-void energies(ffpic_ctx *c, double *dev_out2);
-double max_abs(ffpic_ctx *c, const double *dev, size_t n);
+void energies(ffpic_ctx *c, double *part, double *dev_out2);
+// device scratch of one diagnostics call
+struct DiagBufs {
+    double *part = nullptr;   // diag_partials() * 5
+    double *out = nullptr;    // 16 result slots
+    double *qn = nullptr;     // nn node charges (residuals only)
+    double *L = nullptr;      // nr + 1 (Poynting flux only)
+};
+// everything of ffpic_diagnostics but the scratch: synchronises, fills *out
+// and (nullable) the host array L_of_r; allocates nothing on the device
+void run_diagnostics(ffpic_ctx *c, uint32_t what, ffpic_diag *out, double *L_of_r,
+                     const DiagBufs &b);
+// the same, returning a status (and setting the context's error message)
+// instead of throwing
+int run_diagnostics_checked(ffpic_ctx *c, uint32_t what, ffpic_diag *out, double *L_of_r,
+                            const DiagBufs &b);
 size_t sort_temp_bytes(int64_t cap, int bits);
 size_t scan_temp_bytes(int64_t nblk);
 int sort_block_slots();

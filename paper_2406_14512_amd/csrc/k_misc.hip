@@ -231,17 +231,23 @@ __global__ void k_moments(int nub, const int32_t *nslots, const void *c0, const 
     block_store<5>(v, part);
 }
 
-void moments(ffpic_ctx *c, int s, double *out5) {
+void moments(ffpic_ctx *c, int s, double *part, double *out5) {
     ffpic::Species &S = c->sp[s];
     int n = (int)S.nub;
     if (c->fp64)
         hipLaunchKernelGGL(k_moments<true>, dim3(kRedBlocks), dim3(256), 0, c->stream, n, c->nslots + s,
-                           S.cur[0], S.cur[2], S.cur[3], S.cur[4], c->red);
+                           S.cur[0], S.cur[2], S.cur[3], S.cur[4], part);
     else
         hipLaunchKernelGGL(k_moments<false>, dim3(kRedBlocks), dim3(256), 0, c->stream, n, c->nslots + s,
-                           S.cur[0], S.cur[3], S.cur[4], S.cur[5], c->red);
-    hipLaunchKernelGGL(k_final<5>, dim3(1), dim3(256), 0, c->stream, c->red, kRedBlocks, out5);
+                           S.cur[0], S.cur[3], S.cur[4], S.cur[5], part);
+    hipLaunchKernelGGL(k_final<5>, dim3(1), dim3(256), 0, c->stream, part, kRedBlocks, out5);
     FFPIC_LAUNCH_CHECK();
+}
+
+__global__ void k_fill0(double *p, size_t n) {
+    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+         q += (size_t)gridDim.x * blockDim.x)
+        p[q] = 0.0;
 }
 
 // node charge sum Q S_xi S_eta (FP64 atomics) into `q`
@@ -270,24 +276,53 @@ __global__ void k_charge(int n, const int32_t *nslots, int nr, int nth, int ld, 
     atomicAdd(&qn[ix(ld, i + 1, j + 1)], Q * a * b);
 }
 
-template <typename R>
-__global__ void k_gauss(Geo<double> g, const R *er, const R *et, const double *qn, double *G) {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
-    int i = blockIdx.y;
-    if (j > g.nth) return;
-    size_t k = ix(g.ld, i, j);
-    if (i == 0 || i == g.nr) { G[k] = 0.0; return; }
-    double flux = g.rh2[i] * g.dcd[j] * (double)er[k] - g.rh2[i - 1] * g.dcd[j] * (double)er[k - g.ld];
-    if (j < g.nth) flux += g.sh[j] * g.dr2h[i] * (double)et[k];
-    if (j > 0) flux -= g.sh[j - 1] * g.dr2h[i] * (double)et[k - 1];
-    double vol = g.dr3h[i] * g.dcd[j];
-    G[k] = flux / vol - 4.0 * kPi * qn[k] / vol;
+// block maximum of |x| over the block's threads, written to part[blockIdx.x]
+__device__ void block_max(double m, double *part) {
+    __shared__ double sm[256];
+    sm[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
 }
 
-void gauss_map(ffpic_ctx *c, double *map) {
-    double *qn = nullptr;
-    if (hipMalloc(&qn, c->nn * sizeof(double)) != hipSuccess) throw std::runtime_error("hipMalloc failed");
-    hipMemsetAsync(qn, 0, c->nn * sizeof(double), c->stream);
+// FP64 value of a field entry: the FP64 array itself, or, in FP32-mixed
+// mode, the FP64 background plus the FP32 perturbation
+template <typename R>
+__device__ __forceinline__ double fval(const R *x, const double *x0, size_t k) {
+    return x0 ? x0[k] + (double)x[k] : (double)x[k];
+}
+
+// Gauss-law residual div E - 4 pi rho over the dual cell of each node
+// (zero on the first and last rows), in FP64; written as a map (G) and/or
+// folded into per-block maxima of |G| (part)
+template <typename R>
+__global__ void k_gauss(Geo<double> g, const R *er, const R *et, const double *e0r,
+                        const double *e0t, const double *qn, double *G, double *part) {
+    const size_t total = (size_t)(g.nr + 1) * g.ld;
+    double m = 0.0;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
+         k += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(k / g.ld), j = (int)(k % g.ld);
+        double v = 0.0;
+        if (i > 0 && i < g.nr) {
+            double flux = g.rh2[i] * g.dcd[j] * fval(er, e0r, k) -
+                          g.rh2[i - 1] * g.dcd[j] * fval(er, e0r, k - g.ld);
+            if (j < g.nth) flux += g.sh[j] * g.dr2h[i] * fval(et, e0t, k);
+            if (j > 0) flux -= g.sh[j - 1] * g.dr2h[i] * fval(et, e0t, k - 1);
+            double vol = g.dr3h[i] * g.dcd[j];
+            v = flux / vol - 4.0 * kPi * qn[k] / vol;
+        }
+        if (G) G[k] = v;
+        m = fmax(m, fabs(v));
+    }
+    if (part) block_max(m, part);
+}
+
+void gauss(ffpic_ctx *c, double *qn, double *map, double *part) {
+    hipLaunchKernelGGL(k_fill0, dim3(kRedBlocks), dim3(256), 0, c->stream, qn, c->nn);
     for (int s = 0; s < c->d.nspec; s++) {
         ffpic::Species &S = c->sp[s];
         if (S.nub == 0) continue;
@@ -303,39 +338,51 @@ void gauss_map(ffpic_ctx *c, double *map) {
                                c->dtab64[T_THN], S.cur[0], S.cur[1], S.cur[2], Q, qn);
     }
     Geo<double> g = geo<double>(c);
-    dim3 blk(256), grd((c->nth + 1 + 255) / 256, c->nr + 1);
     if (c->fp64)
-        hipLaunchKernelGGL(k_gauss<double>, grd, blk, 0, c->stream, g, (const double *)c->E[0],
-                           (const double *)c->E[1], qn, map);
+        hipLaunchKernelGGL(k_gauss<double>, dim3(kRedBlocks), dim3(256), 0, c->stream, g,
+                           (const double *)c->E[0], (const double *)c->E[1], nullptr, nullptr, qn,
+                           map, part);
     else
-        hipLaunchKernelGGL(k_gauss<float>, grd, blk, 0, c->stream, g, (const float *)c->E[0],
-                           (const float *)c->E[1], qn, map);
+        hipLaunchKernelGGL(k_gauss<float>, dim3(kRedBlocks), dim3(256), 0, c->stream, g,
+                           (const float *)c->dE[0], (const float *)c->dE[1], c->E0d[0], c->E0d[1],
+                           qn, map, part);
     FFPIC_LAUNCH_CHECK();
-    hipStreamSynchronize(c->stream);
-    hipFree(qn);
 }
 
+// div B over each primal cell (zero past the last row and column), in
+// FP64 (FP32-mixed: FP64 background plus the perturbation)
 template <typename R>
-__global__ void k_divb(Geo<double> g, const R *br, const R *bt, double *D) {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
-    int i = blockIdx.y;
-    if (j > g.nth) return;
-    size_t k = ix(g.ld, i, j);
-    if (i == g.nr || j == g.nth) { D[k] = 0.0; return; }
-    double flux = g.rn2[i + 1] * g.dcn[j] * (double)br[k + g.ld] - g.rn2[i] * g.dcn[j] * (double)br[k] +
-                  g.sn[j + 1] * g.dr2n[i] * (double)bt[k + 1] - g.sn[j] * g.dr2n[i] * (double)bt[k];
-    D[k] = flux / (g.dr3n[i] * g.dcn[j]);
+__global__ void k_divb(Geo<double> g, const R *br, const R *bt, const double *b0r,
+                       const double *b0t, double *D, double *part) {
+    const size_t total = (size_t)(g.nr + 1) * g.ld;
+    double m = 0.0;
+    for (size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x; k < total;
+         k += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(k / g.ld), j = (int)(k % g.ld);
+        double v = 0.0;
+        if (i < g.nr && j < g.nth) {
+            double flux = g.rn2[i + 1] * g.dcn[j] * fval(br, b0r, k + g.ld) -
+                          g.rn2[i] * g.dcn[j] * fval(br, b0r, k) +
+                          g.sn[j + 1] * g.dr2n[i] * fval(bt, b0t, k + 1) -
+                          g.sn[j] * g.dr2n[i] * fval(bt, b0t, k);
+            v = flux / (g.dr3n[i] * g.dcn[j]);
+        }
+        if (D) D[k] = v;
+        m = fmax(m, fabs(v));
+    }
+    if (part) block_max(m, part);
 }
 
-void divb_map(ffpic_ctx *c, double *map) {
+void divb(ffpic_ctx *c, double *map, double *part) {
     Geo<double> g = geo<double>(c);
-    dim3 blk(256), grd((c->nth + 1 + 255) / 256, c->nr + 1);
     if (c->fp64)
-        hipLaunchKernelGGL(k_divb<double>, grd, blk, 0, c->stream, g, (const double *)c->B[0],
-                           (const double *)c->B[1], map);
+        hipLaunchKernelGGL(k_divb<double>, dim3(kRedBlocks), dim3(256), 0, c->stream, g,
+                           (const double *)c->B[0], (const double *)c->B[1], nullptr, nullptr, map,
+                           part);
     else
-        hipLaunchKernelGGL(k_divb<float>, grd, blk, 0, c->stream, g, (const float *)c->B[0],
-                           (const float *)c->B[1], map);
+        hipLaunchKernelGGL(k_divb<float>, dim3(kRedBlocks), dim3(256), 0, c->stream, g,
+                           (const float *)c->dB[0], (const float *)c->dB[1], c->B0d[0], c->B0d[1],
+                           map, part);
     FFPIC_LAUNCH_CHECK();
 }
 
@@ -403,46 +450,22 @@ __global__ void k_energy(Geo<double> g, const R *er, const R *et, const R *ep, c
     block_store<2>(v, part);
 }
 
-void energies(ffpic_ctx *c, double *out2) {
+void energies(ffpic_ctx *c, double *part, double *out2) {
     Geo<double> g = geo<double>(c);
     if (c->fp64)
         hipLaunchKernelGGL(k_energy<double>, dim3(kRedBlocks), dim3(256), 0, c->stream, g,
                            (const double *)c->E[0], (const double *)c->E[1], (const double *)c->E[2],
                            (const double *)c->B[0], (const double *)c->B[1], (const double *)c->B[2],
-                           c->red);
+                           part);
     else
         hipLaunchKernelGGL(k_energy<float>, dim3(kRedBlocks), dim3(256), 0, c->stream, g,
                            (const float *)c->E[0], (const float *)c->E[1], (const float *)c->E[2],
                            (const float *)c->B[0], (const float *)c->B[1], (const float *)c->B[2],
-                           c->red);
-    hipLaunchKernelGGL(k_final<2>, dim3(1), dim3(256), 0, c->stream, c->red, kRedBlocks, out2);
+                           part);
+    hipLaunchKernelGGL(k_final<2>, dim3(1), dim3(256), 0, c->stream, part, kRedBlocks, out2);
     FFPIC_LAUNCH_CHECK();
 }
 
-__global__ void k_maxabs(const double *x, size_t n, double *part) {
-    __shared__ double sm[256];
-    double m = 0.0;
-    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
-         q += (size_t)gridDim.x * blockDim.x)
-        m = fmax(m, fabs(x[q]));
-    sm[threadIdx.x] = m;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + o]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
-}
-
-double max_abs(ffpic_ctx *c, const double *x, size_t n) {
-    hipLaunchKernelGGL(k_maxabs, dim3(kRedBlocks), dim3(256), 0, c->stream, x, n, c->red);
-    FFPIC_LAUNCH_CHECK();
-    std::vector<double> h(kRedBlocks);
-    hipMemcpyAsync(h.data(), c->red, kRedBlocks * sizeof(double), hipMemcpyDeviceToHost, c->stream);
-    hipStreamSynchronize(c->stream);
-    double m = 0.0;
-    for (double v : h) m = v > m ? v : m;
-    return m;
-}
+int diag_partials() { return kRedBlocks; }
 
 }  // namespace ffpic

@@ -348,12 +348,17 @@ void upload_background(ffpic_ctx *c) {
         up(c->rE0[k], rE[k]);
         up(c->E0[k], E0[k]);
     }
+    for (int k = 0; k < 2; k++) {
+        HCHK(hipMemcpy(c->E0d[k], E0[k].data(), c->nn * sizeof(double), hipMemcpyHostToDevice));
+        HCHK(hipMemcpy(c->B0d[k], B0[k].data(), c->nn * sizeof(double), hipMemcpyHostToDevice));
+    }
     up(c->rho0, rho);
 }
 
 void free_all(ffpic_ctx *c) {
     auto F = [](void *p) { if (p) (void)hipFree(p); };
     for (int k = 0; k < 3; k++) { F(c->dE[k]); F(c->dB[k]); F(c->E0[k]); F(c->rE0[k]); F(c->rB0[k]); }
+    for (int k = 0; k < 2; k++) { F(c->E0d[k]); F(c->B0d[k]); }
     F(c->rho0);
     for (int t = 0; t < T_NTAB; t++) {
         if (c->dtab[t] != (void *)c->dtab64[t]) F(c->dtab[t]);
@@ -508,6 +513,67 @@ void one_step(ffpic_ctx *c, uint32_t ph, bool count_step, int tslot) {
 
 }  // namespace
 
+namespace ffpic {
+
+static double host_max(ffpic_ctx *c, const double *part) {
+    double h[1024];
+    const int n = diag_partials();
+    if (n > 1024) throw Fail{FFPIC_EINVAL, "too many partials"};
+    HCHK(hipMemcpyAsync(h, part, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HCHK(hipStreamSynchronize(c->stream));
+    double m = 0.0;
+    for (int k = 0; k < n; k++) m = h[k] > m ? h[k] : m;
+    return m;
+}
+
+void run_diagnostics(ffpic_ctx *c, uint32_t what, ffpic_diag *out, double *L, const DiagBufs &b) {
+    std::memset(out, 0, sizeof(*out));
+    out->step = c->step;
+    HCHK(hipStreamSynchronize(c->stream));
+    unsigned long long rem[FFPIC_MAX_SPECIES * 4];
+    HCHK(hipMemcpy(rem, c->removed, sizeof(rem), hipMemcpyDeviceToHost));
+    HCHK(hipMemcpy(&out->error_word, c->err, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    for (int s = 0; s < c->d.nspec; s++)
+        for (int k = 0; k < 4; k++) out->removed[s][k] = (int64_t)rem[4 * s + k];
+    if (what & FFPIC_DIAG_MOMENTS) {
+        for (int s = 0; s < c->d.nspec; s++) {
+            moments(c, s, b.part, b.out);
+            double h[5];
+            HCHK(hipMemcpyAsync(h, b.out, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+            HCHK(hipStreamSynchronize(c->stream));
+            out->alive[s] = (int64_t)h[0];
+            out->sum_gamma[s] = h[1];
+            for (int k = 0; k < 3; k++) out->sum_u[s][k] = h[2 + k];
+        }
+    }
+    if (what & FFPIC_DIAG_ENERGY) {
+        energies(c, b.part, b.out);
+        double h[2];
+        HCHK(hipMemcpyAsync(h, b.out, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+        HCHK(hipStreamSynchronize(c->stream));
+        out->energy_e = h[0];
+        out->energy_b = h[1];
+    }
+    if (what & FFPIC_DIAG_RESIDUALS) {
+        gauss(c, b.qn, nullptr, b.part);
+        out->gauss_max = host_max(c, b.part);
+        divb(c, nullptr, b.part);
+        out->divb_max = host_max(c, b.part);
+    }
+    if ((what & FFPIC_DIAG_POYNTING) && L) {
+        poynting(c, b.L);
+        HCHK(hipMemcpyAsync(L, b.L, (c->nr + 1) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HCHK(hipStreamSynchronize(c->stream));
+    }
+}
+
+int run_diagnostics_checked(ffpic_ctx *c, uint32_t what, ffpic_diag *out, double *L,
+                            const DiagBufs &b) {
+    return guarded(c, [&] { run_diagnostics(c, what, out, L, b); });
+}
+
+}  // namespace ffpic
+
 extern "C" {
 
 int ffpic_create(const ffpic_desc *d, void *stream, ffpic_ctx **out) {
@@ -519,6 +585,7 @@ int ffpic_create(const ffpic_desc *d, void *stream, ffpic_ctx **out) {
     if (!c) return FFPIC_ENOMEM;
     int rc = guarded(c, [&] {
         c->stream = (hipStream_t)stream;
+        HCHK(hipGetDevice(&c->device));
         setup_geometry(c, d);
         if (c->d.sort_interval == 0) c->d.sort_interval = tuned_sort_interval(d);
         {   // first row where the absorber's factor (in working precision) is below 1
@@ -639,6 +706,10 @@ int ffpic_create(const ffpic_desc *d, void *stream, ffpic_ctx **out) {
                 c->hB0[k] = F[3 + k];
             }
             c->rho0 = dmalloc(fb);
+            for (int k = 0; k < 2; k++) {
+                c->E0d[k] = (double *)dmalloc(c->nn * sizeof(double));
+                c->B0d[k] = (double *)dmalloc(c->nn * sizeof(double));
+            }
             upload_background(c);
         }
         psi_mask(c);
@@ -832,8 +903,14 @@ int ffpic_get_field(ffpic_ctx *c, int comp, double *dst, int on_dev) {
         case FFPIC_JR: case FFPIC_JTH: case FFPIC_JPH: to_f64(c, c->J[comp - 6], d, c->nn); break;
         case FFPIC_PSI: HCHK(hipMemcpyAsync(d, c->psi, c->nn * sizeof(double), hipMemcpyDeviceToDevice, c->stream)); break;
         case FFPIC_F: to_f64(c, c->f, d, c->nn); break;
-        case FFPIC_GAUSS: gauss_map(c, d); break;
-        case FFPIC_DIVB: divb_map(c, d); break;
+        case FFPIC_GAUSS: {
+            double *qn = (double *)dmalloc(c->nn * sizeof(double));
+            gauss(c, qn, d, nullptr);
+            HCHK(hipStreamSynchronize(c->stream));
+            HCHK(hipFree(qn));
+            break;
+        }
+        case FFPIC_DIVB: divb(c, d, nullptr); break;
         }
         if (tmp) {
             HCHK(hipMemcpyAsync(dst, tmp, c->nn * sizeof(double), hipMemcpyDeviceToHost, c->stream));
@@ -933,52 +1010,18 @@ int ffpic_diagnostics(ffpic_ctx *c, uint32_t what, ffpic_diag *out, double *L) {
     return guarded(c, [&] {
         check_ctx(c);
         if (!out) throw Fail{FFPIC_EINVAL, "NULL output"};
-        std::memset(out, 0, sizeof(*out));
-        out->step = c->step;
+        struct Owned {   // per-call device scratch, released on every path
+            std::vector<void *> p;
+            ~Owned() { for (void *q : p) (void)hipFree(q); }
+            double *take(size_t n) { p.push_back(dmalloc(n * sizeof(double))); return (double *)p.back(); }
+        } own;
+        DiagBufs b;
+        b.part = c->red;
+        b.out = own.take(16);
+        if (what & FFPIC_DIAG_RESIDUALS) b.qn = own.take(c->nn);
+        if ((what & FFPIC_DIAG_POYNTING) && L) b.L = own.take(c->nr + 1);
+        run_diagnostics(c, what, out, L, b);
         HCHK(hipStreamSynchronize(c->stream));
-        unsigned long long rem[FFPIC_MAX_SPECIES * 4];
-        int32_t ns[FFPIC_MAX_SPECIES];
-        HCHK(hipMemcpy(rem, c->removed, sizeof(rem), hipMemcpyDeviceToHost));
-        HCHK(hipMemcpy(ns, c->nslots, sizeof(ns), hipMemcpyDeviceToHost));
-        HCHK(hipMemcpy(&out->error_word, c->err, sizeof(uint32_t), hipMemcpyDeviceToHost));
-        for (int s = 0; s < c->d.nspec; s++)
-            for (int k = 0; k < 4; k++) out->removed[s][k] = (int64_t)rem[4 * s + k];
-        double *dv = (double *)dmalloc(16 * sizeof(double));
-        if (what & FFPIC_DIAG_MOMENTS) {
-            for (int s = 0; s < c->d.nspec; s++) {
-                moments(c, s, dv);
-                double h[5];
-                HCHK(hipMemcpyAsync(h, dv, sizeof(h), hipMemcpyDeviceToHost, c->stream));
-                HCHK(hipStreamSynchronize(c->stream));
-                out->alive[s] = (int64_t)h[0];
-                out->sum_gamma[s] = h[1];
-                for (int k = 0; k < 3; k++) out->sum_u[s][k] = h[2 + k];
-            }
-        }
-        if (what & FFPIC_DIAG_ENERGY) {
-            energies(c, dv);
-            double h[2];
-            HCHK(hipMemcpyAsync(h, dv, sizeof(h), hipMemcpyDeviceToHost, c->stream));
-            HCHK(hipStreamSynchronize(c->stream));
-            out->energy_e = h[0];
-            out->energy_b = h[1];
-        }
-        if (what & FFPIC_DIAG_RESIDUALS) {
-            double *m = (double *)dmalloc(c->nn * sizeof(double));
-            gauss_map(c, m);
-            out->gauss_max = max_abs(c, m, c->nn);
-            divb_map(c, m);
-            out->divb_max = max_abs(c, m, c->nn);
-            HCHK(hipFree(m));
-        }
-        if ((what & FFPIC_DIAG_POYNTING) && L) {
-            double *dl = (double *)dmalloc((c->nr + 1) * sizeof(double));
-            poynting(c, dl);
-            HCHK(hipMemcpyAsync(L, dl, (c->nr + 1) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-            HCHK(hipStreamSynchronize(c->stream));
-            HCHK(hipFree(dl));
-        }
-        HCHK(hipFree(dv));
     });
 }
 

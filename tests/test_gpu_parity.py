@@ -330,6 +330,45 @@ def test_residual_maps_match_oracle_fp64():
     assert abs(dg["gauss_max"] - np.abs(ora.gauss()).max()) <= 1e-9 * np.abs(ora.gauss()).max()
 
 
+def _charge_scale(ora, d):
+    """max over interior nodes of |4 pi rho|, rho the oracle's node charge
+    over the dual-cell volume"""
+    dr3h = ffpic.host_table(d, ffpic.TAB_DR3H)
+    dcd = ffpic.host_table(d, ffpic.TAB_DCD)
+    vol = dr3h[:, None] * dcd[None, :]
+    rho = ora.node_charge() / vol
+    return 4.0 * math.pi * np.abs(rho[1:-1]).max()
+
+
+@pytest.mark.parametrize("factory", [W.tiny_dipole, W.tiny_open_dipole])
+def test_gauss_residual_fp32_mixed_in_fp64(factory):
+    """The FP32-mixed path forms its Gauss residual in FP64 from the FP64
+    background plus the FP32 perturbation, so it resolves the FP32 charge
+    conservation error of the deposit rather than the rounding of the
+    corotation background.  After 8 steps its map agrees with the oracle's
+    (which is roundoff) to 2e-5 of the largest 4 pi rho of the particles."""
+    w = factory(50_000, steps=8)
+    sim, ora = pair(w, W.FP32_MIXED)
+    load_both(sim, ora, w)
+    sim.step(8)
+    ora.step(8)
+    g, o = sim.field(ffpic.GAUSS), ora.gauss()
+    scale = _charge_scale(ora, w.desc())
+    err = np.abs(g - o).max() / scale
+    dg = sim.diagnostics(ffpic.DIAG_RESIDUALS)
+    print("FP32-mixed Gauss residual:", factory.__name__, "max |G - G_oracle| / max|4 pi rho| =",
+          err, "max |G| / max|4 pi rho| =", np.abs(g).max() / scale,
+          "oracle:", np.abs(o).max() / scale)
+    assert err < FP32_TOL, err
+    assert dg["gauss_max"] == np.abs(g).max()
+    # the div B residual of the same run, FP64 background plus perturbation
+    db = sim.field(ffpic.DIVB)
+    bscale = np.abs(ora.field(oracle.BR)).max() / (math.exp(ora.dlog) - 1.0)
+    print("FP32-mixed div B:", np.abs(db).max() / bscale, "oracle:", np.abs(ora.divb()).max() / bscale)
+    assert np.abs(db - ora.divb()).max() < 1e-6 * bscale
+    assert dg["divb_max"] == np.abs(db).max()
+
+
 @pytest.mark.parametrize("precision", [W.FP64, W.FP32_MIXED])
 def test_save_restore_resumes(precision):
     w = W.tiny_open_dipole(20_000)
@@ -545,7 +584,7 @@ def test_injection_fp32_and_capacity_error():
     """FP32-mixed hybrid monopole with injection.  E_r, E_phi, B_theta and
     B_phi start at zero here and are ~1e-5 of the corotation field after a
     step, so errors are measured against the norm of the field group: the
-    first 5 steps hold 2e-5.  Later the trajectories' sensitivity (see the
+    first 5 steps hold 2e-5 in L2, the first 4 also element-wise.  Later the trajectories' sensitivity (see the
     FP64 test) amplifies FP32 rounding beyond any fixed bar, and 20 steps
     are held to the particle counts only."""
     w = W.hybrid_monopole(64, precision=W.FP32_MIXED)
@@ -567,6 +606,11 @@ def test_injection_fp32_and_capacity_error():
         print("injected monopole FP32 step", k + 1, "group L2", max(errs.values()),
               "group element-wise", max(errs_max.values()), errs_max)
         assert max(errs.values()) < FP32_TOL, (k + 1, errs)
+        # element-wise (the largest error at any node against the group's
+        # largest entry): held for 4 steps (measured 1.3e-6 .. 4.3e-6); at
+        # step 5 one E_r node next to the injection layer reaches 2.9e-5
+        if k < 4:
+            assert max(errs_max.values()) < FP32_TOL, (k + 1, errs_max)
     sim.step(15)
     ora.step(15)
     sim.sync()
