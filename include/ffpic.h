@@ -327,6 +327,20 @@ int ffpic_host_initial_field(const ffpic_desc *d, int comp, double *out);
    (Sect. 4, eq. michel_spindown form).  Synchronises. */
 int ffpic_diagnostics(ffpic_ctx *ctx, uint32_t what, ffpic_diag *out, double *L_of_r);
 
+/* For callers that cannot allocate device memory (code that must not call
+   hipMalloc, tight serving loops, harnesses that forbid allocation): the
+   same diagnostics as ffpic_diagnostics, same arguments and results, with
+   no device allocation.  Its device scratch (partial sums, result slots,
+   the node charge map of the Gauss residual, L(r)) is one static 32 MiB
+   array per GPU, held until the process ends.  The Gauss residual
+   (FFPIC_DIAG_RESIDUALS) needs nn = (nr+1)(nth+1) doubles of it: EINVAL,
+   with the limit in ffpic_last_error, for a grid of more than about 4.1
+   million nodes; the other diagnostics have no size limit.  EINVAL also
+   when the context's device is not the current device.  Calls on one GPU
+   share the array: calls that overlap in time (several host threads) race
+   on it.  Synchronises. */
+int ffpic_diagnostics_noalloc(ffpic_ctx *ctx, uint32_t what, ffpic_diag *out, double *L_of_r);
+
 /* Spectra of one species over a region of the meridional plane (the
    observables of Sect. 5: particle energy spectra and the synchrotron
    spectral energy distribution).  A live particle counts when

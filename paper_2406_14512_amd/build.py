@@ -35,6 +35,7 @@ SOURCES = [
     ("k_misc.hip", []),
     # spectra follow the oracle's FP64 operation order
     ("k_diag.hip", ["-ffp-contract=off"]),
+    ("noalloc.hip", []),
 ]
 
 COMMON = ["-x", "hip", f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",

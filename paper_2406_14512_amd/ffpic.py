@@ -118,6 +118,7 @@ def lib():
                                             vp, vp, vp, vp, vp, vp]
     L.ffpic_get_sort.argtypes = [P, C.c_int, vp]
     L.ffpic_diagnostics.argtypes = [P, C.c_uint32, C.POINTER(Diag), vp]
+    L.ffpic_diagnostics_noalloc.argtypes = [P, C.c_uint32, C.POINTER(Diag), vp]
     dptr = C.POINTER(C.c_double)
     L.ffpic_spectra.argtypes = [P, C.c_int, C.POINTER(SpectraReq), dptr, dptr, dptr]
     L.ffpic_save.argtypes = [P, vp, C.POINTER(C.c_size_t)]
@@ -143,7 +144,8 @@ def lib():
                  "ffpic_phase_times", "ffpic_get_particles_range", "ffpic_batch_create",
                  "ffpic_batch_view", "ffpic_batch_size", "ffpic_batch_step", "ffpic_batch_sync",
                  "ffpic_batch_destroy", "ffpic_autotune", "ffpic_batch_autotune",
-                 "ffpic_spectra", "ffpic_host_table", "ffpic_host_initial_field"):
+                 "ffpic_spectra", "ffpic_host_table", "ffpic_host_initial_field",
+                 "ffpic_diagnostics_noalloc"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -333,12 +335,15 @@ class Sim:
         self._chk(lib().ffpic_get_sort(self._h, species, C.c_void_p(out.ctypes.data)))
         return out
 
-    def diagnostics(self, what: int = DIAG_ALL, poynting: bool = False) -> Dict:
+    def diagnostics(self, what: int = DIAG_ALL, poynting: bool = False,
+                    noalloc: bool = False) -> Dict:
+        """ffpic_diagnostics, or with noalloc the allocation-free
+        ffpic_diagnostics_noalloc (same results)."""
         d = Diag()
         L = np.zeros(self.nr + 1) if poynting else None
-        self._chk(lib().ffpic_diagnostics(self._h, what | (DIAG_POYNTING if poynting else 0),
-                                          C.byref(d),
-                                          C.c_void_p(L.ctypes.data) if L is not None else None))
+        fn = lib().ffpic_diagnostics_noalloc if noalloc else lib().ffpic_diagnostics
+        self._chk(fn(self._h, what | (DIAG_POYNTING if poynting else 0), C.byref(d),
+                     C.c_void_p(L.ctypes.data) if L is not None else None))
         ns = int(self.desc["nspec"])
         out = dict(step=d.step, alive=[d.alive[s] for s in range(ns)],
                    removed=[[d.removed[s][k] for k in range(4)] for s in range(ns)],
