@@ -70,9 +70,6 @@ def _build_and_run(tmp, tag, text):
     lib = os.path.join(tmp, f"liboracle_{tag}.so")
     with open(src, "w") as f:
         f.write(text)
-    # the oracle's header sits beside its source
-    with open(os.path.join(tmp, "ffpic_oracle.h"), "w") as f:
-        f.write(open(os.path.join(os.path.dirname(oracle.SRC), "ffpic_oracle.h")).read())
     oracle.compile_to(src, lib)
     env = dict(os.environ, FFPIC_ORACLE_LIB=lib)
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
@@ -83,6 +80,9 @@ def _build_and_run(tmp, tag, text):
 def test_pins_fail_on_planted_mistakes(tmp_path):
     with open(oracle.SRC) as f:
         text = f.read()
+    # the oracle's header sits beside its source copies
+    with open(os.path.join(os.path.dirname(oracle.SRC), "ffpic_oracle.h")) as f:
+        (tmp_path / "ffpic_oracle.h").write_text(f.read())
     jobs = [("unchanged", text)]
     for k, (name, old, new) in enumerate(MUTANTS):
         assert text.count(old) == 1, f"planted text not found exactly once: {name}"
