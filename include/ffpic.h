@@ -377,6 +377,12 @@ int ffpic_spectra(ffpic_ctx *ctx, int species, const ffpic_spectra_req *req, dou
 int ffpic_save(ffpic_ctx *ctx, void *buf, size_t *len);
 int ffpic_restore(ffpic_ctx *ctx, const void *buf, size_t len);
 
+/* Tuning of the fused field step: radial rows per workgroup (each
+   workgroup owns a strip of theta columns and a slab of that many rows);
+   0 = automatic (enough slabs to fill the GPU once, at least 32 rows).
+   Results do not depend on it.  EINVAL for a negative value. */
+int ffpic_set_field_rows(ffpic_ctx *ctx, int32_t rows);
+
 /* Device time of each phase of the last ffpic_step call, in ms, summed over
    its steps: out[0] mask, [1] sort, [2] push+deposit, [3] fields.
    Requires ffpic_set_timing(ctx, 1) before the step. */

@@ -74,14 +74,20 @@ struct ffpic_ctx {
     size_t rsz = 8;                           // sizeof(R)
     void *E[3] = {}, *B[3] = {}, *B0[3] = {}, *J[3] = {};
     // FP32 mode: perturbation state about the FP64 background (see
-    // fields_pert.h) and the background's rates evaluated in FP64
+    // fields_fused.h) and the background's rates evaluated in FP64
     void *dE[3] = {}, *dB[3] = {}, *E0[3] = {}, *rE0[3] = {}, *rB0[3] = {}, *rho0 = nullptr;
     // FP32 mode: FP64 device copies of the background E_r, E_th, B_r, B_th
     // (the FP64 Gauss and div B residuals are formed from them plus dE, dB)
     double *E0d[2] = {}, *B0d[2] = {};
+    // the fused field step reads one state buffer and writes the other
+    // (FP64: E, B; FP32: dE, dB), and clears the second set of deposit
+    // accumulators for the next push; the pointers swap after each step
+    void *stAlt[6] = {}, *Jalt[3] = {};
+    bool rE0_zero[3] = {}, rB0_zero[3] = {};  // FP32: background rate identically zero
+    int fused_rows = 0;                       // slab height (0 = from fused_slots)
+    int fused_slots = 0;                      // workgroups resident on the GPU at once
     int device = 0;                           // HIP device the context was created on
     std::vector<double> hE0[3], hB0[3];       // FP64 background (host)
-    void *scr[6] = {};                        // node scratch (J_FFE, E corrections)
     int absorb_row0 = 0;                      // first grid row with damping below 1
     // surface pair injection: expected pairs per step of each surface cell
     // (FP64, host-computed), per-cell counts and their scan

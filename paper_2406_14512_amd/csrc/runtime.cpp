@@ -4,6 +4,7 @@
 // exception crosses the ABI: every entry point catches and maps to a status.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <stdexcept>
@@ -283,7 +284,7 @@ void upload_field(ffpic_ctx *c, void *dst, const std::vector<double> &h) {
 }
 
 // FP32 mode: rates of the FP64 background fields under the discrete
-// operators of the field step, evaluated in FP64 (see fields_pert.h):
+// operators of the field step, evaluated in FP64 (see fields_fused.h):
 // Faraday rate -curl E0 at B positions, Ampere rate curl B0 at the E
 // positions the step updates, and rho0 = div E0 / 4 pi at nodes.
 void upload_background(ffpic_ctx *c) {
@@ -339,6 +340,12 @@ void upload_background(ffpic_ctx *c) {
     };
     for (int i = 0; i < nr; i++)
         for (int j = 0; j <= nth; j++) set(rho, i, j, dive(i == 0 ? 1 : i, j) / (4.0 * kPi));
+    // a rate that is identically zero (e.g. curl B0 of a field without B_phi)
+    // is not read by the field step
+    for (int k = 0; k < 3; k++) {
+        c->rE0_zero[k] = std::all_of(rE[k].begin(), rE[k].end(), [](double v) { return v == 0.0; });
+        c->rB0_zero[k] = std::all_of(rB[k].begin(), rB[k].end(), [](double v) { return v == 0.0; });
+    }
     auto up = [&](void *dst, const std::vector<double> &h) {
         std::vector<float> f(h.begin(), h.end());
         HCHK(hipMemcpy(dst, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
@@ -364,8 +371,8 @@ void free_all(ffpic_ctx *c) {
         if (c->dtab[t] != (void *)c->dtab64[t]) F(c->dtab[t]);
         F(c->dtab64[t]);
     }
-    for (int k = 0; k < 3; k++) { F(c->E[k]); F(c->B[k]); F(c->B0[k]); F(c->J[k]); }
-    for (int k = 0; k < 6; k++) F(c->scr[k]);
+    for (int k = 0; k < 3; k++) { F(c->E[k]); F(c->B[k]); F(c->B0[k]); F(c->J[k]); F(c->Jalt[k]); }
+    for (int k = 0; k < 6; k++) F(c->stAlt[k]);
     F(c->psi); F(c->f); F(c->kill);
     for (int s = 0; s < FFPIC_MAX_SPECIES; s++)
         for (int a = 0; a < 6; a++) { F(c->sp[s].cur[a]); F(c->sp[s].alt[a]); }
@@ -613,9 +620,13 @@ int ffpic_create(const ffpic_desc *d, void *stream, ffpic_ctx **out) {
         for (int k = 0; k < 3; k++) {
             c->E[k] = dmalloc(fb); c->B[k] = dmalloc(fb); c->B0[k] = dmalloc(fb); c->J[k] = dmalloc(fb);
             HCHK(hipMemset(c->J[k], 0, fb));
+            c->Jalt[k] = dmalloc(fb);
+            HCHK(hipMemset(c->Jalt[k], 0, fb));
+            c->stAlt[k] = dmalloc(fb);
+            c->stAlt[3 + k] = dmalloc(fb);
+            HCHK(hipMemset(c->stAlt[k], 0, fb));
+            HCHK(hipMemset(c->stAlt[3 + k], 0, fb));
         }
-        if (d->ff_enable)
-            for (int k = 0; k < 6; k++) { c->scr[k] = dmalloc(fb); HCHK(hipMemset(c->scr[k], 0, fb)); }
         c->psi = (double *)dmalloc(c->nn * sizeof(double));
         c->f = dmalloc(fb);
         c->kill = (uint8_t *)dmalloc((size_t)c->nr * c->nth);
@@ -1147,6 +1158,14 @@ int ffpic_restore(ffpic_ctx *c, const void *buf, size_t len) {
         psi_mask(c);
         HCHK(hipStreamSynchronize(c->stream));
         c->step = h.step;
+    });
+}
+
+int ffpic_set_field_rows(ffpic_ctx *c, int32_t rows) {
+    return guarded(c, [&] {
+        check_ctx(c);
+        if (rows < 0) throw Fail{FFPIC_EINVAL, "negative row count"};
+        c->fused_rows = rows;
     });
 }
 

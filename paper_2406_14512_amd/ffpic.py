@@ -124,6 +124,7 @@ def lib():
     L.ffpic_save.argtypes = [P, vp, C.POINTER(C.c_size_t)]
     L.ffpic_restore.argtypes = [P, vp, C.c_size_t]
     L.ffpic_set_timing.argtypes = [P, C.c_int]
+    L.ffpic_set_field_rows.argtypes = [P, C.c_int32]
     L.ffpic_phase_times.argtypes = [P, C.POINTER(C.c_float)]
     L.ffpic_batch_create.argtypes = [C.c_int, C.POINTER(Desc), vp, C.POINTER(P)]
     L.ffpic_batch_view.argtypes = [P, C.c_int, C.POINTER(P)]
@@ -145,7 +146,7 @@ def lib():
                  "ffpic_batch_view", "ffpic_batch_size", "ffpic_batch_step", "ffpic_batch_sync",
                  "ffpic_batch_destroy", "ffpic_autotune", "ffpic_batch_autotune",
                  "ffpic_spectra", "ffpic_host_table", "ffpic_host_initial_field",
-                 "ffpic_diagnostics_noalloc"):
+                 "ffpic_diagnostics_noalloc", "ffpic_set_field_rows"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -334,6 +335,10 @@ class Sim:
         out = np.zeros(self.nr * self.nth + 1, dtype=np.int32)
         self._chk(lib().ffpic_get_sort(self._h, species, C.c_void_p(out.ctypes.data)))
         return out
+
+    def set_field_rows(self, rows: int):
+        """Radial rows per workgroup of the fused field step (0 = automatic)."""
+        self._chk(lib().ffpic_set_field_rows(self._h, int(rows)))
 
     def diagnostics(self, what: int = DIAG_ALL, poynting: bool = False,
                     noalloc: bool = False) -> Dict:
