@@ -86,7 +86,9 @@ struct ffpic_ctx {
     bool rE0_zero[3] = {}, rB0_zero[3] = {};  // FP32: background rate identically zero
     int fused_rows = 0;                       // slab height (0 = from fused_slots)
     int fused_slots = 0;                      // workgroups resident on the GPU at once
+    void *fz_rowc = nullptr, *fz_colc = nullptr;   // FP32 field step: row / column coefficients
     int device = 0;                           // HIP device the context was created on
+    size_t cstride = 0;                       // elements between the components of a field
     std::vector<double> hE0[3], hB0[3];       // FP64 background (host)
     int absorb_row0 = 0;                      // first grid row with damping below 1
     // surface pair injection: expected pairs per step of each surface cell
@@ -195,6 +197,7 @@ void run_diagnostics(ffpic_ctx *c, uint32_t what, ffpic_diag *out, double *L_of_
                      const DiagBufs &b);
 // the same, returning a status (and setting the context's error message)
 // instead of throwing
+void fused32_tables(const ffpic_ctx *c, std::vector<float> &rowc, std::vector<float> &colc);
 int run_diagnostics_checked(ffpic_ctx *c, uint32_t what, ffpic_diag *out, double *L_of_r,
                             const DiagBufs &b);
 size_t sort_temp_bytes(int64_t cap, int bits);

@@ -9,7 +9,8 @@
 // totals the particle gather reads.  Corotation on the star: E_th and E_ph
 // of row 0 are never updated; axis: E_ph = B_th = 0 on j = 0, nth.
 //
-// FP64 evolves E and B.  The FP32 step is a perturbation form.  In FP32 the
+// This file's kernel is the FP64 step, which evolves E and B.  The FP32
+// step (fields_fused32.h, same stages and tiling) is a perturbation form.  In FP32 the
 // static magnetosphere itself is the problem: the corotation E and the
 // dipole B are discretely curl-free (or nearly so) in exact arithmetic, but
 // once each component is rounded to FP32 their discrete curls are
@@ -21,7 +22,8 @@
 //   dE <- dE + dt (curl(dB) + rateE0) - 4 pi dt J
 //   rho = div(dE) / 4 pi + rho0
 // Rounding then acts on the small perturbation, not on the background; the
-// node quantities (J_FFE, the correction) use the totals F0 + dF.
+// node quantities (J_FFE, the correction) use the totals F0 + dF, which the
+// FP32 step also writes for the particle gather.
 //
 // Tiling.  A workgroup owns a strip of kFzW theta columns (plus kFzL halo
 // columns before and kFzR after, one thread per column) and a slab of
@@ -61,12 +63,9 @@ struct FusedArgs {
     R h;                       // half time step
     int rows;                  // owned rows per workgroup
     int absorb0;               // first row whose absorber factor is below 1
-    const R *sE[3], *sB[3];    // state in: E, B (FP64) or dE, dB (perturbation form)
+    const R *sE[3], *sB[3];    // state in: E, B
     R *oE[3], *oB[3];          // state out (the other buffer)
-    R *tE[3], *tB[3];          // perturbation form: totals E0 + dE, B0 + dB
-    const R *E0[3], *B0[3];    // perturbation form: background; FP64: B0 = initial B
-    const R *rE0[3], *rB0[3];  // perturbation form: background rates, nullptr = 0
-    const R *rho0;             // perturbation form: background div E / 4 pi
+    const R *B0[3];            // initial B (the absorber relaxes B to it)
     const R *J[3];             // this step's deposit accumulators
     R *Jz[3];                  // the other accumulators, cleared here
     const R *f;                // blending function at nodes
@@ -88,13 +87,7 @@ __device__ __forceinline__ void ff_node_f(const float e[3], const float b[3], fl
     }
 }
 
-template <typename R, bool PERT>
-__device__ __forceinline__ void ff_node_any(const R e[3], const R b[3], R o[3]) {
-    if constexpr (PERT) ff_node_f(e, b, o);
-    else ff_node<R>(e, b, o);
-}
-
-template <typename R, bool PERT, bool FF>
+template <typename R, bool FF>
 __global__ void __launch_bounds__(kFzT) k_field_fused(const FusedArgs<R> A) {
     const Geo<R> &g = A.g;
     const int nr = g.nr, nth = g.nth, ld = g.ld;
@@ -116,31 +109,23 @@ __global__ void __launch_bounds__(kFzT) k_field_fused(const FusedArgs<R> A) {
     const R dcn_j = g.dcn[min(jc, nth - 1)], dcd_j = g.dcd[jc], dthd_j = g.dthd[jc];
 
     // LDS rings (theta neighbours); a ring slot holds one row of one quantity
-    constexpr int NE = PERT ? 4 : 3;   // E^n: state r, state phi, state theta (, total theta)
-    constexpr int NB = PERT ? 4 : 2;   // B^{n+1/2}: total r, total phi (, state r, state phi)
-    __shared__ R lE[2][NE][kFzT];
-    __shared__ R lB[4][NB][kFzT];
+    __shared__ R lE[2][3][kFzT];          // E^n: r, phi, theta
+    __shared__ R lB[4][2][kFzT];          // B^{n+1/2}: r, phi
     __shared__ R lN[FF ? 2 : 1][kFzT];    // J_FFE theta
     __shared__ R lF[FF ? 3 : 1][kFzT];    // f
-    __shared__ R lEa[FF ? 2 : 1][kFzT];   // E after Ampere, total theta
+    __shared__ R lEa[FF ? 2 : 1][kFzT];   // E after Ampere, theta
     __shared__ R lD[FF ? 2 : 1][kFzT];    // delta theta
-    __shared__ R lEf[2][2][kFzT];         // final E: state r, state phi
+    __shared__ R lEf[2][2][kFzT];         // final E: r, phi
 
     // own-column history (suffix = rows back from the newest loaded row q)
     R sE0[3] = {}, sE1[3] = {}, sE2[3] = {};        // E state rows q, q-1, q-2
     R sB0[3] = {}, sB1[3] = {};                     // B state rows q, q-1
-    R e00[3] = {}, e01[3] = {}, e02[3] = {}, e03[3] = {}, e04[3] = {};   // E0 rows q..q-4
-    R b00[3] = {}, b01[3] = {}, b02[3] = {}, b03[3] = {}, b04[3] = {};   // B0 rows q..q-4
-    R rb0[3] = {}, rb1[3] = {}, rb2[3] = {}, rb3[3] = {}, rb4[3] = {};   // rate -curl E0
-    R re0[3] = {}, re1[3] = {}, re2[3] = {};        // rate curl B0 rows q..q-2
-    R rho00 = 0, rho01 = 0;                         // rho0 rows q, q-1
     R f0 = 0, f1 = 0, f2 = 0;                       // f rows q, q-1, q-2
     R J0[3] = {}, J1[3] = {}, J2[3] = {};           // deposit rows q, q-1, q-2
-    R Bh1[3] = {}, Bh2[3] = {}, Bh3[3] = {}, Bh4[3] = {};   // B^{n+1/2} state rows q-1..q-4
-    R Bt1[3] = {}, Bt2[3] = {}, Bt3[3] = {};        // B^{n+1/2} totals rows q-1..q-3
+    R Bh1[3] = {}, Bh2[3] = {}, Bh3[3] = {}, Bh4[3] = {};   // B^{n+1/2} rows q-1..q-4
     R n01 = 0, n02 = 0, n11 = 0, n12 = 0, n21 = 0, n22 = 0;   // J_FFE rows q-1, q-2
     R Ea2[3] = {}, Ea3[3] = {};                     // E after Ampere (state) rows q-2, q-3
-    R Eat3r = 0;                                    // its total E_r, row q-3
+    R Eat3r = 0;                                    // its E_r, row q-3
     R d02 = 0, d03 = 0, d13 = 0, d23 = 0;           // delta rows q-2, q-3
     R d12 = 0, d22 = 0;
     R Ef3[3] = {}, Ef4[3] = {};                     // final E (state) rows q-3, q-4
@@ -155,19 +140,11 @@ __global__ void __launch_bounds__(kFzT) k_field_fused(const FusedArgs<R> A) {
                 sE0[c] = ok ? A.sE[c][k] : (R)0;
                 sB0[c] = ok ? A.sB[c][k] : (R)0;
                 J0[c] = ok ? A.J[c][k] : (R)0;
-                if constexpr (PERT) {
-                    e00[c] = ok ? A.E0[c][k] : (R)0;
-                    b00[c] = ok ? A.B0[c][k] : (R)0;
-                    rb0[c] = (ok && A.rB0[c]) ? A.rB0[c][k] : (R)0;
-                    re0[c] = (ok && A.rE0[c]) ? A.rE0[c][k] : (R)0;
-                }
             }
-            if constexpr (PERT && FF) rho00 = ok ? A.rho0[k] : (R)0;
             if constexpr (FF) f0 = ok ? A.f[k] : (R)0;
             lE[q & 1][0][t] = sE0[0];
             lE[q & 1][1][t] = sE0[2];
             lE[q & 1][2][t] = sE0[1];
-            if constexpr (PERT) lE[q & 1][3][t] = e00[1] + sE0[1];
             if constexpr (FF) lF[q % 3][t] = f0;
         }
 
@@ -181,23 +158,20 @@ __global__ void __launch_bounds__(kFzT) k_field_fused(const FusedArgs<R> A) {
             // B_r (j < nth)
             {
                 R circ = g.rn[a] * (sn_j1 * epn - sn_j * sE1[2]);
-                if constexpr (PERT) v[0] = sB1[0] - h * circ / (g.rn2[a] * dcn_j) + h * rb1[0];
-                else v[0] = sB1[0] - h * circ / (g.rn2[a] * dcn_j);
+                v[0] = sB1[0] - h * circ / (g.rn2[a] * dcn_j);
                 if (!jlt) v[0] = sB1[0];
             }
             if (a < nr) {
                 if (jin) {
                     R circ = sn_j * (g.rn[a + 1] * sE0[2] - g.rn[a] * sE1[2]);
-                    if constexpr (PERT) v[1] = sB1[1] + h * circ / (sn_j * g.dr2n[a]) + h * rb1[1];
-                    else v[1] = sB1[1] + h * circ / (sn_j * g.dr2n[a]);
+                    v[1] = sB1[1] + h * circ / (sn_j * g.dr2n[a]);
                 } else {
                     v[1] = (R)0;
                 }
                 if (jlt) {
                     R circ = dth * (g.rn[a + 1] * sE0[1] - g.rn[a] * sE1[1]) -
                              g.drn[a] * (ern - sE1[0]);
-                    if constexpr (PERT) v[2] = sB1[2] - h * circ / (dth * g.dr2n[a]) + h * rb1[2];
-                    else v[2] = sB1[2] - h * circ / (dth * g.dr2n[a]);
+                    v[2] = sB1[2] - h * circ / (dth * g.dr2n[a]);
                 } else {
                     v[2] = sB1[2];
                 }
@@ -205,25 +179,10 @@ __global__ void __launch_bounds__(kFzT) k_field_fused(const FusedArgs<R> A) {
                 v[1] = sB1[1];
                 v[2] = sB1[2];
             }
-            R tot[3];
 #pragma unroll
-            for (int c = 0; c < 3; c++) {
-                if constexpr (PERT) tot[c] = b01[c] + v[c];
-                else tot[c] = v[c];
-            }
-            if constexpr (PERT) {
-                // the perturbation form stores the total B_theta of the
-                // axis as 0, like its background
-                if (a < nr && !jin) tot[1] = (R)0;
-            }
-#pragma unroll
-            for (int c = 0; c < 3; c++) { Bh1[c] = v[c]; Bt1[c] = tot[c]; }
-            lB[a & 3][0][t] = tot[0];
-            lB[a & 3][1][t] = tot[2];
-            if constexpr (PERT) {
-                lB[a & 3][2][t] = v[0];
-                lB[a & 3][3][t] = v[2];
-            }
+            for (int c = 0; c < 3; c++) Bh1[c] = v[c];
+            lB[a & 3][0][t] = v[0];
+            lB[a & 3][1][t] = v[2];
         }
         __syncthreads();
 
@@ -245,46 +204,39 @@ __global__ void __launch_bounds__(kFzT) k_field_fused(const FusedArgs<R> A) {
                     if (jlt) flux += sh_j * g.dr2h[ii] * et_i;
                     if (jgt) flux -= sh_jm * g.dr2h[ii] * et_l;
                     R dv = flux / (g.dr3h[ii] * dcd_j);
-                    if constexpr (PERT) rho = dv / fourpi + rho01;
-                    else rho = dv / fourpi;
+                    rho = dv / fourpi;
                 }
                 // node E^n (totals) and B^{n+1/2} (totals)
                 R e[3], bb[3];
                 {
-                    R tr_i = PERT ? e01[0] + sE1[0] : sE1[0];
-                    R tr_m = PERT ? e02[0] + sE2[0] : sE2[0];
+                    R tr_i = sE1[0];
+                    R tr_m = sE2[0];
                     e[0] = b == 0 ? tr_i : b == nr ? tr_m : (R)0.5 * (tr_m + tr_i);
-                    R tt_j = PERT ? e01[1] + sE1[1] : sE1[1];
-                    R tt_l = lE[b & 1][NE - 1][tl];
+                    R tt_j = sE1[1];
+                    R tt_l = lE[b & 1][2][tl];
                     e[1] = (j == 0 || j == nth) ? (R)0 : (R)0.5 * (tt_l + tt_j);
-                    e[2] = PERT ? e01[2] + sE1[2] : sE1[2];
+                    e[2] = sE1[2];
                 }
                 {
                     const R br_l = lB[b & 3][0][tl];
-                    bb[0] = j == 0 ? Bt1[0] : j == nth ? br_l : (R)0.5 * (br_l + Bt1[0]);
-                    bb[1] = b == 0 ? Bt1[1] : b == nr ? Bt2[1] : (R)0.5 * (Bt2[1] + Bt1[1]);
+                    bb[0] = j == 0 ? Bh1[0] : j == nth ? br_l : (R)0.5 * (br_l + Bh1[0]);
+                    bb[1] = b == 0 ? Bh1[1] : b == nr ? Bh2[1] : (R)0.5 * (Bh2[1] + Bh1[1]);
                     const R bp_l = lB[b & 3][1][tl];
                     if (j == 0 || j == nth) {
                         bb[2] = (R)0;
                     } else if (b == 0) {
-                        bb[2] = (R)0.5 * (bp_l + Bt1[2]);
+                        bb[2] = (R)0.5 * (bp_l + Bh1[2]);
                     } else if (b == nr) {
-                        bb[2] = (R)0.5 * (lB[(b - 1) & 3][1][tl] + Bt2[2]);
+                        bb[2] = (R)0.5 * (lB[(b - 1) & 3][1][tl] + Bh2[2]);
                     } else {
-                        bb[2] = (R)0.25 * (lB[(b - 1) & 3][1][tl] + Bt2[2] + bp_l + Bt1[2]);
+                        bb[2] = (R)0.25 * (lB[(b - 1) & 3][1][tl] + Bh2[2] + bp_l + Bh1[2]);
                     }
                 }
                 R b2 = bb[0] * bb[0] + bb[1] * bb[1] + bb[2] * bb[2];
                 R x0 = e[1] * bb[2] - e[2] * bb[1];
                 R x1 = e[2] * bb[0] - e[0] * bb[2];
                 R x2 = e[0] * bb[1] - e[1] * bb[0];
-                if constexpr (PERT) {
-                    bool ok = b2 > 1e-30f;
-                    const R rb = ok ? rho * __builtin_amdgcn_rcpf(b2) : 0.f;
-                    n01 = rb * x0;
-                    n11 = rb * x1;
-                    n21 = rb * x2;
-                } else {
+                {
                     bool ok = b2 > (R)0;
                     n01 = ok ? rho * x0 / b2 : (R)0;
                     n11 = ok ? rho * x1 / b2 : (R)0;
@@ -298,8 +250,8 @@ __global__ void __launch_bounds__(kFzT) k_field_fused(const FusedArgs<R> A) {
         const int c = q - 2;
         if (c >= qs && c <= nr && (c == 0 || c - 1 >= qs)) {
             R v[3] = {sE2[0], sE2[1], sE2[2]};
-            const R *bl = lB[c & 3][PERT ? 2 : 0];   // row c, B^{n+1/2} state r, j-1 at [tl]
-            const R bp_l = lB[c & 3][PERT ? 3 : 1][tl];
+            const R *bl = lB[c & 3][0];   // row c, B^{n+1/2} state r, j-1 at [tl]
+            const R bp_l = lB[c & 3][1][tl];
             const R jrk = J2[0], jtk = J2[1], jpk = J2[2];
             if (c < nr) {
                 R Ar = g.rh2[c] * dcd_j;
@@ -308,17 +260,13 @@ __global__ void __launch_bounds__(kFzT) k_field_fused(const FusedArgs<R> A) {
                 R J;
                 if constexpr (FF) {
                     R fs = (R)0.5 * (f2 + f1);
-                    if constexpr (PERT) {
-                        J = jrk / (dt * Ar);
-                        if (fs > (R)0) J = ((R)1 - fs) * J + fs * (R)0.5 * (n02 + n01);
-                    } else {
+                    {
                         J = ((R)1 - fs) * jrk / (dt * Ar) + fs * (R)0.5 * (n02 + n01);
                     }
                 } else {
                     J = jrk / (dt * Ar);
                 }
-                if constexpr (PERT) v[0] = sE2[0] + dt * (circ / Ar + re2[0]) - fourpi * dt * J;
-                else v[0] = sE2[0] + (dt * circ / Ar - fourpi * dt * J);
+                v[0] = sE2[0] + (dt * circ / Ar - fourpi * dt * J);
             }
             if (c >= 1 && c < nr) {
                 if (jlt) {
@@ -327,17 +275,13 @@ __global__ void __launch_bounds__(kFzT) k_field_fused(const FusedArgs<R> A) {
                     R J;
                     if constexpr (FF) {
                         R fs = (R)0.5 * (f2 + lF[c % 3][tr]);
-                        if constexpr (PERT) {
-                            J = jtk / (dt * At);
-                            if (fs > (R)0) J = ((R)1 - fs) * J + fs * (R)0.5 * (n12 + lN[c & 1][tr]);
-                        } else {
+                        {
                             J = ((R)1 - fs) * jtk / (dt * At) + fs * (R)0.5 * (n12 + lN[c & 1][tr]);
                         }
                     } else {
                         J = jtk / (dt * At);
                     }
-                    if constexpr (PERT) v[1] = sE2[1] + dt * (circ / At + re2[1]) - fourpi * dt * J;
-                    else v[1] = sE2[1] + (dt * circ / At - fourpi * dt * J);
+                    v[1] = sE2[1] + (dt * circ / At - fourpi * dt * J);
                 }
                 if (jin) {
                     R Ap = dthd_j * g.dr2h[c];
@@ -346,22 +290,18 @@ __global__ void __launch_bounds__(kFzT) k_field_fused(const FusedArgs<R> A) {
                     R J;
                     if constexpr (FF) {
                         R fs = f2;
-                        if constexpr (PERT) {
-                            J = jpk / (g.dr3h[c] * dcd_j);
-                            if (fs > (R)0) J = ((R)1 - fs) * J + fs * n22;
-                        } else {
+                        {
                             J = ((R)1 - fs) * jpk / (g.dr3h[c] * dcd_j) + fs * n22;
                         }
                     } else {
                         J = jpk / (g.dr3h[c] * dcd_j);
                     }
-                    if constexpr (PERT) v[2] = sE2[2] + dt * (circ / Ap + re2[2]) - fourpi * dt * J;
-                    else v[2] = sE2[2] + (dt * circ / Ap - fourpi * dt * J);
+                    v[2] = sE2[2] + (dt * circ / Ap - fourpi * dt * J);
                 }
             }
 #pragma unroll
             for (int k = 0; k < 3; k++) Ea2[k] = v[k];
-            if constexpr (FF) lEa[c & 1][t] = PERT ? e02[1] + v[1] : v[1];
+            if constexpr (FF) lEa[c & 1][t] = v[1];
         }
         __syncthreads();
 
@@ -372,25 +312,25 @@ __global__ void __launch_bounds__(kFzT) k_field_fused(const FusedArgs<R> A) {
                 R o[3] = {(R)0, (R)0, (R)0};
                 if (f2 > (R)0) {
                     R e[3], bb[3], s[3];
-                    const R tr_i = PERT ? e02[0] + Ea2[0] : Ea2[0];
+                    const R tr_i = Ea2[0];
                     e[0] = d == 0 ? tr_i : d == nr ? Eat3r : (R)0.5 * (Eat3r + tr_i);
-                    const R tt_j = PERT ? e02[1] + Ea2[1] : Ea2[1];
+                    const R tt_j = Ea2[1];
                     e[1] = (j == 0 || j == nth) ? (R)0 : (R)0.5 * (lEa[d & 1][tl] + tt_j);
-                    e[2] = PERT ? e02[2] + Ea2[2] : Ea2[2];
+                    e[2] = Ea2[2];
                     const R br_l = lB[d & 3][0][tl];
-                    bb[0] = j == 0 ? Bt2[0] : j == nth ? br_l : (R)0.5 * (br_l + Bt2[0]);
-                    bb[1] = d == 0 ? Bt2[1] : d == nr ? Bt3[1] : (R)0.5 * (Bt3[1] + Bt2[1]);
+                    bb[0] = j == 0 ? Bh2[0] : j == nth ? br_l : (R)0.5 * (br_l + Bh2[0]);
+                    bb[1] = d == 0 ? Bh2[1] : d == nr ? Bh3[1] : (R)0.5 * (Bh3[1] + Bh2[1]);
                     const R bp_l = lB[d & 3][1][tl];
                     if (j == 0 || j == nth) {
                         bb[2] = (R)0;
                     } else if (d == 0) {
-                        bb[2] = (R)0.5 * (bp_l + Bt2[2]);
+                        bb[2] = (R)0.5 * (bp_l + Bh2[2]);
                     } else if (d == nr) {
-                        bb[2] = (R)0.5 * (lB[(d - 1) & 3][1][tl] + Bt3[2]);
+                        bb[2] = (R)0.5 * (lB[(d - 1) & 3][1][tl] + Bh3[2]);
                     } else {
-                        bb[2] = (R)0.25 * (lB[(d - 1) & 3][1][tl] + Bt3[2] + bp_l + Bt2[2]);
+                        bb[2] = (R)0.25 * (lB[(d - 1) & 3][1][tl] + Bh3[2] + bp_l + Bh2[2]);
                     }
-                    ff_node_any<R, PERT>(e, bb, s);
+                    ff_node<R>(e, bb, s);
 #pragma unroll
                     for (int k = 0; k < 3; k++) o[k] = f2 * (s[k] - e[k]);
                 }
@@ -426,23 +366,20 @@ __global__ void __launch_bounds__(kFzT) k_field_fused(const FusedArgs<R> A) {
             R vb[3];
             {
                 R circ = g.rn[fr] * (sn_j1 * epn - sn_j * Ef4[2]);
-                if constexpr (PERT) vb[0] = Bh4[0] - h * circ / (g.rn2[fr] * dcn_j) + h * rb4[0];
-                else vb[0] = Bh4[0] - h * circ / (g.rn2[fr] * dcn_j);
+                vb[0] = Bh4[0] - h * circ / (g.rn2[fr] * dcn_j);
                 if (!jlt) vb[0] = Bh4[0];
             }
             if (fr < nr) {
                 if (jin) {
                     R circ = sn_j * (g.rn[fr + 1] * Ef3[2] - g.rn[fr] * Ef4[2]);
-                    if constexpr (PERT) vb[1] = Bh4[1] + h * circ / (sn_j * g.dr2n[fr]) + h * rb4[1];
-                    else vb[1] = Bh4[1] + h * circ / (sn_j * g.dr2n[fr]);
+                    vb[1] = Bh4[1] + h * circ / (sn_j * g.dr2n[fr]);
                 } else {
                     vb[1] = (R)0;
                 }
                 if (jlt) {
                     R circ = dth * (g.rn[fr + 1] * Ef3[1] - g.rn[fr] * Ef4[1]) -
                              g.drn[fr] * (ern - Ef4[0]);
-                    if constexpr (PERT) vb[2] = Bh4[2] - h * circ / (dth * g.dr2n[fr]) + h * rb4[2];
-                    else vb[2] = Bh4[2] - h * circ / (dth * g.dr2n[fr]);
+                    vb[2] = Bh4[2] - h * circ / (dth * g.dr2n[fr]);
                 } else {
                     vb[2] = Bh4[2];
                 }
@@ -451,59 +388,26 @@ __global__ void __launch_bounds__(kFzT) k_field_fused(const FusedArgs<R> A) {
                 vb[2] = Bh4[2];
             }
             R ve[3] = {Ef4[0], Ef4[1], Ef4[2]};
-            R te[3], tb[3];
-#pragma unroll
-            for (int k = 0; k < 3; k++) {
-                te[k] = PERT ? e04[k] + ve[k] : ve[k];
-                tb[k] = PERT ? b04[k] + vb[k] : vb[k];
-            }
-            if constexpr (PERT) {
-                if (fr < nr && !jin) tb[1] = (R)0;
-            }
             // absorbing layer: E damped, B relaxed to its initial value
             if (fr >= A.absorb0) {
                 const R ln = g.lamn[fr];
                 const R lh = fr < nr ? g.lamh[fr] : (R)1;
                 if (!(ln == (R)1 && lh == (R)1)) {
-                    if constexpr (PERT) {
-                        auto damp_e = [&](int k, R lam) {
-                            R tot = lam * (e04[k] + ve[k]);
-                            ve[k] = tot - e04[k];
-                            te[k] = tot;
-                        };
-                        auto damp_b = [&](int k, R lam) {
-                            vb[k] = lam * vb[k];
-                            tb[k] = b04[k] + vb[k];
-                        };
-                        if (fr < nr) {
-                            damp_e(0, lh);
-                            damp_b(1, lh);
-                            if (jlt) damp_b(2, lh);
-                        }
-                        damp_e(2, ln);
+                    const size_t k = ix(ld, fr, jc);
+                    if (fr < nr) {
+                        ve[0] *= lh;
+                        const R b0t = A.B0[1][k];
+                        vb[1] = b0t + lh * (vb[1] - b0t);
                         if (jlt) {
-                            damp_e(1, ln);
-                            damp_b(0, ln);
+                            const R b0p = A.B0[2][k];
+                            vb[2] = b0p + lh * (vb[2] - b0p);
                         }
-                    } else {
-                        const size_t k = ix(ld, fr, jc);
-                        if (fr < nr) {
-                            ve[0] *= lh;
-                            const R b0t = A.B0[1][k];
-                            vb[1] = b0t + lh * (vb[1] - b0t);
-                            if (jlt) {
-                                const R b0p = A.B0[2][k];
-                                vb[2] = b0p + lh * (vb[2] - b0p);
-                            }
-                        }
-                        ve[2] *= ln;
-                        if (jlt) {
-                            ve[1] *= ln;
-                            const R b0r = A.B0[0][k];
-                            vb[0] = b0r + ln * (vb[0] - b0r);
-                        }
-#pragma unroll
-                        for (int kk = 0; kk < 3; kk++) { te[kk] = ve[kk]; tb[kk] = vb[kk]; }
+                    }
+                    ve[2] *= ln;
+                    if (jlt) {
+                        ve[1] *= ln;
+                        const R b0r = A.B0[0][k];
+                        vb[0] = b0r + ln * (vb[0] - b0r);
                     }
                 }
             }
@@ -514,38 +418,26 @@ __global__ void __launch_bounds__(kFzT) k_field_fused(const FusedArgs<R> A) {
                     A.oE[kk][k] = ve[kk];
                     A.oB[kk][k] = vb[kk];
                     A.Jz[kk][k] = (R)0;
-                    if constexpr (PERT) {
-                        A.tE[kk][k] = te[kk];
-                        A.tB[kk][k] = tb[kk];
-                    }
                 }
             }
         }
         __syncthreads();
 
         // ---- shift the own-column histories by one row
-        Eat3r = PERT ? e02[0] + Ea2[0] : Ea2[0];   // total E_r after Ampere, row q-2
+        Eat3r = Ea2[0];   // E_r after Ampere, row q-2
 #pragma unroll
         for (int k = 0; k < 3; k++) {
             sE2[k] = sE1[k]; sE1[k] = sE0[k];
             sB1[k] = sB0[k];
             J2[k] = J1[k]; J1[k] = J0[k];
             Bh4[k] = Bh3[k]; Bh3[k] = Bh2[k]; Bh2[k] = Bh1[k];
-            Bt3[k] = Bt2[k]; Bt2[k] = Bt1[k];
             Ea3[k] = Ea2[k];
             Ef4[k] = Ef3[k];
-            if constexpr (PERT) {
-                e04[k] = e03[k]; e03[k] = e02[k]; e02[k] = e01[k]; e01[k] = e00[k];
-                b04[k] = b03[k]; b03[k] = b02[k]; b02[k] = b01[k]; b01[k] = b00[k];
-                rb4[k] = rb3[k]; rb3[k] = rb2[k]; rb2[k] = rb1[k]; rb1[k] = rb0[k];
-                re2[k] = re1[k]; re1[k] = re0[k];
-            }
         }
         if constexpr (FF) {
             f2 = f1; f1 = f0;
             n02 = n01; n12 = n11; n22 = n21;
             d03 = d02; d13 = d12; d23 = d22;
-            if constexpr (PERT) rho01 = rho00;
         }
     }
 }
@@ -560,36 +452,26 @@ inline int fused_rows(const ffpic_ctx *c) {
     return c->fused_rows > 0 ? c->fused_rows : std::max(32, rows);
 }
 
-template <typename R, bool PERT>
-static void run_field_fused(ffpic_ctx *c) {
+// FP64 field step (E and B evolved directly)
+static void run_field_fused64(ffpic_ctx *c) {
+    using R = double;
     FusedArgs<R> A{};
     A.g = geo<R>(c);
     A.h = (R)(0.5 * c->dt);
-    A.rows = fused_rows(c);
     A.absorb0 = c->absorb_row0;
     for (int k = 0; k < 3; k++) {
-        if constexpr (PERT) {
-            A.sE[k] = (const R *)c->dE[k]; A.sB[k] = (const R *)c->dB[k];
-            A.oE[k] = (R *)c->stAlt[k];    A.oB[k] = (R *)c->stAlt[3 + k];
-            A.tE[k] = (R *)c->E[k];        A.tB[k] = (R *)c->B[k];
-            A.E0[k] = (const R *)c->E0[k]; A.B0[k] = (const R *)c->B0[k];
-            A.rE0[k] = c->rE0_zero[k] ? nullptr : (const R *)c->rE0[k];
-            A.rB0[k] = c->rB0_zero[k] ? nullptr : (const R *)c->rB0[k];
-        } else {
-            A.sE[k] = (const R *)c->E[k];  A.sB[k] = (const R *)c->B[k];
-            A.oE[k] = (R *)c->stAlt[k];    A.oB[k] = (R *)c->stAlt[3 + k];
-            A.B0[k] = (const R *)c->B0[k];
-        }
+        A.sE[k] = (const R *)c->E[k];  A.sB[k] = (const R *)c->B[k];
+        A.oE[k] = (R *)c->stAlt[k];    A.oB[k] = (R *)c->stAlt[3 + k];
+        A.B0[k] = (const R *)c->B0[k];
         A.J[k] = (const R *)c->J[k];
         A.Jz[k] = (R *)c->Jalt[k];
     }
-    A.rho0 = PERT ? (const R *)c->rho0 : nullptr;
     A.f = (const R *)c->f;
+    auto kern = c->d.ff_enable ? k_field_fused<R, true> : k_field_fused<R, false>;
     if (c->fused_slots == 0) {   // workgroups resident at once, for the slab height
         int per_cu = 0, cus = 0, dev = 0;
-        auto kern = c->d.ff_enable ? (const void *)k_field_fused<R, PERT, true>
-                                   : (const void *)k_field_fused<R, PERT, false>;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kFzT, 0) != hipSuccess ||
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, kFzT, 0) !=
+                hipSuccess ||
             hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
             (void)hipGetLastError();
@@ -597,23 +479,15 @@ static void run_field_fused(ffpic_ctx *c) {
             cus = 256;
         }
         c->fused_slots = std::max(1, per_cu * cus);
-        A.rows = fused_rows(c);
     }
+    A.rows = fused_rows(c);
     dim3 grd((c->nth + 1 + kFzW - 1) / kFzW, (c->nr + 1 + A.rows - 1) / A.rows);
-    if (c->d.ff_enable)
-        hipLaunchKernelGGL((k_field_fused<R, PERT, true>), grd, dim3(kFzT), 0, c->stream, A);
-    else
-        hipLaunchKernelGGL((k_field_fused<R, PERT, false>), grd, dim3(kFzT), 0, c->stream, A);
+    hipLaunchKernelGGL(kern, grd, dim3(kFzT), 0, c->stream, A);
     FFPIC_LAUNCH_CHECK();
     // the new state and the cleared accumulators become current
     for (int k = 0; k < 3; k++) {
-        if constexpr (PERT) {
-            std::swap(c->dE[k], c->stAlt[k]);
-            std::swap(c->dB[k], c->stAlt[3 + k]);
-        } else {
-            std::swap(c->E[k], c->stAlt[k]);
-            std::swap(c->B[k], c->stAlt[3 + k]);
-        }
+        std::swap(c->E[k], c->stAlt[k]);
+        std::swap(c->B[k], c->stAlt[3 + k]);
         std::swap(c->J[k], c->Jalt[k]);
     }
 }

@@ -4,6 +4,6 @@
 #include "fields_fused.h"
 
 namespace ffpic {
-void field_step64(ffpic_ctx *c) { run_field_fused<double, false>(c); }
+void field_step64(ffpic_ctx *c) { run_field_fused64(c); }
 void psi_mask64(ffpic_ctx *c) { run_psi_mask<double>(c); }
 }  // namespace ffpic

@@ -340,11 +340,19 @@ void upload_background(ffpic_ctx *c) {
     };
     for (int i = 0; i < nr; i++)
         for (int j = 0; j <= nth; j++) set(rho, i, j, dive(i == 0 ? 1 : i, j) / (4.0 * kPi));
-    // a rate that is identically zero (e.g. curl B0 of a field without B_phi)
-    // is not read by the field step
+    // A rate that is identically zero (curl B0 of a field without B_phi) is
+    // not read by the field step.  Nor is a Faraday rate -curl E0 that is
+    // FP64 rounding of a curl-free background (the corotation field
+    // E0 = -Omega grad Psi of every initial state): below 1e-9 of
+    // max |E0| / dr_0 it changes no FP32 perturbation.
+    double emax = 0.0;
+    for (int k = 0; k < 3; k++)
+        for (double v : E0[k]) emax = std::max(emax, std::fabs(v));
+    const double rb_floor = 1e-9 * emax / T[T_DRN][0];
     for (int k = 0; k < 3; k++) {
         c->rE0_zero[k] = std::all_of(rE[k].begin(), rE[k].end(), [](double v) { return v == 0.0; });
-        c->rB0_zero[k] = std::all_of(rB[k].begin(), rB[k].end(), [](double v) { return v == 0.0; });
+        c->rB0_zero[k] = std::all_of(rB[k].begin(), rB[k].end(),
+                                     [&](double v) { return std::fabs(v) <= rb_floor; });
     }
     auto up = [&](void *dst, const std::vector<double> &h) {
         std::vector<float> f(h.begin(), h.end());
@@ -362,17 +370,28 @@ void upload_background(ffpic_ctx *c) {
     up(c->rho0, rho);
 }
 
+// one device allocation for the three components of a field, cstride
+// elements apart (the pointers of the components go to p[0..2])
+void alloc3(ffpic_ctx *c, void **p, bool zero) {
+    const size_t cs = c->cstride * c->rsz;
+    char *b = (char *)dmalloc(3 * cs);
+    if (zero) HCHK(hipMemset(b, 0, 3 * cs));
+    for (int k = 0; k < 3; k++) p[k] = b + k * cs;
+}
+
 void free_all(ffpic_ctx *c) {
     auto F = [](void *p) { if (p) (void)hipFree(p); };
-    for (int k = 0; k < 3; k++) { F(c->dE[k]); F(c->dB[k]); F(c->E0[k]); F(c->rE0[k]); F(c->rB0[k]); }
+    // three-component fields: one allocation each, at component 0
+    F(c->dE[0]); F(c->dB[0]); F(c->E0[0]); F(c->rE0[0]); F(c->rB0[0]);
     for (int k = 0; k < 2; k++) { F(c->E0d[k]); F(c->B0d[k]); }
     F(c->rho0);
     for (int t = 0; t < T_NTAB; t++) {
         if (c->dtab[t] != (void *)c->dtab64[t]) F(c->dtab[t]);
         F(c->dtab64[t]);
     }
-    for (int k = 0; k < 3; k++) { F(c->E[k]); F(c->B[k]); F(c->B0[k]); F(c->J[k]); F(c->Jalt[k]); }
-    for (int k = 0; k < 6; k++) F(c->stAlt[k]);
+    F(c->E[0]); F(c->B[0]); F(c->B0[0]); F(c->J[0]); F(c->Jalt[0]);
+    F(c->stAlt[0]); F(c->stAlt[3]);
+    F(c->fz_rowc); F(c->fz_colc);
     F(c->psi); F(c->f); F(c->kill);
     for (int s = 0; s < FFPIC_MAX_SPECIES; s++)
         for (int a = 0; a < 6; a++) { F(c->sp[s].cur[a]); F(c->sp[s].alt[a]); }
@@ -617,16 +636,16 @@ int ffpic_create(const ffpic_desc *d, void *stream, ffpic_ctx **out) {
             }
         }
         size_t fb = c->nn * c->rsz;
-        for (int k = 0; k < 3; k++) {
-            c->E[k] = dmalloc(fb); c->B[k] = dmalloc(fb); c->B0[k] = dmalloc(fb); c->J[k] = dmalloc(fb);
-            HCHK(hipMemset(c->J[k], 0, fb));
-            c->Jalt[k] = dmalloc(fb);
-            HCHK(hipMemset(c->Jalt[k], 0, fb));
-            c->stAlt[k] = dmalloc(fb);
-            c->stAlt[3 + k] = dmalloc(fb);
-            HCHK(hipMemset(c->stAlt[k], 0, fb));
-            HCHK(hipMemset(c->stAlt[3 + k], 0, fb));
-        }
+        // the three components of a field are one allocation, cstride
+        // elements apart (a kernel takes one base per field)
+        c->cstride = (c->nn + 63) & ~size_t(63);
+        alloc3(c, c->E, false);
+        alloc3(c, c->B, false);
+        alloc3(c, c->B0, false);
+        alloc3(c, c->J, true);
+        alloc3(c, c->Jalt, true);
+        alloc3(c, c->stAlt, true);
+        alloc3(c, c->stAlt + 3, true);
         c->psi = (double *)dmalloc(c->nn * sizeof(double));
         c->f = dmalloc(fb);
         c->kill = (uint8_t *)dmalloc((size_t)c->nr * c->nth);
@@ -708,15 +727,24 @@ int ffpic_create(const ffpic_desc *d, void *stream, ffpic_ctx **out) {
             upload_field(c, c->B0[k], F[3 + k]);
         }
         if (!c->fp64) {
+            alloc3(c, c->dE, true);
+            alloc3(c, c->dB, true);
+            alloc3(c, c->E0, false);
+            alloc3(c, c->rE0, false);
+            alloc3(c, c->rB0, false);
             for (int k = 0; k < 3; k++) {
-                c->dE[k] = dmalloc(fb); c->dB[k] = dmalloc(fb); c->E0[k] = dmalloc(fb);
-                c->rE0[k] = dmalloc(fb); c->rB0[k] = dmalloc(fb);
-                HCHK(hipMemset(c->dE[k], 0, fb));
-                HCHK(hipMemset(c->dB[k], 0, fb));
                 c->hE0[k] = F[k];
                 c->hB0[k] = F[3 + k];
             }
             c->rho0 = dmalloc(fb);
+            {
+                std::vector<float> rowc, colc;
+                fused32_tables(c, rowc, colc);
+                c->fz_rowc = dmalloc(rowc.size() * sizeof(float));
+                c->fz_colc = dmalloc(colc.size() * sizeof(float));
+                HCHK(hipMemcpy(c->fz_rowc, rowc.data(), rowc.size() * sizeof(float), hipMemcpyHostToDevice));
+                HCHK(hipMemcpy(c->fz_colc, colc.data(), colc.size() * sizeof(float), hipMemcpyHostToDevice));
+            }
             for (int k = 0; k < 2; k++) {
                 c->E0d[k] = (double *)dmalloc(c->nn * sizeof(double));
                 c->B0d[k] = (double *)dmalloc(c->nn * sizeof(double));
