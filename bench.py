@@ -171,10 +171,33 @@ def batch_run(ffpic, W, steps, warmup, scale):
             "cell_updates_per_s": cells * steps / wall}
 
 
-def cpu_baseline(w, n_sample, steps=2):
+def host_cpu():
+    """CPU model (/proc/cpuinfo), logical CPUs (nproc) and the threads a
+    process is meant to use here (OMP_NUM_THREADS if set, else nproc)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    nproc = os.cpu_count() or 1
+    try:
+        threads = int(os.environ.get("OMP_NUM_THREADS", "")) or nproc
+    except ValueError:
+        threads = nproc
+    return model, nproc, min(threads, nproc)
+
+
+def oracle_rate(w, n_sample, threads, steps=2):
+    """Particle-steps/s and cell-updates/s of the oracle on a sample of the
+    workload: the full grid and n_sample particles for `steps` steps; the
+    push time per particle and the grid time per step are scaled to the
+    workload's particle count."""
     import oracle
-    oracle.build(force=False)
-    o = oracle.Oracle(w.desc())
+    o = oracle.Oracle(w.desc(), threads=threads)
     per = n_sample // w.nspec
     for s in range(w.nspec):
         o.load(s, w.particles(s, limit=per))
@@ -190,16 +213,34 @@ def cpu_baseline(w, n_sample, steps=2):
         t3 = time.perf_counter()
         t_push += t2 - t1
         t_grid += (t1 - t0) + (t3 - t2)
+    o.close()
     per_particle = t_push / (steps * n)
     grid_step = t_grid / steps
     n_full = w.n_per_species * w.nspec
     step_full = grid_step + per_particle * n_full
-    return {"value": n_full / step_full, "unit": "particle-steps/s", "cores": 1,
+    return {"value": n_full / step_full, "per_particle_ns": per_particle * 1e9,
+            "grid_s": grid_step, "cell_updates_per_s": w.nr * w.nth / grid_step, "n": n}
+
+
+def cpu_baseline(w, n_sample, steps=2):
+    """The oracle (its OpenMP build: grid loops over rows, pushes over slot
+    ranges) on the host's threads and on one thread."""
+    import oracle
+    oracle.build(force=False)
+    model, nproc, threads = host_cpu()
+    allc = oracle_rate(w, n_sample, threads, steps)
+    one = oracle_rate(w, n_sample, 1, steps)
+    return {"value": allc["value"], "unit": "particle-steps/s", "cores": threads,
             "kind": "oracle",
-            "sample": (f"{n} particles of the same workload on the full {w.nr}x{w.nth} grid, "
-                       f"{steps} steps; push time per particle ({per_particle*1e9:.0f} ns) and "
-                       f"grid time per step ({grid_step:.2f} s) scaled to {n_full:.3g} particles"),
-            "cell_updates_per_s": w.nr * w.nth / grid_step}
+            "sample": (f"{allc['n']} particles of the same workload on the full {w.nr}x{w.nth} grid, "
+                       f"{steps} steps on {threads} threads; push time per particle "
+                       f"({allc['per_particle_ns']:.1f} ns) and grid time per step "
+                       f"({allc['grid_s']:.3f} s) scaled to {w.n_per_species * w.nspec:.3g} particles"),
+            "cell_updates_per_s": allc["cell_updates_per_s"],
+            "one_core": {"value": one["value"], "cell_updates_per_s": one["cell_updates_per_s"],
+                         "per_particle_ns": round(one["per_particle_ns"], 1),
+                         "grid_s": round(one["grid_s"], 3)},
+            "cpu_model": model, "nproc": nproc}
 
 
 def main():

@@ -17,6 +17,12 @@ SRC = os.path.join(HERE, "ffpic_oracle.c")
 # loads copies with one planted mistake); such a library is used as given.
 LIB_OVERRIDE = os.environ.get("FFPIC_ORACLE_LIB", "")
 LIB = LIB_OVERRIDE or os.path.join(HERE, "libffpic_oracle.so")
+# The same source built with OpenMP: grid loops over rows, particle pushes
+# over slot ranges with per-thread deposit rows added in thread order.  With
+# one thread it is the single-thread oracle; with more it rounds the
+# deposit's sums in another (fixed) order.  Used for timing only: the pins
+# and parity tests use the single-thread build.
+LIB_OMP = os.path.join(HERE, "libffpic_oracle_omp.so")
 
 # field component numbering of the oracle (ffpic_oracle.h)
 ER, ETH, EPH, BR, BTH, BPH, JR, JTH, JPH, PSI, F, B0R, B0TH, B0PH = range(14)
@@ -24,9 +30,9 @@ PHASE_MASK, PHASE_KILL, PHASE_SORT, PHASE_PUSH, PHASE_FIELDS, PHASE_INJECT = 1, 
 PHASE_EXTRACT, PHASE_PAIRS = 64, 128
 
 
-def compile_to(src: str, out: str) -> None:
+def compile_to(src: str, out: str, openmp: bool = False) -> None:
     """Compile an oracle source file into a shared library with gcc (plain C,
-    FP contraction off)."""
+    FP contraction off; with openmp, the OpenMP build)."""
     tmp = out + ".tmp"
     # sin and cos are called as written: with them as builtins GCC merges a
     # sin and a cos of one argument into one sincos call, whose results
@@ -34,8 +40,8 @@ def compile_to(src: str, out: str) -> None:
     # 80 pi / 300 and 159 pi / 300, for example)
     subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared",
                            "-ffp-contract=off", "-fno-fast-math",
-                           "-fno-builtin-sin", "-fno-builtin-cos", "-o", tmp,
-                           src, "-lm"])
+                           "-fno-builtin-sin", "-fno-builtin-cos",
+                           *(["-fopenmp"] if openmp else []), "-o", tmp, src, "-lm"])
     os.replace(tmp, out)
 
 
@@ -45,6 +51,8 @@ def build(force: bool = True) -> str:
         return LIB
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         compile_to(SRC, LIB)
+    if force or not os.path.exists(LIB_OMP) or os.path.getmtime(LIB_OMP) < os.path.getmtime(SRC):
+        compile_to(SRC, LIB_OMP, openmp=True)
     return LIB
 
 
@@ -72,15 +80,15 @@ class _SpecReq(C.Structure):
                 ("ngamma", C.c_int), ("nnu", C.c_int)]
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB):
+def lib(path: str = LIB):
+    """The oracle library at path (the single-thread build by default)."""
+    if path not in _libs:
+        if not os.path.exists(path):
             build()
-        L = C.CDLL(LIB)
+        L = C.CDLL(path)
         P = C.c_void_p
         dp = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
         L.ora_create.restype = P
@@ -128,8 +136,10 @@ def lib():
         L.ora_synchrotron_F.argtypes = [C.c_double]
         L.ora_rr_factor.restype = C.c_double
         L.ora_rr_factor.argtypes = [C.POINTER(_Params), C.c_double]
-        _lib = L
-    return _lib
+        L.ora_set_threads.argtypes = [C.c_int]
+        L.ora_threads.restype = C.c_int
+        _libs[path] = L
+    return _libs[path]
 
 
 def params(desc: dict) -> _Params:
@@ -169,22 +179,27 @@ def philox4x32(ctr, key) -> np.ndarray:
 
 
 class Oracle:
-    """One simulated magnetosphere held by the CPU oracle."""
+    """One simulated magnetosphere held by the CPU oracle.  threads=None uses
+    the single-thread build; an integer uses the OpenMP build with that many
+    threads (for timing)."""
 
-    def __init__(self, desc: dict):
+    def __init__(self, desc: dict, threads=None):
         self.desc = dict(desc)
         self.nr, self.nth = int(desc["nr"]), int(desc["nth"])
         self._p = params(desc)
-        self._h = lib().ora_create(C.byref(self._p))
+        self._L = lib() if threads is None else lib(LIB_OMP)
+        if threads is not None:
+            self._L.ora_set_threads(int(threads))
+        self._h = self._L.ora_create(C.byref(self._p))
         if not self._h:
             raise ValueError("oracle rejected the parameters")
         info = np.zeros(4)
-        lib().ora_info(self._h, info)
+        self._L.ora_info(self._h, info)
         self.dt, self.dlog, self.dth, self.omega = (float(x) for x in info)
 
     def close(self):
         if self._h:
-            lib().ora_destroy(self._h)
+            self._L.ora_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -199,7 +214,7 @@ class Oracle:
 
     def field(self, comp: int) -> np.ndarray:
         out = np.zeros(self.shape)
-        lib().ora_get_field(self._h, comp, out)
+        self._L.ora_get_field(self._h, comp, out)
         return out
 
     def geometry(self, which: int) -> np.ndarray:
@@ -208,93 +223,93 @@ class Oracle:
         n = [self.nr + 1, self.nr, self.nth + 1, self.nth + 1, self.nth + 1,
              self.nth, self.nth][which]
         out = np.zeros(n)
-        lib().ora_geometry(self._h, int(which), out)
+        self._L.ora_geometry(self._h, int(which), out)
         return out
 
     def set_field(self, comp: int, arr: np.ndarray):
-        lib().ora_set_field(self._h, comp, np.ascontiguousarray(arr, dtype=np.float64))
+        self._L.ora_set_field(self._h, comp, np.ascontiguousarray(arr, dtype=np.float64))
 
     def load(self, sp: int, d: dict) -> int:
         a = [np.ascontiguousarray(d[k], dtype=np.float64) for k in ("r", "th", "ur", "uth", "uph")]
-        return int(lib().ora_load_particles(self._h, sp, len(a[0]), *a))
+        return int(self._L.ora_load_particles(self._h, sp, len(a[0]), *a))
 
     def n(self, sp: int) -> int:
-        return int(lib().ora_num_particles(self._h, sp))
+        return int(self._L.ora_num_particles(self._h, sp))
 
     def particles(self, sp: int) -> dict:
         n = self.n(sp)
         out = {k: np.zeros(n) for k in ("r", "th", "ur", "uth", "uph")}
         cell = np.zeros(n, dtype=np.int32)
-        lib().ora_get_particles(self._h, sp, out["r"], out["th"], out["ur"],
+        self._L.ora_get_particles(self._h, sp, out["r"], out["th"], out["ur"],
                                 out["uth"], out["uph"], cell)
         out["cell"] = cell
         return out
 
     def step(self, n: int = 1):
-        lib().ora_step(self._h, int(n))
+        self._L.ora_step(self._h, int(n))
 
     def phases(self, mask: int):
-        lib().ora_run_phases(self._h, int(mask))
+        self._L.ora_run_phases(self._h, int(mask))
 
     def step_count(self) -> int:
-        return int(lib().ora_step_count(self._h))
+        return int(self._L.ora_step_count(self._h))
 
     def set_step(self, n: int):
-        lib().ora_set_step(self._h, int(n))
+        self._L.ora_set_step(self._h, int(n))
 
     def removed(self, sp: int) -> np.ndarray:
         out = np.zeros(4, dtype=np.int64)
-        lib().ora_removed(self._h, sp, out)
+        self._L.ora_removed(self._h, sp, out)
         return out
 
     def moments(self, sp: int) -> np.ndarray:
         out = np.zeros(5)
-        lib().ora_moments(self._h, sp, out)
+        self._L.ora_moments(self._h, sp, out)
         return out
 
     def gauss(self) -> np.ndarray:
         out = np.zeros(self.shape)
-        lib().ora_gauss(self._h, out)
+        self._L.ora_gauss(self._h, out)
         return out
 
     def divb(self) -> np.ndarray:
         out = np.zeros(self.shape)
-        lib().ora_divb(self._h, out)
+        self._L.ora_divb(self._h, out)
         return out
 
     def node_charge(self) -> np.ndarray:
         out = np.zeros(self.shape)
-        lib().ora_node_charge(self._h, out)
+        self._L.ora_node_charge(self._h, out)
         return out
 
     def poynting(self) -> np.ndarray:
         out = np.zeros(self.nr + 1)
-        lib().ora_poynting(self._h, out)
+        self._L.ora_poynting(self._h, out)
         return out
 
     def inject_rate(self, j: int) -> float:
-        return float(lib().ora_inject_rate(self._h, int(j)))
+        return float(self._L.ora_inject_rate(self._h, int(j)))
 
     def spectra(self, sp: int, req: dict) -> dict:
         """gamma histogram dN, radiated power prad and synchrotron SED of one
         species over a region; req keys as in spec_request()."""
         q = spec_request(req)
         dN, sed, prad = np.zeros(q.ngamma), np.zeros(q.nnu), np.zeros(1)
-        lib().ora_spectra(self._h, int(sp), C.byref(q), dN, sed, prad)
+        self._L.ora_spectra(self._h, int(sp), C.byref(q), dN, sed, prad)
         return {"dN": dN, "sed": sed, "prad": float(prad[0])}
 
     def gj_target(self, j: int) -> float:
-        return float(lib().ora_gj_target(self._h, int(j)))
+        return float(self._L.ora_gj_target(self._h, int(j)))
 
     def gather(self, r: float, th: float):
         E = np.zeros(3)
         B = np.zeros(3)
-        lib().ora_gather(self._h, float(r), float(th), E, B)
+        self._L.ora_gather(self._h, float(r), float(th), E, B)
         return E, B
 
     def sort_offsets(self, sp: int) -> np.ndarray:
         out = np.zeros(self.nr * self.nth + 1, dtype=np.int32)
-        lib().ora_sort_offsets(self._h, sp, out)
+        self._L.ora_sort_offsets(self._h, sp, out)
         return out
 
 

@@ -33,8 +33,13 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define PI 3.14159265358979323846
+
+#define ORA_MAXTHREADS 256
 
 struct species {
     int64_t n, cap;
@@ -53,6 +58,8 @@ struct ora_sim {
     uint8_t *kill;            /* nr*nth */
     struct species sp[ORA_MAXSPEC];
     int64_t removed[ORA_MAXSPEC][4];
+    double *tbuf[ORA_MAXTHREADS];   /* OpenMP build: per-thread deposit rows */
+    size_t tcap[ORA_MAXTHREADS];
     int64_t step;
     int32_t *offsets[ORA_MAXSPEC];
 };
@@ -126,6 +133,7 @@ double ora_blend(double psi, const double t[4])
 static void compute_psi_mask(ora_sim *s)
 {
     int nr = s->nr, nth = s->nth;
+#pragma omp parallel for schedule(static)
     for (int i = 0; i <= nr; i++) {
         double psi = 0.0;
         AT(s, ORA_PSI, i, 0) = 0.0;
@@ -134,10 +142,12 @@ static void compute_psi_mask(ora_sim *s)
             AT(s, ORA_PSI, i, j + 1) = psi;
         }
     }
+#pragma omp parallel for schedule(static)
     for (int i = 0; i <= nr; i++)
         for (int j = 0; j <= nth; j++)
             AT(s, ORA_F, i, j) = s->p.ff_enable
                 ? ora_blend(AT(s, ORA_PSI, i, j), s->p.psi_thr) : 0.0;
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < nr; i++)
         for (int j = 0; j < nth; j++)
             s->kill[(size_t)i * nth + j] =
@@ -291,6 +301,7 @@ void ora_destroy(ora_sim *s)
     free(s->rn); free(s->rh); free(s->thn); free(s->sn); free(s->cn);
     free(s->sh); free(s->ch);
     for (int c = 0; c < ORA_NCOMP; c++) free(s->F[c]);
+    for (int t = 0; t < ORA_MAXTHREADS; t++) free(s->tbuf[t]);
     free(s->kill);
     for (int k = 0; k < ORA_MAXSPEC; k++) {
         struct species *q = &s->sp[k];
@@ -314,6 +325,25 @@ void ora_geometry(const ora_sim *s, int which, double *dst)
     size_t len[7] = {(size_t)s->nr + 1, (size_t)s->nr, (size_t)s->nth + 1, (size_t)s->nth + 1,
                      (size_t)s->nth + 1, (size_t)s->nth, (size_t)s->nth};
     if (which >= 0 && which < 7) memcpy(dst, src[which], len[which] * sizeof(double));
+}
+
+/* threads of the OpenMP build (no effect in the single-thread build) */
+void ora_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+int ora_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 void ora_get_field(const ora_sim *s, int c, double *dst)
@@ -413,15 +443,18 @@ static void kill_masked(ora_sim *s)
 {
     for (int k = 0; k < s->p.nspec; k++) {
         struct species *q = &s->sp[k];
+        int64_t nk = 0;
+#pragma omp parallel for reduction(+ : nk) schedule(static)
         for (int64_t p = 0; p < q->n; p++) {
             if (!(q->r[p] > 0.0)) continue;
             int i, j; double a, b;
             locate(s, q->r[p], q->th[p], &i, &j, &a, &b);
             if (s->kill[(size_t)i * s->nth + j]) {
                 q->r[p] = -1.0;
-                s->removed[k][1]++;
+                nk++;
             }
         }
+        s->removed[k][1] += nk;
     }
 }
 
@@ -600,8 +633,14 @@ void ora_boris_rr(double u[3], const double E[3], const double B[3],
    coordinates; radial and polar charge fluxes through the dual faces,
    azimuthal current from v_phi at the mid-point                        */
 
-static void deposit(ora_sim *s, double Q, int i1, int j1, double a1, double b1,
-                    int i2, int j2, double a2, double b2, double vph)
+/* deposit target: the three accumulators of the rows from i0 on, ld
+   entries a row (the grid's own, or in the parallel build one thread's
+   private rows, added to the grid's afterwards in thread order) */
+typedef struct { double *acc[3]; int i0, ld, rows; } jtarget;
+#define JT(t, k, i, j) ((t)->acc[k][(size_t)((i) - (t)->i0) * (t)->ld + (j)])
+
+static void deposit(const ora_sim *s, const jtarget *t, double Q, int i1, int j1, double a1,
+                    double b1, int i2, int j2, double a2, double b2, double vph)
 {
     int di = i2 - i1, dj = j2 - j1;
     double x1 = a1, y1 = b1, x2 = di + a2, y2 = dj + b2;
@@ -611,24 +650,24 @@ static void deposit(ora_sim *s, double Q, int i1, int j1, double a1, double b1,
     double fx2 = Q * (x2 - xr), fy2 = Q * (y2 - yr);
     double wx1 = 0.5 * (x1 + xr), wy1 = 0.5 * (y1 + yr);
     double wx2 = 0.5 * (xr + x2) - di, wy2 = 0.5 * (yr + y2) - dj;
-    AT(s, ORA_JR, i1, j1) += fx1 * (1.0 - wy1);
-    AT(s, ORA_JR, i1, j1 + 1) += fx1 * wy1;
-    AT(s, ORA_JTH, i1, j1) += fy1 * (1.0 - wx1);
-    AT(s, ORA_JTH, i1 + 1, j1) += fy1 * wx1;
-    AT(s, ORA_JR, i2, j2) += fx2 * (1.0 - wy2);
-    AT(s, ORA_JR, i2, j2 + 1) += fx2 * wy2;
-    AT(s, ORA_JTH, i2, j2) += fy2 * (1.0 - wx2);
-    AT(s, ORA_JTH, i2 + 1, j2) += fy2 * wx2;
+    JT(t, 0, i1, j1) += fx1 * (1.0 - wy1);
+    JT(t, 0, i1, j1 + 1) += fx1 * wy1;
+    JT(t, 1, i1, j1) += fy1 * (1.0 - wx1);
+    JT(t, 1, i1 + 1, j1) += fy1 * wx1;
+    JT(t, 0, i2, j2) += fx2 * (1.0 - wy2);
+    JT(t, 0, i2, j2 + 1) += fx2 * wy2;
+    JT(t, 1, i2, j2) += fy2 * (1.0 - wx2);
+    JT(t, 1, i2 + 1, j2) += fy2 * wx2;
     double xm = 0.5 * (x1 + x2), ym = 0.5 * (y1 + y2);
     int im = (int)floor(xm), jm = (int)floor(ym);
     if (i1 + im > s->nr - 1) im = s->nr - 1 - i1;
     if (j1 + jm > s->nth - 1) jm = s->nth - 1 - j1;
     double wx = xm - im, wy = ym - jm;
     double qv = Q * vph;
-    AT(s, ORA_JPH, i1 + im, j1 + jm) += qv * (1.0 - wx) * (1.0 - wy);
-    AT(s, ORA_JPH, i1 + im + 1, j1 + jm) += qv * wx * (1.0 - wy);
-    AT(s, ORA_JPH, i1 + im, j1 + jm + 1) += qv * (1.0 - wx) * wy;
-    AT(s, ORA_JPH, i1 + im + 1, j1 + jm + 1) += qv * wx * wy;
+    JT(t, 2, i1 + im, j1 + jm) += qv * (1.0 - wx) * (1.0 - wy);
+    JT(t, 2, i1 + im + 1, j1 + jm) += qv * wx * (1.0 - wy);
+    JT(t, 2, i1 + im, j1 + jm + 1) += qv * (1.0 - wx) * wy;
+    JT(t, 2, i1 + im + 1, j1 + jm + 1) += qv * wx * wy;
 }
 
 /* Radiation-reaction ramp of Sect. 5 (reduced strength while the
@@ -650,59 +689,144 @@ double ora_rr_factor(const ora_params *p, double t)
     return p->rr_ramp_f[n - 1];
 }
 
+/* one particle of species k: Boris rotation and radiation reaction in the
+   local Cartesian frame at azimuth 0 (x along the cylindrical radius, y
+   along phi, z along the rotation axis), move, rotation back into the
+   meridional plane, deposit; removed[0], removed[1] count the particles
+   that reach the star and the absorber */
+typedef struct { double Q, wq, rr; } push_consts;
+
+static void push_one(ora_sim *s, int k, int64_t p, const push_consts *pc, const jtarget *t,
+                     int64_t removed[2])
+{
+    struct species *q = &s->sp[k];
+    double dt = s->dt;
+    if (!(q->r[p] > 0.0)) return;
+    double r = q->r[p], th = q->th[p];
+    int i, j; double a, b;
+    locate(s, r, th, &i, &j, &a, &b);
+    double Es[3], Bs[3];
+    gather(s, i, j, a, b, Es, Bs);
+    double st = sin(th), ct = cos(th);
+    double E[3] = {Es[0] * st + Es[1] * ct, Es[2], Es[0] * ct - Es[1] * st};
+    double B[3] = {Bs[0] * st + Bs[1] * ct, Bs[2], Bs[0] * ct - Bs[1] * st};
+    double u[3] = {q->ur[p] * st + q->uth[p] * ct, q->uph[p],
+                   q->ur[p] * ct - q->uth[p] * st};
+    ora_boris_rr(u, E, B, dt, pc->wq, pc->rr);
+    if (r < s->p.shell_r) {
+        /* shell around the star (Sect. 5): only the momentum along the
+           local magnetic field is kept */
+        double b2 = dot3(B, B);
+        if (b2 > 0.0) {
+            double ub = dot3(u, B) / b2;
+            for (int c = 0; c < 3; c++) u[c] = ub * B[c];
+        }
+    }
+    double g = sqrt(1.0 + dot3(u, u));
+    double v[3] = {u[0] / g, u[1] / g, u[2] / g};
+    double x = r * st + dt * v[0], y = dt * v[1], z = r * ct + dt * v[2];
+    double w = sqrt(x * x + y * y);
+    double cp = w > 0.0 ? x / w : 1.0, sp = w > 0.0 ? y / w : 0.0;
+    double ux = cp * u[0] + sp * u[1], uy = -sp * u[0] + cp * u[1], uz = u[2];
+    double r2 = sqrt(w * w + z * z);
+    double th2 = atan2(w, z);
+    if (!(r2 >= s->p.rmin)) { q->r[p] = -1.0; removed[0]++; return; }
+    if (r2 >= s->p.r_abs) { q->r[p] = -1.0; removed[1]++; return; }
+    double st2 = w / r2, ct2 = z / r2;
+    int i2, j2; double a2, b2;
+    locate(s, r2, th2, &i2, &j2, &a2, &b2);
+    deposit(s, t, pc->Q, i, j, a, b, i2, j2, a2, b2, v[1]);
+    q->r[p] = r2;
+    q->th[p] = th2;
+    q->ur[p] = ux * st2 + uz * ct2;
+    q->uth[p] = ux * ct2 - uz * st2;
+    q->uph[p] = uy;
+}
+
+#ifdef _OPENMP
+/* The same push on T threads, each over an equal range of slots.  After a
+   sort the slots of a range hold a compact band of cells, so each thread
+   deposits into private rows covering its particles' cells and the reach
+   of a move; the private rows are then added to the grid's in thread
+   order, so the result does not depend on the threads' timing. */
+static void push_species_threads(ora_sim *s, int k, const push_consts *pc, int T)
+{
+    struct species *q = &s->sp[k];
+    const int64_t n = q->n;
+    jtarget tg[ORA_MAXTHREADS];
+    int64_t rem[ORA_MAXTHREADS][2];
+    if (T > ORA_MAXTHREADS) T = ORA_MAXTHREADS;
+#pragma omp parallel num_threads(T)
+    {
+        const int t = omp_get_thread_num();
+        const int64_t a = n * t / T, b = n * (t + 1) / T;
+        int imin = s->nr, imax = -1;
+        for (int64_t p = a; p < b; p++) {
+            if (!(q->r[p] > 0.0)) continue;
+            int i, j; double aa, bb;
+            locate(s, q->r[p], q->th[p], &i, &j, &aa, &bb);
+            if (i < imin) imin = i;
+            if (i > imax) imax = i;
+        }
+        rem[t][0] = rem[t][1] = 0;
+        tg[t].rows = 0;
+        if (imax >= 0) {
+            int r0 = imin - 1 < 0 ? 0 : imin - 1;
+            int r1 = imax + 2 > s->nr ? s->nr : imax + 2;
+            size_t len = (size_t)(r1 - r0 + 1) * s->ld;
+            if (s->tcap[t] < 3 * len) {
+                free(s->tbuf[t]);
+                s->tbuf[t] = malloc(3 * len * sizeof(double));
+                s->tcap[t] = 3 * len;
+            }
+            memset(s->tbuf[t], 0, 3 * len * sizeof(double));
+            tg[t].i0 = r0;
+            tg[t].ld = s->ld;
+            tg[t].rows = r1 - r0 + 1;
+            for (int c = 0; c < 3; c++) tg[t].acc[c] = s->tbuf[t] + c * len;
+            for (int64_t p = a; p < b; p++) push_one(s, k, p, pc, &tg[t], rem[t]);
+        }
+    }
+    /* each grid row adds the threads' rows in thread order */
+#pragma omp parallel for schedule(static) num_threads(T)
+    for (int i = 0; i <= s->nr; i++) {
+        for (int t = 0; t < T; t++) {
+            if (tg[t].rows == 0 || i < tg[t].i0 || i >= tg[t].i0 + tg[t].rows) continue;
+            for (int c = 0; c < 3; c++) {
+                double *dst = s->F[ORA_JR + c] + (size_t)i * s->ld;
+                const double *src = tg[t].acc[c] + (size_t)(i - tg[t].i0) * s->ld;
+                for (int j = 0; j < s->ld; j++) dst[j] += src[j];
+            }
+        }
+    }
+    for (int t = 0; t < T; t++) {
+        s->removed[k][2] += rem[t][0];
+        s->removed[k][3] += rem[t][1];
+    }
+}
+#endif
+
 static void push_species(ora_sim *s, int k)
 {
     struct species *q = &s->sp[k];
     double qm = s->p.qm[k];
-    double Q = (qm > 0 ? 1.0 : -1.0) * s->p.weight[k];
-    double wq = s->p.omega_b * qm;
-    double rr = s->p.rr_coef * ora_rr_factor(&s->p, (double)s->step * s->dt) *
-                fabs(qm) * fabs(qm) * fabs(qm);
-    double dt = s->dt;
-    for (int64_t p = 0; p < q->n; p++) {
-        if (!(q->r[p] > 0.0)) continue;
-        double r = q->r[p], th = q->th[p];
-        int i, j; double a, b;
-        locate(s, r, th, &i, &j, &a, &b);
-        double Es[3], Bs[3];
-        gather(s, i, j, a, b, Es, Bs);
-        double st = sin(th), ct = cos(th);
-        /* local Cartesian frame at phi = 0: x along cylindrical radius,
-           y along phi, z along the rotation axis */
-        double E[3] = {Es[0] * st + Es[1] * ct, Es[2], Es[0] * ct - Es[1] * st};
-        double B[3] = {Bs[0] * st + Bs[1] * ct, Bs[2], Bs[0] * ct - Bs[1] * st};
-        double u[3] = {q->ur[p] * st + q->uth[p] * ct, q->uph[p],
-                       q->ur[p] * ct - q->uth[p] * st};
-        ora_boris_rr(u, E, B, dt, wq, rr);
-        if (r < s->p.shell_r) {
-            /* shell around the star (Sect. 5): only the momentum along
-               the local magnetic field is kept */
-            double b2 = dot3(B, B);
-            if (b2 > 0.0) {
-                double ub = dot3(u, B) / b2;
-                for (int c = 0; c < 3; c++) u[c] = ub * B[c];
-            }
-        }
-        double g = sqrt(1.0 + dot3(u, u));
-        double v[3] = {u[0] / g, u[1] / g, u[2] / g};
-        double x = r * st + dt * v[0], y = dt * v[1], z = r * ct + dt * v[2];
-        double w = sqrt(x * x + y * y);
-        double cp = w > 0.0 ? x / w : 1.0, sp = w > 0.0 ? y / w : 0.0;
-        double ux = cp * u[0] + sp * u[1], uy = -sp * u[0] + cp * u[1], uz = u[2];
-        double r2 = sqrt(w * w + z * z);
-        double th2 = atan2(w, z);
-        if (!(r2 >= s->p.rmin)) { q->r[p] = -1.0; s->removed[k][2]++; continue; }
-        if (r2 >= s->p.r_abs) { q->r[p] = -1.0; s->removed[k][3]++; continue; }
-        double st2 = w / r2, ct2 = z / r2;
-        int i2, j2; double a2, b2;
-        locate(s, r2, th2, &i2, &j2, &a2, &b2);
-        deposit(s, Q, i, j, a, b, i2, j2, a2, b2, v[1]);
-        q->r[p] = r2;
-        q->th[p] = th2;
-        q->ur[p] = ux * st2 + uz * ct2;
-        q->uth[p] = ux * ct2 - uz * st2;
-        q->uph[p] = uy;
+    push_consts pc;
+    pc.Q = (qm > 0 ? 1.0 : -1.0) * s->p.weight[k];
+    pc.wq = s->p.omega_b * qm;
+    pc.rr = s->p.rr_coef * ora_rr_factor(&s->p, (double)s->step * s->dt) *
+            fabs(qm) * fabs(qm) * fabs(qm);
+#ifdef _OPENMP
+    const int T = omp_get_max_threads();
+    if (T > 1 && q->n >= 4096) {
+        push_species_threads(s, k, &pc, T);
+        return;
     }
+#endif
+    jtarget grid = {{s->F[ORA_JR], s->F[ORA_JTH], s->F[ORA_JPH]}, 0, s->ld, s->nr + 1};
+    int64_t rem[2] = {0, 0};
+    for (int64_t p = 0; p < q->n; p++) push_one(s, k, p, &pc, &grid, rem);
+    s->removed[k][2] += rem[0];
+    s->removed[k][3] += rem[1];
 }
 
 /* ------------------------------------------------------------------ */
@@ -712,12 +836,14 @@ static void push_species(ora_sim *s, int k)
 static void faraday(ora_sim *s, double h)
 {
     int nr = s->nr, nth = s->nth;
+#pragma omp parallel for schedule(static)
     for (int i = 0; i <= nr; i++)
         for (int j = 0; j < nth; j++) {
             double circ = s->rn[i] * (s->sn[j + 1] * AT(s, ORA_EPH, i, j + 1) -
                                       s->sn[j] * AT(s, ORA_EPH, i, j));
             AT(s, ORA_BR, i, j) -= h * circ / area_r(s, i, j);
         }
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < nr; i++) {
         for (int j = 1; j < nth; j++) {
             double circ = s->sn[j] * (s->rn[i + 1] * AT(s, ORA_EPH, i + 1, j) -
@@ -727,6 +853,7 @@ static void faraday(ora_sim *s, double h)
         AT(s, ORA_BTH, i, 0) = 0.0;
         AT(s, ORA_BTH, i, nth) = 0.0;
     }
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < nr; i++)
         for (int j = 0; j < nth; j++) {
             double circ = s->dth * (s->rn[i + 1] * AT(s, ORA_ETH, i + 1, j) -
@@ -812,6 +939,7 @@ static void field_step(ora_sim *s)
     /* force-free current at nodes: drift part of eq. JFFE,
        J = rho (E x B) / B^2 with rho = div E / 4 pi (E^n, B^{n+1/2}) */
     if (s->p.ff_enable) {
+#pragma omp parallel for schedule(static)
         for (int i = 0; i <= nr; i++)
             for (int j = 0; j <= nth; j++) {
                 int ii = i == 0 ? 1 : i;
@@ -827,6 +955,7 @@ static void field_step(ora_sim *s)
     }
 
     /* eq. ampere with the blended current of eq. blending */
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < nr; i++)
         for (int j = 0; j <= nth; j++) {
             double A = darea_r(s, i, j);
@@ -837,6 +966,7 @@ static void field_step(ora_sim *s)
                        f * 0.5 * (JN(0, i, j) + JN(0, i + 1, j));
             AT(s, ORA_ER, i, j) += dt * circ / A - fourpi * dt * J;
         }
+#pragma omp parallel for schedule(static)
     for (int i = 1; i < nr; i++)
         for (int j = 0; j < nth; j++) {
             double A = darea_th(s, i, j);
@@ -847,6 +977,7 @@ static void field_step(ora_sim *s)
                        f * 0.5 * (JN(1, i, j) + JN(1, i, j + 1));
             AT(s, ORA_ETH, i, j) += dt * circ / A - fourpi * dt * J;
         }
+#pragma omp parallel for schedule(static)
     for (int i = 1; i < nr; i++)
         for (int j = 1; j < nth; j++) {
             double A = darea_ph(s, i, j);
@@ -861,6 +992,7 @@ static void field_step(ora_sim *s)
 
     /* force-free E correction at nodes, weighted by f, averaged back */
     if (s->p.ff_enable) {
+#pragma omp parallel for schedule(static)
         for (int i = 0; i <= nr; i++)
             for (int j = 0; j <= nth; j++) {
                 double f = AT(s, ORA_F, i, j);
@@ -871,12 +1003,15 @@ static void field_step(ora_sim *s)
                 ora_ff_node(e, b, o);
                 for (int c = 0; c < 3; c++) DL(c, i, j) = f * (o[c] - e[c]);
             }
+#pragma omp parallel for schedule(static)
         for (int i = 0; i < nr; i++)
             for (int j = 0; j <= nth; j++)
                 AT(s, ORA_ER, i, j) += 0.5 * (DL(0, i, j) + DL(0, i + 1, j));
+#pragma omp parallel for schedule(static)
         for (int i = 1; i < nr; i++)
             for (int j = 0; j < nth; j++)
                 AT(s, ORA_ETH, i, j) += 0.5 * (DL(1, i, j) + DL(1, i, j + 1));
+#pragma omp parallel for schedule(static)
         for (int i = 1; i < nr; i++)
             for (int j = 1; j < nth; j++)
                 AT(s, ORA_EPH, i, j) += DL(2, i, j);
@@ -885,6 +1020,7 @@ static void field_step(ora_sim *s)
     faraday(s, 0.5 * dt);                               /* B^{n+1} */
 
     /* absorbing layer beyond r_abs: damp E, relax B to its initial value */
+#pragma omp parallel for schedule(static)
     for (int i = 0; i <= nr; i++) {
         double ln = absorb(s, s->rn[i]);
         double lh = i < nr ? absorb(s, s->rh[i]) : 1.0;

@@ -108,6 +108,10 @@ int64_t ora_num_particles(const ora_sim *s, int sp);
 int64_t ora_get_particles(const ora_sim *s, int sp, double *r, double *th,
                           double *ur, double *uth, double *uph, int32_t *cell);
 void ora_step(ora_sim *s, int nsteps);
+/* threads of the OpenMP build (the single-thread build ignores it, and
+   reports 1) */
+void ora_set_threads(int n);
+int ora_threads(void);
 /* Philox4x32-10 counter-based generator (Salmon et al. 2011): out = the
    four 32-bit words for counter ctr and key */
 void ora_philox4x32(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

@@ -30,11 +30,11 @@ MUTANTS = [
      "double qv = Q * vph;",
      "double qv = -Q * vph;"),
     ("J_phi theta weight of one corner",
-     "AT(s, ORA_JPH, i1 + im + 1, j1 + jm) += qv * wx * (1.0 - wy);",
-     "AT(s, ORA_JPH, i1 + im + 1, j1 + jm) += qv * wx * wy;"),
+     "JT(t, 2, i1 + im + 1, j1 + jm) += qv * wx * (1.0 - wy);",
+     "JT(t, 2, i1 + im + 1, j1 + jm) += qv * wx * wy;"),
     ("J_phi weights of two theta corners exchanged",
-     "AT(s, ORA_JPH, i1 + im, j1 + jm + 1) += qv * (1.0 - wx) * wy;",
-     "AT(s, ORA_JPH, i1 + im, j1 + jm + 1) += qv * (1.0 - wx) * (1.0 - wy);"),
+     "JT(t, 2, i1 + im, j1 + jm + 1) += qv * (1.0 - wx) * wy;",
+     "JT(t, 2, i1 + im, j1 + jm + 1) += qv * (1.0 - wx) * (1.0 - wy);"),
     ("J_phi at the start of the move instead of its midpoint",
      "double xm = 0.5 * (x1 + x2), ym = 0.5 * (y1 + y2);",
      "double xm = x1, ym = y1;"),
