@@ -280,9 +280,26 @@ int ffpic_get_particles_range(ffpic_ctx *ctx, int species, int64_t first, int64_
                               double *r, double *th, double *ur, double *uth, double *uph,
                               int32_t *cell);
 
-/* Test hook: cell offsets of the last sort of a species (nr*nth + 1 int32
-   to host memory): offsets[k] = number of live particles with cell < k. */
-int ffpic_get_sort(ffpic_ctx *ctx, int species, int32_t *cell_offsets);
+/* Test hook: the current order of a species as cell offsets (nr*nth + 1
+   int32 to host memory): cell_offsets[k] = number of live particles with
+   cell < k (the particles are in cell order right after a sort).  perm
+   (nullable, host memory) receives the permutation of the species' last
+   sort: perm[k] = the slot, before that sort, of the particle now in slot
+   k, for k below the live count after that sort, which goes to *nperm
+   (nullable; call with perm NULL first to size it).  The sort is the
+   stable sort by cell of Sect. 3's particle loop, dead and removed
+   particles dropped.  Recording costs one 4-byte write per particle and
+   sort and is off unless ffpic_record_sort(ctx, 1) was called before the
+   sort; EINVAL for perm or nperm when the last sort of that species was
+   not recorded, for a species out of range or NULL offsets.  Synchronises. */
+int ffpic_get_sort(ffpic_ctx *ctx, int species, int32_t *cell_offsets, int32_t *perm,
+                   int64_t *nperm);
+
+/* Turns the recording of the sort permutation (see ffpic_get_sort) on or
+   off for the sorts that follow; turning it on allocates one int32 per
+   particle slot of every species.  Not to be called while a step is being
+   captured. */
+int ffpic_record_sort(ffpic_ctx *ctx, int on);
 
 /* Test hooks, host only (no device is touched, no context is made): what
    ffpic_create builds on the host for descriptor d, so that it can be

@@ -95,8 +95,6 @@ struct ffpic_ctx {
     // (FP64, host-computed), per-cell counts and their scan
     double *inj_rate = nullptr;
     int32_t *inj_cnt = nullptr, *inj_off = nullptr;
-    void *inj_scan_tmp = nullptr;
-    size_t inj_scan_bytes = 0;
     int64_t inj_bound = 0;                    // most pairs one step can add
     // Goldreich-Julian extraction: target charge of each surface cell (FP64,
     // host-computed), per-species particle counts of the surface cells
@@ -106,10 +104,7 @@ struct ffpic_ctx {
     // threshold pair creation: per-block parent counts of both parent
     // species and their exclusive scan
     int32_t *pair_cnt = nullptr, *pair_off = nullptr;
-    void *pair_scan_tmp = nullptr;
-    size_t pair_scan_bytes = 0;
     int64_t pair_blocks = 0;                  // capacity of pair_cnt (entries - 1)
-    int32_t *nslots_host = nullptr;           // pinned copy of nslots
     // spectra: table of ln F of the synchrotron function, the gamma bin
     // edges and frequencies of the last request
     double *spec_tab = nullptr, *spec_edge = nullptr, *spec_nu = nullptr;
@@ -118,8 +113,6 @@ struct ffpic_ctx {
     uint8_t *kill = nullptr;
     ffpic::Species sp[FFPIC_MAX_SPECIES];
     uint32_t *keys[2] = {}, *vals[2] = {};
-    void *sort_tmp = nullptr;
-    size_t sort_tmp_bytes = 0;
     // incremental re-sort: per species the sorted keys and cell offsets of
     // the last sort (double-buffered), plus shared scratch
     uint32_t *skey[FFPIC_MAX_SPECIES][2] = {};
@@ -127,17 +120,23 @@ struct ffpic_ctx {
     int sort_cur[FFPIC_MAX_SPECIES] = {};
     bool sort_valid[FFPIC_MAX_SPECIES] = {};
     bool incremental_sort = true;
-    uint32_t *sort_sb = nullptr;              // stayers before each slot [cap + 1]
-    uint32_t *sort_blk = nullptr;             // block counts and their scans [4 * blocks]
+    uint64_t *sort_smask = nullptr, *sort_mmask = nullptr;   // stayer / mover bits [cap/64 + 1]
+    uint32_t *sort_wsm = nullptr;             // counts before each word in its tile
+    uint2 *sort_tc = nullptr, *sort_ts = nullptr, *sort_gs = nullptr;   // tile / group counts
     uint32_t *sort_aux = nullptr;             // sorted mover slots [cap]
-    uint8_t *sort_cls = nullptr;              // FP32: class of each slot [cap]
-    int32_t *sort_moff = nullptr;             // movers below each key [nr*nth + 1]
     int32_t *sort_mst = nullptr;              // movers before each key's stayers [nr*nth + 1]
-    uint32_t *sort_cbuf = nullptr;            // FP32: non-stayers' state, compacted [6 * cbuf_n]
+    void *sort_cbuf = nullptr;                // movers' state, compacted [narr * cbuf_n]
     int64_t sort_cbuf_n = 0;
     uint32_t *sort_tot = nullptr;             // stayers, movers
-    void *scan_tmp = nullptr;
-    size_t scan_tmp_bytes = 0;
+    uint32_t *rs_hist = nullptr, *rs_dtot = nullptr;   // radix sort: digit counts per tile
+    int rs_stride = 0;                        // tiles per digit row of rs_hist
+    int32_t *rs_n = nullptr;                  // radix sort: pair count (device)
+    int32_t *scan_part = nullptr;             // block sums of exclusive_scan_i32
+    int64_t scan_part_n = 0;
+    // sort permutation of the last sort of each species (ffpic_record_sort)
+    bool record_perm = false;
+    int32_t *perm[FFPIC_MAX_SPECIES] = {};
+    bool perm_valid[FFPIC_MAX_SPECIES] = {};
     int64_t sort_cap = 0;
     int32_t *nslots = nullptr;                // device [FFPIC_MAX_SPECIES]
     int32_t *nsorted = nullptr;               // device: live count at each species' last sort
@@ -200,17 +199,17 @@ void run_diagnostics(ffpic_ctx *c, uint32_t what, ffpic_diag *out, double *L_of_
 void fused32_tables(const ffpic_ctx *c, std::vector<float> &rowc, std::vector<float> &colc);
 int run_diagnostics_checked(ffpic_ctx *c, uint32_t what, ffpic_diag *out, double *L_of_r,
                             const DiagBufs &b);
-size_t sort_temp_bytes(int64_t cap, int bits);
-size_t scan_temp_bytes(int64_t nblk);
-int sort_block_slots();
+void sort_alloc(ffpic_ctx *c, int64_t cap, void *(*dmalloc)(size_t));
 int sort_key_bits(const ffpic_ctx *c);
+// exclusive scan of n int32 values on the device (block sums in scan_part,
+// which must hold scan_part_len(n) entries)
+void exclusive_scan_i32(ffpic_ctx *c, const int32_t *in, int32_t *out, int64_t n);
+int64_t scan_part_len(int64_t n);
 void zero_counters(ffpic_ctx *c, int32_t *p, int n);
 int tuned_sort_interval(const ffpic_desc *d);
 void inject_pairs(ffpic_ctx *c);
 void extract_gj(ffpic_ctx *c);
 void create_pairs(ffpic_ctx *c);
-size_t inject_scan_bytes(int nth);
-size_t pair_scan_bytes(int64_t nblk);
 int pair_block_slots();
 double rr_factor(const ffpic_ctx *c);   // radiation-reaction ramp at this step
 // dev_out: ngamma + nnu + 1 doubles (dN, sed, prad)

@@ -23,7 +23,6 @@
 // cell, species in order) is topped up to gj_extract |rho_GJ| V with
 // ceil(deficit / (w_e + w_i)) electron-ion pairs, placed and appended like
 // the injected pairs (counter word 3 = kExtTag).
-#include <rocprim/device/device_scan.hpp>
 
 #include "device_common.h"
 
@@ -144,15 +143,6 @@ __global__ void k_inject_commit(const int32_t *__restrict__ off, InjArgs A,
     for (int s = 0; s < A.nspec; s++) A.sp[s].nslots[0] += total;
 }
 
-size_t inject_scan_bytes(int nth) {
-    size_t bytes = 0;
-    hipError_t e = rocprim::exclusive_scan((void *)nullptr, bytes, (int32_t *)nullptr,
-                                           (int32_t *)nullptr, 0, (size_t)nth + 1,
-                                           rocprim::plus<int32_t>());
-    if (e != hipSuccess) throw std::runtime_error("rocprim scan size query failed");
-    return bytes;
-}
-
 namespace {
 
 InjArgs inj_args(ffpic_ctx *c, const int *targets, int ntargets, uint32_t tag) {
@@ -185,11 +175,7 @@ void append_surface(ffpic_ctx *c, const int *targets, int ntargets, uint32_t tag
     const InjArgs A = inj_args(c, targets, ntargets, tag);
     const int nth = c->nth;
     const int nb = (nth + 1 + 255) / 256;
-    size_t bytes = c->inj_scan_bytes;
-    if (rocprim::exclusive_scan(c->inj_scan_tmp, bytes, c->inj_cnt, c->inj_off, 0,
-                                (size_t)nth + 1, rocprim::plus<int32_t>(),
-                                c->stream) != hipSuccess)
-        throw std::runtime_error("rocprim scan failed");
+    exclusive_scan_i32(c, c->inj_cnt, c->inj_off, (int64_t)nth + 1);
     if (c->fp64)
         hipLaunchKernelGGL(k_inject_write<true>, dim3(nb), dim3(256), 0, c->stream, c->inj_cnt,
                            c->inj_off, A);

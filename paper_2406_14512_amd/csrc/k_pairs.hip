@@ -17,15 +17,8 @@
 // The parent test 1 + |u|^2 > gamma_th^2 is evaluated by the same code in
 // launches 1 and 3, and this file is compiled without FP contraction, so
 // both launches take the same decision for every particle.
-#include <rocprim/device/device_scan.hpp>
 
 #include "device_common.h"
-
-#define HCHK_PAIRS(x)                                                                   \
-    do {                                                                                \
-        hipError_t e_ = (x);                                                            \
-        if (e_ != hipSuccess) throw std::runtime_error(hipGetErrorString(e_));          \
-    } while (0)
 
 namespace ffpic {
 
@@ -183,18 +176,13 @@ PairTarget target(ffpic_ctx *c, int s) {
 
 int pair_block_slots() { return kPairSlots; }
 
-size_t pair_scan_bytes(int64_t nblk) {
-    size_t bytes = 0;
-    hipError_t e = rocprim::exclusive_scan((void *)nullptr, bytes, (int32_t *)nullptr,
-                                           (int32_t *)nullptr, 0, (size_t)nblk + 1,
-                                           rocprim::plus<int32_t>());
-    if (e != hipSuccess) throw std::runtime_error("rocprim scan size query failed");
-    return bytes;
-}
-
 void create_pairs(ffpic_ctx *c) {
     if (!(c->d.gamma_th > 0.0)) return;
     const int sp[2] = {c->d.pair_species[0], c->d.pair_species[1]};
+    // the number of new slots is known only on the device: from here on the
+    // launches of both species cover all their slots (each kernel stops at
+    // the device count)
+    for (int h = 0; h < 2; h++) c->sp[sp[h]].nub = c->sp[sp[h]].cap;
     int nb[2];
     for (int h = 0; h < 2; h++) nb[h] = (int)((c->sp[sp[h]].nub + kPairSlots - 1) / kPairSlots);
     const int ntot = nb[0] + nb[1];
@@ -217,11 +205,7 @@ void create_pairs(ffpic_ctx *c) {
         }
         first += nb[h];
     }
-    size_t bytes = c->pair_scan_bytes;
-    if (rocprim::exclusive_scan(c->pair_scan_tmp, bytes, c->pair_cnt, c->pair_off, 0,
-                                (size_t)ntot + 1, rocprim::plus<int32_t>(),
-                                c->stream) != hipSuccess)
-        throw std::runtime_error("rocprim scan failed");
+    exclusive_scan_i32(c, c->pair_cnt, c->pair_off, (int64_t)ntot + 1);
     first = 0;
     for (int h = 0; h < 2; h++) {
         if (nb[h] > 0) {
@@ -234,12 +218,6 @@ void create_pairs(ffpic_ctx *c) {
     }
     hipLaunchKernelGGL(k_pair_commit, dim3(1), dim3(1), 0, c->stream, c->pair_off, A, c->err);
     FFPIC_LAUNCH_CHECK();
-    // the number of new slots is known only on the device: read the counts
-    // back so that the next launches cover them
-    HCHK_PAIRS(hipMemcpyAsync(c->nslots_host, c->nslots, FFPIC_MAX_SPECIES * sizeof(int32_t),
-                              hipMemcpyDeviceToHost, c->stream));
-    HCHK_PAIRS(hipStreamSynchronize(c->stream));
-    for (int h = 0; h < 2; h++) c->sp[sp[h]].nub = c->nslots_host[sp[h]];
 }
 
 }  // namespace ffpic

@@ -1,52 +1,114 @@
 // Stable sort of each species by cell (key = i*nth + j), with the removal
-// of particles in the pure force-free domain folded into the key pass.
+// of particles in the pure force-free domain folded into the key pass.  No
+// step of it reads anything back to the host: every count lives on the
+// device, and every launch is sized by the host bound of the slots, so a
+// sort can be captured in a graph.
 //
-// 1. key pass: one thread per slot; dead slots and particles in kill cells
-//    get the dead key (larger than every live key, so they sort last and
-//    are dropped), live ones their cell.  Live particles lie inside the
-//    absorbing radius, so the dead key is the first cell of the row past
-//    it, which keeps the key within 24 bits on a 4096^2 grid (three 8-bit
-//    radix passes instead of four).
-// 2. rocPRIM LSD radix sort of (key, slot) pairs over the key's bit range:
-//    LSD radix sort is stable, so equal keys keep their slot order.
-// 3. the live count is the position of the first dead key in the sorted
-//    keys (binary search), so no pass of the sort contends on a counter.
-// 4. gather pass: the SoA state is permuted into the second buffer.
+// Full sort (the first sort of a species, or after a load):
+//   1. key pass: dead slots and particles in kill cells get the dead key
+//      (larger than every live key: the first cell of the row past the
+//      absorbing radius, so keys of a 4096^2 grid fit 24 bits), live ones
+//      their cell, paired with their slot;
+//   2. LSD radix sort of the (key, slot) pairs, 8-bit digits: per tile of
+//      4096 pairs a digit histogram, a scan of the histograms of each digit
+//      over the tiles, and a stable scatter that ranks equal digits inside
+//      a tile in slot order (so equal keys keep their slot order);
+//   3. the live count is the position of the first dead key;
+//   4. the state is gathered into the second buffer.
 //
-// Between two sorts most particles stay in their cell (a step moves a
-// particle by a fraction of a cell), so after the first sort the array is
-// re-sorted incrementally (sort_species_incremental):
-//   * a particle is a "stayer" if its key equals the key its slot had at the
-//     last sort, else a "mover" (dead slots and killed particles drop out);
-//     stayers are already in (key, slot) order;
-//   * a block scan gives SB[q] = stayers before slot q and compacts the
-//     movers (key, slot) in slot order; only the movers are radix sorted;
-//   * every particle's place in the stable order by (key, slot) follows
-//     from counts: a stayer at q with key k goes to
-//       SB[q] + (movers with key < k) + (movers with key k and slot < q),
+// Incremental sort (every later sort).  Between two sorts few particles
+// change cell, so only those are sorted:
+//   * a slot holds a "stayer" if its particle's key equals the key the slot
+//     had at the last sort, a "mover" otherwise (dead slots and killed
+//     particles drop out); the stayers are already in (key, slot) order;
+//   * the classify pass writes one stayer and one mover bit per slot (a
+//     64-bit word per 64 slots, from a wave ballot), the counts of both
+//     before each word inside its tile of 1024 slots, and the tile's movers
+//     (key, slot) compacted inside the tile; two small scans turn the tile
+//     counts into exclusive prefixes, so SB(x), the stayers before slot x,
+//     and MB(x), the movers before x, are a few loads and a popcount;
+//   * the movers are compacted into one array (slot order) and radix
+//     sorted as above (stable, so by (key, slot));
+//   * each particle's place in the stable order by (key, slot) follows from
+//     counts: a stayer at q with key k goes to
+//       SB(q) + (movers with key < k) + (movers with key k and slot < q),
 //     the mover of rank j (key k, slot q) goes to
-//       j + SB[clamp(q, OFF[k], OFF[k+1])],
+//       j + SB(clamp(q, OFF[k], OFF[k+1])),
 //     with OFF the cell offsets of the last sort (stayers with key < k sit
-//     before OFF[k], those with key k inside [OFF[k], OFF[k+1]));
-//   * one scatter pass writes the state, the sorted keys and (from the same
-//     counts) the new cell offsets, which the next sort compares against.
+//     before OFF[k], those with key k inside [OFF[k], OFF[k+1]), and no
+//     mover of key k does);
+//   * one pass over the keys gives, per key, the movers-before term of the
+//     stayers and the new cell offsets SB(OFF[k]) + (movers with key < k);
+//   * the stayer pass reads every slot once and writes the stayers to their
+//     places and the movers' state, compacted, to a buffer; the mover pass
+//     writes the movers in their sorted order from that buffer (or from
+//     their old slots past its end).
 // The result is the same stable order as a full sort of the keys.
 #include <algorithm>
 #include <cstring>
-#include <rocprim/device/device_radix_sort.hpp>
-#include <rocprim/device/device_scan.hpp>
 
 #include "device_common.h"
 
 namespace ffpic {
 
-constexpr int kSortBlock = 1024;          // slots per classify / compact block
+constexpr int kTile = 1024;                 // slots per classify tile
+constexpr int kTileWords = kTile / 64;      // 64-slot words per tile
+constexpr int kGroup = 1024;                // tiles per group of the tile scan
+constexpr int kRsItems = 16;                // pairs per thread of a radix tile
+constexpr int kRsTile = 256 * kRsItems;     // pairs per radix tile
+constexpr int kKeyChunk = 8;                // keys per thread of the key pass
+constexpr int kMoverBlocks = 2048;          // blocks of the mover placement
+constexpr int kRsBlocks = 2048;             // blocks of a radix pass
 
 #define HCHK_SORT(x)                                                                    \
     do {                                                                                \
         hipError_t e_ = (x);                                                            \
         if (e_ != hipSuccess) throw std::runtime_error(hipGetErrorString(e_));          \
     } while (0)
+
+// ---------------------------------------------------------------------------
+// small device helpers
+
+__device__ __forceinline__ uint64_t lanes_below() {
+    return (1ull << (threadIdx.x & 63)) - 1ull;
+}
+
+// exclusive scan of one value per thread over a block of 256 threads; the
+// block total in *total.  Contains barriers: every thread of the block must
+// call it.
+__device__ __forceinline__ uint64_t block_scan256(uint64_t v, uint64_t *total) {
+    __shared__ uint64_t wt[4];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint64_t x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wt[w] = x;
+    __syncthreads();
+    uint64_t pre = 0;
+    for (int u = 0; u < w; u++) pre += wt[u];
+    *total = wt[0] + wt[1] + wt[2] + wt[3];
+    __syncthreads();
+    return pre + x - v;
+}
+
+// lanes of the wave whose (valid) digit equals this lane's
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; b++) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t x = __ballot(bit);
+        m &= bit ? x : ~x;
+    }
+    return m;
+}
+
+__global__ void k_set_i32(int32_t *p, int32_t v) { p[0] = v; }
+
+// ---------------------------------------------------------------------------
+// key pass of the full sort and of the removal without sorting
 
 __global__ void k_key64(int nub, const int32_t *__restrict__ nslots, int nr, int nth, double rmin,
                         double dlog, double dth, const double *__restrict__ rn,
@@ -103,10 +165,10 @@ __global__ void k_key32(int nub, const int32_t *__restrict__ nslots, int nth,
 }
 
 // number of live keys = index of the first dead key in the sorted keys
-__global__ void k_count_sorted(int nub, const uint32_t *__restrict__ keys, uint32_t dead,
-                               int32_t *__restrict__ nalive, int32_t *__restrict__ nslots,
-                               int32_t *__restrict__ nsorted) {
-    int lo = 0, hi = nub;
+__global__ void k_count_sorted(const int32_t *__restrict__ n_dev, const uint32_t *__restrict__ keys,
+                               uint32_t dead, int32_t *__restrict__ nalive,
+                               int32_t *__restrict__ nslots, int32_t *__restrict__ nsorted) {
+    int lo = 0, hi = n_dev[0];
     while (lo < hi) {
         int mid = (lo + hi) >> 1;
         if (keys[mid] < dead) lo = mid + 1; else hi = mid;
@@ -149,6 +211,13 @@ __global__ void k_gather_set(int nub, const int32_t *__restrict__ nalive,
     }
 }
 
+__global__ void k_copy_u32(const int32_t *__restrict__ n_dev, const uint32_t *__restrict__ src,
+                           uint32_t *__restrict__ dst) {
+    const int n = n_dev[0];
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x)
+        dst[q] = src[q];
+}
+
 __global__ void k_zero_i32(int32_t *p, int n) {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q < n) p[q] = 0;
@@ -157,6 +226,218 @@ __global__ void k_zero_i32(int32_t *p, int n) {
 void zero_counters(ffpic_ctx *c, int32_t *p, int n) {
     hipLaunchKernelGGL(k_zero_i32, dim3((n + 63) / 64), dim3(64), 0, c->stream, p, n);
 }
+
+// ---------------------------------------------------------------------------
+// exclusive scan of n int32 values (n known on the host), three launches:
+// block sums, a scan of the block sums, the scan of each block
+
+__global__ void __launch_bounds__(256) k_scan_sums(const int32_t *__restrict__ in, int n,
+                                                   int32_t *__restrict__ part) {
+    const int base = blockIdx.x * 1024 + threadIdx.x * 4;
+    int s = 0;
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+        if (base + u < n) s += in[base + u];
+    uint64_t tot;
+    (void)block_scan256((uint64_t)(uint32_t)s, &tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = (int32_t)tot;
+}
+
+__global__ void __launch_bounds__(256) k_scan_part(int32_t *__restrict__ part, int nb) {
+    uint64_t carry = 0;
+    for (int b0 = 0; b0 < nb; b0 += 1024) {
+        const int base = b0 + threadIdx.x * 4;
+        int32_t v[4];
+        uint64_t s = 0;
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            v[u] = base + u < nb ? part[base + u] : 0;
+            s += (uint32_t)v[u];
+        }
+        uint64_t tot;
+        uint64_t ex = block_scan256(s, &tot) + carry;
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            if (base + u < nb) part[base + u] = (int32_t)ex;
+            ex += (uint32_t)v[u];
+        }
+        carry += tot;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_scan_apply(const int32_t *__restrict__ in, int n,
+                                                    const int32_t *__restrict__ part,
+                                                    int32_t *__restrict__ out) {
+    const int base = blockIdx.x * 1024 + threadIdx.x * 4;
+    int32_t v[4];
+    uint64_t s = 0;
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+        v[u] = base + u < n ? in[base + u] : 0;
+        s += (uint32_t)v[u];
+    }
+    uint64_t tot;
+    uint64_t ex = block_scan256(s, &tot) + (uint32_t)part[blockIdx.x];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+        if (base + u < n) out[base + u] = (int32_t)ex;
+        ex += (uint32_t)v[u];
+    }
+}
+
+int64_t scan_part_len(int64_t n) { return (n + 1023) / 1024 + 1; }
+
+void exclusive_scan_i32(ffpic_ctx *c, const int32_t *in, int32_t *out, int64_t n) {
+    if (n <= 0) return;
+    const int nb = (int)((n + 1023) / 1024);
+    if (scan_part_len(n) > c->scan_part_n) throw std::runtime_error("scan scratch too small");
+    hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(256), 0, c->stream, in, (int)n, c->scan_part);
+    hipLaunchKernelGGL(k_scan_part, dim3(1), dim3(256), 0, c->stream, c->scan_part, nb);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(256), 0, c->stream, in, (int)n, c->scan_part,
+                       out);
+    FFPIC_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// LSD radix sort of (key, value) pairs; the count is read on the device
+
+// digit histogram of every tile (tiles strided over the blocks)
+__global__ void __launch_bounds__(256) k_rs_hist(const uint32_t *__restrict__ keys,
+                                                 const int32_t *__restrict__ n_dev, int shift,
+                                                 uint32_t *__restrict__ hist, int stride) {
+    const int n = n_dev[0];
+    const int nt = (n + kRsTile - 1) / kRsTile;
+    __shared__ uint32_t h[256];
+    const uint64_t below = lanes_below();
+    for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+        const int i0 = t * kRsTile;
+        h[threadIdx.x] = 0;
+        __syncthreads();
+        for (int r = 0; r < kRsItems; r++) {
+            const int i = i0 + r * 256 + threadIdx.x;
+            const bool valid = i < n;
+            const uint32_t d = valid ? (keys[i] >> shift) & 255u : 0u;
+            const uint64_t peers = digit_peers(d, valid);
+            if (valid && (peers & below) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+        }
+        __syncthreads();
+        hist[(size_t)threadIdx.x * stride + t] = h[threadIdx.x];
+    }
+}
+
+// exclusive scan over the tiles of one digit (one block per digit), in
+// place; the digit's total in dtot
+__global__ void __launch_bounds__(256) k_rs_scan(uint32_t *__restrict__ hist, int stride,
+                                                 const int32_t *__restrict__ n_dev,
+                                                 uint32_t *__restrict__ dtot) {
+    const int nt = (n_dev[0] + kRsTile - 1) / kRsTile;
+    uint32_t *row = hist + (size_t)blockIdx.x * stride;
+    uint64_t carry = 0;
+    for (int t0 = 0; t0 < nt; t0 += 1024) {
+        const int base = t0 + threadIdx.x * 4;
+        uint32_t v[4];
+        uint64_t s = 0;
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            v[u] = base + u < nt ? row[base + u] : 0u;
+            s += v[u];
+        }
+        uint64_t tot;
+        uint64_t ex = block_scan256(s, &tot) + carry;
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            if (base + u < nt) row[base + u] = (uint32_t)ex;
+            ex += v[u];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) dtot[blockIdx.x] = (uint32_t)carry;
+}
+
+// stable scatter (tiles strided over the blocks): a pair's place is the
+// digit's base over all tiles, plus the earlier tiles' pairs of that digit,
+// plus the pairs of the same digit before it in its tile (rounds of 256 in
+// order; inside a round the earlier waves, then the lower lanes of its own
+// wave)
+__global__ void __launch_bounds__(256) k_rs_scatter(
+    const uint32_t *__restrict__ ik, const uint32_t *__restrict__ iv,
+    uint32_t *__restrict__ ok, uint32_t *__restrict__ ov, const int32_t *__restrict__ n_dev,
+    int shift, const uint32_t *__restrict__ hist, int stride, const uint32_t *__restrict__ dtot) {
+    const int n = n_dev[0];
+    const int nt = (n + kRsTile - 1) / kRsTile;
+    if ((int)blockIdx.x >= nt) return;
+    __shared__ uint32_t base[256], run[256], wc[4][256];
+    const int tid = threadIdx.x, w = tid >> 6;
+    uint64_t tot;
+    const uint32_t dbase = (uint32_t)block_scan256(dtot[tid], &tot);
+    const uint64_t below = lanes_below();
+    for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+        const int i0 = t * kRsTile;
+        base[tid] = dbase + hist[(size_t)tid * stride + t];
+        run[tid] = 0;
+#pragma unroll
+        for (int u = 0; u < 4; u++) wc[u][tid] = 0;
+        uint32_t k[kRsItems], v[kRsItems];
+#pragma unroll
+        for (int r = 0; r < kRsItems; r++) {
+            const int i = i0 + r * 256 + tid;
+            k[r] = i < n ? ik[i] : 0u;
+            v[r] = i < n ? iv[i] : 0u;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kRsItems; r++) {
+            const bool valid = i0 + r * 256 + tid < n;
+            const uint32_t d = (k[r] >> shift) & 255u;
+            const uint64_t peers = digit_peers(d, valid);
+            if (valid && (peers & below) == 0) wc[w][d] = (uint32_t)__popcll(peers);
+            __syncthreads();
+            if (valid) {
+                uint32_t off = run[d] + (uint32_t)__popcll(peers & below);
+                for (int u = 0; u < w; u++) off += wc[u][d];
+                const uint32_t dst = base[d] + off;
+                ok[dst] = k[r];
+                ov[dst] = v[r];
+            }
+            __syncthreads();
+            run[tid] += wc[0][tid] + wc[1][tid] + wc[2][tid] + wc[3][tid];
+#pragma unroll
+            for (int u = 0; u < 4; u++) wc[u][tid] = 0;
+            __syncthreads();
+        }
+    }
+}
+
+struct Pairs {
+    uint32_t *k, *v;
+};
+
+// sorts the n_dev[0] <= nmax pairs of A by the low `bits` bits of the key;
+// B is the second buffer.  Returns the buffer that holds the result.
+static Pairs radix_sort(ffpic_ctx *c, Pairs A, Pairs B, const int32_t *n_dev, int64_t nmax,
+                        int bits) {
+    if (nmax <= 0) return A;
+    const int ntile = (int)((nmax + kRsTile - 1) / kRsTile);
+    if (ntile > c->rs_stride) throw std::runtime_error("radix histogram too small");
+    // the count is known only on the device: a fixed grid strides over the
+    // tiles of the largest count
+    const int nb = std::min(ntile, kRsBlocks);
+    Pairs in = A, out = B;
+    for (int shift = 0; shift < bits; shift += 8) {
+        hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(256), 0, c->stream, in.k, n_dev, shift,
+                           c->rs_hist, c->rs_stride);
+        hipLaunchKernelGGL(k_rs_scan, dim3(256), dim3(256), 0, c->stream, c->rs_hist,
+                           c->rs_stride, n_dev, c->rs_dtot);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(256), 0, c->stream, in.k, in.v, out.k,
+                           out.v, n_dev, shift, c->rs_hist, c->rs_stride, c->rs_dtot);
+        FFPIC_LAUNCH_CHECK();
+        std::swap(in, out);
+    }
+    return in;
+}
+
+// ---------------------------------------------------------------------------
+// geometry of the sort
 
 // first key past every live one (see the header comment)
 static uint32_t dead_key(const ffpic_ctx *c) {
@@ -174,35 +455,21 @@ int sort_key_bits(const ffpic_ctx *c) {
     return bits;
 }
 
-size_t scan_temp_bytes(int64_t nblk) {
-    size_t bytes = 0;
-    if (nblk <= 0) return 0;
-    hipError_t e = rocprim::exclusive_scan((void *)nullptr, bytes, (uint32_t *)nullptr,
-                                           (uint32_t *)nullptr, 0u, (size_t)nblk,
-                                           rocprim::plus<uint32_t>());
-    if (e != hipSuccess) throw std::runtime_error("rocprim scan size query failed");
-    return bytes;
-}
-
-int sort_block_slots() { return kSortBlock; }
-
-// temporary storage for sorting any number of pairs up to cap: rocPRIM
-// switches algorithm with the size (merge sort below about 2^20 items), so
-// the largest requirement over the switch points is taken
-size_t sort_temp_bytes(int64_t cap, int bits) {
-    if (cap <= 0) return 0;
-    size_t most = 0;
-    const int64_t sizes[] = {cap, std::min<int64_t>(cap, (1 << 20) - 1),
-                             std::min<int64_t>(cap, (1 << 20) + 1)};
-    for (int64_t n : sizes) {
-        size_t bytes = 0;
-        hipError_t e = rocprim::radix_sort_pairs((void *)nullptr, bytes, (uint32_t *)nullptr,
-                                                 (uint32_t *)nullptr, (uint32_t *)nullptr,
-                                                 (uint32_t *)nullptr, (unsigned int)n, 0, bits);
-        if (e != hipSuccess) throw std::runtime_error("rocprim temp size query failed");
-        most = std::max(most, bytes);
-    }
-    return most;
+// device scratch of the sort for species of up to cap slots
+void sort_alloc(ffpic_ctx *c, int64_t cap, void *(*dmalloc)(size_t)) {
+    const int64_t nw = (cap + 63) / 64 + 1;
+    const int64_t nt = (cap + kTile - 1) / kTile + 1;
+    const int64_t ng = (nt + kGroup - 1) / kGroup + 1;
+    c->sort_smask = (uint64_t *)dmalloc((size_t)nw * 8);
+    c->sort_mmask = (uint64_t *)dmalloc((size_t)nw * 8);
+    c->sort_wsm = (uint32_t *)dmalloc((size_t)nw * 4);
+    c->sort_tc = (uint2 *)dmalloc((size_t)nt * 8);
+    c->sort_ts = (uint2 *)dmalloc((size_t)nt * 8);
+    c->sort_gs = (uint2 *)dmalloc((size_t)ng * 8);
+    c->rs_stride = (int)std::max<int64_t>(1, (cap + kRsTile - 1) / kRsTile);
+    c->rs_hist = (uint32_t *)dmalloc((size_t)256 * c->rs_stride * 4);
+    c->rs_dtot = (uint32_t *)dmalloc(256 * 4);
+    c->rs_n = (int32_t *)dmalloc(4);
 }
 
 static void key_pass(ffpic_ctx *c, int s, uint32_t dead, bool with_vals = true) {
@@ -242,6 +509,7 @@ __global__ void k_offsets(int nalive_host, const uint32_t *__restrict__ keys, in
     off[k] = lo;
 }
 
+// test hook (outside the step): offsets of the current order, synchronises
 void sort_offsets(ffpic_ctx *c, int s, int32_t *dev_off) {
     // keys of the current order (no removal): all-zero kill flags
     ffpic::Species &S = c->sp[s];
@@ -269,388 +537,6 @@ void sort_offsets(ffpic_ctx *c, int s, int32_t *dev_off) {
     FFPIC_LAUNCH_CHECK();
 }
 
-
-// ---------------------------------------------------------------------------
-// incremental re-sort
-
-
-// stayer / mover class of a slot from its new key and the key it had at the
-// last sort (kold is sorted, so stayers are in order)
-__device__ __forceinline__ int slot_class(uint32_t key, uint32_t dead, int q, int nold,
-                                          const uint32_t *__restrict__ kold) {
-    if (key >= dead) return 0;                          // dropped
-    return (q < nold && kold[q] == key) ? 1 : 2;        // 1 stayer, 2 mover
-}
-
-// key pass fused with the stayer / mover counts of each block of
-// kSortBlock slots (incremental sort); same keys and removals as k_key32 /
-// k_key64
-__device__ __forceinline__ void block_counts(uint32_t st, uint32_t mv, uint32_t *bst,
-                                             uint32_t *bmv) {
-    __shared__ uint32_t part[2][4];
-    const int tid = threadIdx.x, w = tid >> 6;
-    if ((tid & 63) == 0) { part[0][w] = st; part[1][w] = mv; }
-    __syncthreads();
-    if (tid == 0) {
-        bst[blockIdx.x] = part[0][0] + part[0][1] + part[0][2] + part[0][3];
-        bmv[blockIdx.x] = part[1][0] + part[1][1] + part[1][2] + part[1][3];
-    }
-}
-
-// FP32 key pass of the incremental sort: kill, then the class of every slot
-// (0 dropped, 1 stayer, 2 mover) as one byte, with the block counts.  The
-// later passes take the key of a slot from its cell, so no key array is
-// written.  The loads of the block's four slots per thread are issued first.
-__global__ void __launch_bounds__(256) k_keyclass32(int nub, const int32_t *__restrict__ nslots,
-                                                    int nth, const uint8_t *__restrict__ kill,
-                                                    uint32_t dead, int32_t *__restrict__ CELL,
-                                                    uint8_t *__restrict__ cls,
-                                                    unsigned long long *__restrict__ removed,
-                                                    const int32_t *__restrict__ nsorted,
-                                                    const uint32_t *__restrict__ kold,
-                                                    uint32_t *__restrict__ bst,
-                                                    uint32_t *__restrict__ bmv) {
-    constexpr int K = kSortBlock / 256;
-    const int ns = nslots[0], no = nsorted[0];
-    int cell[K];
-    uint32_t ko[K];
-#pragma unroll
-    for (int k = 0; k < K; k++) {
-        const int q = blockIdx.x * kSortBlock + k * 256 + threadIdx.x;
-        cell[k] = q < ns ? CELL[q] : -1;
-        ko[k] = q < no ? kold[q] : dead;
-    }
-    uint32_t st = 0, mv = 0;
-#pragma unroll
-    for (int k = 0; k < K; k++) {
-        const int q = blockIdx.x * kSortBlock + k * 256 + threadIdx.x;
-        const int c = cell[k];
-        bool killed = false;
-        int cl = 0;
-        if (c >= 0) {
-            const int i = c >> 16, j = c & 0xffff;
-            if (kill[(size_t)i * nth + j]) {
-                killed = true;
-                CELL[q] = -1;
-            } else {
-                const uint32_t key = (uint32_t)i * (uint32_t)nth + (uint32_t)j;
-                cl = key >= dead ? 0 : (key == ko[k] ? 1 : 2);
-            }
-        }
-        if (q < nub) cls[q] = (uint8_t)cl;
-        count_wave(&removed[1], killed);
-        st += __popcll(__ballot(cl == 1));
-        mv += __popcll(__ballot(cl == 2));
-    }
-    block_counts(st, mv, bst, bmv);
-}
-
-__global__ void __launch_bounds__(256) k_keyclass64(
-    int nub, const int32_t *__restrict__ nslots, int nr, int nth, double rmin, double dlog,
-    double dth, const double *__restrict__ rn, const double *__restrict__ thn,
-    const uint8_t *__restrict__ kill, uint32_t dead, double *__restrict__ R,
-    const double *__restrict__ TH, uint32_t *__restrict__ keys,
-    unsigned long long *__restrict__ removed, const int32_t *__restrict__ nsorted,
-    const uint32_t *__restrict__ kold, uint32_t *__restrict__ bst, uint32_t *__restrict__ bmv) {
-    const int ns = nslots[0], no = nsorted[0];
-    uint32_t st = 0, mv = 0;
-    for (int k = 0; k < kSortBlock / 256; k++) {
-        const int q = blockIdx.x * kSortBlock + k * 256 + threadIdx.x;
-        uint32_t key = dead;
-        bool killed = false;
-        if (q < ns) {
-            const double r = R[q];
-            if (r > 0.0) {
-                int i, j;
-                double a, b;
-                locate64(nr, nth, rmin, dlog, dth, rn, thn, r, TH[q], i, j, a, b);
-                if (kill[(size_t)i * nth + j]) {
-                    killed = true;
-                    R[q] = -1.0;
-                } else {
-                    key = (uint32_t)i * (uint32_t)nth + (uint32_t)j;
-                }
-            }
-        }
-        if (q < nub) keys[q] = key;
-        count_wave(&removed[1], killed);
-        const int cl = q < nub ? slot_class(key, dead, q, no, kold) : 0;
-        st += __popcll(__ballot(cl == 1));
-        mv += __popcll(__ballot(cl == 2));
-    }
-    block_counts(st, mv, bst, bmv);
-}
-
-// SB[q] for every slot (stayers before q), the movers compacted in slot
-// order, and the totals (SB[nub] = stayers, tot[0] = stayers, tot[1] =
-// movers) from the exclusive block scans
-__global__ void __launch_bounds__(256) k_class_compact(
-    int nub, int nblk, const uint32_t *__restrict__ keys, uint32_t dead,
-    const int32_t *__restrict__ nold, const uint32_t *__restrict__ kold,
-    const uint32_t *__restrict__ bst, const uint32_t *__restrict__ bmv,
-    const uint32_t *__restrict__ cst, const uint32_t *__restrict__ cmv, uint32_t *__restrict__ sb,
-    uint32_t *__restrict__ mkey, uint32_t *__restrict__ mval, uint32_t *__restrict__ tot) {
-    __shared__ uint32_t part[2][4];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int no = nold[0];
-    uint32_t st0 = cst[blockIdx.x], mv0 = cmv[blockIdx.x];
-    const unsigned long long below = (1ull << lane) - 1ull;
-    for (int k = 0; k < kSortBlock / 256; k++) {
-        const int q = blockIdx.x * kSortBlock + k * 256 + tid;
-        const uint32_t key = q < nub ? keys[q] : dead;
-        const int cl = q < nub ? slot_class(key, dead, q, no, kold) : 0;
-        const unsigned long long ms = __ballot(cl == 1), mm = __ballot(cl == 2);
-        if (lane == 0) { part[0][w] = __popcll(ms); part[1][w] = __popcll(mm); }
-        __syncthreads();
-        uint32_t os = st0, om = mv0;
-        for (int u = 0; u < w; u++) { os += part[0][u]; om += part[1][u]; }
-        os += __popcll(ms & below);
-        om += __popcll(mm & below);
-        if (q < nub) sb[q] = os;
-        if (cl == 2) { mkey[om] = key; mval[om] = (uint32_t)q; }
-        st0 += part[0][0] + part[0][1] + part[0][2] + part[0][3];
-        mv0 += part[1][0] + part[1][1] + part[1][2] + part[1][3];
-        __syncthreads();
-    }
-    if (blockIdx.x == nblk - 1 && tid == 0) {
-        sb[nub] = st0;
-        tot[0] = st0;
-        tot[1] = mv0;
-    }
-}
-
-// FP32 variant of the compaction: classes from the byte array, the key of a
-// mover from its cell
-__global__ void __launch_bounds__(256) k_class_compact32(
-    int nub, int nblk, int nth, const uint8_t *__restrict__ cls, const int32_t *__restrict__ CELL,
-    const uint32_t *__restrict__ cst, const uint32_t *__restrict__ cmv, uint32_t *__restrict__ sb,
-    uint32_t *__restrict__ mkey, uint32_t *__restrict__ mval, uint32_t *__restrict__ tot) {
-    constexpr int K = kSortBlock / 256;
-    // per-wave counts, double-buffered: a wave writes buffer k & 1 only after
-    // the barrier of pass k - 1, which every wave passes after its reads of
-    // pass k - 2, so one barrier per pass suffices
-    __shared__ uint32_t part[2][2][4];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    int cl[K], cc[K];
-#pragma unroll
-    for (int k = 0; k < K; k++) {
-        const int q = blockIdx.x * kSortBlock + k * 256 + tid;
-        cl[k] = q < nub ? (int)cls[q] : 0;
-    }
-    // the movers' cells are loaded before the passes, off their barriers
-#pragma unroll
-    for (int k = 0; k < K; k++) {
-        const int q = blockIdx.x * kSortBlock + k * 256 + tid;
-        cc[k] = cl[k] == 2 ? CELL[q] : 0;
-    }
-    uint32_t st0 = cst[blockIdx.x], mv0 = cmv[blockIdx.x];
-    const unsigned long long below = (1ull << lane) - 1ull;
-#pragma unroll
-    for (int k = 0; k < K; k++) {
-        const int q = blockIdx.x * kSortBlock + k * 256 + tid;
-        uint32_t(*pt)[4] = part[k & 1];
-        const unsigned long long ms = __ballot(cl[k] == 1), mm = __ballot(cl[k] == 2);
-        if (lane == 0) { pt[0][w] = __popcll(ms); pt[1][w] = __popcll(mm); }
-        __syncthreads();
-        uint32_t os = st0, om = mv0;
-        for (int u = 0; u < w; u++) { os += pt[0][u]; om += pt[1][u]; }
-        os += __popcll(ms & below);
-        om += __popcll(mm & below);
-        if (q < nub) sb[q] = os;
-        if (cl[k] == 2) {
-            const int c = cc[k];
-            mkey[om] = (uint32_t)(c >> 16) * (uint32_t)nth + (uint32_t)(c & 0xffff);
-            mval[om] = (uint32_t)q;
-        }
-        st0 += pt[0][0] + pt[0][1] + pt[0][2] + pt[0][3];
-        mv0 += pt[1][0] + pt[1][1] + pt[1][2] + pt[1][3];
-    }
-    if (blockIdx.x == nblk - 1 && tid == 0) {
-        sb[nub] = st0;
-        tot[0] = st0;
-        tot[1] = mv0;
-    }
-}
-
-// moff[k] = movers with key < k (binary search in the sorted mover keys)
-__global__ void k_mover_offsets(const uint32_t *__restrict__ tot, const uint32_t *__restrict__ mkey,
-                                int nkeys, int32_t *__restrict__ moff) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k > nkeys) return;
-    int lo = 0, hi = (int)tot[1];
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if ((int)mkey[mid] < k) lo = mid + 1; else hi = mid;
-    }
-    moff[k] = lo;
-}
-
-// mst[k] = moff[k] + (movers of key k from a slot below OFF[k]).  A stayer
-// of key k sits in the old range [OFF[k], OFF[k+1]) of its key, and no mover
-// of key k does (its key changed, or it was appended after the sort), so
-// every stayer of key k has the same movers of its key before it: mst[k].
-__global__ void k_mover_start(int nkeys, const int32_t *__restrict__ moff,
-                              const int32_t *__restrict__ offold,
-                              const uint32_t *__restrict__ mval, int32_t *__restrict__ mst) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k > nkeys) return;
-    int lo = moff[k];
-    if (k < nkeys) {
-        int hi = moff[k + 1];
-        const int q0 = offold[k];
-        while (lo < hi) {                 // movers of this key are in slot order
-            const int mid = (lo + hi) >> 1;
-            if ((int)mval[mid] < q0) lo = mid + 1; else hi = mid;
-        }
-    }
-    mst[k] = lo;
-}
-
-// stayers: slot q with key k goes to SB[q] + mst[k]
-// One kernel places both classes: the first nbm blocks stride over the
-// sorted movers (dispatched first, so their dependent loads overlap the
-// streaming copy), the remaining blocks take one slot per thread (stayers).
-//   stayer: slot q with key k goes to SB[q] + mst[k];
-//   mover:  rank j (key k, slot q) goes to j + SB[clamp(q, OFF[k], OFF[k+1])].
-template <typename T, int NA>
-__global__ void k_scatter(int nub, int nbm, const uint32_t *__restrict__ keys, uint32_t dead,
-                          const int32_t *__restrict__ nold, const uint32_t *__restrict__ kold,
-                          const uint32_t *__restrict__ sb, const int32_t *__restrict__ mst,
-                          const uint32_t *__restrict__ tot, const uint32_t *__restrict__ mkey,
-                          const uint32_t *__restrict__ mval, const int32_t *__restrict__ offold,
-                          uint32_t *__restrict__ knew, PtrSet<T, NA> P) {
-    if ((int)blockIdx.x < nbm) {
-        const int m = (int)tot[1];
-        for (int j = (int)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += nbm * blockDim.x) {
-            const uint32_t key = mkey[j];
-            const int q = (int)mval[j];
-            const int lo = offold[key], hi = offold[key + 1];
-            const int c = q < lo ? lo : (q > hi ? hi : q);
-            const uint32_t d = (uint32_t)j + sb[c];
-#pragma unroll
-            for (int a = 0; a < NA; a++) P.dst[a][d] = P.src[a][q];
-            knew[d] = key;
-        }
-        return;
-    }
-    const int q = ((int)blockIdx.x - nbm) * blockDim.x + threadIdx.x;
-    if (q >= nub) return;
-    // the state is read before the class is known, so its loads overlap the
-    // key and offset loads (dead slots are read and dropped)
-    T v[NA];
-#pragma unroll
-    for (int a = 0; a < NA; a++) v[a] = P.src[a][q];
-    const uint32_t key = keys[q];
-    if (slot_class(key, dead, q, nold[0], kold) != 1) return;
-    const uint32_t d = sb[q] + (uint32_t)mst[key];
-#pragma unroll
-    for (int a = 0; a < NA; a++) P.dst[a][d] = v[a];
-    knew[d] = key;
-}
-
-// FP32 variant of the scatter: a stayer's class from the byte array and its
-// key from its cell (the first state array)
-__global__ void k_scatter32(int nub, int nbm, int nth, const uint8_t *__restrict__ cls,
-                            const uint32_t *__restrict__ sb, const int32_t *__restrict__ mst,
-                            const uint32_t *__restrict__ tot, const uint32_t *__restrict__ mkey,
-                            const uint32_t *__restrict__ mval, const int32_t *__restrict__ offold,
-                            uint32_t *__restrict__ knew, PtrSet<uint32_t, 6> P) {
-    if ((int)blockIdx.x < nbm) {
-        const int m = (int)tot[1];
-        for (int j = (int)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += nbm * blockDim.x) {
-            const uint32_t key = mkey[j];
-            const int q = (int)mval[j];
-            const int lo = offold[key], hi = offold[key + 1];
-            const int c = q < lo ? lo : (q > hi ? hi : q);
-            const uint32_t d = (uint32_t)j + sb[c];
-#pragma unroll
-            for (int a = 0; a < 6; a++) P.dst[a][d] = P.src[a][q];
-            knew[d] = key;
-        }
-        return;
-    }
-    const int q = ((int)blockIdx.x - nbm) * blockDim.x + threadIdx.x;
-    if (q >= nub) return;
-    uint32_t v[6];
-#pragma unroll
-    for (int a = 0; a < 6; a++) v[a] = P.src[a][q];
-    if (cls[q] != 1) return;
-    const int cell = (int)v[0];
-    const uint32_t key = (uint32_t)(cell >> 16) * (uint32_t)nth + (uint32_t)(cell & 0xffff);
-    const uint32_t d = sb[q] + (uint32_t)mst[key];
-#pragma unroll
-    for (int a = 0; a < 6; a++) P.dst[a][d] = v[a];
-    knew[d] = key;
-}
-
-// The same placement in two passes, for sorts whose non-stayers fit the
-// compact buffer.  The stayer pass reads every slot once (coalesced), places
-// the stayers, and copies the state of each mover to the buffer at q - SB[q]
-// (the non-stayers before q), so the movers' writes there are coalesced too.
-// The mover pass then reads the movers' state from that dense buffer instead
-// of from their scattered old slots.
-__global__ void k_scatter32_stay(int nub, int nth, const uint8_t *__restrict__ cls,
-                                 const uint32_t *__restrict__ sb, const int32_t *__restrict__ mst,
-                                 uint32_t *__restrict__ knew, PtrSet<uint32_t, 6> P,
-                                 uint32_t *__restrict__ cbuf, int64_t cn) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nub) return;
-    uint32_t v[6];
-#pragma unroll
-    for (int a = 0; a < 6; a++) v[a] = P.src[a][q];
-    const int cl = cls[q];
-    if (cl == 1) {
-        const int cell = (int)v[0];
-        const uint32_t key = (uint32_t)(cell >> 16) * (uint32_t)nth + (uint32_t)(cell & 0xffff);
-        const uint32_t d = sb[q] + (uint32_t)mst[key];
-#pragma unroll
-        for (int a = 0; a < 6; a++) P.dst[a][d] = v[a];
-        knew[d] = key;
-    } else if (cl == 2) {
-        const size_t t = (size_t)((uint32_t)q - sb[q]);
-#pragma unroll
-        for (int a = 0; a < 6; a++) cbuf[(size_t)a * (size_t)cn + t] = v[a];
-    }
-}
-
-__global__ void k_scatter32_move(int nbm, const uint32_t *__restrict__ tot,
-                                 const uint32_t *__restrict__ mkey,
-                                 const uint32_t *__restrict__ mval,
-                                 const int32_t *__restrict__ offold,
-                                 const uint32_t *__restrict__ sb, uint32_t *__restrict__ knew,
-                                 PtrSet<uint32_t, 6> P, const uint32_t *__restrict__ cbuf,
-                                 int64_t cn) {
-    const int m = (int)tot[1];
-    for (int j = (int)blockIdx.x * blockDim.x + threadIdx.x; j < m; j += nbm * blockDim.x) {
-        const uint32_t key = mkey[j];
-        const int q = (int)mval[j];
-        const int lo = offold[key], hi = offold[key + 1];
-        const int c = q < lo ? lo : (q > hi ? hi : q);
-        const uint32_t d = (uint32_t)j + sb[c];
-        const size_t t = (size_t)((uint32_t)q - sb[q]);
-#pragma unroll
-        for (int a = 0; a < 6; a++) P.dst[a][d] = cbuf[(size_t)a * (size_t)cn + t];
-        knew[d] = key;
-    }
-}
-
-// offsets of the new order: stayers with key < k (= SB at the old offset)
-// plus movers with key < k; the last entry is the live count
-__global__ void k_new_offsets(int nkeys, const int32_t *__restrict__ offold,
-                              const uint32_t *__restrict__ sb, const int32_t *__restrict__ moff,
-                              int32_t *__restrict__ offnew, int32_t *__restrict__ nalive,
-                              int32_t *__restrict__ nslots, int32_t *__restrict__ nsorted) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k > nkeys) return;
-    const int v = (int)sb[offold[k]] + moff[k];
-    offnew[k] = v;
-    if (k == nkeys) {
-        nalive[0] = v;
-        nslots[0] = v;
-        nsorted[0] = v;
-    }
-}
-
 // offsets of a sorted key array (after a full sort): off[k] = first slot
 // with key >= k among the live ones
 __global__ void k_offsets_dev(const int32_t *__restrict__ nalive, const uint32_t *__restrict__ keys,
@@ -665,6 +551,342 @@ __global__ void k_offsets_dev(const int32_t *__restrict__ nalive, const uint32_t
     off[k] = lo;
 }
 
+// ---------------------------------------------------------------------------
+// incremental re-sort
+
+// where the classify pass leaves its counts
+struct ClassView {
+    int nub;
+    const uint64_t *smask, *mmask;   // stayer / mover bit per slot
+    const uint32_t *wsm;             // stayers | movers << 16 before the word, in its tile
+    const uint2 *ts;                 // stayers / movers before the tile, in its group
+    const uint2 *gs;                 // stayers / movers before the group
+    const uint32_t *tot;             // stayers, movers
+};
+
+// stayers before slot x (0 <= x <= nub)
+__device__ __forceinline__ uint32_t stayers_before(const ClassView &V, int x) {
+    if (x >= V.nub) return V.tot[0];
+    const int wd = x >> 6;
+    const uint64_t below = (1ull << (x & 63)) - 1ull;
+    return V.gs[x >> 20].x + V.ts[x >> 10].x + (V.wsm[wd] & 0xffffu) +
+           (uint32_t)__popcll(V.smask[wd] & below);
+}
+
+// movers before slot x (0 <= x < nub)
+__device__ __forceinline__ uint32_t movers_before(const ClassView &V, int x) {
+    const int wd = x >> 6;
+    const uint64_t below = (1ull << (x & 63)) - 1ull;
+    return V.gs[x >> 20].y + V.ts[x >> 10].y + (V.wsm[wd] >> 16) +
+           (uint32_t)__popcll(V.mmask[wd] & below);
+}
+
+struct ClassArgs {
+    int nub, nth, nr;
+    uint32_t dead;
+    const int32_t *nslots, *nsorted;
+    const uint8_t *kill;
+    const uint32_t *kold;                       // sorted keys of the last sort
+    unsigned long long *removed;
+    // FP32 state: the cell; FP64 state: r, theta and the geometry
+    int32_t *cell;
+    double *R;
+    const double *TH, *rn, *thn;
+    double rmin, dlog, dth;
+    uint32_t *keys;                             // FP64: key of every slot (out)
+    uint64_t *smask, *mmask;
+    uint32_t *wsm;
+    uint2 *tc;                                  // stayers, movers of each tile
+    uint32_t *tkey, *tval;                      // movers of each tile, compacted in it
+};
+
+// key of every slot, the removal of killed particles, the class bits and
+// counts, and the movers of the tile compacted in slot order
+template <bool FP64>
+__global__ void __launch_bounds__(256) k_classify(ClassArgs A) {
+    constexpr int K = kTile / 256;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int base = blockIdx.x * kTile;
+    const int ns = A.nslots[0], no = A.nsorted[0];
+    uint32_t key[K];
+    int cl[K];
+    if (!FP64) {
+        int cell[K];
+        uint32_t ko[K];
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            const int q = base + k * 256 + tid;
+            cell[k] = q < ns ? A.cell[q] : -1;
+            ko[k] = q < no ? A.kold[q] : A.dead;
+        }
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            const int q = base + k * 256 + tid;
+            bool killed = false;
+            key[k] = A.dead;
+            cl[k] = 0;
+            const int c = cell[k];
+            if (c >= 0) {
+                const int i = c >> 16, j = c & 0xffff;
+                if (A.kill[(size_t)i * A.nth + j]) {
+                    killed = true;
+                    A.cell[q] = -1;
+                } else {
+                    key[k] = (uint32_t)i * (uint32_t)A.nth + (uint32_t)j;
+                    cl[k] = key[k] >= A.dead ? 0 : (key[k] == ko[k] ? 1 : 2);
+                }
+            }
+            count_wave(&A.removed[1], killed);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            const int q = base + k * 256 + tid;
+            bool killed = false;
+            key[k] = A.dead;
+            cl[k] = 0;
+            if (q < ns) {
+                const double r = A.R[q];
+                if (r > 0.0) {
+                    int i, j;
+                    double a, b;
+                    locate64(A.nr, A.nth, A.rmin, A.dlog, A.dth, A.rn, A.thn, r, A.TH[q], i, j,
+                             a, b);
+                    if (A.kill[(size_t)i * A.nth + j]) {
+                        killed = true;
+                        A.R[q] = -1.0;
+                    } else {
+                        key[k] = (uint32_t)i * (uint32_t)A.nth + (uint32_t)j;
+                    }
+                }
+            }
+            if (q < A.nub) A.keys[q] = key[k];
+            if (key[k] < A.dead) cl[k] = (q < no && A.kold[q] == key[k]) ? 1 : 2;
+            count_wave(&A.removed[1], killed);
+        }
+    }
+    __shared__ uint32_t wcnt[2][kTileWords];
+    uint64_t mm[K];
+    const int nwu = (A.nub + 63) >> 6;
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        const uint64_t sm = __ballot(cl[k] == 1);
+        mm[k] = __ballot(cl[k] == 2);
+        const int word = k * 4 + w;
+        const int gw = (base >> 6) + word;
+        if (lane == 0) {
+            wcnt[0][word] = (uint32_t)__popcll(sm);
+            wcnt[1][word] = (uint32_t)__popcll(mm[k]);
+            if (gw < nwu) {
+                A.smask[gw] = sm;
+                A.mmask[gw] = mm[k];
+            }
+        }
+    }
+    __syncthreads();
+    const uint64_t below = lanes_below();
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        const int word = k * 4 + w;
+        const int gw = (base >> 6) + word;
+        uint32_t ps = 0, pm = 0;
+        for (int u = 0; u < word; u++) {
+            ps += wcnt[0][u];
+            pm += wcnt[1][u];
+        }
+        if (lane == 0 && gw < nwu) A.wsm[gw] = ps | (pm << 16);
+        if (cl[k] == 2) {
+            const int r = (int)pm + (int)__popcll(mm[k] & below);
+            A.tkey[base + r] = key[k];
+            A.tval[base + r] = (uint32_t)(base + k * 256 + tid);
+        }
+    }
+    if (tid == 0) {
+        uint32_t ts = 0, tm = 0;
+        for (int u = 0; u < kTileWords; u++) {
+            ts += wcnt[0][u];
+            tm += wcnt[1][u];
+        }
+        A.tc[blockIdx.x] = make_uint2(ts, tm);
+    }
+}
+
+// exclusive scan of the tile counts inside each group of kGroup tiles; the
+// group totals go to gs (scanned by k_group_scan)
+__global__ void __launch_bounds__(256) k_tile_scan(const uint2 *__restrict__ tc, int ntile,
+                                                   uint2 *__restrict__ ts, uint2 *__restrict__ gs) {
+    const int t0 = blockIdx.x * kGroup + threadIdx.x * 4;
+    uint2 v[4];
+    uint64_t s = 0;
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+        v[u] = t0 + u < ntile ? tc[t0 + u] : make_uint2(0u, 0u);
+        s += (uint64_t)v[u].x | ((uint64_t)v[u].y << 32);
+    }
+    uint64_t tot;
+    uint64_t ex = block_scan256(s, &tot);
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+        if (t0 + u < ntile) ts[t0 + u] = make_uint2((uint32_t)ex, (uint32_t)(ex >> 32));
+        ex += (uint64_t)v[u].x | ((uint64_t)v[u].y << 32);
+    }
+    if (threadIdx.x == 0) gs[blockIdx.x] = make_uint2((uint32_t)tot, (uint32_t)(tot >> 32));
+}
+
+// exclusive scan of the group totals (at most 1024 groups), and the totals
+__global__ void __launch_bounds__(256) k_group_scan(uint2 *__restrict__ gs, int ngroup,
+                                                    uint32_t *__restrict__ tot) {
+    const int g0 = threadIdx.x * 4;
+    uint2 v[4];
+    uint64_t s = 0;
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+        v[u] = g0 + u < ngroup ? gs[g0 + u] : make_uint2(0u, 0u);
+        s += (uint64_t)v[u].x | ((uint64_t)v[u].y << 32);
+    }
+    uint64_t all;
+    uint64_t ex = block_scan256(s, &all);
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+        if (g0 + u < ngroup) gs[g0 + u] = make_uint2((uint32_t)ex, (uint32_t)(ex >> 32));
+        ex += (uint64_t)v[u].x | ((uint64_t)v[u].y << 32);
+    }
+    if (threadIdx.x == 0) {
+        tot[0] = (uint32_t)all;
+        tot[1] = (uint32_t)(all >> 32);
+    }
+}
+
+// the movers of every tile into one array, in slot order (one wave a tile)
+__global__ void __launch_bounds__(256) k_movers_dense(int ntile, const uint2 *__restrict__ tc,
+                                                      const uint2 *__restrict__ ts,
+                                                      const uint2 *__restrict__ gs,
+                                                      const uint32_t *__restrict__ tkey,
+                                                      const uint32_t *__restrict__ tval,
+                                                      uint32_t *__restrict__ mk,
+                                                      uint32_t *__restrict__ mv) {
+    const int t = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (t >= ntile) return;
+    const int cnt = (int)tc[t].y;
+    const uint32_t b = gs[t / kGroup].y + ts[t].y;
+    for (int i = lane; i < cnt; i += 64) {
+        mk[b + i] = tkey[(size_t)t * kTile + i];
+        mv[b + i] = tval[(size_t)t * kTile + i];
+    }
+}
+
+// first index in [lo, hi) whose value is >= x
+__device__ __forceinline__ int lower_bound_u32(const uint32_t *a, int lo, int hi, uint32_t x) {
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// per key k (a chunk of consecutive keys per thread): mst[k] = movers with
+// key < k plus movers of key k from a slot below OFF[k]; the new offsets
+// SB(OFF[k]) + (movers with key < k); the new live count
+__global__ void __launch_bounds__(256) k_key_offsets(
+    int nkeys, ClassView V, const uint32_t *__restrict__ mk, const uint32_t *__restrict__ mv,
+    const int32_t *__restrict__ offold, int32_t *__restrict__ mst, int32_t *__restrict__ offnew,
+    int32_t *__restrict__ nalive, int32_t *__restrict__ nslots, int32_t *__restrict__ nsorted) {
+    const int k0 = (blockIdx.x * blockDim.x + threadIdx.x) * kKeyChunk;
+    if (k0 > nkeys) return;
+    const int m = (int)V.tot[1];
+    int p = lower_bound_u32(mk, 0, m, (uint32_t)k0);        // movers with key < k0
+    const int kend = min(k0 + kKeyChunk, nkeys + 1);
+    for (int k = k0; k < kend; k++) {
+        const int x = offold[k];
+        const int v = (int)stayers_before(V, x) + p;
+        offnew[k] = v;
+        if (k == nkeys) {
+            nalive[0] = v;
+            nslots[0] = v;
+            nsorted[0] = v;
+            break;
+        }
+        // movers of key k: [p, hi), found by galloping from p
+        int hi = p;
+        if (hi < m && mk[hi] == (uint32_t)k) {
+            int step = 1;
+            while (p + step < m && mk[p + step] == (uint32_t)k) step <<= 1;
+            hi = lower_bound_u32(mk, p + (step >> 1), min(p + step, m), (uint32_t)k + 1u);
+        }
+        mst[k] = lower_bound_u32(mv, p, hi, (uint32_t)x);   // they are in slot order
+        p = hi;
+    }
+}
+
+// stayers to their places; movers' state to the compact buffer
+template <typename T, int NA, bool FP64>
+__global__ void __launch_bounds__(256) k_place_stayers(
+    ClassView V, int nth, const uint32_t *__restrict__ keys, const int32_t *__restrict__ mst,
+    uint32_t *__restrict__ knew, int32_t *__restrict__ perm, PtrSet<T, NA> P,
+    T *__restrict__ cbuf, int64_t cn) {
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= V.nub) return;
+    // slots past the live ones, dead slots and killed particles have
+    // neither bit
+    const int wd = q >> 6;
+    const uint64_t bit = 1ull << (q & 63);
+    const uint64_t sm = V.smask[wd], mm = V.mmask[wd];
+    if (((sm | mm) & bit) == 0) return;
+    T v[NA];
+#pragma unroll
+    for (int a = 0; a < NA; a++) v[a] = P.src[a][q];
+    if (sm & bit) {
+        uint32_t key;
+        if (FP64) {
+            key = keys[q];
+        } else {
+            const int cell = (int)v[0];
+            key = (uint32_t)(cell >> 16) * (uint32_t)nth + (uint32_t)(cell & 0xffff);
+        }
+        const uint32_t d = stayers_before(V, q) + (uint32_t)mst[key];
+#pragma unroll
+        for (int a = 0; a < NA; a++) P.dst[a][d] = v[a];
+        knew[d] = key;
+        if (perm) perm[d] = q;
+    } else {
+        const int64_t im = movers_before(V, q);
+        if (im < cn) {
+#pragma unroll
+            for (int a = 0; a < NA; a++) cbuf[(size_t)a * (size_t)cn + (size_t)im] = v[a];
+        }
+    }
+}
+
+// movers in their sorted order: rank j (key k, slot q) goes to
+// j + SB(clamp(q, OFF[k], OFF[k+1]))
+template <typename T, int NA>
+__global__ void __launch_bounds__(256) k_place_movers(
+    ClassView V, const uint32_t *__restrict__ mk, const uint32_t *__restrict__ mv,
+    const int32_t *__restrict__ offold, uint32_t *__restrict__ knew, int32_t *__restrict__ perm,
+    PtrSet<T, NA> P, const T *__restrict__ cbuf, int64_t cn) {
+    const int m = (int)V.tot[1];
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < m; j += gridDim.x * blockDim.x) {
+        const uint32_t key = mk[j];
+        const int q = (int)mv[j];
+        const int lo = offold[key], hi = offold[key + 1];
+        const int cq = q < lo ? lo : (q > hi ? hi : q);
+        const uint32_t d = (uint32_t)j + stayers_before(V, cq);
+        const int64_t im = movers_before(V, q);
+        T v[NA];
+        if (im < cn) {
+#pragma unroll
+            for (int a = 0; a < NA; a++) v[a] = cbuf[(size_t)a * (size_t)cn + (size_t)im];
+        } else {
+#pragma unroll
+            for (int a = 0; a < NA; a++) v[a] = P.src[a][q];
+        }
+#pragma unroll
+        for (int a = 0; a < NA; a++) P.dst[a][d] = v[a];
+        knew[d] = key;
+        if (perm) perm[d] = q;
+    }
+}
+
 template <typename T, int NA>
 static PtrSet<T, NA> state_ptrs(ffpic::Species &S) {
     PtrSet<T, NA> P;
@@ -675,35 +897,40 @@ static PtrSet<T, NA> state_ptrs(ffpic::Species &S) {
     return P;
 }
 
+static int32_t *perm_out(ffpic_ctx *c, int s) {
+    c->perm_valid[s] = c->record_perm && c->perm[s];
+    return c->perm_valid[s] ? c->perm[s] : nullptr;
+}
+
 // full sort: key pass, radix sort of all (key, slot) pairs, gather; then the
 // sorted keys and cell offsets are kept for the next (incremental) sort
 static void sort_full(ffpic_ctx *c, int s) {
     ffpic::Species &S = c->sp[s];
-    int nub = (int)S.nub;
-    uint32_t dead = dead_key(c);
+    const int nub = (int)S.nub;
+    const uint32_t dead = dead_key(c);
     key_pass(c, s, dead);
-    size_t bytes = c->sort_tmp_bytes;
-    hipError_t e = rocprim::radix_sort_pairs(c->sort_tmp, bytes, c->keys[0], c->keys[1],
-                                             c->vals[0], c->vals[1], (unsigned int)nub, 0,
-                                             sort_key_bits(c), c->stream);
-    if (e != hipSuccess) throw std::runtime_error("rocprim radix sort failed");
+    hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, c->stream, c->rs_n, nub);
+    const Pairs R = radix_sort(c, Pairs{c->keys[0], c->vals[0]}, Pairs{c->keys[1], c->vals[1]},
+                               c->rs_n, nub, sort_key_bits(c));
     int32_t *nal = c->nalive + s;
-    hipLaunchKernelGGL(k_count_sorted, dim3(1), dim3(1), 0, c->stream, nub, c->keys[1], dead, nal,
+    hipLaunchKernelGGL(k_count_sorted, dim3(1), dim3(1), 0, c->stream, c->rs_n, R.k, dead, nal,
                        c->nslots + s, c->nsorted + s);
-    int nb = std::min((nub + 255) / 256, 65536);
+    const int nb = std::max(1, std::min((nub + 255) / 256, 65536));
     if (c->fp64) {
         hipLaunchKernelGGL((k_gather_set<uint64_t, 5>), dim3(nb), dim3(256), 0, c->stream, nub,
-                           nal, c->vals[1], (state_ptrs<uint64_t, 5>(S)));
+                           nal, R.v, (state_ptrs<uint64_t, 5>(S)));
     } else {
         hipLaunchKernelGGL((k_gather_set<uint32_t, 6>), dim3(nb), dim3(256), 0, c->stream, nub,
-                           nal, c->vals[1], (state_ptrs<uint32_t, 6>(S)));
+                           nal, R.v, (state_ptrs<uint32_t, 6>(S)));
     }
     FFPIC_LAUNCH_CHECK();
     for (int a = 0; a < S.narr; a++) std::swap(S.cur[a], S.alt[a]);
     // the sorted keys and their cell offsets, for the next sort
     const int t = c->sort_cur[s];
-    HCHK_SORT(hipMemcpyAsync(c->skey[s][t], c->keys[1], (size_t)nub * 4, hipMemcpyDeviceToDevice,
-                             c->stream));
+    hipLaunchKernelGGL(k_copy_u32, dim3(nb), dim3(256), 0, c->stream, nal, R.k, c->skey[s][t]);
+    if (int32_t *perm = perm_out(c, s))
+        hipLaunchKernelGGL(k_copy_u32, dim3(nb), dim3(256), 0, c->stream, nal, R.v,
+                           (uint32_t *)perm);
     const int nkeys = c->nr * c->nth;
     hipLaunchKernelGGL(k_offsets_dev, dim3((nkeys + 1 + 255) / 256), dim3(256), 0, c->stream, nal,
                        c->skey[s][t], nkeys, c->soff[s][t]);
@@ -719,79 +946,86 @@ static void sort_incremental(ffpic_ctx *c, int s) {
     const uint32_t dead = dead_key(c);
     const int nkeys = c->nr * c->nth;
     const int t = c->sort_cur[s];
-    const uint32_t *kold = c->skey[s][t];
-    const int32_t *offold = c->soff[s][t];
-    const int32_t *nold = c->nsorted + s;  // live count of the last sort
-    const int nblk = (nub + kSortBlock - 1) / kSortBlock;
-    uint32_t *bst = c->sort_blk, *bmv = bst + nblk, *cst = bmv + nblk, *cmv = cst + nblk;
+    const int ntile = (nub + kTile - 1) / kTile;
+    const int ngroup = (ntile + kGroup - 1) / kGroup;
+    if (ngroup > 1024) throw std::runtime_error("more slots than the sort handles");
+
+    ClassArgs A{};
+    A.nub = nub;
+    A.nth = c->nth;
+    A.nr = c->nr;
+    A.dead = dead;
+    A.nslots = c->nslots + s;
+    A.nsorted = c->nsorted + s;
+    A.kill = c->kill;
+    A.kold = c->skey[s][t];
+    A.removed = c->removed + 4 * s;
+    A.smask = c->sort_smask;
+    A.mmask = c->sort_mmask;
+    A.wsm = c->sort_wsm;
+    A.tc = c->sort_tc;
+    // the movers of each tile go to the second radix buffer, which is free
+    // until the movers have been made dense
+    A.tkey = c->keys[1];
+    A.tval = c->vals[0];
     if (c->fp64) {
-        hipLaunchKernelGGL(k_keyclass64, dim3(nblk), dim3(256), 0, c->stream, nub, c->nslots + s,
-                           c->nr, c->nth, c->d.rmin, c->dlog, c->dth, c->dtab64[T_RN],
-                           c->dtab64[T_THN], c->kill, dead, (double *)S.cur[0],
-                           (const double *)S.cur[1], c->keys[0], c->removed + 4 * s, nold, kold,
-                           bst, bmv);
+        A.R = (double *)S.cur[0];
+        A.TH = (const double *)S.cur[1];
+        A.rn = c->dtab64[T_RN];
+        A.thn = c->dtab64[T_THN];
+        A.rmin = c->d.rmin;
+        A.dlog = c->dlog;
+        A.dth = c->dth;
+        A.keys = c->keys[0];
+        hipLaunchKernelGGL(k_classify<true>, dim3(ntile), dim3(256), 0, c->stream, A);
     } else {
-        hipLaunchKernelGGL(k_keyclass32, dim3(nblk), dim3(256), 0, c->stream, nub, c->nslots + s,
-                           c->nth, c->kill, dead, (int32_t *)S.cur[0], c->sort_cls,
-                           c->removed + 4 * s, nold, kold, bst, bmv);
+        A.cell = (int32_t *)S.cur[0];
+        hipLaunchKernelGGL(k_classify<false>, dim3(ntile), dim3(256), 0, c->stream, A);
     }
+    hipLaunchKernelGGL(k_tile_scan, dim3(ngroup), dim3(256), 0, c->stream, c->sort_tc, ntile,
+                       c->sort_ts, c->sort_gs);
+    hipLaunchKernelGGL(k_group_scan, dim3(1), dim3(256), 0, c->stream, c->sort_gs, ngroup,
+                       c->sort_tot);
     FFPIC_LAUNCH_CHECK();
-    size_t bytes = c->scan_tmp_bytes;
-    if (rocprim::exclusive_scan(c->scan_tmp, bytes, bst, cst, 0u, (size_t)nblk,
-                                rocprim::plus<uint32_t>(), c->stream) != hipSuccess ||
-        rocprim::exclusive_scan(c->scan_tmp, bytes, bmv, cmv, 0u, (size_t)nblk,
-                                rocprim::plus<uint32_t>(), c->stream) != hipSuccess)
-        throw std::runtime_error("rocprim scan failed");
-    uint32_t *mkey = c->keys[1], *mval = c->vals[0];
-    if (c->fp64)
-        hipLaunchKernelGGL(k_class_compact, dim3(nblk), dim3(256), 0, c->stream, nub, nblk,
-                           c->keys[0], dead, nold, kold, bst, bmv, cst, cmv, c->sort_sb, mkey, mval,
-                           c->sort_tot);
-    else
-        hipLaunchKernelGGL(k_class_compact32, dim3(nblk), dim3(256), 0, c->stream, nub, nblk,
-                           c->nth, c->sort_cls, (const int32_t *)S.cur[0], cst, cmv, c->sort_sb,
-                           mkey, mval, c->sort_tot);
+    const Pairs dense{c->vals[1], c->sort_aux}, spare{c->keys[1], c->vals[0]};
+    hipLaunchKernelGGL(k_movers_dense, dim3((ntile + 3) / 4), dim3(256), 0, c->stream, ntile,
+                       c->sort_tc, c->sort_ts, c->sort_gs, A.tkey, A.tval, dense.k, dense.v);
     FFPIC_LAUNCH_CHECK();
-    uint32_t tot[2] = {0, 0};
-    HCHK_SORT(hipMemcpyAsync(tot, c->sort_tot, sizeof(tot), hipMemcpyDeviceToHost, c->stream));
-    HCHK_SORT(hipStreamSynchronize(c->stream));
-    const uint32_t m = tot[1];
-    uint32_t *mkey2 = c->vals[1], *mval2 = c->sort_aux;
-    if (m > 0) {
-        size_t sbytes = c->sort_tmp_bytes;
-        if (rocprim::radix_sort_pairs(c->sort_tmp, sbytes, mkey, mkey2, mval, mval2, m, 0,
-                                      sort_key_bits(c), c->stream) != hipSuccess)
-            throw std::runtime_error("rocprim radix sort failed");
-    }
-    hipLaunchKernelGGL(k_mover_offsets, dim3((nkeys + 1 + 255) / 256), dim3(256), 0, c->stream,
-                       c->sort_tot, mkey2, nkeys, c->sort_moff);
-    hipLaunchKernelGGL(k_mover_start, dim3((nkeys + 1 + 255) / 256), dim3(256), 0, c->stream,
-                       nkeys, c->sort_moff, offold, mval2, c->sort_mst);
+    // the mover count is tot[1], on the device
+    const int32_t *m_dev = (const int32_t *)(c->sort_tot + 1);
+    const Pairs M = radix_sort(c, dense, spare, m_dev, nub, sort_key_bits(c));
+
+    ClassView V{nub, c->sort_smask, c->sort_mmask, c->sort_wsm, c->sort_ts, c->sort_gs,
+                c->sort_tot};
+    const int32_t *offold = c->soff[s][t];
     uint32_t *knew = c->skey[s][1 - t];
     int32_t *offnew = c->soff[s][1 - t];
+    const int nkt = (nkeys + 1 + kKeyChunk - 1) / kKeyChunk;
+    // reads the old live count (through OFF) before replacing it
+    hipLaunchKernelGGL(k_key_offsets, dim3((nkt + 255) / 256), dim3(256), 0, c->stream, nkeys, V,
+                       M.k, M.v, offold, c->sort_mst, offnew, c->nalive + s, c->nslots + s,
+                       c->nsorted + s);
+    FFPIC_LAUNCH_CHECK();
+    int32_t *perm = perm_out(c, s);
     const int nbs = (nub + 255) / 256;
-    const int nbm = std::max(1, std::min((int)((m + 255) / 256), 4096));
+    const int nbm = std::max(1, std::min(nbs, kMoverBlocks));
     if (c->fp64) {
-        hipLaunchKernelGGL((k_scatter<uint64_t, 5>), dim3(nbs + nbm), dim3(256), 0, c->stream,
-                           nub, nbm, c->keys[0], dead, nold, kold, c->sort_sb, c->sort_mst,
-                           c->sort_tot, mkey2, mval2, offold, knew, (state_ptrs<uint64_t, 5>(S)));
-    } else if (c->sort_cbuf && (int64_t)nub - (int64_t)tot[0] <= c->sort_cbuf_n) {
-        const auto P = state_ptrs<uint32_t, 6>(S);
-        hipLaunchKernelGGL(k_scatter32_stay, dim3(nbs), dim3(256), 0, c->stream, nub, c->nth,
-                           c->sort_cls, c->sort_sb, c->sort_mst, knew, P, c->sort_cbuf,
-                           c->sort_cbuf_n);
-        hipLaunchKernelGGL(k_scatter32_move, dim3(nbm), dim3(256), 0, c->stream, nbm, c->sort_tot,
-                           mkey2, mval2, offold, c->sort_sb, knew, P, c->sort_cbuf,
+        auto P = state_ptrs<uint64_t, 5>(S);
+        hipLaunchKernelGGL((k_place_stayers<uint64_t, 5, true>), dim3(nbs), dim3(256), 0,
+                           c->stream, V, c->nth, c->keys[0], c->sort_mst, knew, perm,
+                           P, (uint64_t *)c->sort_cbuf, c->sort_cbuf_n);
+        hipLaunchKernelGGL((k_place_movers<uint64_t, 5>), dim3(nbm), dim3(256), 0, c->stream, V,
+                           M.k, M.v, offold, knew, perm, P, (const uint64_t *)c->sort_cbuf,
                            c->sort_cbuf_n);
     } else {
-        hipLaunchKernelGGL(k_scatter32, dim3(nbs + nbm), dim3(256), 0, c->stream, nub, nbm,
-                           c->nth, c->sort_cls, c->sort_sb, c->sort_mst, c->sort_tot, mkey2,
-                           mval2, offold, knew, (state_ptrs<uint32_t, 6>(S)));
+        auto P = state_ptrs<uint32_t, 6>(S);
+        hipLaunchKernelGGL((k_place_stayers<uint32_t, 6, false>), dim3(nbs), dim3(256), 0,
+                           c->stream, V, c->nth, nullptr, c->sort_mst, knew, perm, P,
+                           (uint32_t *)c->sort_cbuf, c->sort_cbuf_n);
+        hipLaunchKernelGGL((k_place_movers<uint32_t, 6>), dim3(nbm), dim3(256), 0, c->stream, V,
+                           M.k, M.v, offold, knew, perm, P, (const uint32_t *)c->sort_cbuf,
+                           c->sort_cbuf_n);
     }
-    // reads the old live count before replacing it with the new one
-    hipLaunchKernelGGL(k_new_offsets, dim3((nkeys + 1 + 255) / 256), dim3(256), 0, c->stream,
-                       nkeys, offold, c->sort_sb, c->sort_moff, offnew, c->nalive + s,
-                       c->nslots + s, c->nsorted + s);
     FFPIC_LAUNCH_CHECK();
     for (int a = 0; a < S.narr; a++) std::swap(S.cur[a], S.alt[a]);
     c->sort_cur[s] = 1 - t;

@@ -398,13 +398,14 @@ void free_all(ffpic_ctx *c) {
     for (int k = 0; k < 2; k++) { F(c->keys[k]); F(c->vals[k]); }
     for (int s = 0; s < FFPIC_MAX_SPECIES; s++)
         for (int k = 0; k < 2; k++) { F(c->skey[s][k]); F(c->soff[s][k]); }
-    F(c->sort_sb); F(c->sort_blk); F(c->sort_aux); F(c->sort_moff); F(c->sort_mst); F(c->sort_cbuf); F(c->sort_tot); F(c->scan_tmp);
-    F(c->sort_cls);
-    F(c->inj_rate); F(c->inj_cnt); F(c->inj_off); F(c->inj_scan_tmp); F(c->nsorted);
-    F(c->gj_target); F(c->gj_have); F(c->pair_cnt); F(c->pair_off); F(c->pair_scan_tmp);
+    F(c->sort_smask); F(c->sort_mmask); F(c->sort_wsm); F(c->sort_tc); F(c->sort_ts); F(c->sort_gs);
+    F(c->sort_aux); F(c->sort_mst); F(c->sort_cbuf); F(c->sort_tot);
+    F(c->rs_hist); F(c->rs_dtot); F(c->rs_n); F(c->scan_part);
+    for (int s = 0; s < FFPIC_MAX_SPECIES; s++) F(c->perm[s]);
+    F(c->inj_rate); F(c->inj_cnt); F(c->inj_off); F(c->nsorted);
+    F(c->gj_target); F(c->gj_have); F(c->pair_cnt); F(c->pair_off);
     F(c->spec_tab); F(c->spec_edge); F(c->spec_nu);
-    if (c->nslots_host) (void)hipHostFree(c->nslots_host);
-    F(c->sort_tmp); F(c->nslots); F(c->nalive); F(c->removed); F(c->err); F(c->red);
+    F(c->nslots); F(c->nalive); F(c->removed); F(c->err); F(c->red);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
     for (auto &e : c->evpool) (void)hipEventDestroy(e);
@@ -449,8 +450,6 @@ void surface_tables(ffpic_ctx *c, const double *br_surface) {
     if (!c->inj_cnt) {
         c->inj_cnt = (int32_t *)dmalloc((size_t)(nth + 1) * sizeof(int32_t));
         c->inj_off = (int32_t *)dmalloc((size_t)(nth + 1) * sizeof(int32_t));
-        c->inj_scan_bytes = inject_scan_bytes(nth);
-        c->inj_scan_tmp = dmalloc(c->inj_scan_bytes);
     }
     if (inj) {
         if (!c->inj_rate) c->inj_rate = (double *)dmalloc((size_t)nth * sizeof(double));
@@ -517,13 +516,11 @@ void one_step(ffpic_ctx *c, uint32_t ph, bool count_step, int tslot) {
     }
     const bool sources = (c->d.inject_kappa > 0.0 || c->d.gj_extract > 0.0 ||
                           c->d.gamma_th > 0.0) && c->d.nspec > 0;
-    if ((ph & FFPIC_PHASE_SORT) && sources) {
-        // the sources only grow the host bound of the slots: reset it to
-        // the sorted count
-        int32_t ns[FFPIC_MAX_SPECIES] = {};
-        HCHK(hipMemcpyAsync(ns, c->nslots, sizeof(ns), hipMemcpyDeviceToHost, c->stream));
-        HCHK(hipStreamSynchronize(c->stream));
-        for (int s = 0; s < c->d.nspec; s++) c->sp[s].nub = ns[s];
+    if (sources) {
+        // the sources add particles that only the device counts: every
+        // launch covers all slots of a species (each kernel stops at the
+        // device count), so no count is read back during the step
+        for (int s = 0; s < c->d.nspec; s++) c->sp[s].nub = c->sp[s].cap;
     }
     if (ph & FFPIC_PHASE_INJECT) inject_pairs(c);
     if (ph & FFPIC_PHASE_EXTRACT) extract_gj(c);
@@ -668,43 +665,32 @@ int ffpic_create(const ffpic_desc *d, void *stream, ffpic_ctx **out) {
             c->keys[k] = (uint32_t *)dmalloc((size_t)maxcap * 4);
             c->vals[k] = (uint32_t *)dmalloc((size_t)maxcap * 4);
         }
-        c->sort_tmp_bytes = sort_temp_bytes(maxcap, sort_key_bits(c));
-        c->sort_tmp = dmalloc(c->sort_tmp_bytes);
+        sort_alloc(c, maxcap, dmalloc);
         {
-            const int64_t nblk = std::max<int64_t>(1, (maxcap + sort_block_slots() - 1) / sort_block_slots());
             const size_t nk1 = (size_t)c->nr * c->nth + 1;
-            c->sort_sb = (uint32_t *)dmalloc((size_t)(maxcap + 1) * 4);
-            c->sort_blk = (uint32_t *)dmalloc((size_t)nblk * 4 * 4);
             c->sort_aux = (uint32_t *)dmalloc((size_t)std::max<int64_t>(maxcap, 1) * 4);
-            if (!c->fp64) c->sort_cls = (uint8_t *)dmalloc((size_t)std::max<int64_t>(maxcap, 1));
-            c->sort_moff = (int32_t *)dmalloc(nk1 * 4);
             c->sort_mst = (int32_t *)dmalloc(nk1 * 4);
-            if (!c->fp64) {
-                // room for the state of a quarter of the slots changing cell
-                // between two sorts; a sort with more uses the direct scatter
-                c->sort_cbuf_n = std::max<int64_t>(maxcap / 4, 1);
-                c->sort_cbuf = (uint32_t *)dmalloc((size_t)c->sort_cbuf_n * 6 * 4);
-            }
+            // room for the state of a quarter of the slots changing cell
+            // between two sorts; the movers past it are read from their slots
+            c->sort_cbuf_n = std::max<int64_t>(maxcap / 4, 1);
+            c->sort_cbuf = dmalloc((size_t)c->sort_cbuf_n * (c->fp64 ? 5 * 8 : 6 * 4));
             c->sort_tot = (uint32_t *)dmalloc(2 * 4);
-            c->scan_tmp_bytes = scan_temp_bytes(nblk);
-            c->scan_tmp = dmalloc(c->scan_tmp_bytes);
             for (int s = 0; s < d->nspec; s++)
                 for (int k = 0; k < 2; k++) {
                     c->skey[s][k] = (uint32_t *)dmalloc((size_t)std::max<int64_t>(c->sp[s].cap, 1) * 4);
                     c->soff[s][k] = (int32_t *)dmalloc(nk1 * 4);
                 }
         }
+        int64_t scan_n = c->nth + 1;          // surface sources: per-cell counts
         if (d->gamma_th > 0.0) {
             const int64_t per = (maxcap + pair_block_slots() - 1) / pair_block_slots();
             c->pair_blocks = 2 * per;
             c->pair_cnt = (int32_t *)dmalloc((size_t)(c->pair_blocks + 1) * sizeof(int32_t));
             c->pair_off = (int32_t *)dmalloc((size_t)(c->pair_blocks + 1) * sizeof(int32_t));
-            c->pair_scan_bytes = pair_scan_bytes(c->pair_blocks);
-            c->pair_scan_tmp = dmalloc(c->pair_scan_bytes);
-            void *h = nullptr;
-            HCHK(hipHostMalloc(&h, FFPIC_MAX_SPECIES * sizeof(int32_t), hipHostMallocDefault));
-            c->nslots_host = (int32_t *)h;
+            scan_n = std::max<int64_t>(scan_n, c->pair_blocks + 1);
         }
+        c->scan_part_n = scan_part_len(scan_n);
+        c->scan_part = (int32_t *)dmalloc((size_t)c->scan_part_n * sizeof(int32_t));
         c->nslots = (int32_t *)dmalloc(FFPIC_MAX_SPECIES * sizeof(int32_t));
         c->nalive = (int32_t *)dmalloc(FFPIC_MAX_SPECIES * sizeof(int32_t));
         c->nsorted = (int32_t *)dmalloc(FFPIC_MAX_SPECIES * sizeof(int32_t));
@@ -1003,16 +989,43 @@ int ffpic_get_particles(ffpic_ctx *c, int s, double *r, double *th, double *ur, 
     return ffpic_get_particles_range(c, s, 0, &count, r, th, ur, uth, uph, cell);
 }
 
-int ffpic_get_sort(ffpic_ctx *c, int s, int32_t *off) {
+int ffpic_get_sort(ffpic_ctx *c, int s, int32_t *off, int32_t *perm, int64_t *nperm) {
     return guarded(c, [&] {
         check_ctx(c);
         if (s < 0 || s >= c->d.nspec || !off) throw Fail{FFPIC_EINVAL, "bad species or NULL"};
+        if ((perm || nperm) && !c->perm_valid[s])
+            throw Fail{FFPIC_EINVAL, "the last sort of this species was not recorded "
+                                     "(ffpic_record_sort)"};
         size_t nk = (size_t)c->nr * c->nth + 1;
         int32_t *d = (int32_t *)dmalloc(nk * sizeof(int32_t));
         sort_offsets(c, s, d);
         HCHK(hipMemcpyAsync(off, d, nk * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
         HCHK(hipStreamSynchronize(c->stream));
         HCHK(hipFree(d));
+        if (perm || nperm) {
+            // the live count right after that sort is the last cell offset it
+            // recorded
+            const int t = c->sort_cur[s];
+            int32_t n = 0;
+            HCHK(hipMemcpy(&n, c->soff[s][t] + (nk - 1), sizeof(int32_t), hipMemcpyDeviceToHost));
+            if (perm)
+                HCHK(hipMemcpy(perm, c->perm[s], (size_t)n * sizeof(int32_t),
+                               hipMemcpyDeviceToHost));
+            if (nperm) *nperm = n;
+        }
+    });
+}
+
+int ffpic_record_sort(ffpic_ctx *c, int on) {
+    return guarded(c, [&] {
+        check_ctx(c);
+        if (on) {
+            for (int s = 0; s < c->d.nspec; s++)
+                if (!c->perm[s])
+                    c->perm[s] = (int32_t *)dmalloc((size_t)std::max<int64_t>(c->sp[s].cap, 1) *
+                                                    sizeof(int32_t));
+        }
+        c->record_perm = on != 0;
     });
 }
 

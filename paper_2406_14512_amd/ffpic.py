@@ -116,7 +116,8 @@ def lib():
     L.ffpic_get_particles.argtypes = [P, C.c_int, vp, vp, vp, vp, vp, vp]
     L.ffpic_get_particles_range.argtypes = [P, C.c_int, C.c_int64, C.POINTER(C.c_int64),
                                             vp, vp, vp, vp, vp, vp]
-    L.ffpic_get_sort.argtypes = [P, C.c_int, vp]
+    L.ffpic_get_sort.argtypes = [P, C.c_int, vp, vp, C.POINTER(C.c_int64)]
+    L.ffpic_record_sort.argtypes = [P, C.c_int]
     L.ffpic_diagnostics.argtypes = [P, C.c_uint32, C.POINTER(Diag), vp]
     L.ffpic_diagnostics_noalloc.argtypes = [P, C.c_uint32, C.POINTER(Diag), vp]
     dptr = C.POINTER(C.c_double)
@@ -146,7 +147,7 @@ def lib():
                  "ffpic_batch_view", "ffpic_batch_size", "ffpic_batch_step", "ffpic_batch_sync",
                  "ffpic_batch_destroy", "ffpic_autotune", "ffpic_batch_autotune",
                  "ffpic_spectra", "ffpic_host_table", "ffpic_host_initial_field",
-                 "ffpic_diagnostics_noalloc", "ffpic_set_field_rows"):
+                 "ffpic_diagnostics_noalloc", "ffpic_set_field_rows", "ffpic_record_sort"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -333,8 +334,26 @@ class Sim:
 
     def sort_offsets(self, species: int) -> np.ndarray:
         out = np.zeros(self.nr * self.nth + 1, dtype=np.int32)
-        self._chk(lib().ffpic_get_sort(self._h, species, C.c_void_p(out.ctypes.data)))
+        self._chk(lib().ffpic_get_sort(self._h, species, C.c_void_p(out.ctypes.data), None,
+                                       None))
         return out
+
+    def record_sort(self, on: bool = True):
+        """Record the permutation of the following sorts (ffpic_record_sort)."""
+        self._chk(lib().ffpic_record_sort(self._h, int(bool(on))))
+
+    def sort_permutation(self, species: int) -> np.ndarray:
+        """perm[k] = slot before the last (recorded) sort of the particle now
+        in slot k."""
+        off = np.zeros(self.nr * self.nth + 1, dtype=np.int32)
+        n = C.c_int64(0)
+        L = lib()
+        self._chk(L.ffpic_get_sort(self._h, species, C.c_void_p(off.ctypes.data), None,
+                                   C.byref(n)))
+        perm = np.zeros(max(1, n.value), dtype=np.int32)
+        self._chk(L.ffpic_get_sort(self._h, species, C.c_void_p(off.ctypes.data),
+                                   C.c_void_p(perm.ctypes.data), C.byref(n)))
+        return perm[:n.value].copy()
 
     def set_field_rows(self, rows: int):
         """Radial rows per workgroup of the fused field step (0 = automatic)."""

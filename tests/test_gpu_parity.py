@@ -111,9 +111,19 @@ def test_psi_bit_exact_fp32_from_rounded_br(grid):
 def test_load_cells_and_sort_permutation_bit_exact(precision):
     w = W.tiny_open_dipole(30_000)
     sim, ora = pair(w, precision)
+    sim.record_sort(True)
     load_both(sim, ora, w)
     for s in range(2):
         g, o = sim.particles(s), ora.particles(s)
+        # the load's sort: slot k holds input particle perm[k], in stable
+        # cell order (equal cells keep the input order)
+        perm = sim.sort_permutation(s)
+        src = w.particles(s)
+        assert len(perm) == len(g["cell"])
+        assert np.array_equal(g["r"], src["r"][perm].astype(g["r"].dtype)) or \
+            np.allclose(g["r"], src["r"][perm], rtol=1e-7, atol=0)
+        same = np.diff(g["cell"]) == 0
+        assert np.all(np.diff(g["cell"]) >= 0) and np.all(np.diff(perm)[same] > 0)
         assert len(g["cell"]) == len(o["cell"]) > 1000
         assert np.array_equal(g["cell"], o["cell"])
         if precision == W.FP64:
@@ -530,6 +540,7 @@ def check_incremental_sort(w, precision, moved):
     for s in range(2):
         sim.load_particles(s, w.particles(s))
     prev = [sim.particles(s)["cell"] for s in range(2)]
+    sim.record_sort(True)
     for rnd in range(3):
         sim.step(4)
         sim.run_phases(ffpic.PHASE_MASK)
@@ -549,6 +560,7 @@ def check_incremental_sort(w, precision, moved):
             order = expected_stable_order(cells, killed)
             p1 = sim.particles(s)
             assert len(p1["r"]) == len(order), (rnd, s)
+            assert np.array_equal(sim.sort_permutation(s), order), (rnd, s)
             for k in ("cell", "r", "th", "ur", "uth", "uph"):
                 assert np.array_equal(p1[k], p0[k][order]), (rnd, s, k)
             off = sim.sort_offsets(s)
