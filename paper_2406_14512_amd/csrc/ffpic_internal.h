@@ -125,6 +125,7 @@ struct ffpic_ctx {
     uint2 *sort_tc = nullptr, *sort_ts = nullptr, *sort_gs = nullptr;   // tile / group counts
     uint32_t *sort_aux = nullptr;             // sorted mover slots [cap]
     int32_t *sort_mst = nullptr;              // movers before each key's stayers [nr*nth + 1]
+    int32_t *sort_kcnt = nullptr;             // movers per key, zero between sorts [nr*nth + 1]
     void *sort_cbuf = nullptr;                // movers' state, compacted [narr * cbuf_n]
     int64_t sort_cbuf_n = 0;
     uint32_t *sort_tot = nullptr;             // stayers, movers

@@ -56,8 +56,7 @@ constexpr int kTileWords = kTile / 64;      // 64-slot words per tile
 constexpr int kGroup = 1024;                // tiles per group of the tile scan
 constexpr int kRsItems = 16;                // pairs per thread of a radix tile
 constexpr int kRsTile = 256 * kRsItems;     // pairs per radix tile
-constexpr int kKeyChunk = 8;                // keys per thread of the key pass
-constexpr int kMoverBlocks = 2048;          // blocks of the mover placement
+constexpr int kMoverBlocks = 8192;          // blocks of the passes over the movers
 constexpr int kRsBlocks = 2048;             // blocks of a radix pass
 
 #define HCHK_SORT(x)                                                                    \
@@ -665,49 +664,48 @@ __global__ void __launch_bounds__(256) k_classify(ClassArgs A) {
             count_wave(&A.removed[1], killed);
         }
     }
-    __shared__ uint32_t wcnt[2][kTileWords];
+    // the tile's words are staged in LDS and written by 16 lanes at once
+    __shared__ uint64_t wmask[2][kTileWords];
+    __shared__ uint32_t wpre[2][kTileWords];
     uint64_t mm[K];
-    const int nwu = (A.nub + 63) >> 6;
 #pragma unroll
     for (int k = 0; k < K; k++) {
         const uint64_t sm = __ballot(cl[k] == 1);
         mm[k] = __ballot(cl[k] == 2);
-        const int word = k * 4 + w;
-        const int gw = (base >> 6) + word;
         if (lane == 0) {
-            wcnt[0][word] = (uint32_t)__popcll(sm);
-            wcnt[1][word] = (uint32_t)__popcll(mm[k]);
-            if (gw < nwu) {
-                A.smask[gw] = sm;
-                A.mmask[gw] = mm[k];
-            }
+            wmask[0][k * 4 + w] = sm;
+            wmask[1][k * 4 + w] = mm[k];
         }
+    }
+    __syncthreads();
+    const int nwu = (A.nub + 63) >> 6;
+    if (tid < kTileWords) {
+        uint32_t ps = 0, pm = 0;
+        for (int u = 0; u < tid; u++) {
+            ps += (uint32_t)__popcll(wmask[0][u]);
+            pm += (uint32_t)__popcll(wmask[1][u]);
+        }
+        wpre[0][tid] = ps;
+        wpre[1][tid] = pm;
+        const int gw = (base >> 6) + tid;
+        if (gw < nwu) {
+            A.smask[gw] = wmask[0][tid];
+            A.mmask[gw] = wmask[1][tid];
+            A.wsm[gw] = ps | (pm << 16);
+        }
+        if (tid == kTileWords - 1)
+            A.tc[blockIdx.x] = make_uint2(ps + (uint32_t)__popcll(wmask[0][tid]),
+                                          pm + (uint32_t)__popcll(wmask[1][tid]));
     }
     __syncthreads();
     const uint64_t below = lanes_below();
 #pragma unroll
     for (int k = 0; k < K; k++) {
-        const int word = k * 4 + w;
-        const int gw = (base >> 6) + word;
-        uint32_t ps = 0, pm = 0;
-        for (int u = 0; u < word; u++) {
-            ps += wcnt[0][u];
-            pm += wcnt[1][u];
-        }
-        if (lane == 0 && gw < nwu) A.wsm[gw] = ps | (pm << 16);
         if (cl[k] == 2) {
-            const int r = (int)pm + (int)__popcll(mm[k] & below);
+            const int r = (int)wpre[1][k * 4 + w] + (int)__popcll(mm[k] & below);
             A.tkey[base + r] = key[k];
             A.tval[base + r] = (uint32_t)(base + k * 256 + tid);
         }
-    }
-    if (tid == 0) {
-        uint32_t ts = 0, tm = 0;
-        for (int u = 0; u < kTileWords; u++) {
-            ts += wcnt[0][u];
-            tm += wcnt[1][u];
-        }
-        A.tc[blockIdx.x] = make_uint2(ts, tm);
     }
 }
 
@@ -784,37 +782,63 @@ __device__ __forceinline__ int lower_bound_u32(const uint32_t *a, int lo, int hi
     return lo;
 }
 
-// per key k (a chunk of consecutive keys per thread): mst[k] = movers with
-// key < k plus movers of key k from a slot below OFF[k]; the new offsets
-// SB(OFF[k]) + (movers with key < k); the new live count
+// movers per key: the first mover of each run of equal (sorted) keys
+// writes the run's length; keys without movers keep the zero that
+// k_key_offsets leaves behind
+__global__ void __launch_bounds__(256) k_mover_runs(const uint32_t *__restrict__ tot,
+                                                    const uint32_t *__restrict__ mk,
+                                                    int32_t *__restrict__ cnt) {
+    const int m = (int)tot[1];
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < m; j += gridDim.x * blockDim.x) {
+        const uint32_t key = mk[j];
+        if (j > 0 && mk[j - 1] == key) continue;
+        // end of the run, by galloping then bisection
+        int step = 1;
+        while (j + step < m && mk[j + step] == key) step <<= 1;
+        const int hi = lower_bound_u32(mk, j + (step >> 1), min(j + step, m), key + 1u);
+        cnt[key] = hi - j;
+    }
+}
+
+// per key k, from the exclusive scan of the mover counts (the block sums
+// scanned by k_scan_part): moff[k] = movers with key < k; mst[k] = moff[k]
+// plus the movers of key k from a slot below OFF[k]; the new offsets
+// SB(OFF[k]) + moff[k]; the new live count.  Clears the counts for the
+// next sort.
 __global__ void __launch_bounds__(256) k_key_offsets(
-    int nkeys, ClassView V, const uint32_t *__restrict__ mk, const uint32_t *__restrict__ mv,
-    const int32_t *__restrict__ offold, int32_t *__restrict__ mst, int32_t *__restrict__ offnew,
-    int32_t *__restrict__ nalive, int32_t *__restrict__ nslots, int32_t *__restrict__ nsorted) {
-    const int k0 = (blockIdx.x * blockDim.x + threadIdx.x) * kKeyChunk;
-    if (k0 > nkeys) return;
-    const int m = (int)V.tot[1];
-    int p = lower_bound_u32(mk, 0, m, (uint32_t)k0);        // movers with key < k0
-    const int kend = min(k0 + kKeyChunk, nkeys + 1);
-    for (int k = k0; k < kend; k++) {
+    int nkeys, ClassView V, const uint32_t *__restrict__ mv, const int32_t *__restrict__ offold,
+    int32_t *__restrict__ cnt, const int32_t *__restrict__ part, int32_t *__restrict__ mst,
+    int32_t *__restrict__ offnew, int32_t *__restrict__ nalive, int32_t *__restrict__ nslots,
+    int32_t *__restrict__ nsorted) {
+    const int n = nkeys + 1;
+    const int base = blockIdx.x * 1024 + threadIdx.x * 4;
+    int32_t cu[4];
+    uint64_t sum = 0;
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+        cu[u] = base + u < n ? cnt[base + u] : 0;
+        sum += (uint32_t)cu[u];
+    }
+    uint64_t tot;
+    uint32_t lo = (uint32_t)(block_scan256(sum, &tot) + (uint32_t)part[blockIdx.x]);
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+        const int k = base + u;
+        if (k >= n) break;
+        const uint32_t hi = lo + (uint32_t)cu[u];
         const int x = offold[k];
-        const int v = (int)stayers_before(V, x) + p;
+        const int v = (int)(stayers_before(V, x) + lo);
         offnew[k] = v;
         if (k == nkeys) {
             nalive[0] = v;
             nslots[0] = v;
             nsorted[0] = v;
-            break;
+        } else {
+            // the movers of key k are in slot order
+            mst[k] = cu[u] ? lower_bound_u32(mv, (int)lo, (int)hi, (uint32_t)x) : (int)lo;
+            if (cu[u]) cnt[k] = 0;
         }
-        // movers of key k: [p, hi), found by galloping from p
-        int hi = p;
-        if (hi < m && mk[hi] == (uint32_t)k) {
-            int step = 1;
-            while (p + step < m && mk[p + step] == (uint32_t)k) step <<= 1;
-            hi = lower_bound_u32(mk, p + (step >> 1), min(p + step, m), (uint32_t)k + 1u);
-        }
-        mst[k] = lower_bound_u32(mv, p, hi, (uint32_t)x);   // they are in slot order
-        p = hi;
+        lo = hi;
     }
 }
 
@@ -826,15 +850,16 @@ __global__ void __launch_bounds__(256) k_place_stayers(
     T *__restrict__ cbuf, int64_t cn) {
     const int q = blockIdx.x * 256 + threadIdx.x;
     if (q >= V.nub) return;
-    // slots past the live ones, dead slots and killed particles have
-    // neither bit
+    // the state is read before the class is known, so its loads overlap
+    // those of the class words (slots past the live ones, dead slots and
+    // killed particles have neither bit and are read for nothing)
+    T v[NA];
+#pragma unroll
+    for (int a = 0; a < NA; a++) v[a] = P.src[a][q];
     const int wd = q >> 6;
     const uint64_t bit = 1ull << (q & 63);
     const uint64_t sm = V.smask[wd], mm = V.mmask[wd];
     if (((sm | mm) & bit) == 0) return;
-    T v[NA];
-#pragma unroll
-    for (int a = 0; a < NA; a++) v[a] = P.src[a][q];
     if (sm & bit) {
         uint32_t key;
         if (FP64) {
@@ -1000,15 +1025,22 @@ static void sort_incremental(ffpic_ctx *c, int s) {
     const int32_t *offold = c->soff[s][t];
     uint32_t *knew = c->skey[s][1 - t];
     int32_t *offnew = c->soff[s][1 - t];
-    const int nkt = (nkeys + 1 + kKeyChunk - 1) / kKeyChunk;
+    // movers per key, their exclusive scan, and the per-key pass
+    const int nbk = (int)((nkeys + 1 + 1023) / 1024);
+    const int nbm = std::max(1, std::min((nub + 255) / 256, kMoverBlocks));
+    if (scan_part_len(nkeys + 1) > c->scan_part_n) throw std::runtime_error("scan scratch too small");
+    hipLaunchKernelGGL(k_mover_runs, dim3(nbm), dim3(256), 0, c->stream, c->sort_tot, M.k,
+                       c->sort_kcnt);
+    hipLaunchKernelGGL(k_scan_sums, dim3(nbk), dim3(256), 0, c->stream, c->sort_kcnt, nkeys + 1,
+                       c->scan_part);
+    hipLaunchKernelGGL(k_scan_part, dim3(1), dim3(256), 0, c->stream, c->scan_part, nbk);
     // reads the old live count (through OFF) before replacing it
-    hipLaunchKernelGGL(k_key_offsets, dim3((nkt + 255) / 256), dim3(256), 0, c->stream, nkeys, V,
-                       M.k, M.v, offold, c->sort_mst, offnew, c->nalive + s, c->nslots + s,
-                       c->nsorted + s);
+    hipLaunchKernelGGL(k_key_offsets, dim3(nbk), dim3(256), 0, c->stream, nkeys, V, M.v, offold,
+                       c->sort_kcnt, c->scan_part, c->sort_mst, offnew, c->nalive + s,
+                       c->nslots + s, c->nsorted + s);
     FFPIC_LAUNCH_CHECK();
     int32_t *perm = perm_out(c, s);
     const int nbs = (nub + 255) / 256;
-    const int nbm = std::max(1, std::min(nbs, kMoverBlocks));
     if (c->fp64) {
         auto P = state_ptrs<uint64_t, 5>(S);
         hipLaunchKernelGGL((k_place_stayers<uint64_t, 5, true>), dim3(nbs), dim3(256), 0,

@@ -399,7 +399,7 @@ void free_all(ffpic_ctx *c) {
     for (int s = 0; s < FFPIC_MAX_SPECIES; s++)
         for (int k = 0; k < 2; k++) { F(c->skey[s][k]); F(c->soff[s][k]); }
     F(c->sort_smask); F(c->sort_mmask); F(c->sort_wsm); F(c->sort_tc); F(c->sort_ts); F(c->sort_gs);
-    F(c->sort_aux); F(c->sort_mst); F(c->sort_cbuf); F(c->sort_tot);
+    F(c->sort_aux); F(c->sort_mst); F(c->sort_kcnt); F(c->sort_cbuf); F(c->sort_tot);
     F(c->rs_hist); F(c->rs_dtot); F(c->rs_n); F(c->scan_part);
     for (int s = 0; s < FFPIC_MAX_SPECIES; s++) F(c->perm[s]);
     F(c->inj_rate); F(c->inj_cnt); F(c->inj_off); F(c->nsorted);
@@ -670,6 +670,8 @@ int ffpic_create(const ffpic_desc *d, void *stream, ffpic_ctx **out) {
             const size_t nk1 = (size_t)c->nr * c->nth + 1;
             c->sort_aux = (uint32_t *)dmalloc((size_t)std::max<int64_t>(maxcap, 1) * 4);
             c->sort_mst = (int32_t *)dmalloc(nk1 * 4);
+            c->sort_kcnt = (int32_t *)dmalloc(nk1 * 4);
+            HCHK(hipMemset(c->sort_kcnt, 0, nk1 * 4));
             // room for the state of a quarter of the slots changing cell
             // between two sorts; the movers past it are read from their slots
             c->sort_cbuf_n = std::max<int64_t>(maxcap / 4, 1);
@@ -681,7 +683,8 @@ int ffpic_create(const ffpic_desc *d, void *stream, ffpic_ctx **out) {
                     c->soff[s][k] = (int32_t *)dmalloc(nk1 * 4);
                 }
         }
-        int64_t scan_n = c->nth + 1;          // surface sources: per-cell counts
+        // scans: the movers per key of the sort, the surface sources' counts
+        int64_t scan_n = std::max<int64_t>((int64_t)c->nr * c->nth + 1, c->nth + 1);
         if (d->gamma_th > 0.0) {
             const int64_t per = (maxcap + pair_block_slots() - 1) / pair_block_slots();
             c->pair_blocks = 2 * per;
