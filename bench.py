@@ -102,21 +102,29 @@ def make_sim(ffpic, w, precision):
     return ffpic.Sim(d, capacity=[w.n_per_species] * w.nspec)
 
 
-def run_timed(ffpic, sim, steps, warmup, nspec):
+def run_timed(ffpic, sim, steps, warmup, nspec, phase_steps=16):
+    """Wall time of `steps` steps as the library runs them (whole sort cycles
+    as replayed graphs), then the per-phase device times of `phase_steps`
+    more steps launched one by one with events between the phases."""
     sim.step(warmup)
     sim.sync()
     alive0 = sum(sim.diagnostics(ffpic.DIAG_MOMENTS)["alive"])
-    sim.set_timing(True)
+    g0 = sim.graph_stats()
     sim.sync()
     t0 = time.perf_counter()
     sim.step(steps)
     sim.sync()
     t1 = time.perf_counter()
+    g1 = sim.graph_stats()
+    alive1 = sum(sim.diagnostics(ffpic.DIAG_MOMENTS)["alive"])
+    sim.set_timing(True)
+    sim.step(phase_steps)
+    sim.sync()
     sim.set_timing(False)
     ph = sim.phase_times()
-    alive1 = sum(sim.diagnostics(ffpic.DIAG_MOMENTS)["alive"])
     wall = t1 - t0
-    return dict(wall=wall, phases=ph, alive0=alive0, alive1=alive1)
+    return dict(wall=wall, phases=ph, phase_steps=phase_steps, alive0=alive0, alive1=alive1,
+                graphs={"captured": g1[0] - g0[0], "launched": g1[1] - g0[1]})
 
 
 def roofline(precision, res, steps, nspec, copy_gbs):
@@ -124,7 +132,7 @@ def roofline(precision, res, steps, nspec, copy_gbs):
     # step; algorithmic bytes = state read + written per live particle
     n_avg = 0.5 * (res["alive0"] + res["alive1"])
     push_ms = res["phases"][2]
-    launches = steps * nspec
+    launches = res["phase_steps"] * nspec
     avg_launch_s = push_ms / 1e3 / launches
     bytes_per_launch = BYTES_PER_PARTICLE[precision] * n_avg / nspec
     achieved = bytes_per_launch / avg_launch_s / 1e9
@@ -297,8 +305,9 @@ def main():
         log(f"timing {'FP32-mixed' if p == 1 else 'FP64'}: {args.warmup} warmup + {args.steps} steps")
         results[p] = run_timed(ffpic, sims[p], args.steps, args.warmup, w.nspec)
         r = results[p]
-        log(f"  {r['wall'] / args.steps * 1e3:.3f} ms/step, phases (ms/step) mask/sort/push/fields "
-            + " ".join(f"{x / args.steps:.3f}" for x in r["phases"]))
+        log(f"  {r['wall'] / args.steps * 1e3:.3f} ms/step ({r['graphs']['launched']} graph "
+            f"launches), phases (ms/step) mask/sort/push/fields "
+            + " ".join(f"{x / r['phase_steps']:.3f}" for x in r["phases"]))
         if p == 0:
             sims[p].close()
 
@@ -326,8 +335,9 @@ def main():
                    "grid": f"{w.nr}x{w.nth}", "particles": int(n_avg),
                    "precision": "fp32-mixed", "sort_interval": w.sort_interval},
         "cell_updates_per_s": w.nr * w.nth * args.steps / r["wall"],
-        "phase_ms_per_step": {k: round(v / args.steps, 4)
+        "phase_ms_per_step": {k: round(v / r["phase_steps"], 4)
                               for k, v in zip(("mask", "sort", "push_deposit", "fields"), r["phases"])},
+        "graphs": r["graphs"],
         "roofline": roofline(1, r, args.steps, w.nspec, copy_gbs),
     }
     if 0 in results:
@@ -336,7 +346,7 @@ def main():
         out["fp64"] = {"value": n64 * args.steps / r64["wall"], "unit": "particle-steps/s",
                        "ms_per_step": r64["wall"] / args.steps * 1e3,
                        "cell_updates_per_s": w.nr * w.nth * args.steps / r64["wall"],
-                       "phase_ms_per_step": {k: round(v / args.steps, 4) for k, v in
+                       "phase_ms_per_step": {k: round(v / r64["phase_steps"], 4) for k, v in
                                              zip(("mask", "sort", "push_deposit", "fields"),
                                                  r64["phases"])},
                        "roofline": roofline(0, r64, args.steps, w.nspec, copy_gbs)}

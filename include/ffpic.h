@@ -236,7 +236,8 @@ int ffpic_load_particles(ffpic_ctx *ctx, int species, int64_t n, const double *r
                          const double *th, const double *ur, const double *uth,
                          const double *uph, int src_on_device);
 
-/* Advances nsteps time steps, asynchronously on the context's stream. */
+/* Advances nsteps time steps, asynchronously on the context's stream; no
+   call reads from the device or waits for it (see ffpic_set_graph). */
 int ffpic_step(ffpic_ctx *ctx, int32_t nsteps);
 
 /* Test hook: runs single phases of a step without advancing the step
@@ -399,6 +400,20 @@ int ffpic_restore(ffpic_ctx *ctx, const void *buf, size_t len);
    0 = automatic (enough slabs to fill the GPU once, at least 32 rows).
    Results do not depend on it.  EINVAL for a negative value. */
 int ffpic_set_field_rows(ffpic_ctx *ctx, int32_t rows);
+
+/* Graph capture of ffpic_step (on by default).  A call of ffpic_step runs
+   every whole sort cycle it contains (sort_interval steps from a step that
+   sorts) as one HIP graph: captured on the first cycle that starts from a
+   given host state (buffer roles, sort bookkeeping, slot bounds), then
+   replayed for every later cycle from the same state (the buffers
+   alternate, so a steady run replays two or four graphs).  Other steps,
+   cycles whose kernel arguments change every step (surface injection or
+   extraction, a radiation-reaction ramp), the first cycle after a load and
+   steps timed with ffpic_set_timing are launched one by one.  Results do
+   not depend on it.  ffpic_graph_stats reports the graphs captured and
+   launched so far (either pointer nullable). */
+int ffpic_set_graph(ffpic_ctx *ctx, int on);
+int ffpic_graph_stats(ffpic_ctx *ctx, int64_t *builds, int64_t *launches);
 
 /* Device time of each phase of the last ffpic_step call, in ms, summed over
    its steps: out[0] mask, [1] sort, [2] push+deposit, [3] fields.

@@ -59,6 +59,26 @@ struct Species {
     double qm = 0, weight = 0;
 };
 
+// The host state that one sort cycle of steps reads into its kernels'
+// arguments and changes: buffer pointers that swap, sort bookkeeping, slot
+// bounds.  A captured cycle is replayed only from the state it was captured
+// in, and leaves the state its capture left.
+struct CycleState {
+    void *cur[FFPIC_MAX_SPECIES][6], *alt[FFPIC_MAX_SPECIES][6];
+    int64_t nub[FFPIC_MAX_SPECIES];
+    int sort_cur[FFPIC_MAX_SPECIES];
+    bool sort_valid[FFPIC_MAX_SPECIES], perm_valid[FFPIC_MAX_SPECIES];
+    void *E[3], *B[3], *J[3], *dE[3], *dB[3], *stAlt[6], *Jalt[3];
+    int fused_rows;                  // settings the launches depend on
+    bool record_perm, incremental_sort;
+};
+
+struct CycleGraph {
+    int steps = 0;
+    CycleState pre{}, post{};
+    hipGraphExec_t exec = nullptr;
+};
+
 }  // namespace ffpic
 
 struct ffpic_ctx {
@@ -153,6 +173,13 @@ struct ffpic_ctx {
     std::vector<hipEvent_t> evpool;           // 5 per timed step
     float phase_ms[4] = {};
     bool batch_owned = false;                 // a view of a batch system
+    // graph-captured sort cycles (see ffpic_set_graph): the graphs made so
+    // far, each with the host state it starts from and leaves behind
+    bool use_graph = true;
+    hipStream_t gstream = nullptr;            // capture stream (forked from stream)
+    hipEvent_t gfork = nullptr, gjoin = nullptr;
+    std::vector<ffpic::CycleGraph> graphs;
+    int64_t graph_builds = 0, graph_launches = 0;
     std::string last_error;
 };
 

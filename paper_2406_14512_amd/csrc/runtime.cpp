@@ -379,7 +379,15 @@ void alloc3(ffpic_ctx *c, void **p, bool zero) {
     for (int k = 0; k < 3; k++) p[k] = b + k * cs;
 }
 
+void destroy_graphs(ffpic_ctx *c);
+
 void free_all(ffpic_ctx *c) {
+    destroy_graphs(c);
+    if (c->gstream) (void)hipStreamDestroy(c->gstream);
+    if (c->gfork) (void)hipEventDestroy(c->gfork);
+    if (c->gjoin) (void)hipEventDestroy(c->gjoin);
+    c->gstream = nullptr;
+    c->gfork = c->gjoin = nullptr;
     auto F = [](void *p) { if (p) (void)hipFree(p); };
     // three-component fields: one allocation each, at component 0
     F(c->dE[0]); F(c->dB[0]); F(c->E0[0]); F(c->rE0[0]); F(c->rB0[0]);
@@ -532,6 +540,153 @@ void one_step(ffpic_ctx *c, uint32_t ph, bool count_step, int tslot) {
     if (ph & FFPIC_PHASE_FIELDS) field_step(c);
     mark(4);
     if (count_step) c->step++;
+}
+
+// phases of the step about to be taken
+uint32_t step_phases(const ffpic_ctx *c) {
+    uint32_t ph = FFPIC_PHASE_MASK | FFPIC_PHASE_KILL | FFPIC_PHASE_INJECT | FFPIC_PHASE_EXTRACT |
+                  FFPIC_PHASE_PUSH | FFPIC_PHASE_PAIRS | FFPIC_PHASE_FIELDS;
+    if (c->step % c->d.sort_interval == 0) ph |= FFPIC_PHASE_SORT;
+    // the push removes particles of force-free cells itself
+    if (!(ph & FFPIC_PHASE_SORT)) ph &= ~FFPIC_PHASE_KILL;
+    return ph;
+}
+
+CycleState cycle_state(const ffpic_ctx *c) {
+    CycleState st;
+    std::memset(&st, 0, sizeof(st));   // compared bytewise, padding included
+    for (int s = 0; s < FFPIC_MAX_SPECIES; s++) {
+        for (int a = 0; a < 6; a++) {
+            st.cur[s][a] = c->sp[s].cur[a];
+            st.alt[s][a] = c->sp[s].alt[a];
+        }
+        st.nub[s] = c->sp[s].nub;
+        st.sort_cur[s] = c->sort_cur[s];
+        st.sort_valid[s] = c->sort_valid[s];
+        st.perm_valid[s] = c->perm_valid[s];
+    }
+    for (int k = 0; k < 3; k++) {
+        st.E[k] = c->E[k];
+        st.B[k] = c->B[k];
+        st.J[k] = c->J[k];
+        st.dE[k] = c->dE[k];
+        st.dB[k] = c->dB[k];
+        st.Jalt[k] = c->Jalt[k];
+    }
+    for (int k = 0; k < 6; k++) st.stAlt[k] = c->stAlt[k];
+    st.fused_rows = c->fused_rows;
+    st.record_perm = c->record_perm;
+    st.incremental_sort = c->incremental_sort;
+    return st;
+}
+
+void set_cycle_state(ffpic_ctx *c, const CycleState &st) {
+    for (int s = 0; s < FFPIC_MAX_SPECIES; s++) {
+        for (int a = 0; a < 6; a++) {
+            c->sp[s].cur[a] = st.cur[s][a];
+            c->sp[s].alt[a] = st.alt[s][a];
+        }
+        c->sp[s].nub = st.nub[s];
+        c->sort_cur[s] = st.sort_cur[s];
+        c->sort_valid[s] = st.sort_valid[s];
+        c->perm_valid[s] = st.perm_valid[s];
+    }
+    for (int k = 0; k < 3; k++) {
+        c->E[k] = st.E[k];
+        c->B[k] = st.B[k];
+        c->J[k] = st.J[k];
+        c->dE[k] = st.dE[k];
+        c->dB[k] = st.dB[k];
+        c->Jalt[k] = st.Jalt[k];
+    }
+    for (int k = 0; k < 6; k++) c->stAlt[k] = st.stAlt[k];
+}
+
+// A sort cycle can be replayed from a graph when no kernel argument
+// depends on the step number (the surface sources draw from a counter-based
+// generator keyed by the step; a radiation-reaction ramp changes the push's
+// coefficient every step), and every species with particles has had its
+// first (full) sort.
+bool cycle_graphable(const ffpic_ctx *c) {
+    if (!c->use_graph || c->timing) return false;
+    if (c->d.inject_kappa > 0.0 || c->d.gj_extract > 0.0 || c->d.rr_ramp_n > 0) return false;
+    for (int s = 0; s < c->d.nspec; s++)
+        if (c->sp[s].nub > 0 && !c->sort_valid[s]) return false;
+    return true;
+}
+
+constexpr size_t kMaxGraphs = 4;
+
+void destroy_graphs(ffpic_ctx *c) {
+    if (!c->graphs.empty() && c->gstream) (void)hipStreamSynchronize(c->gstream);
+    for (auto &g : c->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    c->graphs.clear();
+}
+
+void launch_graph(ffpic_ctx *c, hipGraphExec_t exec) {
+    // the graph runs on the capture stream, ordered after the work already
+    // on the context's stream and before the work that follows it there
+    HCHK(hipEventRecord(c->gfork, c->stream));
+    HCHK(hipStreamWaitEvent(c->gstream, c->gfork, 0));
+    HCHK(hipGraphLaunch(exec, c->gstream));
+    HCHK(hipEventRecord(c->gjoin, c->gstream));
+    HCHK(hipStreamWaitEvent(c->stream, c->gjoin, 0));
+    c->graph_launches++;
+}
+
+// k steps from a sort step, as one graph: replayed if one was captured from
+// the same host state, else captured (the host bookkeeping of the steps runs
+// while the kernels are recorded), instantiated and kept
+void run_cycle_graph(ffpic_ctx *c, int k) {
+    const CycleState pre = cycle_state(c);
+    for (auto &g : c->graphs) {
+        if (g.steps == k && std::memcmp(&g.pre, &pre, sizeof(pre)) == 0) {
+            launch_graph(c, g.exec);
+            set_cycle_state(c, g.post);
+            c->step += k;
+            return;
+        }
+    }
+    if (!c->gstream) {
+        HCHK(hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
+        HCHK(hipEventCreateWithFlags(&c->gfork, hipEventDisableTiming));
+        HCHK(hipEventCreateWithFlags(&c->gjoin, hipEventDisableTiming));
+    }
+    const int64_t step0 = c->step;
+    hipStream_t saved = c->stream;
+    c->stream = c->gstream;
+    hipGraph_t graph = nullptr;
+    HCHK(hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal));
+    try {
+        for (int i = 0; i < k; i++) one_step(c, step_phases(c), true, -1);
+    } catch (...) {
+        (void)hipStreamEndCapture(c->gstream, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        c->stream = saved;
+        set_cycle_state(c, pre);
+        c->step = step0;
+        throw;
+    }
+    c->stream = saved;
+    HCHK(hipStreamEndCapture(c->gstream, &graph));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        set_cycle_state(c, pre);
+        c->step = step0;
+        throw Fail{FFPIC_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e)};
+    }
+    if (c->graphs.size() >= kMaxGraphs) destroy_graphs(c);
+    CycleGraph g;
+    g.steps = k;
+    g.pre = pre;
+    g.post = cycle_state(c);
+    g.exec = exec;
+    c->graphs.push_back(g);
+    c->graph_builds++;
+    launch_graph(c, exec);
 }
 
 }  // namespace
@@ -881,14 +1036,16 @@ int ffpic_step(ffpic_ctx *c, int32_t nsteps) {
                 c->evpool.push_back(e);
             }
         }
-        for (int k = 0; k < nsteps; k++) {
-            uint32_t ph = FFPIC_PHASE_MASK | FFPIC_PHASE_KILL | FFPIC_PHASE_INJECT |
-                          FFPIC_PHASE_EXTRACT | FFPIC_PHASE_PUSH | FFPIC_PHASE_PAIRS |
-                          FFPIC_PHASE_FIELDS;
-            if (c->step % c->d.sort_interval == 0) ph |= FFPIC_PHASE_SORT;
-            // the push removes particles of force-free cells itself
-            if (!(ph & FFPIC_PHASE_SORT)) ph &= ~FFPIC_PHASE_KILL;
-            one_step(c, ph, true, c->timing ? k : -1);
+        const int si = c->d.sort_interval;
+        for (int k = 0; k < nsteps;) {
+            // whole sort cycles as graphs, the other steps one by one
+            if (c->step % si == 0 && nsteps - k >= si && cycle_graphable(c)) {
+                run_cycle_graph(c, si);
+                k += si;
+                continue;
+            }
+            one_step(c, step_phases(c), true, c->timing ? k : -1);
+            k++;
         }
         if (c->timing && nsteps > 0) {
             // events only: the stream is not drained between steps
@@ -1211,6 +1368,21 @@ int ffpic_set_field_rows(ffpic_ctx *c, int32_t rows) {
         if (rows < 0) throw Fail{FFPIC_EINVAL, "negative row count"};
         c->fused_rows = rows;
     });
+}
+
+int ffpic_set_graph(ffpic_ctx *c, int on) {
+    return guarded(c, [&] {
+        check_ctx(c);
+        c->use_graph = on != 0;
+        if (!c->use_graph) destroy_graphs(c);
+    });
+}
+
+int ffpic_graph_stats(ffpic_ctx *c, int64_t *builds, int64_t *launches) {
+    if (!c) return FFPIC_EINVAL;
+    if (builds) *builds = c->graph_builds;
+    if (launches) *launches = c->graph_launches;
+    return FFPIC_OK;
 }
 
 int ffpic_set_timing(ffpic_ctx *c, int enable) {

@@ -118,6 +118,8 @@ def lib():
                                             vp, vp, vp, vp, vp, vp]
     L.ffpic_get_sort.argtypes = [P, C.c_int, vp, vp, C.POINTER(C.c_int64)]
     L.ffpic_record_sort.argtypes = [P, C.c_int]
+    L.ffpic_set_graph.argtypes = [P, C.c_int]
+    L.ffpic_graph_stats.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     L.ffpic_diagnostics.argtypes = [P, C.c_uint32, C.POINTER(Diag), vp]
     L.ffpic_diagnostics_noalloc.argtypes = [P, C.c_uint32, C.POINTER(Diag), vp]
     dptr = C.POINTER(C.c_double)
@@ -147,7 +149,8 @@ def lib():
                  "ffpic_batch_view", "ffpic_batch_size", "ffpic_batch_step", "ffpic_batch_sync",
                  "ffpic_batch_destroy", "ffpic_autotune", "ffpic_batch_autotune",
                  "ffpic_spectra", "ffpic_host_table", "ffpic_host_initial_field",
-                 "ffpic_diagnostics_noalloc", "ffpic_set_field_rows", "ffpic_record_sort"):
+                 "ffpic_diagnostics_noalloc", "ffpic_set_field_rows", "ffpic_record_sort",
+                 "ffpic_set_graph", "ffpic_graph_stats"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -337,6 +340,16 @@ class Sim:
         self._chk(lib().ffpic_get_sort(self._h, species, C.c_void_p(out.ctypes.data), None,
                                        None))
         return out
+
+    def set_graph(self, on: bool):
+        """Graph capture of whole sort cycles in step() (ffpic_set_graph)."""
+        self._chk(lib().ffpic_set_graph(self._h, int(bool(on))))
+
+    def graph_stats(self):
+        """(graphs captured, graph launches) so far."""
+        b, l = C.c_int64(0), C.c_int64(0)
+        self._chk(lib().ffpic_graph_stats(self._h, C.byref(b), C.byref(l)))
+        return b.value, l.value
 
     def record_sort(self, on: bool = True):
         """Record the permutation of the following sorts (ffpic_record_sort)."""
