@@ -165,18 +165,28 @@ def batch_run(ffpic, W, steps, warmup, scale):
     b.sync()
     alive = lambda: sum(sum(v.diagnostics(ffpic.DIAG_MOMENTS)["alive"]) for v in b.views)
     n0 = alive()
+    g0 = b.graph_stats()
     t0 = time.perf_counter()
     b.step(steps)
     b.sync()
     t1 = time.perf_counter()
+    g1 = b.graph_stats()
     n1 = alive()
+    # the same steps launched one by one, for comparison
+    b.set_graph(False)
+    t2 = time.perf_counter()
+    b.step(steps)
+    b.sync()
+    t3 = time.perf_counter()
     cells = sum(w.nr * w.nth for w in ws)
     b.close()
     wall = t1 - t0
     return {"systems": len(ws), "particles": int(0.5 * (n0 + n1)), "cells": cells,
             "steps": steps, "ms_per_step": wall / steps * 1e3,
             "particle_steps_per_s": 0.5 * (n0 + n1) * steps / wall,
-            "cell_updates_per_s": cells * steps / wall}
+            "cell_updates_per_s": cells * steps / wall,
+            "graphs": {"captured": g1[0] - g0[0], "launched": g1[1] - g0[1]},
+            "eager_ms_per_step": (t3 - t2) / steps * 1e3}
 
 
 def host_cpu():

@@ -446,6 +446,16 @@ int ffpic_batch_view(ffpic_batch *b, int k, ffpic_ctx **view);
 int ffpic_batch_size(const ffpic_batch *b);
 int ffpic_batch_step(ffpic_batch *b, int32_t nsteps);
 int ffpic_batch_sync(ffpic_batch *b);
+
+/* Graph capture of batch steps (on by default): when every system stands
+   at the start of a sort cycle of the same length and each could replay
+   its own cycle from a graph (see ffpic_set_graph), ffpic_batch_step runs
+   that cycle of all systems as one HIP graph, in which every system's
+   launches form their own chain on its stream's branch; captured once per
+   host state of all systems and replayed afterwards.  Other steps are
+   launched one by one.  Results do not depend on it. */
+int ffpic_batch_set_graph(ffpic_batch *b, int on);
+int ffpic_batch_graph_stats(ffpic_batch *b, int64_t *builds, int64_t *launches);
 const char *ffpic_batch_last_error(const ffpic_batch *b);
 int ffpic_batch_destroy(ffpic_batch *b);
 

@@ -32,6 +32,14 @@
 
 #include "ffpic_internal.h"
 
+// one batch sort cycle as a graph, with the host state of every system it
+// starts from and leaves
+struct BatchGraph {
+    int steps = 0;
+    std::vector<ffpic::CycleState> pre, post;
+    hipGraphExec_t exec = nullptr;
+};
+
 struct ffpic_batch {
     hipStream_t caller = nullptr;
     std::vector<ffpic_ctx *> ctx;
@@ -39,6 +47,13 @@ struct ffpic_batch {
     std::vector<int> lane;            // stream of each system
     hipEvent_t fork = nullptr;
     std::vector<hipEvent_t> join;     // one per stream
+    // graph-captured batch cycles: captured from origin, which forks to the
+    // lane streams and joins them back
+    bool use_graph = true;
+    hipStream_t origin = nullptr;
+    hipEvent_t gfork = nullptr, gjoin = nullptr;
+    std::vector<BatchGraph> graphs;
+    int64_t graph_builds = 0, graph_launches = 0;
     std::string last_error;
 };
 
@@ -81,7 +96,20 @@ double cost_of(const ffpic_desc &d) {
     return parts + 4.0 * (double)(d.nr + 1) * (double)(d.nth + 1);
 }
 
+void destroy_batch_graphs(ffpic_batch *b) {
+    if (!b->graphs.empty() && b->origin) (void)hipStreamSynchronize(b->origin);
+    for (auto &g : b->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    b->graphs.clear();
+}
+
 void release(ffpic_batch *b) {
+    destroy_batch_graphs(b);
+    if (b->origin) (void)hipStreamDestroy(b->origin);
+    if (b->gfork) (void)hipEventDestroy(b->gfork);
+    if (b->gjoin) (void)hipEventDestroy(b->gjoin);
+    b->origin = nullptr;
+    b->gfork = b->gjoin = nullptr;
     for (size_t k = 0; k < b->ctx.size(); k++) {
         if (!b->ctx[k]) continue;
         b->ctx[k]->batch_owned = false;
@@ -93,6 +121,101 @@ void release(ffpic_batch *b) {
     if (b->fork) (void)hipEventDestroy(b->fork);
     for (auto e : b->join) (void)hipEventDestroy(e);
     b->join.clear();
+}
+
+// A batch cycle (the common sort interval of all systems) can be a graph
+// when every system's next cycle can (see graphable_cycle) and all systems
+// stand at the start of a cycle.
+int batch_cycle(const ffpic_batch *b) {
+    if (!b->use_graph) return 0;
+    const int si = b->ctx[0]->d.sort_interval;
+    for (ffpic_ctx *c : b->ctx) {
+        if (c->d.sort_interval != si || c->step % si != 0) return 0;
+        if (!ffpic::graphable_cycle(c)) return 0;
+    }
+    return si;
+}
+
+bool same_states(const std::vector<ffpic::CycleState> &a, const std::vector<ffpic::CycleState> &b) {
+    if (a.size() != b.size()) return false;
+    for (size_t k = 0; k < a.size(); k++)
+        if (std::memcmp(&a[k], &b[k], sizeof(ffpic::CycleState)) != 0) return false;
+    return true;
+}
+
+void launch_batch_graph(ffpic_batch *b, hipGraphExec_t exec) {
+    BCHK(hipEventRecord(b->gfork, b->caller));
+    BCHK(hipStreamWaitEvent(b->origin, b->gfork, 0));
+    BCHK(hipGraphLaunch(exec, b->origin));
+    BCHK(hipEventRecord(b->gjoin, b->origin));
+    BCHK(hipStreamWaitEvent(b->caller, b->gjoin, 0));
+    b->graph_launches++;
+}
+
+// k steps of every system as one graph: the systems' launches go to their
+// lane streams, each forked from the capture stream and joined back into
+// it, so the graph keeps the systems independent of each other
+void run_batch_cycle(ffpic_batch *b, int k) {
+    std::vector<ffpic::CycleState> pre;
+    pre.reserve(b->ctx.size());
+    for (ffpic_ctx *c : b->ctx) pre.push_back(ffpic::get_cycle_state(c));
+    for (auto &g : b->graphs) {
+        if (g.steps == k && same_states(g.pre, pre)) {
+            launch_batch_graph(b, g.exec);
+            for (size_t q = 0; q < b->ctx.size(); q++) {
+                ffpic::put_cycle_state(b->ctx[q], g.post[q]);
+                b->ctx[q]->step += k;
+            }
+            return;
+        }
+    }
+    if (!b->origin) {
+        BCHK(hipStreamCreateWithFlags(&b->origin, hipStreamNonBlocking));
+        BCHK(hipEventCreateWithFlags(&b->gfork, hipEventDisableTiming));
+        BCHK(hipEventCreateWithFlags(&b->gjoin, hipEventDisableTiming));
+    }
+    std::vector<int64_t> step0;
+    for (ffpic_ctx *c : b->ctx) step0.push_back(c->step);
+    auto restore = [&] {
+        for (size_t q = 0; q < b->ctx.size(); q++) {
+            ffpic::put_cycle_state(b->ctx[q], pre[q]);
+            b->ctx[q]->step = step0[q];
+        }
+    };
+    hipGraph_t graph = nullptr;
+    BCHK(hipStreamBeginCapture(b->origin, hipStreamCaptureModeThreadLocal));
+    try {
+        BCHK(hipEventRecord(b->fork, b->origin));
+        for (auto s : b->streams) BCHK(hipStreamWaitEvent(s, b->fork, 0));
+        for (int i = 0; i < k; i++)
+            for (ffpic_ctx *c : b->ctx) ffpic::steps_one_by_one(c, 1);
+        for (size_t s = 0; s < b->streams.size(); s++) {
+            BCHK(hipEventRecord(b->join[s], b->streams[s]));
+            BCHK(hipStreamWaitEvent(b->origin, b->join[s], 0));
+        }
+    } catch (...) {
+        (void)hipStreamEndCapture(b->origin, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        restore();
+        throw;
+    }
+    BCHK(hipStreamEndCapture(b->origin, &graph));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        restore();
+        throw BFail{FFPIC_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e)};
+    }
+    if (b->graphs.size() >= 4) destroy_batch_graphs(b);
+    BatchGraph g;
+    g.steps = k;
+    g.pre = pre;
+    for (ffpic_ctx *c : b->ctx) g.post.push_back(ffpic::get_cycle_state(c));
+    g.exec = exec;
+    b->graphs.push_back(std::move(g));
+    b->graph_builds++;
+    launch_batch_graph(b, exec);
 }
 
 std::string cache_key(const ffpic_ctx *c) {
@@ -252,10 +375,6 @@ int ffpic_batch_create(int n, const ffpic_desc *d, void *stream, ffpic_batch **o
             if (r != FFPIC_OK)
                 throw BFail{r, "system " + std::to_string(k) + ": descriptor rejected or allocation failed"};
             c->batch_owned = true;
-            // the incremental sort reads its mover count back to the host,
-            // which would stall the issue of the other systems: batches use
-            // the full sort, which needs no synchronisation
-            c->incremental_sort = false;
             b->ctx[k] = c;
         }
     });
@@ -289,7 +408,34 @@ int ffpic_batch_step(ffpic_batch *b, int32_t nsteps) {
         for (auto s : b->streams) BCHK(hipStreamWaitEvent(s, b->fork, 0));
         int failed = FFPIC_OK;
         std::string why;
-        for (int k = 0; k < nsteps && failed == FFPIC_OK; k++)
+        for (int k = 0; k < nsteps && failed == FFPIC_OK;) {
+            // whole batch cycles as graphs
+            const int kc = batch_cycle(b);
+            if (kc > 0 && nsteps - k >= kc) {
+                // the graph runs from the capture stream, ordered after the
+                // lane streams' earlier work by the caller's stream: join
+                // the lanes into the caller first
+                for (size_t s = 0; s < b->streams.size(); s++) {
+                    BCHK(hipEventRecord(b->join[s], b->streams[s]));
+                    BCHK(hipStreamWaitEvent(b->caller, b->join[s], 0));
+                }
+                try {
+                    run_batch_cycle(b, kc);
+                } catch (const BFail &e) {
+                    failed = e.code;
+                    why = e.msg;
+                    break;
+                } catch (const std::exception &e) {
+                    failed = FFPIC_EHIP;
+                    why = e.what();
+                    break;
+                }
+                // and the lanes' later work after the graph
+                BCHK(hipEventRecord(b->fork, b->caller));
+                for (auto s : b->streams) BCHK(hipStreamWaitEvent(s, b->fork, 0));
+                k += kc;
+                continue;
+            }
             for (size_t q = 0; q < b->ctx.size(); q++) {
                 int r = ffpic_step(b->ctx[q], 1);
                 if (r != FFPIC_OK) {
@@ -298,6 +444,8 @@ int ffpic_batch_step(ffpic_batch *b, int32_t nsteps) {
                     break;
                 }
             }
+            k++;
+        }
         // join even after a failure, so the caller's stream stays ordered
         for (size_t s = 0; s < b->streams.size(); s++) {
             BCHK(hipEventRecord(b->join[s], b->streams[s]));
@@ -316,6 +464,21 @@ int ffpic_batch_sync(ffpic_batch *b) {
                 throw BFail{r, "system " + std::to_string(q) + ": " + ffpic_last_error(b->ctx[q])};
         }
     });
+}
+
+int ffpic_batch_set_graph(ffpic_batch *b, int on) {
+    return bguard(b, [&] {
+        if (!b) throw BFail{FFPIC_EINVAL, "batch is NULL"};
+        b->use_graph = on != 0;
+        if (!b->use_graph) destroy_batch_graphs(b);
+    });
+}
+
+int ffpic_batch_graph_stats(ffpic_batch *b, int64_t *builds, int64_t *launches) {
+    if (!b) return FFPIC_EINVAL;
+    if (builds) *builds = b->graph_builds;
+    if (launches) *launches = b->graph_launches;
+    return FFPIC_OK;
 }
 
 const char *ffpic_batch_last_error(const ffpic_batch *b) {

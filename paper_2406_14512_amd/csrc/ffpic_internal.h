@@ -240,6 +240,13 @@ void extract_gj(ffpic_ctx *c);
 void create_pairs(ffpic_ctx *c);
 int pair_block_slots();
 double rr_factor(const ffpic_ctx *c);   // radiation-reaction ramp at this step
+// steps launched one by one (no graph), for callers that capture themselves
+void steps_one_by_one(ffpic_ctx *c, int n);
+// whether the next sort cycle can be replayed from a graph, and the host
+// state such a replay starts from and leaves (see CycleState)
+bool graphable_cycle(const ffpic_ctx *c);
+CycleState get_cycle_state(const ffpic_ctx *c);
+void put_cycle_state(ffpic_ctx *c, const CycleState &st);
 // dev_out: ngamma + nnu + 1 doubles (dN, sed, prad)
 void spectra(ffpic_ctx *c, int s, const ffpic_spectra_req *req, double *dev_out);
 

@@ -1401,6 +1401,16 @@ int ffpic_phase_times(ffpic_ctx *c, float out[4]) {
 
 namespace ffpic {
 
+void steps_one_by_one(ffpic_ctx *c, int n) {
+    for (int k = 0; k < n; k++) one_step(c, step_phases(c), true, -1);
+}
+
+bool graphable_cycle(const ffpic_ctx *c) { return cycle_graphable(c); }
+
+CycleState get_cycle_state(const ffpic_ctx *c) { return cycle_state(c); }
+
+void put_cycle_state(ffpic_ctx *c, const CycleState &st) { set_cycle_state(c, st); }
+
 double rr_factor(const ffpic_ctx *c) {
 #pragma clang fp contract(off)
     return rr_factor_at(c->d, (double)c->step * c->dt);

@@ -119,6 +119,8 @@ def lib():
     L.ffpic_get_sort.argtypes = [P, C.c_int, vp, vp, C.POINTER(C.c_int64)]
     L.ffpic_record_sort.argtypes = [P, C.c_int]
     L.ffpic_set_graph.argtypes = [P, C.c_int]
+    L.ffpic_batch_set_graph.argtypes = [P, C.c_int]
+    L.ffpic_batch_graph_stats.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     L.ffpic_graph_stats.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     L.ffpic_diagnostics.argtypes = [P, C.c_uint32, C.POINTER(Diag), vp]
     L.ffpic_diagnostics_noalloc.argtypes = [P, C.c_uint32, C.POINTER(Diag), vp]
@@ -150,7 +152,8 @@ def lib():
                  "ffpic_batch_destroy", "ffpic_autotune", "ffpic_batch_autotune",
                  "ffpic_spectra", "ffpic_host_table", "ffpic_host_initial_field",
                  "ffpic_diagnostics_noalloc", "ffpic_set_field_rows", "ffpic_record_sort",
-                 "ffpic_set_graph", "ffpic_graph_stats"):
+                 "ffpic_set_graph", "ffpic_graph_stats", "ffpic_batch_set_graph",
+                 "ffpic_batch_graph_stats"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -462,6 +465,16 @@ class Batch:
 
     def sync(self):
         self._chk(lib().ffpic_batch_sync(self._h))
+
+    def set_graph(self, on: bool):
+        """Graph capture of whole batch cycles (ffpic_batch_set_graph)."""
+        self._chk(lib().ffpic_batch_set_graph(self._h, int(bool(on))))
+
+    def graph_stats(self):
+        """(graphs captured, graph launches) so far."""
+        b, l = C.c_int64(0), C.c_int64(0)
+        self._chk(lib().ffpic_batch_graph_stats(self._h, C.byref(b), C.byref(l)))
+        return b.value, l.value
 
     def autotune(self, budget_ms: float):
         t = (Tuning * len(self.views))()

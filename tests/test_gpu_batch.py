@@ -49,6 +49,48 @@ def descs(ws):
     return out
 
 
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_cycles_as_graphs_match_single_contexts(graph):
+    """Whole sort cycles of the batch as one graph (every system's launches
+    on its own branch), replayed from the state it was captured in, against
+    each system stepped alone one step at a time; between the replays the
+    views are read (synchronising work), and every replay is checked."""
+    ws = systems()
+    for w in ws:
+        w.sort_interval = 4
+    ds = descs(ws)
+    caps = [[w.n_per_species] * w.nspec for w in ws]
+    batch = ffpic.Batch(ds, caps)
+    batch.set_graph(graph)
+    singles = [ffpic.Sim(d, capacity=c) for d, c in zip(ds, caps)]
+    for w, v, s in zip(ws, batch.views, singles):
+        s.set_graph(False)
+        for sp in range(w.nspec):
+            p = w.particles(sp)
+            v.load_particles(sp, p)
+            s.load_particles(sp, p)
+    for rnd in range(4):
+        batch.step(4)
+        batch.sync()
+        for s in singles:
+            s.step(4)
+        for w, d, v, s in zip(ws, ds, batch.views, singles):
+            tol = 1e-12 if d["precision"] == W.FP64 else 1e-5
+            for g, _ in FIELDS:
+                assert rel(v.field(g), s.field(g)) < tol, (rnd, w.name, g)
+            dv, ds_ = v.diagnostics(ffpic.DIAG_MOMENTS), s.diagnostics(ffpic.DIAG_MOMENTS)
+            assert dv["alive"] == ds_["alive"], (rnd, w.name)
+            assert dv["step"] == ds_["step"] == 4 * (rnd + 1)
+    builds, launches = batch.graph_stats()
+    if graph:
+        assert launches == 4 and 1 <= builds <= 2, (builds, launches)
+    else:
+        assert (builds, launches) == (0, 0)
+    batch.close()
+    for s in singles:
+        s.close()
+
+
 def test_batch_matches_single_contexts_and_oracle():
     ws = systems()
     ds = descs(ws)
