@@ -21,6 +21,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -145,7 +146,7 @@ def roofline(precision, res, steps, nspec, copy_gbs):
             "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
 
 
-def batch_run(ffpic, W, steps, warmup, scale):
+def batch_run(ffpic, W, steps, warmup, scale, tune_ms=0.0):
     """The batched workload: 64 independent magnetospheres (grids 256^2 to
     1024^2, 1e6-1e7 particles each, FP32-mixed) stepped together through
     ffpic_batch_step; wall time around the batch step and a full sync."""
@@ -161,6 +162,25 @@ def batch_run(ffpic, W, steps, warmup, scale):
         for s in range(w.nspec):
             for c in range(w.n_chunks()):
                 v.load_particles(s, w.chunk(s, c))
+    tuned = None
+    cycle = 8
+    if tune_ms > 0:
+        # sort interval, push chunk and slab rows of every system, timed
+        # from its state after loading (and restored)
+        t = b.autotune(tune_ms)
+        tuned = {}
+        for key in ("sort_interval", "push_ppt", "field_rows"):
+            vals = [x[key] for x in t]
+            tuned[key] = {str(v): vals.count(v) for v in sorted(set(vals))}
+        tuned["ms"] = round(sum(x["total_ms"] for x in t), 1)
+        cycle = 1
+        for x in t:
+            cycle = cycle * x["sort_interval"] // math.gcd(cycle, x["sort_interval"])
+    # whole batch cycles (the least common multiple of the sort intervals):
+    # two to capture the graphs of both buffer parities, then the timed ones
+    warmup = max(warmup, 2 * cycle)
+    warmup = -(-warmup // cycle) * cycle
+    steps = -(-steps // cycle) * cycle
     b.step(warmup)
     b.sync()
     alive = lambda: sum(sum(v.diagnostics(ffpic.DIAG_MOMENTS)["alive"]) for v in b.views)
@@ -186,7 +206,7 @@ def batch_run(ffpic, W, steps, warmup, scale):
             "particle_steps_per_s": 0.5 * (n0 + n1) * steps / wall,
             "cell_updates_per_s": cells * steps / wall,
             "graphs": {"captured": g1[0] - g0[0], "launched": g1[1] - g0[1]},
-            "eager_ms_per_step": (t3 - t2) / steps * 1e3}
+            "eager_ms_per_step": (t3 - t2) / steps * 1e3, "tuned": tuned}
 
 
 def host_cpu():
@@ -271,8 +291,10 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2_000_000)
-    ap.add_argument("--batch", action="store_true",
-                    help="also time the batched workload (64 systems) and report it under 'batch'")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched workload (64 systems), reported under 'batch'")
+    ap.add_argument("--batch-tune-ms", type=float, default=30000.0,
+                    help="autotuning budget of the batch (all systems together), 0 = none")
     ap.add_argument("--batch-scale", type=float, default=1.0,
                     help="particle-count scale of the batched workload")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -362,9 +384,10 @@ def main():
                        "roofline": roofline(0, r64, args.steps, w.nspec, copy_gbs)}
         out["fp32_over_fp64"] = out["value"] / out["fp64"]["value"]
     sims[1].close()
-    if args.batch:
+    if not args.no_batch:
         log("timing the batched workload (64 systems)")
-        out["batch"] = batch_run(ffpic, W, args.steps, args.warmup, args.batch_scale)
+        out["batch"] = batch_run(ffpic, W, args.steps, args.warmup, args.batch_scale,
+                                 args.batch_tune_ms)
         log(f"  batch: {out['batch']['ms_per_step']:.3f} ms/step, "
             f"{out['batch']['particle_steps_per_s']:.3e} particle-steps/s")
     if not args.no_cpu_baseline:

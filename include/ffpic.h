@@ -117,7 +117,7 @@ typedef struct ffpic_desc {
     int32_t ff_enable;        /* 0: pure PIC (f = 0 everywhere) */
     int32_t precision;        /* enum ffpic_precision */
     int32_t init;             /* enum ffpic_init */
-    int32_t sort_interval;    /* >= 1; 0 = the tuned value (see ffpic_autotune) */
+    int32_t sort_interval;    /* >= 1; 0 = the tuned values (see ffpic_autotune) */
     int32_t nspec;            /* 0 .. FFPIC_MAX_SPECIES */
     int32_t pad_;
     int64_t capacity[FFPIC_MAX_SPECIES]; /* particle slots per species */
@@ -448,9 +448,10 @@ int ffpic_batch_step(ffpic_batch *b, int32_t nsteps);
 int ffpic_batch_sync(ffpic_batch *b);
 
 /* Graph capture of batch steps (on by default): when every system stands
-   at the start of a sort cycle of the same length and each could replay
-   its own cycle from a graph (see ffpic_set_graph), ffpic_batch_step runs
-   that cycle of all systems as one HIP graph, in which every system's
+   at the start of one of its sort cycles and each could replay its own
+   cycle from a graph (see ffpic_set_graph), ffpic_batch_step runs the
+   least common multiple of the systems' sort intervals (up to 64 steps) of
+   all systems as one HIP graph, in which every system's
    launches form their own chain on its stream's branch; captured once per
    host state of all systems and replayed afterwards.  Other steps are
    launched one by one.  Results do not depend on it. */
@@ -460,35 +461,50 @@ const char *ffpic_batch_last_error(const ffpic_batch *b);
 int ffpic_batch_destroy(ffpic_batch *b);
 
 /* ---------------------------------------------------------------------
- * Autotuning of the sort interval.
+ * Autotuning of the sort interval and the kernels' tile sizes.
  *
  * A sort costs one pass over all particle state.  Sorted particles make the
  * push's field gather and current deposit local.  The best interval depends
- * on the workload.  ffpic_autotune checkpoints the context to host memory
- * (as ffpic_save), times whole sort cycles of the candidate intervals
- * 8, 1, 2, 4, 16, 32 from that state, while the wall time stays within
- * budget_ms (the first candidate is always timed).  It then restores the
- * checkpoint and keeps the fastest interval.
+ * on the workload, and so do the tile sizes of the FP32 push (particles per
+ * thread of a workgroup's chunk, which sets how many particles share one
+ * field patch and one current patch) and of the fused field step (radial
+ * rows of a workgroup's slab, see ffpic_set_field_rows).  ffpic_autotune
+ * checkpoints the context to host memory (as ffpic_save) and, from that
+ * state, times whole sort cycles of each candidate, one parameter after the
+ * other, keeping the best value of each before trying the next:
+ *   1. the sort interval: 8, 4, 16, 2, 32, 1;
+ *   2. the field step's slab rows: 0 (automatic), 32, 64, 128, 16;
+ *   3. (FP32) the push's particles per thread: 16, 8, 32;
+ * while the wall time stays within budget_ms (the first candidate of each
+ * parameter is always timed).  It then restores the checkpoint and keeps
+ * the chosen values.
  *
- * The state after the call equals the state before it.  The interval only
- * reorders particles, so results change by the order of floating-point
- * atomic additions in the deposit and in no other way.
+ * The state after the call equals the state before it.  None of the
+ * parameters changes the arithmetic: results change by the order of
+ * floating-point atomic additions in the deposit and in no other way.
  *
  * If the environment variable FFPIC_TUNING_CACHE names a file, a line
- * "nr nth precision nspec slots interval" is appended to it.  ffpic_create
- * with sort_interval = 0 takes the last matching line (same nr, nth,
- * precision, nspec), else 8.
+ * "nr nth precision nspec slots interval rows ppt" is appended to it.
+ * ffpic_create with sort_interval = 0 takes the last matching line (same
+ * nr, nth, precision, nspec) for all three, else 8, 0 and 16.
  *
  * Errors: EINVAL for a non-positive budget; a context in error
  * (ffpic_sync fails) is not tuned.  ffpic_batch_autotune tunes every system
  * with an equal share of the budget and writes n entries to out.
  */
-#define FFPIC_TUNE_MAX 8
+#define FFPIC_TUNE_MAX 16
+enum ffpic_tune_kind {
+    FFPIC_TUNE_SORT_INTERVAL = 0,
+    FFPIC_TUNE_FIELD_ROWS = 1,
+    FFPIC_TUNE_PUSH_PPT = 2
+};
 typedef struct ffpic_tuning {
-    int32_t sort_interval;               /* the interval chosen (and now in use) */
+    int32_t sort_interval;               /* the values chosen (and now in use) */
+    int32_t field_rows;
+    int32_t push_ppt;                    /* 0 for FP64 contexts */
     int32_t ncand;                       /* candidates timed */
-    int32_t cand[FFPIC_TUNE_MAX];        /* their intervals */
-    int32_t pad_;
+    int32_t cand_kind[FFPIC_TUNE_MAX];   /* the parameter of each (ffpic_tune_kind) */
+    int32_t cand[FFPIC_TUNE_MAX];        /* its value */
     double ms_per_step[FFPIC_TUNE_MAX];  /* measured GPU time per step */
     double total_ms;                     /* wall time spent tuning */
 } ffpic_tuning;

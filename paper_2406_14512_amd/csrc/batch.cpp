@@ -13,11 +13,13 @@
 //
 // Autotune: the sort costs a pass over all particle state, while sorted
 // particles make the push's gather and deposit local; the best interval
-// depends on the workload.  The tuner checkpoints the context to host memory,
-// times whole sort cycles of each candidate interval from that same state,
-// restores the checkpoint and keeps the fastest interval.  The sort interval
-// only reorders particles, so the choice changes results by the order of
-// floating-point atomic additions in the deposit and nothing else.
+// depends on the workload, as do the push's chunk (particles per thread) and
+// the field step's slab height.  The tuner checkpoints the context to host
+// memory, times whole sort cycles of each candidate from that same state,
+// one parameter after the other, restores the checkpoint and keeps the
+// fastest values.  None of them changes the arithmetic, so the choice
+// changes results by the order of floating-point atomic additions in the
+// deposit and nothing else.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,6 +28,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <numeric>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -123,17 +126,20 @@ void release(ffpic_batch *b) {
     b->join.clear();
 }
 
-// A batch cycle (the common sort interval of all systems) can be a graph
-// when every system's next cycle can (see graphable_cycle) and all systems
-// stand at the start of a cycle.
+// A batch cycle (the least common multiple of the systems' sort intervals,
+// up to 64 steps) can be a graph when every system's next cycle can (see
+// graphable_cycle) and every system stands at the start of one of its own
+// cycles.
 int batch_cycle(const ffpic_batch *b) {
     if (!b->use_graph) return 0;
-    const int si = b->ctx[0]->d.sort_interval;
+    int64_t k = 1;
     for (ffpic_ctx *c : b->ctx) {
-        if (c->d.sort_interval != si || c->step % si != 0) return 0;
-        if (!ffpic::graphable_cycle(c)) return 0;
+        const int si = c->d.sort_interval;
+        if (si < 1 || c->step % si != 0 || !ffpic::graphable_cycle(c)) return 0;
+        k = k / std::gcd<int64_t>(k, si) * si;
+        if (k > 64) return 0;
     }
-    return si;
+    return (int)k;
 }
 
 bool same_states(const std::vector<ffpic::CycleState> &a, const std::vector<ffpic::CycleState> &b) {
@@ -251,6 +257,19 @@ double time_steps(ffpic_ctx *c, int steps) {
     return ms / steps;
 }
 
+// the three tuned settings of a context
+struct Setting {
+    int interval, rows, ppt;
+};
+
+Setting setting_of(const ffpic_ctx *c) { return {c->d.sort_interval, c->fused_rows, c->push_ppt}; }
+
+void apply(ffpic_ctx *c, const Setting &v) {
+    c->d.sort_interval = v.interval;
+    c->fused_rows = v.rows;
+    c->push_ppt = v.ppt;
+}
+
 void tune_one(ffpic_ctx *c, double budget_ms, ffpic_tuning *out) {
     auto t0 = std::chrono::steady_clock::now();
     auto elapsed_ms = [&] {
@@ -264,49 +283,75 @@ void tune_one(ffpic_ctx *c, double budget_ms, ffpic_tuning *out) {
     std::vector<char> ckpt(len);
     rc = ffpic_save(c, ckpt.data(), &len);
     if (rc != FFPIC_OK) throw BFail{rc, ffpic_last_error(c)};
-    const int32_t keep = c->d.sort_interval;
+    const Setting keep = setting_of(c);
     const int timing = c->timing;
     c->timing = 0;
     ffpic_tuning t{};
-    double best = 0;
+    Setting best = keep;
+    // one parameter after the other, the first candidate of each always
+    // timed; every candidate times whole sort cycles from the checkpoint
+    struct Param {
+        int kind;
+        std::vector<int> values;
+    };
+    std::vector<Param> params = {{FFPIC_TUNE_SORT_INTERVAL, {8, 4, 16, 2, 32, 1}},
+                                 {FFPIC_TUNE_FIELD_ROWS, {0, 32, 64, 128, 16}}};
+    if (!c->fp64) params.push_back({FFPIC_TUNE_PUSH_PPT, {16, 8, 32}});
     try {
-        // the default interval first, so a small budget still measures it
-        std::vector<int> order = {8, 1, 2, 4, 16, 32};
         double last_ms = 0;
-        for (int cand : order) {
-            if (t.ncand >= FFPIC_TUNE_MAX) break;
-            int steps = std::max(cand, 8);
-            if (t.ncand > 0 && elapsed_ms() + last_ms * steps * 1.5 > budget_ms) continue;
-            rc = ffpic_restore(c, ckpt.data(), len);
-            if (rc != FFPIC_OK) throw BFail{rc, ffpic_last_error(c)};
-            c->d.sort_interval = cand;
-            c->step = 0;              // the first timed step sorts
-            double ms = time_steps(c, steps);
-            t.cand[t.ncand] = cand;
-            t.ms_per_step[t.ncand] = ms;
-            t.ncand++;
-            last_ms = ms;
-            if (t.ncand == 1 || ms < best) { best = ms; t.sort_interval = cand; }
+        for (const Param &pm : params) {
+            double best_ms = 0;
+            bool first = true;
+            for (int v : pm.values) {
+                if (t.ncand >= FFPIC_TUNE_MAX) break;
+                Setting cand = best;
+                if (pm.kind == FFPIC_TUNE_SORT_INTERVAL) cand.interval = v;
+                if (pm.kind == FFPIC_TUNE_FIELD_ROWS) cand.rows = v;
+                if (pm.kind == FFPIC_TUNE_PUSH_PPT) cand.ppt = v;
+                // whole cycles, at least 8 steps
+                const int steps = cand.interval * std::max(1, (8 + cand.interval - 1) / cand.interval);
+                if (!first && elapsed_ms() + last_ms * steps * 1.5 > budget_ms) continue;
+                rc = ffpic_restore(c, ckpt.data(), len);
+                if (rc != FFPIC_OK) throw BFail{rc, ffpic_last_error(c)};
+                apply(c, cand);
+                c->step = 0;              // the first timed step sorts
+                const double ms = time_steps(c, steps);
+                t.cand_kind[t.ncand] = pm.kind;
+                t.cand[t.ncand] = v;
+                t.ms_per_step[t.ncand] = ms;
+                t.ncand++;
+                last_ms = ms;
+                if (first || ms < best_ms) {
+                    best_ms = ms;
+                    best = cand;
+                }
+                first = false;
+            }
         }
     } catch (...) {
         (void)ffpic_restore(c, ckpt.data(), len);
-        c->d.sort_interval = keep;
+        apply(c, keep);
         c->timing = timing;
         throw;
     }
     rc = ffpic_restore(c, ckpt.data(), len);
     c->timing = timing;
     if (rc != FFPIC_OK) {
-        c->d.sort_interval = keep;
+        apply(c, keep);
         throw BFail{rc, ffpic_last_error(c)};
     }
-    c->d.sort_interval = t.sort_interval;
+    apply(c, best);
+    t.sort_interval = best.interval;
+    t.field_rows = best.rows;
+    t.push_ppt = c->fp64 ? 0 : best.ppt;
     t.total_ms = elapsed_ms();
     if (out) *out = t;
     if (const char *path = std::getenv("FFPIC_TUNING_CACHE")) {
         if (*path) {
             std::ofstream f(path, std::ios::app);
-            if (f) f << cache_key(c) << ' ' << total_slots(c) << ' ' << t.sort_interval << '\n';
+            if (f)
+                f << cache_key(c) << ' ' << total_slots(c) << ' ' << best.interval << ' '
+                  << best.rows << ' ' << best.ppt << '\n';
         }
     }
 }
@@ -315,23 +360,29 @@ void tune_one(ffpic_ctx *c, double budget_ms, ffpic_tuning *out) {
 
 namespace ffpic {
 
-// sort interval for a descriptor that asks for the tuned one (0): the last
-// cache entry with the same grid, precision and species count, else 8
-int tuned_sort_interval(const ffpic_desc *d) {
-    int pick = 8;
+// settings for a descriptor that asks for the tuned ones (sort interval 0):
+// the last cache entry with the same grid, precision and species count,
+// else interval 8, automatic slab rows and 16 particles per thread
+void tuned_settings(const ffpic_desc *d, int *interval, int *rows, int *ppt) {
+    *interval = 8;
+    *rows = 0;
+    *ppt = 16;
     const char *path = std::getenv("FFPIC_TUNING_CACHE");
-    if (!path || !*path) return pick;
+    if (!path || !*path) return;
     std::ifstream f(path);
     std::string line;
     while (std::getline(f, line)) {
         std::istringstream in(line);
-        long nr, nth, prec, nspec, nslots, si;
+        long nr, nth, prec, nspec, nslots, si, rw = 0, pp = 16;
         if (!(in >> nr >> nth >> prec >> nspec >> nslots >> si)) continue;
+        if (!(in >> rw >> pp)) { rw = 0; pp = 16; }
         if (nr == d->nr && nth == d->nth && prec == d->precision && nspec == d->nspec && si >= 1 &&
-            si <= 1024)
-            pick = (int)si;
+            si <= 1024 && rw >= 0 && rw <= 4096 && (pp == 8 || pp == 16 || pp == 32)) {
+            *interval = (int)si;
+            *rows = (int)rw;
+            *ppt = (int)pp;
+        }
     }
-    return pick;
 }
 
 }  // namespace ffpic

@@ -69,7 +69,7 @@ struct CycleState {
     int sort_cur[FFPIC_MAX_SPECIES];
     bool sort_valid[FFPIC_MAX_SPECIES], perm_valid[FFPIC_MAX_SPECIES];
     void *E[3], *B[3], *J[3], *dE[3], *dB[3], *stAlt[6], *Jalt[3];
-    int fused_rows;                  // settings the launches depend on
+    int fused_rows, push_ppt;        // settings the launches depend on
     bool record_perm, incremental_sort;
 };
 
@@ -105,6 +105,7 @@ struct ffpic_ctx {
     void *stAlt[6] = {}, *Jalt[3] = {};
     bool rE0_zero[3] = {}, rB0_zero[3] = {};  // FP32: background rate identically zero
     int fused_rows = 0;                       // slab height (0 = from fused_slots)
+    int push_ppt = 16;                        // FP32 push: particles per thread (8, 16, 32)
     int fused_slots = 0;                      // workgroups resident on the GPU at once
     void *fz_rowc = nullptr, *fz_colc = nullptr;   // FP32 field step: row / column coefficients
     int device = 0;                           // HIP device the context was created on
@@ -234,7 +235,7 @@ int sort_key_bits(const ffpic_ctx *c);
 void exclusive_scan_i32(ffpic_ctx *c, const int32_t *in, int32_t *out, int64_t n);
 int64_t scan_part_len(int64_t n);
 void zero_counters(ffpic_ctx *c, int32_t *p, int n);
-int tuned_sort_interval(const ffpic_desc *d);
+void tuned_settings(const ffpic_desc *d, int *interval, int *rows, int *ppt);
 void inject_pairs(ffpic_ctx *c);
 void extract_gj(ffpic_ctx *c);
 void create_pairs(ffpic_ctx *c);

@@ -45,10 +45,10 @@
 namespace ffpic {
 
 constexpr int kWG = 256;
-// particles per thread per chunk: a chunk of 4096 sorted particles spans few
-// cells, so its patches' load and flush are spread over many particles
-constexpr int kPPT = 16;
-constexpr int kChunk = kWG * kPPT;
+// particles per thread per chunk (a template parameter, chosen by the
+// autotuner among 8, 16 and 32; 16 by default): a chunk of 4096 sorted
+// particles spans few cells, so its patches' load and flush are spread over
+// many particles
 constexpr int kTile = 1024;              // LDS deposit patch entries per component
 constexpr int kFld = 512;                // LDS field patch nodes (six components each)
 constexpr int kQueue = 64;               // queued cell-crossing moves per workgroup
@@ -210,7 +210,7 @@ struct Patch {
     unsigned rowB;       // bytes per patch row (24 per node)
 };
 
-template <bool LDS, bool SHELL>
+template <bool LDS, bool SHELL, int kPPT>
 __device__ __forceinline__ void push_chunk(const P32 &p, const Fields &F, const Patch &P,
                                            const Acc<LDS> &acc,
                                            int n, int base, int tid, int lane,
@@ -524,7 +524,7 @@ __device__ __forceinline__ void push_chunk(const P32 &p, const Fields &F, const 
 }
 
 // six waves per SIMD: the prefetched momentum fits in 80 VGPRs without spills
-template <bool SHELL>
+template <bool SHELL, int kPPT>
 __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(6, 8))) k_push32(
     P32 p, int nub, const int32_t *__restrict__ nslots, const uint8_t *__restrict__ kill,
     const float *__restrict__ Er, const float *__restrict__ Et, const float *__restrict__ Ep,
@@ -541,6 +541,7 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(6, 8))
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int n = min(nub, nslots[0]);
+    constexpr int kChunk = kWG * kPPT;
     const int base = blockIdx.x * kChunk;
     // slots are below 2^30 (the capacity limit), so the byte offset q * 4
     // fits 32 unsigned bits
@@ -604,7 +605,7 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(6, 8))
         __syncthreads();
         const Patch P{fld, fi0, fj0, (unsigned)TJf * 24u};
         Acc<true> acc{tile, ti0, tj0, TJ, {Jr, Jt, Jp}, p.ld};
-        push_chunk<true, SHELL>(p, Fields{}, P, acc, n, base, tid, lane, kill, S, err, nkill, nstar,
+        push_chunk<true, SHELL, kPPT>(p, Fields{}, P, acc, n, base, tid, lane, kill, S, err, nkill, nstar,
                                 nabs, queue, &qn, nullptr);
         __syncthreads();
         for (int e = tid; e < m; e += kWG) {
@@ -632,7 +633,7 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(6, 8))
         Acc<false> acc{nullptr, 0, 0, 0, {Jr, Jt, Jp}, p.ld};
         const int kc = lane_comp(lane);
         float *kg = kc == 0 ? Jr : (kc == 1 ? Jt : Jp);
-        push_chunk<false, SHELL>(p, F, Patch{nullptr, 0, 0, 0u}, acc, n, base, tid, lane, kill, S, err, nkill, nstar,
+        push_chunk<false, SHELL, kPPT>(p, F, Patch{nullptr, 0, 0, 0u}, acc, n, base, tid, lane, kill, S, err, nkill, nstar,
                                  nabs, queue, &qn, kg);
     }
     int tk = nkill, ts = nstar, ta = nabs;
@@ -672,8 +673,12 @@ void push32(ffpic_ctx *c, int s) {
     p.ishell = (int)floor(xs);
     p.ashell = (float)(xs - floor(xs));
     float **E = (float **)c->E, **B = (float **)c->B, **J = (float **)c->J;
-    int nb = (int)((S.nub + kChunk - 1) / kChunk);
-    auto kern = shell ? k_push32<true> : k_push32<false>;
+    const int ppt = c->push_ppt == 8 || c->push_ppt == 32 ? c->push_ppt : 16;
+    const int chunk = kWG * ppt;
+    int nb = (int)((S.nub + chunk - 1) / chunk);
+    auto kern = ppt == 8 ? (shell ? k_push32<true, 8> : k_push32<false, 8>)
+              : ppt == 32 ? (shell ? k_push32<true, 32> : k_push32<false, 32>)
+                          : (shell ? k_push32<true, 16> : k_push32<false, 16>);
     hipLaunchKernelGGL(kern, dim3(nb), dim3(kWG), 0, c->stream, p, (int)S.nub,
                        c->nslots + s, c->kill, E[0], E[1], E[2], B[0], B[1], B[2],
                        (int32_t *)S.cur[0], (float *)S.cur[1], (float *)S.cur[2],

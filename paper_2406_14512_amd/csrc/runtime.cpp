@@ -575,6 +575,7 @@ CycleState cycle_state(const ffpic_ctx *c) {
     }
     for (int k = 0; k < 6; k++) st.stAlt[k] = c->stAlt[k];
     st.fused_rows = c->fused_rows;
+    st.push_ppt = c->push_ppt;
     st.record_perm = c->record_perm;
     st.incremental_sort = c->incremental_sort;
     return st;
@@ -765,7 +766,13 @@ int ffpic_create(const ffpic_desc *d, void *stream, ffpic_ctx **out) {
         c->stream = (hipStream_t)stream;
         HCHK(hipGetDevice(&c->device));
         setup_geometry(c, d);
-        if (c->d.sort_interval == 0) c->d.sort_interval = tuned_sort_interval(d);
+        if (c->d.sort_interval == 0) {
+            int si, rows, ppt;
+            tuned_settings(d, &si, &rows, &ppt);
+            c->d.sort_interval = si;
+            c->fused_rows = rows;
+            c->push_ppt = ppt;
+        }
         {   // first row where the absorber's factor (in working precision) is below 1
             auto below1 = [&](double v) { return c->fp64 ? v != 1.0 : (float)v != 1.0f; };
             c->absorb_row0 = c->nr + 1;

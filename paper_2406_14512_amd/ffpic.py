@@ -71,19 +71,25 @@ class SpectraReq(C.Structure):
                 ("ngamma", C.c_int32), ("nnu", C.c_int32)]
 
 
-TUNE_MAX = 8
+TUNE_MAX = 16
 
 
 class Tuning(C.Structure):
-    _fields_ = [("sort_interval", C.c_int32), ("ncand", C.c_int32),
-                ("cand", C.c_int32 * TUNE_MAX), ("pad_", C.c_int32),
+    _fields_ = [("sort_interval", C.c_int32), ("field_rows", C.c_int32),
+                ("push_ppt", C.c_int32), ("ncand", C.c_int32),
+                ("cand_kind", C.c_int32 * TUNE_MAX), ("cand", C.c_int32 * TUNE_MAX),
                 ("ms_per_step", C.c_double * TUNE_MAX), ("total_ms", C.c_double)]
+
+    KINDS = ("sort_interval", "field_rows", "push_ppt")
 
     def as_dict(self) -> Dict:
         n = self.ncand
-        return {"sort_interval": self.sort_interval,
-                "ms_per_step": {int(self.cand[k]): float(self.ms_per_step[k]) for k in range(n)},
-                "total_ms": float(self.total_ms)}
+        timed = {k: {} for k in self.KINDS}
+        for k in range(n):
+            timed[self.KINDS[self.cand_kind[k]]][int(self.cand[k])] = float(self.ms_per_step[k])
+        return {"sort_interval": self.sort_interval, "field_rows": self.field_rows,
+                "push_ppt": self.push_ppt, "ms_per_step": timed["sort_interval"],
+                "timed": timed, "total_ms": float(self.total_ms)}
 
 
 _lib = None

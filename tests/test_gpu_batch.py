@@ -161,9 +161,12 @@ def test_autotune_keeps_state_and_semantics(tmp_path, monkeypatch):
     assert t["sort_interval"] in t["ms_per_step"]
     assert 8 in t["ms_per_step"] and len(t["ms_per_step"]) >= 1
     assert all(v > 0 for v in t["ms_per_step"].values())
+    # the slab rows were tuned after the interval (FP64: no push chunk)
+    assert 0 in t["timed"]["field_rows"] and t["field_rows"] in t["timed"]["field_rows"]
+    assert t["push_ppt"] == 0 and not t["timed"]["push_ppt"]
     line = cache.read_text().split()
     assert line[:4] == [str(w.nr), str(w.nth), "0", str(w.nspec)]
-    assert int(line[5]) == t["sort_interval"]
+    assert int(line[5]) == t["sort_interval"] and int(line[6]) == t["field_rows"]
     # stepping on with the tuned interval matches the oracle (which sorts
     # every step): the interval only reorders particles
     sim.step(4)
@@ -185,3 +188,33 @@ def test_autotune_keeps_state_and_semantics(tmp_path, monkeypatch):
     sim.close()
     with pytest.raises(ffpic.FfpicError):
         ffpic.Sim(d, capacity=[10, 10]).autotune(0.0)
+
+
+def test_autotune_fp32_tunes_the_push_chunk():
+    """FP32-mixed: all three parameters are timed, the state is unchanged,
+    and stepping on with the chosen chunk and slab height matches a context
+    that keeps the defaults (only the order of atomic additions differs)."""
+    w = W.sheet_1024(n_total=60000, precision=W.FP32_MIXED)
+    w.nr = w.nth = 192
+    d = w.desc()
+    d["precision"] = W.FP32_MIXED
+    sims = [ffpic.Sim(d, capacity=[w.n_per_species] * w.nspec) for _ in range(2)]
+    for sim in sims:
+        for sp in range(w.nspec):
+            sim.load_particles(sp, w.particles(sp))
+        sim.step(3)
+    before = snapshot(sims[0], w.nspec)
+    t = sims[0].autotune(5000.0)
+    after = snapshot(sims[0], w.nspec)
+    for a, b in zip(before[0], after[0]):
+        assert np.array_equal(a, b)
+    assert t["push_ppt"] in (8, 16, 32) and 16 in t["timed"]["push_ppt"]
+    assert t["field_rows"] in t["timed"]["field_rows"]
+    # both on the tuned interval, one with the defaults for the rest
+    sims[1]._chk(ffpic.lib().ffpic_set_field_rows(sims[1]._h, 0))
+    for sim in sims:
+        sim.step(8)
+    for g, _ in FIELDS:
+        assert rel(sims[0].field(g), sims[1].field(g)) < 1e-5, g
+    for sim in sims:
+        sim.close()
