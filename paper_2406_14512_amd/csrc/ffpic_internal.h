@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/ffpic.h"
+#include "sort_view.h"
 
 namespace ffpic {
 
@@ -134,22 +135,27 @@ struct ffpic_ctx {
     uint8_t *kill = nullptr;
     ffpic::Species sp[FFPIC_MAX_SPECIES];
     uint32_t *keys[2] = {}, *vals[2] = {};
-    // incremental re-sort: per species the sorted keys and cell offsets of
-    // the last sort (double-buffered), plus shared scratch
-    uint32_t *skey[FFPIC_MAX_SPECIES][2] = {};
+    // incremental re-sort: per species the cell offsets of the last sort
+    // (double-buffered), plus shared scratch
     int32_t *soff[FFPIC_MAX_SPECIES][2] = {};
     int sort_cur[FFPIC_MAX_SPECIES] = {};
     bool sort_valid[FFPIC_MAX_SPECIES] = {};
     bool incremental_sort = true;
-    uint64_t *sort_smask = nullptr, *sort_mmask = nullptr;   // stayer / mover bits [cap/64 + 1]
-    uint32_t *sort_wsm = nullptr;             // counts before each word in its tile
-    uint2 *sort_tc = nullptr, *sort_ts = nullptr, *sort_gs = nullptr;   // tile / group counts
+    // per species (see sort_alloc): class words, counts, key offsets of the
+    // stayers, the movers' places
+    uint64_t *sort_smask[FFPIC_MAX_SPECIES] = {}, *sort_mmask[FFPIC_MAX_SPECIES] = {};   // [cap/64 + 1]
+    uint32_t *sort_wsm[FFPIC_MAX_SPECIES] = {};   // counts before each word in its tile
+    uint2 *sort_tc[FFPIC_MAX_SPECIES] = {}, *sort_ts[FFPIC_MAX_SPECIES] = {},
+          *sort_gs[FFPIC_MAX_SPECIES] = {};   // tile / group counts
     uint32_t *sort_aux = nullptr;             // sorted mover slots [cap]
-    int32_t *sort_mst = nullptr;              // movers before each key's stayers [nr*nth + 1]
+    int32_t *sort_mst[FFPIC_MAX_SPECIES] = {};   // movers before each key's stayers [nr*nth + 1]
     int32_t *sort_kcnt = nullptr;             // movers per key, zero between sorts [nr*nth + 1]
     void *sort_cbuf = nullptr;                // movers' state, compacted [narr * cbuf_n]
     int64_t sort_cbuf_n = 0;
-    uint32_t *sort_tot = nullptr;             // stayers, movers
+    uint32_t *sort_tot[FFPIC_MAX_SPECIES] = {};  // stayers, movers, slots before the sort
+    int32_t *sort_dest[FFPIC_MAX_SPECIES] = {};   // FP32: place of each slot's particle [cap]
+    bool sort_pending[FFPIC_MAX_SPECIES] = {};   // the next push places the sort
+    ffpic::SortPlace place[FFPIC_MAX_SPECIES] = {};
     uint32_t *rs_hist = nullptr, *rs_dtot = nullptr;   // radix sort: digit counts per tile
     int rs_stride = 0;                        // tiles per digit row of rs_hist
     int32_t *rs_n = nullptr;                  // radix sort: pair count (device)
@@ -191,7 +197,9 @@ Geo<R> geo(const ffpic_ctx *c);
 
 // kernels (launchers); all enqueue on c->stream
 void psi_mask(ffpic_ctx *c);
-void sort_species(ffpic_ctx *c, int s);           // kill + stable sort by cell
+// kill + stable sort by cell; with defer (FP32, incremental sorts) the
+// particles are placed in the new order by the species' next push
+void sort_species(ffpic_ctx *c, int s, bool defer = false);
 void kill_species(ffpic_ctx *c, int s);           // kill without sorting
 void push_species(ffpic_ctx *c, int s);
 void field_step(ffpic_ctx *c);

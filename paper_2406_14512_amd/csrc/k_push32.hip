@@ -210,13 +210,14 @@ struct Patch {
     unsigned rowB;       // bytes per patch row (24 per node)
 };
 
-template <bool LDS, bool SHELL, int kPPT>
+template <bool LDS, bool SHELL, int kPPT, bool PLACE>
 __device__ __forceinline__ void push_chunk(const P32 &p, const Fields &F, const Patch &P,
                                            const Acc<LDS> &acc,
                                            int n, int base, int tid, int lane,
                                            const uint8_t *__restrict__ kill, const State &S,
                                            uint32_t *__restrict__ err, int &nkill, int &nstar,
-                                           int &nabs, float4 *queue, int *qn, float *kg) {
+                                           int &nabs, float4 *queue, int *qn, float *kg,
+                                           const SortPlace &SP) {
     const int ld = p.ld, nth = p.nth;
     const unsigned ld4 = (unsigned)ld << 2;
     // the next particle's offsets and momentum are loaded one iteration
@@ -232,10 +233,11 @@ __device__ __forceinline__ void push_chunk(const P32 &p, const Fields &F, const 
     const int kdj = (kq == 1 || kq == 6 || kq == 7) ? 1 : 0;
     const bool row_lead = (lane & 8) == 0;
     float an = 0.f, bn = 0.f, urn = 0.f, utn = 0.f, upn = 0.f;
-    int cn = -1;
+    int cn = -1, dn = -1;
     if (base + tid < n) {
         const unsigned q0 = (unsigned)(base + tid);
         cn = S.ldc(q0);
+        if (PLACE) dn = ldo(SP.dest, q0);
         an = State::ld(S.a, q0);
         bn = State::ld(S.b, q0);
         urn = State::ld(S.ur, q0);
@@ -246,12 +248,16 @@ __device__ __forceinline__ void push_chunk(const P32 &p, const Fields &F, const 
     for (int k = 0; k < kPPT; k++) {
         const unsigned q = (unsigned)(base + k * kWG + tid);
         const int c = cn;
-        const bool live = c >= 0;
+        bool live = c >= 0;
         const int i = c >> 16, j = c & 0xffff;
+        // PLACE: the slot's place in the new order (-1: no particle of it)
+        const int dq = dn;
+        if (PLACE) live = live && dq >= 0;
         const float a = an, b = bn, ur = urn, ut = utn, up = upn;
         cn = -1;
         if (k + 1 < kPPT && (int)(q + kWG) < n) {
             cn = S.ldc(q + kWG);
+            if (PLACE) dn = ldo(SP.dest, q + kWG);
             an = State::ld(S.a, q + kWG);
             bn = State::ld(S.b, q + kWG);
             urn = State::ld(S.ur, q + kWG);
@@ -423,13 +429,25 @@ __device__ __forceinline__ void push_chunk(const P32 &p, const Fields &F, const 
             if (cfl && !killed) atomicOr(err, FFPIC_ERR_CFL);
             // non-finite state is flagged in the error word and never deposited
             if (!finite && !killed) atomicOr(err, FFPIC_ERR_NONFINITE);
-            S.stc(q, keep ? ((i2 << 16) | j2) : -1);
-            if (keep) {
-                State::st(S.a, q, na);
-                State::st(S.b, q, nb);
-                State::st(S.ur, q, rx * st2 + rz * ct2);
-                State::st(S.ut, q, rx * ct2 - rz * st2);
-                State::st(S.up, q, ry);
+            if (PLACE) {
+                const unsigned d = (unsigned)dq;
+                sto(SP.cell, d, keep ? ((i2 << 16) | j2) : -1);
+                if (keep) {
+                    sto(SP.a, d, na);
+                    sto(SP.b, d, nb);
+                    sto(SP.ur, d, rx * st2 + rz * ct2);
+                    sto(SP.ut, d, rx * ct2 - rz * st2);
+                    sto(SP.up, d, ry);
+                }
+            } else {
+                S.stc(q, keep ? ((i2 << 16) | j2) : -1);
+                if (keep) {
+                    State::st(S.a, q, na);
+                    State::st(S.b, q, nb);
+                    State::st(S.ur, q, rx * st2 + rz * ct2);
+                    State::st(S.ut, q, rx * ct2 - rz * st2);
+                    State::st(S.up, q, ry);
+                }
             }
             x1 = a; y1 = b;
             x2 = (float)di + na;
@@ -524,7 +542,7 @@ __device__ __forceinline__ void push_chunk(const P32 &p, const Fields &F, const 
 }
 
 // six waves per SIMD: the prefetched momentum fits in 80 VGPRs without spills
-template <bool SHELL, int kPPT>
+template <bool SHELL, int kPPT, bool PLACE>
 __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(6, 8))) k_push32(
     P32 p, int nub, const int32_t *__restrict__ nslots, const uint8_t *__restrict__ kill,
     const float *__restrict__ Er, const float *__restrict__ Et, const float *__restrict__ Ep,
@@ -532,7 +550,7 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(6, 8))
     int32_t *__restrict__ CELL, float *__restrict__ A, float *__restrict__ Bo,
     float *__restrict__ UR, float *__restrict__ UT, float *__restrict__ UP,
     float *__restrict__ Jr, float *__restrict__ Jt, float *__restrict__ Jp,
-    unsigned long long *__restrict__ removed, uint32_t *__restrict__ err) {
+    unsigned long long *__restrict__ removed, uint32_t *__restrict__ err, SortPlace SP) {
     __shared__ float tile[3 * kTile];
     __shared__ float fld[6 * kFld];
     __shared__ float4 queue[2 * kQueue];
@@ -540,7 +558,9 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(6, 8))
     __shared__ int qn;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int n = min(nub, nslots[0]);
+    // PLACE: the slots before the sort (the slot count already holds the
+    // new order's)
+    const int n = min(nub, nslots[PLACE ? 2 : 0]);
     constexpr int kChunk = kWG * kPPT;
     const int base = blockIdx.x * kChunk;
     // slots are below 2^30 (the capacity limit), so the byte offset q * 4
@@ -605,8 +625,8 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(6, 8))
         __syncthreads();
         const Patch P{fld, fi0, fj0, (unsigned)TJf * 24u};
         Acc<true> acc{tile, ti0, tj0, TJ, {Jr, Jt, Jp}, p.ld};
-        push_chunk<true, SHELL, kPPT>(p, Fields{}, P, acc, n, base, tid, lane, kill, S, err, nkill, nstar,
-                                nabs, queue, &qn, nullptr);
+        push_chunk<true, SHELL, kPPT, PLACE>(p, Fields{}, P, acc, n, base, tid, lane, kill, S, err, nkill, nstar,
+                                nabs, queue, &qn, nullptr, SP);
         __syncthreads();
         for (int e = tid; e < m; e += kWG) {
             const int ti = e / TJ, tj = e - ti * TJ;
@@ -633,8 +653,8 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(6, 8))
         Acc<false> acc{nullptr, 0, 0, 0, {Jr, Jt, Jp}, p.ld};
         const int kc = lane_comp(lane);
         float *kg = kc == 0 ? Jr : (kc == 1 ? Jt : Jp);
-        push_chunk<false, SHELL, kPPT>(p, F, Patch{nullptr, 0, 0, 0u}, acc, n, base, tid, lane, kill, S, err, nkill, nstar,
-                                 nabs, queue, &qn, kg);
+        push_chunk<false, SHELL, kPPT, PLACE>(p, F, Patch{nullptr, 0, 0, 0u}, acc, n, base, tid, lane, kill, S, err, nkill, nstar,
+                                 nabs, queue, &qn, kg, SP);
     }
     int tk = nkill, ts = nstar, ta = nabs;
     for (int o = 32; o >= 1; o >>= 1) {
@@ -676,15 +696,34 @@ void push32(ffpic_ctx *c, int s) {
     const int ppt = c->push_ppt == 8 || c->push_ppt == 32 ? c->push_ppt : 16;
     const int chunk = kWG * ppt;
     int nb = (int)((S.nub + chunk - 1) / chunk);
-    auto kern = ppt == 8 ? (shell ? k_push32<true, 8> : k_push32<false, 8>)
-              : ppt == 32 ? (shell ? k_push32<true, 32> : k_push32<false, 32>)
-                          : (shell ? k_push32<true, 16> : k_push32<false, 16>);
+    // after a sort whose placement was left to this push, it reads the old
+    // order and writes the new one into the second buffer
+    const bool place = c->sort_pending[s];
+    using Kern = decltype(&k_push32<false, 16, false>);
+    Kern kern;
+    if (place)
+        kern = ppt == 8 ? (shell ? k_push32<true, 8, true> : k_push32<false, 8, true>)
+             : ppt == 32 ? (shell ? k_push32<true, 32, true> : k_push32<false, 32, true>)
+                         : (shell ? k_push32<true, 16, true> : k_push32<false, 16, true>);
+    else
+        kern = ppt == 8 ? (shell ? k_push32<true, 8, false> : k_push32<false, 8, false>)
+             : ppt == 32 ? (shell ? k_push32<true, 32, false> : k_push32<false, 32, false>)
+                         : (shell ? k_push32<true, 16, false> : k_push32<false, 16, false>);
+    SortPlace sp{};
+    if (place) sp = c->place[s];
+    // the placing push runs over the slots before the sort: the third
+    // entry of the sort's totals
+    const int32_t *nsl = place ? (const int32_t *)c->sort_tot[s] : c->nslots + s;
     hipLaunchKernelGGL(kern, dim3(nb), dim3(kWG), 0, c->stream, p, (int)S.nub,
-                       c->nslots + s, c->kill, E[0], E[1], E[2], B[0], B[1], B[2],
+                       nsl, c->kill, E[0], E[1], E[2], B[0], B[1], B[2],
                        (int32_t *)S.cur[0], (float *)S.cur[1], (float *)S.cur[2],
                        (float *)S.cur[3], (float *)S.cur[4], (float *)S.cur[5], J[0], J[1], J[2],
-                       c->removed + 4 * s, c->err);
+                       c->removed + 4 * s, c->err, sp);
     FFPIC_LAUNCH_CHECK();
+    if (place) {
+        for (int a = 0; a < S.narr; a++) std::swap(S.cur[a], S.alt[a]);
+        c->sort_pending[s] = false;
+    }
 }
 
 }  // namespace ffpic

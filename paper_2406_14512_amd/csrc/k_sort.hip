@@ -20,10 +20,12 @@
 // change cell, so only those are sorted:
 //   * a slot holds a "stayer" if its particle's key equals the key the slot
 //     had at the last sort, a "mover" otherwise (dead slots and killed
-//     particles drop out); the stayers are already in (key, slot) order;
+//     particles drop out); the stayers are already in (key, slot) order.
+//     The key a slot had is read off that sort's cell offsets: it is the
+//     key whose range [OFF[k], OFF[k+1]) holds the slot;
 //   * the classify pass writes one stayer and one mover bit per slot (a
 //     64-bit word per 64 slots, from a wave ballot), the counts of both
-//     before each word inside its tile of 1024 slots, and the tile's movers
+//     before each word inside its tile of 2048 slots, and the tile's movers
 //     (key, slot) compacted inside the tile; two small scans turn the tile
 //     counts into exclusive prefixes, so SB(x), the stayers before slot x,
 //     and MB(x), the movers before x, are a few loads and a popcount;
@@ -48,12 +50,13 @@
 #include <cstring>
 
 #include "device_common.h"
+#include "sort_view.h"
 
 namespace ffpic {
 
-constexpr int kTile = 1024;                 // slots per classify tile
+constexpr int kTile = 1 << kTileShift;      // slots per classify tile (8 per thread)
 constexpr int kTileWords = kTile / 64;      // 64-slot words per tile
-constexpr int kGroup = 1024;                // tiles per group of the tile scan
+constexpr int kGroup = 1 << kGroupShift;    // tiles per group of the tile scan
 constexpr int kRsItems = 16;                // pairs per thread of a radix tile
 constexpr int kRsTile = 256 * kRsItems;     // pairs per radix tile
 constexpr int kMoverBlocks = 8192;          // blocks of the passes over the movers
@@ -454,21 +457,31 @@ int sort_key_bits(const ffpic_ctx *c) {
     return bits;
 }
 
-// device scratch of the sort for species of up to cap slots
-void sort_alloc(ffpic_ctx *c, int64_t cap, void *(*dmalloc)(size_t)) {
-    const int64_t nw = (cap + 63) / 64 + 1;
-    const int64_t nt = (cap + kTile - 1) / kTile + 1;
-    const int64_t ng = (nt + kGroup - 1) / kGroup + 1;
-    c->sort_smask = (uint64_t *)dmalloc((size_t)nw * 8);
-    c->sort_mmask = (uint64_t *)dmalloc((size_t)nw * 8);
-    c->sort_wsm = (uint32_t *)dmalloc((size_t)nw * 4);
-    c->sort_tc = (uint2 *)dmalloc((size_t)nt * 8);
-    c->sort_ts = (uint2 *)dmalloc((size_t)nt * 8);
-    c->sort_gs = (uint2 *)dmalloc((size_t)ng * 8);
-    c->rs_stride = (int)std::max<int64_t>(1, (cap + kRsTile - 1) / kRsTile);
+// device scratch of the sort: shared by the species where a sort uses it
+// only while it runs (radix histograms, count), per species where a
+// placement left to the push still needs it after the sort (class words
+// and counts, the key offsets of the stayers, the movers' places)
+void sort_alloc(ffpic_ctx *c, int64_t maxcap, void *(*dmalloc)(size_t)) {
+    c->rs_stride = (int)std::max<int64_t>(1, (maxcap + kRsTile - 1) / kRsTile);
     c->rs_hist = (uint32_t *)dmalloc((size_t)256 * c->rs_stride * 4);
     c->rs_dtot = (uint32_t *)dmalloc(256 * 4);
     c->rs_n = (int32_t *)dmalloc(4);
+    const size_t nk1 = (size_t)c->nr * c->nth + 1;
+    for (int s = 0; s < c->d.nspec; s++) {
+        const int64_t cap = std::max<int64_t>(c->sp[s].cap, 1);
+        const int64_t nw = (cap + 63) / 64 + 1;
+        const int64_t nt = (cap + kTile - 1) / kTile + 1;
+        const int64_t ng = (nt + kGroup - 1) / kGroup + 1;
+        c->sort_smask[s] = (uint64_t *)dmalloc((size_t)nw * 8);
+        c->sort_mmask[s] = (uint64_t *)dmalloc((size_t)nw * 8);
+        c->sort_wsm[s] = (uint32_t *)dmalloc((size_t)nw * 4);
+        c->sort_tc[s] = (uint2 *)dmalloc((size_t)nt * 8);
+        c->sort_ts[s] = (uint2 *)dmalloc((size_t)nt * 8);
+        c->sort_gs[s] = (uint2 *)dmalloc((size_t)ng * 8);
+        c->sort_tot[s] = (uint32_t *)dmalloc(4 * 4);
+        c->sort_mst[s] = (int32_t *)dmalloc(nk1 * 4);
+        if (!c->fp64) c->sort_dest[s] = (int32_t *)dmalloc((size_t)cap * 4);
+    }
 }
 
 static void key_pass(ffpic_ctx *c, int s, uint32_t dead, bool with_vals = true) {
@@ -553,39 +566,12 @@ __global__ void k_offsets_dev(const int32_t *__restrict__ nalive, const uint32_t
 // ---------------------------------------------------------------------------
 // incremental re-sort
 
-// where the classify pass leaves its counts
-struct ClassView {
-    int nub;
-    const uint64_t *smask, *mmask;   // stayer / mover bit per slot
-    const uint32_t *wsm;             // stayers | movers << 16 before the word, in its tile
-    const uint2 *ts;                 // stayers / movers before the tile, in its group
-    const uint2 *gs;                 // stayers / movers before the group
-    const uint32_t *tot;             // stayers, movers
-};
-
-// stayers before slot x (0 <= x <= nub)
-__device__ __forceinline__ uint32_t stayers_before(const ClassView &V, int x) {
-    if (x >= V.nub) return V.tot[0];
-    const int wd = x >> 6;
-    const uint64_t below = (1ull << (x & 63)) - 1ull;
-    return V.gs[x >> 20].x + V.ts[x >> 10].x + (V.wsm[wd] & 0xffffu) +
-           (uint32_t)__popcll(V.smask[wd] & below);
-}
-
-// movers before slot x (0 <= x < nub)
-__device__ __forceinline__ uint32_t movers_before(const ClassView &V, int x) {
-    const int wd = x >> 6;
-    const uint64_t below = (1ull << (x & 63)) - 1ull;
-    return V.gs[x >> 20].y + V.ts[x >> 10].y + (V.wsm[wd] >> 16) +
-           (uint32_t)__popcll(V.mmask[wd] & below);
-}
-
 struct ClassArgs {
     int nub, nth, nr;
     uint32_t dead;
     const int32_t *nslots, *nsorted;
     const uint8_t *kill;
-    const uint32_t *kold;                       // sorted keys of the last sort
+    const int32_t *offold;                      // cell offsets of the last sort
     unsigned long long *removed;
     // FP32 state: the cell; FP64 state: r, theta and the geometry
     int32_t *cell;
@@ -596,8 +582,19 @@ struct ClassArgs {
     uint64_t *smask, *mmask;
     uint32_t *wsm;
     uint2 *tc;                                  // stayers, movers of each tile
+    uint32_t *tot;                              // [2]: the slot count before the sort
     uint32_t *tkey, *tval;                      // movers of each tile, compacted in it
 };
+
+// The key a slot had at the last sort is the one whose range of that
+// sort's cell offsets holds the slot: a particle keeps its key since then
+// exactly when its slot lies in [OFF[key], OFF[key+1]).  Two reads of the
+// per-key offsets instead of a stored key per slot (sorted particles of a
+// wave mostly share a key, so the reads share cache lines).
+__device__ __forceinline__ bool in_old_range(const int32_t *__restrict__ off, uint32_t key, int q,
+                                             int nold) {
+    return q < nold && off[key] <= q && q < off[key + 1];
+}
 
 // key of every slot, the removal of killed particles, the class bits and
 // counts, and the movers of the tile compacted in slot order
@@ -607,16 +604,15 @@ __global__ void __launch_bounds__(256) k_classify(ClassArgs A) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int base = blockIdx.x * kTile;
     const int ns = A.nslots[0], no = A.nsorted[0];
+    if (blockIdx.x == 0 && tid == 0) A.tot[2] = (uint32_t)ns;   // for a push that places
     uint32_t key[K];
     int cl[K];
     if (!FP64) {
         int cell[K];
-        uint32_t ko[K];
 #pragma unroll
         for (int k = 0; k < K; k++) {
             const int q = base + k * 256 + tid;
             cell[k] = q < ns ? A.cell[q] : -1;
-            ko[k] = q < no ? A.kold[q] : A.dead;
         }
 #pragma unroll
         for (int k = 0; k < K; k++) {
@@ -632,7 +628,7 @@ __global__ void __launch_bounds__(256) k_classify(ClassArgs A) {
                     A.cell[q] = -1;
                 } else {
                     key[k] = (uint32_t)i * (uint32_t)A.nth + (uint32_t)j;
-                    cl[k] = key[k] >= A.dead ? 0 : (key[k] == ko[k] ? 1 : 2);
+                    cl[k] = key[k] >= A.dead ? 0 : (in_old_range(A.offold, key[k], q, no) ? 1 : 2);
                 }
             }
             count_wave(&A.removed[1], killed);
@@ -660,7 +656,7 @@ __global__ void __launch_bounds__(256) k_classify(ClassArgs A) {
                 }
             }
             if (q < A.nub) A.keys[q] = key[k];
-            if (key[k] < A.dead) cl[k] = (q < no && A.kold[q] == key[k]) ? 1 : 2;
+            if (key[k] < A.dead) cl[k] = in_old_range(A.offold, key[k], q, no) ? 1 : 2;
             count_wave(&A.removed[1], killed);
         }
     }
@@ -842,24 +838,15 @@ __global__ void __launch_bounds__(256) k_key_offsets(
     }
 }
 
-// stayers to their places; movers' state to the compact buffer
+// stayers to their places; movers' state to the compact buffer.  Each
+// thread takes two slots 256 apart, so twice the state loads are in flight
 template <typename T, int NA, bool FP64>
-__global__ void __launch_bounds__(256) k_place_stayers(
-    ClassView V, int nth, const uint32_t *__restrict__ keys, const int32_t *__restrict__ mst,
-    uint32_t *__restrict__ knew, int32_t *__restrict__ perm, PtrSet<T, NA> P,
-    T *__restrict__ cbuf, int64_t cn) {
-    const int q = blockIdx.x * 256 + threadIdx.x;
-    if (q >= V.nub) return;
-    // the state is read before the class is known, so its loads overlap
-    // those of the class words (slots past the live ones, dead slots and
-    // killed particles have neither bit and are read for nothing)
-    T v[NA];
-#pragma unroll
-    for (int a = 0; a < NA; a++) v[a] = P.src[a][q];
+__device__ __forceinline__ void place_slot(const ClassView &V, int nth, const uint32_t *keys,
+                                           const int32_t *mst, int32_t *perm, const PtrSet<T, NA> &P,
+                                           T *cbuf, int64_t cn, int q, const T (&v)[NA]) {
     const int wd = q >> 6;
     const uint64_t bit = 1ull << (q & 63);
     const uint64_t sm = V.smask[wd], mm = V.mmask[wd];
-    if (((sm | mm) & bit) == 0) return;
     if (sm & bit) {
         uint32_t key;
         if (FP64) {
@@ -871,9 +858,8 @@ __global__ void __launch_bounds__(256) k_place_stayers(
         const uint32_t d = stayers_before(V, q) + (uint32_t)mst[key];
 #pragma unroll
         for (int a = 0; a < NA; a++) P.dst[a][d] = v[a];
-        knew[d] = key;
         if (perm) perm[d] = q;
-    } else {
+    } else if (mm & bit) {
         const int64_t im = movers_before(V, q);
         if (im < cn) {
 #pragma unroll
@@ -882,13 +868,31 @@ __global__ void __launch_bounds__(256) k_place_stayers(
     }
 }
 
+template <typename T, int NA, bool FP64>
+__global__ void __launch_bounds__(256) k_place_stayers(
+    ClassView V, int nth, const uint32_t *__restrict__ keys, const int32_t *__restrict__ mst,
+    int32_t *__restrict__ perm, PtrSet<T, NA> P, T *__restrict__ cbuf, int64_t cn) {
+    // slots past the live ones, dead slots and killed particles have
+    // neither bit (and are read for nothing); the state is read before the
+    // class words so that its loads overlap theirs
+    const int q0 = blockIdx.x * 512 + threadIdx.x, q1 = q0 + 256;
+    T v0[NA], v1[NA];
+#pragma unroll
+    for (int a = 0; a < NA; a++) {
+        v0[a] = q0 < V.nub ? P.src[a][q0] : T(0);
+        v1[a] = q1 < V.nub ? P.src[a][q1] : T(0);
+    }
+    if (q0 < V.nub) place_slot<T, NA, FP64>(V, nth, keys, mst, perm, P, cbuf, cn, q0, v0);
+    if (q1 < V.nub) place_slot<T, NA, FP64>(V, nth, keys, mst, perm, P, cbuf, cn, q1, v1);
+}
+
 // movers in their sorted order: rank j (key k, slot q) goes to
 // j + SB(clamp(q, OFF[k], OFF[k+1]))
 template <typename T, int NA>
 __global__ void __launch_bounds__(256) k_place_movers(
     ClassView V, const uint32_t *__restrict__ mk, const uint32_t *__restrict__ mv,
-    const int32_t *__restrict__ offold, uint32_t *__restrict__ knew, int32_t *__restrict__ perm,
-    PtrSet<T, NA> P, const T *__restrict__ cbuf, int64_t cn) {
+    const int32_t *__restrict__ offold, int32_t *__restrict__ perm, PtrSet<T, NA> P,
+    const T *__restrict__ cbuf, int64_t cn) {
     const int m = (int)V.tot[1];
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < m; j += gridDim.x * blockDim.x) {
         const uint32_t key = mk[j];
@@ -907,8 +911,75 @@ __global__ void __launch_bounds__(256) k_place_movers(
         }
 #pragma unroll
         for (int a = 0; a < NA; a++) P.dst[a][d] = v[a];
-        knew[d] = key;
         if (perm) perm[d] = q;
+    }
+}
+
+// For a push that places the sort: the place of the particle in every
+// slot, written by slot.  Movers first (from their ranks), then the other
+// slots: a stayer's place as in k_place_stayers, -1 for a slot that holds no
+// particle of the new order.  Both write the permutation.
+__global__ void __launch_bounds__(256) k_mover_dest(ClassView V, const uint32_t *__restrict__ mk,
+                                                    const uint32_t *__restrict__ mv,
+                                                    const int32_t *__restrict__ offold,
+                                                    int32_t *__restrict__ dest,
+                                                    int32_t *__restrict__ perm) {
+    const int m = (int)V.tot[1];
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < m; j += gridDim.x * blockDim.x) {
+        const uint32_t key = mk[j];
+        const int q = (int)mv[j];
+        const int lo = offold[key], hi = offold[key + 1];
+        const int cq = q < lo ? lo : (q > hi ? hi : q);
+        const uint32_t d = (uint32_t)j + stayers_before(V, cq);
+        dest[q] = (int32_t)d;
+        if (perm) perm[d] = q;
+    }
+}
+
+// eight slots per thread, 256 apart: the loads of all eight cells, then of
+// their keys' offsets, are in flight together
+constexpr int kDestSlots = 8;
+
+__global__ void __launch_bounds__(256) k_stayer_dest(ClassView V, int nth,
+                                                     const int32_t *__restrict__ cell,
+                                                     const int32_t *__restrict__ mst,
+                                                     int32_t *__restrict__ dest,
+                                                     int32_t *__restrict__ perm) {
+    const int base = blockIdx.x * (256 * kDestSlots) + threadIdx.x;
+    int c[kDestSlots];
+#pragma unroll
+    for (int k = 0; k < kDestSlots; k++) {
+        const int q = base + k * 256;
+        c[k] = q < V.nub ? cell[q] : -1;
+    }
+    int cls[kDestSlots];                      // 0 none, 1 stayer, 2 mover
+    int32_t m[kDestSlots];
+#pragma unroll
+    for (int k = 0; k < kDestSlots; k++) {
+        const int q = base + k * 256;
+        cls[k] = 0;
+        m[k] = 0;
+        if (q < V.nub) {
+            const int wd = q >> 6;
+            const uint64_t bit = 1ull << (q & 63);
+            cls[k] = (V.smask[wd] & bit) ? 1 : ((V.mmask[wd] & bit) ? 2 : 0);
+            if (cls[k] == 1) {
+                const uint32_t key =
+                    (uint32_t)(c[k] >> 16) * (uint32_t)nth + (uint32_t)(c[k] & 0xffff);
+                m[k] = mst[key];
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kDestSlots; k++) {
+        const int q = base + k * 256;
+        if (q >= V.nub || cls[k] == 2) continue;   // a mover: placed by its rank
+        int32_t d = -1;
+        if (cls[k] == 1) {
+            d = (int32_t)(stayers_before(V, q) + (uint32_t)m[k]);
+            if (perm) perm[d] = q;
+        }
+        dest[q] = d;
     }
 }
 
@@ -952,20 +1023,19 @@ static void sort_full(ffpic_ctx *c, int s) {
     for (int a = 0; a < S.narr; a++) std::swap(S.cur[a], S.alt[a]);
     // the sorted keys and their cell offsets, for the next sort
     const int t = c->sort_cur[s];
-    hipLaunchKernelGGL(k_copy_u32, dim3(nb), dim3(256), 0, c->stream, nal, R.k, c->skey[s][t]);
     if (int32_t *perm = perm_out(c, s))
         hipLaunchKernelGGL(k_copy_u32, dim3(nb), dim3(256), 0, c->stream, nal, R.v,
                            (uint32_t *)perm);
     const int nkeys = c->nr * c->nth;
     hipLaunchKernelGGL(k_offsets_dev, dim3((nkeys + 1 + 255) / 256), dim3(256), 0, c->stream, nal,
-                       c->skey[s][t], nkeys, c->soff[s][t]);
+                       R.k, nkeys, c->soff[s][t]);
     FFPIC_LAUNCH_CHECK();
     c->sort_valid[s] = true;
 }
 
 // incremental sort (see the header comment); requires the keys and offsets
 // of the previous sort of this species
-static void sort_incremental(ffpic_ctx *c, int s) {
+static void sort_incremental(ffpic_ctx *c, int s, bool defer) {
     ffpic::Species &S = c->sp[s];
     const int nub = (int)S.nub;
     const uint32_t dead = dead_key(c);
@@ -983,12 +1053,13 @@ static void sort_incremental(ffpic_ctx *c, int s) {
     A.nslots = c->nslots + s;
     A.nsorted = c->nsorted + s;
     A.kill = c->kill;
-    A.kold = c->skey[s][t];
+    A.offold = c->soff[s][t];
     A.removed = c->removed + 4 * s;
-    A.smask = c->sort_smask;
-    A.mmask = c->sort_mmask;
-    A.wsm = c->sort_wsm;
-    A.tc = c->sort_tc;
+    A.smask = c->sort_smask[s];
+    A.mmask = c->sort_mmask[s];
+    A.wsm = c->sort_wsm[s];
+    A.tc = c->sort_tc[s];
+    A.tot = c->sort_tot[s];
     // the movers of each tile go to the second radix buffer, which is free
     // until the movers have been made dense
     A.tkey = c->keys[1];
@@ -1007,55 +1078,76 @@ static void sort_incremental(ffpic_ctx *c, int s) {
         A.cell = (int32_t *)S.cur[0];
         hipLaunchKernelGGL(k_classify<false>, dim3(ntile), dim3(256), 0, c->stream, A);
     }
-    hipLaunchKernelGGL(k_tile_scan, dim3(ngroup), dim3(256), 0, c->stream, c->sort_tc, ntile,
-                       c->sort_ts, c->sort_gs);
-    hipLaunchKernelGGL(k_group_scan, dim3(1), dim3(256), 0, c->stream, c->sort_gs, ngroup,
-                       c->sort_tot);
+    hipLaunchKernelGGL(k_tile_scan, dim3(ngroup), dim3(256), 0, c->stream, c->sort_tc[s], ntile,
+                       c->sort_ts[s], c->sort_gs[s]);
+    hipLaunchKernelGGL(k_group_scan, dim3(1), dim3(256), 0, c->stream, c->sort_gs[s], ngroup,
+                       c->sort_tot[s]);
     FFPIC_LAUNCH_CHECK();
     const Pairs dense{c->vals[1], c->sort_aux}, spare{c->keys[1], c->vals[0]};
     hipLaunchKernelGGL(k_movers_dense, dim3((ntile + 3) / 4), dim3(256), 0, c->stream, ntile,
-                       c->sort_tc, c->sort_ts, c->sort_gs, A.tkey, A.tval, dense.k, dense.v);
+                       c->sort_tc[s], c->sort_ts[s], c->sort_gs[s], A.tkey, A.tval, dense.k, dense.v);
     FFPIC_LAUNCH_CHECK();
     // the mover count is tot[1], on the device
-    const int32_t *m_dev = (const int32_t *)(c->sort_tot + 1);
+    const int32_t *m_dev = (const int32_t *)(c->sort_tot[s] + 1);
     const Pairs M = radix_sort(c, dense, spare, m_dev, nub, sort_key_bits(c));
 
-    ClassView V{nub, c->sort_smask, c->sort_mmask, c->sort_wsm, c->sort_ts, c->sort_gs,
-                c->sort_tot};
+    ClassView V{nub, c->sort_smask[s], c->sort_mmask[s], c->sort_wsm[s], c->sort_ts[s], c->sort_gs[s],
+                c->sort_tot[s]};
     const int32_t *offold = c->soff[s][t];
-    uint32_t *knew = c->skey[s][1 - t];
     int32_t *offnew = c->soff[s][1 - t];
     // movers per key, their exclusive scan, and the per-key pass
     const int nbk = (int)((nkeys + 1 + 1023) / 1024);
     const int nbm = std::max(1, std::min((nub + 255) / 256, kMoverBlocks));
     if (scan_part_len(nkeys + 1) > c->scan_part_n) throw std::runtime_error("scan scratch too small");
-    hipLaunchKernelGGL(k_mover_runs, dim3(nbm), dim3(256), 0, c->stream, c->sort_tot, M.k,
+    hipLaunchKernelGGL(k_mover_runs, dim3(nbm), dim3(256), 0, c->stream, c->sort_tot[s], M.k,
                        c->sort_kcnt);
     hipLaunchKernelGGL(k_scan_sums, dim3(nbk), dim3(256), 0, c->stream, c->sort_kcnt, nkeys + 1,
                        c->scan_part);
     hipLaunchKernelGGL(k_scan_part, dim3(1), dim3(256), 0, c->stream, c->scan_part, nbk);
     // reads the old live count (through OFF) before replacing it
     hipLaunchKernelGGL(k_key_offsets, dim3(nbk), dim3(256), 0, c->stream, nkeys, V, M.v, offold,
-                       c->sort_kcnt, c->scan_part, c->sort_mst, offnew, c->nalive + s,
+                       c->sort_kcnt, c->scan_part, c->sort_mst[s], offnew, c->nalive + s,
                        c->nslots + s, c->nsorted + s);
     FFPIC_LAUNCH_CHECK();
     int32_t *perm = perm_out(c, s);
-    const int nbs = (nub + 255) / 256;
+    if (defer) {
+        // the next push reads the particles in the old order and writes
+        // them in the new one (FP32): it reads where each goes
+        hipLaunchKernelGGL(k_mover_dest, dim3(nbm), dim3(256), 0, c->stream, V, M.k, M.v, offold,
+                           c->sort_dest[s], perm);
+        hipLaunchKernelGGL(k_stayer_dest, dim3((nub + 256 * kDestSlots - 1) / (256 * kDestSlots)),
+                           dim3(256), 0, c->stream, V,
+                           c->nth, (const int32_t *)S.cur[0], c->sort_mst[s], c->sort_dest[s],
+                           perm);
+        FFPIC_LAUNCH_CHECK();
+        SortPlace &P = c->place[s];
+        P.dest = c->sort_dest[s];
+        P.cell = (int32_t *)S.alt[0];
+        P.a = (float *)S.alt[1];
+        P.b = (float *)S.alt[2];
+        P.ur = (float *)S.alt[3];
+        P.ut = (float *)S.alt[4];
+        P.up = (float *)S.alt[5];
+        c->sort_pending[s] = true;
+        c->sort_cur[s] = 1 - t;
+        return;
+    }
+    const int nbs = (nub + 511) / 512;
     if (c->fp64) {
         auto P = state_ptrs<uint64_t, 5>(S);
         hipLaunchKernelGGL((k_place_stayers<uint64_t, 5, true>), dim3(nbs), dim3(256), 0,
-                           c->stream, V, c->nth, c->keys[0], c->sort_mst, knew, perm,
+                           c->stream, V, c->nth, c->keys[0], c->sort_mst[s], perm,
                            P, (uint64_t *)c->sort_cbuf, c->sort_cbuf_n);
         hipLaunchKernelGGL((k_place_movers<uint64_t, 5>), dim3(nbm), dim3(256), 0, c->stream, V,
-                           M.k, M.v, offold, knew, perm, P, (const uint64_t *)c->sort_cbuf,
+                           M.k, M.v, offold, perm, P, (const uint64_t *)c->sort_cbuf,
                            c->sort_cbuf_n);
     } else {
         auto P = state_ptrs<uint32_t, 6>(S);
         hipLaunchKernelGGL((k_place_stayers<uint32_t, 6, false>), dim3(nbs), dim3(256), 0,
-                           c->stream, V, c->nth, nullptr, c->sort_mst, knew, perm, P,
+                           c->stream, V, c->nth, nullptr, c->sort_mst[s], perm, P,
                            (uint32_t *)c->sort_cbuf, c->sort_cbuf_n);
         hipLaunchKernelGGL((k_place_movers<uint32_t, 6>), dim3(nbm), dim3(256), 0, c->stream, V,
-                           M.k, M.v, offold, knew, perm, P, (const uint32_t *)c->sort_cbuf,
+                           M.k, M.v, offold, perm, P, (const uint32_t *)c->sort_cbuf,
                            c->sort_cbuf_n);
     }
     FFPIC_LAUNCH_CHECK();
@@ -1063,10 +1155,10 @@ static void sort_incremental(ffpic_ctx *c, int s) {
     c->sort_cur[s] = 1 - t;
 }
 
-void sort_species(ffpic_ctx *c, int s) {
+void sort_species(ffpic_ctx *c, int s, bool defer) {
     ffpic::Species &S = c->sp[s];
     if (S.nub == 0) return;
-    if (c->sort_valid[s] && c->incremental_sort) sort_incremental(c, s);
+    if (c->sort_valid[s] && c->incremental_sort) sort_incremental(c, s, defer && !c->fp64);
     else sort_full(c, s);
 }
 

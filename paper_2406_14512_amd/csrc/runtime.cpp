@@ -405,9 +405,13 @@ void free_all(ffpic_ctx *c) {
         for (int a = 0; a < 6; a++) { F(c->sp[s].cur[a]); F(c->sp[s].alt[a]); }
     for (int k = 0; k < 2; k++) { F(c->keys[k]); F(c->vals[k]); }
     for (int s = 0; s < FFPIC_MAX_SPECIES; s++)
-        for (int k = 0; k < 2; k++) { F(c->skey[s][k]); F(c->soff[s][k]); }
-    F(c->sort_smask); F(c->sort_mmask); F(c->sort_wsm); F(c->sort_tc); F(c->sort_ts); F(c->sort_gs);
-    F(c->sort_aux); F(c->sort_mst); F(c->sort_kcnt); F(c->sort_cbuf); F(c->sort_tot);
+        for (int k = 0; k < 2; k++) F(c->soff[s][k]);
+    for (int s = 0; s < FFPIC_MAX_SPECIES; s++) {
+        F(c->sort_smask[s]); F(c->sort_mmask[s]); F(c->sort_wsm[s]); F(c->sort_tc[s]);
+        F(c->sort_ts[s]); F(c->sort_gs[s]); F(c->sort_tot[s]); F(c->sort_mst[s]);
+        F(c->sort_dest[s]);
+    }
+    F(c->sort_aux); F(c->sort_kcnt); F(c->sort_cbuf);
     F(c->rs_hist); F(c->rs_dtot); F(c->rs_n); F(c->scan_part);
     for (int s = 0; s < FFPIC_MAX_SPECIES; s++) F(c->perm[s]);
     F(c->inj_rate); F(c->inj_cnt); F(c->inj_off); F(c->nsorted);
@@ -518,8 +522,14 @@ void one_step(ffpic_ctx *c, uint32_t ph, bool count_step, int tslot) {
     mark(0);
     if (ph & FFPIC_PHASE_MASK) psi_mask(c);
     mark(1);
+    // FP32: when this step pushes and nothing is appended between the sort
+    // and the push, the push writes its particles in the sorted order (one
+    // pass over the state instead of two)
+    const bool defer = (ph & FFPIC_PHASE_PUSH) && !c->fp64 &&
+                       !((ph & FFPIC_PHASE_INJECT) && c->d.inject_kappa > 0.0) &&
+                       !((ph & FFPIC_PHASE_EXTRACT) && c->d.gj_extract > 0.0);
     for (int s = 0; s < c->d.nspec; s++) {
-        if (ph & FFPIC_PHASE_SORT) sort_species(c, s);
+        if (ph & FFPIC_PHASE_SORT) sort_species(c, s, defer);
         else if (ph & FFPIC_PHASE_KILL) kill_species(c, s);
     }
     const bool sources = (c->d.inject_kappa > 0.0 || c->d.gj_extract > 0.0 ||
@@ -831,19 +841,15 @@ int ffpic_create(const ffpic_desc *d, void *stream, ffpic_ctx **out) {
         {
             const size_t nk1 = (size_t)c->nr * c->nth + 1;
             c->sort_aux = (uint32_t *)dmalloc((size_t)std::max<int64_t>(maxcap, 1) * 4);
-            c->sort_mst = (int32_t *)dmalloc(nk1 * 4);
             c->sort_kcnt = (int32_t *)dmalloc(nk1 * 4);
             HCHK(hipMemset(c->sort_kcnt, 0, nk1 * 4));
             // room for the state of a quarter of the slots changing cell
             // between two sorts; the movers past it are read from their slots
             c->sort_cbuf_n = std::max<int64_t>(maxcap / 4, 1);
             c->sort_cbuf = dmalloc((size_t)c->sort_cbuf_n * (c->fp64 ? 5 * 8 : 6 * 4));
-            c->sort_tot = (uint32_t *)dmalloc(2 * 4);
+
             for (int s = 0; s < d->nspec; s++)
-                for (int k = 0; k < 2; k++) {
-                    c->skey[s][k] = (uint32_t *)dmalloc((size_t)std::max<int64_t>(c->sp[s].cap, 1) * 4);
-                    c->soff[s][k] = (int32_t *)dmalloc(nk1 * 4);
-                }
+                for (int k = 0; k < 2; k++) c->soff[s][k] = (int32_t *)dmalloc(nk1 * 4);
         }
         // scans: the movers per key of the sort, the surface sources' counts
         int64_t scan_n = std::max<int64_t>((int64_t)c->nr * c->nth + 1, c->nth + 1);

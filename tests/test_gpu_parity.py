@@ -569,6 +569,61 @@ def check_incremental_sort(w, precision, moved):
             prev[s] = p1["cell"]
 
 
+def test_sort_placed_by_the_push_fp32():
+    """FP32: in a step that sorts and pushes, the push writes its particles
+    in the sorted order (the sort's separate placement pass is skipped).
+    Twin contexts take the same steps, one through ffpic_step (graph cycles
+    included) and one with the sort and the rest of each step as separate
+    phase calls (the sort then places the particles itself): the particle
+    state after every step is bit-identical, the recorded permutation of
+    each sort is the stable order of the pre-sort cells, and the fields
+    agree exactly.  The particles carry no charge (weight 0), so the
+    deposit adds zeros and the order of its atomic additions cannot make
+    the twins' fields, and so their particles, differ."""
+    w = small_sheet(60_000, nr=192)
+    d = w.desc()
+    d["precision"] = W.FP32_MIXED
+    d["sort_interval"] = 4
+    d["weight"] = [0.0, 0.0]
+    a = ffpic.Sim(d, capacity=[w.n_per_species] * 2)
+    b = ffpic.Sim(d, capacity=[w.n_per_species] * 2)
+    for sim in (a, b):
+        sim.record_sort(True)
+        for s in range(2):
+            sim.load_particles(s, w.particles(s))
+    rest = (ffpic.PHASE_INJECT | ffpic.PHASE_EXTRACT | ffpic.PHASE_PUSH | ffpic.PHASE_PAIRS |
+            ffpic.PHASE_FIELDS)
+    for cycle in range(3):
+        # b: the cycle's four steps as phase calls, the sort on its own
+        b.run_phases(ffpic.PHASE_MASK)
+        kc = kill_cells(b, w.nr, w.nth)
+        before = [b.particles(s)["cell"] for s in range(2)]
+        b.run_phases(ffpic.PHASE_SORT)
+        b.run_phases(rest)
+        for _ in range(3):
+            b.run_phases(ffpic.PHASE_MASK | rest)
+        # a: the same four steps as one call (a graph after the first cycle)
+        a.step(4)
+        a.sync()
+        b.sync()
+        for s in range(2):
+            pa, pb = a.particles(s), b.particles(s)
+            for k in ("cell", "r", "th", "ur", "uth", "uph"):
+                assert np.array_equal(pa[k], pb[k]), (cycle, s, k)
+            c0 = before[s]
+            killed = np.zeros(len(c0), dtype=bool)
+            ok = c0 >= 0
+            killed[ok] = kc[c0[ok]]
+            order = expected_stable_order(c0, killed)
+            assert np.array_equal(a.sort_permutation(s), order), (cycle, s)
+            assert np.array_equal(b.sort_permutation(s), order), (cycle, s)
+        for g, _, n in FIELDS:
+            assert np.array_equal(a.field(g), b.field(g)), (cycle, n)
+    assert a.graph_stats()[1] >= 1
+    a.close()
+    b.close()
+
+
 def oracle_ulp_sensitivity(desc, steps):
     """Relative field change of the oracle after `steps` steps when every
     E node is moved by one ulp after the first step: the size of difference
