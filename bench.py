@@ -42,8 +42,10 @@ COUNTER_FILE = {1: "profiles/k_push32_sheet4096_hbm_counters.txt",
 KERNEL_SOURCES = {1: ["paper_2406_14512_amd/csrc/k_push32.hip"],
                   0: ["paper_2406_14512_amd/csrc/k_push64.hip",
                       "paper_2406_14512_amd/csrc/gather.h"]}
+# headers whose device code the push kernels compile in (the context struct
+# of ffpic_internal.h is host-side bookkeeping, left out)
 COMMON_SOURCES = ["paper_2406_14512_amd/csrc/device_common.h",
-                  "paper_2406_14512_amd/csrc/ffpic_internal.h"]
+                  "paper_2406_14512_amd/csrc/sort_view.h"]
 
 
 def log(*a):
@@ -177,8 +179,10 @@ def batch_run(ffpic, W, steps, warmup, scale, tune_ms=0.0):
         for x in t:
             cycle = cycle * x["sort_interval"] // math.gcd(cycle, x["sort_interval"])
     # whole batch cycles (the least common multiple of the sort intervals):
-    # two to capture the graphs of both buffer parities, then the timed ones
-    warmup = max(warmup, 2 * cycle)
+    # the first (launched step by step after the tuner's restore, whose
+    # sorts are full ones), two to capture the graphs of both buffer
+    # parities, then the timed ones
+    warmup = max(warmup, 3 * cycle)
     warmup = -(-warmup // cycle) * cycle
     steps = -(-steps // cycle) * cycle
     b.step(warmup)
