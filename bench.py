@@ -139,13 +139,52 @@ def roofline(precision, res, steps, nspec, copy_gbs):
     avg_launch_s = push_ms / 1e3 / launches
     bytes_per_launch = BYTES_PER_PARTICLE[precision] * n_avg / nspec
     achieved = bytes_per_launch / avg_launch_s / 1e9
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(precision),
-            "kernel": "k_push32" if precision == 1 else "k_push64",
-            "avg_launch_ms": round(avg_launch_s * 1e3, 4),
-            "bytes_per_launch": bytes_per_launch,
-            "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
+    traffic = measured_traffic(precision)
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+           "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+           "traffic": traffic,
+           "kernel": "k_push32" if precision == 1 else "k_push64",
+           "achieved_basis": f"algorithmic bytes: {BYTES_PER_PARTICLE[precision]} B per live "
+                             "particle (state read + written once)",
+           "avg_launch_ms": round(avg_launch_s * 1e3, 4),
+           "bytes_per_launch": bytes_per_launch,
+           "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
+           "target_frac": 0.6}
+    if traffic:
+        # the counter-measured bytes over the same launch time
+        out["traffic_gbs"] = round(traffic / avg_launch_s / 1e9, 1)
+        out["traffic_frac"] = round(traffic / avg_launch_s / 1e9 / HBM_PEAK_GBS, 4)
+    valu = valu_per_particle(precision)
+    if valu:
+        # VALU issue against the SIMDs' capacity: one wave64 instruction per
+        # SIMD every 4 clocks, 256 CUs x 4 SIMDs at 2.4 GHz
+        issue = valu * (n_avg / nspec) / 64.0 * 4.0 / (256 * 4 * 2.4e9 * avg_launch_s)
+        out["alu"] = {"valu_per_particle": valu, "issue_frac": round(issue, 3),
+                      "source": SQ_FILE}
+    return out
+
+
+SQ_FILE = "profiles/push_sheet4096_sq_counters.txt"
+
+
+def valu_per_particle(precision):
+    """VALU wave instructions x 64 per particle of the push (steps without a
+    sort), from the committed instruction-counter summary; None if absent."""
+    path = os.path.join(ROOT, SQ_FILE)
+    if not os.path.exists(path):
+        return None
+    want = "k_push32<false, 16, false>" if precision == 1 else "k_push64 :"
+    block = False
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("ffpic::"):
+                block = want in line
+            elif block and line.strip().startswith("SQ_INSTS_VALU") and "per particle" in line:
+                try:
+                    return float(line.split()[-3])
+                except ValueError:
+                    return None
+    return None
 
 
 def batch_run(ffpic, W, steps, warmup, scale, tune_ms=0.0):
