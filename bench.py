@@ -214,6 +214,10 @@ def batch_run(ffpic, W, steps, warmup, scale, tune_ms=0.0):
             vals = [x[key] for x in t]
             tuned[key] = {str(v): vals.count(v) for v in sorted(set(vals))}
         tuned["ms"] = round(sum(x["total_ms"] for x in t), 1)
+        # the batch's graph mode, chosen by timing both from one checkpoint
+        mode, mode_ms = b.get_graph()
+        tuned["graph_mode"] = mode
+        tuned["graph_mode_ms_per_step"] = {str(k): round(v, 3) for k, v in mode_ms.items()}
         cycle = 1
         for x in t:
             cycle = cycle * x["sort_interval"] // math.gcd(cycle, x["sort_interval"])
@@ -229,13 +233,25 @@ def batch_run(ffpic, W, steps, warmup, scale, tune_ms=0.0):
     alive = lambda: sum(sum(v.diagnostics(ffpic.DIAG_MOMENTS)["alive"]) for v in b.views)
     n0 = alive()
     g0 = b.graph_stats()
+    grouped0 = b.grouped_launches()
     t0 = time.perf_counter()
     b.step(steps)
     b.sync()
     t1 = time.perf_counter()
     g1 = b.graph_stats()
     n1 = alive()
-    # the same steps launched one by one, for comparison
+    grouped = b.grouped_launches() - grouped0
+    mode = b.get_graph()[0]
+    # for comparison: the same steps in the other graph mode (two cycles to
+    # capture its graphs first), then launched one by one
+    other = b.GRAPH_PER_SYSTEM if mode == b.GRAPH_GROUPED else b.GRAPH_GROUPED
+    b.set_graph(other)
+    b.step(2 * cycle)
+    b.sync()
+    t4 = time.perf_counter()
+    b.step(steps)
+    b.sync()
+    t5 = time.perf_counter()
     b.set_graph(False)
     t2 = time.perf_counter()
     b.step(steps)
@@ -248,7 +264,10 @@ def batch_run(ffpic, W, steps, warmup, scale, tune_ms=0.0):
             "steps": steps, "ms_per_step": wall / steps * 1e3,
             "particle_steps_per_s": 0.5 * (n0 + n1) * steps / wall,
             "cell_updates_per_s": cells * steps / wall,
-            "graphs": {"captured": g1[0] - g0[0], "launched": g1[1] - g0[1]},
+            "graphs": {"captured": g1[0] - g0[0], "launched": g1[1] - g0[1],
+                       "grouped": grouped},
+            "graph_mode": {1: "per-system", 2: "grouped"}.get(mode, "off"),
+            "other_graph_mode_ms_per_step": (t5 - t4) / steps * 1e3,
             "eager_ms_per_step": (t3 - t2) / steps * 1e3, "tuned": tuned}
 
 
@@ -431,8 +450,11 @@ def main():
         log("timing the batched workload (64 systems)")
         out["batch"] = batch_run(ffpic, W, args.steps, args.warmup, args.batch_scale,
                                  args.batch_tune_ms)
-        log(f"  batch: {out['batch']['ms_per_step']:.3f} ms/step, "
-            f"{out['batch']['particle_steps_per_s']:.3e} particle-steps/s")
+        bo = out["batch"]
+        log(f"  batch: {bo['ms_per_step']:.3f} ms/step, "
+            f"{bo['particle_steps_per_s']:.3e} particle-steps/s, graphs {bo['graphs']}; "
+            f"mode {bo['graph_mode']}, other mode {bo['other_graph_mode_ms_per_step']:.3f} ms/step, "
+            f"one by one {bo['eager_ms_per_step']:.3f} ms/step")
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)

@@ -401,6 +401,14 @@ int ffpic_restore(ffpic_ctx *ctx, const void *buf, size_t len);
    Results do not depend on it.  EINVAL for a negative value. */
 int ffpic_set_field_rows(ffpic_ctx *ctx, int32_t rows);
 
+/* Tuning of the FP32 push: particles per thread of a workgroup's chunk
+   (8, 16 or 32; chunks of 256 threads).  Larger chunks share one field and
+   one current patch among more particles; smaller ones make more
+   workgroups for small systems.  Ignored by the FP64 push.  Results do not
+   depend on it beyond the order of floating-point atomic additions.
+   EINVAL for another value. */
+int ffpic_set_push_chunk(ffpic_ctx *ctx, int32_t ppt);
+
 /* Graph capture of ffpic_step (on by default).  A call of ffpic_step runs
    every whole sort cycle it contains (sort_interval steps from a step that
    sorts) as one HIP graph: captured on the first cycle that starts from a
@@ -447,16 +455,37 @@ int ffpic_batch_size(const ffpic_batch *b);
 int ffpic_batch_step(ffpic_batch *b, int32_t nsteps);
 int ffpic_batch_sync(ffpic_batch *b);
 
-/* Graph capture of batch steps (on by default): when every system stands
-   at the start of one of its sort cycles and each could replay its own
-   cycle from a graph (see ffpic_set_graph), ffpic_batch_step runs the
-   least common multiple of the systems' sort intervals (up to 64 steps) of
-   all systems as one HIP graph, in which every system's
-   launches form their own chain on its stream's branch; captured once per
-   host state of all systems and replayed afterwards.  Other steps are
-   launched one by one.  Results do not depend on it. */
-int ffpic_batch_set_graph(ffpic_batch *b, int on);
+/* Graph capture of batch steps.  When every system stands at the start of
+   one of its sort cycles and each could replay its own cycle from a graph
+   (see ffpic_set_graph), ffpic_batch_step runs the least common multiple of
+   the systems' sort intervals (up to 64 steps) of all systems as one HIP
+   graph, captured once per host state of all systems and replayed
+   afterwards.  Other steps are launched one by one.  `mode`:
+     0  no graphs;
+     1  the graph holds every system's own launches, each system's chain on
+        its stream's branch;
+     2  (default) where every system is FP32-mixed and has no plasma sources
+        (injection, extraction, pair creation): the graph holds, per step,
+        ONE launch of persistent workgroups for the flux functions of all
+        systems, one for their masks, one per push kernel instance for all
+        systems' pushes and one per field-step instance for all their field
+        steps (each workgroup takes work items, such as a 4096-particle chunk
+        of one system, from a counter in device memory until none is left);
+        only the sorts stay per system.  The job tables those launches read
+        are owned by the graph (device memory, freed with it).  Other
+        batches fall back to mode 1.
+   Results do not depend on the mode beyond the order of floating-point
+   atomic additions in the deposit.  EINVAL for another mode.
+   ffpic_batch_graph_stats: graphs captured and graph launches so far;
+   ffpic_batch_grouped_launches: how many of the launches were mode-2
+   graphs. */
+int ffpic_batch_set_graph(ffpic_batch *b, int mode);
 int ffpic_batch_graph_stats(ffpic_batch *b, int64_t *builds, int64_t *launches);
+int ffpic_batch_grouped_launches(const ffpic_batch *b, int64_t *launches);
+/* The graph mode in use (after ffpic_batch_autotune: the one it chose) and,
+   when ms_per_step is not NULL, the batch-step times the tuner measured for
+   modes 0, 1, 2 (0 where not measured). */
+int ffpic_batch_get_graph(const ffpic_batch *b, int32_t *mode, double ms_per_step[3]);
 const char *ffpic_batch_last_error(const ffpic_batch *b);
 int ffpic_batch_destroy(ffpic_batch *b);
 
@@ -490,7 +519,13 @@ int ffpic_batch_destroy(ffpic_batch *b);
  *
  * Errors: EINVAL for a non-positive budget; a context in error
  * (ffpic_sync fails) is not tuned.  ffpic_batch_autotune tunes every system
- * with an equal share of the budget and writes n entries to out.
+ * with an equal share of the budget and writes n entries to out.  Then, for
+ * a batch that can run as grouped launches (see ffpic_batch_set_graph) with
+ * graphs on, it checkpoints every system, times whole batch cycles with
+ * per-system graphs (mode 1) and with grouped launches (mode 2) from that
+ * same state, restores the checkpoints and keeps the faster mode
+ * (ffpic_batch_get_graph reports both times).  The systems' states after
+ * the call are those before it.
  */
 #define FFPIC_TUNE_MAX 16
 enum ffpic_tune_kind {

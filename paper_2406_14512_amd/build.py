@@ -22,7 +22,10 @@ SOURCES = [
     ("runtime.cpp", []),
     ("batch.cpp", []),
     ("k_fields64.hip", ["-ffp-contract=off"]),
-    ("k_fields32.hip", []),
+    # FP32 field step: products fused only within one expression, so that a
+    # node computed by two slabs (its halo copy and its own) rounds the same
+    # in every unrolled copy of the row step
+    ("k_fields32.hip", ["-ffp-contract=on"]),
     ("k_push64.hip", ["-ffp-contract=off"]),
     # LDS adds of the row sums share one address per wave: keep them plain
     # atomics instead of the compiler's lane-by-lane pre-reduction loop

@@ -36,11 +36,14 @@
 #include "ffpic_internal.h"
 
 // one batch sort cycle as a graph, with the host state of every system it
-// starts from and leaves
+// starts from and leaves; a grouped graph also owns the job tables its
+// launches read
 struct BatchGraph {
     int steps = 0;
+    int mode = 1;
     std::vector<ffpic::CycleState> pre, post;
     hipGraphExec_t exec = nullptr;
+    void *tables = nullptr;
 };
 
 struct ffpic_batch {
@@ -51,8 +54,14 @@ struct ffpic_batch {
     hipEvent_t fork = nullptr;
     std::vector<hipEvent_t> join;     // one per stream
     // graph-captured batch cycles: captured from origin, which forks to the
-    // lane streams and joins them back
-    bool use_graph = true;
+    // lane streams and joins them back (mode 1), or grouped launches of all
+    // systems on origin (mode 2, where every system allows it); mode 0: no
+    // graphs
+    int graph_mode = 2;
+    int *gctr = nullptr;              // work counters of the grouped launches
+    int push_slots[12] = {}, field_slots[8] = {}, psi_slots = 0;
+    int64_t grouped_launches = 0;
+    double mode_ms[3] = {0, 0, 0};    // batch-step time of each graph mode at the last tuning
     hipStream_t origin = nullptr;
     hipEvent_t gfork = nullptr, gjoin = nullptr;
     std::vector<BatchGraph> graphs;
@@ -101,8 +110,10 @@ double cost_of(const ffpic_desc &d) {
 
 void destroy_batch_graphs(ffpic_batch *b) {
     if (!b->graphs.empty() && b->origin) (void)hipStreamSynchronize(b->origin);
-    for (auto &g : b->graphs)
+    for (auto &g : b->graphs) {
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.tables) (void)hipFree(g.tables);
+    }
     b->graphs.clear();
 }
 
@@ -113,6 +124,8 @@ void release(ffpic_batch *b) {
     if (b->gjoin) (void)hipEventDestroy(b->gjoin);
     b->origin = nullptr;
     b->gfork = b->gjoin = nullptr;
+    if (b->gctr) (void)hipFree(b->gctr);
+    b->gctr = nullptr;
     for (size_t k = 0; k < b->ctx.size(); k++) {
         if (!b->ctx[k]) continue;
         b->ctx[k]->batch_owned = false;
@@ -131,7 +144,7 @@ void release(ffpic_batch *b) {
 // graphable_cycle) and every system stands at the start of one of its own
 // cycles.
 int batch_cycle(const ffpic_batch *b) {
-    if (!b->use_graph) return 0;
+    if (b->graph_mode == 0) return 0;
     int64_t k = 1;
     for (ffpic_ctx *c : b->ctx) {
         const int si = c->d.sort_interval;
@@ -158,16 +171,163 @@ void launch_batch_graph(ffpic_batch *b, hipGraphExec_t exec) {
     b->graph_launches++;
 }
 
+// Grouped cycles: every system FP32-mixed, with no plasma sources (their
+// kernels are per system and read per-step arguments).
+bool grouped_possible(const ffpic_batch *b) {
+    for (const ffpic_ctx *c : b->ctx) {
+        if (c->fp64 || c->d.nspec < 1) return false;
+        if (c->d.inject_kappa > 0.0 || c->d.gj_extract > 0.0 || c->d.gamma_th > 0.0) return false;
+    }
+    return true;
+}
+
+bool grouped_ok(const ffpic_batch *b) { return b->graph_mode == 2 && grouped_possible(b); }
+
+// Host copies of the job tables of a grouped cycle, laid out as they go to
+// device memory (each array at a 256-byte boundary), and the device
+// addresses the captured launches read them from.
+struct Tables {
+    std::vector<char> host;
+    char *dev = nullptr;
+    size_t cap = 0;
+    size_t put(const void *p, size_t n) {
+        const size_t off = (host.size() + 255) & ~(size_t)255;
+        if (off + n > cap) throw BFail{FFPIC_EHIP, "grouped job tables exceed their bound"};
+        host.resize(off + n);
+        std::memcpy(host.data() + off, p, n);
+        return off;
+    }
+};
+
+// one launch's jobs: their bytes back to back and the first item of each
+struct Group {
+    std::vector<char> jobs;
+    std::vector<int> starts{0};
+    int njobs() const { return (int)starts.size() - 1; }
+    int items() const { return starts.back(); }
+    // the table pair in device memory
+    std::pair<const void *, const int *> place(Tables &T) const {
+        const size_t oj = T.put(jobs.data(), jobs.size());
+        const size_t os = T.put(starts.data(), starts.size() * sizeof(int));
+        return {T.dev + oj, (const int *)(T.dev + os)};
+    }
+};
+
+size_t table_bound(const ffpic_batch *b, int steps) {
+    size_t n = b->ctx.size(), sp = 0;
+    for (const ffpic_ctx *c : b->ctx) sp += (size_t)c->d.nspec;
+    // per step: two tables (jobs, first items) for each of the flux, mask,
+    // up to 12 push and up to 8 field launches, each array starting at a
+    // 256-byte boundary
+    const size_t pad = 256;
+    const size_t psi = n * ffpic::psi_job_bytes() + (n + 1) * 4 + 2 * pad;
+    const size_t mask = n * ffpic::mask_job_bytes() + (n + 1) * 4 + 2 * pad;
+    const size_t push = sp * ffpic::push_job_bytes() + (sp + 12) * 4 + 24 * pad;
+    const size_t field = n * ffpic::field_job_bytes() + (n + 8) * 4 + 16 * pad;
+    return (size_t)steps * (psi + mask + push + field) + pad;
+}
+
+void grouped_setup(ffpic_batch *b) {
+    if (b->gctr) return;
+    BCHK(hipMalloc((void **)&b->gctr, 2 * sizeof(int)));
+    BCHK(hipMemset(b->gctr, 0, 2 * sizeof(int)));
+    BCHK(hipDeviceSynchronize());
+    for (int k = 0; k < 12; k++) b->push_slots[k] = ffpic::push_group_slots(k);
+    for (int k = 0; k < 8; k++) b->field_slots[k] = ffpic::field_group_slots(k);
+    b->psi_slots = ffpic::psi_group_slots();
+}
+
+// One batch step as grouped launches on stream st (being captured): the
+// flux functions and masks of all systems, then each system's sort if it
+// sorts this step (its own launches, on its own stream's branch, forked from
+// st and joined back), then the pushes of all systems grouped by kernel
+// instance, then their field steps likewise.  The host bookkeeping of every
+// system follows what ffpic_step does for that step.
+void grouped_step(ffpic_batch *b, hipStream_t st, Tables &T) {
+    int *ctr = b->gctr;
+    const std::vector<ffpic_ctx *> &sys = b->ctx;
+    const int n = (int)sys.size();
+    std::vector<char> tmp(std::max({ffpic::psi_job_bytes(), ffpic::mask_job_bytes(),
+                                    ffpic::push_job_bytes(), ffpic::field_job_bytes()}));
+    Group psi, mask;
+    for (ffpic_ctx *c : sys) {
+        int m = ffpic::psi_job32(c, tmp.data());
+        psi.jobs.insert(psi.jobs.end(), tmp.begin(), tmp.begin() + ffpic::psi_job_bytes());
+        psi.starts.push_back(psi.items() + m);
+        m = ffpic::mask_job32(c, tmp.data());
+        mask.jobs.insert(mask.jobs.end(), tmp.begin(), tmp.begin() + ffpic::mask_job_bytes());
+        mask.starts.push_back(mask.items() + m);
+    }
+    {
+        auto t = psi.place(T);
+        ffpic::psi_group_launch(st, t.first, t.second, n, std::min(psi.items(), b->psi_slots),
+                                ctr);
+        t = mask.place(T);
+        ffpic::mask_group_launch(st, t.first, t.second, n, std::min(mask.items(), 4096));
+    }
+    // each sorting system's own launches on its own stream's branch, so
+    // that the sorts of different systems may overlap
+    bool sorts = false;
+    for (ffpic_ctx *c : sys) sorts = sorts || ffpic::step_sorts(c);
+    if (sorts) {
+        BCHK(hipEventRecord(b->fork, st));
+        for (auto l : b->streams) BCHK(hipStreamWaitEvent(l, b->fork, 0));
+        for (ffpic_ctx *c : sys) {
+            if (!ffpic::step_sorts(c)) continue;
+            // the push of this step places the sorted order
+            for (int s = 0; s < c->d.nspec; s++) ffpic::sort_species(c, s, true);
+        }
+        for (size_t l = 0; l < b->streams.size(); l++) {
+            BCHK(hipEventRecord(b->join[l], b->streams[l]));
+            BCHK(hipStreamWaitEvent(st, b->join[l], 0));
+        }
+    }
+    Group push[12];
+    for (ffpic_ctx *c : sys) {
+        for (int s = 0; s < c->d.nspec; s++) {
+            if (c->sp[s].nub == 0) continue;
+            Group &g = push[ffpic::push_group_key(c, s)];
+            const int m = ffpic::push_job(c, s, tmp.data());
+            g.jobs.insert(g.jobs.end(), tmp.begin(), tmp.begin() + ffpic::push_job_bytes());
+            g.starts.push_back(g.items() + m);
+        }
+    }
+    for (int k = 0; k < 12; k++) {
+        if (push[k].njobs() == 0 || push[k].items() == 0) continue;
+        auto t = push[k].place(T);
+        ffpic::push_group_launch(st, k, t.first, t.second, push[k].njobs(),
+                                 std::min(push[k].items(), b->push_slots[k]), ctr);
+    }
+    Group field[8];
+    for (ffpic_ctx *c : sys) {
+        int key = 0;
+        const int m = ffpic::field_job(c, tmp.data(), &key);
+        Group &g = field[key];
+        g.jobs.insert(g.jobs.end(), tmp.begin(), tmp.begin() + ffpic::field_job_bytes());
+        g.starts.push_back(g.items() + m);
+    }
+    for (int k = 0; k < 8; k++) {
+        if (field[k].njobs() == 0) continue;
+        auto t = field[k].place(T);
+        ffpic::field_group_launch(st, k, t.first, t.second, field[k].njobs(),
+                                  std::min(field[k].items(), b->field_slots[k]), ctr);
+    }
+    for (ffpic_ctx *c : sys) c->step++;
+}
+
 // k steps of every system as one graph: the systems' launches go to their
 // lane streams, each forked from the capture stream and joined back into
-// it, so the graph keeps the systems independent of each other
+// it, so the graph keeps the systems independent of each other; or, where
+// every system allows it, grouped launches of all systems on the capture
+// stream
 void run_batch_cycle(ffpic_batch *b, int k) {
     std::vector<ffpic::CycleState> pre;
     pre.reserve(b->ctx.size());
     for (ffpic_ctx *c : b->ctx) pre.push_back(ffpic::get_cycle_state(c));
     for (auto &g : b->graphs) {
-        if (g.steps == k && same_states(g.pre, pre)) {
+        if (g.steps == k && same_states(g.pre, pre) && g.mode == (grouped_ok(b) ? 2 : 1)) {
             launch_batch_graph(b, g.exec);
+            if (g.mode == 2) b->grouped_launches++;
             for (size_t q = 0; q < b->ctx.size(); q++) {
                 ffpic::put_cycle_state(b->ctx[q], g.post[q]);
                 b->ctx[q]->step += k;
@@ -181,23 +341,41 @@ void run_batch_cycle(ffpic_batch *b, int k) {
         BCHK(hipEventCreateWithFlags(&b->gjoin, hipEventDisableTiming));
     }
     std::vector<int64_t> step0;
-    for (ffpic_ctx *c : b->ctx) step0.push_back(c->step);
+    std::vector<hipStream_t> own;
+    for (ffpic_ctx *c : b->ctx) {
+        step0.push_back(c->step);
+        own.push_back(c->stream);
+    }
+    const bool grouped = grouped_ok(b);
+    Tables T;
     auto restore = [&] {
         for (size_t q = 0; q < b->ctx.size(); q++) {
             ffpic::put_cycle_state(b->ctx[q], pre[q]);
             b->ctx[q]->step = step0[q];
+            b->ctx[q]->stream = own[q];
         }
+        if (T.dev) (void)hipFree(T.dev);
     };
+    if (grouped) {
+        grouped_setup(b);
+        T.cap = table_bound(b, k);
+        BCHK(hipMalloc((void **)&T.dev, T.cap));
+        T.host.reserve(T.cap);
+    }
     hipGraph_t graph = nullptr;
     BCHK(hipStreamBeginCapture(b->origin, hipStreamCaptureModeThreadLocal));
     try {
-        BCHK(hipEventRecord(b->fork, b->origin));
-        for (auto s : b->streams) BCHK(hipStreamWaitEvent(s, b->fork, 0));
-        for (int i = 0; i < k; i++)
-            for (ffpic_ctx *c : b->ctx) ffpic::steps_one_by_one(c, 1);
-        for (size_t s = 0; s < b->streams.size(); s++) {
-            BCHK(hipEventRecord(b->join[s], b->streams[s]));
-            BCHK(hipStreamWaitEvent(b->origin, b->join[s], 0));
+        if (grouped) {
+            for (int i = 0; i < k; i++) grouped_step(b, b->origin, T);
+        } else {
+            BCHK(hipEventRecord(b->fork, b->origin));
+            for (auto s : b->streams) BCHK(hipStreamWaitEvent(s, b->fork, 0));
+            for (int i = 0; i < k; i++)
+                for (ffpic_ctx *c : b->ctx) ffpic::steps_one_by_one(c, 1);
+            for (size_t s = 0; s < b->streams.size(); s++) {
+                BCHK(hipEventRecord(b->join[s], b->streams[s]));
+                BCHK(hipStreamWaitEvent(b->origin, b->join[s], 0));
+            }
         }
     } catch (...) {
         (void)hipStreamEndCapture(b->origin, &graph);
@@ -213,15 +391,28 @@ void run_batch_cycle(ffpic_batch *b, int k) {
         restore();
         throw BFail{FFPIC_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e)};
     }
+    if (grouped) {
+        // the tables the captured launches read, in place before the first
+        // replay
+        const hipError_t ec = hipMemcpy(T.dev, T.host.data(), T.host.size(), hipMemcpyHostToDevice);
+        if (ec != hipSuccess) {
+            (void)hipGraphExecDestroy(exec);
+            restore();
+            throw BFail{FFPIC_EHIP, std::string("job tables: ") + hipGetErrorString(ec)};
+        }
+    }
     if (b->graphs.size() >= 4) destroy_batch_graphs(b);
     BatchGraph g;
     g.steps = k;
+    g.mode = grouped ? 2 : 1;
     g.pre = pre;
     for (ffpic_ctx *c : b->ctx) g.post.push_back(ffpic::get_cycle_state(c));
     g.exec = exec;
+    g.tables = T.dev;
     b->graphs.push_back(std::move(g));
     b->graph_builds++;
     launch_batch_graph(b, exec);
+    if (grouped) b->grouped_launches++;
 }
 
 std::string cache_key(const ffpic_ctx *c) {
@@ -354,6 +545,87 @@ void tune_one(ffpic_ctx *c, double budget_ms, ffpic_tuning *out) {
                   << best.rows << ' ' << best.ppt << '\n';
         }
     }
+}
+
+// ms per batch step of whole batch cycles in graph mode `mode`, from the
+// state every system was checkpointed in: the steps to a common cycle start
+// and three cycles (a restored system's first sort is a full one, launched
+// step by step; then the graphs of both buffer parities are captured), then
+// one timed cycle
+double time_batch_mode(ffpic_batch *b, int mode, const std::vector<std::vector<char>> &ckpt,
+                       int cycle) {
+    for (size_t q = 0; q < b->ctx.size(); q++) {
+        const int rc = ffpic_restore(b->ctx[q], ckpt[q].data(), ckpt[q].size());
+        if (rc != FFPIC_OK) throw BFail{rc, ffpic_last_error(b->ctx[q])};
+    }
+    if (mode != b->graph_mode) destroy_batch_graphs(b);
+    b->graph_mode = mode;
+    int64_t lead = 0;   // steps to the next common cycle start
+    for (ffpic_ctx *c : b->ctx) lead = std::max<int64_t>(lead, (cycle - c->step % cycle) % cycle);
+    int rc = ffpic_batch_step(b, (int32_t)(lead + 3 * cycle));
+    if (rc == FFPIC_OK) rc = ffpic_batch_sync(b);
+    if (rc != FFPIC_OK) throw BFail{rc, b->last_error};
+    hipEvent_t e0, e1;
+    BCHK(hipEventCreate(&e0));
+    BCHK(hipEventCreate(&e1));
+    BCHK(hipEventRecord(e0, b->caller));
+    rc = ffpic_batch_step(b, cycle);
+    BCHK(hipEventRecord(e1, b->caller));
+    BCHK(hipEventSynchronize(e1));
+    float ms = 0;
+    BCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != FFPIC_OK) throw BFail{rc, b->last_error};
+    return ms / cycle;
+}
+
+// After each system's settings are tuned: for a batch that can run as
+// grouped launches, time whole batch cycles with per-system graphs and with
+// grouped launches from the same checkpoint of every system, restore the
+// checkpoint and keep the faster mode.  Which one wins depends on the
+// batch: per-system graphs let one system's push overlap another's field
+// step; grouped launches need far fewer launches per step.
+void tune_batch_mode(ffpic_batch *b) {
+    b->mode_ms[0] = b->mode_ms[1] = b->mode_ms[2] = 0;
+    if (b->graph_mode == 0 || !grouped_possible(b)) return;
+    int64_t cycle = 1;
+    for (ffpic_ctx *c : b->ctx) {
+        // graph capture possible once the system has sorted (a restored
+        // system sorts in full first)
+        const int si = c->d.sort_interval;
+        if (si < 1 || !c->use_graph || c->timing || c->d.rr_ramp_n > 0) return;
+        cycle = cycle / std::gcd<int64_t>(cycle, si) * si;
+        if (cycle > 64) return;
+    }
+    const int keep = b->graph_mode;
+    std::vector<std::vector<char>> ckpt(b->ctx.size());
+    for (size_t q = 0; q < b->ctx.size(); q++) {
+        size_t len = 0;
+        int rc = ffpic_save(b->ctx[q], nullptr, &len);
+        if (rc == FFPIC_OK) {
+            ckpt[q].resize(len);
+            rc = ffpic_save(b->ctx[q], ckpt[q].data(), &len);
+        }
+        if (rc != FFPIC_OK) throw BFail{rc, ffpic_last_error(b->ctx[q])};
+    }
+    int best = keep;
+    try {
+        for (int mode : {1, 2}) b->mode_ms[mode] = time_batch_mode(b, mode, ckpt, (int)cycle);
+        best = b->mode_ms[2] < b->mode_ms[1] ? 2 : 1;
+    } catch (...) {
+        for (size_t q = 0; q < b->ctx.size(); q++)
+            (void)ffpic_restore(b->ctx[q], ckpt[q].data(), ckpt[q].size());
+        destroy_batch_graphs(b);
+        b->graph_mode = keep;
+        throw;
+    }
+    for (size_t q = 0; q < b->ctx.size(); q++) {
+        const int rc = ffpic_restore(b->ctx[q], ckpt[q].data(), ckpt[q].size());
+        if (rc != FFPIC_OK) throw BFail{rc, ffpic_last_error(b->ctx[q])};
+    }
+    destroy_batch_graphs(b);
+    b->graph_mode = best;
 }
 
 }  // namespace
@@ -517,11 +789,12 @@ int ffpic_batch_sync(ffpic_batch *b) {
     });
 }
 
-int ffpic_batch_set_graph(ffpic_batch *b, int on) {
+int ffpic_batch_set_graph(ffpic_batch *b, int mode) {
     return bguard(b, [&] {
         if (!b) throw BFail{FFPIC_EINVAL, "batch is NULL"};
-        b->use_graph = on != 0;
-        if (!b->use_graph) destroy_batch_graphs(b);
+        if (mode < 0 || mode > 2) throw BFail{FFPIC_EINVAL, "graph mode must be 0, 1 or 2"};
+        if (mode != b->graph_mode) destroy_batch_graphs(b);
+        b->graph_mode = mode;
     });
 }
 
@@ -529,6 +802,20 @@ int ffpic_batch_graph_stats(ffpic_batch *b, int64_t *builds, int64_t *launches) 
     if (!b) return FFPIC_EINVAL;
     if (builds) *builds = b->graph_builds;
     if (launches) *launches = b->graph_launches;
+    return FFPIC_OK;
+}
+
+int ffpic_batch_get_graph(const ffpic_batch *b, int32_t *mode, double ms_per_step[3]) {
+    if (!b || !mode) return FFPIC_EINVAL;
+    *mode = b->graph_mode;
+    if (ms_per_step)
+        for (int k = 0; k < 3; k++) ms_per_step[k] = b->mode_ms[k];
+    return FFPIC_OK;
+}
+
+int ffpic_batch_grouped_launches(const ffpic_batch *b, int64_t *launches) {
+    if (!b || !launches) return FFPIC_EINVAL;
+    *launches = b->grouped_launches;
     return FFPIC_OK;
 }
 
@@ -575,6 +862,7 @@ int ffpic_batch_autotune(ffpic_batch *b, double budget_ms, ffpic_tuning *out) {
             if (r != FFPIC_OK)
                 throw BFail{r, "system " + std::to_string(q) + ": " + ffpic_last_error(b->ctx[q])};
         }
+        tune_batch_mode(b);
     });
 }
 

@@ -46,6 +46,50 @@ __device__ __forceinline__ int count_wave_i(int *ctr, bool pred) {
     return (int)__popcll(m);
 }
 
+// A table entry that every lane reads alike (the job of a grouped launch),
+// copied into scalar registers: the first threads of the workgroup load one
+// word each into the LDS array `stage` (kJobWords words), and after a
+// barrier every wave takes the words from there with readfirstlane.  The
+// values then stay in scalar registers (or their spill lanes) through the
+// loops that use them: a load from device memory that the compiler knows
+// to be uniform and unchanging would instead be repeated inside those
+// loops.  Only the first `bytes` bytes are copied.  Every thread of the
+// workgroup calls it; `stage` must not be written again before the next
+// barrier of all threads.
+constexpr int kJobWords = 96;
+template <typename T>
+__device__ __forceinline__ T stage_uniform(const T *src, uint32_t *stage,
+                                           size_t bytes = sizeof(T)) {
+    static_assert(sizeof(T) % 4 == 0 && sizeof(T) <= 4 * kJobWords, "whole words, fits the stage");
+    const int words = (int)(bytes / 4);
+    if ((int)threadIdx.x < words)
+        stage[threadIdx.x] = reinterpret_cast<const uint32_t *>(src)[threadIdx.x];
+    __syncthreads();
+    T out{};
+    char *d = reinterpret_cast<char *>(&out);
+#pragma unroll
+    for (int w = 0; w < (int)(sizeof(T) / 4); w++) {
+        if (w >= words) break;
+        const uint32_t v = __builtin_amdgcn_readfirstlane(stage[w]);
+        __builtin_memcpy(d + 4 * w, &v, 4);
+    }
+    return out;
+}
+
+// End of a launch of persistent workgroups that take their work items from
+// the counter ctr[0]: each workgroup counts itself finished in ctr[1] after
+// its last take (fenced), so the last one to finish knows that no take is
+// left and returns both counters to zero for the next launch.
+__device__ __forceinline__ void group_done(int *ctr) {
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(&ctr[1], 1) == (int)gridDim.x - 1) {
+            atomicExch(&ctr[0], 0);
+            atomicExch(&ctr[1], 0);
+        }
+    }
+}
+
 }  // namespace ffpic
 
 namespace ffpic {

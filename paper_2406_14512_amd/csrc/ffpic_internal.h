@@ -254,10 +254,38 @@ void steps_one_by_one(ffpic_ctx *c, int n);
 // whether the next sort cycle can be replayed from a graph, and the host
 // state such a replay starts from and leaves (see CycleState)
 bool graphable_cycle(const ffpic_ctx *c);
+bool step_sorts(const ffpic_ctx *c);    // the step about to be taken sorts
 CycleState get_cycle_state(const ffpic_ctx *c);
 void put_cycle_state(ffpic_ctx *c, const CycleState &st);
 // dev_out: ngamma + nnu + 1 doubles (dN, sed, prad)
 void spectra(ffpic_ctx *c, int s, const ffpic_spectra_req *req, double *dev_out);
+
+// Grouped launches over several FP32-mixed contexts: each *_job call writes
+// one context's job (the arguments its launch would take) into out, does
+// the host bookkeeping that follows the launch, and returns the job's number
+// of work items; the *_group_launch calls run the jobs of a table in device
+// memory (job k owns items [starts[k], starts[k + 1])) on persistent
+// workgroups (grid of them) that take items from the counter pair ctr
+// (zero before the launch, zero again after it).
+size_t push_job_bytes();
+int push_group_key(const ffpic_ctx *c, int s);    // kernel instance, 0..11
+int push_job(ffpic_ctx *c, int s, void *out);
+int push_group_slots(int key);
+void push_group_launch(hipStream_t st, int key, const void *jobs, const int *starts, int njobs,
+                       int grid, int *ctr);
+size_t field_job_bytes();
+int field_job(ffpic_ctx *c, void *out, int *key); // key: kernel instance, 0..7
+int field_group_slots(int key);
+void field_group_launch(hipStream_t st, int key, const void *jobs, const int *starts, int njobs,
+                        int grid, int *ctr);
+size_t psi_job_bytes();
+size_t mask_job_bytes();
+int psi_job32(const ffpic_ctx *c, void *out);
+int mask_job32(const ffpic_ctx *c, void *out);
+int psi_group_slots();
+void psi_group_launch(hipStream_t st, const void *jobs, const int *starts, int njobs, int grid,
+                      int *ctr);
+void mask_group_launch(hipStream_t st, const void *jobs, const int *starts, int njobs, int grid);
 
 }  // namespace ffpic
 

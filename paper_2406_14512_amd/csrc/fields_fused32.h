@@ -377,26 +377,31 @@ struct F32Kernel {
     }
 };
 
-// RE: bit k set when component k of the background rate curl B0 is
-// loaded (the others are zero); RB: the background rate -curl E0 is loaded
+// LDS of one workgroup of the FP32 field step
+template <bool FF>
+struct F32Smem {
+    float lE[2][4][kFzT];
+    float lB[4][4][kFzT];
+    float lN[FF ? 2 : 1][kFzT];
+    float lF[FF ? 3 : 1][kFzT];
+    float lEa[FF ? 2 : 1][kFzT];
+    float lD[FF ? 2 : 1][kFzT];
+    float lEf[2][2][kFzT];
+};
+
+// One strip of columns (bx) over one slab of rows (by).  Every thread of
+// the workgroup calls it and returns from it together.
 template <bool FF, int RE, bool RB>
-__global__ void __launch_bounds__(kFzT) k_field_f32(const F32Args A,
-                                                    const float4 *__restrict__ rowc) {
-    __shared__ float lE[2][4][kFzT];
-    __shared__ float lB[4][4][kFzT];
-    __shared__ float lN[FF ? 2 : 1][kFzT];
-    __shared__ float lF[FF ? 3 : 1][kFzT];
-    __shared__ float lEa[FF ? 2 : 1][kFzT];
-    __shared__ float lD[FF ? 2 : 1][kFzT];
-    __shared__ float lEf[2][2][kFzT];
+__device__ __forceinline__ void field_block(const F32Args &A, const float4 *__restrict__ rowc,
+                                            int bx, int by, F32Smem<FF> &L) {
     F32Kernel<FF, RE, RB> K{A, rowc};
     K.nr = A.nr; K.nth = A.nth; K.ld = A.ld;
     K.t = threadIdx.x;
-    K.j = (int)blockIdx.x * kFzW + K.t - kFzL;
+    K.j = bx * kFzW + K.t - kFzL;
     K.jc = (unsigned)min(max(K.j, 0), K.nth);
     K.tl = K.t > 0 ? K.t - 1 : K.t;
     K.tr = K.t < kFzT - 1 ? K.t + 1 : K.t;
-    K.i0 = (int)blockIdx.y * A.rows;
+    K.i0 = by * A.rows;
     K.iL = min(K.i0 + A.rows - 1, K.nr);
     K.qs = max(K.i0 - 2, 0);
     K.jlt = K.j < K.nth;
@@ -406,7 +411,8 @@ __global__ void __launch_bounds__(kFzT) k_field_f32(const F32Args A,
     const float4 cc0 = A.colc[K.jc * kColC], cc1 = A.colc[K.jc * kColC + 1];
     K.sn_j = cc0.x; K.sn_j1 = cc0.y; K.cA_j = cc0.z; K.sh_j = cc0.w;
     K.sh_jm = cc1.x; K.cdcd_j = cc1.y; K.csh_j = cc1.z; K.cdthd_j = cc1.w;
-    K.lE = lE; K.lB = lB; K.lN = lN; K.lF = lF; K.lEa = lEa; K.lD = lD; K.lEf = lEf;
+    K.lE = L.lE; K.lB = L.lB; K.lN = L.lN; K.lF = L.lF; K.lEa = L.lEa; K.lD = L.lD;
+    K.lEf = L.lEf;
     // prologue: E^n state and E0 of the first row
     {
         const unsigned o = K.off(K.qs);
@@ -425,10 +431,108 @@ __global__ void __launch_bounds__(kFzT) k_field_f32(const F32Args A,
     }
 }
 
+// RE: bit k set when component k of the background rate curl B0 is
+// loaded (the others are zero); RB: the background rate -curl E0 is loaded
+template <bool FF, int RE, bool RB>
+__global__ void __launch_bounds__(kFzT) k_field_f32(const F32Args A,
+                                                    const float4 *__restrict__ rowc) {
+    __shared__ F32Smem<FF> L;
+    field_block<FF, RE, RB>(A, rowc, (int)blockIdx.x, (int)blockIdx.y, L);
+}
+
+// one system's field step in a grouped launch: its arguments, its row
+// coefficients and its strips (the slabs are items / strips)
+struct F32Job {
+    F32Args A;
+    const float4 *rowc;
+    int strips;
+};
+
+// The field steps of many systems in one launch of persistent workgroups,
+// which take (system, strip, slab) items from a counter in device memory;
+// job k owns items [starts[k], starts[k + 1]).
+template <bool FF, int RE, bool RB>
+__global__ void __launch_bounds__(kFzT) k_field_f32_group(const F32Job *__restrict__ jobs,
+                                                          const int *__restrict__ starts,
+                                                          int njobs, int *__restrict__ ctr) {
+    __shared__ F32Smem<FF> L;
+    __shared__ int next;
+    __shared__ uint32_t stage[kJobWords];
+    const int total = starts[njobs];
+    while (true) {
+        if (threadIdx.x == 0) next = atomicAdd(&ctr[0], 1);
+        __syncthreads();
+        const int item = __builtin_amdgcn_readfirstlane(next);
+        if (item >= total) break;
+        int lo = 0, hi = njobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (starts[mid] <= item) lo = mid; else hi = mid - 1;
+        }
+        const F32Job J = stage_uniform(jobs + lo, stage);
+        const int local = item - starts[lo];
+        const int by = local / J.strips;
+        field_block<FF, RE, RB>(J.A, J.rowc, local - by * J.strips, by, L);
+        __syncthreads();
+    }
+    group_done(ctr);
+}
+
 // row and column coefficient tables of the FP32 step (host, FP64, rounded)
 void fused32_tables(const ffpic_ctx *c, std::vector<float> &rowc, std::vector<float> &colc);
 
-static void run_field_f32(ffpic_ctx *c) {
+using F32Kern = void (*)(const F32Args, const float4 *);
+using F32GroupKern = void (*)(const F32Job *, const int *, int, int *);
+
+// kernel instance index: force-free domain on or off; which background
+// rates are read (curl B0: only E_phi's, or all three; -curl E0: none or all)
+static int f32_key(const ffpic_ctx *c, const F32Args &A) {
+    const bool ff = c->d.ff_enable != 0;
+    const bool re_all = (A.rates & 3u) != 0, rb = (A.rates >> 3) != 0;
+    return (ff ? 4 : 0) + (re_all ? 2 : 0) + (rb ? 1 : 0);
+}
+
+static F32Kern f32_kern(int key) {
+    switch (key) {
+    case 0: return k_field_f32<false, 4, false>;
+    case 1: return k_field_f32<false, 4, true>;
+    case 2: return k_field_f32<false, 7, false>;
+    case 3: return k_field_f32<false, 7, true>;
+    case 4: return k_field_f32<true, 4, false>;
+    case 5: return k_field_f32<true, 4, true>;
+    case 6: return k_field_f32<true, 7, false>;
+    default: return k_field_f32<true, 7, true>;
+    }
+}
+
+static F32GroupKern f32_group_kern(int key) {
+    switch (key) {
+    case 0: return k_field_f32_group<false, 4, false>;
+    case 1: return k_field_f32_group<false, 4, true>;
+    case 2: return k_field_f32_group<false, 7, false>;
+    case 3: return k_field_f32_group<false, 7, true>;
+    case 4: return k_field_f32_group<true, 4, false>;
+    case 5: return k_field_f32_group<true, 4, true>;
+    case 6: return k_field_f32_group<true, 7, false>;
+    default: return k_field_f32_group<true, 7, true>;
+    }
+}
+
+static int occupancy_slots(const void *kern, int threads, int fallback_per_cu) {
+    int per_cu = 0, cus = 0, dev = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, 0) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        per_cu = fallback_per_cu;
+        cus = 256;
+    }
+    return std::max(1, per_cu) * std::max(1, cus);
+}
+
+// the arguments of a context's FP32 field step, and the buffer swaps that
+// follow its launch
+static F32Args f32_args(ffpic_ctx *c) {
     F32Args A{};
     A.nr = c->nr; A.nth = c->nth; A.ld = c->ld;
     A.absorb0 = c->absorb_row0;
@@ -452,38 +556,27 @@ static void run_field_f32(ffpic_ctx *c) {
     A.rho0 = (const float *)c->rho0;
     A.f = (const float *)c->f;
     A.colc = (const float4 *)c->fz_colc;
-    // the kernel instance: force-free domain on or off; which background
-    // rates are read (curl B0: only E_phi's, or all three; -curl E0: none or all)
-    const bool ff = c->d.ff_enable != 0;
-    const bool re_all = (A.rates & 3u) != 0, rb = (A.rates >> 3) != 0;
-    using KFn = void (*)(const F32Args, const float4 *);
-    KFn kern;
-    if (ff) kern = re_all ? (rb ? k_field_f32<true, 7, true> : k_field_f32<true, 7, false>)
-                          : (rb ? k_field_f32<true, 4, true> : k_field_f32<true, 4, false>);
-    else kern = re_all ? (rb ? k_field_f32<false, 7, true> : k_field_f32<false, 7, false>)
-                       : (rb ? k_field_f32<false, 4, true> : k_field_f32<false, 4, false>);
-    if (c->fused_slots == 0) {
-        int per_cu = 0, cus = 0, dev = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kern, kFzT, 0) !=
-                hipSuccess ||
-            hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
-            (void)hipGetLastError();
-            per_cu = 3;
-            cus = 256;
-        }
-        c->fused_slots = std::max(1, per_cu * cus);
-    }
+    if (c->fused_slots == 0)
+        c->fused_slots = occupancy_slots((const void *)f32_kern(f32_key(c, A)), kFzT, 3);
     A.rows = fused_rows(c);
-    dim3 grd((c->nth + 1 + kFzW - 1) / kFzW, (c->nr + 1 + A.rows - 1) / A.rows);
-    const float4 *rowc = (const float4 *)c->fz_rowc;
-    hipLaunchKernelGGL(kern, grd, dim3(kFzT), 0, c->stream, A, rowc);
-    FFPIC_LAUNCH_CHECK();
+    return A;
+}
+
+static void after_field_f32(ffpic_ctx *c) {
     for (int k = 0; k < 3; k++) {
         std::swap(c->dE[k], c->stAlt[k]);
         std::swap(c->dB[k], c->stAlt[3 + k]);
         std::swap(c->J[k], c->Jalt[k]);
     }
+}
+
+static void run_field_f32(ffpic_ctx *c) {
+    const F32Args A = f32_args(c);
+    dim3 grd((c->nth + 1 + kFzW - 1) / kFzW, (c->nr + 1 + A.rows - 1) / A.rows);
+    const float4 *rowc = (const float4 *)c->fz_rowc;
+    hipLaunchKernelGGL(f32_kern(f32_key(c, A)), grd, dim3(kFzT), 0, c->stream, A, rowc);
+    FFPIC_LAUNCH_CHECK();
+    after_field_f32(c);
 }
 
 }  // namespace ffpic

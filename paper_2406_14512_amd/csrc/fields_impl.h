@@ -29,24 +29,37 @@ __device__ __forceinline__ void lds_barrier() {
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
+// the arguments of one system's flux function
 template <typename R>
-__global__ void __launch_bounds__(kPsiCols) k_psi(Geo<double> g, const R *__restrict__ br,
-                                                  double *__restrict__ psi) {
-    __shared__ double tile[kPsiRows][kPsiCols + 1];
+struct PsiJob {
+    int nr, nth, ld;
+    int blocks;                // workgroups of kPsiRows rows
+    const double *rn2, *dcn;   // r_i^2, cos theta_j - cos theta_{j+1}
+    const R *br;
+    double *psi;
+};
+
+// rows [bx * kPsiRows, ...) of one system; every thread of the workgroup
+// calls it and returns from it together
+template <typename R>
+__device__ __forceinline__ void psi_block(const PsiJob<R> &P, int bx,
+                                          double (*tile)[kPsiCols + 1]) {
     const int t = threadIdx.x;
-    const int i0 = blockIdx.x * kPsiRows;
-    const int ld = g.ld, nr = g.nr, nth = g.nth;
+    const int i0 = bx * kPsiRows;
+    const int ld = P.ld, nr = P.nr, nth = P.nth;
+    const R *__restrict__ br = P.br;
+    double *__restrict__ psi = P.psi;
     const int rows = min(kPsiRows, nr + 1 - i0);
     double r2[kPsiRows];
 #pragma unroll
-    for (int rr = 0; rr < kPsiRows; rr++) r2[rr] = rr < rows ? g.rn2[i0 + rr] : 0.0;
+    for (int rr = 0; rr < kPsiRows; rr++) r2[rr] = rr < rows ? P.rn2[i0 + rr] : 0.0;
     double acc = 0.0;
     if (t < rows) psi[ix(ld, i0 + t, 0)] = 0.0;
     // The tile's B_r and column areas are loaded one tile ahead.
     R nxt[kPsiRows];
     double arn;
     auto load = [&](int jt) {
-        arn = jt + t < nth ? g.dcn[jt + t] : 0.0;
+        arn = jt + t < nth ? P.dcn[jt + t] : 0.0;
 #pragma unroll
         for (int rr = 0; rr < kPsiRows; rr++)
             nxt[rr] = (rr < rows && jt + t < nth) ? br[ix(ld, i0 + rr, jt + t)] : (R)0;
@@ -91,24 +104,92 @@ __global__ void __launch_bounds__(kPsiCols) k_psi(Geo<double> g, const R *__rest
     }
 }
 
-// blending function f at nodes (eq. transition, four thresholds) and the
-// kill flag of each cell (all four corners at f = 1)
 template <typename R>
-__global__ void k_mask(int nr, int nth, int ld, int ff, double t0, double t1, double t2,
-                       double t3, const double *__restrict__ psi, R *__restrict__ f,
-                       uint8_t *__restrict__ kill) {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
-    int i = blockIdx.y;
+__global__ void __launch_bounds__(kPsiCols) k_psi(const PsiJob<R> P) {
+    __shared__ double tile[kPsiRows][kPsiCols + 1];
+    psi_block<R>(P, (int)blockIdx.x, tile);
+}
+
+// the arguments of one system's mask
+template <typename R>
+struct MaskJob {
+    int nr, nth, ld, ff;
+    int cblocks;               // workgroups of 256 columns per row
+    double t0, t1, t2, t3;
+    const double *psi;
+    R *f;
+    uint8_t *kill;
+};
+
+// blending function f at nodes (eq. transition, four thresholds) and the
+// kill flag of each cell (all four corners at f = 1): columns from bx * 256
+// of row i
+template <typename R>
+__device__ __forceinline__ void mask_row(const MaskJob<R> &M, int bx, int i) {
+    const int j = bx * 256 + (int)threadIdx.x;
+    const int nr = M.nr, nth = M.nth, ld = M.ld;
     if (j > nth) return;
-    double fv = ff ? blend(psi[ix(ld, i, j)], t0, t1, t2, t3) : 0.0;
-    f[ix(ld, i, j)] = (R)fv;
+    const double t0 = M.t0, t1 = M.t1, t2 = M.t2, t3 = M.t3;
+    const double *__restrict__ psi = M.psi;
+    double fv = M.ff ? blend(psi[ix(ld, i, j)], t0, t1, t2, t3) : 0.0;
+    M.f[ix(ld, i, j)] = (R)fv;
     if (i < nr && j < nth) {
         bool k = false;
-        if (ff && fv == 1.0)
+        if (M.ff && fv == 1.0)
             k = blend(psi[ix(ld, i + 1, j)], t0, t1, t2, t3) == 1.0 &&
                 blend(psi[ix(ld, i, j + 1)], t0, t1, t2, t3) == 1.0 &&
                 blend(psi[ix(ld, i + 1, j + 1)], t0, t1, t2, t3) == 1.0;
-        kill[(size_t)i * nth + j] = k ? 1 : 0;
+        M.kill[(size_t)i * nth + j] = k ? 1 : 0;
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_mask(const MaskJob<R> M) {
+    mask_row<R>(M, (int)blockIdx.x, (int)blockIdx.y);
+}
+
+// The flux functions of many systems in one launch of persistent
+// workgroups taking row blocks from a counter (job k owns items
+// [starts[k], starts[k + 1])), and their masks in a second launch whose
+// workgroups stride over (system, row) items: a mask row is a few kB of
+// streaming, too little to be worth a counter.
+template <typename R>
+__global__ void __launch_bounds__(kPsiCols) k_psi_group(const PsiJob<R> *__restrict__ jobs,
+                                                        const int *__restrict__ starts,
+                                                        int njobs, int *__restrict__ ctr) {
+    __shared__ double tile[kPsiRows][kPsiCols + 1];
+    __shared__ int next;
+    __shared__ uint32_t stage[kJobWords];
+    const int total = starts[njobs];
+    while (true) {
+        if (threadIdx.x == 0) next = atomicAdd(&ctr[0], 1);
+        __syncthreads();
+        const int item = __builtin_amdgcn_readfirstlane(next);
+        if (item >= total) break;
+        int lo = 0, hi = njobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (starts[mid] <= item) lo = mid; else hi = mid - 1;
+        }
+        psi_block<R>(stage_uniform(jobs + lo, stage), item - starts[lo], tile);
+        __syncthreads();
+    }
+    group_done(ctr);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_mask_group(const MaskJob<R> *__restrict__ jobs,
+                                                    const int *__restrict__ starts, int njobs) {
+    const int total = starts[njobs];
+    for (int item = (int)blockIdx.x; item < total; item += (int)gridDim.x) {
+        int lo = 0, hi = njobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (starts[mid] <= item) lo = mid; else hi = mid - 1;
+        }
+        const MaskJob<R> &M = jobs[lo];
+        const int i = item - starts[lo];
+        for (int bx = 0; bx < M.cblocks; bx++) mask_row<R>(M, bx, i);
     }
 }
 
@@ -131,15 +212,37 @@ __device__ __forceinline__ void ff_node(const R e[3], const R b[3], R o[3]) {
 }
 
 template <typename R>
-static void run_psi_mask(ffpic_ctx *c) {
-    Geo<double> g = geo<double>(c);
-    hipLaunchKernelGGL(k_psi<R>, dim3((c->nr + 1 + kPsiRows - 1) / kPsiRows), dim3(kPsiCols), 0,
-                       c->stream, g, (const R *)c->B[0], c->psi);
-    dim3 blk(256), grd((c->nth + 1 + 255) / 256, c->nr + 1);
+PsiJob<R> psi_job(const ffpic_ctx *c) {
+    PsiJob<R> P;
+    P.nr = c->nr; P.nth = c->nth; P.ld = c->ld;
+    P.blocks = (c->nr + 1 + kPsiRows - 1) / kPsiRows;
+    P.rn2 = c->dtab64[T_RN2];
+    P.dcn = c->dtab64[T_DCN];
+    P.br = (const R *)c->B[0];
+    P.psi = c->psi;
+    return P;
+}
+
+template <typename R>
+MaskJob<R> mask_job(const ffpic_ctx *c) {
+    MaskJob<R> M;
+    M.nr = c->nr; M.nth = c->nth; M.ld = c->ld;
+    M.ff = c->d.ff_enable ? 1 : 0;
+    M.cblocks = (c->nth + 1 + 255) / 256;
     const double *t = c->d.psi_thr;
-    hipLaunchKernelGGL(k_mask<R>, grd, blk, 0, c->stream, c->nr, c->nth, c->ld,
-                       c->d.ff_enable ? 1 : 0, t[0], t[1], t[2], t[3], c->psi, (R *)c->f,
-                       c->kill);
+    M.t0 = t[0]; M.t1 = t[1]; M.t2 = t[2]; M.t3 = t[3];
+    M.psi = c->psi;
+    M.f = (R *)c->f;
+    M.kill = c->kill;
+    return M;
+}
+
+template <typename R>
+static void run_psi_mask(ffpic_ctx *c) {
+    const PsiJob<R> P = psi_job<R>(c);
+    hipLaunchKernelGGL(k_psi<R>, dim3(P.blocks), dim3(kPsiCols), 0, c->stream, P);
+    const MaskJob<R> M = mask_job<R>(c);
+    hipLaunchKernelGGL(k_mask<R>, dim3(M.cblocks, c->nr + 1), dim3(256), 0, c->stream, M);
     FFPIC_LAUNCH_CHECK();
 }
 

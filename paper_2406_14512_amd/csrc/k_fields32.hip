@@ -1,6 +1,8 @@
 // FP32 instantiation of the field-step kernels (perturbation form about the
 // FP64 background); the flux function is still integrated in FP64 (from the
 // FP32 B_r) so the force-free / PIC boundary is set at FP64 accuracy.
+#include <cstring>
+
 #include "fields_fused32.h"
 
 namespace ffpic {
@@ -58,4 +60,61 @@ void fused32_tables(const ffpic_ctx *c, std::vector<float> &rowc, std::vector<fl
 
 void field_step32(ffpic_ctx *c) { run_field_f32(c); }
 void psi_mask32(ffpic_ctx *c) { run_psi_mask<float>(c); }
+
+// ---- grouped launches over several FP32 contexts (batches)
+
+size_t field_job_bytes() { return sizeof(F32Job); }
+
+int field_job(ffpic_ctx *c, void *out, int *key) {
+    F32Job J;
+    J.A = f32_args(c);
+    J.rowc = (const float4 *)c->fz_rowc;
+    J.strips = (c->nth + 1 + kFzW - 1) / kFzW;
+    const int slabs = (c->nr + 1 + J.A.rows - 1) / J.A.rows;
+    *key = f32_key(c, J.A);
+    std::memcpy(out, &J, sizeof(J));
+    after_field_f32(c);
+    return J.strips * slabs;
+}
+
+int field_group_slots(int key) {
+    return occupancy_slots((const void *)f32_group_kern(key), kFzT, 3);
+}
+
+void field_group_launch(hipStream_t st, int key, const void *jobs, const int *starts, int njobs,
+                        int grid, int *ctr) {
+    hipLaunchKernelGGL(f32_group_kern(key), dim3(grid), dim3(kFzT), 0, st,
+                       (const F32Job *)jobs, starts, njobs, ctr);
+    FFPIC_LAUNCH_CHECK();
+}
+
+size_t psi_job_bytes() { return sizeof(PsiJob<float>); }
+size_t mask_job_bytes() { return sizeof(MaskJob<float>); }
+
+int psi_job32(const ffpic_ctx *c, void *out) {
+    const PsiJob<float> P = psi_job<float>(c);
+    std::memcpy(out, &P, sizeof(P));
+    return P.blocks;
+}
+
+int mask_job32(const ffpic_ctx *c, void *out) {
+    const MaskJob<float> M = mask_job<float>(c);
+    std::memcpy(out, &M, sizeof(M));
+    return c->nr + 1;
+}
+
+int psi_group_slots() { return occupancy_slots((const void *)k_psi_group<float>, kPsiCols, 4); }
+
+void psi_group_launch(hipStream_t st, const void *jobs, const int *starts, int njobs, int grid,
+                      int *ctr) {
+    hipLaunchKernelGGL(k_psi_group<float>, dim3(grid), dim3(kPsiCols), 0, st,
+                       (const PsiJob<float> *)jobs, starts, njobs, ctr);
+    FFPIC_LAUNCH_CHECK();
+}
+
+void mask_group_launch(hipStream_t st, const void *jobs, const int *starts, int njobs, int grid) {
+    hipLaunchKernelGGL(k_mask_group<float>, dim3(grid), dim3(256), 0, st,
+                       (const MaskJob<float> *)jobs, starts, njobs);
+    FFPIC_LAUNCH_CHECK();
+}
 }  // namespace ffpic

@@ -40,6 +40,10 @@
 // zigzag runs in one wave per chunk rather than in nearly every wave.
 // Chunks whose box is too large for the patches (sparse regions) gather
 // from HBM through buffer resources and add straight to HBM.
+#include <algorithm>
+#include <cstddef>
+#include <cstring>
+
 #include "device_common.h"
 
 namespace ffpic {
@@ -541,31 +545,49 @@ __device__ __forceinline__ void push_chunk(const P32 &p, const Fields &F, const 
     }
 }
 
-// six waves per SIMD: the prefetched momentum fits in 80 VGPRs without spills
+// Everything one push of one species reads from the host, by value: the
+// single-system kernel takes it as its argument, the grouped kernel reads
+// each system's from a table in device memory.
+struct PushJob {
+    P32 p;
+    int nub;                             // slot bound known to the host
+    const int32_t *nslots;               // slot count on the device
+    const uint8_t *kill;
+    const float *E[3], *B[3];
+    int32_t *cell;
+    float *a, *b, *ur, *ut, *up;
+    float *J[3];
+    unsigned long long *removed;         // this species' removal counters
+    uint32_t *err;
+    SortPlace SP;                        // placing push: where each slot goes
+};
+
+struct PushSmem {
+    float *tile, *fld;
+    float4 *queue;
+    int *box, *qn;
+};
+
+// One chunk of kWG * kPPT slots.  Every thread of the workgroup calls it
+// and returns from it together.
 template <bool SHELL, int kPPT, bool PLACE>
-__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(6, 8))) k_push32(
-    P32 p, int nub, const int32_t *__restrict__ nslots, const uint8_t *__restrict__ kill,
-    const float *__restrict__ Er, const float *__restrict__ Et, const float *__restrict__ Ep,
-    const float *__restrict__ Br, const float *__restrict__ Bt, const float *__restrict__ Bp,
-    int32_t *__restrict__ CELL, float *__restrict__ A, float *__restrict__ Bo,
-    float *__restrict__ UR, float *__restrict__ UT, float *__restrict__ UP,
-    float *__restrict__ Jr, float *__restrict__ Jt, float *__restrict__ Jp,
-    unsigned long long *__restrict__ removed, uint32_t *__restrict__ err, SortPlace SP) {
-    __shared__ float tile[3 * kTile];
-    __shared__ float fld[6 * kFld];
-    __shared__ float4 queue[2 * kQueue];
-    __shared__ int box[4];
-    __shared__ int qn;
+__device__ __forceinline__ void push_block(const PushJob &J, int chunk, const PushSmem &sm) {
+    const P32 &p = J.p;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
+    float *tile = sm.tile, *fld = sm.fld;
+    int *box = sm.box;
     // PLACE: the slots before the sort (the slot count already holds the
     // new order's)
-    const int n = min(nub, nslots[PLACE ? 2 : 0]);
+    const int n = min(J.nub, J.nslots[PLACE ? 2 : 0]);
     constexpr int kChunk = kWG * kPPT;
-    const int base = blockIdx.x * kChunk;
+    const int base = chunk * kChunk;
     // slots are below 2^30 (the capacity limit), so the byte offset q * 4
     // fits 32 unsigned bits
-    const State S{CELL, A, Bo, UR, UT, UP};
+    const State S{J.cell, J.a, J.b, J.ur, J.ut, J.up};
+    const float *Er = J.E[0], *Et = J.E[1], *Ep = J.E[2];
+    const float *Br = J.B[0], *Bt = J.B[1], *Bp = J.B[2];
+    float *Jr = J.J[0], *Jt = J.J[1], *Jp = J.J[2];
 
     // bounding box of the chunk's cells
     int imin = 1 << 30, imax = -1, jmin = 1 << 30, jmax = -1;
@@ -581,7 +603,7 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(6, 8))
     }
     if (tid == 0) {
         box[0] = 1 << 30; box[1] = -1; box[2] = 1 << 30; box[3] = -1;
-        qn = 0;
+        *sm.qn = 0;
     }
     __syncthreads();
     for (int o = 32; o >= 1; o >>= 1) {
@@ -625,8 +647,9 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(6, 8))
         __syncthreads();
         const Patch P{fld, fi0, fj0, (unsigned)TJf * 24u};
         Acc<true> acc{tile, ti0, tj0, TJ, {Jr, Jt, Jp}, p.ld};
-        push_chunk<true, SHELL, kPPT, PLACE>(p, Fields{}, P, acc, n, base, tid, lane, kill, S, err, nkill, nstar,
-                                nabs, queue, &qn, nullptr, SP);
+        push_chunk<true, SHELL, kPPT, PLACE>(p, Fields{}, P, acc, n, base, tid, lane, J.kill, S,
+                                             J.err, nkill, nstar, nabs, sm.queue, sm.qn, nullptr,
+                                             J.SP);
         __syncthreads();
         for (int e = tid; e < m; e += kWG) {
             const int ti = e / TJ, tj = e - ti * TJ;
@@ -653,8 +676,9 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(6, 8))
         Acc<false> acc{nullptr, 0, 0, 0, {Jr, Jt, Jp}, p.ld};
         const int kc = lane_comp(lane);
         float *kg = kc == 0 ? Jr : (kc == 1 ? Jt : Jp);
-        push_chunk<false, SHELL, kPPT, PLACE>(p, F, Patch{nullptr, 0, 0, 0u}, acc, n, base, tid, lane, kill, S, err, nkill, nstar,
-                                 nabs, queue, &qn, kg, SP);
+        push_chunk<false, SHELL, kPPT, PLACE>(p, F, Patch{nullptr, 0, 0, 0u}, acc, n, base, tid,
+                                              lane, J.kill, S, J.err, nkill, nstar, nabs,
+                                              sm.queue, sm.qn, kg, J.SP);
     }
     int tk = nkill, ts = nstar, ta = nabs;
     for (int o = 32; o >= 1; o >>= 1) {
@@ -663,16 +687,83 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(6, 8))
         ta += __shfl_xor(ta, o, 64);
     }
     if (lane == 0) {
-        if (tk) atomicAdd(&removed[1], (unsigned long long)tk);
-        if (ts) atomicAdd(&removed[2], (unsigned long long)ts);
-        if (ta) atomicAdd(&removed[3], (unsigned long long)ta);
+        if (tk) atomicAdd(&J.removed[1], (unsigned long long)tk);
+        if (ts) atomicAdd(&J.removed[2], (unsigned long long)ts);
+        if (ta) atomicAdd(&J.removed[3], (unsigned long long)ta);
     }
 }
 
-void push32(ffpic_ctx *c, int s) {
+// six waves per SIMD: the prefetched momentum fits in 80 VGPRs without spills
+template <bool SHELL, int kPPT, bool PLACE>
+__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(6, 8)))
+k_push32(const PushJob J) {
+    __shared__ float tile[3 * kTile];
+    __shared__ float fld[6 * kFld];
+    __shared__ float4 queue[2 * kQueue];
+    __shared__ int box[4];
+    __shared__ int qn;
+    push_block<SHELL, kPPT, PLACE>(J, (int)blockIdx.x, PushSmem{tile, fld, queue, box, &qn});
+}
+
+// The pushes of many systems in one launch of persistent workgroups: each
+// workgroup takes chunks (items) from a counter in device memory until none
+// is left.  Job k owns items [starts[k], starts[k + 1]).  The workgroup that
+// finishes last returns both counters to zero for the next launch.
+template <bool SHELL, int kPPT, bool PLACE>
+__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(6, 8)))
+k_push32_group(const PushJob *__restrict__ jobs, const int *__restrict__ starts, int njobs,
+               int *__restrict__ ctr) {
+    __shared__ float tile[3 * kTile];
+    __shared__ float fld[6 * kFld];
+    __shared__ float4 queue[2 * kQueue];
+    __shared__ int box[4];
+    __shared__ int qn;
+    __shared__ int next;
+    __shared__ uint32_t stage[kJobWords];
+    const PushSmem sm{tile, fld, queue, box, &qn};
+    const int total = starts[njobs];
+    while (true) {
+        if (threadIdx.x == 0) next = atomicAdd(&ctr[0], 1);
+        __syncthreads();
+        const int item = __builtin_amdgcn_readfirstlane(next);
+        if (item >= total) break;
+        int lo = 0, hi = njobs - 1;   // the job holding the item
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (starts[mid] <= item) lo = mid; else hi = mid - 1;
+        }
+        // a plain push reads no placement pointers (the job's last member)
+        const PushJob J =
+            stage_uniform(jobs + lo, stage, PLACE ? sizeof(PushJob) : offsetof(PushJob, SP));
+        push_block<SHELL, kPPT, PLACE>(J, item - starts[lo], sm);
+        __syncthreads();
+    }
+    group_done(ctr);
+}
+
+// the kernel instance of a species' push: particles per thread, shell,
+// placing
+struct PushKey {
+    int ppt;
+    bool shell, place;
+};
+
+PushKey push_key(const ffpic_ctx *c, int s) {
+    return {c->push_ppt == 8 || c->push_ppt == 32 ? c->push_ppt : 16,
+            c->d.shell_r > c->d.rmin, c->sort_pending[s]};
+}
+
+int push_key_index(const PushKey &k) {
+    return (k.ppt == 8 ? 0 : (k.ppt == 16 ? 1 : 2)) + (k.shell ? 3 : 0) + (k.place ? 6 : 0);
+}
+
+// the job of one species' push from the context's state, and the host
+// bookkeeping that follows the launch (a placing push leaves the new order
+// in the second buffer)
+PushJob make_push_job(ffpic_ctx *c, int s) {
     ffpic::Species &S = c->sp[s];
-    if (S.nub == 0) return;
-    P32 p;
+    PushJob J{};
+    P32 &p = J.p;
     p.nr = c->nr; p.nth = c->nth; p.ld = c->ld;
     p.dlog = (float)c->dlog; p.dth = (float)c->dth; p.dt = (float)c->dt;
     p.inv_dlog = (float)(1.0 / c->dlog);
@@ -692,38 +783,106 @@ void push32(ffpic_ctx *c, int s) {
     const double xs = shell ? log(c->d.shell_r / c->d.rmin) / c->dlog : 0.0;
     p.ishell = (int)floor(xs);
     p.ashell = (float)(xs - floor(xs));
-    float **E = (float **)c->E, **B = (float **)c->B, **J = (float **)c->J;
-    const int ppt = c->push_ppt == 8 || c->push_ppt == 32 ? c->push_ppt : 16;
-    const int chunk = kWG * ppt;
-    int nb = (int)((S.nub + chunk - 1) / chunk);
-    // after a sort whose placement was left to this push, it reads the old
-    // order and writes the new one into the second buffer
+    J.nub = (int)S.nub;
     const bool place = c->sort_pending[s];
-    using Kern = decltype(&k_push32<false, 16, false>);
-    Kern kern;
-    if (place)
-        kern = ppt == 8 ? (shell ? k_push32<true, 8, true> : k_push32<false, 8, true>)
-             : ppt == 32 ? (shell ? k_push32<true, 32, true> : k_push32<false, 32, true>)
-                         : (shell ? k_push32<true, 16, true> : k_push32<false, 16, true>);
-    else
-        kern = ppt == 8 ? (shell ? k_push32<true, 8, false> : k_push32<false, 8, false>)
-             : ppt == 32 ? (shell ? k_push32<true, 32, false> : k_push32<false, 32, false>)
-                         : (shell ? k_push32<true, 16, false> : k_push32<false, 16, false>);
-    SortPlace sp{};
-    if (place) sp = c->place[s];
     // the placing push runs over the slots before the sort: the third
     // entry of the sort's totals
-    const int32_t *nsl = place ? (const int32_t *)c->sort_tot[s] : c->nslots + s;
-    hipLaunchKernelGGL(kern, dim3(nb), dim3(kWG), 0, c->stream, p, (int)S.nub,
-                       nsl, c->kill, E[0], E[1], E[2], B[0], B[1], B[2],
-                       (int32_t *)S.cur[0], (float *)S.cur[1], (float *)S.cur[2],
-                       (float *)S.cur[3], (float *)S.cur[4], (float *)S.cur[5], J[0], J[1], J[2],
-                       c->removed + 4 * s, c->err, sp);
-    FFPIC_LAUNCH_CHECK();
-    if (place) {
+    J.nslots = place ? (const int32_t *)c->sort_tot[s] : c->nslots + s;
+    J.kill = c->kill;
+    for (int k = 0; k < 3; k++) {
+        J.E[k] = (const float *)c->E[k];
+        J.B[k] = (const float *)c->B[k];
+        J.J[k] = (float *)c->J[k];
+    }
+    J.cell = (int32_t *)S.cur[0];
+    J.a = (float *)S.cur[1];
+    J.b = (float *)S.cur[2];
+    J.ur = (float *)S.cur[3];
+    J.ut = (float *)S.cur[4];
+    J.up = (float *)S.cur[5];
+    J.removed = c->removed + 4 * s;
+    J.err = c->err;
+    if (place) J.SP = c->place[s];
+    return J;
+}
+
+void after_push(ffpic_ctx *c, int s) {
+    ffpic::Species &S = c->sp[s];
+    if (c->sort_pending[s]) {
         for (int a = 0; a < S.narr; a++) std::swap(S.cur[a], S.alt[a]);
         c->sort_pending[s] = false;
     }
+}
+
+using PushKern = void (*)(const PushJob);
+using PushGroupKern = void (*)(const PushJob *, const int *, int, int *);
+
+template <bool SHELL, bool PLACE>
+PushKern push_kern(int ppt) {
+    return ppt == 8 ? k_push32<SHELL, 8, PLACE>
+                    : (ppt == 32 ? k_push32<SHELL, 32, PLACE> : k_push32<SHELL, 16, PLACE>);
+}
+template <bool SHELL, bool PLACE>
+PushGroupKern push_group_kern(int ppt) {
+    return ppt == 8 ? k_push32_group<SHELL, 8, PLACE>
+                    : (ppt == 32 ? k_push32_group<SHELL, 32, PLACE>
+                                 : k_push32_group<SHELL, 16, PLACE>);
+}
+
+void push32(ffpic_ctx *c, int s) {
+    ffpic::Species &S = c->sp[s];
+    if (S.nub == 0) return;
+    const PushKey k = push_key(c, s);
+    const PushJob J = make_push_job(c, s);
+    const int chunk = kWG * k.ppt;
+    const int nb = (int)((S.nub + chunk - 1) / chunk);
+    const PushKern kern = k.shell ? (k.place ? push_kern<true, true>(k.ppt) : push_kern<true, false>(k.ppt))
+                                  : (k.place ? push_kern<false, true>(k.ppt) : push_kern<false, false>(k.ppt));
+    hipLaunchKernelGGL(kern, dim3(nb), dim3(kWG), 0, c->stream, J);
+    FFPIC_LAUNCH_CHECK();
+    after_push(c, s);
+}
+
+// ---- grouped pushes of several contexts (batches)
+
+size_t push_job_bytes() { return sizeof(PushJob); }
+
+int push_group_key(const ffpic_ctx *c, int s) { return push_key_index(push_key(c, s)); }
+
+int push_job(ffpic_ctx *c, int s, void *out) {
+    ffpic::Species &S = c->sp[s];
+    const PushKey k = push_key(c, s);
+    const PushJob J = make_push_job(c, s);
+    std::memcpy(out, &J, sizeof(J));
+    after_push(c, s);
+    const int chunk = kWG * k.ppt;
+    return (int)((S.nub + chunk - 1) / chunk);
+}
+
+static PushGroupKern group_kern_of(int key) {
+    const int ppt = key % 3 == 0 ? 8 : (key % 3 == 1 ? 16 : 32);
+    const bool shell = (key / 3) % 2 != 0, place = key >= 6;
+    return shell ? (place ? push_group_kern<true, true>(ppt) : push_group_kern<true, false>(ppt))
+                 : (place ? push_group_kern<false, true>(ppt) : push_group_kern<false, false>(ppt));
+}
+
+int push_group_slots(int key) {
+    int per_cu = 0, cus = 0, dev = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)group_kern_of(key), kWG,
+                                                     0) != hipSuccess ||
+        hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 1024;
+    }
+    return std::max(1, per_cu) * std::max(1, cus);
+}
+
+void push_group_launch(hipStream_t st, int key, const void *jobs, const int *starts, int njobs,
+                       int grid, int *ctr) {
+    hipLaunchKernelGGL(group_kern_of(key), dim3(grid), dim3(kWG), 0, st,
+                       (const PushJob *)jobs, starts, njobs, ctr);
+    FFPIC_LAUNCH_CHECK();
 }
 
 }  // namespace ffpic

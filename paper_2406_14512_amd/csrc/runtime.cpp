@@ -1383,6 +1383,15 @@ int ffpic_set_field_rows(ffpic_ctx *c, int32_t rows) {
     });
 }
 
+int ffpic_set_push_chunk(ffpic_ctx *c, int32_t ppt) {
+    return guarded(c, [&] {
+        check_ctx(c);
+        if (ppt != 8 && ppt != 16 && ppt != 32)
+            throw Fail{FFPIC_EINVAL, "particles per thread must be 8, 16 or 32"};
+        c->push_ppt = ppt;
+    });
+}
+
 int ffpic_set_graph(ffpic_ctx *c, int on) {
     return guarded(c, [&] {
         check_ctx(c);
@@ -1419,6 +1428,8 @@ void steps_one_by_one(ffpic_ctx *c, int n) {
 }
 
 bool graphable_cycle(const ffpic_ctx *c) { return cycle_graphable(c); }
+
+bool step_sorts(const ffpic_ctx *c) { return (step_phases(c) & FFPIC_PHASE_SORT) != 0; }
 
 CycleState get_cycle_state(const ffpic_ctx *c) { return cycle_state(c); }
 

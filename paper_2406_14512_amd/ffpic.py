@@ -127,6 +127,8 @@ def lib():
     L.ffpic_set_graph.argtypes = [P, C.c_int]
     L.ffpic_batch_set_graph.argtypes = [P, C.c_int]
     L.ffpic_batch_graph_stats.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    L.ffpic_batch_grouped_launches.argtypes = [P, C.POINTER(C.c_int64)]
+    L.ffpic_batch_get_graph.argtypes = [P, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
     L.ffpic_graph_stats.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     L.ffpic_diagnostics.argtypes = [P, C.c_uint32, C.POINTER(Diag), vp]
     L.ffpic_diagnostics_noalloc.argtypes = [P, C.c_uint32, C.POINTER(Diag), vp]
@@ -136,6 +138,7 @@ def lib():
     L.ffpic_restore.argtypes = [P, vp, C.c_size_t]
     L.ffpic_set_timing.argtypes = [P, C.c_int]
     L.ffpic_set_field_rows.argtypes = [P, C.c_int32]
+    L.ffpic_set_push_chunk.argtypes = [P, C.c_int32]
     L.ffpic_phase_times.argtypes = [P, C.POINTER(C.c_float)]
     L.ffpic_batch_create.argtypes = [C.c_int, C.POINTER(Desc), vp, C.POINTER(P)]
     L.ffpic_batch_view.argtypes = [P, C.c_int, C.POINTER(P)]
@@ -158,8 +161,10 @@ def lib():
                  "ffpic_batch_destroy", "ffpic_autotune", "ffpic_batch_autotune",
                  "ffpic_spectra", "ffpic_host_table", "ffpic_host_initial_field",
                  "ffpic_diagnostics_noalloc", "ffpic_set_field_rows", "ffpic_record_sort",
+                 "ffpic_set_push_chunk",
                  "ffpic_set_graph", "ffpic_graph_stats", "ffpic_batch_set_graph",
-                 "ffpic_batch_graph_stats"):
+                 "ffpic_batch_graph_stats", "ffpic_batch_grouped_launches",
+                 "ffpic_batch_get_graph"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -381,6 +386,10 @@ class Sim:
         """Radial rows per workgroup of the fused field step (0 = automatic)."""
         self._chk(lib().ffpic_set_field_rows(self._h, int(rows)))
 
+    def set_push_chunk(self, ppt: int):
+        """Particles per thread of the FP32 push's chunks (8, 16 or 32)."""
+        self._chk(lib().ffpic_set_push_chunk(self._h, int(ppt)))
+
     def diagnostics(self, what: int = DIAG_ALL, poynting: bool = False,
                     noalloc: bool = False) -> Dict:
         """ffpic_diagnostics, or with noalloc the allocation-free
@@ -472,15 +481,34 @@ class Batch:
     def sync(self):
         self._chk(lib().ffpic_batch_sync(self._h))
 
-    def set_graph(self, on: bool):
-        """Graph capture of whole batch cycles (ffpic_batch_set_graph)."""
-        self._chk(lib().ffpic_batch_set_graph(self._h, int(bool(on))))
+    GRAPH_OFF, GRAPH_PER_SYSTEM, GRAPH_GROUPED = 0, 1, 2
+
+    def set_graph(self, mode):
+        """Graph capture of whole batch cycles (ffpic_batch_set_graph):
+        False / 0 off, 1 per-system launches, True / 2 grouped launches
+        of all systems where every system allows them (the default)."""
+        if isinstance(mode, bool):
+            mode = self.GRAPH_GROUPED if mode else self.GRAPH_OFF
+        self._chk(lib().ffpic_batch_set_graph(self._h, int(mode)))
 
     def graph_stats(self):
         """(graphs captured, graph launches) so far."""
         b, l = C.c_int64(0), C.c_int64(0)
         self._chk(lib().ffpic_batch_graph_stats(self._h, C.byref(b), C.byref(l)))
         return b.value, l.value
+
+    def get_graph(self):
+        """(graph mode in use, {mode: ms per batch step} the tuner measured)."""
+        m = C.c_int32(0)
+        t = (C.c_double * 3)()
+        self._chk(lib().ffpic_batch_get_graph(self._h, C.byref(m), t))
+        return m.value, {k: t[k] for k in range(3) if t[k] > 0}
+
+    def grouped_launches(self):
+        """How many graph launches ran grouped launches of all systems."""
+        n = C.c_int64(0)
+        self._chk(lib().ffpic_batch_grouped_launches(self._h, C.byref(n)))
+        return n.value
 
     def autotune(self, budget_ms: float):
         t = (Tuning * len(self.views))()

@@ -86,6 +86,75 @@ def test_batch_cycles_as_graphs_match_single_contexts(graph):
         assert launches == 4 and 1 <= builds <= 2, (builds, launches)
     else:
         assert (builds, launches) == (0, 0)
+    # FP64 systems: grouped launches are not used, the graphs hold every
+    # system's own launches
+    assert batch.grouped_launches() == 0
+    batch.close()
+    for s in singles:
+        s.close()
+
+
+def test_grouped_batch_graph_matches_single_contexts():
+    """Mode 2 (the default for FP32-mixed batches without plasma sources):
+    per step, one persistent launch each for the flux functions, masks,
+    pushes and field steps of all systems.  Three systems of different grids
+    and sort intervals (2 and 4, so that some steps sort only some systems
+    and the push launches mix placing and plain pushes) and a non-default
+    slab height on one of them, against each system stepped alone one step
+    at a time; every replay checked, with reads between the replays."""
+    ws = [W.tiny_open_dipole(20000), W.tiny_dipole(15000),
+          W.sheet_1024(n_total=60000, precision=W.FP32_MIXED)]
+    ws[1].nr, ws[1].nth = 96, 80
+    ws[2].nr = ws[2].nth = 192
+    ds = []
+    for w, si in zip(ws, (2, 4, 4)):
+        w.sort_interval = si
+        d = w.desc()
+        d["precision"] = W.FP32_MIXED
+        ds.append(d)
+    caps = [[w.n_per_species] * w.nspec for w in ws]
+    batch = ffpic.Batch(ds, caps)
+    singles = [ffpic.Sim(d, capacity=c) for d, c in zip(ds, caps)]
+    for w, v, s in zip(ws, batch.views, singles):
+        s.set_graph(False)
+        for sp in range(w.nspec):
+            p = w.particles(sp)
+            v.load_particles(sp, p)
+            s.load_particles(sp, p)
+    batch.views[2].set_field_rows(7)
+    singles[2].set_field_rows(7)
+    for rnd in range(5):
+        batch.step(4)
+        batch.sync()
+        for s in singles:
+            s.step(4)
+        for w, v, s in zip(ws, batch.views, singles):
+            for g, _ in FIELDS:
+                assert rel(v.field(g), s.field(g)) < 1e-5, (rnd, w.name, g)
+            dv, ds_ = v.diagnostics(ffpic.DIAG_MOMENTS), s.diagnostics(ffpic.DIAG_MOMENTS)
+            assert dv["alive"] == ds_["alive"], (rnd, w.name)
+            assert dv["step"] == ds_["step"] == 4 * (rnd + 1)
+            for sp in range(w.nspec):
+                pv, ps = v.particles(sp), s.particles(sp)
+                assert len(pv["cell"]) == len(ps["cell"])
+                assert np.mean(pv["cell"] != ps["cell"]) < 1e-3, (rnd, w.name, sp)
+                for k in ("ur", "uth", "uph"):
+                    assert rel(pv[k], ps[k]) < 2e-5, (rnd, w.name, sp, k)
+    builds, launches = batch.graph_stats()
+    assert launches == 5 and 1 <= builds <= 2, (builds, launches)
+    assert batch.grouped_launches() == 5
+    # mode 1 on the same batch: graphs of every system's own launches
+    batch.set_graph(1)
+    batch.step(4)
+    batch.sync()
+    for s in singles:
+        s.step(4)
+    for w, v, s in zip(ws, batch.views, singles):
+        for g, _ in FIELDS:
+            assert rel(v.field(g), s.field(g)) < 1e-5, (w.name, g)
+    assert batch.grouped_launches() == 5 and batch.graph_stats()[1] == 6
+    with pytest.raises(ffpic.FfpicError):
+        batch.set_graph(3)
     batch.close()
     for s in singles:
         s.close()
@@ -218,3 +287,110 @@ def test_autotune_fp32_tunes_the_push_chunk():
         assert rel(sims[0].field(g), sims[1].field(g)) < 1e-5, g
     for sim in sims:
         sim.close()
+
+
+@pytest.mark.parametrize("ppt", [8, 32])
+def test_push_chunk_setting_single_context(ppt):
+    """ffpic_set_push_chunk: a chunk of 8 or 32 particles per thread gives
+    what the default 16 gives, over sort cycles whose pushes place the
+    sorted order (only the order of the deposit's atomic additions
+    differs)."""
+    w = W.sheet_1024(n_total=60000, precision=W.FP32_MIXED)
+    w.nr = w.nth = 192
+    w.sort_interval = 4
+    d = w.desc()
+    d["precision"] = W.FP32_MIXED
+    sims = [ffpic.Sim(d, capacity=[w.n_per_species] * w.nspec) for _ in range(2)]
+    for sim in sims:
+        for sp in range(w.nspec):
+            sim.load_particles(sp, w.particles(sp))
+    sims[0].set_push_chunk(ppt)
+    with pytest.raises(ffpic.FfpicError):
+        sims[1].set_push_chunk(12)
+    for rnd in range(4):
+        for sim in sims:
+            sim.step(4)
+            sim.sync()
+        for g, _ in FIELDS:
+            assert rel(sims[0].field(g), sims[1].field(g)) < 1e-5, (rnd, g)
+        a, b = (s.diagnostics(ffpic.DIAG_MOMENTS) for s in sims)
+        assert a["alive"] == b["alive"], rnd
+    for sim in sims:
+        sim.close()
+
+
+@pytest.mark.parametrize("ppt", [8, 32])
+def test_grouped_batch_push_chunk(ppt):
+    """Grouped batch launches with every system's push chunk set to 8 or 32
+    particles per thread, against the same systems stepped alone."""
+    ws = [W.sheet_1024(n_total=60000, precision=W.FP32_MIXED) for _ in range(2)]
+    ws[0].nr = ws[0].nth = 192
+    ws[1].nr, ws[1].nth = 128, 160
+    ds = []
+    for w in ws:
+        w.sort_interval = 4
+        d = w.desc()
+        d["precision"] = W.FP32_MIXED
+        ds.append(d)
+    caps = [[w.n_per_species] * w.nspec for w in ws]
+    batch = ffpic.Batch(ds, caps)
+    singles = [ffpic.Sim(d, capacity=c) for d, c in zip(ds, caps)]
+    for w, v, s in zip(ws, batch.views, singles):
+        s.set_graph(False)
+        v.set_push_chunk(ppt)
+        for sp in range(w.nspec):
+            p = w.particles(sp)
+            v.load_particles(sp, p)
+            s.load_particles(sp, p)
+    for rnd in range(4):
+        batch.step(4)
+        batch.sync()
+        for s in singles:
+            s.step(4)
+        for w, v, s in zip(ws, batch.views, singles):
+            for g, _ in FIELDS:
+                assert rel(v.field(g), s.field(g)) < 1e-5, (rnd, g)
+            assert v.diagnostics(ffpic.DIAG_MOMENTS)["alive"] == \
+                s.diagnostics(ffpic.DIAG_MOMENTS)["alive"]
+    assert batch.grouped_launches() == 4
+    batch.close()
+    for s in singles:
+        s.close()
+
+
+def test_batch_autotune_chooses_the_graph_mode():
+    """ffpic_batch_autotune on an FP32-mixed batch without plasma sources
+    also times whole batch cycles with per-system graphs and with grouped
+    launches from one checkpoint of every system, keeps the faster mode, and
+    leaves every system's state as it was."""
+    ws = [W.sheet_1024(n_total=40000, precision=W.FP32_MIXED) for _ in range(3)]
+    for w, n in zip(ws, (96, 128, 160)):
+        w.nr = w.nth = n
+    ds = []
+    for w in ws:
+        d = w.desc()
+        d["precision"] = W.FP32_MIXED
+        ds.append(d)
+    caps = [[w.n_per_species] * w.nspec for w in ws]
+    batch = ffpic.Batch(ds, caps)
+    for w, v in zip(ws, batch.views):
+        for sp in range(w.nspec):
+            v.load_particles(sp, w.particles(sp))
+    batch.step(3)
+    batch.sync()
+    before = [snapshot(v, w.nspec) for w, v in zip(ws, batch.views)]
+    batch.autotune(3000.0)
+    mode, ms = batch.get_graph()
+    assert mode in (1, 2) and set(ms) == {1, 2} and all(v > 0 for v in ms.values())
+    assert mode == min(ms, key=ms.get)
+    for (f0, p0), w, v in zip(before, ws, batch.views):
+        f1, p1 = snapshot(v, w.nspec)
+        for a, b in zip(f0, f1):
+            assert np.array_equal(a, b)
+        for pa, pb in zip(p0, p1):
+            for k in pa:
+                assert np.array_equal(pa[k], pb[k]), k
+        assert v.diagnostics(ffpic.DIAG_MOMENTS)["step"] == 3
+    batch.step(16)
+    batch.sync()
+    batch.close()
