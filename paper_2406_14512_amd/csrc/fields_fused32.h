@@ -77,7 +77,7 @@ struct F32Kernel {
     float (*lEf)[2][kFzT];  // [2]: final state r, phi
     // register rings, indexed by (row - qs) & (size - 1)
     float sE[4][3], e0[4][3];      // rows q+1 .. q-2
-    float sB[2][3], b0[2][3];      // rows q, q-1
+    float sB[2][3], b0[4][3];      // rows q, q-1 (B0: rows q .. q-3)
     float rho[2], fv[4];           // rho0 rows q, q-1; f rows q .. q-3
     float Jr[2][3], rE[2][3] = {};  // rows q-1, q-2
     float Bh[4][3], Bt[4][3];      // B^{n+1/2} state and total, rows q-1 .. q-4
@@ -86,7 +86,7 @@ struct F32Kernel {
     float dl[2][3];                // delta rows q-2, q-3
     float Ef[2][3];                // final E state rows q-3, q-4
     float eF[2][3], bF[2][3];      // E0, B0 rows q-3, q-4 (totals, absorber)
-    float rbA[2][3], rbF[2][3];    // -curl E0 rows q, q-1 (Faraday at a) and q-3, q-4 (at fr)
+    float rbA[4][3], rbF[2][3];    // -curl E0 rows q .. q-3 (Faraday at a) and q-3, q-4 (at fr)
 
     __device__ __forceinline__ unsigned off(int row) const { return (unsigned)row * (unsigned)ld + jc; }
     __device__ __forceinline__ float4 rc(int row, int k) const { return rowc[row * kRowC + k]; }
@@ -106,19 +106,26 @@ struct F32Kernel {
         const unsigned cs = A.cs;
         auto clampr = [&](int r) { return min(max(r, 0), nr); };
 
-        // ---- loads for the coming iterations
+        // ---- loads for the coming iterations.  E0, B0 (and -curl E0) of row
+        // q-3, which the stores of the next iteration need, are taken from
+        // the rings that loaded them four rows ago (row q-3 shares its ring
+        // slot with row q+1, so before that slot is reloaded), not read again
         {
             const unsigned o1 = off(clampr(q + 1)), o0 = off(clampr(q));
-            const unsigned om1 = off(clampr(q - 1)), om3 = off(clampr(q - 3));
+            const unsigned om1 = off(clampr(q - 1));
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                eF[s2_m1][c] = e0[s4_1][c];                 // E0, B0 of row q-3 (stores)
+                bF[s2_m1][c] = b0[s4_1][c];
+                if constexpr (RB) rbF[s2_m1][c] = rbA[s4_1][c];   // row q-3, Faraday at q+1
+            }
 #pragma unroll
             for (int c = 0; c < 3; c++) {
                 sE[s4_1][c] = ld32(A.sE, o1 + c * cs);      // E^n state and E0, row q+1
                 e0[s4_1][c] = ld32(A.E0, o1 + c * cs);
                 sB[s2_0][c] = ld32(A.sB, o0 + c * cs);      // B state and B0, row q
-                b0[s2_0][c] = ld32(A.B0, o0 + c * cs);
+                b0[s4_0][c] = ld32(A.B0, o0 + c * cs);
                 Jr[s2_m1][c] = ld32(A.J, om1 + c * cs);     // deposit, row q-1
-                eF[s2_m1][c] = ld32(A.E0, om3 + c * cs);    // E0, B0 of row q-3 (stores)
-                bF[s2_m1][c] = ld32(A.B0, om3 + c * cs);
             }
             if constexpr (RE & 1) rE[s2_m1][0] = ld32(A.rE0, om1);
             if constexpr (RE & 2) rE[s2_m1][1] = ld32(A.rE0, om1 + cs);
@@ -128,12 +135,8 @@ struct F32Kernel {
                 fv[s4_0] = ld32(A.f, o0);
             }
             if constexpr (RB) {
-                const unsigned oa = off(clampr(q)), of = off(clampr(q - 3));
 #pragma unroll
-                for (int c = 0; c < 3; c++) {
-                    rbA[s2_0][c] = ld32(A.rB0, oa + c * cs);    // row q, Faraday at q+1
-                    rbF[s2_m1][c] = ld32(A.rB0, of + c * cs);   // row q-3, Faraday at q+1
-                }
+                for (int c = 0; c < 3; c++) rbA[s4_0][c] = ld32(A.rB0, o0 + c * cs);   // row q
             }
         }
 
@@ -166,7 +169,7 @@ struct F32Kernel {
             v[1] = inner ? v1 : sb[1];
             v[2] = inner ? v2 : sb[2];
             if constexpr (RB) {
-                const float *rb = rbA[s2_m1];
+                const float *rb = rbA[s4_m1];
                 v[0] += jlt ? h * rb[0] : 0.f;
                 v[1] += (inner && jin) ? h * rb[1] : 0.f;
                 v[2] += (inner && jlt) ? h * rb[2] : 0.f;
@@ -174,7 +177,7 @@ struct F32Kernel {
 #pragma unroll
             for (int c = 0; c < 3; c++) {
                 Bh[s4_m1][c] = v[c];
-                Bt[s4_m1][c] = b0[s2_m1][c] + v[c];
+                Bt[s4_m1][c] = b0[s4_m1][c] + v[c];
             }
             if (inner && !jin) Bt[s4_m1][1] = 0.f;
             if (a >= 0 && a <= nr) {
