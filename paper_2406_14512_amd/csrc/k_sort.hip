@@ -937,7 +937,9 @@ __global__ void __launch_bounds__(256) k_mover_dest(ClassView V, const uint32_t 
 }
 
 // eight slots per thread, 256 apart: the loads of all eight cells, then of
-// their keys' offsets, are in flight together
+// their keys' offsets, are in flight together.  The 64 slots of a wave are
+// one class word, so the words, their counts and the tile and group counts
+// are read once per wave with scalar loads.
 constexpr int kDestSlots = 8;
 
 __global__ void __launch_bounds__(256) k_stayer_dest(ClassView V, int nth,
@@ -945,41 +947,46 @@ __global__ void __launch_bounds__(256) k_stayer_dest(ClassView V, int nth,
                                                      const int32_t *__restrict__ mst,
                                                      int32_t *__restrict__ dest,
                                                      int32_t *__restrict__ perm) {
-    const int base = blockIdx.x * (256 * kDestSlots) + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    // first slot of this wave in round k: wave-uniform
+    const int wbase = __builtin_amdgcn_readfirstlane(
+        (int)(blockIdx.x * (256 * kDestSlots) + (threadIdx.x & ~63u)));
+    const uint64_t below = (1ull << lane) - 1ull;
     int c[kDestSlots];
 #pragma unroll
     for (int k = 0; k < kDestSlots; k++) {
-        const int q = base + k * 256;
+        const int q = wbase + k * 256 + lane;
         c[k] = q < V.nub ? cell[q] : -1;
     }
-    int cls[kDestSlots];                      // 0 none, 1 stayer, 2 mover
-    int32_t m[kDestSlots];
+    int32_t d[kDestSlots];
+    bool mover[kDestSlots];
 #pragma unroll
     for (int k = 0; k < kDestSlots; k++) {
-        const int q = base + k * 256;
-        cls[k] = 0;
-        m[k] = 0;
-        if (q < V.nub) {
-            const int wd = q >> 6;
-            const uint64_t bit = 1ull << (q & 63);
-            cls[k] = (V.smask[wd] & bit) ? 1 : ((V.mmask[wd] & bit) ? 2 : 0);
-            if (cls[k] == 1) {
+        const int q0 = wbase + k * 256;             // a whole class word
+        const int q = q0 + lane;
+        d[k] = -1;
+        mover[k] = false;
+        if (q0 < V.nub) {
+            const int wd = q0 >> 6;
+            const uint64_t sm = V.smask[wd], mm = V.mmask[wd];
+            mover[k] = ((mm >> lane) & 1ull) != 0;
+            if ((sm >> lane) & 1ull) {
                 const uint32_t key =
                     (uint32_t)(c[k] >> 16) * (uint32_t)nth + (uint32_t)(c[k] & 0xffff);
-                m[k] = mst[key];
+                const uint32_t before = V.gs[q0 >> (kTileShift + kGroupShift)].x +
+                                        V.ts[q0 >> kTileShift].x + (V.wsm[wd] & 0xffffu) +
+                                        (uint32_t)__popcll(sm & below);
+                d[k] = (int32_t)(before + (uint32_t)mst[key]);
             }
         }
+        (void)q;
     }
 #pragma unroll
     for (int k = 0; k < kDestSlots; k++) {
-        const int q = base + k * 256;
-        if (q >= V.nub || cls[k] == 2) continue;   // a mover: placed by its rank
-        int32_t d = -1;
-        if (cls[k] == 1) {
-            d = (int32_t)(stayers_before(V, q) + (uint32_t)m[k]);
-            if (perm) perm[d] = q;
-        }
-        dest[q] = d;
+        const int q = wbase + k * 256 + lane;
+        if (q >= V.nub || mover[k]) continue;       // a mover: placed by its rank
+        if (d[k] >= 0 && perm) perm[d[k]] = q;
+        dest[q] = d[k];
     }
 }
 
