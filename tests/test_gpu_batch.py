@@ -99,13 +99,16 @@ def test_grouped_batch_graph_matches_single_contexts():
     per step, one persistent launch each for the flux functions, masks,
     pushes and field steps of all systems.  Three systems of different grids
     and sort intervals (2 and 4, so that some steps sort only some systems
-    and the push launches mix placing and plain pushes) and a non-default
-    slab height on one of them, against each system stepped alone one step
-    at a time; every replay checked, with reads between the replays."""
+    and the push launches mix placing and plain pushes), a non-default
+    slab height on one of them and the transverse-momentum shell on another
+    (its pushes are a kernel instance of their own), against each system
+    stepped alone one step at a time; every replay checked, with reads
+    between the replays."""
     ws = [W.tiny_open_dipole(20000), W.tiny_dipole(15000),
           W.sheet_1024(n_total=60000, precision=W.FP32_MIXED)]
     ws[1].nr, ws[1].nth = 96, 80
     ws[2].nr = ws[2].nth = 192
+    ws[1].shell_r = 4.0
     ds = []
     for w, si in zip(ws, (2, 4, 4)):
         w.sort_interval = si
