@@ -248,10 +248,12 @@ def batch_run(ffpic, W, steps, warmup, scale, tune_ms=0.0):
     b.set_graph(other)
     b.step(2 * cycle)
     b.sync()
+    n2 = alive()
     t4 = time.perf_counter()
     b.step(steps)
     b.sync()
     t5 = time.perf_counter()
+    n3 = alive()
     b.set_graph(False)
     t2 = time.perf_counter()
     b.step(steps)
@@ -268,6 +270,8 @@ def batch_run(ffpic, W, steps, warmup, scale, tune_ms=0.0):
                        "grouped": grouped},
             "graph_mode": {1: "per-system", 2: "grouped"}.get(mode, "off"),
             "other_graph_mode_ms_per_step": (t5 - t4) / steps * 1e3,
+            # later in the run, with fewer live particles: compare per particle
+            "other_graph_mode_particle_steps_per_s": 0.5 * (n2 + n3) * steps / (t5 - t4),
             "eager_ms_per_step": (t3 - t2) / steps * 1e3, "tuned": tuned}
 
 
@@ -453,7 +457,8 @@ def main():
         bo = out["batch"]
         log(f"  batch: {bo['ms_per_step']:.3f} ms/step, "
             f"{bo['particle_steps_per_s']:.3e} particle-steps/s, graphs {bo['graphs']}; "
-            f"mode {bo['graph_mode']}, other mode {bo['other_graph_mode_ms_per_step']:.3f} ms/step, "
+            f"mode {bo['graph_mode']}, other mode {bo['other_graph_mode_ms_per_step']:.3f} ms/step "
+            f"({bo['other_graph_mode_particle_steps_per_s']:.3e} particle-steps/s), "
             f"one by one {bo['eager_ms_per_step']:.3f} ms/step")
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample")

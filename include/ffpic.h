@@ -499,8 +499,10 @@ int ffpic_batch_destroy(ffpic_batch *b);
  * field patch and one current patch) and of the fused field step (radial
  * rows of a workgroup's slab, see ffpic_set_field_rows).  ffpic_autotune
  * checkpoints the context to host memory (as ffpic_save) and, from that
- * state, times whole sort cycles of each candidate, one parameter after the
- * other, keeping the best value of each before trying the next:
+ * state, times whole sort cycles of each candidate (after one untimed
+ * cycle: a restored context's first sort is a full one, later sorts are
+ * incremental), one parameter after the other, keeping the best value of
+ * each before trying the next:
  *   1. the sort interval: 8, 4, 16, 2, 32, 1;
  *   2. the field step's slab rows: 0 (automatic), 32, 64, 128, 16;
  *   3. (FP32) the push's particles per thread: 16, 8, 32;
@@ -523,8 +525,9 @@ int ffpic_batch_destroy(ffpic_batch *b);
  * a batch that can run as grouped launches (see ffpic_batch_set_graph) with
  * graphs on, it checkpoints every system, times whole batch cycles with
  * per-system graphs (mode 1) and with grouped launches (mode 2) from that
- * same state, restores the checkpoints and keeps the faster mode
- * (ffpic_batch_get_graph reports both times).  The systems' states after
+ * same state (each mode twice, alternating, its faster timing kept),
+ * restores the checkpoints and keeps the faster mode (ffpic_batch_get_graph
+ * reports both times).  The systems' states after
  * the call are those before it.
  */
 #define FFPIC_TUNE_MAX 16
