@@ -112,3 +112,14 @@ def test_null_and_invalid_arguments_fail_cleanly(lib):
     q = ffpic.SpectraReq(1.0, 2.0, 0.0, 3.0, 1.0, 10.0, 1.0, 2.0, 4, 4)
     buf = (ctypes.c_double * 8)()
     assert lib.ffpic_spectra(None, 0, ctypes.byref(q), buf, buf, buf) == ffpic.EINVAL
+    # graph and tuning settings
+    n64 = ctypes.c_int64(0)
+    mode = ctypes.c_int32(0)
+    assert lib.ffpic_set_push_chunk(None, 16) == ffpic.EINVAL
+    assert lib.ffpic_set_field_rows(None, 0) == ffpic.EINVAL
+    assert lib.ffpic_set_graph(None, 1) == ffpic.EINVAL
+    assert lib.ffpic_batch_set_graph(None, 1) == ffpic.EINVAL
+    assert lib.ffpic_batch_get_graph(None, ctypes.byref(mode), None) == ffpic.EINVAL
+    assert lib.ffpic_batch_grouped_launches(None, ctypes.byref(n64)) == ffpic.EINVAL
+    assert lib.ffpic_batch_graph_stats(None, ctypes.byref(n64), ctypes.byref(n64)) == ffpic.EINVAL
+    assert lib.ffpic_batch_autotune(None, 100.0, None) == ffpic.EINVAL
