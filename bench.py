@@ -215,8 +215,9 @@ def batch_run(ffpic, W, steps, warmup, scale, tune_ms=0.0):
             tuned[key] = {str(v): vals.count(v) for v in sorted(set(vals))}
         tuned["ms"] = round(sum(x["total_ms"] for x in t), 1)
         # the batch's graph mode, chosen by timing both from one checkpoint
-        mode, mode_ms = b.get_graph()
+        mode, gppt, mode_ms = b.graph_settings()
         tuned["graph_mode"] = mode
+        tuned["grouped_push_ppt"] = gppt or "own"
         tuned["graph_mode_ms_per_step"] = {str(k): round(v, 3) for k, v in mode_ms.items()}
         cycle = 1
         for x in t:

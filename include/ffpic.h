@@ -482,10 +482,20 @@ int ffpic_batch_sync(ffpic_batch *b);
 int ffpic_batch_set_graph(ffpic_batch *b, int mode);
 int ffpic_batch_graph_stats(ffpic_batch *b, int64_t *builds, int64_t *launches);
 int ffpic_batch_grouped_launches(const ffpic_batch *b, int64_t *launches);
-/* The graph mode in use (after ffpic_batch_autotune: the one it chose) and,
-   when ms_per_step is not NULL, the batch-step times the tuner measured for
-   modes 0, 1, 2 (0 where not measured). */
-int ffpic_batch_get_graph(const ffpic_batch *b, int32_t *mode, double ms_per_step[3]);
+/* Particles per thread of the grouped pushes (mode 2): 8, 16 or 32 for every
+   system, or 0 (the default) for each system's own setting (see
+   ffpic_set_push_chunk).  A system's own setting is tuned for that system
+   filling the GPU alone; grouped, the systems fill it together.  The
+   arithmetic does not change (see ffpic_set_push_chunk).  EINVAL for another
+   value. */
+int ffpic_batch_set_grouped_chunk(ffpic_batch *b, int32_t ppt);
+/* The graph mode in use (after ffpic_batch_autotune: the one it chose), when
+   grouped_ppt is not NULL the grouped push chunk in use (0: each system's
+   own), and, when ms_per_step is not NULL, the batch-step times the tuner
+   measured for modes 0, 1, 2 (0 where not measured; for mode 2 the faster of
+   its two chunk settings). */
+int ffpic_batch_get_graph(const ffpic_batch *b, int32_t *mode, int32_t *grouped_ppt,
+                          double ms_per_step[3]);
 const char *ffpic_batch_last_error(const ffpic_batch *b);
 int ffpic_batch_destroy(ffpic_batch *b);
 
@@ -524,10 +534,11 @@ int ffpic_batch_destroy(ffpic_batch *b);
  * with an equal share of the budget and writes n entries to out.  Then, for
  * a batch that can run as grouped launches (see ffpic_batch_set_graph) with
  * graphs on, it checkpoints every system, times whole batch cycles with
- * per-system graphs (mode 1) and with grouped launches (mode 2) from that
- * same state (each mode twice, alternating, its faster timing kept),
- * restores the checkpoints and keeps the faster mode (ffpic_batch_get_graph
- * reports both times).  The systems' states after
+ * per-system graphs (mode 1), with grouped launches (mode 2) using each
+ * system's push chunk and with grouped launches using 16 particles per thread
+ * for every system, from that same state (each candidate twice, alternating,
+ * its faster timing kept), restores the checkpoints and keeps the fastest
+ * (ffpic_batch_get_graph reports the choice and the times).  The systems' states after
  * the call are those before it.
  */
 #define FFPIC_TUNE_MAX 16

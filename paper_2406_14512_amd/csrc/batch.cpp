@@ -42,6 +42,7 @@
 struct BatchGraph {
     int steps = 0;
     int mode = 1;
+    int gppt = 0;                     // grouped push chunk it was captured with
     std::vector<ffpic::CycleState> pre, post;
     hipGraphExec_t exec = nullptr;
     void *tables = nullptr;
@@ -59,6 +60,7 @@ struct ffpic_batch {
     // systems on origin (mode 2, where every system allows it); mode 0: no
     // graphs
     int graph_mode = 2;
+    int grouped_ppt = 0;              // grouped pushes: particles per thread, 0 = each system's
     int *gctr = nullptr;              // work counters of the grouped launches
     int push_slots[12] = {}, field_slots[8] = {}, psi_slots = 0;
     int64_t grouped_launches = 0;
@@ -287,8 +289,8 @@ void grouped_step(ffpic_batch *b, hipStream_t st, Tables &T) {
     for (ffpic_ctx *c : sys) {
         for (int s = 0; s < c->d.nspec; s++) {
             if (c->sp[s].nub == 0) continue;
-            Group &g = push[ffpic::push_group_key(c, s)];
-            const int m = ffpic::push_job(c, s, tmp.data());
+            Group &g = push[ffpic::push_group_key(c, s, b->grouped_ppt)];
+            const int m = ffpic::push_job(c, s, tmp.data(), b->grouped_ppt);
             g.jobs.insert(g.jobs.end(), tmp.begin(), tmp.begin() + ffpic::push_job_bytes());
             g.starts.push_back(g.items() + m);
         }
@@ -326,7 +328,9 @@ void run_batch_cycle(ffpic_batch *b, int k) {
     pre.reserve(b->ctx.size());
     for (ffpic_ctx *c : b->ctx) pre.push_back(ffpic::get_cycle_state(c));
     for (auto &g : b->graphs) {
-        if (g.steps == k && same_states(g.pre, pre) && g.mode == (grouped_ok(b) ? 2 : 1)) {
+        const bool gr = grouped_ok(b);
+        if (g.steps == k && same_states(g.pre, pre) && g.mode == (gr ? 2 : 1) &&
+            (!gr || g.gppt == b->grouped_ppt)) {
             launch_batch_graph(b, g.exec);
             if (g.mode == 2) b->grouped_launches++;
             for (size_t q = 0; q < b->ctx.size(); q++) {
@@ -406,6 +410,7 @@ void run_batch_cycle(ffpic_batch *b, int k) {
     BatchGraph g;
     g.steps = k;
     g.mode = grouped ? 2 : 1;
+    g.gppt = b->grouped_ppt;
     g.pre = pre;
     for (ffpic_ctx *c : b->ctx) g.post.push_back(ffpic::get_cycle_state(c));
     g.exec = exec;
@@ -555,19 +560,21 @@ void tune_one(ffpic_ctx *c, double budget_ms, ffpic_tuning *out) {
     }
 }
 
-// ms per batch step of whole batch cycles in graph mode `mode`, from the
-// state every system was checkpointed in: the steps to a common cycle start
-// and three cycles (a restored system's first sort is a full one, launched
-// step by step; then the graphs of both buffer parities are captured), then
-// one timed cycle
-double time_batch_mode(ffpic_batch *b, int mode, const std::vector<std::vector<char>> &ckpt,
-                       int cycle) {
+// ms per batch step of whole batch cycles in graph mode `mode` (grouped
+// pushes with `gppt` particles per thread), from the state every system
+// was checkpointed in: the steps to a common cycle start and three cycles
+// (a restored system's first sort is a full one, launched step by step;
+// then the graphs of both buffer parities are captured), then one timed
+// cycle
+double time_batch_mode(ffpic_batch *b, int mode, int gppt,
+                       const std::vector<std::vector<char>> &ckpt, int cycle) {
     for (size_t q = 0; q < b->ctx.size(); q++) {
         const int rc = ffpic_restore(b->ctx[q], ckpt[q].data(), ckpt[q].size());
         if (rc != FFPIC_OK) throw BFail{rc, ffpic_last_error(b->ctx[q])};
     }
-    if (mode != b->graph_mode) destroy_batch_graphs(b);
+    if (mode != b->graph_mode || gppt != b->grouped_ppt) destroy_batch_graphs(b);
     b->graph_mode = mode;
+    b->grouped_ppt = gppt;
     int64_t lead = 0;   // steps to the next common cycle start
     for (ffpic_ctx *c : b->ctx) lead = std::max<int64_t>(lead, (cycle - c->step % cycle) % cycle);
     int rc = ffpic_batch_step(b, (int32_t)(lead + 3 * cycle));
@@ -589,11 +596,14 @@ double time_batch_mode(ffpic_batch *b, int mode, const std::vector<std::vector<c
 }
 
 // After each system's settings are tuned: for a batch that can run as
-// grouped launches, time whole batch cycles with per-system graphs and with
-// grouped launches from the same checkpoint of every system, restore the
-// checkpoint and keep the faster mode.  Which one wins depends on the
-// batch: per-system graphs let one system's push overlap another's field
-// step; grouped launches need far fewer launches per step.
+// grouped launches, time whole batch cycles with per-system graphs, with
+// grouped launches using each system's push chunk, and with grouped
+// launches using 16 particles per thread for every system (the per-system
+// chunk is chosen for one system filling the GPU alone; grouped, all
+// systems fill it together), from the same checkpoint of every system;
+// restore the checkpoint and keep the fastest.  Which one wins depends on
+// the batch: per-system graphs let one system's push overlap another's
+// field step; grouped launches need far fewer launches per step.
 void tune_batch_mode(ffpic_batch *b) {
     b->mode_ms[0] = b->mode_ms[1] = b->mode_ms[2] = 0;
     if (b->graph_mode == 0 || !grouped_possible(b)) return;
@@ -606,7 +616,7 @@ void tune_batch_mode(ffpic_batch *b) {
         cycle = cycle / std::gcd<int64_t>(cycle, si) * si;
         if (cycle > 64) return;
     }
-    const int keep = b->graph_mode;
+    const int keep = b->graph_mode, keep_ppt = b->grouped_ppt;
     std::vector<std::vector<char>> ckpt(b->ctx.size());
     for (size_t q = 0; q < b->ctx.size(); q++) {
         size_t len = 0;
@@ -617,21 +627,25 @@ void tune_batch_mode(ffpic_batch *b) {
         }
         if (rc != FFPIC_OK) throw BFail{rc, ffpic_last_error(b->ctx[q])};
     }
-    int best = keep;
+    // (mode, grouped chunk); each timed twice, alternating, the faster of
+    // its two timings kept: a single cycle's time varies by a few per cent
+    const int cand[3][2] = {{1, 0}, {2, 0}, {2, 16}};
+    double ms[3] = {0, 0, 0};
+    int best = 0;
     try {
-        // each mode twice, alternating, the faster of its two timings kept:
-        // a single cycle's time varies by a few per cent
         for (int rep = 0; rep < 2; rep++)
-            for (int mode : {1, 2}) {
-                const double ms = time_batch_mode(b, mode, ckpt, (int)cycle);
-                b->mode_ms[mode] = rep == 0 ? ms : std::min(b->mode_ms[mode], ms);
+            for (int k = 0; k < 3; k++) {
+                const double t = time_batch_mode(b, cand[k][0], cand[k][1], ckpt, (int)cycle);
+                ms[k] = rep == 0 ? t : std::min(ms[k], t);
             }
-        best = b->mode_ms[2] < b->mode_ms[1] ? 2 : 1;
+        for (int k = 1; k < 3; k++)
+            if (ms[k] < ms[best]) best = k;
     } catch (...) {
         for (size_t q = 0; q < b->ctx.size(); q++)
             (void)ffpic_restore(b->ctx[q], ckpt[q].data(), ckpt[q].size());
         destroy_batch_graphs(b);
         b->graph_mode = keep;
+        b->grouped_ppt = keep_ppt;
         throw;
     }
     for (size_t q = 0; q < b->ctx.size(); q++) {
@@ -639,7 +653,10 @@ void tune_batch_mode(ffpic_batch *b) {
         if (rc != FFPIC_OK) throw BFail{rc, ffpic_last_error(b->ctx[q])};
     }
     destroy_batch_graphs(b);
-    b->graph_mode = best;
+    b->mode_ms[1] = ms[0];
+    b->mode_ms[2] = std::min(ms[1], ms[2]);
+    b->graph_mode = cand[best][0];
+    b->grouped_ppt = best == 0 ? keep_ppt : cand[best][1];
 }
 
 }  // namespace
@@ -819,9 +836,21 @@ int ffpic_batch_graph_stats(ffpic_batch *b, int64_t *builds, int64_t *launches) 
     return FFPIC_OK;
 }
 
-int ffpic_batch_get_graph(const ffpic_batch *b, int32_t *mode, double ms_per_step[3]) {
+int ffpic_batch_set_grouped_chunk(ffpic_batch *b, int32_t ppt) {
+    return bguard(b, [&] {
+        if (!b) throw BFail{FFPIC_EINVAL, "batch is NULL"};
+        if (ppt != 0 && ppt != 8 && ppt != 16 && ppt != 32)
+            throw BFail{FFPIC_EINVAL, "grouped push chunk must be 0, 8, 16 or 32"};
+        if (ppt != b->grouped_ppt) destroy_batch_graphs(b);
+        b->grouped_ppt = ppt;
+    });
+}
+
+int ffpic_batch_get_graph(const ffpic_batch *b, int32_t *mode, int32_t *grouped_ppt,
+                          double ms_per_step[3]) {
     if (!b || !mode) return FFPIC_EINVAL;
     *mode = b->graph_mode;
+    if (grouped_ppt) *grouped_ppt = b->grouped_ppt;
     if (ms_per_step)
         for (int k = 0; k < 3; k++) ms_per_step[k] = b->mode_ms[k];
     return FFPIC_OK;

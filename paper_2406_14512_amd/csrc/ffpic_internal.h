@@ -268,8 +268,10 @@ void spectra(ffpic_ctx *c, int s, const ffpic_spectra_req *req, double *dev_out)
 // workgroups (grid of them) that take items from the counter pair ctr
 // (zero before the launch, zero again after it).
 size_t push_job_bytes();
-int push_group_key(const ffpic_ctx *c, int s);    // kernel instance, 0..11
-int push_job(ffpic_ctx *c, int s, void *out);
+// ppt: particles per thread of the grouped push (8, 16, 32), 0 = the
+// context's own setting
+int push_group_key(const ffpic_ctx *c, int s, int ppt);   // kernel instance, 0..11
+int push_job(ffpic_ctx *c, int s, void *out, int ppt);
 int push_group_slots(int key);
 void push_group_launch(hipStream_t st, int key, const void *jobs, const int *starts, int njobs,
                        int grid, int *ctr);

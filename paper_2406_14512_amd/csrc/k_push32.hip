@@ -748,9 +748,10 @@ struct PushKey {
     bool shell, place;
 };
 
-PushKey push_key(const ffpic_ctx *c, int s) {
-    return {c->push_ppt == 8 || c->push_ppt == 32 ? c->push_ppt : 16,
-            c->d.shell_r > c->d.rmin, c->sort_pending[s]};
+// ppt: particles per thread, 0 = the context's own setting
+PushKey push_key(const ffpic_ctx *c, int s, int ppt = 0) {
+    const int v = ppt > 0 ? ppt : c->push_ppt;
+    return {v == 8 || v == 32 ? v : 16, c->d.shell_r > c->d.rmin, c->sort_pending[s]};
 }
 
 int push_key_index(const PushKey &k) {
@@ -847,11 +848,13 @@ void push32(ffpic_ctx *c, int s) {
 
 size_t push_job_bytes() { return sizeof(PushJob); }
 
-int push_group_key(const ffpic_ctx *c, int s) { return push_key_index(push_key(c, s)); }
+int push_group_key(const ffpic_ctx *c, int s, int ppt) {
+    return push_key_index(push_key(c, s, ppt));
+}
 
-int push_job(ffpic_ctx *c, int s, void *out) {
+int push_job(ffpic_ctx *c, int s, void *out, int ppt) {
     ffpic::Species &S = c->sp[s];
-    const PushKey k = push_key(c, s);
+    const PushKey k = push_key(c, s, ppt);
     const PushJob J = make_push_job(c, s);
     std::memcpy(out, &J, sizeof(J));
     after_push(c, s);

@@ -128,7 +128,9 @@ def lib():
     L.ffpic_batch_set_graph.argtypes = [P, C.c_int]
     L.ffpic_batch_graph_stats.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     L.ffpic_batch_grouped_launches.argtypes = [P, C.POINTER(C.c_int64)]
-    L.ffpic_batch_get_graph.argtypes = [P, C.POINTER(C.c_int32), C.POINTER(C.c_double)]
+    L.ffpic_batch_get_graph.argtypes = [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                        C.POINTER(C.c_double)]
+    L.ffpic_batch_set_grouped_chunk.argtypes = [P, C.c_int32]
     L.ffpic_graph_stats.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     L.ffpic_diagnostics.argtypes = [P, C.c_uint32, C.POINTER(Diag), vp]
     L.ffpic_diagnostics_noalloc.argtypes = [P, C.c_uint32, C.POINTER(Diag), vp]
@@ -164,7 +166,7 @@ def lib():
                  "ffpic_set_push_chunk",
                  "ffpic_set_graph", "ffpic_graph_stats", "ffpic_batch_set_graph",
                  "ffpic_batch_graph_stats", "ffpic_batch_grouped_launches",
-                 "ffpic_batch_get_graph"):
+                 "ffpic_batch_get_graph", "ffpic_batch_set_grouped_chunk"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -497,12 +499,22 @@ class Batch:
         self._chk(lib().ffpic_batch_graph_stats(self._h, C.byref(b), C.byref(l)))
         return b.value, l.value
 
+    def set_grouped_chunk(self, ppt: int):
+        """Particles per thread of grouped pushes (8, 16, 32; 0 = each
+        system's own setting)."""
+        self._chk(lib().ffpic_batch_set_grouped_chunk(self._h, int(ppt)))
+
     def get_graph(self):
         """(graph mode in use, {mode: ms per batch step} the tuner measured)."""
-        m = C.c_int32(0)
+        return self.graph_settings()[::2]
+
+    def graph_settings(self):
+        """(graph mode, grouped push chunk (0 = each system's own),
+        {mode: ms per batch step} the tuner measured)."""
+        m, g = C.c_int32(0), C.c_int32(0)
         t = (C.c_double * 3)()
-        self._chk(lib().ffpic_batch_get_graph(self._h, C.byref(m), t))
-        return m.value, {k: t[k] for k in range(3) if t[k] > 0}
+        self._chk(lib().ffpic_batch_get_graph(self._h, C.byref(m), C.byref(g), t))
+        return m.value, g.value, {k: t[k] for k in range(3) if t[k] > 0}
 
     def grouped_launches(self):
         """How many graph launches ran grouped launches of all systems."""

@@ -119,7 +119,8 @@ def test_null_and_invalid_arguments_fail_cleanly(lib):
     assert lib.ffpic_set_field_rows(None, 0) == ffpic.EINVAL
     assert lib.ffpic_set_graph(None, 1) == ffpic.EINVAL
     assert lib.ffpic_batch_set_graph(None, 1) == ffpic.EINVAL
-    assert lib.ffpic_batch_get_graph(None, ctypes.byref(mode), None) == ffpic.EINVAL
+    assert lib.ffpic_batch_get_graph(None, ctypes.byref(mode), None, None) == ffpic.EINVAL
+    assert lib.ffpic_batch_set_grouped_chunk(None, 16) == ffpic.EINVAL
     assert lib.ffpic_batch_grouped_launches(None, ctypes.byref(n64)) == ffpic.EINVAL
     assert lib.ffpic_batch_graph_stats(None, ctypes.byref(n64), ctypes.byref(n64)) == ffpic.EINVAL
     assert lib.ffpic_batch_autotune(None, 100.0, None) == ffpic.EINVAL

@@ -322,10 +322,12 @@ def test_push_chunk_setting_single_context(ppt):
         sim.close()
 
 
-@pytest.mark.parametrize("ppt", [8, 32])
-def test_grouped_batch_push_chunk(ppt):
-    """Grouped batch launches with every system's push chunk set to 8 or 32
-    particles per thread, against the same systems stepped alone."""
+@pytest.mark.parametrize("ppt,gppt", [(8, 0), (32, 0), (8, 16), (16, 32)])
+def test_grouped_batch_push_chunk(ppt, gppt):
+    """Grouped batch launches with every system's push chunk set to 8, 16 or
+    32 particles per thread, and with the batch's grouped chunk overriding
+    it (gppt > 0), against the same systems stepped alone with their own
+    chunk."""
     ws = [W.sheet_1024(n_total=60000, precision=W.FP32_MIXED) for _ in range(2)]
     ws[0].nr = ws[0].nth = 192
     ws[1].nr, ws[1].nth = 128, 160
@@ -341,10 +343,15 @@ def test_grouped_batch_push_chunk(ppt):
     for w, v, s in zip(ws, batch.views, singles):
         s.set_graph(False)
         v.set_push_chunk(ppt)
+        s.set_push_chunk(ppt)
         for sp in range(w.nspec):
             p = w.particles(sp)
             v.load_particles(sp, p)
             s.load_particles(sp, p)
+    batch.set_grouped_chunk(gppt)
+    assert batch.graph_settings()[:2] == (2, gppt)
+    with pytest.raises(ffpic.FfpicError):
+        batch.set_grouped_chunk(12)
     for rnd in range(4):
         batch.step(4)
         batch.sync()
@@ -383,9 +390,11 @@ def test_batch_autotune_chooses_the_graph_mode():
     batch.sync()
     before = [snapshot(v, w.nspec) for w, v in zip(ws, batch.views)]
     batch.autotune(3000.0)
-    mode, ms = batch.get_graph()
+    mode, gppt, ms = batch.graph_settings()
     assert mode in (1, 2) and set(ms) == {1, 2} and all(v > 0 for v in ms.values())
     assert mode == min(ms, key=ms.get)
+    assert gppt in (0, 16) and (mode == 2 or gppt == 0)
+    assert batch.get_graph() == (mode, ms)
     for (f0, p0), w, v in zip(before, ws, batch.views):
         f1, p1 = snapshot(v, w.nspec)
         for a, b in zip(f0, f1):
