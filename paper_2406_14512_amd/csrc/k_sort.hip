@@ -590,10 +590,10 @@ struct ClassArgs {
 // sort's cell offsets holds the slot: a particle keeps its key since then
 // exactly when its slot lies in [OFF[key], OFF[key+1]).  Two reads of the
 // per-key offsets instead of a stored key per slot (sorted particles of a
-// wave mostly share a key, so the reads share cache lines).
-__device__ __forceinline__ bool in_old_range(const int32_t *__restrict__ off, uint32_t key, int q,
-                                             int nold) {
-    return q < nold && off[key] <= q && q < off[key + 1];
+// wave mostly share a key, so the reads share cache lines).  lo, hi: the
+// key's OFF[key], OFF[key+1]; nold: the slots the last sort ordered.
+__device__ __forceinline__ bool in_old_range(int q, int nold, int lo, int hi) {
+    return q < nold && lo <= q && q < hi;
 }
 
 // key of every slot, the removal of killed particles, the class bits and
@@ -608,55 +608,78 @@ __global__ void __launch_bounds__(256) k_classify(ClassArgs A) {
     uint32_t key[K];
     int cl[K];
     if (!FP64) {
+        // the cells of all K slots, then for every slot its cell's kill flag
+        // and its key's old offset range, loaded whether needed or not (a
+        // slot without a particle reads those of key 0): with no branch
+        // around them, all 3K loads are in flight together instead of one
+        // round trip after another
         int cell[K];
 #pragma unroll
         for (int k = 0; k < K; k++) {
             const int q = base + k * 256 + tid;
             cell[k] = q < ns ? A.cell[q] : -1;
         }
+        uint8_t kf[K];
+        int lo[K], hi[K];
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            const int c = cell[k];
+            const uint32_t kk =
+                c >= 0 ? (uint32_t)(c >> 16) * (uint32_t)A.nth + (uint32_t)(c & 0xffff) : 0u;
+            key[k] = kk;
+            kf[k] = A.kill[kk];
+            lo[k] = A.offold[kk];
+            hi[k] = A.offold[kk + 1];
+        }
 #pragma unroll
         for (int k = 0; k < K; k++) {
             const int q = base + k * 256 + tid;
-            bool killed = false;
-            key[k] = A.dead;
-            cl[k] = 0;
-            const int c = cell[k];
-            if (c >= 0) {
-                const int i = c >> 16, j = c & 0xffff;
-                if (A.kill[(size_t)i * A.nth + j]) {
-                    killed = true;
-                    A.cell[q] = -1;
-                } else {
-                    key[k] = (uint32_t)i * (uint32_t)A.nth + (uint32_t)j;
-                    cl[k] = key[k] >= A.dead ? 0 : (in_old_range(A.offold, key[k], q, no) ? 1 : 2);
-                }
-            }
+            const bool live = cell[k] >= 0;
+            const bool killed = live && kf[k] != 0;
+            if (killed) A.cell[q] = -1;
+            if (!live || killed) key[k] = A.dead;
+            cl[k] = key[k] >= A.dead ? 0 : (in_old_range(q, no, lo[k], hi[k]) ? 1 : 2);
             count_wave(&A.removed[1], killed);
         }
     } else {
+        // the positions of all K slots, their cells, then (as in the FP32
+        // branch) the kill flags and old offset ranges, loaded unconditionally
+        double r[K], th[K];
 #pragma unroll
         for (int k = 0; k < K; k++) {
             const int q = base + k * 256 + tid;
-            bool killed = false;
-            key[k] = A.dead;
-            cl[k] = 0;
-            if (q < ns) {
-                const double r = A.R[q];
-                if (r > 0.0) {
-                    int i, j;
-                    double a, b;
-                    locate64(A.nr, A.nth, A.rmin, A.dlog, A.dth, A.rn, A.thn, r, A.TH[q], i, j,
-                             a, b);
-                    if (A.kill[(size_t)i * A.nth + j]) {
-                        killed = true;
-                        A.R[q] = -1.0;
-                    } else {
-                        key[k] = (uint32_t)i * (uint32_t)A.nth + (uint32_t)j;
-                    }
-                }
+            r[k] = q < ns ? A.R[q] : -1.0;
+            th[k] = q < ns ? A.TH[q] : 0.0;
+        }
+        int cix[K];                                 // i * nth + j, -1: no particle
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            cix[k] = -1;
+            if (r[k] > 0.0) {
+                int i, j;
+                double a, b;
+                locate64(A.nr, A.nth, A.rmin, A.dlog, A.dth, A.rn, A.thn, r[k], th[k], i, j, a, b);
+                cix[k] = i * A.nth + j;
             }
+        }
+        uint8_t kf[K];
+        int lo[K], hi[K];
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            const uint32_t kk = cix[k] >= 0 ? (uint32_t)cix[k] : 0u;
+            kf[k] = A.kill[kk];
+            lo[k] = A.offold[kk];
+            hi[k] = A.offold[kk + 1];
+        }
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            const int q = base + k * 256 + tid;
+            const bool live = cix[k] >= 0;
+            const bool killed = live && kf[k] != 0;
+            if (killed) A.R[q] = -1.0;
+            key[k] = live && !killed ? (uint32_t)cix[k] : A.dead;
             if (q < A.nub) A.keys[q] = key[k];
-            if (key[k] < A.dead) cl[k] = in_old_range(A.offold, key[k], q, no) ? 1 : 2;
+            cl[k] = key[k] >= A.dead ? 0 : (in_old_range(q, no, lo[k], hi[k]) ? 1 : 2);
             count_wave(&A.removed[1], killed);
         }
     }
@@ -937,9 +960,10 @@ __global__ void __launch_bounds__(256) k_mover_dest(ClassView V, const uint32_t 
 }
 
 // eight slots per thread, 256 apart: the loads of all eight cells, then of
-// their keys' offsets, are in flight together.  The 64 slots of a wave are
-// one class word, so the words, their counts and the tile and group counts
-// are read once per wave with scalar loads.
+// their keys' mover counts (for every slot, a slot without a particle reading
+// key 0's, so that no branch separates them), are in flight together.  The
+// 64 slots of a wave are one class word, so the words, their counts and the
+// tile and group counts are read once per wave with scalar loads.
 constexpr int kDestSlots = 8;
 
 __global__ void __launch_bounds__(256) k_stayer_dest(ClassView V, int nth,
@@ -958,12 +982,18 @@ __global__ void __launch_bounds__(256) k_stayer_dest(ClassView V, int nth,
         const int q = wbase + k * 256 + lane;
         c[k] = q < V.nub ? cell[q] : -1;
     }
+    int32_t ms[kDestSlots];
+#pragma unroll
+    for (int k = 0; k < kDestSlots; k++) {
+        const uint32_t key =
+            c[k] >= 0 ? (uint32_t)(c[k] >> 16) * (uint32_t)nth + (uint32_t)(c[k] & 0xffff) : 0u;
+        ms[k] = mst[key];
+    }
     int32_t d[kDestSlots];
     bool mover[kDestSlots];
 #pragma unroll
     for (int k = 0; k < kDestSlots; k++) {
         const int q0 = wbase + k * 256;             // a whole class word
-        const int q = q0 + lane;
         d[k] = -1;
         mover[k] = false;
         if (q0 < V.nub) {
@@ -971,15 +1001,12 @@ __global__ void __launch_bounds__(256) k_stayer_dest(ClassView V, int nth,
             const uint64_t sm = V.smask[wd], mm = V.mmask[wd];
             mover[k] = ((mm >> lane) & 1ull) != 0;
             if ((sm >> lane) & 1ull) {
-                const uint32_t key =
-                    (uint32_t)(c[k] >> 16) * (uint32_t)nth + (uint32_t)(c[k] & 0xffff);
                 const uint32_t before = V.gs[q0 >> (kTileShift + kGroupShift)].x +
                                         V.ts[q0 >> kTileShift].x + (V.wsm[wd] & 0xffffu) +
                                         (uint32_t)__popcll(sm & below);
-                d[k] = (int32_t)(before + (uint32_t)mst[key]);
+                d[k] = (int32_t)(before + (uint32_t)ms[k]);
             }
         }
-        (void)q;
     }
 #pragma unroll
     for (int k = 0; k < kDestSlots; k++) {
