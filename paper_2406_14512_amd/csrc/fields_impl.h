@@ -21,6 +21,7 @@ namespace ffpic {
 // flight, and the tile of partial sums is written back coalesced.
 constexpr int kPsiRows = 16;
 constexpr int kPsiCols = 256;
+constexpr int kPsiRun = 32;     // terms a lane sums between LDS reads
 
 // workgroup barrier that orders LDS accesses only: unlike __syncthreads it
 // does not wait for the thread's global loads and stores, so the next
@@ -80,11 +81,28 @@ __device__ __forceinline__ void psi_block(const PsiJob<R> &P, int bx,
         const int jn = j0 + kPsiCols;
         if (jn < nth) load(jn);
         if (t < rows) {
-#pragma unroll 16
-            for (int k = 0; k < w; k++) {
+            // in blocks of kPsiRun terms: all reads, then the serial sums in
+            // registers, then all writes, so that the chain of additions
+            // waits for LDS once per block rather than every few terms
+            double *__restrict__ row = tile[t];
+            int k = 0;
+            for (; k + kPsiRun <= w; k += kPsiRun) {
+                double v[kPsiRun];
+#pragma unroll
+                for (int u = 0; u < kPsiRun; u++) v[u] = row[k + u];
+#pragma unroll
+                for (int u = 0; u < kPsiRun; u++) {
 #pragma clang fp contract(off)
-                acc = acc + tile[t][k];
-                tile[t][k] = acc;
+                    acc = acc + v[u];
+                    v[u] = acc;
+                }
+#pragma unroll
+                for (int u = 0; u < kPsiRun; u++) row[k + u] = v[u];
+            }
+            for (; k < w; k++) {
+#pragma clang fp contract(off)
+                acc = acc + row[k];
+                row[k] = acc;
             }
         }
         lds_barrier();
@@ -131,14 +149,18 @@ __device__ __forceinline__ void mask_row(const MaskJob<R> &M, int bx, int i) {
     if (j > nth) return;
     const double t0 = M.t0, t1 = M.t1, t2 = M.t2, t3 = M.t3;
     const double *__restrict__ psi = M.psi;
-    double fv = M.ff ? blend(psi[ix(ld, i, j)], t0, t1, t2, t3) : 0.0;
+    // the node and its three neighbours towards the cell's far corner are
+    // loaded together (the last row and column read their own node again):
+    // behind a branch each, the compiler would wait for one after the other
+    const bool cell = i < nr && j < nth;
+    const int i1 = cell ? i + 1 : i, j1 = cell ? j + 1 : j;
+    const double p00 = psi[ix(ld, i, j)], p10 = psi[ix(ld, i1, j)];
+    const double p01 = psi[ix(ld, i, j1)], p11 = psi[ix(ld, i1, j1)];
+    const double fv = M.ff ? blend(p00, t0, t1, t2, t3) : 0.0;
     M.f[ix(ld, i, j)] = (R)fv;
-    if (i < nr && j < nth) {
-        bool k = false;
-        if (M.ff && fv == 1.0)
-            k = blend(psi[ix(ld, i + 1, j)], t0, t1, t2, t3) == 1.0 &&
-                blend(psi[ix(ld, i, j + 1)], t0, t1, t2, t3) == 1.0 &&
-                blend(psi[ix(ld, i + 1, j + 1)], t0, t1, t2, t3) == 1.0;
+    if (cell) {
+        const bool k = M.ff && fv == 1.0 && blend(p10, t0, t1, t2, t3) == 1.0 &&
+                       blend(p01, t0, t1, t2, t3) == 1.0 && blend(p11, t0, t1, t2, t3) == 1.0;
         M.kill[(size_t)i * nth + j] = k ? 1 : 0;
     }
 }
