@@ -104,16 +104,20 @@ __device__ __forceinline__ void locate64(int nr, int nth, double rmin, double dl
                                          double th, int &ci, int &cj, double &a, double &b) {
     const float gi = __logf((float)(r / rmin)) * (float)(1.0 / dlog);
     int i = gi > 0.f ? (gi < (float)(nr - 1) ? (int)gi : nr - 1) : 0;
-    while (i > 0 && r < rn[i]) i--;
-    while (i < nr - 1 && r >= rn[i + 1]) i++;
-    double aa = log(r / rn[i]) / dlog;
-    if (aa < 0.0) aa = 0.0;
-    if (aa > 1.0) aa = 1.0;
     const float gj = (float)th * (float)(1.0 / dth);
     int j = gj > 0.f ? (gj < (float)(nth - 1) ? (int)gj : nth - 1) : 0;
-    while (j > 0 && th < thn[j]) j--;
-    while (j < nth - 1 && th >= thn[j + 1]) j++;
-    double bb = (th - thn[j]) / dth;
+    // the guessed cells' bounding nodes are read together; the walks below
+    // keep the pair of the current cell (a guess is off by one at most, as
+    // a rule, so they rarely read more)
+    double rlo = rn[i], rhi = rn[i + 1], tlo = thn[j], thi = thn[j + 1];
+    while (i > 0 && r < rlo) { i--; rhi = rlo; rlo = rn[i]; }
+    while (i < nr - 1 && r >= rhi) { i++; rlo = rhi; rhi = rn[i + 1]; }
+    double aa = log(r / rlo) / dlog;
+    if (aa < 0.0) aa = 0.0;
+    if (aa > 1.0) aa = 1.0;
+    while (j > 0 && th < tlo) { j--; thi = tlo; tlo = thn[j]; }
+    while (j < nth - 1 && th >= thi) { j++; tlo = thi; thi = thn[j + 1]; }
+    double bb = (th - tlo) / dth;
     if (bb < 0.0) bb = 0.0;
     if (bb > 1.0) bb = 1.0;
     ci = i; cj = j; a = aa; b = bb;

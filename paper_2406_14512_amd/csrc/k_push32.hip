@@ -589,12 +589,18 @@ __device__ __forceinline__ void push_block(const PushJob &J, int chunk, const Pu
     const float *Br = J.B[0], *Bt = J.B[1], *Bp = J.B[2];
     float *Jr = J.J[0], *Jt = J.J[1], *Jp = J.J[2];
 
-    // bounding box of the chunk's cells
+    if (base >= n) return;    // no slot in the chunk (uniform)
+    // bounding box of the chunk's cells: every thread loads all its cells at
+    // once (a slot past the last reads the last slot's cell and ignores it;
+    // behind a branch each, the loads would wait one after the other)
     int imin = 1 << 30, imax = -1, jmin = 1 << 30, jmax = -1;
+    int cb[kPPT];
+#pragma unroll
+    for (int k = 0; k < kPPT; k++) cb[k] = S.ldc((unsigned)min(base + k * kWG + tid, n - 1));
 #pragma unroll
     for (int k = 0; k < kPPT; k++) {
         const int q = base + k * kWG + tid;
-        const int ck = q < n ? S.ldc((unsigned)q) : -1;
+        const int ck = q < n ? cb[k] : -1;
         if (ck >= 0) {
             const int i = ck >> 16, j = ck & 0xffff;
             imin = min(imin, i); imax = max(imax, i);
@@ -633,16 +639,28 @@ __device__ __forceinline__ void push_block(const PushJob &J, int chunk, const Pu
         for (int e = tid; e < m; e += kWG) {
             tile[e] = 0.f; tile[kTile + e] = 0.f; tile[2 * kTile + e] = 0.f;
         }
+        // the field patch: at most two nodes per thread, both loaded before
+        // either is stored (a thread past the last node loads the last one)
         const int mf = TIf * TJf;
-        for (int e = tid; e < mf; e += kWG) {
+        static_assert(kFld <= 2 * kWG, "two patch nodes per thread");
+        float fv[2][6];
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int e = min(tid + h * kWG, mf - 1);
             const int ti = e / TJf, tj = e - ti * TJf;
             const unsigned g = (unsigned)((fi0 + ti) * p.ld + fj0 + tj);
-            fld[e * 6 + 0] = ldo(Er, g);
-            fld[e * 6 + 1] = ldo(Et, g);
-            fld[e * 6 + 2] = ldo(Ep, g);
-            fld[e * 6 + 3] = ldo(Br, g);
-            fld[e * 6 + 4] = ldo(Bt, g);
-            fld[e * 6 + 5] = ldo(Bp, g);
+            fv[h][0] = ldo(Er, g);
+            fv[h][1] = ldo(Et, g);
+            fv[h][2] = ldo(Ep, g);
+            fv[h][3] = ldo(Br, g);
+            fv[h][4] = ldo(Bt, g);
+            fv[h][5] = ldo(Bp, g);
+        }
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int e = tid + h * kWG;
+            if (e < mf)
+                for (int c = 0; c < 6; c++) fld[e * 6 + c] = fv[h][c];
         }
         __syncthreads();
         const Patch P{fld, fi0, fj0, (unsigned)TJf * 24u};

@@ -124,14 +124,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
     __shared__ int box[4];
     const int tid = threadIdx.x, lane = tid & 63;
     const int q = blockIdx.x * blockDim.x + tid;
+    // the slot's whole state is loaded at once (a thread past the last slot
+    // loads the last one and ignores it; nub >= 1): loaded where first used,
+    // behind the branches, each load waited for the one before
+    const int qs = min(q, nub - 1);
+    const double r0 = R[qs], th0 = TH[qs], ur0 = UR[qs], ut0 = UT[qs], up0 = UP[qs];
     bool live = q < nub && q < nslots[0];
-    double r = live ? R[q] : -1.0;
+    const double r = live ? r0 : -1.0;
     live = live && r > 0.0;
     double th = 0.0;
     int i = 0, j = 0;
     double a = 0.0, b = 0.0;
     if (live) {
-        th = TH[q];
+        th = th0;
         locate64(p.nr, p.nth, p.rmin, p.dlog, p.dth, p.rn, p.thn, r, th, i, j, a, b);
     }
     // bounding box of the block's cells
@@ -188,7 +193,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
         sincos(th, &st, &ct);           // one argument reduction for both
         double E[3] = {Es[0] * st + Es[1] * ct, Es[2], Es[0] * ct - Es[1] * st};
         double B[3] = {Bs[0] * st + Bs[1] * ct, Bs[2], Bs[0] * ct - Bs[1] * st};
-        double ur = UR[q], ut = UT[q], up = UP[q];
+        const double ur = ur0, ut = ut0, up = up0;
         double u[3] = {ur * st + ut * ct, up, ur * ct - ut * st};
         boris_rr(u, E, B, p.dt, p.wq, p.rr);
         if (r < p.shell_r) {
