@@ -838,6 +838,24 @@ __global__ void __launch_bounds__(256) k_key_offsets(
         cu[u] = base + u < n ? cnt[base + u] : 0;
         sum += (uint32_t)cu[u];
     }
+    // the four keys' old offsets, then the stayer counts before them, each
+    // loaded for all four at once (a key past the last reads the last key's;
+    // an offset at or past the slot bound reads slot nub - 1's words and
+    // takes the stayer total instead): behind a branch per key, each load
+    // waited for the one before
+    int x[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) x[u] = offold[min(base + u, n - 1)];
+    uint32_t sb[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+        const int xs = min(x[u], V.nub - 1);
+        const int wd = xs >> 6;
+        const uint64_t below = (1ull << (xs & 63)) - 1ull;
+        sb[u] = V.gs[xs >> (kTileShift + kGroupShift)].x + V.ts[xs >> kTileShift].x +
+                (V.wsm[wd] & 0xffffu) + (uint32_t)__popcll(V.smask[wd] & below);
+    }
+    const uint32_t stot = V.tot[0];
     uint64_t tot;
     uint32_t lo = (uint32_t)(block_scan256(sum, &tot) + (uint32_t)part[blockIdx.x]);
 #pragma unroll
@@ -845,8 +863,7 @@ __global__ void __launch_bounds__(256) k_key_offsets(
         const int k = base + u;
         if (k >= n) break;
         const uint32_t hi = lo + (uint32_t)cu[u];
-        const int x = offold[k];
-        const int v = (int)(stayers_before(V, x) + lo);
+        const int v = (int)((x[u] >= V.nub ? stot : sb[u]) + lo);
         offnew[k] = v;
         if (k == nkeys) {
             nalive[0] = v;
@@ -854,7 +871,7 @@ __global__ void __launch_bounds__(256) k_key_offsets(
             nsorted[0] = v;
         } else {
             // the movers of key k are in slot order
-            mst[k] = cu[u] ? lower_bound_u32(mv, (int)lo, (int)hi, (uint32_t)x) : (int)lo;
+            mst[k] = cu[u] ? lower_bound_u32(mv, (int)lo, (int)hi, (uint32_t)x[u]) : (int)lo;
             if (cu[u]) cnt[k] = 0;
         }
         lo = hi;
