@@ -46,6 +46,17 @@ __device__ __forceinline__ int count_wave_i(int *ctr, bool pred) {
     return (int)__popcll(m);
 }
 
+// The job of a grouped launch that holds work item `item` (job k owns items
+// [starts[k], starts[k + 1]), starts ascending): the workgroup's threads test
+// the jobs side by side and the one that matches writes its index to *slot,
+// to be read after the next barrier.  One round of loads, where a bisection
+// would wait for one load per halving.
+__device__ __forceinline__ void find_job(const int *__restrict__ starts, int njobs, int item,
+                                         int *slot) {
+    for (int t = (int)threadIdx.x; t < njobs; t += (int)blockDim.x)
+        if (starts[t] <= item && item < starts[t + 1]) *slot = t;
+}
+
 // A table entry that every lane reads alike (the job of a grouped launch),
 // copied into scalar registers: the first threads of the workgroup load one
 // word each into the LDS array `stage` (kJobWords words), and after a

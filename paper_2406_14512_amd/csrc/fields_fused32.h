@@ -459,24 +459,25 @@ __global__ void __launch_bounds__(kFzT) k_field_f32_group(const F32Job *__restri
                                                           const int *__restrict__ starts,
                                                           int njobs, int *__restrict__ ctr) {
     __shared__ F32Smem<FF> L;
-    __shared__ int next;
+    __shared__ int next, job;
     __shared__ uint32_t stage[kJobWords];
     const int total = starts[njobs];
-    while (true) {
-        if (threadIdx.x == 0) next = atomicAdd(&ctr[0], 1);
+    if (threadIdx.x == 0) next = atomicAdd(&ctr[0], 1);
+    __syncthreads();
+    int item = __builtin_amdgcn_readfirstlane(next);
+    while (item < total) {
+        find_job(starts, njobs, item, &job);
+        int nx = 0;                    // the next item, taken during this one
+        if (threadIdx.x == 0) nx = atomicAdd(&ctr[0], 1);
         __syncthreads();
-        const int item = __builtin_amdgcn_readfirstlane(next);
-        if (item >= total) break;
-        int lo = 0, hi = njobs - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (starts[mid] <= item) lo = mid; else hi = mid - 1;
-        }
+        const int lo = __builtin_amdgcn_readfirstlane(job);
         const F32Job J = stage_uniform(jobs + lo, stage);
         const int local = item - starts[lo];
         const int by = local / J.strips;
         field_block<FF, RE, RB>(J.A, J.rowc, local - by * J.strips, by, L);
+        if (threadIdx.x == 0) next = nx;
         __syncthreads();
+        item = __builtin_amdgcn_readfirstlane(next);
     }
     group_done(ctr);
 }

@@ -180,21 +180,22 @@ __global__ void __launch_bounds__(kPsiCols) k_psi_group(const PsiJob<R> *__restr
                                                         const int *__restrict__ starts,
                                                         int njobs, int *__restrict__ ctr) {
     __shared__ double tile[kPsiRows][kPsiCols + 1];
-    __shared__ int next;
+    __shared__ int next, job;
     __shared__ uint32_t stage[kJobWords];
     const int total = starts[njobs];
-    while (true) {
-        if (threadIdx.x == 0) next = atomicAdd(&ctr[0], 1);
+    if (threadIdx.x == 0) next = atomicAdd(&ctr[0], 1);
+    __syncthreads();
+    int item = __builtin_amdgcn_readfirstlane(next);
+    while (item < total) {
+        find_job(starts, njobs, item, &job);
+        int nx = 0;                    // the next item, taken during this one
+        if (threadIdx.x == 0) nx = atomicAdd(&ctr[0], 1);
         __syncthreads();
-        const int item = __builtin_amdgcn_readfirstlane(next);
-        if (item >= total) break;
-        int lo = 0, hi = njobs - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (starts[mid] <= item) lo = mid; else hi = mid - 1;
-        }
+        const int lo = __builtin_amdgcn_readfirstlane(job);
         psi_block<R>(stage_uniform(jobs + lo, stage), item - starts[lo], tile);
+        if (threadIdx.x == 0) next = nx;
         __syncthreads();
+        item = __builtin_amdgcn_readfirstlane(next);
     }
     group_done(ctr);
 }
@@ -202,16 +203,16 @@ __global__ void __launch_bounds__(kPsiCols) k_psi_group(const PsiJob<R> *__restr
 template <typename R>
 __global__ void __launch_bounds__(256) k_mask_group(const MaskJob<R> *__restrict__ jobs,
                                                     const int *__restrict__ starts, int njobs) {
+    __shared__ int job;
     const int total = starts[njobs];
     for (int item = (int)blockIdx.x; item < total; item += (int)gridDim.x) {
-        int lo = 0, hi = njobs - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (starts[mid] <= item) lo = mid; else hi = mid - 1;
-        }
+        find_job(starts, njobs, item, &job);
+        __syncthreads();
+        const int lo = __builtin_amdgcn_readfirstlane(job);
         const MaskJob<R> &M = jobs[lo];
         const int i = item - starts[lo];
         for (int bx = 0; bx < M.cblocks; bx++) mask_row<R>(M, bx, i);
+        __syncthreads();               // job is rewritten for the next item
     }
 }
 

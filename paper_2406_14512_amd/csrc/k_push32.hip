@@ -736,25 +736,28 @@ k_push32_group(const PushJob *__restrict__ jobs, const int *__restrict__ starts,
     __shared__ float4 queue[2 * kQueue];
     __shared__ int box[4];
     __shared__ int qn;
-    __shared__ int next;
+    __shared__ int next, job;
     __shared__ uint32_t stage[kJobWords];
     const PushSmem sm{tile, fld, queue, box, &qn};
     const int total = starts[njobs];
-    while (true) {
-        if (threadIdx.x == 0) next = atomicAdd(&ctr[0], 1);
+    if (threadIdx.x == 0) next = atomicAdd(&ctr[0], 1);
+    __syncthreads();
+    int item = __builtin_amdgcn_readfirstlane(next);
+    while (item < total) {
+        find_job(starts, njobs, item, &job);
+        // the next item is taken now, so that the counter's round trip
+        // overlaps this item's work
+        int nx = 0;
+        if (threadIdx.x == 0) nx = atomicAdd(&ctr[0], 1);
         __syncthreads();
-        const int item = __builtin_amdgcn_readfirstlane(next);
-        if (item >= total) break;
-        int lo = 0, hi = njobs - 1;   // the job holding the item
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (starts[mid] <= item) lo = mid; else hi = mid - 1;
-        }
+        const int lo = __builtin_amdgcn_readfirstlane(job);
         // a plain push reads no placement pointers (the job's last member)
         const PushJob J =
             stage_uniform(jobs + lo, stage, PLACE ? sizeof(PushJob) : offsetof(PushJob, SP));
         push_block<SHELL, kPPT, PLACE>(J, item - starts[lo], sm);
+        if (threadIdx.x == 0) next = nx;
         __syncthreads();
+        item = __builtin_amdgcn_readfirstlane(next);
     }
     group_done(ctr);
 }
