@@ -639,28 +639,16 @@ __device__ __forceinline__ void push_block(const PushJob &J, int chunk, const Pu
         for (int e = tid; e < m; e += kWG) {
             tile[e] = 0.f; tile[kTile + e] = 0.f; tile[2 * kTile + e] = 0.f;
         }
-        // the field patch: at most two nodes per thread, both loaded before
-        // either is stored (a thread past the last node loads the last one)
         const int mf = TIf * TJf;
-        static_assert(kFld <= 2 * kWG, "two patch nodes per thread");
-        float fv[2][6];
-#pragma unroll
-        for (int h = 0; h < 2; h++) {
-            const int e = min(tid + h * kWG, mf - 1);
+        for (int e = tid; e < mf; e += kWG) {
             const int ti = e / TJf, tj = e - ti * TJf;
             const unsigned g = (unsigned)((fi0 + ti) * p.ld + fj0 + tj);
-            fv[h][0] = ldo(Er, g);
-            fv[h][1] = ldo(Et, g);
-            fv[h][2] = ldo(Ep, g);
-            fv[h][3] = ldo(Br, g);
-            fv[h][4] = ldo(Bt, g);
-            fv[h][5] = ldo(Bp, g);
-        }
-#pragma unroll
-        for (int h = 0; h < 2; h++) {
-            const int e = tid + h * kWG;
-            if (e < mf)
-                for (int c = 0; c < 6; c++) fld[e * 6 + c] = fv[h][c];
+            fld[e * 6 + 0] = ldo(Er, g);
+            fld[e * 6 + 1] = ldo(Et, g);
+            fld[e * 6 + 2] = ldo(Ep, g);
+            fld[e * 6 + 3] = ldo(Br, g);
+            fld[e * 6 + 4] = ldo(Bt, g);
+            fld[e * 6 + 5] = ldo(Bp, g);
         }
         __syncthreads();
         const Patch P{fld, fi0, fj0, (unsigned)TJf * 24u};
