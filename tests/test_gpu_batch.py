@@ -368,6 +368,53 @@ def test_grouped_batch_push_chunk(ppt, gppt):
         s.close()
 
 
+def test_grouped_batch_more_jobs_than_threads():
+    """A grouped push launch with more jobs than a workgroup has threads
+    (132 two-species systems: 264 jobs of one kernel instance), so that the
+    workgroup's threads need two rounds to find an item's job; systems on
+    both sides of job 256 against the same systems stepped alone."""
+    n = 132
+    ws = []
+    for k in range(n):
+        w = W.tiny_open_dipole(1500)
+        w.nr = w.nth = 32
+        w.seed += k
+        w.sort_interval = 4
+        ws.append(w)
+    ds = []
+    for w in ws:
+        d = w.desc()
+        d["precision"] = W.FP32_MIXED
+        ds.append(d)
+    caps = [[w.n_per_species] * w.nspec for w in ws]
+    batch = ffpic.Batch(ds, caps)
+    pick = (0, 1, 127, 128, 130, 131)
+    singles = {k: ffpic.Sim(ds[k], capacity=caps[k]) for k in pick}
+    for s in singles.values():
+        s.set_graph(False)
+    for k, (w, v) in enumerate(zip(ws, batch.views)):
+        for sp in range(w.nspec):
+            p = w.particles(sp)
+            v.load_particles(sp, p)
+            if k in singles:
+                singles[k].load_particles(sp, p)
+    for rnd in range(3):
+        batch.step(4)
+        batch.sync()
+        for s in singles.values():
+            s.step(4)
+        for k, s in singles.items():
+            v = batch.views[k]
+            for g, _ in FIELDS:
+                assert rel(v.field(g), s.field(g)) < 1e-5, (rnd, k, g)
+            assert v.diagnostics(ffpic.DIAG_MOMENTS)["alive"] == \
+                s.diagnostics(ffpic.DIAG_MOMENTS)["alive"], (rnd, k)
+    assert batch.grouped_launches() == 3
+    batch.close()
+    for s in singles.values():
+        s.close()
+
+
 def test_batch_autotune_chooses_the_graph_mode():
     """ffpic_batch_autotune on an FP32-mixed batch without plasma sources
     also times whole batch cycles with per-system graphs and with grouped
