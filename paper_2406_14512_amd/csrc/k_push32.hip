@@ -236,6 +236,10 @@ __device__ __forceinline__ void push_chunk(const P32 &p, const Fields &F, const 
     const int kdi = (kq == 3 || kq == 5 || kq == 7) ? 1 : 0;
     const int kdj = (kq == 1 || kq == 6 || kq == 7) ? 1 : 0;
     const bool row_lead = (lane & 8) == 0;
+    // LDS mode: a cell's key in the current patch is i * TJ + j (unique over
+    // the patch's cells), and the entry this lane adds to after a row sum
+    // lies kofs entries from it
+    const int kofs = LDS ? kcomp * kTile + kdi * acc.TJ + kdj - acc.ti0 * acc.TJ - acc.tj0 : 0;
     float an = 0.f, bn = 0.f, urn = 0.f, utn = 0.f, upn = 0.f;
     int cn = -1, dn = -1;
     if (base + tid < n) {
@@ -489,14 +493,15 @@ __device__ __forceinline__ void push_chunk(const P32 &p, const Fields &F, const 
         // sorts, so a wave holds several cells; the passes with few lanes
         // still cost less than per-lane adds.)
         bool pend = simple;
+        const int ckey = LDS ? (int)mul24(i, (unsigned)acc.TJ) + j : c;
 #pragma unroll 1
         while (true) {
             const unsigned long long m = __ballot(pend);
             if (m == 0ull) break;
             const unsigned rowm = (unsigned)(m >> (lane & 48)) & 0xffffu;
             const int src = rowm ? (lane & 48) + __builtin_ctz(rowm) : lane;
-            const int lc = __shfl(c, src, 64);
-            const bool part = pend && c == lc;
+            const int lc = __shfl(ckey, src, 64);
+            const bool part = pend && ckey == lc;
             float pk[4], pp[4];
 #pragma unroll
             for (int e = 0; e < 4; e++) {
@@ -506,10 +511,13 @@ __device__ __forceinline__ void push_chunk(const P32 &p, const Fields &F, const 
             const float v = row_sum8(pk, pp, b1, b2);
             // a row with pending lanes has participants: its leader
             if (row_lead && rowm != 0u) {
-                const int li = (lc >> 16) + kdi, lj = (lc & 0xffff) + kdj;
-                if (LDS) acc.add(kcomp, li, lj, v);
-                else gadd(reinterpret_cast<float *>(reinterpret_cast<char *>(kg) +
-                                                    ((mul24(li, acc.ld) + (unsigned)lj) << 2)), v);
+                if (LDS) {
+                    atomicAdd(&acc.tile[lc + kofs], v);
+                } else {
+                    const int li = (lc >> 16) + kdi, lj = (lc & 0xffff) + kdj;
+                    gadd(reinterpret_cast<float *>(reinterpret_cast<char *>(kg) +
+                                                   ((mul24(li, acc.ld) + (unsigned)lj) << 2)), v);
+                }
             }
             pend = pend && !part;
         }
