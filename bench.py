@@ -105,10 +105,13 @@ def make_sim(ffpic, w, precision):
     return ffpic.Sim(d, capacity=[w.n_per_species] * w.nspec)
 
 
-def run_timed(ffpic, sim, steps, warmup, nspec, phase_steps=16):
+def run_timed(ffpic, sim, steps, warmup, nspec, sort_interval, phase_steps=16):
     """Wall time of `steps` steps as the library runs them (whole sort cycles
     as replayed graphs), then the per-phase device times of `phase_steps`
-    more steps launched one by one with events between the phases."""
+    more steps launched one by one with events between the phases, then the
+    push phase alone over the steps of one sort cycle that do not sort
+    (their pushes are the plain kernel instance; a step that sorts also
+    places the new order in its push)."""
     sim.step(warmup)
     sim.sync()
     alive0 = sum(sim.diagnostics(ffpic.DIAG_MOMENTS)["alive"])
@@ -126,17 +129,40 @@ def run_timed(ffpic, sim, steps, warmup, nspec, phase_steps=16):
     sim.set_timing(False)
     ph = sim.phase_times()
     wall = t1 - t0
-    return dict(wall=wall, phases=ph, phase_steps=phase_steps, alive0=alive0, alive1=alive1,
-                graphs={"captured": g1[0] - g0[0], "launched": g1[1] - g0[1]})
+    out = dict(wall=wall, phases=ph, phase_steps=phase_steps, alive0=alive0, alive1=alive1,
+               graphs={"captured": g1[0] - g0[0], "launched": g1[1] - g0[1]})
+    if sort_interval > 1:
+        # to the step after the next sort, then the cycle's steps without one
+        step = sim.diagnostics(ffpic.DIAG_MOMENTS)["step"]
+        sim.step(1 + (-step) % sort_interval)
+        sim.sync()
+        n0 = sum(sim.diagnostics(ffpic.DIAG_MOMENTS)["alive"])
+        sim.set_timing(True)
+        sim.step(sort_interval - 1)
+        sim.sync()
+        sim.set_timing(False)
+        n1 = sum(sim.diagnostics(ffpic.DIAG_MOMENTS)["alive"])
+        out["plain"] = dict(push_ms=sim.phase_times()[2], steps=sort_interval - 1,
+                            alive=0.5 * (n0 + n1))
+    return out
 
 
 def roofline(precision, res, steps, nspec, copy_gbs):
     # dominant kernel: the push + deposit kernel, one launch per species and
-    # step; algorithmic bytes = state read + written per live particle
+    # step; algorithmic bytes = state read + written per live particle.  The
+    # launch time is that of the plain instance (steps without a sort) where
+    # measured; the average over whole sort cycles, which includes the
+    # pushes that also place the new order, is reported beside it
     n_avg = 0.5 * (res["alive0"] + res["alive1"])
-    push_ms = res["phases"][2]
-    launches = res["phase_steps"] * nspec
-    avg_launch_s = push_ms / 1e3 / launches
+    cycle_launch_s = res["phases"][2] / 1e3 / (res["phase_steps"] * nspec)
+    avg_launch_s = cycle_launch_s
+    timing = "push phase of whole sort cycles, placing pushes included"
+    if "plain" in res:
+        pl = res["plain"]
+        n_avg = pl["alive"]
+        avg_launch_s = pl["push_ms"] / 1e3 / (pl["steps"] * nspec)
+        timing = (f"push phase of the {pl['steps']} steps of a sort cycle without a sort "
+                  "(plain kernel instance), launched one by one")
     bytes_per_launch = BYTES_PER_PARTICLE[precision] * n_avg / nspec
     achieved = bytes_per_launch / avg_launch_s / 1e9
     traffic = measured_traffic(precision)
@@ -147,6 +173,8 @@ def roofline(precision, res, steps, nspec, copy_gbs):
            "achieved_basis": f"algorithmic bytes: {BYTES_PER_PARTICLE[precision]} B per live "
                              "particle (state read + written once)",
            "avg_launch_ms": round(avg_launch_s * 1e3, 4),
+           "launch_timing": "HIP events on the push's stream: " + timing,
+           "avg_launch_ms_cycle": round(cycle_launch_s * 1e3, 4),
            "bytes_per_launch": bytes_per_launch,
            "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
            "target_frac": 0.6}
@@ -402,11 +430,16 @@ def main():
     results = {}
     for p in precisions:
         log(f"timing {'FP32-mixed' if p == 1 else 'FP64'}: {args.warmup} warmup + {args.steps} steps")
-        results[p] = run_timed(ffpic, sims[p], args.steps, args.warmup, w.nspec)
+        results[p] = run_timed(ffpic, sims[p], args.steps, args.warmup, w.nspec,
+                               w.sort_interval)
         r = results[p]
         log(f"  {r['wall'] / args.steps * 1e3:.3f} ms/step ({r['graphs']['launched']} graph "
             f"launches), phases (ms/step) mask/sort/push/fields "
             + " ".join(f"{x / r['phase_steps']:.3f}" for x in r["phases"]))
+        if "plain" in r:
+            pl = r["plain"]
+            log(f"  push launch without a sort: {pl['push_ms'] / (pl['steps'] * w.nspec):.4f} ms "
+                f"(over {pl['steps']} steps)")
         if p == 0:
             sims[p].close()
 
